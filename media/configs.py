@@ -1,0 +1,290 @@
+"""Seeded recipes for the five benchmark workloads and for small parity cases.
+
+All randomness comes from ``numpy.random.default_rng`` with fixed seeds, so every
+array is reproducible.  The recipes are stand-ins for the paper's fracture network,
+whose geometry exists only in a figure: a unit square, a matrix continuum, an optional
+natural-fracture continuum on the same grid, and straight fracture segments cut into
+cells of length h.
+
+Matrix-fracture transfer input: the discrete transfer coefficient of fracture cell l with
+its host cell in Omega continuum a is supplied as ``sigma_f[a, l] = k_a(host) * len_l / h``
+(the workload's "sigma = k_m / h between each fracture cell and its host" stated per unit
+fracture length).  Fracture cells of different segments that share a host cell are joined
+by an edge with centre distance h; consecutive cells of one segment by an edge of centre
+distance equal to the cell length.
+"""
+from __future__ import annotations
+
+from typing import List, Optional, Tuple
+
+import numpy as np
+from scipy.signal import fftconvolve
+
+from .problem import BC_DIRICHLET, BC_NOFLOW, OmegaContinuum, Problem
+
+CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5")
+
+# fracture physics shared by every workload
+K_F, C_F, APERTURE = 1.0, 0.1, 1e-3
+# natural-fracture continuum of the three-continuum workloads
+K_NAT, C_NAT, SIGMA_NAT = 1e-2, 0.05, 10.0
+
+
+# --------------------------------------------------------------------------------------
+# permeability fields
+# --------------------------------------------------------------------------------------
+def lognormal_field(n: int, rng: np.random.Generator, median: float = 1e-4,
+                    sigma_log: float = 1.5, corr_len: float = 0.05,
+                    ny: Optional[int] = None) -> np.ndarray:
+    """ln k = ln(median) + sigma_log * g with g a unit-variance Gaussian field whose
+    covariance is exp(-r^2 / corr_len^2) on the unit square (h = 1/n).
+
+    g is white noise convolved with exp(-2 r^2 / corr_len^2) (zero-padded, so the field is
+    not periodic) and divided by the kernel's L2 norm, which gives unit variance.
+    """
+    ny = n if ny is None else ny
+    h = 1.0 / n
+    pad = int(np.ceil(2.0 * corr_len / h))
+    off = np.arange(-pad, pad + 1) * h
+    kern = np.exp(-2.0 * (off[:, None] ** 2 + off[None, :] ** 2) / corr_len ** 2)
+    kern /= np.sqrt(np.sum(kern ** 2))
+    noise = rng.standard_normal((ny + 2 * pad, n + 2 * pad))
+    g = fftconvolve(noise, kern, mode="valid")
+    assert g.shape == (ny, n)
+    return np.exp(np.log(median) + sigma_log * g)
+
+
+# --------------------------------------------------------------------------------------
+# fracture geometry
+# --------------------------------------------------------------------------------------
+def _axis_segments(n: int, nseg: int, lmin: int, lmax: int, rng: np.random.Generator,
+                   min_cells: int = 0) -> List[np.ndarray]:
+    """Axis-aligned segments on an n x n grid, each a list of host cells (in order).
+
+    Orientation ~ Bernoulli(1/2); length ~ U{lmin..lmax} cells; row (or column) ~ U{0..n-1};
+    start ~ U{0..n-L}.  A segment that overlaps a collinear one is redrawn.  With
+    ``min_cells`` > 0, segments are added past ``nseg`` until that many cells exist.
+    """
+    used_h = {}   # row -> list of (start, end) occupied by horizontal segments
+    used_v = {}
+    segs: List[np.ndarray] = []
+    total = 0
+    while len(segs) < nseg or total < min_cells:
+        horiz = bool(rng.integers(0, 2))
+        L = int(rng.integers(lmin, lmax + 1))
+        L = min(L, n)
+        line = int(rng.integers(0, n))
+        start = int(rng.integers(0, n - L + 1))
+        book = used_h if horiz else used_v
+        if any(not (start + L <= s or e <= start) for (s, e) in book.get(line, [])):
+            continue                                   # collinear overlap: redraw
+        book.setdefault(line, []).append((start, start + L))
+        j = np.arange(start, start + L)
+        cells = line * n + j if horiz else j * n + line
+        segs.append(cells.astype(np.int64))
+        total += L
+    return segs
+
+
+def _angle_segments(n: int, nseg: int, lmin: int, lmax: int,
+                    rng: np.random.Generator) -> List[np.ndarray]:
+    """Any-angle segments: midpoint ~ U[0,1]^2, angle ~ U[0, pi), L ~ U{lmin..lmax} cells of
+    length h centred at x0 + (j - (L-1)/2) h (cos t, sin t); the host is the grid cell that
+    contains the centre, and cells whose centre falls outside (0,1)^2 are dropped."""
+    h = 1.0 / n
+    segs: List[np.ndarray] = []
+    for _ in range(nseg):
+        x0, y0 = rng.random(2)
+        th = rng.random() * np.pi
+        L = int(rng.integers(lmin, lmax + 1))
+        j = np.arange(L) - (L - 1) / 2.0
+        cx = x0 + j * h * np.cos(th)
+        cy = y0 + j * h * np.sin(th)
+        keep = (cx > 0) & (cx < 1) & (cy > 0) & (cy < 1)
+        ix = np.minimum(np.floor(cx[keep] / h).astype(np.int64), n - 1)
+        iy = np.minimum(np.floor(cy[keep] / h).astype(np.int64), n - 1)
+        if len(ix):
+            segs.append(iy * n + ix)
+    return segs
+
+
+def _fracture_arrays(segs: List[np.ndarray], h: float):
+    """Concatenate segments (segment-major cell order) and build the connection list:
+    chain edges between consecutive cells of a segment (distance h) and, for every host
+    cell holding cells of different segments, an edge between each such pair (distance h).
+    """
+    if not segs:
+        return (np.zeros(0, np.int32), np.zeros(0), np.zeros((0, 2), np.int32), np.zeros(0),
+                np.zeros(0, np.int32))
+    host = np.concatenate(segs).astype(np.int64)
+    seg_id = np.concatenate([np.full(len(s), i) for i, s in enumerate(segs)])
+    nf = len(host)
+    flen = np.full(nf, h)
+    chain = []
+    off = 0
+    for s in segs:
+        L = len(s)
+        if L > 1:
+            a = np.arange(off, off + L - 1)
+            chain.append(np.stack([a, a + 1], axis=1))
+        off += L
+    chain = np.concatenate(chain) if chain else np.zeros((0, 2), np.int64)
+    # crossings: cells of different segments sharing a host
+    order = np.lexsort((np.arange(nf), host))
+    hs = host[order]
+    cross = []
+    starts = np.flatnonzero(np.r_[True, hs[1:] != hs[:-1]])
+    ends = np.r_[starts[1:], nf]
+    for s0, e0 in zip(starts, ends):
+        if e0 - s0 < 2:
+            continue
+        grp = order[s0:e0]
+        for i in range(len(grp)):
+            for j in range(i + 1, len(grp)):
+                a, b = int(grp[i]), int(grp[j])
+                if seg_id[a] != seg_id[b]:
+                    cross.append((min(a, b), max(a, b)))
+    cross = np.array(sorted(cross), np.int64).reshape(-1, 2)
+    edges = np.concatenate([chain, cross]).astype(np.int32)
+    edge_d = np.full(len(edges), h)
+    return host.astype(np.int32), flen, edges, edge_d, seg_id.astype(np.int32)
+
+
+def _sigma_f(omega: List[OmegaContinuum], host: np.ndarray, flen: np.ndarray, n: int,
+             h: float) -> np.ndarray:
+    """Transfer input sigma_f[a, l] = k_a(host(l)) * len_l / h."""
+    out = np.zeros((len(omega), len(host)))
+    for a, o in enumerate(omega):
+        k = o.k_field(n, n).reshape(-1)
+        out[a] = k[host] * flen / h
+    return out
+
+
+def _bc_c1() -> Tuple[np.ndarray, np.ndarray]:
+    # Dirichlet p = 1 on the west side, p = 0 on the east side, no-flow south and north
+    return (np.array([BC_DIRICHLET, BC_DIRICHLET, BC_NOFLOW, BC_NOFLOW], np.int32),
+            np.array([1.0, 0.0, 0.0, 0.0]))
+
+
+def build_problem(n: int, omega: List[OmegaContinuum], segs: List[np.ndarray], tau: float,
+                  nsteps: int, sigma_omega: float = 0.0, meta: Optional[dict] = None,
+                  k_f: float = K_F, c_f: float = C_F, aperture: float = APERTURE) -> Problem:
+    h = 1.0 / n
+    host, flen, edges, edge_d, seg_id = _fracture_arrays(segs, h)
+    bct, bcv = _bc_c1()
+    m = dict(meta or {})
+    m["seg_id"] = seg_id
+    p = Problem(nx=n, ny=n, h=h, omega=omega, sigma_omega=sigma_omega, host=host, flen=flen,
+                edges=edges, edge_d=edge_d, k_f=k_f, c_f=c_f, aperture=aperture,
+                sigma_f=_sigma_f(omega, host, flen, n, h), bc_type=bct, bc_value=bcv,
+                src=None, p0=None, tau=tau, nsteps=nsteps, meta=m)
+    p.check()
+    return p
+
+
+# --------------------------------------------------------------------------------------
+# the five workloads
+# --------------------------------------------------------------------------------------
+def _c1(seed: int = 1, n: int = 64) -> Problem:
+    rng = np.random.default_rng(seed)
+    segs = _axis_segments(n, 8, 10, 40, rng)
+    return build_problem(n, [OmegaContinuum(c=1.0, k_const=1e-4)], segs, tau=0.01, nsteps=20,
+                         meta=dict(name="C1", precond="jacobi", tol=1e-12, precision="fp64"))
+
+
+def _c2(seed: int = 2, n: int = 2048, nseg: int = 400) -> Problem:
+    rng = np.random.default_rng(seed)
+    k = lognormal_field(n, rng, median=1e-4, sigma_log=1.5, corr_len=0.05)
+    segs = _angle_segments(n, nseg, 20, 300, rng)
+    return build_problem(n, [OmegaContinuum(c=1.0, k=k)], segs, tau=1e-3, nsteps=100,
+                         meta=dict(name="C2", precond="ic0", tol=1e-10, precision="fp64"))
+
+
+def _c3(seed: int = 3, n: int = 4096, min_cells: int = 150_000) -> Problem:
+    rng = np.random.default_rng(seed)
+    scale = n // 64
+    segs = _axis_segments(n, 8, 10 * scale, 40 * scale, rng, min_cells=min_cells)
+    omega = [OmegaContinuum(c=1.0, k_const=1e-4), OmegaContinuum(c=C_NAT, k_const=K_NAT)]
+    return build_problem(n, omega, segs, tau=1e-3, nsteps=50, sigma_omega=SIGMA_NAT,
+                         meta=dict(name="C3", precond="jacobi", tol=1e-10, precision="mixed"))
+
+
+def config_problem(name: str, **kw) -> Problem:
+    """Problem of workload C1, C2 or C3 (C4 and C5 are families: see c4_problems, c5_trace)."""
+    return {"C1": _c1, "C2": _c2, "C3": _c3}[name](**kw)
+
+
+def _family_member(rng: np.random.Generator, n: int, three: bool, sigma_log: Optional[float],
+                   k_m_const: Optional[float], nseg: int, nsteps: int, name: str) -> Problem:
+    if k_m_const is None:
+        k = lognormal_field(n, rng, median=1e-4, sigma_log=sigma_log, corr_len=0.05)
+        omega = [OmegaContinuum(c=1.0, k=k)]
+    else:
+        omega = [OmegaContinuum(c=1.0, k_const=k_m_const)]
+    if three:
+        omega.append(OmegaContinuum(c=C_NAT, k_const=K_NAT))
+    segs = _angle_segments(n, nseg, 20, 300, rng)
+    return build_problem(n, omega, segs, tau=1e-3, nsteps=nsteps,
+                         sigma_omega=SIGMA_NAT if three else 0.0,
+                         meta=dict(name=name, precond="jacobi", tol=1e-10, precision="mixed"))
+
+
+def c4_problems(count: int = 256, seed: int = 4, n_range=(128, 1024)) -> List[Problem]:
+    """Batched realizations: two- or three-continuum (1/2 each), side n ~ U{n_range},
+    lognormal matrix permeability with sigma_log ~ U[0.5, 2.5], 20..200 segments."""
+    out = []
+    for i, ss in enumerate(np.random.SeedSequence(seed).spawn(count)):
+        rng = np.random.default_rng(ss)
+        three = bool(rng.integers(0, 2))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        sl = float(rng.uniform(0.5, 2.5))
+        nseg = int(rng.integers(20, 201))
+        out.append(_family_member(rng, n, three, sl, None, nseg, 50, f"C4[{i}]"))
+    return out
+
+
+def c5_trace(count: int = 400, seed: int = 5, rate: float = 40.0, n_range=(64, 2048),
+             steps_range=(10, 500)):
+    """Serving trace: list of (arrival_time_s, n, three, contrast, nsteps, seed_seq).  The
+    problems are built on demand with ``c5_problem`` so the trace itself stays small."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    kids = np.random.SeedSequence(seed + 1000).spawn(count)
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        n = int(round(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1])))))
+        three = bool(rng.integers(0, 2))
+        contrast = float(np.exp(rng.uniform(np.log(1e2), np.log(1e6))))
+        ns = int(rng.integers(steps_range[0], steps_range[1] + 1))
+        out.append((t, n, three, contrast, ns, kids[i]))
+    return out
+
+
+def c5_problem(entry) -> Problem:
+    t, n, three, contrast, ns, ss = entry
+    rng = np.random.default_rng(ss)
+    nseg = int(rng.integers(20, 201))
+    return _family_member(rng, n, three, None, K_F / contrast, nseg, ns, "C5")
+
+
+def small_problem(n: int = 40, seed: int = 7, three: bool = False, nseg: int = 6,
+                  lognormal: bool = True, axis: bool = False, tau: float = 1e-3,
+                  nsteps: int = 5, sigma_log: float = 1.5, seg_len=(5, 30)) -> Problem:
+    """Small problems with the workloads' structure, for parity tests the oracle finishes
+    in seconds (lognormal or constant matrix k, any-angle or axis-aligned segments)."""
+    rng = np.random.default_rng(seed)
+    if lognormal:
+        omega = [OmegaContinuum(c=1.0, k=lognormal_field(n, rng, sigma_log=sigma_log))]
+    else:
+        omega = [OmegaContinuum(c=1.0, k_const=1e-4)]
+    if three:
+        omega.append(OmegaContinuum(c=C_NAT, k_const=K_NAT))
+    if axis:
+        segs = _axis_segments(n, nseg, seg_len[0], min(seg_len[1], n), rng)
+    else:
+        segs = _angle_segments(n, nseg, seg_len[0], seg_len[1], rng)
+    return build_problem(n, omega, segs, tau=tau, nsteps=nsteps,
+                         sigma_omega=SIGMA_NAT if three else 0.0,
+                         meta=dict(name=f"small{n}", precond="jacobi", tol=1e-12,
+                                   precision="fp64"))

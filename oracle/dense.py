@@ -1,0 +1,84 @@
+"""Brute-force dense assembly for tiny problems (oracle cross-check; test infrastructure only).
+
+Builds the coupled matrix M/tau + A row by row from the semi-discrete balance of each cell
+(Section 3.1, eqs. app-md / app-tc / app): storage c|cell|/tau on the diagonal, one
+two-point flux term T (p_i - p_j) per face or fracture connection, one transfer term
+sigma (p_i - p_j) per matrix-fracture or matrix-natural-fracture pair.  Written as plain
+Python loops over cells and faces, independently of the vectorized sparse assembly.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def coupled_dense(prob, tau: float):
+    nx, ny, h = prob.nx, prob.ny, prob.h
+    nc = nx * ny
+    no = prob.n_omega
+    nf = prob.nf
+    off = [a * nc for a in range(no)] + [no * nc]
+    N = no * nc + nf
+    K = np.zeros((N, N))
+    rhs_f = np.zeros(N)
+
+    def flux(i, j, t):
+        K[i, i] += t
+        K[i, j] -= t
+
+    for a, o in enumerate(prob.omega):
+        k = o.k_field(nx, ny)
+        for y in range(ny):
+            for x in range(nx):
+                i = off[a] + y * nx + x
+                K[i, i] += o.c * h * h / tau
+                for (xx, yy) in ((x - 1, y), (x + 1, y), (x, y - 1), (x, y + 1)):
+                    if 0 <= xx < nx and 0 <= yy < ny:
+                        k1, k2 = k[y, x], k[yy, xx]
+                        t = 0.0 if k1 + k2 == 0 else 1.0 / (0.5 / k1 + 0.5 / k2) \
+                            if k1 > 0 and k2 > 0 else 0.0
+                        flux(i, off[a] + yy * nx + xx, t)
+                    else:
+                        side = 0 if xx < 0 else 1 if xx >= nx else 2 if yy < 0 else 3
+                        if int(prob.bc_type[side]) == 1:
+                            t = k[y, x] / (0.5 * h) * h      # |E| = h, d = h/2
+                            K[i, i] += t
+                            rhs_f[i] += t * prob.bc_value[side]
+                src = prob.source(a)
+                if src is not None:
+                    rhs_f[i] += src[y * nx + x] * h * h
+        if no == 2:
+            b = 1 - a
+            for c in range(nc):
+                flux(off[a] + c, off[b] + c, prob.sigma_omega * h * h)
+    if nf:
+        fo = off[no]
+        for l in range(nf):
+            meas = prob.aperture * prob.flen[l]
+            K[fo + l, fo + l] += prob.c_f * meas / tau
+            src = prob.source(no)
+            if src is not None:
+                rhs_f[fo + l] += src[l] * meas
+        for e in range(len(prob.edges)):
+            l, m = int(prob.edges[e, 0]), int(prob.edges[e, 1])
+            t = prob.k_f * prob.aperture / prob.edge_d[e]
+            flux(fo + l, fo + m, t)
+            flux(fo + m, fo + l, t)
+        for a in range(no):
+            for l in range(nf):
+                s = prob.sigma_f[a, l]
+                i = off[a] + int(prob.host[l])
+                flux(i, fo + l, s)
+                flux(fo + l, i, s)
+    mdiag = np.zeros(N)
+    for a, o in enumerate(prob.omega):
+        mdiag[off[a]:off[a] + nc] = o.c * h * h
+    if nf:
+        mdiag[off[no]:] = prob.c_f * prob.aperture * np.asarray(prob.flen)
+    return K, mdiag, rhs_f, off
+
+
+def coupled_step_dense(prob, tau: float, p_prev):
+    """One backward-Euler step of the coupled system by a dense solve."""
+    K, mdiag, rf, off = coupled_dense(prob, tau)
+    x = np.linalg.solve(K, mdiag / tau * np.concatenate(p_prev) + rf)
+    return x

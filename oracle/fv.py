@@ -1,0 +1,183 @@
+"""Finite-volume assembly of the multicontinuum system (oracle; test infrastructure only).
+
+Follows Section 3.1 of the paper:
+
+* storage  m_{a,i} = c_a |cell_i|                                (matrix M, eq. app-mc)
+* diffusion: two-point flux T_ij = k |E_ij| / d_ij between neighbouring cells; the
+  operator D_a has a_ii = sum_j T_ij and a_ij = -T_ij          (eqs. app-md, app-mc)
+* transfer: q_{ab,ij} = sigma_{ab,ij} where cell i of continuum a meets cell j of b;
+  Q_ab = Q_ba^T, and the diagonal block of Q for continuum a is the row-sum diagonal of
+  sum_{b != a} Q_ab                                              (eqs. app, app-mc)
+* right-hand side F_a = f_a |cell| plus boundary contributions.
+
+Readings where the paper is silent (each is also listed in the design notes):
+* square cells of side h, so |E|/d = 1 for interior faces; with a cellwise permeability the
+  face value is the harmonic mean 2 k_i k_j / (k_i + k_j) (the two half-cell conductances
+  in series), which is k for a constant k;
+* a Dirichlet side (the workloads replace the paper's no-flow condition on the west and east
+  sides) is a half-cell conductance T_b = 2 k_i added to a_ii, with T_b p_D added to F;
+* fracture cell measure |iota_l| = aperture * len_l; fracture connection
+  T_e = k_f * aperture / d_e; the discrete matrix-fracture coefficients sigma_il are inputs;
+* the Omega-Omega transfer of the three-continuum model is sigma_12 |cell| per cell.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Tuple
+
+import numpy as np
+import scipy.sparse as sp
+
+BC_DIRICHLET = 1   # input code for a Dirichlet side (0 = no-flow)
+
+
+def omega_transmissibilities(k: np.ndarray):
+    """Face transmissibilities of an ny x nx cell grid with square cells.
+
+    Returns (tx, ty): tx[y, x] couples cells (x, y) and (x+1, y), shape (ny, nx-1);
+    ty[y, x] couples (x, y) and (x, y+1), shape (ny-1, nx).  T = k|E|/d with |E| = d = h
+    for constant k; harmonic mean for a cellwise k.
+    """
+    k = np.asarray(k, np.float64)
+    def harm(a, b):
+        s = a + b
+        out = np.zeros_like(s)
+        nz = s > 0
+        out[nz] = 2.0 * a[nz] * b[nz] / s[nz]
+        return out
+    tx = harm(k[:, :-1], k[:, 1:])
+    ty = harm(k[:-1, :], k[1:, :])
+    return tx, ty
+
+
+def omega_diffusion(k: np.ndarray, bc_type, bc_value) -> Tuple[sp.csr_matrix, np.ndarray]:
+    """D_a (sparse, n x n with n = nx*ny, row-major cells) and its boundary right-hand side.
+
+    Each interior face contributes T to both diagonals and -T to both off-diagonals; each
+    Dirichlet side face contributes T_b = 2 k_i to a_ii and T_b p_D to F_i.
+    """
+    ny, nx = k.shape
+    n = nx * ny
+    idx = np.arange(n).reshape(ny, nx)
+    tx, ty = omega_transmissibilities(k)
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n)
+    for t, a, b in ((tx, idx[:, :-1], idx[:, 1:]), (ty, idx[:-1, :], idx[1:, :])):
+        t, a, b = t.ravel(), a.ravel(), b.ravel()
+        rows += [a, b]
+        cols += [b, a]
+        vals += [-t, -t]
+        np.add.at(diag, a, t)
+        np.add.at(diag, b, t)
+    fb = np.zeros(n)
+    sides = {0: idx[:, 0], 1: idx[:, -1], 2: idx[0, :], 3: idx[-1, :]}   # W, E, S, N
+    kf = k.ravel()
+    for s in range(4):
+        if int(bc_type[s]) == BC_DIRICHLET:
+            cells = sides[s]
+            tb = 2.0 * kf[cells]
+            np.add.at(diag, cells, tb)
+            np.add.at(fb, cells, tb * float(bc_value[s]))
+    rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(diag)
+    D = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    D.sum_duplicates()
+    return D, fb
+
+
+def fracture_diffusion(nf: int, edges: np.ndarray, edge_d: np.ndarray, k_f: float,
+                       aperture: float) -> sp.csr_matrix:
+    """D_f on the fracture-cell graph: T_e = k_f * aperture / d_e per connection."""
+    if nf == 0:
+        return sp.csr_matrix((0, 0))
+    e = np.asarray(edges, np.int64).reshape(-1, 2)
+    t = k_f * aperture / np.asarray(edge_d, np.float64)
+    diag = np.zeros(nf)
+    np.add.at(diag, e[:, 0], t)
+    np.add.at(diag, e[:, 1], t)
+    rows = np.concatenate([e[:, 0], e[:, 1], np.arange(nf)])
+    cols = np.concatenate([e[:, 1], e[:, 0], np.arange(nf)])
+    vals = np.concatenate([-t, -t, diag])
+    D = sp.csr_matrix((vals, (rows, cols)), shape=(nf, nf))
+    D.sum_duplicates()
+    return D
+
+
+@dataclass
+class Assembled:
+    """All blocks of M dp/dt + (D + Q) p = F for one problem (continuum order: Omega
+    continua, then the fracture)."""
+    sizes: List[int]
+    M: List[np.ndarray]                         # diagonal of M_a
+    D: List[sp.csr_matrix]                      # D_a
+    Q: Dict[Tuple[int, int], sp.csr_matrix]     # Q_ab for a != b (N_a x N_b), nonnegative
+    F: List[np.ndarray]                         # F_a (sources and boundary terms)
+
+    @property
+    def L(self) -> int:
+        return len(self.sizes)
+
+    def S(self, a: int) -> np.ndarray:
+        """Row-sum diagonal of sum_{b != a} Q_ab (the diagonal block of Q)."""
+        s = np.zeros(self.sizes[a])
+        for b in range(self.L):
+            if b != a and (a, b) in self.Q:
+                s += np.asarray(self.Q[(a, b)].sum(axis=1)).ravel()
+        return s
+
+    def Qfull(self) -> sp.csr_matrix:
+        """The block matrix Q with row-sum diagonal blocks and -Q_ab off-diagonal blocks."""
+        blocks = [[None] * self.L for _ in range(self.L)]
+        for a in range(self.L):
+            blocks[a][a] = sp.diags(self.S(a))
+            for b in range(self.L):
+                if b != a and (a, b) in self.Q:
+                    blocks[a][b] = -self.Q[(a, b)]
+        return sp.bmat(blocks, format="csr")
+
+    def Afull(self) -> sp.csr_matrix:
+        return (sp.block_diag(self.D, format="csr") + self.Qfull()).tocsr()
+
+    def Mfull(self) -> np.ndarray:
+        return np.concatenate(self.M)
+
+    def Ffull(self) -> np.ndarray:
+        return np.concatenate(self.F)
+
+
+def assemble(prob) -> Assembled:
+    """Assemble M, D, Q, F for a ``media.Problem``."""
+    nx, ny, h = prob.nx, prob.ny, prob.h
+    nc = nx * ny
+    no = prob.n_omega
+    nf = prob.nf
+    sizes = [nc] * no + ([nf] if nf > 0 else [])
+    M, D, F = [], [], []
+    for a, o in enumerate(prob.omega):
+        k = o.k_field(nx, ny)
+        Da, fb = omega_diffusion(k, prob.bc_type, prob.bc_value)
+        D.append(Da)
+        M.append(np.full(nc, o.c * h * h))
+        src = prob.source(a)
+        F.append(fb + (0.0 if src is None else src * h * h))
+    if nf > 0:
+        meas = prob.aperture * np.asarray(prob.flen, np.float64)
+        M.append(prob.c_f * meas)
+        D.append(fracture_diffusion(nf, prob.edges, prob.edge_d, prob.k_f, prob.aperture))
+        src = prob.source(no)
+        F.append(np.zeros(nf) if src is None else src * meas)
+    Q: Dict[Tuple[int, int], sp.csr_matrix] = {}
+    if no == 2 and prob.sigma_omega != 0.0:
+        q = sp.diags(np.full(nc, prob.sigma_omega * h * h)).tocsr()
+        Q[(0, 1)] = q
+        Q[(1, 0)] = q.T.tocsr()
+    if nf > 0:
+        fi = no
+        host = np.asarray(prob.host, np.int64)
+        for a in range(no):
+            sig = np.asarray(prob.sigma_f[a], np.float64)
+            qaf = sp.csr_matrix((sig, (host, np.arange(nf))), shape=(nc, nf))
+            qaf.sum_duplicates()
+            Q[(a, fi)] = qaf
+            Q[(fi, a)] = qaf.T.tocsr()
+    return Assembled(sizes=sizes, M=M, D=D, Q=Q, F=F)

@@ -1,0 +1,325 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix (no GPU).
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term, a wrong sign,
+a wrong index, a transposed block) fails at least one of them:
+
+* hand-computed fixture (tests/golden/hand_2x1.json)       -> every assembled entry, F,
+                                                              coupled and D steps exactly
+* textbook eigenvalues of the 5-point operator            -> stencil assembly with BCs
+* layered-medium series-resistance solution              -> harmonic mean, Dirichlet faces
+* two-cell closed forms (coupled, D, EX)                  -> transfer and the recurrences
+* brute-force dense assembly on tiny problems             -> the whole coupled matrix
+* constant states, maximum principle, mass identity      -> transfer signs, antisymmetry
+* Theorems 2 and 3 (energy decay), symmetry, Q_ab=Q_ba^T  -> operator structure
+* first order in tau of decoupled vs coupled              -> the splitting itself
+* fast diagonalization vs LU                              -> the large-grid fallback
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import media
+from media import OmegaContinuum, Problem
+from oracle import dense, fastdiag, fv, schemes
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tiny(n=4, ny=None, three=False, nfc=3, seed=0, bc=(1, 1, 0, 0), bcv=(1.0, 0.0, 0, 0),
+          tau=0.1, lognormal=True):
+    rng = np.random.default_rng(seed)
+    ny = n if ny is None else ny
+    h = 1.0 / n
+    k = np.exp(rng.normal(np.log(1e-1), 1.0, (ny, n))) if lognormal else None
+    om = [OmegaContinuum(c=1.0, k=k, k_const=0.3)]
+    if three:
+        om.append(OmegaContinuum(c=0.05, k_const=2.0))
+    host = rng.integers(0, n * ny, nfc).astype(np.int32)
+    edges = np.array([[i, i + 1] for i in range(nfc - 1)], np.int32).reshape(-1, 2)
+    p = Problem(nx=n, ny=ny, h=h, omega=om, sigma_omega=3.0 if three else 0.0, host=host,
+                flen=np.full(nfc, h), edges=edges, edge_d=rng.uniform(0.5, 1.5, len(edges)) * h,
+                k_f=5.0, c_f=0.1, aperture=0.2,
+                sigma_f=rng.uniform(0.1, 1.0, (len(om), nfc)),
+                bc_type=np.array(bc, np.int32), bc_value=np.array(bcv, float), tau=tau)
+    p.check()
+    return p
+
+
+# ------------------------------------------------------------------------------------
+def test_hand_computed_fixture():
+    g = json.load(open(os.path.join(GOLD, "hand_2x1.json")))
+    q = g["problem"]
+    p = Problem(nx=q["nx"], ny=q["ny"], h=q["h"], omega=[OmegaContinuum(c=q["c"], k_const=q["k"])],
+                host=np.array(q["host"], np.int32), flen=np.array(q["flen"]),
+                k_f=q["k_f"], c_f=q["c_f"], aperture=q["aperture"],
+                sigma_f=np.array(q["sigma_f"]), bc_type=np.array(q["bc_type"], np.int32),
+                bc_value=np.array(q["bc_value"]), tau=q["tau"])
+    asm = fv.assemble(p)
+    K = schemes.coupled_matrix(asm, p.tau).toarray()
+    np.testing.assert_array_equal(K, np.array(g["coupled_matrix"]))
+    np.testing.assert_array_equal(asm.Ffull(), np.array(g["F"]))
+    frac = lambda v: np.array([float(Fraction(a, b)) for a, b in v])
+    x = schemes.run(p, "coupled", 1)[-1]
+    np.testing.assert_allclose(np.concatenate(x), frac(g["coupled_step1"]), rtol=0, atol=1e-15)
+    h = schemes.run(p, "D", 2)
+    np.testing.assert_allclose(np.concatenate(h[1]), frac(g["D_step1"]), rtol=0, atol=1e-15)
+    assert abs(h[2][1][0] - float(Fraction(*g["D_step2_fracture"]))) < 1e-15
+
+
+@pytest.mark.parametrize("bc", [(1, 1, 0, 0), (0, 0, 1, 1), (0, 0, 0, 0), (1, 1, 1, 1)])
+def test_stencil_eigenvalues_textbook(bc):
+    """Constant-k 5-point operator: eigenvalues k (4 sin^2(pi i/2nx) + 4 sin^2(pi j/2ny)) with
+    i, j from 1 (Dirichlet half-cell ends) or 0 (no-flow ends)."""
+    nx, ny, k = 7, 5, 0.37
+    D, _ = fv.omega_diffusion(np.full((ny, nx), k), bc, (0, 0, 0, 0))
+    ev = np.sort(np.linalg.eigvalsh(D.toarray()))
+    ix = np.arange(1, nx + 1) if bc[0] else np.arange(nx)
+    iy = np.arange(1, ny + 1) if bc[2] else np.arange(ny)
+    lx = 4 * np.sin(np.pi * ix / (2 * nx)) ** 2
+    ly = 4 * np.sin(np.pi * iy / (2 * ny)) ** 2
+    ref = np.sort((k * (lx[None, :] + ly[:, None])).ravel())
+    np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_layered_medium_series_resistance(axis):
+    """Steady flow through layers k_0..k_{n-1} between p=1 and p=0 half-cell faces: flux
+    1/sum(1/k_i) and p_i = 1 - flux (sum_{j<i} 1/k_j + 1/(2 k_i)) exactly (Darcy's law for
+    conductances in series); the transverse direction carries no flow."""
+    rng = np.random.default_rng(3)
+    n, m = 9, 4
+    kl = np.exp(rng.normal(0, 1.5, n))
+    if axis == "x":
+        k = np.tile(kl, (m, 1)); nx, ny = n, m; bc = (1, 1, 0, 0); bcv = (1, 0, 0, 0)
+    else:
+        k = np.tile(kl[:, None], (1, m)); nx, ny = m, n; bc = (0, 0, 1, 1); bcv = (0, 0, 1, 0)
+    p = Problem(nx=nx, ny=ny, h=1.0 / nx, omega=[OmegaContinuum(c=1.0, k=k)],
+                bc_type=np.array(bc, np.int32), bc_value=np.array(bcv, float), tau=1e18)
+    x = schemes.run(p, "coupled", 1)[-1][0].reshape(ny, nx)
+    flux = 1.0 / np.sum(1.0 / kl)
+    ref = 1.0 - flux * (np.concatenate([[0], np.cumsum(1.0 / kl)[:-1]]) + 0.5 / kl)
+    got = x[0, :] if axis == "x" else x[:, 0]
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+    assert np.ptp(x, axis=0 if axis == "x" else 1).max() < 1e-12
+
+
+def _two_cell(mm=0.7, mf=0.2, sig=1.3, tau=0.4, pm=1.0, pf=-0.5):
+    p = Problem(nx=1, ny=1, h=1.0, omega=[OmegaContinuum(c=mm, k_const=1.0)],
+                host=np.array([0], np.int32), flen=np.array([1.0]), k_f=1.0, c_f=mf,
+                aperture=1.0, sigma_f=np.array([[sig]]), tau=tau,
+                p0=[np.array([pm]), np.array([pf])])
+    return p
+
+
+def test_two_cell_coupled_closed_form():
+    mm, mf, sig, tau = 0.7, 0.2, 1.3, 0.4
+    p = _two_cell(mm, mf, sig, tau)
+    hist = schemes.run(p, "coupled", 6)
+    d0 = 1.5
+    mass0 = mm * 1.0 + mf * (-0.5)
+    for n, s in enumerate(hist):
+        d = s[0][0] - s[1][0]
+        assert abs(d - d0 / (1 + tau * sig * (1 / mm + 1 / mf)) ** n) < 1e-14
+        assert abs(mm * s[0][0] + mf * s[1][0] - mass0) < 1e-14
+
+
+def test_two_cell_D_and_EX_closed_form():
+    mm, mf, sig, tau = 0.7, 0.2, 1.3, 0.4
+    a = sig / (mm / tau + sig)
+    b = sig / (mf / tau + sig)
+    p = _two_cell(mm, mf, sig, tau)
+    hist = schemes.run(p, "D", 8)
+    G = np.array([[1 - a, a], [b, 1 - b]])
+    v = np.array([1.0, -0.5])
+    for s in hist:
+        np.testing.assert_allclose([s[0][0], s[1][0]], v, rtol=0, atol=1e-14)
+        assert abs(b * s[0][0] + a * s[1][0] - (b * 1.0 + a * -0.5)) < 1e-14
+        v = G @ v
+    # EX: (m/tau) p^n = (m/tau - sig) p^{n-1} + sig q^{n-1}  (whole transfer lagged)
+    e = sig * tau / mm
+    f = sig * tau / mf
+    G2 = np.array([[1 - e, e], [f, 1 - f]])
+    hist = schemes.run(p, "EX", 5)
+    v = np.array([1.0, -0.5])
+    for s in hist:
+        np.testing.assert_allclose([s[0][0], s[1][0]], v, rtol=0, atol=1e-13)
+        v = G2 @ v
+
+
+def test_EX_unstable_where_D_is_not():
+    # tau*sigma/m_f = 5 > 2: the EX amplification 1 - tau sigma (1/m_m + 1/m_f) leaves the
+    # unit disc, the D-scheme's 1 - a - b stays inside
+    p = _two_cell(mm=1.0, mf=0.2, sig=1.0, tau=1.0)
+    ex = schemes.run(p, "EX", 20)[-1]
+    d = schemes.run(p, "D", 20)[-1]
+    assert abs(ex[0][0] - ex[1][0]) > 1e3
+    assert abs(d[0][0] - d[1][0]) < 1.5
+
+
+@pytest.mark.parametrize("three", [False, True])
+def test_dense_brute_force(three):
+    p = _tiny(n=4, ny=3, three=three, nfc=4, seed=11, tau=0.05)
+    K, mdiag, rf, _ = dense.coupled_dense(p, p.tau)
+    asm = fv.assemble(p)
+    np.testing.assert_allclose(schemes.coupled_matrix(asm, p.tau).toarray(), K, rtol=1e-14,
+                               atol=1e-14)
+    np.testing.assert_allclose(asm.Ffull(), rf, rtol=1e-14, atol=1e-15)
+    rng = np.random.default_rng(5)
+    p.p0 = [rng.random(s) for s in p.sizes()]
+    x = schemes.run(p, "coupled", 1)[-1]
+    np.testing.assert_allclose(np.concatenate(x), dense.coupled_step_dense(p, p.tau, p.p0),
+                               rtol=1e-12, atol=1e-13)
+    # D-scheme from the dense blocks: block-diagonal implicit part, off-diagonal lagged
+    N = K.shape[0]
+    off = np.cumsum([0] + p.sizes())
+    K0 = np.zeros_like(K)
+    for a in range(len(p.sizes())):
+        s = slice(off[a], off[a + 1])
+        K0[s, s] = K[s, s]
+    A1 = K - K0
+    xd = np.linalg.solve(K0, mdiag / p.tau * np.concatenate(p.p0) + rf - A1 @ np.concatenate(p.p0))
+    np.testing.assert_allclose(np.concatenate(schemes.run(p, "D", 1)[-1]), xd, rtol=1e-12,
+                               atol=1e-13)
+    # L and U from the dense blocks: triangular implicit parts
+    for sch, tri in (("L", np.tril), ("U", np.triu)):
+        mask = np.zeros((len(p.sizes()),) * 2)
+        mask = tri(np.ones_like(mask))
+        KL = np.zeros_like(K)
+        for a in range(len(p.sizes())):
+            for b in range(len(p.sizes())):
+                if mask[a, b]:
+                    KL[off[a]:off[a + 1], off[b]:off[b + 1]] = K[off[a]:off[a + 1], off[b]:off[b + 1]]
+        xl = np.linalg.solve(KL, mdiag / p.tau * np.concatenate(p.p0) + rf
+                             - (K - KL) @ np.concatenate(p.p0))
+        np.testing.assert_allclose(np.concatenate(schemes.run(p, sch, 1)[-1]), xl, rtol=1e-12,
+                                   atol=1e-13)
+
+
+@pytest.mark.parametrize("scheme", schemes.SCHEMES)
+@pytest.mark.parametrize("three", [False, True])
+def test_constant_state_preserved(scheme, three):
+    # EX only within its stability bound tau * sigma / m < 1 (rounding grows otherwise)
+    tau = 1e-3 if scheme == "EX" else 0.1
+    p = _tiny(n=5, three=three, nfc=6, seed=2, bc=(1, 1, 0, 1), bcv=(0.7, 0.7, 0, 0.7), tau=tau)
+    p.p0 = [np.full(s, 0.7) for s in p.sizes()]
+    for s in schemes.run(p, scheme, 4):
+        for v in s:
+            np.testing.assert_allclose(v, 0.7, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("scheme", ["coupled", "D", "L", "U"])
+def test_maximum_principle(scheme):
+    p = media.small_problem(n=24, seed=4, nseg=5, tau=1e-2, nsteps=6)
+    for s in schemes.run(p, scheme):
+        for v in s:
+            assert v.min() >= -1e-14 and v.max() <= 1 + 1e-14
+
+
+@pytest.mark.parametrize("three", [False, True])
+def test_symmetry_and_splitting_condition(three):
+    p = _tiny(n=5, three=three, nfc=7, seed=9)
+    asm = fv.assemble(p)
+    A = asm.Afull()
+    assert abs(A - A.T).max() < 1e-15
+    for (a, b), q in asm.Q.items():
+        assert abs(q - asm.Q[(b, a)].T).max() == 0
+        assert q.min() >= 0
+    # A >= 0 and A0 - A1 >= 0 for the D-split (Section 3.3 condition dc-op)
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert ev.min() > -1e-12
+    A0 = sp.block_diag([asm.D[a] + sp.diags(asm.S(a)) for a in range(asm.L)]).toarray()
+    A1 = A.toarray() - A0
+    assert np.linalg.eigvalsh(A0 - A1).min() > -1e-12
+
+
+@pytest.mark.parametrize("scheme", ["coupled", "D", "L", "U"])
+@pytest.mark.parametrize("tau", [1e-3, 1.0, 1e3])
+def test_energy_decay_theorems(scheme, tau):
+    """Theorems 2 and 3 with F = 0: ||p^n||_A <= ||p^{n-1}||_A (no-flow sides, no source)."""
+    p = _tiny(n=6, three=True, nfc=8, seed=21, bc=(0, 0, 0, 0), tau=tau)
+    rng = np.random.default_rng(1)
+    p.p0 = [rng.normal(size=s) for s in p.sizes()]
+    asm = fv.assemble(p)
+    hist = schemes.run(p, scheme, 6)
+    e = [schemes.energy(asm, s) for s in hist]
+    # rounding floor: ||A|| ||x||^2 * eps relative to the initial energy
+    assert all(e[i + 1] <= e[i] + 1e-14 * e[0] for i in range(len(e) - 1)), e
+    assert e[-1] < e[0]
+
+
+def test_mass_identities():
+    p = _tiny(n=6, three=True, nfc=8, seed=8, bc=(0, 0, 0, 0), tau=0.3)
+    rng = np.random.default_rng(2)
+    p.p0 = [rng.random(s) for s in p.sizes()]
+    asm = fv.assemble(p)
+    mass = lambda s: sum(float(asm.M[a] @ s[a]) for a in range(asm.L))
+    hist = schemes.run(p, "coupled", 5)
+    for s in hist:
+        assert abs(mass(s) - mass(hist[0])) < 1e-13 * abs(mass(hist[0]))
+    # D-scheme: each transfer pair (i in a, j in b, sigma) changes the mass by
+    # -tau sigma (dp_a,i + dp_b,j) per step
+    hist = schemes.run(p, "D", 3)
+    for s0, s1 in zip(hist[:-1], hist[1:]):
+        dm = mass(s1) - mass(s0)
+        pred = 0.0
+        for (a, b), q in asm.Q.items():
+            if a < b:
+                qc = q.tocoo()
+                pred -= p.tau * np.sum(qc.data * ((s1[a] - s0[a])[qc.row] + (s1[b] - s0[b])[qc.col]))
+        assert abs(dm - pred) < 1e-13
+
+
+def test_first_order_in_tau():
+    """||p_D(T) - p_C(T)|| / ||p_C(T)|| halves with tau (the lagged coupling is O(tau))."""
+    p = media.config_problem("C1")
+    errs = []
+    for tau in (0.02, 0.01, 0.005, 0.0025):
+        ns = int(round(0.2 / tau))
+        d = schemes.run(p, "D", ns, tau=tau, keep="last")
+        c = schemes.run(p, "coupled", ns, tau=tau, keep="last")
+        errs.append(schemes.rel_l2(d, c))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(1.8 <= r <= 2.2 for r in ratios), (errs, ratios)
+
+
+def test_fast_diagonalization_matches_lu():
+    n = 48
+    p = Problem(nx=n, ny=n, h=1.0 / n, omega=[OmegaContinuum(c=1.0, k_const=1e-4)],
+                bc_type=np.array([1, 1, 0, 0], np.int32), bc_value=np.array([1.0, 0, 0, 0]),
+                tau=1e-3)
+    rng = np.random.default_rng(0)
+    p.p0 = [rng.random(n * n)]
+    x = schemes.run(p, "D", 1)[-1][0]
+    asm = fv.assemble(p)
+    b = asm.M[0] / p.tau * p.p0[0] + asm.F[0]
+    y = fastdiag.fd_solve(b, n, n, 1e-4, p.h ** 2 / p.tau, p.bc_type)
+    np.testing.assert_allclose(y, x, rtol=1e-12, atol=0)
+    # with fracture-host transfer perturbations: CG preconditioned by the exact part
+    q = media.small_problem(n=n, seed=3, lognormal=False, axis=True, nseg=6)
+    asm = fv.assemble(q)
+    K = schemes.continuum_matrix(asm, q.tau, 0)
+    b = rng.random(n * n)
+    xs = schemes.DirectSolver(K).solve(b)
+    xf, it, rr = fastdiag.fd_pcg(K, b, n, n, 1e-4, q.h ** 2 / q.tau, q.bc_type)
+    np.testing.assert_allclose(xf, xs, rtol=1e-11, atol=0)
+
+
+def test_decoupled_close_to_coupled_c1():
+    """The paper reports decoupled-vs-coupled errors well below 1% and the U-scheme as the
+    most accurate (qualitative; its geometry cannot be reproduced)."""
+    p = media.config_problem("C1")
+    c = schemes.run(p, "coupled", keep="last")
+    e = {s: schemes.rel_l2(schemes.run(p, s, keep="last"), c) for s in ("D", "L", "U")}
+    assert max(e.values()) < 1e-2
+    assert e["U"] < e["D"]
+
+
+def test_dof_counts():
+    # the paper's fine-grid sizes: 200^2 + 2684 and 2 * 200^2 + 2684
+    assert 200 * 200 + 2684 == 42684 and 2 * 200 * 200 + 2684 == 82684
+    p = media.config_problem("C1")
+    assert p.dof() == 64 * 64 + p.nf
