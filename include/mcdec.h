@@ -1,0 +1,210 @@
+/*
+ * mcdec.h -- C ABI of the MI355X (gfx950) decoupled multicontinuum flow library.
+ *
+ * What it computes (Vasilyeva, "Efficient decoupling schemes for multiscale multicontinuum
+ * problems in fractured porous media"):
+ *   the L-continuum model  c_a dp_a/dt - div(k_a grad p_a) + sum_b sigma_ab (p_a - p_b) = f_a
+ *   (Section 2, eq. mm) discretized by two-point-flux finite volumes on an h x h grid with an
+ *   embedded 1-D fracture mesh (Section 3.1, eqs. app-md, app-tc, app, app-mc):
+ *       M dp/dt + (D + Q) p = F,
+ *   and advanced in time by
+ *     - the coupled backward-Euler scheme  (M/tau + A) p^n = M/tau p^{n-1} + F  (Section 3.2,
+ *       eq. ct-mc), or
+ *     - the decoupled D-scheme (Section 3.3, eq. si-mc with block-diagonal A0): each
+ *       continuum solves its own SPD system
+ *         (M_a/tau + D_a + S_a) p_a^n = M_a/tau p_a^{n-1} + sum_{b!=a} Q_ab p_b^{n-1} + F_a,
+ *       S_a = row-sum diagonal of sum_{b!=a} Q_ab; or the L-/U-schemes (block lower/upper
+ *       triangular A0, Section 3.3); or the fully lagged split "EX" (A0 = D, A1 = Q, only
+ *       conditionally stable).
+ *   Every linear system is solved on the GPU by preconditioned conjugate gradients.
+ *
+ * Conventions
+ *   - All functions return mc_status; no C++ exception crosses this boundary.
+ *   - Omega cells are row-major: cell (x, y), x in [0,nx) west->east, y in [0,ny)
+ *     south->north, has index y*nx + x.  Sides are ordered W, E, S, N.
+ *   - Continuum index a: 0 = matrix (lowest permeability), 1 = natural-fracture continuum
+ *     (three-continuum media only), then the explicit fracture continuum (if nf > 0).
+ *     This is the ascending-permeability order the L-/U-schemes use.
+ *   - Descriptor arrays are HOST memory owned by the caller, read only during
+ *     mc_create_problem / mc_server_submit; the library copies what it needs to the device.
+ *   - Pointers named *_dev are DEVICE memory owned by the caller, accessed in stream order on
+ *     the problem's stream.
+ *   - One handle is used by one host thread at a time.  All device work of a handle is
+ *     ordered on its stream (mc_options.stream, or a stream the library creates).
+ *   - After MC_EDEVICE a handle may only be destroyed.
+ */
+#ifndef MCDEC_H
+#define MCDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MC_OK = 0,
+  MC_EINVAL = -1,      /* invalid argument or descriptor (message in mc_last_error)        */
+  MC_ENOMEM = -2,      /* device allocation failed / request can never fit the budget        */
+  MC_ENOCONV = -3,     /* PCG reached max_iter (or refinement max_outer) before tolerance     */
+  MC_EBREAKDOWN = -4,  /* PCG breakdown: p.Ap <= 0 or a non-finite value                      */
+  MC_EDEVICE = -5,     /* HIP runtime error                                                   */
+  MC_ENOTFOUND = -6    /* unknown request id (server)                                         */
+} mc_status;
+
+typedef enum {
+  MC_SCHEME_D = 0,        /* decoupled, block-diagonal A0 (Section 3.3)                       */
+  MC_SCHEME_COUPLED = 1,  /* coupled backward Euler (Section 3.2)                             */
+  MC_SCHEME_L = 2,        /* block lower-triangular A0 (ascending permeability first)          */
+  MC_SCHEME_U = 3,        /* block upper-triangular A0 (highest permeability first)            */
+  MC_SCHEME_EX = 4        /* A0 = D, A1 = Q: whole transfer lagged; stable only if
+                             tau * max(S_a / m_a) < 1 per cell (not unconditionally stable)     */
+} mc_scheme;
+
+typedef enum {
+  MC_FP64 = 0,   /* FP64 storage and arithmetic throughout                                     */
+  MC_MIXED = 1   /* FP32 operator copies and inner PCG (FP64 dot products) inside FP64
+                    iterative refinement; residual, right-hand side and transfer stay FP64     */
+} mc_precision;
+
+typedef enum {
+  MC_JACOBI = 0, /* z = r / diag                                                               */
+  MC_BIC0 = 1    /* block incomplete Cholesky, zero fill: the grid split into 64-column x TY-row
+                    blocks and the fracture graph into its chains of consecutive cells; inside a
+                    block, IC(0) in natural order; couplings between blocks are dropped        */
+} mc_precond;
+
+/* One continuum on the Omega grid. */
+typedef struct {
+  double c;              /* storage coefficient c_a > 0                                       */
+  double k_const;        /* permeability when k == NULL (>= 0)                                */
+  const double *k;       /* [ny*nx] cell permeability (>= 0, finite) or NULL                  */
+  const double *src;     /* [ny*nx] source f_a per unit area, or NULL (= 0)                   */
+  const double *p0;      /* [ny*nx] initial pressure, or NULL (= 0)                           */
+} mc_omega_desc;
+
+/* A problem: grid, continua, fracture mesh, boundary data, time step. */
+typedef struct {
+  int32_t nx, ny;        /* grid cells (>= 1)                                                 */
+  double h;              /* cell side (> 0); cell area h^2, interior |E|/d = 1                */
+  int32_t n_omega;       /* 1 (matrix only) or 2 (matrix + natural fractures)                  */
+  mc_omega_desc omega[2];
+  double sigma_omega;    /* Omega-Omega transfer coefficient per unit area (>= 0); the discrete
+                            coefficient of each cell pair is sigma_omega * h^2                  */
+  int32_t nf;            /* fracture cells (0 = no explicit fracture continuum)                */
+  const int32_t *host;   /* [nf] row-major index of the Omega cell containing fracture cell l  */
+  const double *flen;    /* [nf] fracture cell length (> 0); measure = aperture * flen         */
+  int32_t ne;            /* fracture-fracture connections                                      */
+  const int32_t *edges;  /* [2*ne] endpoint pairs (distinct, in [0,nf))                        */
+  const double *edge_d;  /* [ne] centre distance (> 0); conductance k_f * aperture / d         */
+  double k_f, c_f, aperture;   /* fracture permeability (>= 0), storage (> 0), aperture (> 0)  */
+  const double *sigma_f; /* [n_omega*nf] (continuum-major) discrete matrix-fracture transfer
+                            coefficient sigma_il of fracture cell l with its host in continuum a */
+  const double *src_f;   /* [nf] fracture source per unit measure, or NULL                     */
+  const double *p0_f;    /* [nf] initial fracture pressure, or NULL                            */
+  int32_t bc_type[4];    /* W,E,S,N for every Omega continuum: 0 no-flow, 1 Dirichlet given by a
+                            half-cell conductance 2 k_i; fracture tips are always no-flow      */
+  double bc_value[4];    /* Dirichlet pressures                                                */
+  double tau;            /* time step (> 0)                                                    */
+} mc_problem_desc;
+
+typedef struct {
+  int32_t scheme;        /* mc_scheme                                                          */
+  int32_t precision;     /* mc_precision                                                       */
+  int32_t precond;       /* mc_precond                                                         */
+  double tol;            /* PCG stop: ||b - A x||_2 <= tol ||b||_2 (recursive residual), 0<tol<1 */
+  int32_t max_iter;      /* per solve (per inner solve in MC_MIXED), >= 1                      */
+  double outer_tol;      /* MC_MIXED: FP64 residual target relative to ||b||                   */
+  int32_t max_outer;     /* MC_MIXED: maximum refinement passes                                */
+  double inner_tol;      /* MC_MIXED: inner FP32 PCG tolerance relative to the outer residual  */
+  int32_t check_every;   /* PCG iterations launched between host convergence polls (0 = auto)  */
+  int32_t tile_rows;     /* grid tile height in rows (0 = auto: 16)                             */
+  void *stream;          /* hipStream_t to order all work on, or NULL (library-owned stream)   */
+} mc_options;
+
+typedef struct {
+  int32_t n_cont;        /* continua in the problem                                            */
+  int32_t iters[3];      /* PCG iterations of the last step per continuum (coupled: all equal;
+                            mixed: total inner iterations)                                     */
+  int32_t outer[3];      /* refinement passes of the last step (MC_MIXED), else 0             */
+  int32_t converged[3];  /* 1 if that continuum's last solve met its tolerance                 */
+  double relres[3];      /* final ||r||/||b|| (FP64 true residual for MC_MIXED)                */
+  double seconds;        /* host wall time of the call                                         */
+  int64_t step;          /* time layers completed since creation or the last mc_set_time       */
+  int32_t failed;        /* -1, or the continuum whose solve failed                            */
+} mc_report;
+
+typedef struct {
+  int32_t n_cont;
+  int32_t sizes[3];      /* unknowns per continuum                                             */
+  int64_t device_bytes;  /* device memory held by the problem                                  */
+  int32_t grid_tiles;    /* grid tiles per Omega continuum                                     */
+  int32_t n_chains;      /* fracture chains (blocks of the fracture preconditioner)            */
+} mc_info;
+
+typedef struct mc_problem mc_problem;
+
+/* Fill *opt with defaults: D-scheme, FP64, Jacobi, tol 1e-10, max_iter 20000, outer_tol
+   1e-10, max_outer 30, inner_tol 1e-6, automatic polling and tiles, NULL stream. */
+mc_status mc_options_default(mc_options *opt);
+
+/* Validate *desc (MC_EINVAL with a message on any violation of the ranges stated above),
+   allocate device memory for the problem, copy the inputs and build every coefficient on the
+   device (storage, face conductances, Dirichlet terms, transfer row sums, fracture graph,
+   preconditioner factors).  The state is set to the initial pressures.  *out is NULL on
+   failure. */
+mc_status mc_create_problem(const mc_problem_desc *desc, const mc_options *opt,
+                            mc_problem **out);
+
+/* Release everything; NULL-safe. */
+mc_status mc_destroy(mc_problem *p);
+
+/* Advance n_steps (>= 1) time layers with the problem's scheme.  Transactional per layer: if a
+   solve fails (MC_ENOCONV, MC_EBREAKDOWN) the state stays at the last completed layer and
+   last->failed names the continuum.  last may be NULL. */
+mc_status mc_step(mc_problem *p, int32_t n_steps, mc_report *last);
+
+/* Solve (M_a/tau + D_a + S_a) x = rhs for one continuum a (the D-scheme system of Section 3.3;
+   without S_a under MC_SCHEME_EX).  rhs_dev and x_dev are device arrays of that continuum's
+   size; x_dev holds the initial guess on entry and the solution on return.  The problem's
+   state is not touched. */
+mc_status mc_solve_continuum(mc_problem *p, int32_t alpha, const double *rhs_dev,
+                             double *x_dev, mc_report *rep);
+
+/* y = (M_a/tau + D_a + S_a) x for continuum a (the operator mc_solve_continuum inverts).
+   Device arrays of that continuum's size.  Runs the same operator kernel the solver uses. */
+mc_status mc_apply_continuum(mc_problem *p, int32_t alpha, const double *x_dev, double *y_dev);
+
+/* y = (M/tau + D + Q) x on the concatenated vector [p_0; p_1; (p_2)] (the coupled operator of
+   Section 3.2).  Device arrays of the total size. */
+mc_status mc_apply_coupled(mc_problem *p, const double *x_dev, double *y_dev);
+
+/* b_dev = right-hand side of continuum a in the D-scheme from the current state p^{n-1}:
+   M_a/tau p_a^{n-1} + sum_{b!=a} Q_ab p_b^{n-1} + F_a (Section 3.3).  Always FP64. */
+mc_status mc_assemble_rhs(mc_problem *p, int32_t alpha, double *b_dev);
+
+/* Copy continuum a of the current state to / from host memory (synchronous). */
+mc_status mc_get_state(mc_problem *p, int32_t alpha, double *host_out);
+mc_status mc_set_state(mc_problem *p, int32_t alpha, const double *host_in);
+
+/* Replace the solver options (scheme, precision, preconditioner, tolerances); coefficients
+   that depend on the scheme are rebuilt on the device.  The stream cannot change. */
+mc_status mc_set_options(mc_problem *p, const mc_options *opt);
+
+mc_status mc_get_info(const mc_problem *p, mc_info *info);
+
+/* Message of the last failure on this handle, or (p == NULL) of the calling thread's last
+   failed mc_create_problem / server call.  Never NULL. */
+const char *mc_last_error(const mc_problem *p);
+
+/* Kernel timing on the problem's stream (HIP events around each launch of the dominant
+   kernel family).  which: 0 = grid operator kernel, 1 = grid update kernel.  enable = 1 starts
+   recording (and clears totals), 0 stops. */
+mc_status mc_profile(mc_problem *p, int32_t enable);
+mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCDEC_H */

@@ -1,0 +1,163 @@
+#include "host_setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+namespace mc {
+
+namespace {
+bool fin(double v) { return std::isfinite(v); }
+
+std::string fmt(const char* f, long a = 0, long b = 0) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), f, a, b);
+  return buf;
+}
+}  // namespace
+
+std::string validate_desc(const mc_problem_desc& d) {
+  if (d.nx < 1 || d.ny < 1) return "nx and ny must be >= 1";
+  if ((long)d.nx * (long)d.ny > (1L << 31) - 2) return "grid too large for 32-bit cell indices";
+  if (!(d.h > 0) || !fin(d.h)) return "h must be finite and > 0";
+  if (!(d.tau > 0) || !fin(d.tau)) return "tau must be finite and > 0";
+  if (d.n_omega != 1 && d.n_omega != 2) return "n_omega must be 1 or 2";
+  const long nc = (long)d.nx * d.ny;
+  for (int a = 0; a < d.n_omega; ++a) {
+    const mc_omega_desc& o = d.omega[a];
+    if (!(o.c > 0) || !fin(o.c)) return fmt("omega[%ld].c must be finite and > 0", a);
+    if (o.k) {
+      for (long i = 0; i < nc; ++i)
+        if (!(o.k[i] >= 0) || !fin(o.k[i])) return fmt("omega[%ld].k[%ld] invalid", a, i);
+    } else if (!(o.k_const >= 0) || !fin(o.k_const)) {
+      return fmt("omega[%ld].k_const must be finite and >= 0", a);
+    }
+    if (o.src)
+      for (long i = 0; i < nc; ++i)
+        if (!fin(o.src[i])) return fmt("omega[%ld].src[%ld] not finite", a, i);
+    if (o.p0)
+      for (long i = 0; i < nc; ++i)
+        if (!fin(o.p0[i])) return fmt("omega[%ld].p0[%ld] not finite", a, i);
+  }
+  if (!(d.sigma_omega >= 0) || !fin(d.sigma_omega)) return "sigma_omega must be finite and >= 0";
+  for (int s = 0; s < 4; ++s) {
+    if (d.bc_type[s] != 0 && d.bc_type[s] != 1) return fmt("bc_type[%ld] must be 0 or 1", s);
+    if (d.bc_type[s] == 1 && !fin(d.bc_value[s])) return fmt("bc_value[%ld] not finite", s);
+  }
+  if (d.nf < 0) return "nf must be >= 0";
+  if (d.nf > 0) {
+    if (!d.host || !d.flen || !d.sigma_f) return "host, flen and sigma_f are required when nf > 0";
+    if (!(d.k_f >= 0) || !fin(d.k_f)) return "k_f must be finite and >= 0";
+    if (!(d.c_f > 0) || !fin(d.c_f)) return "c_f must be finite and > 0";
+    if (!(d.aperture > 0) || !fin(d.aperture)) return "aperture must be finite and > 0";
+    for (int l = 0; l < d.nf; ++l) {
+      if (d.host[l] < 0 || d.host[l] >= nc) return fmt("host[%ld] = %ld out of range", l, d.host[l]);
+      if (!(d.flen[l] > 0) || !fin(d.flen[l])) return fmt("flen[%ld] must be > 0", l);
+    }
+    for (long j = 0; j < (long)d.n_omega * d.nf; ++j)
+      if (!(d.sigma_f[j] >= 0) || !fin(d.sigma_f[j])) return fmt("sigma_f[%ld] invalid", j);
+    if (d.src_f)
+      for (int l = 0; l < d.nf; ++l)
+        if (!fin(d.src_f[l])) return fmt("src_f[%ld] not finite", l);
+    if (d.p0_f)
+      for (int l = 0; l < d.nf; ++l)
+        if (!fin(d.p0_f[l])) return fmt("p0_f[%ld] not finite", l);
+  }
+  if (d.ne < 0) return "ne must be >= 0";
+  if (d.ne > 0) {
+    if (d.nf == 0 || !d.edges || !d.edge_d) return "edges and edge_d are required when ne > 0";
+    for (int e = 0; e < d.ne; ++e) {
+      int a = d.edges[2 * e], b = d.edges[2 * e + 1];
+      if (a < 0 || a >= d.nf || b < 0 || b >= d.nf) return fmt("edge %ld endpoint out of range", e);
+      if (a == b) return fmt("edge %ld joins a cell to itself", e);
+      if (!(d.edge_d[e] > 0) || !fin(d.edge_d[e])) return fmt("edge_d[%ld] must be > 0", e);
+    }
+  }
+  return "";
+}
+
+std::string validate_options(const mc_options& o) {
+  if (o.scheme < MC_SCHEME_D || o.scheme > MC_SCHEME_EX) return "unknown scheme";
+  if (o.precision != MC_FP64 && o.precision != MC_MIXED) return "unknown precision";
+  if (o.precond != MC_JACOBI && o.precond != MC_BIC0) return "unknown preconditioner";
+  if (!(o.tol > 0 && o.tol < 1)) return "tol must be in (0, 1)";
+  if (o.max_iter < 1) return "max_iter must be >= 1";
+  if (o.precision == MC_MIXED) {
+    if (!(o.outer_tol > 0 && o.outer_tol < 1)) return "outer_tol must be in (0, 1)";
+    if (!(o.inner_tol > 0 && o.inner_tol < 1)) return "inner_tol must be in (0, 1)";
+    if (o.max_outer < 1) return "max_outer must be >= 1";
+    if (o.scheme == MC_SCHEME_COUPLED) return "the coupled scheme runs in FP64 only";
+  }
+  if (o.check_every < 0) return "check_every must be >= 0";
+  if (o.tile_rows < 0 || o.tile_rows > 64 || (o.tile_rows % 4) != 0)
+    return "tile_rows must be 0 (auto) or a multiple of 4 up to 64";
+  return "";
+}
+
+GraphCSR build_graph(int nf, int ne, const int32_t* edges) {
+  GraphCSR g;
+  g.rowptr.assign(nf + 1, 0);
+  for (int e = 0; e < ne; ++e) {
+    g.rowptr[edges[2 * e] + 1]++;
+    g.rowptr[edges[2 * e + 1] + 1]++;
+  }
+  for (int l = 0; l < nf; ++l) g.rowptr[l + 1] += g.rowptr[l];
+  std::vector<std::pair<int, int>> ent(g.rowptr[nf]);
+  std::vector<int> fill(g.rowptr.begin(), g.rowptr.end() - 1);
+  for (int e = 0; e < ne; ++e) {
+    int a = edges[2 * e], b = edges[2 * e + 1];
+    ent[fill[a]++] = {b, e};
+    ent[fill[b]++] = {a, e};
+  }
+  for (int l = 0; l < nf; ++l)
+    std::sort(ent.begin() + g.rowptr[l], ent.begin() + g.rowptr[l + 1]);
+  g.col.resize(ent.size());
+  g.eidx.resize(ent.size());
+  for (size_t j = 0; j < ent.size(); ++j) {
+    g.col[j] = ent[j].first;
+    g.eidx[j] = ent[j].second;
+  }
+  return g;
+}
+
+HostMap build_host_map(int ncell, int nf, const int32_t* host) {
+  HostMap m;
+  m.hptr.assign((size_t)ncell + 1, 0);
+  for (int l = 0; l < nf; ++l) m.hptr[(size_t)host[l] + 1]++;
+  for (long i = 0; i < ncell; ++i) m.hptr[i + 1] += m.hptr[i];
+  m.hidx.resize(nf);
+  std::vector<int> fill(m.hptr.begin(), m.hptr.end() - 1);
+  for (int l = 0; l < nf; ++l) m.hidx[fill[host[l]]++] = l;   // ascending l within a host
+  return m;
+}
+
+std::vector<int> build_chains(int nf, const GraphCSR& g) {
+  std::vector<int> ptr{0};
+  for (int l = 0; l + 1 < nf; ++l) {
+    bool linked = false;
+    for (int j = g.rowptr[l]; j < g.rowptr[l + 1]; ++j)
+      if (g.col[j] == l + 1) linked = true;
+    if (!linked) ptr.push_back(l + 1);
+  }
+  if (nf > 0) ptr.push_back(nf);
+  return ptr;
+}
+
+std::vector<int> xcd_order(int n, int nxcd) {
+  if (nxcd <= 1 || n < 2 * nxcd) {
+    std::vector<int> o(n);
+    std::iota(o.begin(), o.end(), 0);
+    return o;
+  }
+  const int per = (n + nxcd - 1) / nxcd;
+  std::vector<int> o((size_t)per * nxcd, -1);
+  for (int b = 0; b < per * nxcd; ++b) {
+    const int j = b % nxcd, k = b / nxcd;
+    const int idx = j * per + k;
+    o[b] = idx < n ? idx : -1;
+  }
+  return o;
+}
+
+}  // namespace mc

@@ -1,0 +1,321 @@
+"""ctypes binding of libmcdec.so (argument marshalling only; every computation runs in the
+HIP library).  Names follow include/mcdec.h.
+
+Importing this module loads the in-tree ``libmcdec.so`` and fails loudly if it is missing:
+there is no fallback path.  torch is imported first when available so that the library and
+torch share one HIP runtime (device pointers from torch tensors are then valid here).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+try:  # share torch's HIP runtime (same soname) when torch is present
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcdec.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2209_01158_amd.build` (hipcc, gfx950)")
+_lib = C.CDLL(LIB_PATH)
+
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_ENOCONV, MC_EBREAKDOWN, MC_EDEVICE, MC_ENOTFOUND = \
+    0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENOCONV",
+                -4: "MC_EBREAKDOWN", -5: "MC_EDEVICE", -6: "MC_ENOTFOUND"}
+SCHEMES = {"D": 0, "coupled": 1, "L": 2, "U": 3, "EX": 4}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECONDS = {"jacobi": 0, "bic0": 1}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class OmegaDesc(C.Structure):
+    _fields_ = [("c", C.c_double), ("k_const", C.c_double), ("k", _dp), ("src", _dp),
+                ("p0", _dp)]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("h", C.c_double),
+                ("n_omega", C.c_int32), ("omega", OmegaDesc * 2), ("sigma_omega", C.c_double),
+                ("nf", C.c_int32), ("host", _ip), ("flen", _dp), ("ne", C.c_int32),
+                ("edges", _ip), ("edge_d", _dp), ("k_f", C.c_double), ("c_f", C.c_double),
+                ("aperture", C.c_double), ("sigma_f", _dp), ("src_f", _dp), ("p0_f", _dp),
+                ("bc_type", C.c_int32 * 4), ("bc_value", C.c_double * 4), ("tau", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
+                ("tol", C.c_double), ("max_iter", C.c_int32), ("outer_tol", C.c_double),
+                ("max_outer", C.c_int32), ("inner_tol", C.c_double),
+                ("check_every", C.c_int32), ("tile_rows", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Report(C.Structure):
+    _fields_ = [("n_cont", C.c_int32), ("iters", C.c_int32 * 3), ("outer", C.c_int32 * 3),
+                ("converged", C.c_int32 * 3), ("relres", C.c_double * 3),
+                ("seconds", C.c_double), ("step", C.c_int64), ("failed", C.c_int32)]
+
+    def as_dict(self):
+        n = self.n_cont
+        return dict(iters=list(self.iters)[:n], outer=list(self.outer)[:n],
+                    converged=list(self.converged)[:n], relres=list(self.relres)[:n],
+                    seconds=self.seconds, step=self.step, failed=self.failed)
+
+
+class Info(C.Structure):
+    _fields_ = [("n_cont", C.c_int32), ("sizes", C.c_int32 * 3), ("device_bytes", C.c_int64),
+                ("grid_tiles", C.c_int32), ("n_chains", C.c_int32)]
+
+
+_PROBLEM = C.c_void_p
+
+
+def _sig(name, restype, argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = argtypes
+    return f
+
+
+mc_options_default = _sig("mc_options_default", C.c_int, [C.POINTER(Options)])
+mc_create_problem = _sig("mc_create_problem", C.c_int,
+                         [C.POINTER(ProblemDesc), C.POINTER(Options), C.POINTER(_PROBLEM)])
+mc_destroy = _sig("mc_destroy", C.c_int, [_PROBLEM])
+mc_step = _sig("mc_step", C.c_int, [_PROBLEM, C.c_int32, C.POINTER(Report)])
+mc_solve_continuum = _sig("mc_solve_continuum", C.c_int,
+                          [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Report)])
+mc_apply_continuum = _sig("mc_apply_continuum", C.c_int,
+                          [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p])
+mc_apply_coupled = _sig("mc_apply_coupled", C.c_int, [_PROBLEM, C.c_void_p, C.c_void_p])
+mc_assemble_rhs = _sig("mc_assemble_rhs", C.c_int, [_PROBLEM, C.c_int32, C.c_void_p])
+mc_get_state = _sig("mc_get_state", C.c_int, [_PROBLEM, C.c_int32, _dp])
+mc_set_state = _sig("mc_set_state", C.c_int, [_PROBLEM, C.c_int32, _dp])
+mc_set_options = _sig("mc_set_options", C.c_int, [_PROBLEM, C.POINTER(Options)])
+mc_get_info = _sig("mc_get_info", C.c_int, [_PROBLEM, C.POINTER(Info)])
+mc_last_error = _sig("mc_last_error", C.c_char_p, [_PROBLEM])
+mc_profile = _sig("mc_profile", C.c_int, [_PROBLEM, C.c_int32])
+mc_profile_read = _sig("mc_profile_read", C.c_int,
+                       [_PROBLEM, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)])
+
+
+class McError(RuntimeError):
+    def __init__(self, status: int, msg: str, report: Optional[dict] = None):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.report = report
+
+
+def _check(st, handle=None, report=None):
+    if st != MC_OK:
+        msg = mc_last_error(handle)
+        raise McError(st, msg.decode() if msg else "", report)
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_iter=20000,
+                 outer_tol=1e-10, max_outer=30, inner_tol=1e-6, check_every=0, tile_rows=0,
+                 stream=None) -> Options:
+    o = Options()
+    _check(mc_options_default(C.byref(o)))
+    o.scheme = SCHEMES[scheme]
+    o.precision = PRECISIONS[precision]
+    o.precond = PRECONDS[precond]
+    o.tol, o.max_iter = tol, max_iter
+    o.outer_tol, o.max_outer, o.inner_tol = outer_tol, max_outer, inner_tol
+    o.check_every, o.tile_rows = check_every, tile_rows
+    o.stream = stream
+    return o
+
+
+def _default_stream():
+    if torch is not None and torch.cuda.is_available():
+        return torch.cuda.current_stream().cuda_stream
+    return None
+
+
+def _sync_torch():
+    """Order the caller's pending torch work (e.g. the fill of an output tensor) before a
+    library call that touches caller-owned device memory on the library stream."""
+    if torch is not None and torch.cuda.is_available():
+        torch.cuda.current_stream().synchronize()
+
+
+def _dev_ptr(t):
+    """Device address of a torch tensor (contiguous float64 on the GPU)."""
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One multicontinuum problem resident on the GPU (wraps mc_problem)."""
+
+    def __init__(self, prob, scheme="D", precision="fp64", precond="jacobi", tol=1e-10,
+                 max_iter=20000, stream="default", **kw):
+        if stream == "default":
+            stream = _default_stream()
+        self._keep = []
+        d = ProblemDesc()
+        d.nx, d.ny, d.h = prob.nx, prob.ny, prob.h
+        d.n_omega = len(prob.omega)
+        for a, o in enumerate(prob.omega):
+            od = d.omega[a]
+            od.c, od.k_const = o.c, o.k_const
+            if o.k is not None:
+                k = np.ascontiguousarray(o.k, np.float64).reshape(-1)
+                self._keep.append(k)
+                od.k = _ptr(k, C.c_double)
+            src = prob.source(a) if hasattr(prob, "source") else None
+            if src is not None:
+                src = np.ascontiguousarray(src, np.float64)
+                self._keep.append(src)
+                od.src = _ptr(src, C.c_double)
+            p0 = None if prob.p0 is None else prob.p0[a]
+            if p0 is not None:
+                p0 = np.ascontiguousarray(p0, np.float64).reshape(-1)
+                self._keep.append(p0)
+                od.p0 = _ptr(p0, C.c_double)
+        d.sigma_omega = prob.sigma_omega
+        nf = int(len(prob.host))
+        d.nf = nf
+        if nf:
+            host = np.ascontiguousarray(prob.host, np.int32)
+            flen = np.ascontiguousarray(prob.flen, np.float64)
+            sig = np.ascontiguousarray(prob.sigma_f, np.float64).reshape(-1)
+            edges = np.ascontiguousarray(prob.edges, np.int32).reshape(-1)
+            ed = np.ascontiguousarray(prob.edge_d, np.float64)
+            self._keep += [host, flen, sig, edges, ed]
+            d.host, d.flen, d.sigma_f = _ptr(host, C.c_int32), _ptr(flen, C.c_double), \
+                _ptr(sig, C.c_double)
+            d.ne = int(len(ed))
+            d.edges, d.edge_d = _ptr(edges, C.c_int32), _ptr(ed, C.c_double)
+            srcf = prob.source(d.n_omega) if hasattr(prob, "source") else None
+            if srcf is not None:
+                srcf = np.ascontiguousarray(srcf, np.float64)
+                self._keep.append(srcf)
+                d.src_f = _ptr(srcf, C.c_double)
+            p0f = None if prob.p0 is None else prob.p0[d.n_omega]
+            if p0f is not None:
+                p0f = np.ascontiguousarray(p0f, np.float64)
+                self._keep.append(p0f)
+                d.p0_f = _ptr(p0f, C.c_double)
+        d.k_f, d.c_f, d.aperture = prob.k_f, prob.c_f, prob.aperture
+        for s in range(4):
+            d.bc_type[s] = int(prob.bc_type[s])
+            d.bc_value[s] = float(prob.bc_value[s])
+        d.tau = prob.tau
+        self.opt = make_options(scheme, precision, precond, tol, max_iter, stream=stream, **kw)
+        h = _PROBLEM()
+        _check(mc_create_problem(C.byref(d), C.byref(self.opt), C.byref(h)))
+        self._keep = []
+        self.h = h
+        self.sizes = list(prob.sizes()) if hasattr(prob, "sizes") else None
+        inf = self.info()
+        self.sizes = list(inf.sizes)[:inf.n_cont]
+        self.n_cont = inf.n_cont
+
+    # --- lifecycle -----------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            mc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # --- calls ---------------------------------------------------------------------
+    def step(self, n_steps: int = 1) -> dict:
+        rep = Report()
+        st = mc_step(self.h, n_steps, C.byref(rep))
+        _check(st, self.h, rep.as_dict())
+        return rep.as_dict()
+
+    def solve_continuum(self, alpha: int, rhs, x) -> dict:
+        rep = Report()
+        _sync_torch()
+        st = mc_solve_continuum(self.h, alpha, _dev_ptr(rhs), _dev_ptr(x), C.byref(rep))
+        _check(st, self.h, rep.as_dict())
+        return rep.as_dict()
+
+    def apply_continuum(self, alpha: int, x, y):
+        _sync_torch()
+        _check(mc_apply_continuum(self.h, alpha, _dev_ptr(x), _dev_ptr(y)), self.h)
+
+    def apply_coupled(self, x, y):
+        _sync_torch()
+        _check(mc_apply_coupled(self.h, _dev_ptr(x), _dev_ptr(y)), self.h)
+
+    def assemble_rhs(self, alpha: int, b):
+        _sync_torch()
+        _check(mc_assemble_rhs(self.h, alpha, _dev_ptr(b)), self.h)
+
+    def get_state(self, alpha: int) -> np.ndarray:
+        out = np.empty(self.sizes[alpha])
+        _check(mc_get_state(self.h, alpha, _ptr(out, C.c_double)), self.h)
+        return out
+
+    def get_states(self):
+        return [self.get_state(a) for a in range(self.n_cont)]
+
+    def set_state(self, alpha: int, v):
+        v = np.ascontiguousarray(v, np.float64).reshape(-1)
+        if v.size != self.sizes[alpha]:
+            raise ValueError("state size mismatch")
+        _check(mc_set_state(self.h, alpha, _ptr(v, C.c_double)), self.h)
+
+    def set_states(self, states):
+        for a, v in enumerate(states):
+            self.set_state(a, v)
+
+    def set_options(self, **kw):
+        cur = dict(scheme={v: k for k, v in SCHEMES.items()}[self.opt.scheme],
+                   precision={v: k for k, v in PRECISIONS.items()}[self.opt.precision],
+                   precond={v: k for k, v in PRECONDS.items()}[self.opt.precond],
+                   tol=self.opt.tol, max_iter=self.opt.max_iter, outer_tol=self.opt.outer_tol,
+                   max_outer=self.opt.max_outer, inner_tol=self.opt.inner_tol,
+                   check_every=self.opt.check_every, tile_rows=self.opt.tile_rows,
+                   stream=self.opt.stream)
+        cur.update(kw)
+        o = make_options(**cur)
+        _check(mc_set_options(self.h, C.byref(o)), self.h)
+        self.opt = o
+
+    def info(self) -> Info:
+        inf = Info()
+        _check(mc_get_info(self.h, C.byref(inf)), self.h)
+        return inf
+
+    def profile(self, enable: bool):
+        _check(mc_profile(self.h, int(enable)), self.h)
+
+    def profile_read(self, which: int):
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(mc_profile_read(self.h, which, C.byref(n), C.byref(ms)), self.h)
+        return n.value, ms.value
+
+
+EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
+           "mc_solve_continuum", "mc_apply_continuum", "mc_apply_coupled", "mc_assemble_rhs",
+           "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
+           "mc_profile", "mc_profile_read"]

@@ -1,0 +1,155 @@
+"""GPU parity of the HIP path against the CPU oracle (element by element, same seeded inputs).
+
+Tolerances: FP64 operator applications agree to rounding (<= 1e-14 relative, the only
+difference is summation order and FMA contraction); FP64 solves and trajectories to a
+relative L2 error <= 1e-10; mixed-precision refinement to <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+import media
+from oracle import fv, schemes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2209_01158_amd import mcdec  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a = np.concatenate([np.ravel(v) for v in a]) if isinstance(a, (list, tuple)) else np.ravel(a)
+    b = np.concatenate([np.ravel(v) for v in b]) if isinstance(b, (list, tuple)) else np.ravel(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def T(v):
+    return torch.tensor(np.ascontiguousarray(v, np.float64), device=DEV)
+
+
+CASES = {
+    "c1": lambda: media.config_problem("C1"),
+    # ragged: 200 = 3 * 64 + 8 columns, 200 = 12 * 16 + 8 rows; lognormal k, any-angle fractures
+    "ragged200": lambda: media.small_problem(n=200, seed=11, nseg=12, seg_len=(10, 80)),
+    "three70": lambda: media.small_problem(n=70, seed=5, three=True, nseg=6, seg_len=(5, 40)),
+    "tiny1": lambda: media.small_problem(n=1, seed=1, nseg=0, lognormal=False),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    print(f"\n[case {request.param}]", flush=True)
+    return request.param, CASES[request.param]()
+
+
+def test_apply_continuum(case):
+    name, p = case
+    asm = fv.assemble(p)
+    rng = np.random.default_rng(0)
+    with mcdec.Problem(p) as g:
+        for a in range(p.n_cont):
+            K = schemes.continuum_matrix(asm, p.tau, a)
+            x = rng.standard_normal(p.sizes()[a])
+            y = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
+            g.apply_continuum(a, T(x), y)
+            ref = K @ x
+            assert rel(y.cpu().numpy(), ref) < 1e-14, (name, a)
+
+
+def test_apply_coupled(case):
+    name, p = case
+    asm = fv.assemble(p)
+    K = schemes.coupled_matrix(asm, p.tau)
+    x = np.random.default_rng(1).standard_normal(p.dof())
+    y = torch.zeros(p.dof(), dtype=torch.float64, device=DEV)
+    with mcdec.Problem(p) as g:
+        g.apply_coupled(T(x), y)
+    assert rel(y.cpu().numpy(), K @ x) < 1e-14
+
+
+def test_assemble_rhs(case):
+    name, p = case
+    asm = fv.assemble(p)
+    rng = np.random.default_rng(2)
+    st = [rng.random(s) for s in p.sizes()]
+    with mcdec.Problem(p) as g:
+        g.set_states(st)
+        for a in range(p.n_cont):
+            b = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
+            g.assemble_rhs(a, b)
+            ref = schemes.decoupled_rhs(asm, p.tau, a, st, "D")
+            assert rel(b.cpu().numpy(), ref) < 1e-14, a
+
+
+def test_solve_continuum(case):
+    name, p = case
+    asm = fv.assemble(p)
+    rng = np.random.default_rng(3)
+    with mcdec.Problem(p, tol=1e-14) as g:
+        for a in range(p.n_cont):
+            K = schemes.continuum_matrix(asm, p.tau, a)
+            rhs = rng.random(p.sizes()[a])
+            ref = schemes.DirectSolver(K).solve(rhs)
+            x = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
+            rep = g.solve_continuum(a, T(rhs), x)
+            err = rel(x.cpu().numpy(), ref)
+            print(name, a, rep["iters"][a], err)
+            assert err < 1e-10
+
+
+@pytest.mark.parametrize("scheme", ["D", "coupled", "L", "U"])
+def test_trajectory(case, scheme):
+    name, p = case
+    nsteps = 20 if name == "c1" else 4
+    ref = schemes.run(p, scheme, nsteps, keep="all")
+    with mcdec.Problem(p, scheme=scheme, tol=1e-14) as g:
+        for n in range(1, nsteps + 1):
+            rep = g.step(1)
+            err = rel(g.get_states(), ref[n])
+            assert err < 1e-10, (name, scheme, n, err, rep)
+
+
+def test_ex_scheme_small_tau():
+    p = media.small_problem(n=40, seed=2, nseg=4, tau=1e-5, nsteps=3)
+    ref = schemes.run(p, "EX", 3, keep="last")
+    with mcdec.Problem(p, scheme="EX", tol=1e-14) as g:
+        g.step(3)
+        assert rel(g.get_states(), ref) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["ragged200", "three70"])
+def test_mixed_precision_refinement(name):
+    p = CASES[name]()
+    ref = schemes.run(p, "D", 3, keep="last")
+    with mcdec.Problem(p, precision="mixed", outer_tol=1e-12, inner_tol=1e-5) as g:
+        rep = g.step(3)
+        err = rel(g.get_states(), ref)
+        print(name, rep, err)
+        assert err < 1e-8
+        assert all(c == 1 for c in rep["converged"])
+
+
+def test_noconv_is_transactional():
+    p = media.small_problem(n=64, seed=3, nseg=4)
+    with mcdec.Problem(p, tol=1e-14, max_iter=1) as g:
+        before = g.get_states()
+        with pytest.raises(mcdec.McError) as ei:
+            g.step(1)
+        assert ei.value.status == mcdec.MC_ENOCONV
+        after = g.get_states()
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b)
+
+
+def test_invalid_descriptor_rejected():
+    p = media.small_problem(n=16, seed=3, nseg=2)
+    p.host = p.host.copy()
+    p.host[0] = 16 * 16 + 5
+    with pytest.raises(mcdec.McError) as ei:
+        mcdec.Problem(p)
+    assert ei.value.status == mcdec.MC_EINVAL and "host" in str(ei.value)
