@@ -70,9 +70,10 @@ typedef enum {
 
 typedef enum {
   MC_JACOBI = 0, /* z = r / diag                                                               */
-  MC_BIC0 = 1    /* block incomplete Cholesky, zero fill: the grid split into 64-column x TY-row
-                    blocks and the fracture graph into its chains of consecutive cells; inside a
-                    block, IC(0) in natural order; couplings between blocks are dropped        */
+  MC_BIC0 = 1    /* block incomplete Cholesky, zero fill: the grid split into 64-column x 16-row
+                    blocks and the fracture graph into its chains of consecutive connected cells;
+                    inside a block, IC(0) in natural order (exact Cholesky on a chain);
+                    couplings between blocks are dropped                                        */
 } mc_precond;
 
 /* One continuum on the Omega grid. */
@@ -119,7 +120,7 @@ typedef struct {
   int32_t max_outer;     /* MC_MIXED: maximum refinement passes                                */
   double inner_tol;      /* MC_MIXED: inner FP32 PCG tolerance relative to the outer residual  */
   int32_t check_every;   /* PCG iterations launched between host convergence polls (0 = auto)  */
-  int32_t tile_rows;     /* grid tile height in rows (0 = auto: 16)                             */
+  int32_t tile_rows;     /* grid tile height in rows: 0 (default) or 32                         */
   void *stream;          /* hipStream_t to order all work on, or NULL (library-owned stream)   */
 } mc_options;
 
@@ -180,6 +181,13 @@ mc_status mc_apply_continuum(mc_problem *p, int32_t alpha, const double *x_dev, 
    Section 3.2).  Device arrays of the total size. */
 mc_status mc_apply_coupled(mc_problem *p, const double *x_dev, double *y_dev);
 
+/* z = M_a^-1 r for continuum a with the problem's preconditioner: Jacobi (z = r / diag) or
+   block IC(0) (MC_BIC0).  M approximates the D-scheme matrix of mc_solve_continuum; PCG
+   converges to the same solution with either (the preconditioner changes only iteration
+   counts; no preconditioner appears in the paper's scheme itself).  Device arrays of that
+   continuum's size; r and z must not overlap. */
+mc_status mc_apply_precond(mc_problem *p, int32_t alpha, const double *r_dev, double *z_dev);
+
 /* b_dev = right-hand side of continuum a in the D-scheme from the current state p^{n-1}:
    M_a/tau p_a^{n-1} + sum_{b!=a} Q_ab p_b^{n-1} + F_a (Section 3.3).  Always FP64. */
 mc_status mc_assemble_rhs(mc_problem *p, int32_t alpha, double *b_dev);
@@ -198,9 +206,11 @@ mc_status mc_get_info(const mc_problem *p, mc_info *info);
    failed mc_create_problem / server call.  Never NULL. */
 const char *mc_last_error(const mc_problem *p);
 
-/* Kernel timing on the problem's stream (HIP events around each launch of the dominant
-   kernel family).  which: 0 = grid operator kernel, 1 = grid update kernel.  enable = 1 starts
-   recording (and clears totals), 0 stops. */
+/* Kernel timing on the problem's main stream: HIP events bound to the dispatch of sampled
+   launches of the grid PCG kernels (they time the kernel execution itself).  which: 0 = grid
+   operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z).  enable >= 1
+   starts recording and clears the totals, sampling one launch in `enable` (1 = every launch;
+   each sampled launch costs the stream a few microseconds); 0 stops. */
 mc_status mc_profile(mc_problem *p, int32_t enable);
 mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *launches, double *total_ms);
 

@@ -1,0 +1,106 @@
+"""Block incomplete factorization with zero fill (oracle; test infrastructure only).
+
+The paper solves every SPD system with CG and an incomplete factorization preconditioner;
+the GPU path uses a block form of it.  This module states that preconditioner by its plain
+definition so the GPU sweep can be compared with it:
+
+* blocks: the Omega grid cut into 64-column x 16-row blocks; the fracture cells cut into
+  chains (maximal runs of consecutive cells l, l+1 joined by a connection); inside a chain
+  only the couplings between consecutive cells are kept;
+* inside a block, ILU(0) in natural order (Saad, Iterative Methods for Sparse Linear
+  Systems, ILU(0) in IKJ form): for each row i and each k < i in the pattern,
+  a_ik <- a_ik / a_kk, then a_ij <- a_ij - a_ik a_kj for j > k in the pattern of row i.
+  For a symmetric matrix this is IC(0) written as L U; M = L U;
+* couplings between blocks are dropped; z = M^-1 r block by block.
+
+Written with plain Python loops over sparse rows: meant for small test problems.
+"""
+from __future__ import annotations
+
+from typing import Dict, List
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def ilu0(B: sp.spmatrix):
+    """ILU(0) of a square sparse matrix in natural order.  Returns (rows, diag) where rows[i]
+    is a dict col -> value holding L (strictly lower, unit diagonal implied) and U (upper,
+    diagonal included) in the pattern of B."""
+    B = sp.csr_matrix(B)
+    n = B.shape[0]
+    rows: List[Dict[int, float]] = []
+    for i in range(n):
+        rows.append({int(j): float(v) for j, v in zip(B.indices[B.indptr[i]:B.indptr[i + 1]],
+                                                     B.data[B.indptr[i]:B.indptr[i + 1]])})
+    for i in range(1, n):
+        ri = rows[i]
+        for k in sorted(c for c in ri if c < i):
+            ri[k] = ri[k] / rows[k][k]
+            for j, ukj in rows[k].items():
+                if j > k and j in ri:
+                    ri[j] -= ri[k] * ukj
+    return rows
+
+
+def ilu0_solve(rows, r: np.ndarray) -> np.ndarray:
+    n = len(rows)
+    y = np.array(r, np.float64)
+    for i in range(n):
+        for k, v in rows[i].items():
+            if k < i:
+                y[i] -= v * y[k]
+    z = y
+    for i in range(n - 1, -1, -1):
+        s = z[i]
+        for j, v in rows[i].items():
+            if j > i:
+                s -= v * z[j]
+        z[i] = s / rows[i][i]
+    return z
+
+
+def grid_tile_blocks(nx: int, ny: int, tx: int = 64, ty: int = 16) -> List[np.ndarray]:
+    """Row-major cell indices of each tile, in natural (row-major) order inside the tile."""
+    out = []
+    for y0 in range(0, ny, ty):
+        for x0 in range(0, nx, tx):
+            ys = np.arange(y0, min(y0 + ty, ny))
+            xs = np.arange(x0, min(x0 + tx, nx))
+            out.append((ys[:, None] * nx + xs[None, :]).ravel())
+    return out
+
+
+def chain_blocks(nf: int, edges: np.ndarray) -> List[np.ndarray]:
+    linked = set()
+    for a, b in np.asarray(edges).reshape(-1, 2):
+        if abs(int(a) - int(b)) == 1:
+            linked.add(min(int(a), int(b)))
+    out, start = [], 0
+    for l in range(nf - 1):
+        if l not in linked:
+            out.append(np.arange(start, l + 1))
+            start = l + 1
+    if nf:
+        out.append(np.arange(start, nf))
+    return out
+
+
+def block_precond(K: sp.spmatrix, blocks: List[np.ndarray], tridiagonal: bool = False):
+    """Factors of the block preconditioner of K; with tridiagonal=True each block keeps
+    only its diagonal and the couplings between consecutive cells."""
+    K = sp.csr_matrix(K)
+    facs = []
+    for idx in blocks:
+        B = K[idx][:, idx].tocsr()
+        if tridiagonal:
+            B = sp.triu(sp.tril(B, 1), -1).tocsr()
+        facs.append((idx, ilu0(B)))
+    return facs
+
+
+def block_precond_apply(facs, r: np.ndarray) -> np.ndarray:
+    z = np.zeros_like(np.asarray(r, np.float64))
+    for idx, rows in facs:
+        z[idx] = ilu0_solve(rows, r[idx])
+    return z

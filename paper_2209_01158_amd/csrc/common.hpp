@@ -13,27 +13,37 @@
 #define MC_BLOCK 256           // threads per workgroup (4 waves of 64)
 #define MC_TX 64               // grid tile width: one wavefront across 64 consecutive cells
 #define MC_GRAPH_ROWS 256      // fracture rows per workgroup
-#define MC_SLOT 4              // doubles per partial-sum slot
+#define MC_SLOT 8              // doubles per partial-sum slot
+#define MC_TY 32               // grid tile height (rows) of the LDS-staged operator
+#define MC_ICY 16              // rows of a grid block of the block IC(0) preconditioner
+#define MC_ICB (MC_TY / MC_ICY)  // IC(0) blocks per grid tile
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };
 enum { PREC_JACOBI = 0, PREC_BIC0 = 1 };
 enum { ST_RUN = 0, ST_CONV = 1, ST_NOCONV = 2, ST_BREAK = 3 };
 
-// kernel ids for arrival counters (one counter per kernel family, so consecutive launches of
-// different kernels never share a counter)
-enum { KC_INIT = 0, KC_A = 1, KC_B = 2, KC_RES = 3, KC_N = 4 };
-
+// Per-system state.  Reductions never cross workgroups inside a kernel: every kernel writes
+// one partial-sum slot per workgroup, and the next kernel in stream order has each of its
+// workgroups sum all slots of its system in slot order (the same order in every workgroup,
+// so every workgroup obtains the bitwise-identical scalar).  Workgroup 0 of a kernel records
+// the scalars later kernels and the host need; a kernel never reads a field that a
+// workgroup of the same kernel writes.
 struct SysState {
-  double rz, pq, rr, bb, alpha, beta, tol2, rr0;   // PCG scalars (FP64 always); tol2 = tol^2
-  double orr, obb, otol2;                          // outer refinement scalars (MC_MIXED)
-  int iter, done, status, first, max_iter, total_iter;
-  int outer, outer_done, outer_status, max_outer;
-  unsigned int cnt[KC_N];                          // arrival counters per kernel family
-  int nslots;                                      // tiles of this system per launch
-  int pad;
-  double* partials;                                // [nslots * MC_SLOT]
-  int* active;                                     // shared counter of unfinished systems
-  int* oactive;                                    // shared counter of unfinished outer loops
+  double rzh[2];        // (r,z) of iterations with even / odd index
+  double bb;            // ||b||^2 (inner solves: ||r_start||^2)
+  double rr;            // last ||r||^2
+  double rr0;           // ||r||^2 at the start of the (inner) solve
+  double obb, orr;      // refinement: ||b||^2 and the last FP64 ||r||^2
+  double tol2, otol2;   // squared relative tolerances (inner / outer)
+  int iter;             // iterations done by the last (inner) solve
+  int done;             // the (inner) solve has ended
+  int status;           // ST_* of the (inner) solve
+  int total_iter;       // inner iterations summed over refinement passes
+  int outer, outer_done, outer_status;
+  int max_iter, max_outer;
+  int nslots;           // workgroups (partial slots) of this system per launch
+  double* partA;        // [nslots * MC_SLOT] written by operator kernels
+  double* partB;        // [nslots * MC_SLOT] written by update / init / residual kernels
 };
 
 // One continuum block of a system.  Pointers are device memory.  Coefficient arrays exist in
@@ -45,7 +55,6 @@ struct PartD {
   int n;             // unknowns
   int nx, ny;        // grid shape
   int tiles_x;       // grid tiles per row of tiles
-  int trows;         // grid tile height in rows
   int slot0;         // first partial slot of this part inside its system
   int coupled;       // operator includes the off-diagonal transfer blocks (coupled scheme)
   int ex;            // EX split: diagonal excludes S, RHS subtracts S p^{n-1}
@@ -75,6 +84,9 @@ struct PartD {
   const double* fdinv;
   const float* fdinv32;
   const int* chain_ptr;    // (graph) chain boundaries [nchains+1]
+  const int* gtile;        // (graph) work tiles as chain ranges [ntiles+1]
+  const double* cT;        // (graph) conductance between cell l and l-1 of its chain (0 at starts)
+  const float* cT32;
   int nchains;
   int pad2;
   // transfer structure
@@ -99,7 +111,9 @@ struct PartD {
   double* x64;             // FP64 iterate (refinement)
 };
 
+// One workgroup's work: tiles [t0, t1) of a part, reporting into partial slot `slot`.
 struct Tile {
-  int part;
-  int tile;
+  int part;   // -1: padding workgroup (does nothing)
+  int slot;
+  int t0, t1;
 };

@@ -1,6 +1,7 @@
 // Runtime of the MI355X multicontinuum library: device memory of a problem, coefficient
 // setup, launch tables, PCG orchestration for every scheme and precision, and the C ABI.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
@@ -8,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -42,6 +44,21 @@ static bool env_flag(const char* name, bool dflt) {
   return std::atoi(v) != 0;
 }
 
+static int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+// Workgroups per launch over a continuum: one per tile up to a cap, beyond which each
+// workgroup takes a contiguous run of tiles.  Depends only on the continuum's size, so the
+// reduction order of a system never depends on what else shares the launch.
+static int blocks_for(int ntiles, int kind) {
+  const int cap = kind == PART_GRID ? env_int("MCDEC_GRID_BLOCKS", 1024)
+                                    : env_int("MCDEC_GRAPH_BLOCKS", 256);
+  return std::max(1, std::min(ntiles, std::max(cap, 1)));
+}
+
 // ------------------------------------------------------------------------------------
 // device buffers
 // ------------------------------------------------------------------------------------
@@ -74,11 +91,14 @@ struct DevArena {
   }
 };
 
-// A launch table: parts + tiles in device memory, plus per-system slot counts.
+// A launch table: parts in device memory and, per part kind (grid / graph), the list of
+// tiles in launch order.  Kernels are instantiated per kind, so a launch covers the tiles of
+// one kind only.
 struct Table {
   PartD* parts = nullptr;
-  Tile* tiles = nullptr;
-  int nblocks = 0;
+  Tile* tiles[2] = {nullptr, nullptr};
+  int nblk[2] = {0, 0};
+  int cap[2] = {0, 0};
   int nparts = 0;
   std::vector<PartD> hparts;
 };
@@ -87,12 +107,15 @@ struct Cont {  // one continuum
   int kind;    // PART_GRID / PART_GRAPH
   long n;
   int tiles;   // tiles of its part
+  int blocks;  // workgroups (and partial slots) per launch over this continuum
   // FP64 coefficients
   double *diag = nullptr, *tx = nullptr, *ty = nullptr, *F = nullptr, *val = nullptr,
          *mt = nullptr;
   float *diag32 = nullptr, *tx32 = nullptr, *ty32 = nullptr, *val32 = nullptr;
-  double* fdinv = nullptr;
+  double* fdinv = nullptr;   // block IC(0) inverse pivots
   float* fdinv32 = nullptr;
+  double* cT = nullptr;      // (graph) chain conductances to the previous cell
+  float* cT32 = nullptr;
   // state and PCG vectors
   double* ps[2] = {nullptr, nullptr};
   double *b = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *z = nullptr;
@@ -109,8 +132,10 @@ using namespace mc;
 struct mc_problem {
   mc_problem_desc d{};   // scalars only (array pointers are not kept)
   mc_options opt{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // main stream (grid groups, coupled, setup)
+  hipStream_t stream2 = nullptr;  // second stream: the fracture group of a decoupled step
   bool own_stream = false;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_poll[4] = {nullptr, nullptr, nullptr, nullptr};
   int ncont = 0, n_omega = 0, nf = 0, ne = 0;
   long ncell = 0;
   int ty = 16;
@@ -120,15 +145,13 @@ struct mc_problem {
   double* k[2] = {nullptr, nullptr};
   double* src[3] = {nullptr, nullptr, nullptr};
   int *host = nullptr, *rowptr = nullptr, *col = nullptr, *eidx = nullptr, *hptr = nullptr,
-      *hidx = nullptr, *chain_ptr = nullptr;
+      *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr, *cidx = nullptr;
   double *flen = nullptr, *edge_d = nullptr, *sigma_f = nullptr;
-  int nchains = 0;
+  int nchains = 0, ngtiles = 0;
   // systems: 0..ncont-1 decoupled per continuum, ncont = coupled
   SysState* sys = nullptr;
   std::vector<double*> partials;
-  int* counters = nullptr;       // [0] active, [1] outer active
-  int* h_counters = nullptr;     // pinned
-  SysState* h_sys = nullptr;     // pinned
+  SysState* h_sys = nullptr;     // pinned mirror of the system records
   int cur = 0;                   // state ping-pong index
   long step_count = 0;
   std::map<std::string, Table> tables;
@@ -139,6 +162,8 @@ struct mc_problem {
   std::vector<Ev> ev_free, ev_pending;
   long prof_launch[2] = {0, 0};
   double prof_ms[2] = {0, 0};
+  long prof_count[2] = {0, 0};
+  int prof_every = 8;
 };
 
 namespace mc {
@@ -158,7 +183,6 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0, bool fp32) {
   q.n = (int)C.n;
   q.nx = P->d.nx;
   q.ny = P->d.ny;
-  q.trows = P->ty;
   q.tiles_x = (int)cdiv(P->d.nx, MC_TX);
   q.slot0 = slot0;
   q.ex = P->opt.scheme == MC_SCHEME_EX;
@@ -186,6 +210,9 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0, bool fp32) {
   q.fdinv32 = C.fdinv32;
   q.chain_ptr = P->chain_ptr;
   q.nchains = P->nchains;
+  q.gtile = P->gtile;
+  q.cT = C.cT;
+  q.cT32 = C.cT32;
   if (C.kind == PART_GRID) {
     q.hptr = P->nf ? P->hptr : nullptr;
     q.hidx = P->hidx;
@@ -225,25 +252,41 @@ static Table& upload_table(mc_problem* P, const std::string& key, std::vector<Pa
     return it->second;
   Table T;
   if (it != P->tables.end()) T = it->second;
-  // tile list: parts in order, tiles in natural order, then the XCD-aware launch order
-  std::vector<Tile> nat;
-  for (int pi = 0; pi < (int)parts.size(); ++pi) {
-    int nt = parts[pi].kind == PART_GRID
-                 ? (int)(cdiv(parts[pi].nx, MC_TX) * cdiv(parts[pi].ny, parts[pi].trows))
-                 : (int)cdiv(parts[pi].n, MC_GRAPH_ROWS);
-    for (int t = 0; t < nt; ++t) nat.push_back(Tile{pi, t});
-  }
-  std::vector<int> ord = xcd_order((int)nat.size(), env_flag("MCDEC_XCD", true) ? 8 : 1);
-  std::vector<Tile> tiles(ord.size());
-  for (size_t b = 0; b < ord.size(); ++b) tiles[b] = ord[b] >= 0 ? nat[ord[b]] : Tile{-1, 0};
   if (!T.parts || T.nparts < (int)parts.size()) T.parts = P->mem.alloc<PartD>(parts.size() + 2);
-  if (!T.tiles || T.nblocks < (int)tiles.size()) T.tiles = P->mem.alloc<Tile>(tiles.size() + 8);
   HIPCHK(hipMemcpyAsync(T.parts, parts.data(), parts.size() * sizeof(PartD),
                         hipMemcpyHostToDevice, P->stream));
-  HIPCHK(hipMemcpyAsync(T.tiles, tiles.data(), tiles.size() * sizeof(Tile),
-                        hipMemcpyHostToDevice, P->stream));
+  const bool xcd = env_flag("MCDEC_XCD", true);
+  std::vector<Tile> kept[2];
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<Tile>& tiles = kept[kind];
+    for (int pi = 0; pi < (int)parts.size(); ++pi) {
+      const PartD& q = parts[pi];
+      if (q.kind != kind) continue;
+      const Cont& C = P->cont[q.cont];
+      const int nt = C.tiles, nb = C.blocks;
+      // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die j
+      // of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
+      std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
+      for (int b : ord) {
+        if (b < 0) {
+          tiles.push_back(Tile{-1, 0, 0, 0});
+          continue;
+        }
+        const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
+        tiles.push_back(Tile{pi, q.slot0 + b, t0, t1});
+      }
+      while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0});
+    }
+    if (!tiles.empty() && (!T.tiles[kind] || T.cap[kind] < (int)tiles.size())) {
+      T.tiles[kind] = P->mem.alloc<Tile>(tiles.size() + 8);
+      T.cap[kind] = (int)tiles.size() + 8;
+    }
+    if (!tiles.empty())
+      HIPCHK(hipMemcpyAsync(T.tiles[kind], tiles.data(), tiles.size() * sizeof(Tile),
+                            hipMemcpyHostToDevice, P->stream));
+    T.nblk[kind] = (int)tiles.size();
+  }
   HIPCHK(hipStreamSynchronize(P->stream));   // host vectors die at return
-  T.nblocks = (int)tiles.size();
   T.nparts = (int)parts.size();
   T.hparts = std::move(parts);
   P->tables[key] = T;
@@ -313,6 +356,48 @@ static void build_coefficients(mc_problem* P) {
     hipLaunchKernelGGL(k_setup_graph, dim3(cdiv(P->nf, 256)), dim3(256), 0, P->stream, g);
   }
   HIPCHK(hipGetLastError());
+  if (P->opt.precond == MC_BIC0) {
+    for (auto& C : P->cont) {
+      if (!C.fdinv) C.fdinv = P->mem.alloc<double>(C.n);
+      if (!C.z) C.z = P->mem.alloc<double>(C.n);
+      if (C.kind == PART_GRID) {
+        GridIC0Setup g;
+        g.nx = P->d.nx;
+        g.ny = P->d.ny;
+        g.tiles_x = (int)cdiv(P->d.nx, MC_TX);
+        g.ntiles = C.tiles;
+        g.diag = C.diag;
+        g.tx = C.tx;
+        g.ty = C.ty;
+        g.dinv = C.fdinv;
+        hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)C.tiles * MC_ICB, 64)), dim3(64), 0, P->stream, g);
+      } else {
+        if (!C.cT) C.cT = P->mem.alloc<double>(C.n);
+        ChainSetup g;
+        g.nchains = P->nchains;
+        g.chain_ptr = P->chain_ptr;
+        g.cidx = P->cidx;
+        g.val = C.val;
+        g.diag = C.diag;
+        g.cT = C.cT;
+        g.dinv = C.fdinv;
+        hipLaunchKernelGGL(k_setup_chains, dim3(cdiv(P->nchains, 64)), dim3(64), 0, P->stream, g);
+      }
+    }
+    HIPCHK(hipGetLastError());
+    // FP32 copies of the grid factor and conductances read by the tile sweeps
+    for (auto& C : P->cont) {
+      if (C.kind != PART_GRID) continue;
+      auto cv = [&](double* a, float*& b, long n) {
+        if (!b) b = P->mem.alloc<float>(n);
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, P->stream, a, b, n);
+      };
+      cv(C.fdinv, C.fdinv32, C.n);
+      cv(C.tx, C.tx32, C.n);
+      cv(C.ty, C.ty32, C.n);
+    }
+    HIPCHK(hipGetLastError());
+  }
   if (P->opt.precision == MC_MIXED) {
     for (auto& C : P->cont) {
       auto cv = [&](double* a, float*& b, long n) {
@@ -321,6 +406,11 @@ static void build_coefficients(mc_problem* P) {
         hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, P->stream, a, b, n);
       };
       cv(C.diag, C.diag32, C.n);
+      if (P->opt.precond == MC_BIC0) {
+        cv(C.fdinv, C.fdinv32, C.n);
+        if (C.kind == PART_GRAPH) cv(C.cT, C.cT32, C.n);
+        if (!C.z32) C.z32 = P->mem.alloc<float>(C.n);
+      }
       if (C.kind == PART_GRID) {
         cv(C.tx, C.tx32, C.n);
         cv(C.ty, C.ty32, C.n);
@@ -346,10 +436,9 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   if (!m.empty()) fail(P, m);
   m = validate_options(o);
   if (!m.empty()) fail(P, m);
-  if (o.precond == MC_BIC0) fail(P, "block IC(0) is not available in this build");
   P->d = d;
   P->opt = o;
-  P->ty = o.tile_rows > 0 ? o.tile_rows : 16;
+  P->ty = MC_TY;
   P->n_omega = d.n_omega;
   P->nf = d.nf;
   P->ne = d.ne;
@@ -361,6 +450,10 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     HIPCHK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
     P->own_stream = true;
   }
+  HIPCHK(hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  for (auto& e : P->ev_poll) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   hipStream_t s = P->stream;
   DevArena& M = P->mem;
   // inputs
@@ -386,6 +479,11 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     P->hidx = M.upload(hm.hidx.data(), hm.hidx.size(), s);
     P->chain_ptr = M.upload(chains.data(), chains.size(), s);
     P->nchains = (int)chains.size() - 1;
+    std::vector<int> gt = build_graph_tiles(chains, MC_GRAPH_ROWS);
+    std::vector<int> ce = chain_prev_entry(d.nf, g, chains);
+    P->gtile = M.upload(gt.data(), gt.size(), s);
+    P->cidx = M.upload(ce.data(), ce.size(), s);
+    P->ngtiles = (int)gt.size() - 1;
     if (d.src_f) P->src[d.n_omega] = M.upload(d.src_f, d.nf, s);
   }
   // continua
@@ -395,7 +493,8 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     const bool grid = c < d.n_omega;
     C.kind = grid ? PART_GRID : PART_GRAPH;
     C.n = grid ? P->ncell : d.nf;
-    C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, P->ty)) : (int)cdiv(d.nf, MC_GRAPH_ROWS);
+    C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY)) : P->ngtiles;
+    C.blocks = blocks_for(C.tiles, C.kind);
     C.diag = M.alloc<double>(C.n);
     C.F = M.alloc<double>(C.n);
     if (grid) {
@@ -418,19 +517,17 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   // systems: one per continuum + the coupled one
   const int nsys = P->ncont + 1;
   P->sys = M.alloc<SysState>(nsys);
-  P->counters = M.alloc<int>(4);
-  HIPCHK(hipHostMalloc((void**)&P->h_counters, 4 * sizeof(int), hipHostMallocDefault));
   HIPCHK(hipHostMalloc((void**)&P->h_sys, nsys * sizeof(SysState), hipHostMallocDefault));
   std::vector<SysState> hs(nsys);
   std::memset(hs.data(), 0, nsys * sizeof(SysState));
   int coupled_slots = 0;
-  for (int c = 0; c < P->ncont; ++c) coupled_slots += P->cont[c].tiles;
+  for (int c = 0; c < P->ncont; ++c) coupled_slots += P->cont[c].blocks;
   for (int sI = 0; sI < nsys; ++sI) {
-    int ns = sI < P->ncont ? P->cont[sI].tiles : coupled_slots;
+    const int ns = sI < P->ncont ? P->cont[sI].blocks : coupled_slots;
     hs[sI].nslots = ns;
-    hs[sI].partials = M.alloc<double>((size_t)ns * MC_SLOT);
-    hs[sI].active = P->counters;
-    hs[sI].oactive = P->counters + 1;
+    hs[sI].partA = M.alloc<double>((size_t)ns * MC_SLOT);
+    hs[sI].partB = M.alloc<double>((size_t)ns * MC_SLOT);
+    hs[sI].done = 1;
   }
   HIPCHK(hipMemcpyAsync(P->sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
@@ -440,21 +537,17 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
 // ------------------------------------------------------------------------------------
 // profiling helpers
 // ------------------------------------------------------------------------------------
-static void prof_begin(mc_problem* P, int which, mc_problem::Ev& e) {
+static mc_problem::Ev prof_take(mc_problem* P, int which) {
   if (P->ev_free.empty()) {
     mc_problem::Ev n;
     HIPCHK(hipEventCreate(&n.a));
     HIPCHK(hipEventCreate(&n.b));
     P->ev_free.push_back(n);
   }
-  e = P->ev_free.back();
+  mc_problem::Ev e = P->ev_free.back();
   P->ev_free.pop_back();
   e.which = which;
-  HIPCHK(hipEventRecord(e.a, P->stream));
-}
-static void prof_end(mc_problem* P, mc_problem::Ev& e) {
-  HIPCHK(hipEventRecord(e.b, P->stream));
-  P->ev_pending.push_back(e);
+  return e;
 }
 static void prof_harvest(mc_problem* P) {
   for (auto& e : P->ev_pending) {
@@ -471,110 +564,288 @@ static void prof_harvest(mc_problem* P) {
 // ------------------------------------------------------------------------------------
 // solve orchestration
 // ------------------------------------------------------------------------------------
+// A group is a set of systems (a contiguous range of system records) whose tiles are
+// launched together on one stream.  Decoupled continua of different kinds form separate
+// groups on separate streams, so the small, latency-bound fracture solve overlaps the
+// bandwidth-bound grid solve.  The host advances each group as a small state machine and
+// only ever waits on an event recorded after a copy of that group's system records.
+struct Group {
+  hipStream_t s = nullptr;
+  const Table* T = nullptr;
+  int kinds = 0;      // bit k set: launch the kind-k tiles of the table
+  int s0 = 0, s1 = 0; // system records [s0, s1)
+  bool mixed = false, assemble = true;
+  int phase = 0;      // 0 start, 1 iterating, 2 after a residual (mixed), 3 finished
+  int K = 8;
+  int k = 0;          // next PCG iteration index
+  int outer = 0;
+  SysState* hbuf = nullptr;
+  hipEvent_t ev = nullptr;
+  bool inflight = false;
+};
+
 template <class T, int PREC>
-static void launch_iter(mc_problem* P, const Table& Tb) {
-  mc_problem::Ev e;
-  if (P->prof) prof_begin(P, 0, e);
-  hipLaunchKernelGGL((k_pcg_A<T, PREC>), dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream,
-                     Tb.parts, Tb.tiles, P->sys);
-  if (P->prof) prof_end(P, e);
-  if (P->prof) prof_begin(P, 1, e);
-  hipLaunchKernelGGL((k_pcg_B<T, PREC>), dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream,
-                     Tb.parts, Tb.tiles, P->sys);
-  if (P->prof) prof_end(P, e);
-}
-
-static void poll(mc_problem* P) {
-  HIPCHK(hipMemcpyAsync(P->h_counters, P->counters, 2 * sizeof(int), hipMemcpyDeviceToHost,
-                        P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
-  if (P->prof) prof_harvest(P);
-}
-
-static void set_sys_params(mc_problem* P, const std::vector<int>& systems, double tol,
-                           int max_iter, bool mixed) {
-  // small per-solve parameters written into the device system records
-  for (int sI : systems) {
-    SysState* S = P->sys + sI;
-    double t2 = tol * tol;
-    HIPCHK(hipMemcpyAsync(&S->tol2, &t2, sizeof(double), hipMemcpyHostToDevice, P->stream));
-    HIPCHK(hipMemcpyAsync(&S->max_iter, &max_iter, sizeof(int), hipMemcpyHostToDevice,
-                          P->stream));
-    if (mixed) {
-      double o2 = P->opt.outer_tol * P->opt.outer_tol;
-      HIPCHK(hipMemcpyAsync(&S->otol2, &o2, sizeof(double), hipMemcpyHostToDevice, P->stream));
-      HIPCHK(hipMemcpyAsync(&S->max_outer, &P->opt.max_outer, sizeof(int),
-                            hipMemcpyHostToDevice, P->stream));
+static void launch_iter(mc_problem* P, Group& G, int k, int outer_check) {
+  const Table& Tb = *G.T;
+  auto L = [&](auto kern, int kind, int which, auto... extra) {
+    if (!(G.kinds >> kind & 1) || Tb.nblk[kind] == 0) return;
+    if (P->prof && kind == PART_GRID && G.s == P->stream &&
+        (P->prof_count[which]++ % P->prof_every) == 0) {
+      // events bound to this dispatch time the kernel itself; they cost the stream a few
+      // microseconds per dispatch, so only every prof_every-th launch is sampled
+      mc_problem::Ev e = prof_take(P, which);
+      hipExtLaunchKernelGGL(kern, dim3(Tb.nblk[kind]), dim3(MC_BLOCK), 0, G.s, e.a, e.b, 0,
+                            Tb.parts, Tb.tiles[kind], P->sys, extra...);
+      P->ev_pending.push_back(e);
+    } else {
+      hipLaunchKernelGGL(kern, dim3(Tb.nblk[kind]), dim3(MC_BLOCK), 0, G.s, Tb.parts,
+                         Tb.tiles[kind], P->sys, extra...);
     }
-  }
-  HIPCHK(hipStreamSynchronize(P->stream));   // sources are stack values
+  };
+  L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0, k, outer_check);
+  L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0, k, outer_check);
+  L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1, k);
+  L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1, k);
 }
 
-// Runs PCG to completion for the systems of table Tb (FP64).  Returns after every system is
-// done; statuses are in the device system records.
+// launch the grid-kind kernel over the grid tiles and the graph-kind kernel over the graph
+// tiles of the group's table (each only if the group has tiles of that kind)
+template <class KG, class KF, class... A>
+static void launch2(const Group& G, KG kg, KF kf, A... args) {
+  if ((G.kinds & 1) && G.T->nblk[PART_GRID])
+    hipLaunchKernelGGL(kg, dim3(G.T->nblk[PART_GRID]), dim3(MC_BLOCK), 0, G.s, G.T->parts,
+                       G.T->tiles[PART_GRID], args...);
+  if ((G.kinds & 2) && G.T->nblk[PART_GRAPH])
+    hipLaunchKernelGGL(kf, dim3(G.T->nblk[PART_GRAPH]), dim3(MC_BLOCK), 0, G.s, G.T->parts,
+                       G.T->tiles[PART_GRAPH], args...);
+}
+
+template <class KG, class KF>
+static void launch_all(mc_problem* P, const Table& T, KG kg, KF kf) {
+  Group g;
+  g.s = P->stream;
+  g.T = &T;
+  g.kinds = 3;
+  launch2(g, kg, kf);
+}
+
+static void submit_poll(mc_problem* P, Group& G) {
+  HIPCHK(hipMemcpyAsync(G.hbuf, P->sys + G.s0, (G.s1 - G.s0) * sizeof(SysState),
+                        hipMemcpyDeviceToHost, G.s));
+  HIPCHK(hipEventRecord(G.ev, G.s));
+  G.inflight = true;
+}
+
+// Chunk size from the observed convergence: the number of further iterations the slowest
+// unfinished system needs if its residual keeps shrinking at its average rate so far.
+static int next_chunk(const Group& G) {
+  double need = 0;
+  bool any = false;
+  for (int k = 0; k < G.s1 - G.s0; ++k) {
+    const SysState& S = G.hbuf[k];
+    if (S.done) continue;
+    any = true;
+    const double target = S.tol2 * S.bb;
+    if (S.iter < 2 || !(S.rr < S.rr0) || !(S.rr > 0) || !(target > 0)) {
+      need = std::max(need, 16.0);
+      continue;
+    }
+    const double rate = std::log(S.rr / S.rr0) / S.iter;   // per-iteration log decrease
+    double rem = std::log(target / S.rr) / rate;
+    if (!(rem > 0)) rem = 1;
+    need = std::max(need, rem);
+  }
+  if (!any) return 1;
+  int K = (int)std::ceil(0.85 * need) + 1;
+  return std::max(2, std::min(K, 256));
+}
+
+static bool all_done(const Group& G, bool outer) {
+  for (int k = 0; k < G.s1 - G.s0; ++k)
+    if (!(outer ? G.hbuf[k].outer_done : G.hbuf[k].done)) return false;
+  return true;
+}
+
 template <int PREC>
-static void run_pcg64(mc_problem* P, const Table& Tb, int nsys_active, int max_iter) {
-  int K = P->opt.check_every > 0 ? P->opt.check_every : 8;
-  long launched = 0;
-  for (;;) {
-    for (int k = 0; k < K; ++k) launch_iter<double, PREC>(P, Tb);
-    HIPCHK(hipGetLastError());
-    launched += K;
-    poll(P);
-    if (P->h_counters[0] <= 0) break;
-    if (launched > (long)max_iter + 2L * K + 4)
-      throw Error{MC_EDEVICE, "PCG did not report completion within max_iter launches"};
-    if (K < 64) K *= 2;   // long solves poll less often
-  }
-}
-
-static void solve_systems64(mc_problem* P, const Table& Tb, const std::vector<int>& systems,
-                            bool assemble) {
-  const int ns = (int)systems.size();
-  set_sys_params(P, systems, P->opt.tol, P->opt.max_iter, false);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, P->stream, P->sys, P->ncont + 1,
-                     P->counters, ns, 0, 0);
-  if (assemble)
-    hipLaunchKernelGGL(k_rhs, dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream, Tb.parts,
-                       Tb.tiles);
-  hipLaunchKernelGGL((k_init<PREC_JACOBI>), dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream,
-                     Tb.parts, Tb.tiles, P->sys);
-  HIPCHK(hipGetLastError());
-  run_pcg64<PREC_JACOBI>(P, Tb, ns, P->opt.max_iter);
-}
-
-static void solve_systems_mixed(mc_problem* P, const Table& Tb, const std::vector<int>& systems,
-                                bool assemble) {
-  const int ns = (int)systems.size();
-  set_sys_params(P, systems, P->opt.inner_tol, P->opt.max_iter, true);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, P->stream, P->sys, P->ncont + 1,
-                     P->counters, 0, ns, 1);
-  if (assemble)
-    hipLaunchKernelGGL(k_rhs, dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream, Tb.parts,
-                       Tb.tiles);
-  const double it2 = P->opt.inner_tol * P->opt.inner_tol;
-  for (int outer = 0; outer <= P->opt.max_outer + 1; ++outer) {
-    hipLaunchKernelGGL(k_residual, dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream, Tb.parts,
-                       Tb.tiles, P->sys, it2);
-    HIPCHK(hipGetLastError());
-    poll(P);
-    if (P->h_counters[1] <= 0) return;
-    int K = P->opt.check_every > 0 ? P->opt.check_every : 8;
-    long launched = 0;
-    while (P->h_counters[0] > 0) {
-      for (int k = 0; k < K; ++k) launch_iter<float, PREC_JACOBI>(P, Tb);
-      HIPCHK(hipGetLastError());
-      launched += K;
-      poll(P);
-      if (launched > (long)P->opt.max_iter + 2L * K + 4)
-        throw Error{MC_EDEVICE, "inner PCG did not report completion"};
-      if (K < 64) K *= 2;
+static void advance_t(mc_problem* P, Group& G) {
+  const int max_iter = P->opt.max_iter;
+  auto chunk = [&](auto tag, int first_outer_check) {
+    using T = decltype(tag);
+    const long room = (long)max_iter + 2 - G.k;
+    const int K = (int)std::max<long>(1, std::min<long>(G.K, room));
+    for (int j = 0; j < K; ++j) {
+      launch_iter<T, PREC>(P, G, G.k, j == 0 ? first_outer_check : 0);
+      G.k += 1;
     }
-    hipLaunchKernelGGL(k_correct, dim3(Tb.nblocks), dim3(MC_BLOCK), 0, P->stream, Tb.parts,
-                       Tb.tiles, P->sys);
-    hipLaunchKernelGGL(k_outer_count, dim3(1), dim3(64), 0, P->stream, P->sys, P->ncont + 1);
+    HIPCHK(hipGetLastError());
+    submit_poll(P, G);
+  };
+  if (!G.mixed) {
+    if (G.phase == 0) {
+      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, G.s, P->sys, G.s0, G.s1);
+      if (G.assemble) launch2(G, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+      launch2(G, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, P->sys);
+      G.k = 0;
+      G.K = 8;
+      G.phase = 1;
+    } else {
+      if (all_done(G, false)) {
+        G.phase = 3;
+        return;
+      }
+      if (G.k > (long)max_iter + 1)
+        throw Error{MC_EDEVICE, "PCG did not report completion within max_iter iterations"};
+      G.K = next_chunk(G);
+    }
+    chunk(double(0), 0);
+    return;
   }
-  throw Error{MC_EDEVICE, "refinement loop did not terminate"};
+  // mixed precision: FP64 residual -> FP32 inner PCG -> FP64 correction, repeated
+  if (G.phase == 0) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, G.s, P->sys, G.s0, G.s1);
+    if (G.assemble) launch2(G, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+    launch2(G, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
+    G.outer = 0;
+    G.k = 0;
+    G.K = 8;
+    G.phase = 1;
+    chunk(float(0), 1);
+    return;
+  }
+  if (all_done(G, true)) {
+    G.phase = 3;
+    return;
+  }
+  if (all_done(G, false)) {
+    // every unfinished system ended its inner solve: correct, new residual, restart
+    if (G.outer > P->opt.max_outer + 1) throw Error{MC_EDEVICE, "refinement did not terminate"};
+    launch2(G, k_correct<PART_GRID>, k_correct<PART_GRAPH>, P->sys);
+    launch2(G, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
+    G.outer += 1;
+    G.k = 0;
+    G.K = 8;
+    chunk(float(0), 1);
+    return;
+  }
+  if (G.k > (long)max_iter + 1) throw Error{MC_EDEVICE, "inner PCG did not finish"};
+  G.K = next_chunk(G);
+  chunk(float(0), 0);
+}
+
+static void advance(mc_problem* P, Group& G) {
+  if (P->opt.precond == MC_BIC0) advance_t<PREC_BIC0>(P, G);
+  else advance_t<PREC_JACOBI>(P, G);
+}
+
+// Runs one group's state machine to completion on the calling host thread.
+static void drive_group(mc_problem* P, Group& g) {
+  advance(P, g);
+  while (g.phase != 3) {
+    if (!g.inflight) {
+      advance(P, g);
+      continue;
+    }
+    hipError_t q = hipEventQuery(g.ev);
+    if (q == hipSuccess) {
+      g.inflight = false;
+      advance(P, g);
+    } else if (q != hipErrorNotReady) {
+      HIPCHK(q);
+    }
+  }
+}
+
+// Runs every group to completion.  With more than one group, each group is driven by its
+// own host thread, so that enqueueing a long chunk of one group never delays the next
+// chunk of another.
+static void run_groups(mc_problem* P, std::vector<Group>& G) {
+  // streams of the groups start after all work already ordered on the main stream
+  HIPCHK(hipEventRecord(P->ev_fork, P->stream));
+  for (size_t k = 0; k < G.size(); ++k) {
+    Group& g = G[k];
+    if (g.s != P->stream) HIPCHK(hipStreamWaitEvent(g.s, P->ev_fork, 0));
+    g.phase = 0;
+    g.inflight = false;
+    g.hbuf = P->h_sys + g.s0;   // disjoint ranges of the pinned mirror
+    g.ev = P->ev_poll[k];
+  }
+  if (G.size() == 1) {
+    drive_group(P, G[0]);
+  } else {
+    std::vector<Error> errs(G.size(), Error{MC_OK, ""});
+    std::vector<std::thread> th;
+    for (size_t k = 1; k < G.size(); ++k)
+      th.emplace_back([&, k] {
+        try {
+          drive_group(P, G[k]);
+        } catch (const Error& e) {
+          errs[k] = e;
+        } catch (const std::exception& e) {
+          errs[k] = Error{MC_EDEVICE, e.what()};
+        }
+      });
+    try {
+      drive_group(P, G[0]);
+    } catch (const Error& e) {
+      errs[0] = e;
+    } catch (const std::exception& e) {
+      errs[0] = Error{MC_EDEVICE, e.what()};
+    }
+    for (auto& t : th) t.join();
+    for (auto& e : errs)
+      if (e.st != MC_OK) throw e;
+  }
+  for (auto& g : G)
+    if (g.s != P->stream) {
+      HIPCHK(hipEventRecord(P->ev_join, g.s));
+      HIPCHK(hipStreamWaitEvent(P->stream, P->ev_join, 0));
+    }
+}
+
+static void set_sys_params(mc_problem* P, int s0, int s1, double tol, int max_iter,
+                           bool mixed) {
+  HIPCHK(hipMemcpyAsync(P->h_sys, P->sys, (P->ncont + 1) * sizeof(SysState),
+                        hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  for (int sI = s0; sI < s1; ++sI) {
+    SysState& S = P->h_sys[sI];
+    S.tol2 = tol * tol;
+    S.max_iter = max_iter;
+    S.otol2 = P->opt.outer_tol * P->opt.outer_tol;
+    S.max_outer = P->opt.max_outer;
+  }
+  HIPCHK(hipMemcpyAsync(P->sys + s0, P->h_sys + s0, (s1 - s0) * sizeof(SysState),
+                        hipMemcpyHostToDevice, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+}
+
+// Solve the systems [s0, s1) of table Tb: one group per kind on its own stream when the
+// kinds belong to different systems (decoupled), else one group.
+static void solve_table(mc_problem* P, const Table& Tb, int s0, int s1, bool assemble,
+                        bool mixed, bool split_kinds) {
+  set_sys_params(P, s0, s1, mixed ? P->opt.inner_tol : P->opt.tol, P->opt.max_iter, mixed);
+  std::vector<Group> G;
+  auto mk = [&](int kinds, int a, int b, hipStream_t st) {
+    Group g;
+    g.s = st;
+    g.T = &Tb;
+    g.kinds = kinds;
+    g.s0 = a;
+    g.s1 = b;
+    g.mixed = mixed;
+    g.assemble = assemble;
+    G.push_back(g);
+  };
+  if (split_kinds && Tb.nblk[PART_GRID] && Tb.nblk[PART_GRAPH]) {
+    // decoupled: grid systems are [s0, s0 + n_grid), the fracture system follows
+    int ngrid = 0;
+    for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID;
+    mk(1, s0, s0 + ngrid, P->stream);
+    mk(2, s0 + ngrid, s1, env_flag("MCDEC_ONE_STREAM", false) ? P->stream : P->stream2);
+  } else {
+    mk(3, s0, s1, P->stream);
+  }
+  run_groups(P, G);
 }
 
 // Reads back the system records; fills the report; returns the first failing status.
@@ -629,7 +900,7 @@ static std::vector<PartD> coupled_parts(mc_problem* P) {
   const int sysI = P->ncont;
   for (int c = 0; c < P->ncont; ++c) {
     PartD q = base_part(P, c, sysI, slot, false);
-    slot += P->cont[c].tiles;
+    slot += P->cont[c].blocks;
     q.coupled = 1;
     parts.push_back(q);
   }
@@ -653,14 +924,13 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
   mc_status st;
   if (sch == MC_SCHEME_COUPLED) {
     Table& T = upload_table(P, "coupled" + std::to_string(P->cur), coupled_parts(P));
-    solve_systems64(P, T, {P->ncont}, true);
+    solve_table(P, T, P->ncont, P->ncont + 1, true, false, false);
     st = collect(P, {P->ncont}, {0}, rep, false);
     fill_coupled_report(P, rep);
   } else if (sch == MC_SCHEME_D || sch == MC_SCHEME_EX) {
     Table& T = upload_table(P, std::string(mixed ? "dm" : "d") + std::to_string(P->cur),
                             decoupled_parts(P, all, mixed));
-    if (mixed) solve_systems_mixed(P, T, all, true);
-    else solve_systems64(P, T, all, true);
+    solve_table(P, T, 0, P->ncont, true, mixed, true);
     st = collect(P, all, all, rep, mixed);
   } else {
     // L: ascending index order, each continuum sees the new values of those before it;
@@ -674,8 +944,7 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
       for (size_t j = 0; j < k; ++j) parts[0].tsrc[order[j]] = P->cont[order[j]].ps[1 - P->cur];
       Table& T = upload_table(P, std::string(mixed ? "sm" : "s") + std::to_string(c) + "_" +
                                      std::to_string(P->cur), parts);
-      if (mixed) solve_systems_mixed(P, T, {c}, true);
-      else solve_systems64(P, T, {c}, true);
+      solve_table(P, T, c, c + 1, true, mixed, false);
       mc_status s1 = collect(P, {c}, {c}, rep, mixed);
       if (s1 != MC_OK) {
         st = s1;
@@ -764,8 +1033,13 @@ mc_status mc_destroy(mc_problem* P) {
     (void)hipEventDestroy(e.b);
   }
   P->mem.release();
-  if (P->h_counters) (void)hipHostFree(P->h_counters);
   if (P->h_sys) (void)hipHostFree(P->h_sys);
+  if (P->stream2) (void)hipStreamSynchronize(P->stream2);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  for (auto e : P->ev_poll)
+    if (e) (void)hipEventDestroy(e);
+  if (P->stream2) (void)hipStreamDestroy(P->stream2);
   if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
   delete P;
   return MC_OK;
@@ -804,7 +1078,7 @@ mc_status mc_solve_continuum(mc_problem* P, int32_t alpha, const double* rhs, do
   parts[0].x64 = x;
   parts[0].b = const_cast<double*>(rhs);
   mc::Table& T = mc::upload_table(P, "solve" + std::to_string(alpha), parts);
-  mc::solve_systems64(P, T, {alpha}, false);
+  mc::solve_table(P, T, alpha, alpha + 1, false, false, false);
   mc_report r;
   std::memset(&r, 0, sizeof(r));
   r.n_cont = P->ncont;
@@ -825,8 +1099,7 @@ mc_status mc_apply_continuum(mc_problem* P, int32_t alpha, const double* x, doub
   parts[0].x = const_cast<double*>(x);
   parts[0].q = y;
   mc::Table& T = mc::upload_table(P, "apply" + std::to_string(alpha), parts);
-  hipLaunchKernelGGL(mc::k_apply, dim3(T.nblocks), dim3(MC_BLOCK), 0, P->stream, T.parts,
-                     T.tiles);
+  mc::launch_all(P, T, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
   return MC_OK;
@@ -845,8 +1118,27 @@ mc_status mc_apply_coupled(mc_problem* P, const double* x, double* y) {
     off += P->cont[c].n;
   }
   mc::Table& T = mc::upload_table(P, "applyc", parts);
-  hipLaunchKernelGGL(mc::k_apply, dim3(T.nblocks), dim3(MC_BLOCK), 0, P->stream, T.parts,
-                     T.tiles);
+  mc::launch_all(P, T, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return MC_OK;
+  ABI_END(P)
+}
+
+mc_status mc_apply_precond(mc_problem* P, int32_t alpha, const double* r, double* z) {
+  if (!P) return MC_EINVAL;
+  ABI_BEGIN
+  if (alpha < 0 || alpha >= P->ncont) throw mc::Error{MC_EINVAL, "alpha out of range"};
+  if (!r || !z) throw mc::Error{MC_EINVAL, "r and z must be device pointers"};
+  std::vector<PartD> parts = mc::decoupled_parts(P, {alpha}, false);
+  parts[0].r = const_cast<double*>(r);
+  parts[0].z = z;
+  mc::Table& T = mc::upload_table(P, "prec" + std::to_string(alpha), parts);
+  if (P->opt.precond == MC_BIC0)
+    mc::launch_all(P, T, mc::k_precond<PREC_BIC0, PART_GRID>, mc::k_precond<PREC_BIC0, PART_GRAPH>);
+  else
+    mc::launch_all(P, T, mc::k_precond<PREC_JACOBI, PART_GRID>,
+                   mc::k_precond<PREC_JACOBI, PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
   return MC_OK;
@@ -863,8 +1155,7 @@ mc_status mc_assemble_rhs(mc_problem* P, int32_t alpha, double* b) {
   parts[0].x64 = P->cont[alpha].r;    // warm-start copy goes to scratch
   parts[0].coupled = 0;
   mc::Table& T = mc::upload_table(P, "rhs" + std::to_string(alpha), parts);
-  hipLaunchKernelGGL(mc::k_rhs, dim3(T.nblocks), dim3(MC_BLOCK), 0, P->stream, T.parts,
-                     T.tiles);
+  mc::launch_all(P, T, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
   return MC_OK;
@@ -898,8 +1189,6 @@ mc_status mc_set_options(mc_problem* P, const mc_options* o) {
   ABI_BEGIN
   std::string m = mc::validate_options(*o);
   if (!m.empty()) throw mc::Error{MC_EINVAL, m};
-  const int ty = o->tile_rows > 0 ? o->tile_rows : 16;
-  if (ty != P->ty) throw mc::Error{MC_EINVAL, "tile_rows cannot change after creation"};
   if (o->stream && o->stream != (void*)P->stream)
     throw mc::Error{MC_EINVAL, "the stream cannot change after creation"};
   const bool rebuild = (o->scheme == MC_SCHEME_EX) != (P->opt.scheme == MC_SCHEME_EX) ||
@@ -937,6 +1226,8 @@ mc_status mc_profile(mc_problem* P, int32_t enable) {
   if (enable) {
     P->prof_launch[0] = P->prof_launch[1] = 0;
     P->prof_ms[0] = P->prof_ms[1] = 0;
+    P->prof_count[0] = P->prof_count[1] = 0;
+    P->prof_every = enable > 1 ? enable : 8;
   }
   return MC_OK;
   ABI_END(P)

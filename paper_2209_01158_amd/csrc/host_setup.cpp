@@ -90,8 +90,8 @@ std::string validate_options(const mc_options& o) {
     if (o.scheme == MC_SCHEME_COUPLED) return "the coupled scheme runs in FP64 only";
   }
   if (o.check_every < 0) return "check_every must be >= 0";
-  if (o.tile_rows < 0 || o.tile_rows > 64 || (o.tile_rows % 4) != 0)
-    return "tile_rows must be 0 (auto) or a multiple of 4 up to 64";
+  if (o.tile_rows != 0 && o.tile_rows != 32)
+    return "tile_rows must be 0 (default) or 32 in this build";
   return "";
 }
 
@@ -142,6 +142,36 @@ std::vector<int> build_chains(int nf, const GraphCSR& g) {
   }
   if (nf > 0) ptr.push_back(nf);
   return ptr;
+}
+
+std::vector<int> build_graph_tiles(const std::vector<int>& chain_ptr, int target) {
+  std::vector<int> t{0};
+  const int nch = (int)chain_ptr.size() - 1;
+  int cells = 0;
+  for (int c = 0; c < nch; ++c) {
+    cells += chain_ptr[c + 1] - chain_ptr[c];
+    if (cells >= target) {
+      t.push_back(c + 1);
+      cells = 0;
+    }
+  }
+  if (t.back() != nch) t.push_back(nch);
+  return t;
+}
+
+std::vector<int> chain_prev_entry(int nf, const GraphCSR& g, const std::vector<int>& chain_ptr) {
+  std::vector<int> e(nf, -1);
+  std::vector<char> start(nf + 1, 0);
+  for (size_t c = 0; c + 1 < chain_ptr.size(); ++c) start[chain_ptr[c]] = 1;
+  for (int l = 1; l < nf; ++l) {
+    if (start[l]) continue;
+    for (int j = g.rowptr[l]; j < g.rowptr[l + 1]; ++j)
+      if (g.col[j] == l - 1) {
+        e[l] = j;
+        break;
+      }
+  }
+  return e;
 }
 
 std::vector<int> xcd_order(int n, int nxcd) {

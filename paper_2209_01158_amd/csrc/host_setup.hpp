@@ -32,6 +32,14 @@ HostMap build_host_map(int ncell, int nf, const int32_t* host);
 // Chains: maximal runs of consecutive fracture cells l, l+1 joined by a connection.
 std::vector<int> build_chains(int nf, const GraphCSR& g);
 
+// Fracture work tiles: consecutive whole chains packed until a tile holds at least
+// `target` cells.  Returns chain boundaries of the tiles, [ntiles+1].
+std::vector<int> build_graph_tiles(const std::vector<int>& chain_ptr, int target);
+
+// For every fracture cell l that is not the first of its chain, the CSR entry of its
+// connection to l-1; -1 for chain starts.
+std::vector<int> chain_prev_entry(int nf, const GraphCSR& g, const std::vector<int>& chain_ptr);
+
 // Launch order of `n` work items such that hardware round-robin dispatch over `nxcd`
 // compute dies gives die j a contiguous range of items.  Entries of -1 are padding.
 std::vector<int> xcd_order(int n, int nxcd);

@@ -17,6 +17,15 @@ template <class T> __device__ __forceinline__ const T* pick(const double* d, con
 template <> __device__ __forceinline__ const double* pick<double>(const double* d, const float*) { return d; }
 template <> __device__ __forceinline__ const float* pick<float>(const double*, const float* f) { return f; }
 
+// Pointers read from descriptors are generic; these casts let the compiler emit global
+// (not flat) memory instructions, which keep the LDS counter out of the memory waits.
+template <class T>
+using gconst = const __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gconst<T> gc(const T* p) {
+  return (gconst<T>)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -48,47 +57,50 @@ __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Every block of a system deposits its NV partial sums in its slot; the block that arrives
-// last sums all slots in slot order (so the result does not depend on arrival order or on
-// other systems in the launch) and returns true with the totals in tot (all threads).
+// Sum of all partial slots of a system, in slot order.  Every workgroup of the system runs
+// the same loads and the same reduction tree, so all obtain the identical value.  Must be
+// reached by all threads of the workgroup.
 template <int NV>
-__device__ bool arrive(SysState& S, int slot, double (&v)[NV], int kc, double (&tot)[NV]) {
+__device__ __forceinline__ void reduce_slots(const double* __restrict__ part, int nslots,
+                                             double (&tot)[NV]) {
   __shared__ double red[4][NV];
-  __shared__ int last;
   __shared__ double bc[NV];
-  block_sum<NV>(v, red);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) st_agent(&S.partials[slot * MC_SLOT + k], v[k]);
-    unsigned prev = __hip_atomic_fetch_add(&S.cnt[kc], 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    last = (prev == (unsigned)(S.nslots - 1));
-  }
-  __syncthreads();
-  if (!last) return false;
   double a[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) a[k] = 0.0;
-  for (int s = threadIdx.x; s < S.nslots; s += MC_BLOCK) {
+  for (int s = threadIdx.x; s < nslots; s += MC_BLOCK) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] += ld_agent(&S.partials[s * MC_SLOT + k]);
+    for (int k = 0; k < NV; ++k) a[k] += part[s * MC_SLOT + k];
   }
   block_sum<NV>(a, red);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) bc[k] = a[k];
-    __hip_atomic_store(&S.cnt[kc], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) tot[k] = bc[k];
-  return true;
 }
 
-__device__ __forceinline__ void finish(SysState& S, int status) {
-  S.done = 1;
-  S.status = status;
-  __hip_atomic_fetch_add(S.active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Reduce this workgroup's NV values and store them in its slot.
+template <int NV>
+__device__ __forceinline__ void write_slot(double* __restrict__ part, int slot, double (&v)[NV]) {
+  __shared__ double red[4][NV];
+  block_sum<NV>(v, red);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) part[slot * MC_SLOT + k] = v[k];
+  }
+}
+
+// The done flag is written by workgroup 0 of a kernel while other workgroups of the same
+// kernel may read it; every workgroup reaches the same decision from the same reduction, so
+// either value it observes leads to the same behaviour.  Relaxed atomics keep it race-free.
+__device__ __forceinline__ int ld_flag(int* f) {
+  return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(int* f, int v) {
+  __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ bool finite(double v) { return v == v && v - v == 0.0; }
@@ -247,71 +259,344 @@ __device__ __forceinline__ double graph_coupling(const PartD& P, int l, const VP
   return acc;
 }
 
+
 // ------------------------------------------------------------------------------------
-// right-hand side assembly (transfer lagged / taken from tsrc), always FP64
-// b = M/tau p_old + F + sum_b Q_ab p_b (decoupled) [- S p_old for EX];  coupled: no transfer
-// x = p_old (warm start)
+// block incomplete Cholesky, zero fill (IC(0) in natural order inside each block)
+//   M = (D + E) D^-1 (D + E^T),  E = strictly lower part of A restricted to the block,
+//   d_i = a_ii - sum_{j<i, j~i in block} a_ij^2 / d_j;  we store dinv_i = 1/d_i.
+// Grid blocks are the 64 x MC_TY tiles; fracture blocks are the chains (tridiagonal, so
+// IC(0) is their exact Cholesky factorization).
 // ------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ parts,
-                                                  const Tile* __restrict__ tiles) {
-  const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
-  const PartD& P = parts[t.part];
-  double* x = P.x64;   // the FP64 iterate (the same buffer as P.x in FP64 solves)
-  if (P.kind == PART_GRID) {
-    const int x0 = (t.tile % P.tiles_x) * MC_TX, y0 = (t.tile / P.tiles_x) * P.trows;
-    const int cx = x0 + (threadIdx.x & 63);
-    if (cx >= P.nx) return;
-    for (int r = threadIdx.x >> 6; r < P.trows; r += 4) {
-      const int cy = y0 + r;
-      if (cy >= P.ny) break;
-      const long i = (long)cy * P.nx + cx;
-      const double po = P.pold[i];
-      double b = P.mtau * po + (P.F ? P.F[i] : 0.0);
-      if (!P.coupled) {
-        double tr = 0.0, S = 0.0;
-        if (P.s12 != 0.0 && P.tsrc[1 - P.cont]) {
-          tr += P.s12 * P.tsrc[1 - P.cont][i];
-          S += P.s12;
-        }
-        if (P.hptr) {
-          const double* pf = P.tsrc[P.n_omega];
-          for (int j = P.hptr[i]; j < P.hptr[i + 1]; ++j) {
-            const int l = P.hidx[j];
-            tr += P.hsig[l] * pf[l];
-            S += P.hsig[l];
-          }
-        }
-        b += tr;
-        if (P.ex) b -= S * po;
-      }
-      P.b[i] = b;
-      x[i] = po;
-    }
-  } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l >= P.n) return;
-    const double po = P.pold[l];
-    double b = P.mt[l] * po + (P.F ? P.F[l] : 0.0);
-    if (!P.coupled) {
-      const long h = P.host[l];
-      double tr = P.fsig0[l] * P.tsrc[0][h];
-      double S = P.fsig0[l];
-      if (P.n_omega > 1) {
-        tr += P.fsig1[l] * P.tsrc[1][h];
-        S += P.fsig1[l];
-      }
-      b += tr;
-      if (P.ex) b -= S * po;
-    }
-    P.b[l] = b;
-    x[l] = po;
+struct ChainSetup {
+  int nchains;
+  const int* chain_ptr;
+  const int* cidx;     // CSR entry of (l, l-1), -1 at chain starts
+  const double* val;
+  const double* diag;
+  double* cT;
+  double* dinv;
+};
+
+__global__ void k_setup_chains(ChainSetup g) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= g.nchains) return;
+  const int l0 = g.chain_ptr[c], l1 = g.chain_ptr[c + 1];
+  double dprev = g.diag[l0];
+  g.cT[l0] = 0.0;
+  g.dinv[l0] = 1.0 / dprev;
+  for (int l = l0 + 1; l < l1; ++l) {
+    const double t = g.cidx[l] >= 0 ? g.val[g.cidx[l]] : 0.0;
+    const double d = g.diag[l] - t * t / dprev;
+    g.cT[l] = t;
+    g.dinv[l] = 1.0 / d;
+    dprev = d;
   }
 }
 
+struct GridIC0Setup {
+  int nx, ny, tiles_x, ntiles;
+  const double* diag;
+  const double* tx;
+  const double* ty;
+  double* dinv;   // first holds d, then 1/d
+};
+
+// One thread per IC(0) block (64 columns x MC_ICY rows): pivots in natural order (row by
+// row, west to east) with the west and south couplings that stay inside the block.
+__global__ void k_setup_grid_ic0(GridIC0Setup g) {
+  const int unit = blockIdx.x * blockDim.x + threadIdx.x;
+  if (unit >= g.ntiles * MC_ICB) return;
+  const int tile = unit / MC_ICB;
+  const int x0 = (tile % g.tiles_x) * MC_TX;
+  const int y0 = (tile / g.tiles_x) * MC_TY + (unit % MC_ICB) * MC_ICY;
+  const int x1 = min(x0 + MC_TX, g.nx), y1 = min(y0 + MC_ICY, g.ny);
+  if (y0 >= g.ny) return;
+  for (int y = y0; y < y1; ++y)
+    for (int x = x0; x < x1; ++x) {
+      const long i = (long)y * g.nx + x;
+      double d = g.diag[i];
+      if (x > x0) {
+        const double t = g.tx[i - 1];
+        d -= t * t / g.dinv[i - 1];
+      }
+      if (y > y0) {
+        const double t = g.ty[i - g.nx];
+        d -= t * t / g.dinv[i - g.nx];
+      }
+      g.dinv[i] = d;
+    }
+  for (int y = y0; y < y1; ++y)
+    for (int x = x0; x < x1; ++x) {
+      const long i = (long)y * g.nx + x;
+      g.dinv[i] = 1.0 / g.dinv[i];
+    }
+}
+
+// ---- wave-level scans of affine maps u -> A + B u ------------------------------------
+// DPP moves on 32-bit halves.  A lane whose source is outside the row (or whose row is
+// masked) keeps `old`, which we set to the identity map (A = 0, B = 1).
+template <int CTRL, int ROWM>
+__device__ __forceinline__ double dpp_d(double old, double src) {
+  const long long o = __builtin_bit_cast(long long, old), s = __builtin_bit_cast(long long, src);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, CTRL, ROWM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), CTRL, ROWM, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, int ROWM>
+__device__ __forceinline__ float dpp_d(float old, float src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                __builtin_bit_cast(int, src),
+                                                                CTRL, ROWM, 0xF, false));
+}
+template <int CTRL, int ROWM, class T>
+__device__ __forceinline__ void combine_dpp(T& A, T& B) {
+  const T Ap = dpp_d<CTRL, ROWM>((T)0, A);
+  const T Bp = dpp_d<CTRL, ROWM>((T)1, B);
+  A = A + B * Ap;
+  B = B * Bp;
+}
+// Inclusive prefix over the 64 lanes, lane 0 applied first: row_shr 1,2,4,8 inside each
+// row of 16 lanes, then row_bcast:15 (rows 1, 3 take the end of the row before) and
+// row_bcast:31 (rows 2, 3 take lane 31).
+template <class T>
+__device__ __forceinline__ void scan_maps_up(T& A, T& B) {
+  combine_dpp<0x111, 0xF>(A, B);
+  combine_dpp<0x112, 0xF>(A, B);
+  combine_dpp<0x114, 0xF>(A, B);
+  combine_dpp<0x118, 0xF>(A, B);
+  combine_dpp<0x142, 0xA>(A, B);
+  combine_dpp<0x143, 0xC>(A, B);
+}
+// Inclusive prefix with lane 63 applied first: row_shl 1,2,4,8 inside rows, then rows 0 and
+// 2 take the first lane of the row after them, then rows 0 and 1 take lane 32.
+template <class T>
+__device__ __forceinline__ void scan_maps_down(T& A, T& B) {
+  combine_dpp<0x101, 0xF>(A, B);
+  combine_dpp<0x102, 0xF>(A, B);
+  combine_dpp<0x104, 0xF>(A, B);
+  combine_dpp<0x108, 0xF>(A, B);
+  const int lane = threadIdx.x & 63, row = lane >> 4;
+  // the shuffles run on every lane (a lane can only read lanes that execute them); the
+  // lanes that do not take a value then combine with the identity
+  {
+    const int src = ((row + 1) << 4) & 63;
+    const bool take = row == 0 || row == 2;
+    T Ap = __shfl(A, src, 64), Bp = __shfl(B, src, 64);
+    Ap = take ? Ap : (T)0;
+    Bp = take ? Bp : (T)1;
+    A = A + B * Ap;
+    B = B * Bp;
+  }
+  {
+    const bool take = row < 2;
+    T Ap = __shfl(A, 32, 64), Bp = __shfl(B, 32, 64);
+    Ap = take ? Ap : (T)0;
+    Bp = take ? Bp : (T)1;
+    A = A + B * Ap;
+    B = B * Bp;
+  }
+}
+
+// z = M^-1 r on one fracture chain [l0, l1) by one wavefront.  Forward u_l = (r_l + T_l
+// u_{l-1}) / d_l and backward z_l = u_l + T_{l+1} z_{l+1} / d_l are first-order affine
+// recurrences: each lane composes the maps of CH consecutive cells, a 64-lane scan gives
+// every lane its incoming value, and each lane then runs its cells.
+template <class T>
+__device__ void chain_solve(const T* __restrict__ rin, T* __restrict__ z,
+                            const T* __restrict__ dinvin, const T* __restrict__ cTin, int l0,
+                            int l1) {
+  constexpr int CH = 4;
+  const gconst<T> r = gc(rin);
+  const gconst<T> dinv = gc(dinvin);
+  const gconst<T> cT = gc(cTin);
+  const int lane = threadIdx.x & 63;
+  T carry = (T)0;
+  for (int base = l0; base < l1; base += 64 * CH) {
+    const int s = base + lane * CH;
+    T A = (T)0, B = (T)1;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int l = s + j;
+      if (l < l1) {
+        const T di = dinv[l];
+        A = r[l] * di + (cT[l] * di) * A;
+        B = (cT[l] * di) * B;
+      }
+    }
+    scan_maps_up(A, B);
+    T Ae = __shfl_up(A, 1, 64), Be = __shfl_up(B, 1, 64);
+    if (lane == 0) {
+      Ae = (T)0;
+      Be = (T)1;
+    }
+    T u = Ae + Be * carry;
+#pragma unroll
+    for (int j = 0; j < CH; ++j) {
+      const int l = s + j;
+      if (l < l1) {
+        const T di = dinv[l];
+        u = r[l] * di + (cT[l] * di) * u;
+        z[l] = u;
+      }
+    }
+    carry = __shfl(A + B * carry, 63, 64);
+  }
+  __threadfence_block();   // the backward pass reads u written by other lanes
+  carry = (T)0;
+  for (int top = l1; top > l0; top -= 64 * CH) {
+    const int lo = max(l0, top - 64 * CH);
+    const int e = top - lane * CH;   // this lane: cells e-1 down to e-CH (>= lo)
+    T A = (T)0, B = (T)1;
+#pragma unroll
+    for (int j = 1; j <= CH; ++j) {
+      const int l = e - j;
+      if (l >= lo) {
+        const T c = l + 1 < l1 ? cT[l + 1] * dinv[l] : (T)0;
+        A = z[l] + c * A;
+        B = c * B;
+      }
+    }
+    scan_maps_up(A, B);
+    T Ae = __shfl_up(A, 1, 64), Be = __shfl_up(B, 1, 64);
+    if (lane == 0) {
+      Ae = (T)0;
+      Be = (T)1;
+    }
+    T zz = Ae + Be * carry;
+#pragma unroll
+    for (int j = 1; j <= CH; ++j) {
+      const int l = e - j;
+      if (l >= lo) {
+        const T c = l + 1 < l1 ? cT[l + 1] * dinv[l] : (T)0;
+        zz = z[l] + c * zz;
+        z[l] = zz;
+      }
+    }
+    carry = __shfl(A + B * carry, 63, 64);
+    __threadfence_block();
+  }
+}
+
+// Block IC(0) solve on one grid tile by one wavefront, entirely in registers (lane =
+// column).  rrow(y, i, act) returns this column's residual in tile row y (cell i; it may
+// update the iterate and store r on the way; 0 for cells outside the grid).  The inverse
+// pivots and face conductances are read once, as FP32 copies (a preconditioner needs no
+// more; PCG still converges to the FP64 solution).  Rows are swept in order; inside a row
+// the west (forward) or east (backward) coupling is a first-order recurrence across lanes,
+// solved by a 64-lane scan.  z is stored to zout.
+// Dot products: with M = (D + E) D^-1 (D + E^T), the forward values u = (D + E)^-1 r and
+// z = M^-1 r satisfy (D + E^T) z = D u, hence (r, z) = (M z, z) = sum_i d_i u_i^2: both
+// (r,z) and (r,r) are complete after the forward sweep, so r never has to stay live.
+template <class T, bool HAS_T, class RR>
+__device__ __forceinline__ void ic0_column_sweep(const PartD& P, int unit, const RR& rrow,
+                                                 T* __restrict__ zout, double& rz,
+                                                 double& rr) {
+  const int lane = threadIdx.x & 63;
+  const int nx = P.nx, ny = P.ny;
+  const int tile = unit / MC_ICB;   // unit = IC(0) block: tile and its band of MC_ICY rows
+  const int x0 = (tile % P.tiles_x) * MC_TX;
+  const int y0 = (tile / P.tiles_x) * MC_TY + (unit % MC_ICB) * MC_ICY;
+  const int cx = x0 + lane;
+  const int cxs = min(cx, nx - 1);
+  const bool colact = cx < nx;
+  const gconst<float> dinv = gc(P.fdinv32);
+  const gconst<float> tx = gc(P.tx32);
+  const gconst<float> ty = gc(P.ty32);
+  const float tc = (float)P.tconst;
+  float dv[MC_ICY], te[MC_ICY], tn[MC_ICY];
+#pragma unroll
+  for (int y = 0; y < MC_ICY; ++y) {
+    const int cy = y0 + y;
+    const bool act = colact && cy < ny;
+    const long i = (long)min(cy, ny - 1) * nx + cxs;   // a valid cell for every lane
+    const float d = dinv[i];
+    float e, n;
+    if constexpr (HAS_T) {
+      e = tx[i];
+      n = ty[i];
+    } else {
+      e = cx + 1 < nx ? tc : 0.0f;
+      n = cy + 1 < ny ? tc : 0.0f;
+    }
+    dv[y] = act ? d : 0.0f;
+    te[y] = act ? e : 0.0f;
+    tn[y] = act && y + 1 < MC_ICY ? n : 0.0f;   // couplings inside the tile only
+  }
+  T u[MC_ICY];
+  T uprev = (T)0;
+#pragma unroll
+  for (int y = 0; y < MC_ICY; ++y) {
+    const int cy = y0 + y;
+    const bool act = colact && cy < ny;
+    const long i = (long)cy * nx + cx;
+    const T ri = rrow(y, i, act);
+    const T di = (T)dv[y];
+    // west conductance = east conductance of the lane to the left (0 for lane 0)
+    const float tw = __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, te[y]), 0x138, 0xF, 0xF,
+                                           false));
+    const T ts = y > 0 ? (T)tn[y - 1] : (T)0;
+    T a = (ri + ts * uprev) * di;
+    T b = (T)tw * di;
+    scan_maps_up(a, b);
+    u[y] = a;
+    uprev = a;
+    rr += (double)ri * (double)ri;
+    if (act) rz += (double)a * (double)a / (double)dv[y];
+  }
+  T zabove = (T)0;
+#pragma unroll
+  for (int y = MC_ICY - 1; y >= 0; --y) {
+    const T di = (T)dv[y];
+    const T e = lane < 63 ? (T)te[y] : (T)0;
+    T a = u[y] + (T)tn[y] * zabove * di;
+    T b = e * di;
+    scan_maps_down(a, b);
+    zabove = a;
+    const int cy = y0 + y;
+    if (colact && cy < ny) zout[(long)cy * nx + cx] = a;
+  }
+}
+
+template <class T, class RR>
+__device__ __forceinline__ void ic0_column(const PartD& P, int unit, const RR& rrow,
+                                           T* __restrict__ zout, double& rz, double& rr) {
+  if (P.has_t) ic0_column_sweep<T, true>(P, unit, rrow, zout, rz, rr);
+  else ic0_column_sweep<T, false>(P, unit, rrow, zout, rz, rr);
+}
+
+// Runs f(unit) for the IC(0) blocks of the workgroup's tile run, one wavefront per block.
+template <class F>
+__device__ __forceinline__ void for_wave_tiles(const Tile& t, const F& f) {
+  for (int unit = t.t0 * MC_ICB + (int)(threadIdx.x >> 6); unit < t.t1 * MC_ICB; unit += 4)
+    f(unit);
+}
+
 // ------------------------------------------------------------------------------------
-// PCG (templated on the vector/coefficient type T; reductions always FP64)
+// work iteration: a workgroup walks the tiles [t0, t1) of its part
 // ------------------------------------------------------------------------------------
+template <class F>
+__device__ __forceinline__ void grid_cells(const PartD& P, int tile, const F& f) {
+  const int x0 = (tile % P.tiles_x) * MC_TX, y0 = (tile / P.tiles_x) * MC_TY;
+  const int cx = x0 + (threadIdx.x & 63);
+  if (cx >= P.nx) return;
+  const int yend = min(y0 + MC_TY, P.ny);
+  for (int cy = y0 + (threadIdx.x >> 6); cy < yend; cy += 4) f(cx, cy, (long)cy * P.nx + cx);
+}
+
+template <int KIND, class FG, class FF>
+__device__ __forceinline__ void for_cells(const PartD& P, const Tile& t, const FG& fg,
+                                          const FF& ff) {
+  for (int tile = t.t0; tile < t.t1; ++tile) {
+    if constexpr (KIND == PART_GRID) {
+      grid_cells(P, tile, fg);
+    } else {
+      const int l0 = P.chain_ptr[P.gtile[tile]], l1 = P.chain_ptr[P.gtile[tile + 1]];
+      for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) ff(l);
+    }
+  }
+}
+
 template <class T, int PREC>
 __device__ __forceinline__ T zval(const PartD& P, long i) {
   if (PREC == PREC_JACOBI) {
@@ -323,320 +608,473 @@ __device__ __forceinline__ T zval(const PartD& P, long i) {
   }
 }
 
-// Iterate a grid tile: calls f(cx, cy, i) for every cell of the tile owned by this thread.
-template <class F>
-__device__ __forceinline__ void for_tile_cells(const PartD& P, int tile, const F& f) {
-  const int x0 = (tile % P.tiles_x) * MC_TX, y0 = (tile / P.tiles_x) * P.trows;
-  const int cx = x0 + (threadIdx.x & 63);
-  if (cx >= P.nx) return;
-  const int yend = min(y0 + P.trows, P.ny);
-  for (int cy = y0 + (threadIdx.x >> 6); cy < yend; cy += 4) f(cx, cy, (long)cy * P.nx + cx);
+// ------------------------------------------------------------------------------------
+// right-hand side assembly, always FP64 (Section 3.3, D-scheme; Section 3.2, coupled):
+// decoupled  b = M/tau p_old + F + sum_b Q_ab p_b   [EX: - S p_old]
+// coupled    b = M/tau p_old + F
+// and the warm start x = p_old
+// ------------------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ parts,
+                                                  const Tile* __restrict__ tiles) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  double* x = P.x64;
+  for_cells<KIND>(
+      P, t,
+      [&](int, int, long i) {
+        const double po = P.pold[i];
+        double b = P.mtau * po + (P.F ? P.F[i] : 0.0);
+        if (!P.coupled) {
+          double tr = 0.0, S = 0.0;
+          if (P.s12 != 0.0 && P.tsrc[1 - P.cont]) {
+            tr += P.s12 * P.tsrc[1 - P.cont][i];
+            S += P.s12;
+          }
+          if (P.hptr) {
+            const double* pf = P.tsrc[P.n_omega];
+            for (int j = P.hptr[i]; j < P.hptr[i + 1]; ++j) {
+              const int l = P.hidx[j];
+              tr += P.hsig[l] * pf[l];
+              S += P.hsig[l];
+            }
+          }
+          b += tr;
+          if (P.ex) b -= S * po;
+        }
+        P.b[i] = b;
+        x[i] = po;
+      },
+      [&](int l) {
+        const double po = P.pold[l];
+        double b = P.mt[l] * po + (P.F ? P.F[l] : 0.0);
+        if (!P.coupled) {
+          const long h = P.host[l];
+          double tr = P.fsig0[l] * P.tsrc[0][h];
+          double S = P.fsig0[l];
+          if (P.n_omega > 1) {
+            tr += P.fsig1[l] * P.tsrc[1][h];
+            S += P.fsig1[l];
+          }
+          b += tr;
+          if (P.ex) b -= S * po;
+        }
+        P.b[l] = b;
+        x[l] = po;
+      });
 }
 
-// initial residual r = b - A x (FP64); partial (r,z), (b,b), (r,r)
-template <int PREC>
-__global__ void __launch_bounds__(MC_BLOCK) k_init(const PartD* __restrict__ parts,
+// ------------------------------------------------------------------------------------
+// PCG.  Iteration k is the launch pair (k_pcg_A(k), k_pcg_B(k)); k is a launch argument.
+//   init   r = b - A x                               -> partB (rz, rr, bb)
+//   A(k)   from partB: stop test, beta; p_new = z + beta p_old; q = A p_new -> partA (pq)
+//   B(k)   from partA: alpha; x += alpha p; r -= alpha q; z = M^-1 r        -> partB (rz, rr)
+// ------------------------------------------------------------------------------------
+// Shared by the FP64 initial residual and the refinement residual: computes
+// r = b - A x64 per cell (FP64), hands it to `emit(i, r, b)` which stores it in the solve's
+// precision and returns the stored value, then applies the preconditioner to the stored
+// residuals and accumulates (r,z), (r,r) into v[0], v[1].
+template <class T, int PREC, int KIND, class Emit>
+__device__ __forceinline__ void residual_and_precond(const PartD* parts, const PartD& P,
+                                                     const Tile& t, const double* x,
+                                                     T* __restrict__ rs, T* __restrict__ z,
+                                                     const Emit& emit, double (&v)[5],
+                                                     bool use_x64) {
+  auto xs = [&](long j) { return x[j]; };
+  auto xpart = [&](int pi, long j) {
+    return use_x64 ? parts[pi].x64[j] : ((const double*)parts[pi].x)[j];
+  };
+  auto res = [&](int cx, int cy, long i) {
+    double ax = grid_Av<double>(P, cx, cy, i, x[i], xs);
+    if (P.coupled) ax += grid_coupling(parts, P, i, xpart);
+    return P.b[i] - ax;
+  };
+  auto resg = [&](int l) {
+    double ax = graph_Av<double>(P, l, x[l], xs);
+    if (P.coupled) ax += graph_coupling(P, l, xpart);
+    return P.b[l] - ax;
+  };
+  const T* d = pick<T>(P.diag, P.diag32);
+  if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
+    auto rrow = [&](int, long i, bool act) -> T {
+      if (!act) return (T)0;
+      const int cy = (int)(i / P.nx), cx = (int)(i - (long)cy * P.nx);
+      return emit(i, res(cx, cy, i), P.b[i]);
+    };
+    for_wave_tiles(t, [&](int tile) { ic0_column<T>(P, tile, rrow, z, v[0], v[1]); });
+  } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
+    const T* dinv = pick<T>(P.fdinv, P.fdinv32);
+    const T* cT = pick<T>(P.cT, P.cT32);
+    for (int tile = t.t0; tile < t.t1; ++tile) {
+      const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
+      const int l0 = P.chain_ptr[c0], l1 = P.chain_ptr[c1];
+      for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) emit(l, resg(l), P.b[l]);
+      __syncthreads();
+      for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
+        chain_solve<T>(rs, z, dinv, cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
+      __syncthreads();
+      for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
+        v[0] += (double)rs[l] * (double)z[l];
+        v[1] += (double)rs[l] * (double)rs[l];
+      }
+    }
+  } else {
+    for_cells<KIND>(
+        P, t,
+        [&](int cx, int cy, long i) {
+          const T rn = emit(i, res(cx, cy, i), P.b[i]);
+          v[0] += (double)rn * (double)(rn / d[i]);
+          v[1] += (double)rn * (double)rn;
+        },
+        [&](int l) {
+          const T rn = emit(l, resg(l), P.b[l]);
+          v[0] += (double)rn * (double)(rn / d[l]);
+          v[1] += (double)rn * (double)rn;
+        });
+  }
+}
+
+// initial residual r = b - A x (FP64) and z = M^-1 r  -> partB (rz, rr, bb)
+template <int PREC, int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_init(const PartD* __restrict__ parts,
                                                    const Tile* __restrict__ tiles,
                                                    SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
+  if (t.part < 0) return;
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
-  double v[3] = {0.0, 0.0, 0.0};
-  const double* x = (const double*)P.x;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double* r = (double*)P.r;
-  auto xpart = [&](int pi, long j) { return ((const double*)parts[pi].x)[j]; };
-  auto xs = [&](long j) { return x[j]; };
-  auto body = [&](long i, double ax) {
-    const double b = P.b[i];
-    const double ri = b - ax;
+  auto emit = [&](long i, double ri, double b) {
     r[i] = ri;
-    if (PREC == PREC_JACOBI) v[0] += ri * (ri / P.diag[i]);
-    v[1] += b * b;
-    v[2] += ri * ri;
+    v[2] += b * b;
+    return ri;
   };
-  if (P.kind == PART_GRID) {
-    for_tile_cells(P, t.tile, [&](int cx, int cy, long i) {
-      double ax = grid_Av<double>(P, cx, cy, i, x[i], xs);
-      if (P.coupled) ax += grid_coupling(parts, P, i, xpart);
-      body(i, ax);
-    });
-  } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l < P.n) {
-      double ax = graph_Av<double>(P, l, x[l], xs);
-      if (P.coupled) ax += graph_coupling(P, l, xpart);
-      body(l, ax);
-    }
-  }
-  double tot[3];
-  if (arrive<3>(S, P.slot0 + t.tile, v, KC_INIT, tot) && threadIdx.x == 0) {
-    S.rz = tot[0];
-    S.bb = tot[1];
-    S.rr = tot[2];
-    S.rr0 = tot[2];
-    S.iter = 0;
-    S.first = 1;
-    S.beta = 0.0;
-    S.done = 0;
-    S.status = ST_RUN;
-    if (S.rr <= S.tol2 * S.bb) finish(S, ST_CONV);
-    else if (!finite(S.rz) || !finite(S.rr)) finish(S, ST_BREAK);
-  }
+  residual_and_precond<double, PREC, KIND>(parts, P, t, (const double*)P.x, r, (double*)P.z,
+                                           emit, v, false);
+  write_slot<5>(S.partB, t.slot, v);
 }
 
-// q = A p_new, p_new = z + beta p_old (z recomputed where a neighbour needs it); the new
-// direction goes to the other buffer; partial (p_new, q); finalize alpha = (r,z)/(p,q).
-template <class T, int PREC>
+template <class T, int PREC, int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ parts,
                                                     const Tile* __restrict__ tiles,
-                                                    SysState* __restrict__ sys) {
+                                                    SysState* __restrict__ sys, int k,
+                                                    int outer_check) {
+  constexpr int W = MC_TX + 2, H = MC_TY + 2;
+  __shared__ T sp[KIND == PART_GRID ? W * H : 1];
   const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
+  if (t.part < 0) return;
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
-  if (S.done) return;
-  const T beta = (T)S.beta;
-  const bool first = S.first != 0;
-  const int par = S.iter & 1;
-  auto pold = [&](const PartD& Q) { return (const T*)(par ? Q.p2 : Q.p); };
+  if (ld_flag(&S.done)) return;
+  const bool w0 = t.slot == 0;
+  double v[5];
+  reduce_slots<5>(S.partB, S.nslots, v);
+  if (outer_check) {   // first inner iteration after an FP64 residual: refinement test
+    const double orr = v[3];
+    const double obb = S.outer == 0 ? v[4] : S.obb;
+    int ost = ST_RUN;
+    if (orr <= S.otol2 * obb) ost = ST_CONV;
+    else if (!finite(orr)) ost = ST_BREAK;
+    else if (S.outer >= S.max_outer) ost = ST_NOCONV;
+    if (w0) {
+      S.orr = orr;
+      if (S.outer == 0) S.obb = obb;
+    }
+    if (ost != ST_RUN) {
+      if (w0) {
+        S.outer_done = 1;
+        S.outer_status = ost;
+        S.status = ost;
+        S.iter = 0;
+        st_flag(&S.done, 1);
+      }
+      return;
+    }
+  }
+  const double rz = v[0], rr = v[1];
+  const double bb = k == 0 ? v[2] : S.bb;
+  int st = ST_RUN;
+  if (rr <= S.tol2 * bb) st = ST_CONV;
+  else if (!finite(rz) || !finite(rr) || !(rz > 0.0)) st = ST_BREAK;
+  else if (k >= S.max_iter) st = ST_NOCONV;
+  if (w0) {
+    S.rzh[k & 1] = rz;
+    S.rr = rr;
+    S.iter = k;
+    if (k == 0) {
+      S.bb = bb;
+      S.rr0 = rr;
+    }
+  }
+  if (st != ST_RUN) {
+    if (w0) {
+      S.status = st;
+      S.total_iter += k;
+      st_flag(&S.done, 1);
+    }
+    return;
+  }
+  const bool first = k == 0;
+  const T beta = first ? (T)0 : (T)(rz / S.rzh[(k - 1) & 1]);
+  const int par = k & 1;   // p_old in (par ? p2 : p), p_new to the other buffer
   auto pn_of = [&](const PartD& Q, long j) -> T {
     const T z = zval<T, PREC>(Q, j);
-    return first ? z : z + beta * pold(Q)[j];
+    return first ? z : z + beta * ((const T*)(par ? Q.p2 : Q.p))[j];
   };
   T* pnew = (T*)(par ? P.p : P.p2);
   T* q = (T*)P.q;
-  double v[1] = {0.0};
-  auto pself = [&](long j) { return pn_of(P, j); };
-  auto body = [&](long i, T pi, T ax) {
-    if (P.coupled) {
-      auto vp = [&](int pj, long j) { return (double)pn_of(parts[pj], j); };
-      ax = (T)((double)ax + (P.kind == PART_GRID ? grid_coupling(parts, P, i, vp)
-                                                 : graph_coupling(P, (int)i, vp)));
+  double pq = 0.0;
+  if constexpr (KIND == PART_GRID) {
+    const int nx = P.nx, ny = P.ny;
+    const T* d = pick<T>(P.diag, P.diag32);
+    const T* tx = pick<T>(P.tx, P.tx32);
+    const T* ty = pick<T>(P.ty, P.ty32);
+    const T tc = (T)P.tconst;
+    for (int tile = t.t0; tile < t.t1; ++tile) {
+      const int x0 = (tile % P.tiles_x) * MC_TX, y0 = (tile / P.tiles_x) * MC_TY;
+      // stage p_new on the tile and its one-cell halo (zero outside the grid)
+      for (int e = threadIdx.x; e < W * H; e += MC_BLOCK) {
+        const int gx = x0 + e % W - 1, gy = y0 + e / W - 1;
+        T val = (T)0;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) val = pn_of(P, (long)gy * nx + gx);
+        sp[e] = val;
+      }
+      __syncthreads();
+      const int lane = threadIdx.x & 63, cx = x0 + lane;
+      if (cx < nx) {
+        const int yend = min(y0 + MC_TY, ny);
+        for (int cy = y0 + (threadIdx.x >> 6); cy < yend; cy += 4) {
+          const long i = (long)cy * nx + cx;
+          const int c = (cy - y0 + 1) * W + lane + 1;
+          const T pc = sp[c];
+          T acc = d[i] * pc;
+          if (P.has_t) {
+            // tx = 0 on the last column and ty = 0 on the last row, where the halo is 0 too
+            acc -= tx[i] * sp[c + 1];
+            if (cx > 0) acc -= tx[i - 1] * sp[c - 1];
+            acc -= ty[i] * sp[c + W];
+            if (cy > 0) acc -= ty[i - nx] * sp[c - W];
+          } else {
+            acc -= tc * ((sp[c - 1] + sp[c + 1]) + (sp[c - W] + sp[c + W]));
+          }
+          if (P.coupled) {
+            auto vp = [&](int pj, long j) { return (double)pn_of(parts[pj], j); };
+            acc = (T)((double)acc + grid_coupling(parts, P, i, vp));
+          }
+          q[i] = acc;
+          pnew[i] = pc;
+          pq += (double)pc * (double)acc;
+        }
+      }
+      __syncthreads();
     }
-    q[i] = ax;
-    pnew[i] = pi;
-    v[0] += (double)pi * (double)ax;
-  };
-  if (P.kind == PART_GRID) {
-    for_tile_cells(P, t.tile, [&](int cx, int cy, long i) {
-      const T pi = pn_of(P, i);
-      body(i, pi, grid_Av<T>(P, cx, cy, i, pi, pself));
-    });
   } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l < P.n) {
-      const T pl = pn_of(P, l);
-      body(l, pl, graph_Av<T>(P, l, pl, pself));
+    auto pself = [&](long j) { return pn_of(P, j); };
+    for (int tile = t.t0; tile < t.t1; ++tile) {
+      const int l0 = P.chain_ptr[P.gtile[tile]], l1 = P.chain_ptr[P.gtile[tile + 1]];
+      for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
+        const T pl = pn_of(P, l);
+        T acc = graph_Av<T>(P, l, pl, pself);
+        if (P.coupled) {
+          auto vp = [&](int pj, long j) { return (double)pn_of(parts[pj], j); };
+          acc = (T)((double)acc + graph_coupling(P, l, vp));
+        }
+        q[l] = acc;
+        pnew[l] = pl;
+        pq += (double)pl * (double)acc;
+      }
     }
   }
-  double tot[1];
-  if (arrive<1>(S, P.slot0 + t.tile, v, KC_A, tot) && threadIdx.x == 0) {
-    S.pq = tot[0];
-    if (!(S.pq > 0.0) || !finite(S.pq)) finish(S, ST_BREAK);
-    else S.alpha = S.rz / S.pq;
-  }
+  double o[1] = {pq};
+  write_slot<1>(S.partA, t.slot, o);
 }
 
-// x += alpha p, r -= alpha q, z = M^-1 r; partial (r,z), (r,r); finalize beta and the
-// stopping test ||r||^2 <= tol^2 ||b||^2.
-template <class T, int PREC>
-__global__ void __launch_bounds__(MC_BLOCK) k_pcg_B(const PartD* __restrict__ parts,
+template <class T, int PREC, int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_pcg_B(const PartD* __restrict__ parts,
                                                     const Tile* __restrict__ tiles,
-                                                    SysState* __restrict__ sys) {
+                                                    SysState* __restrict__ sys, int k) {
   const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
+  if (t.part < 0) return;
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
-  if (S.done) return;
-  const T alpha = (T)S.alpha;
-  const int par = S.iter & 1;
-  const T* p = (const T*)(par ? P.p : P.p2);   // the buffer k_pcg_A just wrote
+  if (ld_flag(&S.done)) return;
+  double v1[1];
+  reduce_slots<1>(S.partA, S.nslots, v1);
+  const double pq = v1[0];
+  double o[2] = {0.0, 0.0};
+  if (!(pq > 0.0) || !finite(pq)) {
+    // breakdown: every workgroup sees it; the NaN stops the system in the next A
+    o[0] = __builtin_nan("");
+    write_slot<2>(S.partB, t.slot, o);
+    return;
+  }
+  const T alpha = (T)(S.rzh[k & 1] / pq);
+  const int par = k & 1;
+  const T* p = (const T*)(par ? P.p : P.p2);   // the buffer A(k) wrote
   const T* q = (const T*)P.q;
   T* x = (T*)P.x;
   T* r = (T*)P.r;
+  T* z = (T*)P.z;
   const T* d = pick<T>(P.diag, P.diag32);
-  double v[2] = {0.0, 0.0};
-  auto body = [&](long i) {
-    x[i] = x[i] + alpha * p[i];
-    const T ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    if (PREC == PREC_JACOBI) v[0] += (double)ri * (double)(ri / d[i]);
-    v[1] += (double)ri * (double)ri;
-  };
-  if (P.kind == PART_GRID) {
-    for_tile_cells(P, t.tile, [&](int, int, long i) { body(i); });
-  } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l < P.n) body(l);
-  }
-  double tot[2];
-  if (arrive<2>(S, P.slot0 + t.tile, v, KC_B, tot) && threadIdx.x == 0) {
-    const double rz = tot[0];
-    S.rr = tot[1];
-    S.iter += 1;
-    S.total_iter += 1;
-    if (S.rr <= S.tol2 * S.bb) finish(S, ST_CONV);
-    else if (!finite(rz) || !finite(S.rr) || !(rz > 0.0)) finish(S, ST_BREAK);
-    else if (S.iter >= S.max_iter) finish(S, ST_NOCONV);
-    else {
-      S.beta = rz / S.rz;
-      S.rz = rz;
-      S.first = 0;
+  if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
+    // one wavefront per tile: x and r are updated row by row inside the forward sweep
+    T* __restrict__ xw = x;
+    T* __restrict__ rw = r;
+    const gconst<T> pg = gc(p);
+    const gconst<T> qg = gc(q);
+    auto rrow = [&](int, long i, bool act) -> T {
+      if (!act) return (T)0;
+      xw[i] = xw[i] + alpha * pg[i];
+      const T rn = rw[i] - alpha * qg[i];
+      rw[i] = rn;
+      return rn;
+    };
+    for_wave_tiles(t, [&](int tile) { ic0_column<T>(P, tile, rrow, z, o[0], o[1]); });
+  } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
+    const T* dinv = pick<T>(P.fdinv, P.fdinv32);
+    const T* cT = pick<T>(P.cT, P.cT32);
+    for (int tile = t.t0; tile < t.t1; ++tile) {
+      const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
+      const int l0 = P.chain_ptr[c0], l1 = P.chain_ptr[c1];
+      for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
+        x[l] = x[l] + alpha * p[l];
+        r[l] = r[l] - alpha * q[l];
+      }
+      __syncthreads();
+      for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
+        chain_solve<T>(r, z, dinv, cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
+      __syncthreads();
+      for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
+        o[0] += (double)r[l] * (double)z[l];
+        o[1] += (double)r[l] * (double)r[l];
+      }
     }
+  } else {
+    auto body = [&](long i) {
+      x[i] = x[i] + alpha * p[i];
+      const T ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      o[0] += (double)ri * (double)(ri / d[i]);
+      o[1] += (double)ri * (double)ri;
+    };
+    for_cells<KIND>(P, t, [&](int, int, long i) { body(i); }, [&](int l) { body(l); });
   }
+  write_slot<2>(S.partB, t.slot, o);
 }
 
 // ------------------------------------------------------------------------------------
-// mixed precision: FP64 residual of the FP64 iterate, handed to the FP32 inner solve
+// mixed precision: FP64 residual of the FP64 iterate handed to the FP32 inner PCG
+//   r64 = b - A64 x64;  r32 = (float) r64;  x32 = 0   -> partB (rz32, rr32, rr32, rr64, bb)
 // ------------------------------------------------------------------------------------
-// r64 = b - A64 x64; inner r32 = (float) r64, inner x32 = 0; partial (r64,r64), (r32,z32),
-// (r32,r32).  Finalize: outer test ||r64|| <= outer_tol ||b||; otherwise (re)start the inner
-// PCG with tolerance inner_tol relative to ||r32||.
-__global__ void __launch_bounds__(MC_BLOCK) k_residual(const PartD* __restrict__ parts,
+template <int PREC, int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_residual(const PartD* __restrict__ parts,
                                                        const Tile* __restrict__ tiles,
-                                                       SysState* __restrict__ sys,
-                                                       double inner_tol2) {
+                                                       SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
+  if (t.part < 0) return;
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
   if (S.outer_done) return;
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
-  const double* x = P.x64;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   float* r32 = (float*)P.r;
   float* x32 = (float*)P.x;
-  auto xs = [&](long j) { return x[j]; };
-  auto xpart = [&](int pi, long j) { return parts[pi].x64[j]; };
-  auto body = [&](long i, double ax) {
-    const double bi = P.b[i];
-    const double ri = bi - ax;
+  auto emit = [&](long i, double ri, double bi) {
     const float rf = (float)ri;
     r32[i] = rf;
     x32[i] = 0.0f;
-    v[0] += ri * ri;
-    v[1] += (double)rf * (double)(rf / P.diag32[i]);
-    v[2] += (double)rf * (double)rf;
-    v[3] += bi * bi;
+    v[3] += ri * ri;
+    v[4] += bi * bi;
+    return rf;
   };
-  if (P.kind == PART_GRID) {
-    for_tile_cells(P, t.tile, [&](int cx, int cy, long i) {
-      double ax = grid_Av<double>(P, cx, cy, i, x[i], xs);
-      if (P.coupled) ax += grid_coupling(parts, P, i, xpart);
-      body(i, ax);
-    });
-  } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l < P.n) {
-      double ax = graph_Av<double>(P, l, x[l], xs);
-      if (P.coupled) ax += graph_coupling(P, l, xpart);
-      body(l, ax);
-    }
-  }
-  double tot[4];
-  if (arrive<4>(S, P.slot0 + t.tile, v, KC_RES, tot) && threadIdx.x == 0) {
-    S.orr = tot[0];
-    if (S.outer == 0) S.obb = tot[3];
-    bool stop = true;
-    if (S.orr <= S.otol2 * S.obb) S.outer_status = ST_CONV;
-    else if (!finite(S.orr)) S.outer_status = ST_BREAK;
-    else if (S.outer >= S.max_outer) S.outer_status = ST_NOCONV;
-    else stop = false;
-    if (stop) {
-      S.outer_done = 1;
-      __hip_atomic_fetch_add(S.oactive, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      S.done = 1;
-      S.status = S.outer_status;
-    } else {
-      S.rz = tot[1];
-      S.rr = tot[2];
-      S.bb = tot[2];          // inner stop is relative to the residual it starts from
-      S.tol2 = inner_tol2;
-      S.iter = 0;
-      S.first = 1;
-      S.beta = 0.0;
-      S.done = 0;
-      S.status = ST_RUN;
-      __hip_atomic_fetch_add(S.active, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (!(S.rz > 0.0)) finish(S, ST_BREAK);
-    }
-  }
+  residual_and_precond<float, PREC, KIND>(parts, P, t, P.x64, r32, (float*)P.z, emit, v, true);
+  v[2] = v[1];
+  write_slot<5>(S.partB, t.slot, v);
+  if (t.slot == 0 && threadIdx.x == 0) st_flag(&S.done, 0);   // a new inner solve starts
 }
 
-// x64 += (double) x32 for systems still refining; counts the pass.
+// x64 += (double) x32 for systems still refining; workgroup 0 counts the pass.
+template <int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) k_correct(const PartD* __restrict__ parts,
                                                       const Tile* __restrict__ tiles,
                                                       SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
+  if (t.part < 0) return;
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
   if (S.outer_done) return;
   const float* d = (const float*)P.x;
   double* x = P.x64;
-  if (P.kind == PART_GRID) {
-    for_tile_cells(P, t.tile, [&](int, int, long i) { x[i] += (double)d[i]; });
-  } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l < P.n) x[l] += (double)d[l];
-  }
+  for_cells<KIND>(P, t, [&](int, int, long i) { x[i] += (double)d[i]; },
+                  [&](int l) { x[l] += (double)d[l]; });
+  if (t.slot == 0 && threadIdx.x == 0) S.outer += 1;
 }
 
-// y = A x (same operator code as the solver; FP64), y in P.q, x in P.x
+// y = A x (FP64, the operator the solver inverts); y in P.q, x in P.x
+template <int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) k_apply(const PartD* __restrict__ parts,
                                                     const Tile* __restrict__ tiles) {
   const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;   // padding of the XCD-aware launch order
+  if (t.part < 0) return;
   const PartD& P = parts[t.part];
   const double* x = (const double*)P.x;
   double* y = (double*)P.q;
   auto xs = [&](long j) { return x[j]; };
   auto xpart = [&](int pi, long j) { return ((const double*)parts[pi].x)[j]; };
-  if (P.kind == PART_GRID) {
-    for_tile_cells(P, t.tile, [&](int cx, int cy, long i) {
-      double ax = grid_Av<double>(P, cx, cy, i, x[i], xs);
-      if (P.coupled) ax += grid_coupling(parts, P, i, xpart);
-      y[i] = ax;
-    });
-  } else {
-    const int l = t.tile * MC_GRAPH_ROWS + threadIdx.x;
-    if (l < P.n) {
-      double ax = graph_Av<double>(P, l, x[l], xs);
-      if (P.coupled) ax += graph_coupling(P, l, xpart);
-      y[l] = ax;
+  for_cells<KIND>(
+      P, t,
+      [&](int cx, int cy, long i) {
+        double ax = grid_Av<double>(P, cx, cy, i, x[i], xs);
+        if (P.coupled) ax += grid_coupling(parts, P, i, xpart);
+        y[i] = ax;
+      },
+      [&](int l) {
+        double ax = graph_Av<double>(P, l, x[l], xs);
+        if (P.coupled) ax += graph_coupling(P, l, xpart);
+        y[l] = ax;
+      });
+}
+
+// z = M^-1 r with the solver's preconditioner (FP64), r in P.r, z in P.z
+template <int PREC, int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_precond(const PartD* __restrict__ parts,
+                                                      const Tile* __restrict__ tiles) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  const double* r = (const double*)P.r;
+  double* z = (double*)P.z;
+  if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
+    double dz = 0.0, dr = 0.0;
+    auto rrow = [&](int, long i, bool act) { return act ? r[i] : 0.0; };
+    for_wave_tiles(t, [&](int tile) { ic0_column<double>(P, tile, rrow, z, dz, dr); });
+  } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
+    for (int tile = t.t0; tile < t.t1; ++tile) {
+      const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
+      for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
+        chain_solve<double>(r, z, P.fdinv, P.cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
     }
+  } else {
+    for_cells<KIND>(P, t, [&](int, int, long i) { z[i] = r[i] / P.diag[i]; },
+                    [&](int l) { z[l] = r[l] / P.diag[l]; });
   }
 }
 
-// Reset of the shared counters and per-system scalars before a solve phase (a kernel, not a
-// memset, so that the sequence stays capturable).
-__global__ void k_reset(SysState* sys, int nsys, int* counters, int active, int oactive,
-                        int outer_mode) {
-  // FP64 solves start with every system active; refinement starts with every outer loop
-  // active and the inner solves are activated one by one by k_residual.
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) {
-    counters[0] = active;
-    counters[1] = oactive;
-  }
-  if (s < nsys) {
+// Per-solve reset of the system records [s0, s1) (a kernel, so the sequence stays free of
+// memset nodes).
+__global__ void k_reset(SysState* sys, int s0, int s1) {
+  const int s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < s1) {
     SysState& S = sys[s];
-    for (int k = 0; k < KC_N; ++k) S.cnt[k] = 0u;
     S.done = 0;
     S.status = ST_RUN;
+    S.iter = 0;
     S.total_iter = 0;
-    if (outer_mode) {
-      S.outer = 0;
-      S.outer_done = 0;
-      S.outer_status = ST_RUN;
-    }
+    S.outer = 0;
+    S.outer_done = 0;
+    S.outer_status = ST_RUN;
   }
-}
-
-// outer bookkeeping for refinement: count a pass for systems still refining
-__global__ void k_outer_count(SysState* sys, int nsys) {
-  int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < nsys && !sys[s].outer_done) sys[s].outer += 1;
 }
 
 }  // namespace mc

@@ -96,6 +96,7 @@ mc_apply_continuum = _sig("mc_apply_continuum", C.c_int,
                           [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p])
 mc_apply_coupled = _sig("mc_apply_coupled", C.c_int, [_PROBLEM, C.c_void_p, C.c_void_p])
 mc_assemble_rhs = _sig("mc_assemble_rhs", C.c_int, [_PROBLEM, C.c_int32, C.c_void_p])
+mc_apply_precond = _sig("mc_apply_precond", C.c_int, [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p])
 mc_get_state = _sig("mc_get_state", C.c_int, [_PROBLEM, C.c_int32, _dp])
 mc_set_state = _sig("mc_set_state", C.c_int, [_PROBLEM, C.c_int32, _dp])
 mc_set_options = _sig("mc_set_options", C.c_int, [_PROBLEM, C.POINTER(Options)])
@@ -265,6 +266,10 @@ class Problem:
         _sync_torch()
         _check(mc_apply_coupled(self.h, _dev_ptr(x), _dev_ptr(y)), self.h)
 
+    def apply_precond(self, alpha: int, r, z):
+        _sync_torch()
+        _check(mc_apply_precond(self.h, alpha, _dev_ptr(r), _dev_ptr(z)), self.h)
+
     def assemble_rhs(self, alpha: int, b):
         _sync_torch()
         _check(mc_assemble_rhs(self.h, alpha, _dev_ptr(b)), self.h)
@@ -305,8 +310,9 @@ class Problem:
         _check(mc_get_info(self.h, C.byref(inf)), self.h)
         return inf
 
-    def profile(self, enable: bool):
-        _check(mc_profile(self.h, int(enable)), self.h)
+    def profile(self, enable: bool, every: int = 8):
+        """Start (sampling one grid PCG launch in `every`) or stop kernel timing."""
+        _check(mc_profile(self.h, max(1, int(every)) if enable else 0), self.h)
 
     def profile_read(self, which: int):
         n = C.c_int64()
@@ -317,5 +323,6 @@ class Problem:
 
 EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
            "mc_solve_continuum", "mc_apply_continuum", "mc_apply_coupled", "mc_assemble_rhs",
+           "mc_apply_precond",
            "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
            "mc_profile", "mc_profile_read"]

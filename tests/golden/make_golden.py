@@ -1,0 +1,65 @@
+"""Writes stored expected values for full-size workloads by running the CPU oracle.
+
+Calls only ``oracle`` (and the seeded input generator ``media``).  Output: one .npz per
+workload with the oracle state sampled at fixed seeded cell indices after selected steps,
+plus the full norms, so a GPU run at the same size can be checked entry by entry on the
+sample and by relative error on the norm.
+
+    python tests/golden/make_golden.py C2        # about 5-10 minutes, ~20 GB RAM
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import media  # noqa: E402
+from oracle import schemes  # noqa: E402
+
+NSAMPLE = 20000
+
+
+def sample_indices(p, seed=99):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in p.sizes():
+        out.append(np.sort(rng.choice(n, size=min(n, NSAMPLE), replace=False)).astype(np.int64))
+    return out
+
+
+def run(name, d_steps, c_steps):
+    p = media.config_problem(name)
+    idx = sample_indices(p)
+    data = {f"idx{a}": idx[a] for a in range(p.n_cont)}
+    for scheme, keep in (("D", d_steps), ("coupled", c_steps)):
+        t = time.time()
+        st = schemes.Stepper(p, None, scheme)
+        print(f"{name} {scheme}: factor {st.factor_seconds:.1f}s", flush=True)
+        x = p.initial_state()
+        last = max(keep)
+        for n in range(1, last + 1):
+            x = st.step(x)
+            if n in keep:
+                for a in range(p.n_cont):
+                    data[f"{scheme}_s{n}_c{a}"] = x[a][idx[a]]
+                    data[f"{scheme}_s{n}_norm{a}"] = np.array(np.linalg.norm(x[a]))
+                print(f"  step {n} stored ({time.time() - t:.0f}s)", flush=True)
+    data["steps_D"] = np.array(d_steps)
+    data["steps_coupled"] = np.array(c_steps)
+    out = os.path.join(HERE, f"{name.lower()}_oracle.npz")
+    np.savez_compressed(out, **data)
+    print("wrote", out, os.path.getsize(out), "bytes")
+
+
+if __name__ == "__main__":
+    name = sys.argv[1] if len(sys.argv) > 1 else "C2"
+    if name == "C2":
+        run("C2", d_steps=[1, 10, 100], c_steps=[1, 5, 100])
+    elif name == "C1":
+        run("C1", d_steps=list(range(1, 21)), c_steps=list(range(1, 21)))
+    else:
+        raise SystemExit("unknown workload " + name)

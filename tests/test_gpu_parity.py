@@ -153,3 +153,70 @@ def test_invalid_descriptor_rejected():
     with pytest.raises(mcdec.McError) as ei:
         mcdec.Problem(p)
     assert ei.value.status == mcdec.MC_EINVAL and "host" in str(ei.value)
+
+
+# ------------------------------------------------------------------------------------
+# block IC(0) preconditioner
+# ------------------------------------------------------------------------------------
+from oracle import precond  # noqa: E402
+
+
+@pytest.mark.parametrize("name", ["ragged200", "three70", "c1"])
+def test_block_ic0_apply(name):
+    p = CASES[name]()
+    asm = fv.assemble(p)
+    rng = np.random.default_rng(4)
+    with mcdec.Problem(p, precond="bic0") as g:
+        for a in range(p.n_cont):
+            K = schemes.continuum_matrix(asm, p.tau, a)
+            if a < p.n_omega:
+                facs = precond.block_precond(K, precond.grid_tile_blocks(p.nx, p.ny))
+            else:
+                facs = precond.block_precond(K, precond.chain_blocks(p.nf, p.edges),
+                                             tridiagonal=True)
+            r = rng.standard_normal(p.sizes()[a])
+            z = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
+            g.apply_precond(a, T(r), z)
+            ref = precond.block_precond_apply(facs, r)
+            err = rel(z.cpu().numpy(), ref)
+            print(name, a, err)
+            # grid blocks keep their factor and conductances as FP32 copies (about 6e-8
+            # relative rounding); the fracture chains use the FP64 factor
+            tol = 2e-6 if a < p.n_omega else 1e-12
+            assert err < tol, (name, a, err)
+
+
+@pytest.mark.parametrize("scheme", ["D", "coupled", "U"])
+def test_trajectory_bic0(case, scheme):
+    name, p = case
+    nsteps = 5 if name == "c1" else 3
+    ref = schemes.run(p, scheme, nsteps, keep="all")
+    with mcdec.Problem(p, scheme=scheme, precond="bic0", tol=1e-14) as g:
+        for n in range(1, nsteps + 1):
+            rep = g.step(1)
+            err = rel(g.get_states(), ref[n])
+            assert err < 1e-10, (name, scheme, n, err, rep)
+
+
+def test_chain_ic0_exact_without_crossings():
+    # axis-aligned, non-overlapping segments that do not cross: every chain is a segment and
+    # block IC(0) on the fracture system is its exact inverse -> one PCG iteration
+    p = media.small_problem(n=64, seed=21, nseg=3, axis=True, seg_len=(10, 30))
+    cross = (p.edges[:, 1] - p.edges[:, 0]) != 1
+    if cross.any():
+        pytest.skip("generator produced a crossing")
+    with mcdec.Problem(p, precond="bic0", tol=1e-12) as g:
+        rep = g.step(1)
+    assert rep["iters"][-1] <= 1, rep
+
+
+@pytest.mark.parametrize("name", ["ragged200", "three70"])
+def test_mixed_precision_bic0(name):
+    p = CASES[name]()
+    ref = schemes.run(p, "D", 3, keep="last")
+    with mcdec.Problem(p, precision="mixed", precond="bic0", outer_tol=1e-12,
+                       inner_tol=1e-5) as g:
+        rep = g.step(3)
+        err = rel(g.get_states(), ref)
+        print(name, rep, err)
+        assert err < 1e-8

@@ -323,3 +323,54 @@ def test_dof_counts():
     assert 200 * 200 + 2684 == 42684 and 2 * 200 * 200 + 2684 == 82684
     p = media.config_problem("C1")
     assert p.dof() == 64 * 64 + p.nf
+
+
+# ------------------------------------------------------------------------------------
+# block incomplete factorization (the preconditioner the GPU path applies)
+# ------------------------------------------------------------------------------------
+from oracle import precond  # noqa: E402
+
+
+def test_ilu0_exact_on_tridiagonal_and_dense():
+    rng = np.random.default_rng(0)
+    n = 30
+    off = -rng.uniform(0.1, 1.0, n - 1)
+    T = sp.diags([off, np.abs(np.r_[0, off]) + np.abs(np.r_[off, 0]) + rng.uniform(0.01, 1, n),
+                  off], [-1, 0, 1]).tocsr()
+    r = rng.standard_normal(n)
+    z = precond.ilu0_solve(precond.ilu0(T), r)
+    np.testing.assert_allclose(z, sp.linalg.spsolve(T.tocsc(), r), rtol=1e-13, atol=0)
+    Q = rng.standard_normal((8, 8))
+    D = sp.csr_matrix(Q @ Q.T + 8 * np.eye(8))
+    z = precond.ilu0_solve(precond.ilu0(D), r[:8])
+    np.testing.assert_allclose(z, np.linalg.solve(D.toarray(), r[:8]), rtol=1e-12, atol=0)
+
+
+def test_ilu0_matches_matrix_on_pattern():
+    """ILU(0) property: (L U)_ij = a_ij on the pattern of A; for SPD A, M is SPD."""
+    p = media.small_problem(n=12, seed=3, nseg=0)
+    K = schemes.continuum_matrix(fv.assemble(p), p.tau, 0)
+    rows = precond.ilu0(K)
+    n = K.shape[0]
+    L = np.eye(n)
+    U = np.zeros((n, n))
+    for i, row in enumerate(rows):
+        for j, v in row.items():
+            if j < i:
+                L[i, j] = v
+            else:
+                U[i, j] = v
+    M = L @ U
+    Kd = K.toarray()
+    mask = Kd != 0
+    np.testing.assert_allclose(M[mask], Kd[mask], rtol=1e-12, atol=1e-18)
+    assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+
+
+def test_block_partitions():
+    b = precond.grid_tile_blocks(130, 40)
+    assert len(b) == 3 * 3 and sorted(np.concatenate(b).tolist()) == list(range(130 * 40))
+    assert b[0][:3].tolist() == [0, 1, 2] and b[0][64] == 130
+    ch = precond.chain_blocks(6, np.array([[0, 1], [1, 2], [3, 4], [2, 5]]))
+    assert [c.tolist() for c in ch] == [[0, 1, 2], [3, 4], [5]]
