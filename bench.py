@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--coupled-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB copied once by a plain device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -171,6 +173,14 @@ def main():
                        "pcg_iters_per_step": float(np.mean(citers)),
                        "decoupled_over_coupled": value / cval, "accuracy": cacc}
         g.close()
+        if args.calibrate_copy:
+            n = args.calibrate_copy * 2**20 // 8
+            src = torch.ones(n, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            torch.cuda.synchronize()
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            log(f"calibration copy of {args.calibrate_copy} MiB done")
 
     lat_ms = np.array(lat) * 1e3
     it = np.array(iters)

@@ -41,9 +41,10 @@ struct SysState {
   int total_iter;       // inner iterations summed over refinement passes
   int outer, outer_done, outer_status;
   int max_iter, max_outer;
-  int nslots;           // workgroups (partial slots) of this system per launch
-  double* partA;        // [nslots * MC_SLOT] written by operator kernels
-  double* partB;        // [nslots * MC_SLOT] written by update / init / residual kernels
+  int nslotsA;          // workgroups (partial slots) of this system in an operator launch
+  int nslotsB;          // ... in an update / init / residual launch (its own tiling)
+  double* partA;        // [nslotsA * MC_SLOT] written by operator kernels
+  double* partB;        // [nslotsB * MC_SLOT] written by update / init / residual kernels
 };
 
 // One continuum block of a system.  Pointers are device memory.  Coefficient arrays exist in
@@ -55,7 +56,7 @@ struct PartD {
   int n;             // unknowns
   int nx, ny;        // grid shape
   int tiles_x;       // grid tiles per row of tiles
-  int slot0;         // first partial slot of this part inside its system
+  int slot0A, slot0B; // first partial slot of this part inside its system (per tiling)
   int coupled;       // operator includes the off-diagonal transfer blocks (coupled scheme)
   int ex;            // EX split: diagonal excludes S, RHS subtracts S p^{n-1}
   int has_t;         // grid: per-face conductance arrays (0 = constant tconst)

@@ -50,12 +50,18 @@ static int env_int(const char* name, int dflt) {
   return std::atoi(v);
 }
 
-// Workgroups per launch over a continuum: one per tile up to a cap, beyond which each
-// workgroup takes a contiguous run of tiles.  Depends only on the continuum's size, so the
-// reduction order of a system never depends on what else shares the launch.
-static int blocks_for(int ntiles, int kind) {
-  const int cap = kind == PART_GRID ? env_int("MCDEC_GRID_BLOCKS", 1024)
-                                    : env_int("MCDEC_GRAPH_BLOCKS", 256);
+// Workgroups per launch over a continuum, for the operator tiling (fam 0) and for the
+// update / init / residual tiling (fam 1): one per tile up to a cap, beyond which each
+// workgroup takes a contiguous run of tiles.  With block IC(0) the update workgroups take
+// four tiles (eight 64 x 16 blocks) so that all four wavefronts sweep.  Depends only on the
+// continuum's size and the preconditioner, so the reduction order of a system never depends
+// on what else shares the launch.
+static int blocks_for(int ntiles, int kind, int fam, bool bic0) {
+  int cap;
+  if (kind == PART_GRAPH) cap = env_int("MCDEC_GRAPH_BLOCKS", 256);
+  else if (fam == 0) cap = env_int("MCDEC_GRID_BLOCKS_A", 2048);
+  else cap = bic0 ? std::max(1, env_int("MCDEC_GRID_BLOCKS_B", (ntiles + 3) / 4))
+                  : env_int("MCDEC_GRID_BLOCKS_A", 2048);
   return std::max(1, std::min(ntiles, std::max(cap, 1)));
 }
 
@@ -96,9 +102,9 @@ struct DevArena {
 // one kind only.
 struct Table {
   PartD* parts = nullptr;
-  Tile* tiles[2] = {nullptr, nullptr};
-  int nblk[2] = {0, 0};
-  int cap[2] = {0, 0};
+  Tile* tiles[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [tiling][kind]
+  int nblk[2][2] = {{0, 0}, {0, 0}};
+  int cap[2][2] = {{0, 0}, {0, 0}};
   int nparts = 0;
   std::vector<PartD> hparts;
 };
@@ -106,8 +112,8 @@ struct Table {
 struct Cont {  // one continuum
   int kind;    // PART_GRID / PART_GRAPH
   long n;
-  int tiles;   // tiles of its part
-  int blocks;  // workgroups (and partial slots) per launch over this continuum
+  int tiles;      // tiles of its part
+  int blocks[2];  // workgroups (and partial slots) per launch: operator / update tiling
   // FP64 coefficients
   double *diag = nullptr, *tx = nullptr, *ty = nullptr, *F = nullptr, *val = nullptr,
          *mt = nullptr;
@@ -173,7 +179,7 @@ static void fail(mc_problem* p, const std::string& m) { throw Error{MC_EINVAL, m
 // ------------------------------------------------------------------------------------
 // tables
 // ------------------------------------------------------------------------------------
-static PartD base_part(mc_problem* P, int c, int sys, int slot0, bool fp32) {
+static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bool fp32) {
   Cont& C = P->cont[c];
   PartD q;
   std::memset(&q, 0, sizeof(q));
@@ -184,7 +190,8 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0, bool fp32) {
   q.nx = P->d.nx;
   q.ny = P->d.ny;
   q.tiles_x = (int)cdiv(P->d.nx, MC_TX);
-  q.slot0 = slot0;
+  q.slot0A = slot0A;
+  q.slot0B = slot0B;
   q.ex = P->opt.scheme == MC_SCHEME_EX;
   q.has_t = C.has_t;
   q.n_omega = P->n_omega;
@@ -256,36 +263,38 @@ static Table& upload_table(mc_problem* P, const std::string& key, std::vector<Pa
   HIPCHK(hipMemcpyAsync(T.parts, parts.data(), parts.size() * sizeof(PartD),
                         hipMemcpyHostToDevice, P->stream));
   const bool xcd = env_flag("MCDEC_XCD", true);
-  std::vector<Tile> kept[2];
-  for (int kind = 0; kind < 2; ++kind) {
-    std::vector<Tile>& tiles = kept[kind];
-    for (int pi = 0; pi < (int)parts.size(); ++pi) {
-      const PartD& q = parts[pi];
-      if (q.kind != kind) continue;
-      const Cont& C = P->cont[q.cont];
-      const int nt = C.tiles, nb = C.blocks;
-      // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die j
-      // of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
-      std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
-      for (int b : ord) {
-        if (b < 0) {
-          tiles.push_back(Tile{-1, 0, 0, 0});
-          continue;
+  std::vector<Tile> kept[2][2];
+  for (int fam = 0; fam < 2; ++fam)
+    for (int kind = 0; kind < 2; ++kind) {
+      std::vector<Tile>& tiles = kept[fam][kind];
+      for (int pi = 0; pi < (int)parts.size(); ++pi) {
+        const PartD& q = parts[pi];
+        if (q.kind != kind) continue;
+        const Cont& C = P->cont[q.cont];
+        const int nt = C.tiles, nb = C.blocks[fam];
+        const int slot0 = fam == 0 ? q.slot0A : q.slot0B;
+        // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die
+        // j of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
+        std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
+        for (int b : ord) {
+          if (b < 0) {
+            tiles.push_back(Tile{-1, 0, 0, 0});
+            continue;
+          }
+          const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
+          tiles.push_back(Tile{pi, slot0 + b, t0, t1});
         }
-        const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
-        tiles.push_back(Tile{pi, q.slot0 + b, t0, t1});
+        while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0});
       }
-      while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0});
+      if (!tiles.empty() && (!T.tiles[fam][kind] || T.cap[fam][kind] < (int)tiles.size())) {
+        T.tiles[fam][kind] = P->mem.alloc<Tile>(tiles.size() + 8);
+        T.cap[fam][kind] = (int)tiles.size() + 8;
+      }
+      if (!tiles.empty())
+        HIPCHK(hipMemcpyAsync(T.tiles[fam][kind], tiles.data(), tiles.size() * sizeof(Tile),
+                              hipMemcpyHostToDevice, P->stream));
+      T.nblk[fam][kind] = (int)tiles.size();
     }
-    if (!tiles.empty() && (!T.tiles[kind] || T.cap[kind] < (int)tiles.size())) {
-      T.tiles[kind] = P->mem.alloc<Tile>(tiles.size() + 8);
-      T.cap[kind] = (int)tiles.size() + 8;
-    }
-    if (!tiles.empty())
-      HIPCHK(hipMemcpyAsync(T.tiles[kind], tiles.data(), tiles.size() * sizeof(Tile),
-                            hipMemcpyHostToDevice, P->stream));
-    T.nblk[kind] = (int)tiles.size();
-  }
   HIPCHK(hipStreamSynchronize(P->stream));   // host vectors die at return
   T.nparts = (int)parts.size();
   T.hparts = std::move(parts);
@@ -431,6 +440,24 @@ static void build_coefficients(mc_problem* P) {
   P->tables.clear();
 }
 
+// Workgroup counts of every continuum for the current preconditioner, and the slot counts
+// of the system records (in host memory `hs`).
+static void set_slot_counts(mc_problem* P, SysState* hs) {
+  const bool bic0 = P->opt.precond == MC_BIC0;
+  int ca = 0, cb = 0;
+  for (int c = 0; c < P->ncont; ++c) {
+    Cont& C = P->cont[c];
+    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, bic0);
+    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, bic0);
+    hs[c].nslotsA = C.blocks[0];
+    hs[c].nslotsB = C.blocks[1];
+    ca += C.blocks[0];
+    cb += C.blocks[1];
+  }
+  hs[P->ncont].nslotsA = ca;
+  hs[P->ncont].nslotsB = cb;
+}
+
 static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o) {
   std::string m = validate_desc(d);
   if (!m.empty()) fail(P, m);
@@ -494,7 +521,8 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     C.kind = grid ? PART_GRID : PART_GRAPH;
     C.n = grid ? P->ncell : d.nf;
     C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY)) : P->ngtiles;
-    C.blocks = blocks_for(C.tiles, C.kind);
+    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, o.precond == MC_BIC0);
+    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, o.precond == MC_BIC0);
     C.diag = M.alloc<double>(C.n);
     C.F = M.alloc<double>(C.n);
     if (grid) {
@@ -520,15 +548,17 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   HIPCHK(hipHostMalloc((void**)&P->h_sys, nsys * sizeof(SysState), hipHostMallocDefault));
   std::vector<SysState> hs(nsys);
   std::memset(hs.data(), 0, nsys * sizeof(SysState));
-  int coupled_slots = 0;
-  for (int c = 0; c < P->ncont; ++c) coupled_slots += P->cont[c].blocks;
+  // partial-slot arrays sized for one workgroup per tile (the most any tiling uses), so the
+  // tilings can follow option changes
+  int coupled_tiles = 0;
+  for (int c = 0; c < P->ncont; ++c) coupled_tiles += P->cont[c].tiles;
   for (int sI = 0; sI < nsys; ++sI) {
-    const int ns = sI < P->ncont ? P->cont[sI].blocks : coupled_slots;
-    hs[sI].nslots = ns;
+    const int ns = sI < P->ncont ? P->cont[sI].tiles : coupled_tiles;
     hs[sI].partA = M.alloc<double>((size_t)ns * MC_SLOT);
     hs[sI].partB = M.alloc<double>((size_t)ns * MC_SLOT);
     hs[sI].done = 1;
   }
+  set_slot_counts(P, hs.data());
   HIPCHK(hipMemcpyAsync(P->sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   build_coefficients(P);
@@ -588,18 +618,19 @@ template <class T, int PREC>
 static void launch_iter(mc_problem* P, Group& G, int k, int outer_check) {
   const Table& Tb = *G.T;
   auto L = [&](auto kern, int kind, int which, auto... extra) {
-    if (!(G.kinds >> kind & 1) || Tb.nblk[kind] == 0) return;
+    const int fam = which;   // operator kernels: tiling 0, update kernels: tiling 1
+    if (!(G.kinds >> kind & 1) || Tb.nblk[fam][kind] == 0) return;
     if (P->prof && kind == PART_GRID && G.s == P->stream &&
         (P->prof_count[which]++ % P->prof_every) == 0) {
       // events bound to this dispatch time the kernel itself; they cost the stream a few
       // microseconds per dispatch, so only every prof_every-th launch is sampled
       mc_problem::Ev e = prof_take(P, which);
-      hipExtLaunchKernelGGL(kern, dim3(Tb.nblk[kind]), dim3(MC_BLOCK), 0, G.s, e.a, e.b, 0,
-                            Tb.parts, Tb.tiles[kind], P->sys, extra...);
+      hipExtLaunchKernelGGL(kern, dim3(Tb.nblk[fam][kind]), dim3(MC_BLOCK), 0, G.s, e.a, e.b,
+                            0, Tb.parts, Tb.tiles[fam][kind], P->sys, extra...);
       P->ev_pending.push_back(e);
     } else {
-      hipLaunchKernelGGL(kern, dim3(Tb.nblk[kind]), dim3(MC_BLOCK), 0, G.s, Tb.parts,
-                         Tb.tiles[kind], P->sys, extra...);
+      hipLaunchKernelGGL(kern, dim3(Tb.nblk[fam][kind]), dim3(MC_BLOCK), 0, G.s, Tb.parts,
+                         Tb.tiles[fam][kind], P->sys, extra...);
     }
   };
   L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0, k, outer_check);
@@ -611,22 +642,22 @@ static void launch_iter(mc_problem* P, Group& G, int k, int outer_check) {
 // launch the grid-kind kernel over the grid tiles and the graph-kind kernel over the graph
 // tiles of the group's table (each only if the group has tiles of that kind)
 template <class KG, class KF, class... A>
-static void launch2(const Group& G, KG kg, KF kf, A... args) {
-  if ((G.kinds & 1) && G.T->nblk[PART_GRID])
-    hipLaunchKernelGGL(kg, dim3(G.T->nblk[PART_GRID]), dim3(MC_BLOCK), 0, G.s, G.T->parts,
-                       G.T->tiles[PART_GRID], args...);
-  if ((G.kinds & 2) && G.T->nblk[PART_GRAPH])
-    hipLaunchKernelGGL(kf, dim3(G.T->nblk[PART_GRAPH]), dim3(MC_BLOCK), 0, G.s, G.T->parts,
-                       G.T->tiles[PART_GRAPH], args...);
+static void launch2(const Group& G, int fam, KG kg, KF kf, A... args) {
+  if ((G.kinds & 1) && G.T->nblk[fam][PART_GRID])
+    hipLaunchKernelGGL(kg, dim3(G.T->nblk[fam][PART_GRID]), dim3(MC_BLOCK), 0, G.s,
+                       G.T->parts, G.T->tiles[fam][PART_GRID], args...);
+  if ((G.kinds & 2) && G.T->nblk[fam][PART_GRAPH])
+    hipLaunchKernelGGL(kf, dim3(G.T->nblk[fam][PART_GRAPH]), dim3(MC_BLOCK), 0, G.s,
+                       G.T->parts, G.T->tiles[fam][PART_GRAPH], args...);
 }
 
 template <class KG, class KF>
-static void launch_all(mc_problem* P, const Table& T, KG kg, KF kf) {
+static void launch_all(mc_problem* P, const Table& T, int fam, KG kg, KF kf) {
   Group g;
   g.s = P->stream;
   g.T = &T;
   g.kinds = 3;
-  launch2(g, kg, kf);
+  launch2(g, fam, kg, kf);
 }
 
 static void submit_poll(mc_problem* P, Group& G) {
@@ -683,8 +714,8 @@ static void advance_t(mc_problem* P, Group& G) {
   if (!G.mixed) {
     if (G.phase == 0) {
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, G.s, P->sys, G.s0, G.s1);
-      if (G.assemble) launch2(G, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-      launch2(G, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, P->sys);
+      if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+      launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, P->sys);
       G.k = 0;
       G.K = 8;
       G.phase = 1;
@@ -703,8 +734,8 @@ static void advance_t(mc_problem* P, Group& G) {
   // mixed precision: FP64 residual -> FP32 inner PCG -> FP64 correction, repeated
   if (G.phase == 0) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, G.s, P->sys, G.s0, G.s1);
-    if (G.assemble) launch2(G, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-    launch2(G, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
+    if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
     G.outer = 0;
     G.k = 0;
     G.K = 8;
@@ -719,8 +750,8 @@ static void advance_t(mc_problem* P, Group& G) {
   if (all_done(G, false)) {
     // every unfinished system ended its inner solve: correct, new residual, restart
     if (G.outer > P->opt.max_outer + 1) throw Error{MC_EDEVICE, "refinement did not terminate"};
-    launch2(G, k_correct<PART_GRID>, k_correct<PART_GRAPH>, P->sys);
-    launch2(G, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
+    launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, P->sys);
+    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
     G.outer += 1;
     G.k = 0;
     G.K = 8;
@@ -836,7 +867,7 @@ static void solve_table(mc_problem* P, const Table& Tb, int s0, int s1, bool ass
     g.assemble = assemble;
     G.push_back(g);
   };
-  if (split_kinds && Tb.nblk[PART_GRID] && Tb.nblk[PART_GRAPH]) {
+  if (split_kinds && Tb.nblk[0][PART_GRID] && Tb.nblk[0][PART_GRAPH]) {
     // decoupled: grid systems are [s0, s0 + n_grid), the fracture system follows
     int ngrid = 0;
     for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID;
@@ -890,17 +921,18 @@ static void fill_coupled_report(mc_problem* P, mc_report* rep) {
 static std::vector<PartD> decoupled_parts(mc_problem* P, const std::vector<int>& conts,
                                           bool fp32) {
   std::vector<PartD> parts;
-  for (int c : conts) parts.push_back(base_part(P, c, c, 0, fp32));
+  for (int c : conts) parts.push_back(base_part(P, c, c, 0, 0, fp32));
   return parts;
 }
 
 static std::vector<PartD> coupled_parts(mc_problem* P) {
   std::vector<PartD> parts;
-  int slot = 0;
+  int slotA = 0, slotB = 0;
   const int sysI = P->ncont;
   for (int c = 0; c < P->ncont; ++c) {
-    PartD q = base_part(P, c, sysI, slot, false);
-    slot += P->cont[c].blocks;
+    PartD q = base_part(P, c, sysI, slotA, slotB, false);
+    slotA += P->cont[c].blocks[0];
+    slotB += P->cont[c].blocks[1];
     q.coupled = 1;
     parts.push_back(q);
   }
@@ -1099,7 +1131,7 @@ mc_status mc_apply_continuum(mc_problem* P, int32_t alpha, const double* x, doub
   parts[0].x = const_cast<double*>(x);
   parts[0].q = y;
   mc::Table& T = mc::upload_table(P, "apply" + std::to_string(alpha), parts);
-  mc::launch_all(P, T, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
+  mc::launch_all(P, T, 0, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
   return MC_OK;
@@ -1118,7 +1150,7 @@ mc_status mc_apply_coupled(mc_problem* P, const double* x, double* y) {
     off += P->cont[c].n;
   }
   mc::Table& T = mc::upload_table(P, "applyc", parts);
-  mc::launch_all(P, T, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
+  mc::launch_all(P, T, 0, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
   return MC_OK;
@@ -1135,9 +1167,10 @@ mc_status mc_apply_precond(mc_problem* P, int32_t alpha, const double* r, double
   parts[0].z = z;
   mc::Table& T = mc::upload_table(P, "prec" + std::to_string(alpha), parts);
   if (P->opt.precond == MC_BIC0)
-    mc::launch_all(P, T, mc::k_precond<PREC_BIC0, PART_GRID>, mc::k_precond<PREC_BIC0, PART_GRAPH>);
+    mc::launch_all(P, T, 1, mc::k_precond<PREC_BIC0, PART_GRID>,
+                   mc::k_precond<PREC_BIC0, PART_GRAPH>);
   else
-    mc::launch_all(P, T, mc::k_precond<PREC_JACOBI, PART_GRID>,
+    mc::launch_all(P, T, 1, mc::k_precond<PREC_JACOBI, PART_GRID>,
                    mc::k_precond<PREC_JACOBI, PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
@@ -1155,7 +1188,7 @@ mc_status mc_assemble_rhs(mc_problem* P, int32_t alpha, double* b) {
   parts[0].x64 = P->cont[alpha].r;    // warm-start copy goes to scratch
   parts[0].coupled = 0;
   mc::Table& T = mc::upload_table(P, "rhs" + std::to_string(alpha), parts);
-  mc::launch_all(P, T, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
+  mc::launch_all(P, T, 0, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->stream));
   return MC_OK;
@@ -1197,6 +1230,11 @@ mc_status mc_set_options(mc_problem* P, const mc_options* o) {
   P->opt.stream = P->stream;
   if (rebuild) mc::build_coefficients(P);
   P->tables.clear();
+  // the update tiling depends on the preconditioner: refresh the slot counts
+  const size_t nb = (P->ncont + 1) * sizeof(SysState);
+  HIPCHK(hipMemcpy(P->h_sys, P->sys, nb, hipMemcpyDeviceToHost));
+  mc::set_slot_counts(P, P->h_sys);
+  HIPCHK(hipMemcpy(P->sys, P->h_sys, nb, hipMemcpyHostToDevice));
   return MC_OK;
   ABI_END(P)
 }

@@ -770,7 +770,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
   if (ld_flag(&S.done)) return;
   const bool w0 = t.slot == 0;
   double v[5];
-  reduce_slots<5>(S.partB, S.nslots, v);
+  reduce_slots<5>(S.partB, S.nslotsB, v);
   if (outer_check) {   // first inner iteration after an FP64 residual: refinement test
     const double orr = v[3];
     const double obb = S.outer == 0 ? v[4] : S.obb;
@@ -901,7 +901,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   SysState& S = sys[P.sys];
   if (ld_flag(&S.done)) return;
   double v1[1];
-  reduce_slots<1>(S.partA, S.nslots, v1);
+  reduce_slots<1>(S.partA, S.nslotsA, v1);
   const double pq = v1[0];
   double o[2] = {0.0, 0.0};
   if (!(pq > 0.0) || !finite(pq)) {
