@@ -28,6 +28,16 @@ METRIC = ("cell-updates/s per decoupled time step vs coupled+FP64 at 1e-8 rel er
           "p50/p99 step latency")
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per dispatch of the grid operator kernel, from two rocprofv3 counter passes
+# (FETCH_SIZE, then WRITE_SIZE) of `bench.py --steps 2 --warmup 0 --no-cpu --no-coupled
+# --calibrate-copy 4096`, each scaled by what the same counter reads for a 2 GiB sum (read
+# factor 1.9999) and a 2 GiB fill (write factor 0.9999).  Valid only for the kernel sources
+# they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
+MEASURED_TRAFFIC = {
+    ("C2", "bic0"): {"sources": "7be7f8b36faa832f", "fetch_kib": 84047.2, "write_kib": 65600.4,
+                     "read_factor": 1.9999, "write_factor": 0.9999},
+}
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -41,6 +51,22 @@ def grid_A_bytes_per_cell(precision, precond, has_t):
     reads = 3 + (2 if has_t else 0)
     writes = 2
     return (reads + writes) * w
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2209_01158_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precond):
+    m = MEASURED_TRAFFIC.get((workload, precond))
+    if m is None or m["sources"] != kernel_sources_hash():
+        return None
+    return (m["fetch_kib"] * m["read_factor"] + m["write_kib"] * m["write_factor"]) * 1024.0
 
 
 def golden_check(g, name, steps, scheme):
@@ -100,7 +126,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
-                    help="MiB copied once by a plain device copy (HBM counter calibration)")
+                    help="MiB written by a fill and read by a sum (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -174,13 +200,13 @@ def main():
                        "decoupled_over_coupled": value / cval, "accuracy": cacc}
         g.close()
         if args.calibrate_copy:
+            # known traffic for the HBM counters: a fill writes N bytes, a sum reads N bytes
             n = args.calibrate_copy * 2**20 // 8
-            src = torch.ones(n, dtype=torch.float64, device="cuda")
-            dst = torch.empty_like(src)
+            src = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
             torch.cuda.synchronize()
-            dst.copy_(src)
+            tot = float(src.sum())
             torch.cuda.synchronize()
-            log(f"calibration copy of {args.calibrate_copy} MiB done")
+            log(f"calibration: filled and summed {args.calibrate_copy} MiB (sum {tot:.0f})")
 
     lat_ms = np.array(lat) * 1e3
     it = np.array(iters)
@@ -189,9 +215,13 @@ def main():
     bpc = grid_A_bytes_per_cell("fp64", args.precond, has_t)
     avgA = msA / max(nA, 1) * 1e-3
     achieved = ncell_grid * bpc / avgA / 1e9 if nA else None
-    roof = {"bound": "hbm", "kernel": "k_pcg_A<double,JACOBI,GRID> (p = z + beta p; q = A p; "
-            "partial p.q)", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+    pname = {"bic0": "BIC0", "jacobi": "JACOBI"}.get(args.precond, args.precond)
+    traffic = measured_traffic(args.workload, args.precond)
+    roof = {"bound": "hbm", "kernel": f"k_pcg_A<double,{pname},GRID> (p = z + beta p; q = A p; "
+            "partial p.q), grid continuum", "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": traffic, "traffic_unit": "bytes per launch",
+            "algorithmic_bytes_per_launch": ncell_grid * bpc,
             "bytes_per_cell": bpc, "cells_per_launch": ncell_grid, "launches": nA,
             "avg_launch_us": avgA * 1e6,
             "update_kernel_avg_us": msB / max(nB, 1) * 1e3, "update_kernel_launches": nB}

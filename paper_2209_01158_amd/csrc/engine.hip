@@ -140,6 +140,11 @@ struct mc_problem {
   mc_options opt{};
   hipStream_t stream = nullptr;   // main stream (grid groups, coupled, setup)
   hipStream_t stream2 = nullptr;  // second stream: the fracture group of a decoupled step
+  // CU-partitioned streams of a decoupled step: the grid group and the fracture group each
+  // get their own compute units, so the fracture's short, latency-bound kernels never wait
+  // for CU slots behind the bandwidth-bound grid kernels (null: no partition)
+  hipStream_t stream_grid = nullptr, stream_frac = nullptr;
+  int frac_cus = 0;
   bool own_stream = false;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_poll[4] = {nullptr, nullptr, nullptr, nullptr};
   int ncont = 0, n_omega = 0, nf = 0, ne = 0;
@@ -440,6 +445,39 @@ static void build_coefficients(mc_problem* P) {
   P->tables.clear();
 }
 
+// CU partition for decoupled steps: the fracture group gets every k-th compute unit (one
+// eighth of them by default, spread over all dies), the grid group the rest.  Left out
+// (both streams null) if the device is small or the masked streams cannot be created.
+static void create_cu_streams(mc_problem* P) {
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int fcu = env_int("MCDEC_FRAC_CUS", ncu >= 64 ? ncu / 8 : 0);
+  if (fcu <= 0 || fcu >= ncu) return;
+  const int words = (ncu + 31) / 32, stride = ncu / fcu;
+  std::vector<uint32_t> fm(words, 0u), gm(words, 0u);
+  int taken = 0;
+  for (int c = 0; c < ncu; ++c) {
+    if (c % stride == 0 && taken < fcu) {
+      fm[c / 32] |= 1u << (c % 32);
+      ++taken;
+    } else {
+      gm[c / 32] |= 1u << (c % 32);
+    }
+  }
+  hipStream_t a = nullptr, b = nullptr;
+  if (hipExtStreamCreateWithCUMask(&a, words, gm.data()) != hipSuccess ||
+      hipExtStreamCreateWithCUMask(&b, words, fm.data()) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipStreamDestroy(a);
+    if (b) (void)hipStreamDestroy(b);
+    return;
+  }
+  P->stream_grid = a;
+  P->stream_frac = b;
+  P->frac_cus = fcu;
+}
+
 // Workgroup counts of every continuum for the current preconditioner, and the slot counts
 // of the system records (in host memory `hs`).
 static void set_slot_counts(mc_problem* P, SysState* hs) {
@@ -478,6 +516,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     P->own_stream = true;
   }
   HIPCHK(hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking));
+  create_cu_streams(P);
   HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
   for (auto& e : P->ev_poll) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -620,7 +659,7 @@ static void launch_iter(mc_problem* P, Group& G, int k, int outer_check) {
   auto L = [&](auto kern, int kind, int which, auto... extra) {
     const int fam = which;   // operator kernels: tiling 0, update kernels: tiling 1
     if (!(G.kinds >> kind & 1) || Tb.nblk[fam][kind] == 0) return;
-    if (P->prof && kind == PART_GRID && G.s == P->stream &&
+    if (P->prof && kind == PART_GRID &&
         (P->prof_count[which]++ % P->prof_every) == 0) {
       // events bound to this dispatch time the kernel itself; they cost the stream a few
       // microseconds per dispatch, so only every prof_every-th launch is sampled
@@ -871,8 +910,10 @@ static void solve_table(mc_problem* P, const Table& Tb, int s0, int s1, bool ass
     // decoupled: grid systems are [s0, s0 + n_grid), the fracture system follows
     int ngrid = 0;
     for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID;
-    mk(1, s0, s0 + ngrid, P->stream);
-    mk(2, s0 + ngrid, s1, env_flag("MCDEC_ONE_STREAM", false) ? P->stream : P->stream2);
+    const bool one = env_flag("MCDEC_ONE_STREAM", false);
+    const bool part = P->stream_grid && !one;
+    mk(1, s0, s0 + ngrid, part ? P->stream_grid : P->stream);
+    mk(2, s0 + ngrid, s1, one ? P->stream : (part ? P->stream_frac : P->stream2));
   } else {
     mk(3, s0, s1, P->stream);
   }
@@ -1072,6 +1113,11 @@ mc_status mc_destroy(mc_problem* P) {
   for (auto e : P->ev_poll)
     if (e) (void)hipEventDestroy(e);
   if (P->stream2) (void)hipStreamDestroy(P->stream2);
+  for (hipStream_t st : {P->stream_grid, P->stream_frac})
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
   if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
   delete P;
   return MC_OK;
