@@ -119,7 +119,9 @@ typedef struct {
   double outer_tol;      /* MC_MIXED: FP64 residual target relative to ||b||                   */
   int32_t max_outer;     /* MC_MIXED: maximum refinement passes                                */
   double inner_tol;      /* MC_MIXED: inner FP32 PCG tolerance relative to the outer residual  */
-  int32_t check_every;   /* PCG iterations launched between host convergence polls (0 = auto)  */
+  int32_t check_every;   /* PCG iterations launched between host convergence polls (0 = auto:
+                            estimated from the observed residual decrease); the device stops
+                            each system at its own tolerance either way                        */
   int32_t tile_rows;     /* grid tile height in rows: 0 (default) or 32                         */
   void *stream;          /* hipStream_t to order all work on, or NULL (library-owned stream)   */
 } mc_options;
@@ -210,9 +212,48 @@ const char *mc_last_error(const mc_problem *p);
    launches of the grid PCG kernels (they time the kernel execution itself).  which: 0 = grid
    operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z).  enable >= 1
    starts recording and clears the totals, sampling one launch in `enable` (1 = every launch;
-   each sampled launch costs the stream a few microseconds); 0 stops. */
+   each sampled launch costs the stream a few microseconds); 0 stops.  While timing is on,
+   PCG iterations are launched one by one instead of replayed from captured graphs. */
 mc_status mc_profile(mc_problem *p, int32_t enable);
 mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *launches, double *total_ms);
+
+/* ---- batches: many problems advanced by shared launches ---------------------------------
+ *
+ * A batch executor advances a list of problems by one time layer per step with every
+ * continuum of every problem in the same kernel launches: one launch per PCG kernel covers
+ * the tiles of all grid continua of all problems, another those of all fracture continua
+ * (each system keeps its own scalars and stopping test, Section 3.3 D-scheme per problem).
+ * Iterations are replayed from captured HIP graphs.  Each problem keeps its own tiling and
+ * partial-sum order, so its result is bitwise the one mc_step gives it alone with the same
+ * options.  Problems may differ in size, continua and fracture network.
+ */
+typedef struct mc_batch mc_batch;
+
+/* Create a batch executor.  opt gives the solver options of every batch step (tolerances,
+   max_iter, refinement) and the stream (NULL = library-owned).  scheme must be D, EX or
+   COUPLED.  *out is NULL on failure (message from mc_batch_last_error(NULL)). */
+mc_status mc_batch_create(const mc_options *opt, mc_batch **out);
+
+/* Release the executor (not the problems); NULL-safe. */
+mc_status mc_batch_destroy(mc_batch *b);
+
+/* Advance the n (>= 1) distinct problems probs[0..n) by n_steps layers together.  Every
+   problem must have been created with the batch's scheme class (D/EX, or COUPLED),
+   precision and preconditioner (MC_EINVAL otherwise).  Per problem and per layer the step is
+   transactional: a problem whose solve fails keeps its state (reps[i].failed names the
+   continuum) while the others advance; the call then returns the first failure after that
+   layer.  reps (nullable) receives one report per problem.  The problems must not be used by
+   another thread during the call; their device memory is accessed on the batch's stream. */
+mc_status mc_batch_step(mc_batch *b, mc_problem *const *probs, int32_t n, int32_t n_steps,
+                        mc_report *reps);
+
+const char *mc_batch_last_error(const mc_batch *b);
+
+/* Kernel timing of the batch's grid PCG kernels, as mc_profile / mc_profile_read.  While
+   timing is on, iterations are launched one by one instead of from graphs. */
+mc_status mc_batch_profile(mc_batch *b, int32_t enable);
+mc_status mc_batch_profile_read(mc_batch *b, int32_t which, int64_t *launches,
+                                double *total_ms);
 
 #ifdef __cplusplus
 }

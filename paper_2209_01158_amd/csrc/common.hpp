@@ -41,6 +41,12 @@ struct SysState {
   int total_iter;       // inner iterations summed over refinement passes
   int outer, outer_done, outer_status;
   int max_iter, max_outer;
+  // PCG iteration index, kept on the device so that launches carry no per-iteration
+  // argument: the operator kernel reads ka and records it in kb; the update kernel reads kb
+  // and sets ka = kb + 1 for the next operator kernel
+  int ka, kb;
+  int mixed;            // inner solve of FP64 refinement: iteration 0 first tests the outer residual
+  int pad0;
   int nslotsA;          // workgroups (partial slots) of this system in an operator launch
   int nslotsB;          // ... in an update / init / residual launch (its own tiling)
   double* partA;        // [nslotsA * MC_SLOT] written by operator kernels

@@ -1,18 +1,21 @@
 // Runtime of the MI355X multicontinuum library: device memory of a problem, coefficient
-// setup, launch tables, PCG orchestration for every scheme and precision, and the C ABI.
+// setup, launch tables, PCG orchestration for every scheme and precision, batches of
+// problems advanced by shared launches, and the C ABI.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
-#include <thread>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mcdec.h"
@@ -97,17 +100,98 @@ struct DevArena {
   }
 };
 
-// A launch table: parts in device memory and, per part kind (grid / graph), the list of
-// tiles in launch order.  Kernels are instantiated per kind, so a launch covers the tiles of
-// one kind only.
+// ------------------------------------------------------------------------------------
+// launch tables
+// ------------------------------------------------------------------------------------
+// Parts in device memory and, per tiling and part kind (grid / graph), the list of tiles in
+// launch order.  Kernels are instantiated per kind, so a launch covers the tiles of one
+// kind only.  Graphs of captured PCG iteration chunks over this table are cached with it.
 struct Table {
   PartD* parts = nullptr;
+  int pcap = 0;
   Tile* tiles[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [tiling][kind]
   int nblk[2][2] = {{0, 0}, {0, 0}};
   int cap[2][2] = {{0, 0}, {0, 0}};
   int nparts = 0;
   std::vector<PartD> hparts;
+  std::vector<int> htil;                      // tiles, blocksA, blocksB per part
+  std::map<long, hipGraphExec_t> graphs;
 };
+
+static void drop_graphs(Table& T) {
+  for (auto& g : T.graphs) (void)hipGraphExecDestroy(g.second);
+  T.graphs.clear();
+}
+
+// Tiling of one part: its tiles and the workgroups of its operator / update launches.
+struct PartTiling {
+  int tiles;
+  int blocks[2];
+};
+
+static bool table_matches(const Table& T, const std::vector<PartD>& parts,
+                          const std::vector<PartTiling>& til) {
+  if (T.hparts.size() != parts.size() || T.htil.size() != 3 * til.size()) return false;
+  if (std::memcmp(T.hparts.data(), parts.data(), parts.size() * sizeof(PartD)) != 0) return false;
+  for (size_t i = 0; i < til.size(); ++i)
+    if (T.htil[3 * i] != til[i].tiles || T.htil[3 * i + 1] != til[i].blocks[0] ||
+        T.htil[3 * i + 2] != til[i].blocks[1])
+      return false;
+  return true;
+}
+
+// Writes parts and their tile lists into T (reusing its device buffers when large enough).
+static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> parts,
+                       const std::vector<PartTiling>& til) {
+  drop_graphs(T);
+  if (!T.parts || T.pcap < (int)parts.size()) {
+    T.pcap = (int)parts.size() + 2;
+    T.parts = M.alloc<PartD>(T.pcap);
+  }
+  HIPCHK(hipMemcpyAsync(T.parts, parts.data(), parts.size() * sizeof(PartD),
+                        hipMemcpyHostToDevice, s));
+  const bool xcd = env_flag("MCDEC_XCD", true);
+  std::vector<Tile> kept[2][2];
+  for (int fam = 0; fam < 2; ++fam)
+    for (int kind = 0; kind < 2; ++kind) {
+      std::vector<Tile>& tiles = kept[fam][kind];
+      for (int pi = 0; pi < (int)parts.size(); ++pi) {
+        const PartD& q = parts[pi];
+        if (q.kind != kind) continue;
+        const int nt = til[pi].tiles, nb = til[pi].blocks[fam];
+        const int slot0 = fam == 0 ? q.slot0A : q.slot0B;
+        // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die
+        // j of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
+        std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
+        for (int b : ord) {
+          if (b < 0) {
+            tiles.push_back(Tile{-1, 0, 0, 0});
+            continue;
+          }
+          const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
+          tiles.push_back(Tile{pi, slot0 + b, t0, t1});
+        }
+        while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0});
+      }
+      if (!tiles.empty() && (!T.tiles[fam][kind] || T.cap[fam][kind] < (int)tiles.size())) {
+        T.cap[fam][kind] = (int)tiles.size() + 8;
+        T.tiles[fam][kind] = M.alloc<Tile>(T.cap[fam][kind]);
+      }
+      if (!tiles.empty())
+        HIPCHK(hipMemcpyAsync(T.tiles[fam][kind], tiles.data(), tiles.size() * sizeof(Tile),
+                              hipMemcpyHostToDevice, s));
+      T.nblk[fam][kind] = (int)tiles.size();
+    }
+  HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
+  T.nparts = (int)parts.size();
+  T.hparts = std::move(parts);
+  T.htil.clear();
+  for (auto& t : til) {
+    T.htil.push_back(t.tiles);
+    T.htil.push_back(t.blocks[0]);
+    T.htil.push_back(t.blocks[1]);
+  }
+}
 
 struct Cont {  // one continuum
   int kind;    // PART_GRID / PART_GRAPH
@@ -131,43 +215,24 @@ struct Cont {  // one continuum
   int has_t = 1;
 };
 
-}  // namespace mc
-
-using namespace mc;
-
-struct mc_problem {
-  mc_problem_desc d{};   // scalars only (array pointers are not kept)
+// ------------------------------------------------------------------------------------
+// execution context: streams, system records, polling, graphs, kernel timing
+// ------------------------------------------------------------------------------------
+struct Exec {
   mc_options opt{};
-  hipStream_t stream = nullptr;   // main stream (grid groups, coupled, setup)
-  hipStream_t stream2 = nullptr;  // second stream: the fracture group of a decoupled step
-  // CU-partitioned streams of a decoupled step: the grid group and the fracture group each
-  // get their own compute units, so the fracture's short, latency-bound kernels never wait
-  // for CU slots behind the bandwidth-bound grid kernels (null: no partition)
+  hipStream_t stream = nullptr;    // main stream (grid group, coupled systems, setup)
+  hipStream_t stream2 = nullptr;   // fracture group of a decoupled solve (created on first use)
+  // optional CU-partitioned streams of a decoupled solve (MCDEC_FRAC_CUS > 0): the fracture
+  // group gets its own compute units
   hipStream_t stream_grid = nullptr, stream_frac = nullptr;
-  int frac_cus = 0;
-  bool own_stream = false;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_poll[4] = {nullptr, nullptr, nullptr, nullptr};
-  int ncont = 0, n_omega = 0, nf = 0, ne = 0;
-  long ncell = 0;
-  int ty = 16;
-  DevArena mem;
-  std::vector<Cont> cont;
-  // inputs kept on the device (for re-setup)
-  double* k[2] = {nullptr, nullptr};
-  double* src[3] = {nullptr, nullptr, nullptr};
-  int *host = nullptr, *rowptr = nullptr, *col = nullptr, *eidx = nullptr, *hptr = nullptr,
-      *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr, *cidx = nullptr;
-  double *flen = nullptr, *edge_d = nullptr, *sigma_f = nullptr;
-  int nchains = 0, ngtiles = 0;
-  // systems: 0..ncont-1 decoupled per continuum, ncont = coupled
-  SysState* sys = nullptr;
-  std::vector<double*> partials;
-  SysState* h_sys = nullptr;     // pinned mirror of the system records
-  int cur = 0;                   // state ping-pong index
-  long step_count = 0;
-  std::map<std::string, Table> tables;
-  std::string err;
-  // profiling
+  bool own_stream = false, side = false;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_poll[2] = {nullptr, nullptr};
+  SysState* sys = nullptr;         // device system records
+  SysState* h_sys = nullptr;       // pinned mirror
+  int nsys = 0, sys_cap = 0;
+  bool graphs = true;              // replay captured iteration chunks
+  std::mutex graph_mu;
+  // kernel timing
   bool prof = false;
   struct Ev { hipEvent_t a, b; int which; };
   std::vector<Ev> ev_free, ev_pending;
@@ -177,12 +242,156 @@ struct mc_problem {
   int prof_every = 8;
 };
 
+static void exec_init(Exec& X, void* user_stream) {
+  if (user_stream) {
+    X.stream = (hipStream_t)user_stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&X.stream, hipStreamNonBlocking));
+    X.own_stream = true;
+  }
+  HIPCHK(hipEventCreateWithFlags(&X.ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&X.ev_join, hipEventDisableTiming));
+  for (auto& e : X.ev_poll) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  X.graphs = env_flag("MCDEC_GRAPHS", true);
+}
+
+// CU partition (opt-in): the fracture group gets every k-th compute unit, spread over all
+// dies, the grid group the rest.  Left out if the masked streams cannot be created.
+static void create_cu_streams(Exec& X) {
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int fcu = env_int("MCDEC_FRAC_CUS", 0);
+  if (fcu <= 0 || fcu >= ncu) return;
+  const int words = (ncu + 31) / 32, stride = ncu / fcu;
+  std::vector<uint32_t> fm(words, 0u), gm(words, 0u);
+  int taken = 0;
+  for (int c = 0; c < ncu; ++c) {
+    if (c % stride == 0 && taken < fcu) {
+      fm[c / 32] |= 1u << (c % 32);
+      ++taken;
+    } else {
+      gm[c / 32] |= 1u << (c % 32);
+    }
+  }
+  hipStream_t a = nullptr, b = nullptr;
+  if (hipExtStreamCreateWithCUMask(&a, words, gm.data()) != hipSuccess ||
+      hipExtStreamCreateWithCUMask(&b, words, fm.data()) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) (void)hipStreamDestroy(a);
+    if (b) (void)hipStreamDestroy(b);
+    return;
+  }
+  X.stream_grid = a;
+  X.stream_frac = b;
+}
+
+static void exec_side_streams(Exec& X) {
+  if (X.side) return;
+  HIPCHK(hipStreamCreateWithFlags(&X.stream2, hipStreamNonBlocking));
+  create_cu_streams(X);
+  X.side = true;
+}
+
+// Device and pinned records for n systems; returns true if they moved (graphs that captured
+// the old address must then be dropped).
+static bool exec_sys_capacity(Exec& X, int n) {
+  X.nsys = n;
+  if (n <= X.sys_cap) return false;
+  if (X.sys) {
+    HIPCHK(hipStreamSynchronize(X.stream));
+    (void)hipFree(X.sys);
+    X.sys = nullptr;
+  }
+  if (X.h_sys) {
+    (void)hipHostFree(X.h_sys);
+    X.h_sys = nullptr;
+  }
+  const int cap = std::max(n, 2 * X.sys_cap);
+  X.sys_cap = 0;
+  if (hipMalloc((void**)&X.sys, cap * sizeof(SysState)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{MC_ENOMEM, "hipMalloc of the system records failed"};
+  }
+  HIPCHK(hipHostMalloc((void**)&X.h_sys, cap * sizeof(SysState), hipHostMallocDefault));
+  X.sys_cap = cap;
+  return true;
+}
+
+static void exec_release(Exec& X) {
+  if (X.stream) (void)hipStreamSynchronize(X.stream);
+  for (hipStream_t st : {X.stream2, X.stream_grid, X.stream_frac})
+    if (st) (void)hipStreamSynchronize(st);
+  for (auto& e : X.ev_free) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (auto& e : X.ev_pending) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  X.ev_free.clear();
+  X.ev_pending.clear();
+  if (X.sys) (void)hipFree(X.sys);
+  if (X.h_sys) (void)hipHostFree(X.h_sys);
+  X.sys = nullptr;
+  X.h_sys = nullptr;
+  if (X.ev_fork) (void)hipEventDestroy(X.ev_fork);
+  if (X.ev_join) (void)hipEventDestroy(X.ev_join);
+  for (auto e : X.ev_poll)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t st : {X.stream2, X.stream_grid, X.stream_frac})
+    if (st) (void)hipStreamDestroy(st);
+  if (X.own_stream && X.stream) (void)hipStreamDestroy(X.stream);
+  X.stream = X.stream2 = X.stream_grid = X.stream_frac = nullptr;
+}
+
+}  // namespace mc
+
+using namespace mc;
+
+struct mc_problem {
+  mc_problem_desc d{};   // scalars only (array pointers are not kept)
+  Exec X;                // X.opt: the problem's options
+  int ncont = 0, n_omega = 0, nf = 0, ne = 0;
+  long ncell = 0;
+  DevArena mem;
+  std::vector<Cont> cont;
+  // inputs kept on the device (for re-setup)
+  double* k[2] = {nullptr, nullptr};
+  double* src[3] = {nullptr, nullptr, nullptr};
+  int *host = nullptr, *rowptr = nullptr, *col = nullptr, *eidx = nullptr, *hptr = nullptr,
+      *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr, *cidx = nullptr;
+  double *flen = nullptr, *edge_d = nullptr, *sigma_f = nullptr;
+  int nchains = 0, ngtiles = 0;
+  // systems: 0..ncont-1 decoupled per continuum, ncont = coupled; their partial-sum slots
+  std::vector<double*> partA, partB;
+  int cur = 0;                   // state ping-pong index
+  long step_count = 0;
+  std::map<std::string, Table> tables;
+  std::string err;
+};
+
+// Many problems advanced together: every launch covers the tiles of all of them.
+struct mc_batch {
+  Exec X;          // X.opt: the batch's solver options
+  DevArena mem;    // launch tables
+  Table tab[2];    // the two most recent compositions (consecutive steps alternate state buffers)
+  int lru = 0;
+  std::string err;
+};
+
 namespace mc {
 
-static void fail(mc_problem* p, const std::string& m) { throw Error{MC_EINVAL, m}; }
+static void fail(const std::string& m) { throw Error{MC_EINVAL, m}; }
+
+static void clear_tables(mc_problem* P) {
+  for (auto& t : P->tables) drop_graphs(t.second);
+  P->tables.clear();
+}
 
 // ------------------------------------------------------------------------------------
-// tables
+// parts of a problem
 // ------------------------------------------------------------------------------------
 static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bool fp32) {
   Cont& C = P->cont[c];
@@ -197,7 +406,7 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.tiles_x = (int)cdiv(P->d.nx, MC_TX);
   q.slot0A = slot0A;
   q.slot0B = slot0B;
-  q.ex = P->opt.scheme == MC_SCHEME_EX;
+  q.ex = P->X.opt.scheme == MC_SCHEME_EX;
   q.has_t = C.has_t;
   q.n_omega = P->n_omega;
   q.other = -1;
@@ -257,64 +466,58 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   return q;
 }
 
-static Table& upload_table(mc_problem* P, const std::string& key, std::vector<PartD> parts) {
-  auto it = P->tables.find(key);
-  if (it != P->tables.end() && it->second.hparts.size() == parts.size() &&
-      std::memcmp(it->second.hparts.data(), parts.data(), parts.size() * sizeof(PartD)) == 0)
-    return it->second;
-  Table T;
-  if (it != P->tables.end()) T = it->second;
-  if (!T.parts || T.nparts < (int)parts.size()) T.parts = P->mem.alloc<PartD>(parts.size() + 2);
-  HIPCHK(hipMemcpyAsync(T.parts, parts.data(), parts.size() * sizeof(PartD),
-                        hipMemcpyHostToDevice, P->stream));
-  const bool xcd = env_flag("MCDEC_XCD", true);
-  std::vector<Tile> kept[2][2];
-  for (int fam = 0; fam < 2; ++fam)
-    for (int kind = 0; kind < 2; ++kind) {
-      std::vector<Tile>& tiles = kept[fam][kind];
-      for (int pi = 0; pi < (int)parts.size(); ++pi) {
-        const PartD& q = parts[pi];
-        if (q.kind != kind) continue;
-        const Cont& C = P->cont[q.cont];
-        const int nt = C.tiles, nb = C.blocks[fam];
-        const int slot0 = fam == 0 ? q.slot0A : q.slot0B;
-        // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die
-        // j of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
-        std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
-        for (int b : ord) {
-          if (b < 0) {
-            tiles.push_back(Tile{-1, 0, 0, 0});
-            continue;
-          }
-          const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
-          tiles.push_back(Tile{pi, slot0 + b, t0, t1});
-        }
-        while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0});
-      }
-      if (!tiles.empty() && (!T.tiles[fam][kind] || T.cap[fam][kind] < (int)tiles.size())) {
-        T.tiles[fam][kind] = P->mem.alloc<Tile>(tiles.size() + 8);
-        T.cap[fam][kind] = (int)tiles.size() + 8;
-      }
-      if (!tiles.empty())
-        HIPCHK(hipMemcpyAsync(T.tiles[fam][kind], tiles.data(), tiles.size() * sizeof(Tile),
-                              hipMemcpyHostToDevice, P->stream));
-      T.nblk[fam][kind] = (int)tiles.size();
-    }
-  HIPCHK(hipStreamSynchronize(P->stream));   // host vectors die at return
-  T.nparts = (int)parts.size();
-  T.hparts = std::move(parts);
-  P->tables[key] = T;
-  return P->tables[key];
+static PartTiling tiling_of(const mc_problem* P, int c) {
+  const Cont& C = P->cont[c];
+  return PartTiling{C.tiles, {C.blocks[0], C.blocks[1]}};
 }
 
-static int part_tiles(mc_problem* P, int c) { return P->cont[c].tiles; }
+static Table& upload_table(mc_problem* P, const std::string& key, std::vector<PartD> parts) {
+  std::vector<PartTiling> til;
+  for (auto& q : parts) til.push_back(tiling_of(P, q.cont));
+  Table& T = P->tables[key];
+  if (table_matches(T, parts, til)) return T;
+  fill_table(T, P->mem, P->X.stream, std::move(parts), til);
+  return T;
+}
+
+static std::vector<PartD> decoupled_parts(mc_problem* P, const std::vector<int>& conts,
+                                          bool fp32) {
+  std::vector<PartD> parts;
+  for (int c : conts) parts.push_back(base_part(P, c, c, 0, 0, fp32));
+  return parts;
+}
+
+// Parts of the coupled system `sysI` of a problem; cross-part references are indices into
+// the returned vector plus `base` (the position of its first part in the launch table).
+static std::vector<PartD> coupled_parts(mc_problem* P, int sysI, int base) {
+  std::vector<PartD> parts;
+  int slotA = 0, slotB = 0;
+  for (int c = 0; c < P->ncont; ++c) {
+    PartD q = base_part(P, c, sysI, slotA, slotB, false);
+    slotA += P->cont[c].blocks[0];
+    slotB += P->cont[c].blocks[1];
+    q.coupled = 1;
+    parts.push_back(q);
+  }
+  for (int c = 0; c < P->ncont; ++c) {
+    if (c < P->n_omega) {
+      parts[c].other = P->n_omega == 2 ? base + 1 - c : -1;
+      parts[c].frac = P->nf ? base + P->n_omega : -1;
+    } else {
+      parts[c].omg[0] = base;
+      parts[c].omg[1] = P->n_omega > 1 ? base + 1 : -1;
+    }
+  }
+  return parts;
+}
 
 // ------------------------------------------------------------------------------------
 // setup
 // ------------------------------------------------------------------------------------
 static void build_coefficients(mc_problem* P) {
-  const bool ex = P->opt.scheme == MC_SCHEME_EX;
+  const bool ex = P->X.opt.scheme == MC_SCHEME_EX;
   const double h = P->d.h, tau = P->d.tau;
+  hipStream_t s = P->X.stream;
   for (int a = 0; a < P->n_omega; ++a) {
     Cont& C = P->cont[a];
     GridSetup g;
@@ -327,9 +530,9 @@ static void build_coefficients(mc_problem* P) {
     g.h = h;
     g.tau = tau;
     g.s12 = P->n_omega == 2 ? P->d.sigma_omega * h * h : 0.0;
-    for (int s = 0; s < 4; ++s) {
-      g.bc_type[s] = P->d.bc_type[s];
-      g.bc_value[s] = P->d.bc_value[s];
+    for (int k = 0; k < 4; ++k) {
+      g.bc_type[k] = P->d.bc_type[k];
+      g.bc_value[k] = P->d.bc_value[k];
     }
     g.src = P->src[a];
     g.hptr = P->nf ? P->hptr : nullptr;
@@ -340,7 +543,7 @@ static void build_coefficients(mc_problem* P) {
     g.tx = C.tx;
     g.ty = C.ty;
     g.F = C.F;
-    hipLaunchKernelGGL(k_setup_grid, dim3(cdiv(C.n, 256)), dim3(256), 0, P->stream, g);
+    hipLaunchKernelGGL(k_setup_grid, dim3(cdiv(C.n, 256)), dim3(256), 0, s, g);
     C.mtau = P->d.omega[a].c * h * h / tau;
     C.has_t = P->k[a] != nullptr;
     C.tconst = P->d.omega[a].k_const;
@@ -367,10 +570,10 @@ static void build_coefficients(mc_problem* P) {
     g.diag = C.diag;
     g.mt = C.mt;
     g.F = C.F;
-    hipLaunchKernelGGL(k_setup_graph, dim3(cdiv(P->nf, 256)), dim3(256), 0, P->stream, g);
+    hipLaunchKernelGGL(k_setup_graph, dim3(cdiv(P->nf, 256)), dim3(256), 0, s, g);
   }
   HIPCHK(hipGetLastError());
-  if (P->opt.precond == MC_BIC0) {
+  if (P->X.opt.precond == MC_BIC0) {
     for (auto& C : P->cont) {
       if (!C.fdinv) C.fdinv = P->mem.alloc<double>(C.n);
       if (!C.z) C.z = P->mem.alloc<double>(C.n);
@@ -384,7 +587,8 @@ static void build_coefficients(mc_problem* P) {
         g.tx = C.tx;
         g.ty = C.ty;
         g.dinv = C.fdinv;
-        hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)C.tiles * MC_ICB, 64)), dim3(64), 0, P->stream, g);
+        hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)C.tiles * MC_ICB, 64)), dim3(64),
+                           0, s, g);
       } else {
         if (!C.cT) C.cT = P->mem.alloc<double>(C.n);
         ChainSetup g;
@@ -395,7 +599,7 @@ static void build_coefficients(mc_problem* P) {
         g.diag = C.diag;
         g.cT = C.cT;
         g.dinv = C.fdinv;
-        hipLaunchKernelGGL(k_setup_chains, dim3(cdiv(P->nchains, 64)), dim3(64), 0, P->stream, g);
+        hipLaunchKernelGGL(k_setup_chains, dim3(cdiv(P->nchains, 64)), dim3(64), 0, s, g);
       }
     }
     HIPCHK(hipGetLastError());
@@ -404,7 +608,7 @@ static void build_coefficients(mc_problem* P) {
       if (C.kind != PART_GRID) continue;
       auto cv = [&](double* a, float*& b, long n) {
         if (!b) b = P->mem.alloc<float>(n);
-        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, P->stream, a, b, n);
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, s, a, b, n);
       };
       cv(C.fdinv, C.fdinv32, C.n);
       cv(C.tx, C.tx32, C.n);
@@ -412,15 +616,15 @@ static void build_coefficients(mc_problem* P) {
     }
     HIPCHK(hipGetLastError());
   }
-  if (P->opt.precision == MC_MIXED) {
+  if (P->X.opt.precision == MC_MIXED) {
     for (auto& C : P->cont) {
       auto cv = [&](double* a, float*& b, long n) {
         if (!a || n == 0) return;
         if (!b) b = P->mem.alloc<float>(n);
-        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, P->stream, a, b, n);
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, s, a, b, n);
       };
       cv(C.diag, C.diag32, C.n);
-      if (P->opt.precond == MC_BIC0) {
+      if (P->X.opt.precond == MC_BIC0) {
         cv(C.fdinv, C.fdinv32, C.n);
         if (C.kind == PART_GRAPH) cv(C.cT, C.cT32, C.n);
         if (!C.z32) C.z32 = P->mem.alloc<float>(C.n);
@@ -441,47 +645,14 @@ static void build_coefficients(mc_problem* P) {
     }
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipStreamSynchronize(P->stream));
-  P->tables.clear();
-}
-
-// CU partition for decoupled steps: the fracture group gets every k-th compute unit (one
-// eighth of them by default, spread over all dies), the grid group the rest.  Left out
-// (both streams null) if the device is small or the masked streams cannot be created.
-static void create_cu_streams(mc_problem* P) {
-  int dev = 0, ncu = 0;
-  HIPCHK(hipGetDevice(&dev));
-  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int fcu = env_int("MCDEC_FRAC_CUS", ncu >= 64 ? ncu / 8 : 0);
-  if (fcu <= 0 || fcu >= ncu) return;
-  const int words = (ncu + 31) / 32, stride = ncu / fcu;
-  std::vector<uint32_t> fm(words, 0u), gm(words, 0u);
-  int taken = 0;
-  for (int c = 0; c < ncu; ++c) {
-    if (c % stride == 0 && taken < fcu) {
-      fm[c / 32] |= 1u << (c % 32);
-      ++taken;
-    } else {
-      gm[c / 32] |= 1u << (c % 32);
-    }
-  }
-  hipStream_t a = nullptr, b = nullptr;
-  if (hipExtStreamCreateWithCUMask(&a, words, gm.data()) != hipSuccess ||
-      hipExtStreamCreateWithCUMask(&b, words, fm.data()) != hipSuccess) {
-    (void)hipGetLastError();
-    if (a) (void)hipStreamDestroy(a);
-    if (b) (void)hipStreamDestroy(b);
-    return;
-  }
-  P->stream_grid = a;
-  P->stream_frac = b;
-  P->frac_cus = fcu;
+  HIPCHK(hipStreamSynchronize(s));
+  clear_tables(P);
 }
 
 // Workgroup counts of every continuum for the current preconditioner, and the slot counts
 // of the system records (in host memory `hs`).
 static void set_slot_counts(mc_problem* P, SysState* hs) {
-  const bool bic0 = P->opt.precond == MC_BIC0;
+  const bool bic0 = P->X.opt.precond == MC_BIC0;
   int ca = 0, cb = 0;
   for (int c = 0; c < P->ncont; ++c) {
     Cont& C = P->cont[c];
@@ -498,29 +669,19 @@ static void set_slot_counts(mc_problem* P, SysState* hs) {
 
 static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o) {
   std::string m = validate_desc(d);
-  if (!m.empty()) fail(P, m);
+  if (!m.empty()) fail(m);
   m = validate_options(o);
-  if (!m.empty()) fail(P, m);
+  if (!m.empty()) fail(m);
   P->d = d;
-  P->opt = o;
-  P->ty = MC_TY;
+  P->X.opt = o;
   P->n_omega = d.n_omega;
   P->nf = d.nf;
   P->ne = d.ne;
   P->ncell = (long)d.nx * d.ny;
   P->ncont = d.n_omega + (d.nf > 0 ? 1 : 0);
-  if (o.stream) {
-    P->stream = (hipStream_t)o.stream;
-  } else {
-    HIPCHK(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
-    P->own_stream = true;
-  }
-  HIPCHK(hipStreamCreateWithFlags(&P->stream2, hipStreamNonBlocking));
-  create_cu_streams(P);
-  HIPCHK(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
-  for (auto& e : P->ev_poll) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  hipStream_t s = P->stream;
+  exec_init(P->X, o.stream);
+  P->X.opt.stream = P->X.stream;
+  hipStream_t s = P->X.stream;
   DevArena& M = P->mem;
   // inputs
   for (int a = 0; a < d.n_omega; ++a) {
@@ -583,8 +744,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   }
   // systems: one per continuum + the coupled one
   const int nsys = P->ncont + 1;
-  P->sys = M.alloc<SysState>(nsys);
-  HIPCHK(hipHostMalloc((void**)&P->h_sys, nsys * sizeof(SysState), hipHostMallocDefault));
+  exec_sys_capacity(P->X, nsys);
   std::vector<SysState> hs(nsys);
   std::memset(hs.data(), 0, nsys * sizeof(SysState));
   // partial-slot arrays sized for one workgroup per tile (the most any tiling uses), so the
@@ -596,38 +756,40 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     hs[sI].partA = M.alloc<double>((size_t)ns * MC_SLOT);
     hs[sI].partB = M.alloc<double>((size_t)ns * MC_SLOT);
     hs[sI].done = 1;
+    P->partA.push_back(hs[sI].partA);
+    P->partB.push_back(hs[sI].partB);
   }
   set_slot_counts(P, hs.data());
-  HIPCHK(hipMemcpyAsync(P->sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(P->X.sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   build_coefficients(P);
 }
 
 // ------------------------------------------------------------------------------------
-// profiling helpers
+// kernel timing
 // ------------------------------------------------------------------------------------
-static mc_problem::Ev prof_take(mc_problem* P, int which) {
-  if (P->ev_free.empty()) {
-    mc_problem::Ev n;
+static Exec::Ev prof_take(Exec& X, int which) {
+  if (X.ev_free.empty()) {
+    Exec::Ev n;
     HIPCHK(hipEventCreate(&n.a));
     HIPCHK(hipEventCreate(&n.b));
-    P->ev_free.push_back(n);
+    X.ev_free.push_back(n);
   }
-  mc_problem::Ev e = P->ev_free.back();
-  P->ev_free.pop_back();
+  Exec::Ev e = X.ev_free.back();
+  X.ev_free.pop_back();
   e.which = which;
   return e;
 }
-static void prof_harvest(mc_problem* P) {
-  for (auto& e : P->ev_pending) {
+static void prof_harvest(Exec& X) {
+  for (auto& e : X.ev_pending) {
     float ms = 0;
     HIPCHK(hipEventSynchronize(e.b));
     HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
-    P->prof_ms[e.which] += ms;
-    P->prof_launch[e.which] += 1;
-    P->ev_free.push_back(e);
+    X.prof_ms[e.which] += ms;
+    X.prof_launch[e.which] += 1;
+    X.ev_free.push_back(e);
   }
-  P->ev_pending.clear();
+  X.ev_pending.clear();
 }
 
 // ------------------------------------------------------------------------------------
@@ -635,47 +797,87 @@ static void prof_harvest(mc_problem* P) {
 // ------------------------------------------------------------------------------------
 // A group is a set of systems (a contiguous range of system records) whose tiles are
 // launched together on one stream.  Decoupled continua of different kinds form separate
-// groups on separate streams, so the small, latency-bound fracture solve overlaps the
-// bandwidth-bound grid solve.  The host advances each group as a small state machine and
+// groups on separate streams, so the small, latency-bound fracture solves overlap the
+// bandwidth-bound grid solves.  The host advances each group as a small state machine and
 // only ever waits on an event recorded after a copy of that group's system records.
 struct Group {
   hipStream_t s = nullptr;
-  const Table* T = nullptr;
+  Table* T = nullptr;
   int kinds = 0;      // bit k set: launch the kind-k tiles of the table
   int s0 = 0, s1 = 0; // system records [s0, s1)
   bool mixed = false, assemble = true;
-  int phase = 0;      // 0 start, 1 iterating, 2 after a residual (mixed), 3 finished
+  int phase = 0;      // 0 start, 1 iterating, 3 finished
   int K = 8;
-  int k = 0;          // next PCG iteration index
+  long k = 0;         // PCG iterations launched in the current (inner) solve
   int outer = 0;
   SysState* hbuf = nullptr;
   hipEvent_t ev = nullptr;
   bool inflight = false;
 };
 
+// One PCG iteration over the group's tiles: operator kernels, then update kernels.
 template <class T, int PREC>
-static void launch_iter(mc_problem* P, Group& G, int k, int outer_check) {
+static void launch_iter(Exec& X, Group& G, bool timed) {
   const Table& Tb = *G.T;
-  auto L = [&](auto kern, int kind, int which, auto... extra) {
+  auto L = [&](auto kern, int kind, int which) {
     const int fam = which;   // operator kernels: tiling 0, update kernels: tiling 1
     if (!(G.kinds >> kind & 1) || Tb.nblk[fam][kind] == 0) return;
-    if (P->prof && kind == PART_GRID &&
-        (P->prof_count[which]++ % P->prof_every) == 0) {
+    if (timed && X.prof && kind == PART_GRID &&
+        (X.prof_count[which]++ % X.prof_every) == 0) {
       // events bound to this dispatch time the kernel itself; they cost the stream a few
       // microseconds per dispatch, so only every prof_every-th launch is sampled
-      mc_problem::Ev e = prof_take(P, which);
+      Exec::Ev e = prof_take(X, which);
       hipExtLaunchKernelGGL(kern, dim3(Tb.nblk[fam][kind]), dim3(MC_BLOCK), 0, G.s, e.a, e.b,
-                            0, Tb.parts, Tb.tiles[fam][kind], P->sys, extra...);
-      P->ev_pending.push_back(e);
+                            0, Tb.parts, Tb.tiles[fam][kind], X.sys);
+      X.ev_pending.push_back(e);
     } else {
       hipLaunchKernelGGL(kern, dim3(Tb.nblk[fam][kind]), dim3(MC_BLOCK), 0, G.s, Tb.parts,
-                         Tb.tiles[fam][kind], P->sys, extra...);
+                         Tb.tiles[fam][kind], X.sys);
     }
   };
-  L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0, k, outer_check);
-  L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0, k, outer_check);
-  L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1, k);
-  L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1, k);
+  L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0);
+  L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0);
+  L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1);
+  L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1);
+}
+
+// Executable graph of K iterations over the group's tiles (captured on first use).  The
+// launches carry no per-iteration argument, so one graph serves every chunk of that length.
+template <class T, int PREC>
+static hipGraphExec_t chunk_graph(Exec& X, Group& G, int K) {
+  const long key = ((long)G.kinds << 40) | ((long)sizeof(T) << 32) | ((long)PREC << 24) | K;
+  std::lock_guard<std::mutex> lk(X.graph_mu);
+  auto it = G.T->graphs.find(key);
+  if (it != G.T->graphs.end()) return it->second;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(G.s, hipStreamCaptureModeThreadLocal));
+  for (int j = 0; j < K; ++j) launch_iter<T, PREC>(X, G, false);
+  hipError_t le = hipGetLastError();
+  hipError_t ce = hipStreamEndCapture(G.s, &g);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    throw Error{MC_EDEVICE, std::string("graph capture failed: ") +
+                                hipGetErrorString(le != hipSuccess ? le : ce)};
+  }
+  hipGraphExec_t e = nullptr;
+  hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) throw Error{MC_EDEVICE, std::string("graph instantiate failed: ") +
+                                                    hipGetErrorString(ie)};
+  G.T->graphs[key] = e;
+  return e;
+}
+
+// K iterations: replayed from captured graphs of power-of-two lengths, or launched one by
+// one while kernel timing is on (or graphs are switched off).
+template <class T, int PREC>
+static void launch_chunk(Exec& X, Group& G, int K) {
+  if (!X.graphs || X.prof) {
+    for (int j = 0; j < K; ++j) launch_iter<T, PREC>(X, G, true);
+    return;
+  }
+  for (int b = 0; (1 << b) <= K; ++b)
+    if (K >> b & 1) HIPCHK(hipGraphLaunch(chunk_graph<T, PREC>(X, G, 1 << b), G.s));
 }
 
 // launch the grid-kind kernel over the grid tiles and the graph-kind kernel over the graph
@@ -691,16 +893,16 @@ static void launch2(const Group& G, int fam, KG kg, KF kf, A... args) {
 }
 
 template <class KG, class KF>
-static void launch_all(mc_problem* P, const Table& T, int fam, KG kg, KF kf) {
+static void launch_all(hipStream_t s, Table& T, int fam, KG kg, KF kf) {
   Group g;
-  g.s = P->stream;
+  g.s = s;
   g.T = &T;
   g.kinds = 3;
   launch2(g, fam, kg, kf);
 }
 
-static void submit_poll(mc_problem* P, Group& G) {
-  HIPCHK(hipMemcpyAsync(G.hbuf, P->sys + G.s0, (G.s1 - G.s0) * sizeof(SysState),
+static void submit_poll(Exec& X, Group& G) {
+  HIPCHK(hipMemcpyAsync(G.hbuf, X.sys + G.s0, (G.s1 - G.s0) * sizeof(SysState),
                         hipMemcpyDeviceToHost, G.s));
   HIPCHK(hipEventRecord(G.ev, G.s));
   G.inflight = true;
@@ -737,26 +939,28 @@ static bool all_done(const Group& G, bool outer) {
 }
 
 template <int PREC>
-static void advance_t(mc_problem* P, Group& G) {
-  const int max_iter = P->opt.max_iter;
-  auto chunk = [&](auto tag, int first_outer_check) {
+static void advance_t(Exec& X, Group& G) {
+  const int max_iter = X.opt.max_iter;
+  auto chunk = [&](auto tag) {
     using T = decltype(tag);
     const long room = (long)max_iter + 2 - G.k;
     const int K = (int)std::max<long>(1, std::min<long>(G.K, room));
-    for (int j = 0; j < K; ++j) {
-      launch_iter<T, PREC>(P, G, G.k, j == 0 ? first_outer_check : 0);
-      G.k += 1;
-    }
+    launch_chunk<T, PREC>(X, G, K);
+    G.k += K;
     HIPCHK(hipGetLastError());
-    submit_poll(P, G);
+    submit_poll(X, G);
+  };
+  auto pick_K = [&]() {
+    G.K = X.opt.check_every > 0 ? X.opt.check_every : next_chunk(G);
   };
   if (!G.mixed) {
     if (G.phase == 0) {
-      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, G.s, P->sys, G.s0, G.s1);
+      hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
+                         G.s1);
       if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-      launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, P->sys);
+      launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
       G.k = 0;
-      G.K = 8;
+      G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
       G.phase = 1;
     } else {
       if (all_done(G, false)) {
@@ -765,21 +969,22 @@ static void advance_t(mc_problem* P, Group& G) {
       }
       if (G.k > (long)max_iter + 1)
         throw Error{MC_EDEVICE, "PCG did not report completion within max_iter iterations"};
-      G.K = next_chunk(G);
+      pick_K();
     }
-    chunk(double(0), 0);
+    chunk(double(0));
     return;
   }
   // mixed precision: FP64 residual -> FP32 inner PCG -> FP64 correction, repeated
   if (G.phase == 0) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, G.s, P->sys, G.s0, G.s1);
+    hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
+                       G.s1);
     if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
+    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
     G.outer = 0;
     G.k = 0;
-    G.K = 8;
+    G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
     G.phase = 1;
-    chunk(float(0), 1);
+    chunk(float(0));
     return;
   }
   if (all_done(G, true)) {
@@ -788,37 +993,37 @@ static void advance_t(mc_problem* P, Group& G) {
   }
   if (all_done(G, false)) {
     // every unfinished system ended its inner solve: correct, new residual, restart
-    if (G.outer > P->opt.max_outer + 1) throw Error{MC_EDEVICE, "refinement did not terminate"};
-    launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, P->sys);
-    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, P->sys);
+    if (G.outer > X.opt.max_outer + 1) throw Error{MC_EDEVICE, "refinement did not terminate"};
+    launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, X.sys);
+    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
     G.outer += 1;
     G.k = 0;
-    G.K = 8;
-    chunk(float(0), 1);
+    G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
+    chunk(float(0));
     return;
   }
   if (G.k > (long)max_iter + 1) throw Error{MC_EDEVICE, "inner PCG did not finish"};
-  G.K = next_chunk(G);
-  chunk(float(0), 0);
+  pick_K();
+  chunk(float(0));
 }
 
-static void advance(mc_problem* P, Group& G) {
-  if (P->opt.precond == MC_BIC0) advance_t<PREC_BIC0>(P, G);
-  else advance_t<PREC_JACOBI>(P, G);
+static void advance(Exec& X, Group& G) {
+  if (X.opt.precond == MC_BIC0) advance_t<PREC_BIC0>(X, G);
+  else advance_t<PREC_JACOBI>(X, G);
 }
 
 // Runs one group's state machine to completion on the calling host thread.
-static void drive_group(mc_problem* P, Group& g) {
-  advance(P, g);
+static void drive_group(Exec& X, Group& g) {
+  advance(X, g);
   while (g.phase != 3) {
     if (!g.inflight) {
-      advance(P, g);
+      advance(X, g);
       continue;
     }
     hipError_t q = hipEventQuery(g.ev);
     if (q == hipSuccess) {
       g.inflight = false;
-      advance(P, g);
+      advance(X, g);
     } else if (q != hipErrorNotReady) {
       HIPCHK(q);
     }
@@ -828,26 +1033,26 @@ static void drive_group(mc_problem* P, Group& g) {
 // Runs every group to completion.  With more than one group, each group is driven by its
 // own host thread, so that enqueueing a long chunk of one group never delays the next
 // chunk of another.
-static void run_groups(mc_problem* P, std::vector<Group>& G) {
+static void run_groups(Exec& X, std::vector<Group>& G) {
   // streams of the groups start after all work already ordered on the main stream
-  HIPCHK(hipEventRecord(P->ev_fork, P->stream));
+  HIPCHK(hipEventRecord(X.ev_fork, X.stream));
   for (size_t k = 0; k < G.size(); ++k) {
     Group& g = G[k];
-    if (g.s != P->stream) HIPCHK(hipStreamWaitEvent(g.s, P->ev_fork, 0));
+    if (g.s != X.stream) HIPCHK(hipStreamWaitEvent(g.s, X.ev_fork, 0));
     g.phase = 0;
     g.inflight = false;
-    g.hbuf = P->h_sys + g.s0;   // disjoint ranges of the pinned mirror
-    g.ev = P->ev_poll[k];
+    g.hbuf = X.h_sys + g.s0;   // disjoint ranges of the pinned mirror
+    g.ev = X.ev_poll[k];
   }
   if (G.size() == 1) {
-    drive_group(P, G[0]);
+    drive_group(X, G[0]);
   } else {
     std::vector<Error> errs(G.size(), Error{MC_OK, ""});
     std::vector<std::thread> th;
     for (size_t k = 1; k < G.size(); ++k)
       th.emplace_back([&, k] {
         try {
-          drive_group(P, G[k]);
+          drive_group(X, G[k]);
         } catch (const Error& e) {
           errs[k] = e;
         } catch (const std::exception& e) {
@@ -855,7 +1060,7 @@ static void run_groups(mc_problem* P, std::vector<Group>& G) {
         }
       });
     try {
-      drive_group(P, G[0]);
+      drive_group(X, G[0]);
     } catch (const Error& e) {
       errs[0] = e;
     } catch (const std::exception& e) {
@@ -866,34 +1071,35 @@ static void run_groups(mc_problem* P, std::vector<Group>& G) {
       if (e.st != MC_OK) throw e;
   }
   for (auto& g : G)
-    if (g.s != P->stream) {
-      HIPCHK(hipEventRecord(P->ev_join, g.s));
-      HIPCHK(hipStreamWaitEvent(P->stream, P->ev_join, 0));
+    if (g.s != X.stream) {
+      HIPCHK(hipEventRecord(X.ev_join, g.s));
+      HIPCHK(hipStreamWaitEvent(X.stream, X.ev_join, 0));
     }
 }
 
-static void set_sys_params(mc_problem* P, int s0, int s1, double tol, int max_iter,
-                           bool mixed) {
-  HIPCHK(hipMemcpyAsync(P->h_sys, P->sys, (P->ncont + 1) * sizeof(SysState),
-                        hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
-  for (int sI = s0; sI < s1; ++sI) {
-    SysState& S = P->h_sys[sI];
-    S.tol2 = tol * tol;
-    S.max_iter = max_iter;
-    S.otol2 = P->opt.outer_tol * P->opt.outer_tol;
-    S.max_outer = P->opt.max_outer;
-  }
-  HIPCHK(hipMemcpyAsync(P->sys + s0, P->h_sys + s0, (s1 - s0) * sizeof(SysState),
-                        hipMemcpyHostToDevice, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
+static void sys_params(const Exec& X, SysState& S, double tol, bool mixed) {
+  S.tol2 = tol * tol;
+  S.max_iter = X.opt.max_iter;
+  S.otol2 = X.opt.outer_tol * X.opt.outer_tol;
+  S.max_outer = X.opt.max_outer;
+  S.mixed = mixed ? 1 : 0;
 }
 
-// Solve the systems [s0, s1) of table Tb: one group per kind on its own stream when the
-// kinds belong to different systems (decoupled), else one group.
-static void solve_table(mc_problem* P, const Table& Tb, int s0, int s1, bool assemble,
-                        bool mixed, bool split_kinds) {
-  set_sys_params(P, s0, s1, mixed ? P->opt.inner_tol : P->opt.tol, P->opt.max_iter, mixed);
+static void set_sys_params(Exec& X, int s0, int s1, double tol, bool mixed) {
+  HIPCHK(hipMemcpyAsync(X.h_sys + s0, X.sys + s0, (s1 - s0) * sizeof(SysState),
+                        hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+  for (int sI = s0; sI < s1; ++sI) sys_params(X, X.h_sys[sI], tol, mixed);
+  HIPCHK(hipMemcpyAsync(X.sys + s0, X.h_sys + s0, (s1 - s0) * sizeof(SysState),
+                        hipMemcpyHostToDevice, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+}
+
+// Solve the systems [s0, s1) of table Tb (system parameters already set).  Decoupled
+// tables (split_kinds) number their grid systems first: they form one group on the main
+// stream and the fracture systems a second group on the side stream.
+static void solve_table(Exec& X, Table& Tb, int s0, int s1, bool assemble, bool mixed,
+                        bool split_kinds) {
   std::vector<Group> G;
   auto mk = [&](int kinds, int a, int b, hipStream_t st) {
     Group g;
@@ -907,30 +1113,33 @@ static void solve_table(mc_problem* P, const Table& Tb, int s0, int s1, bool ass
     G.push_back(g);
   };
   if (split_kinds && Tb.nblk[0][PART_GRID] && Tb.nblk[0][PART_GRAPH]) {
-    // decoupled: grid systems are [s0, s0 + n_grid), the fracture system follows
     int ngrid = 0;
     for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID;
     const bool one = env_flag("MCDEC_ONE_STREAM", false);
-    const bool part = P->stream_grid && !one;
-    mk(1, s0, s0 + ngrid, part ? P->stream_grid : P->stream);
-    mk(2, s0 + ngrid, s1, one ? P->stream : (part ? P->stream_frac : P->stream2));
+    if (!one) exec_side_streams(X);
+    const bool part = X.stream_grid && !one;
+    mk(1, s0, s0 + ngrid, part ? X.stream_grid : X.stream);
+    mk(2, s0 + ngrid, s1, one ? X.stream : (part ? X.stream_frac : X.stream2));
   } else {
-    mk(3, s0, s1, P->stream);
+    mk(3, s0, s1, X.stream);
   }
-  run_groups(P, G);
+  run_groups(X, G);
 }
 
-// Reads back the system records; fills the report; returns the first failing status.
-static mc_status collect(mc_problem* P, const std::vector<int>& systems,
-                         const std::vector<int>& conts_of_sys, mc_report* rep, bool mixed) {
-  const int nsys = P->ncont + 1;
-  HIPCHK(hipMemcpyAsync(P->h_sys, P->sys, nsys * sizeof(SysState), hipMemcpyDeviceToHost,
-                        P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
+static void read_sys(Exec& X) {
+  HIPCHK(hipMemcpyAsync(X.h_sys, X.sys, X.nsys * sizeof(SysState), hipMemcpyDeviceToHost,
+                        X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+}
+
+// Fills the report from the (already read) system records; returns the first failing
+// status.
+static mc_status fill_report(const Exec& X, const std::vector<int>& systems,
+                             const std::vector<int>& conts_of_sys, mc_report* rep, bool mixed) {
   mc_status st = MC_OK;
   int failed = -1;
   for (size_t k = 0; k < systems.size(); ++k) {
-    const SysState& S = P->h_sys[systems[k]];
+    const SysState& S = X.h_sys[systems[k]];
     const int status = mixed ? S.outer_status : S.status;
     const int c = conts_of_sys[k];
     if (rep && c >= 0 && c < 3) {
@@ -949,9 +1158,9 @@ static mc_status collect(mc_problem* P, const std::vector<int>& systems,
   return st;
 }
 
-static void fill_coupled_report(mc_problem* P, mc_report* rep) {
+static void fill_coupled_report(int ncont, mc_report* rep) {
   if (!rep) return;
-  for (int c = 1; c < P->ncont; ++c) {
+  for (int c = 1; c < ncont; ++c) {
     rep->iters[c] = rep->iters[0];
     rep->outer[c] = rep->outer[0];
     rep->converged[c] = rep->converged[0];
@@ -959,52 +1168,27 @@ static void fill_coupled_report(mc_problem* P, mc_report* rep) {
   }
 }
 
-static std::vector<PartD> decoupled_parts(mc_problem* P, const std::vector<int>& conts,
-                                          bool fp32) {
-  std::vector<PartD> parts;
-  for (int c : conts) parts.push_back(base_part(P, c, c, 0, 0, fp32));
-  return parts;
-}
-
-static std::vector<PartD> coupled_parts(mc_problem* P) {
-  std::vector<PartD> parts;
-  int slotA = 0, slotB = 0;
-  const int sysI = P->ncont;
-  for (int c = 0; c < P->ncont; ++c) {
-    PartD q = base_part(P, c, sysI, slotA, slotB, false);
-    slotA += P->cont[c].blocks[0];
-    slotB += P->cont[c].blocks[1];
-    q.coupled = 1;
-    parts.push_back(q);
-  }
-  for (int c = 0; c < P->ncont; ++c) {
-    if (c < P->n_omega) {
-      parts[c].other = P->n_omega == 2 ? 1 - c : -1;
-      parts[c].frac = P->nf ? P->n_omega : -1;
-    } else {
-      parts[c].omg[0] = 0;
-      parts[c].omg[1] = P->n_omega > 1 ? 1 : -1;
-    }
-  }
-  return parts;
-}
-
 static mc_status step_once(mc_problem* P, mc_report* rep) {
-  const bool mixed = P->opt.precision == MC_MIXED;
-  const int sch = P->opt.scheme;
+  Exec& X = P->X;
+  const bool mixed = X.opt.precision == MC_MIXED;
+  const int sch = X.opt.scheme;
   std::vector<int> all;
   for (int c = 0; c < P->ncont; ++c) all.push_back(c);
   mc_status st;
   if (sch == MC_SCHEME_COUPLED) {
-    Table& T = upload_table(P, "coupled" + std::to_string(P->cur), coupled_parts(P));
-    solve_table(P, T, P->ncont, P->ncont + 1, true, false, false);
-    st = collect(P, {P->ncont}, {0}, rep, false);
-    fill_coupled_report(P, rep);
+    Table& T = upload_table(P, "coupled" + std::to_string(P->cur), coupled_parts(P, P->ncont, 0));
+    set_sys_params(X, P->ncont, P->ncont + 1, X.opt.tol, false);
+    solve_table(X, T, P->ncont, P->ncont + 1, true, false, false);
+    read_sys(X);
+    st = fill_report(X, {P->ncont}, {0}, rep, false);
+    fill_coupled_report(P->ncont, rep);
   } else if (sch == MC_SCHEME_D || sch == MC_SCHEME_EX) {
     Table& T = upload_table(P, std::string(mixed ? "dm" : "d") + std::to_string(P->cur),
                             decoupled_parts(P, all, mixed));
-    solve_table(P, T, 0, P->ncont, true, mixed, true);
-    st = collect(P, all, all, rep, mixed);
+    set_sys_params(X, 0, P->ncont, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
+    solve_table(X, T, 0, P->ncont, true, mixed, true);
+    read_sys(X);
+    st = fill_report(X, all, all, rep, mixed);
   } else {
     // L: ascending index order, each continuum sees the new values of those before it;
     // U: descending order, new values of those after it.
@@ -1017,8 +1201,10 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
       for (size_t j = 0; j < k; ++j) parts[0].tsrc[order[j]] = P->cont[order[j]].ps[1 - P->cur];
       Table& T = upload_table(P, std::string(mixed ? "sm" : "s") + std::to_string(c) + "_" +
                                      std::to_string(P->cur), parts);
-      solve_table(P, T, c, c + 1, true, mixed, false);
-      mc_status s1 = collect(P, {c}, {c}, rep, mixed);
+      set_sys_params(X, c, c + 1, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
+      solve_table(X, T, c, c + 1, true, mixed, false);
+      read_sys(X);
+      mc_status s1 = fill_report(X, {c}, {c}, rep, mixed);
       if (s1 != MC_OK) {
         st = s1;
         break;
@@ -1028,6 +1214,126 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
   if (st == MC_OK) {
     P->cur ^= 1;
     P->step_count += 1;
+  }
+  return st;
+}
+
+// ------------------------------------------------------------------------------------
+// batches
+// ------------------------------------------------------------------------------------
+static bool coupled_class(int scheme) { return scheme == MC_SCHEME_COUPLED; }
+
+static void batch_check(const mc_batch* B, mc_problem* const* probs, int n) {
+  if (n < 1 || !probs) fail("a batch step needs at least one problem");
+  const mc_options& o = B->X.opt;
+  for (int i = 0; i < n; ++i) {
+    const mc_problem* P = probs[i];
+    if (!P) fail("problem " + std::to_string(i) + " is NULL");
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == P) fail("problem " + std::to_string(i) + " appears twice");
+    const mc_options& q = P->X.opt;
+    if (q.scheme == MC_SCHEME_L || q.scheme == MC_SCHEME_U)
+      fail("problem " + std::to_string(i) + ": the L- and U-schemes are not batched");
+    if (coupled_class(q.scheme) != coupled_class(o.scheme) || q.precision != o.precision ||
+        q.precond != o.precond)
+      fail("problem " + std::to_string(i) +
+           ": scheme class, precision and preconditioner must match the batch options");
+  }
+}
+
+// One time layer of every problem.  Decoupled: system records and parts list the grid
+// continua of all problems first, then their fracture continua; coupled: one system per
+// problem.  Each problem keeps its own tilings and partial-sum slots, so its arithmetic is
+// the same as when it is stepped alone.
+static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, mc_report* reps) {
+  Exec& X = B->X;
+  const bool coupled = coupled_class(X.opt.scheme);
+  const bool mixed = X.opt.precision == MC_MIXED;
+  std::vector<PartD> parts;
+  std::vector<PartTiling> til;
+  std::vector<SysState> hs;
+  std::vector<std::vector<int>> sys_of(n), cont_of(n);
+  auto rec = [&](mc_problem* P, int sI, int nA, int nB) {
+    SysState S;
+    std::memset(&S, 0, sizeof(S));
+    S.partA = P->partA[sI];
+    S.partB = P->partB[sI];
+    S.nslotsA = nA;
+    S.nslotsB = nB;
+    S.done = 1;
+    sys_params(X, S, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
+    hs.push_back(S);
+  };
+  if (!coupled) {
+    for (int pass = 0; pass < 2; ++pass)          // grid continua, then fracture continua
+      for (int i = 0; i < n; ++i) {
+        mc_problem* P = probs[i];
+        for (int c = 0; c < P->ncont; ++c) {
+          if ((P->cont[c].kind == PART_GRID) != (pass == 0)) continue;
+          const int sI = (int)hs.size();
+          rec(P, c, P->cont[c].blocks[0], P->cont[c].blocks[1]);
+          parts.push_back(base_part(P, c, sI, 0, 0, mixed));
+          til.push_back(tiling_of(P, c));
+          sys_of[i].push_back(sI);
+          cont_of[i].push_back(c);
+        }
+      }
+  } else {
+    for (int i = 0; i < n; ++i) {
+      mc_problem* P = probs[i];
+      const int sI = (int)hs.size();
+      int nA = 0, nB = 0;
+      for (auto& C : P->cont) {
+        nA += C.blocks[0];
+        nB += C.blocks[1];
+      }
+      rec(P, P->ncont, nA, nB);
+      std::vector<PartD> cp = coupled_parts(P, sI, (int)parts.size());
+      for (int c = 0; c < P->ncont; ++c) {
+        parts.push_back(cp[c]);
+        til.push_back(tiling_of(P, c));
+      }
+      sys_of[i].push_back(sI);
+      cont_of[i].push_back(0);
+    }
+  }
+  const int nsys = (int)hs.size();
+  if (exec_sys_capacity(X, nsys)) {
+    drop_graphs(B->tab[0]);
+    drop_graphs(B->tab[1]);
+  }
+  HIPCHK(hipMemcpyAsync(X.sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice,
+                        X.stream));
+  Table* T = nullptr;
+  for (auto& t : B->tab)
+    if (table_matches(t, parts, til)) T = &t;
+  if (!T) {
+    T = &B->tab[B->lru];
+    B->lru ^= 1;
+    fill_table(*T, B->mem, X.stream, std::move(parts), til);
+  }
+  HIPCHK(hipStreamSynchronize(X.stream));
+  solve_table(X, *T, 0, nsys, true, mixed, !coupled);
+  read_sys(X);
+  mc_status st = MC_OK;
+  for (int i = 0; i < n; ++i) {
+    mc_problem* P = probs[i];
+    mc_report* r = reps ? &reps[i] : nullptr;
+    if (r) {
+      std::memset(r, 0, sizeof(*r));
+      r->n_cont = P->ncont;
+    }
+    mc_status si = fill_report(X, sys_of[i], cont_of[i], r, mixed && !coupled);
+    if (coupled) fill_coupled_report(P->ncont, r);
+    if (si == MC_OK) {
+      P->cur ^= 1;
+      P->step_count += 1;
+    } else if (st == MC_OK) {
+      st = si;
+      B->err = "problem " + std::to_string(i) + " failed in continuum " +
+               std::to_string(r ? r->failed : -1);
+    }
+    if (r) r->step = P->step_count;
   }
   return st;
 }
@@ -1096,29 +1402,10 @@ mc_status mc_create_problem(const mc_problem_desc* d, const mc_options* o, mc_pr
 
 mc_status mc_destroy(mc_problem* P) {
   if (!P) return MC_OK;
-  if (P->stream) (void)hipStreamSynchronize(P->stream);
-  for (auto& e : P->ev_free) {
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
-  }
-  for (auto& e : P->ev_pending) {
-    (void)hipEventDestroy(e.a);
-    (void)hipEventDestroy(e.b);
-  }
+  if (P->X.stream) (void)hipStreamSynchronize(P->X.stream);
+  mc::clear_tables(P);
   P->mem.release();
-  if (P->h_sys) (void)hipHostFree(P->h_sys);
-  if (P->stream2) (void)hipStreamSynchronize(P->stream2);
-  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
-  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
-  for (auto e : P->ev_poll)
-    if (e) (void)hipEventDestroy(e);
-  if (P->stream2) (void)hipStreamDestroy(P->stream2);
-  for (hipStream_t st : {P->stream_grid, P->stream_frac})
-    if (st) {
-      (void)hipStreamSynchronize(st);
-      (void)hipStreamDestroy(st);
-    }
-  if (P->own_stream && P->stream) (void)hipStreamDestroy(P->stream);
+  mc::exec_release(P->X);
   delete P;
   return MC_OK;
 }
@@ -1148,7 +1435,7 @@ mc_status mc_solve_continuum(mc_problem* P, int32_t alpha, const double* rhs, do
   ABI_BEGIN
   if (alpha < 0 || alpha >= P->ncont) throw mc::Error{MC_EINVAL, "alpha out of range"};
   if (!rhs || !x) throw mc::Error{MC_EINVAL, "rhs and x must be device pointers"};
-  if (P->opt.precision == MC_MIXED)
+  if (P->X.opt.precision == MC_MIXED)
     throw mc::Error{MC_EINVAL, "mc_solve_continuum solves in FP64; set precision MC_FP64"};
   auto t0 = std::chrono::steady_clock::now();
   std::vector<PartD> parts = mc::decoupled_parts(P, {alpha}, false);
@@ -1156,11 +1443,13 @@ mc_status mc_solve_continuum(mc_problem* P, int32_t alpha, const double* rhs, do
   parts[0].x64 = x;
   parts[0].b = const_cast<double*>(rhs);
   mc::Table& T = mc::upload_table(P, "solve" + std::to_string(alpha), parts);
-  mc::solve_table(P, T, alpha, alpha + 1, false, false, false);
+  mc::set_sys_params(P->X, alpha, alpha + 1, P->X.opt.tol, false);
+  mc::solve_table(P->X, T, alpha, alpha + 1, false, false, false);
+  mc::read_sys(P->X);
   mc_report r;
   std::memset(&r, 0, sizeof(r));
   r.n_cont = P->ncont;
-  mc_status st = mc::collect(P, {alpha}, {alpha}, &r, false);
+  mc_status st = mc::fill_report(P->X, {alpha}, {alpha}, &r, false);
   r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   r.step = P->step_count;
   if (rep) *rep = r;
@@ -1177,9 +1466,9 @@ mc_status mc_apply_continuum(mc_problem* P, int32_t alpha, const double* x, doub
   parts[0].x = const_cast<double*>(x);
   parts[0].q = y;
   mc::Table& T = mc::upload_table(P, "apply" + std::to_string(alpha), parts);
-  mc::launch_all(P, T, 0, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
+  mc::launch_all(P->X.stream, T, 0, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
   ABI_END(P)
 }
@@ -1188,7 +1477,7 @@ mc_status mc_apply_coupled(mc_problem* P, const double* x, double* y) {
   if (!P) return MC_EINVAL;
   ABI_BEGIN
   if (!x || !y) throw mc::Error{MC_EINVAL, "x and y must be device pointers"};
-  std::vector<PartD> parts = mc::coupled_parts(P);
+  std::vector<PartD> parts = mc::coupled_parts(P, P->ncont, 0);
   long off = 0;
   for (int c = 0; c < P->ncont; ++c) {
     parts[c].x = const_cast<double*>(x) + off;
@@ -1196,9 +1485,9 @@ mc_status mc_apply_coupled(mc_problem* P, const double* x, double* y) {
     off += P->cont[c].n;
   }
   mc::Table& T = mc::upload_table(P, "applyc", parts);
-  mc::launch_all(P, T, 0, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
+  mc::launch_all(P->X.stream, T, 0, mc::k_apply<PART_GRID>, mc::k_apply<PART_GRAPH>);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
   ABI_END(P)
 }
@@ -1212,14 +1501,14 @@ mc_status mc_apply_precond(mc_problem* P, int32_t alpha, const double* r, double
   parts[0].r = const_cast<double*>(r);
   parts[0].z = z;
   mc::Table& T = mc::upload_table(P, "prec" + std::to_string(alpha), parts);
-  if (P->opt.precond == MC_BIC0)
-    mc::launch_all(P, T, 1, mc::k_precond<PREC_BIC0, PART_GRID>,
+  if (P->X.opt.precond == MC_BIC0)
+    mc::launch_all(P->X.stream, T, 1, mc::k_precond<PREC_BIC0, PART_GRID>,
                    mc::k_precond<PREC_BIC0, PART_GRAPH>);
   else
-    mc::launch_all(P, T, 1, mc::k_precond<PREC_JACOBI, PART_GRID>,
+    mc::launch_all(P->X.stream, T, 1, mc::k_precond<PREC_JACOBI, PART_GRID>,
                    mc::k_precond<PREC_JACOBI, PART_GRAPH>);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
   ABI_END(P)
 }
@@ -1234,9 +1523,9 @@ mc_status mc_assemble_rhs(mc_problem* P, int32_t alpha, double* b) {
   parts[0].x64 = P->cont[alpha].r;    // warm-start copy goes to scratch
   parts[0].coupled = 0;
   mc::Table& T = mc::upload_table(P, "rhs" + std::to_string(alpha), parts);
-  mc::launch_all(P, T, 0, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
+  mc::launch_all(P->X.stream, T, 0, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
   ABI_END(P)
 }
@@ -1246,8 +1535,8 @@ mc_status mc_get_state(mc_problem* P, int32_t alpha, double* out) {
   ABI_BEGIN
   if (alpha < 0 || alpha >= P->ncont || !out) throw mc::Error{MC_EINVAL, "bad argument"};
   HIPCHK(hipMemcpyAsync(out, P->cont[alpha].ps[P->cur], P->cont[alpha].n * sizeof(double),
-                        hipMemcpyDeviceToHost, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
+                        hipMemcpyDeviceToHost, P->X.stream));
+  HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
   ABI_END(P)
 }
@@ -1257,8 +1546,8 @@ mc_status mc_set_state(mc_problem* P, int32_t alpha, const double* in) {
   ABI_BEGIN
   if (alpha < 0 || alpha >= P->ncont || !in) throw mc::Error{MC_EINVAL, "bad argument"};
   HIPCHK(hipMemcpyAsync(P->cont[alpha].ps[P->cur], in, P->cont[alpha].n * sizeof(double),
-                        hipMemcpyHostToDevice, P->stream));
-  HIPCHK(hipStreamSynchronize(P->stream));
+                        hipMemcpyHostToDevice, P->X.stream));
+  HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
   ABI_END(P)
 }
@@ -1268,19 +1557,20 @@ mc_status mc_set_options(mc_problem* P, const mc_options* o) {
   ABI_BEGIN
   std::string m = mc::validate_options(*o);
   if (!m.empty()) throw mc::Error{MC_EINVAL, m};
-  if (o->stream && o->stream != (void*)P->stream)
+  if (o->stream && o->stream != (void*)P->X.stream)
     throw mc::Error{MC_EINVAL, "the stream cannot change after creation"};
-  const bool rebuild = (o->scheme == MC_SCHEME_EX) != (P->opt.scheme == MC_SCHEME_EX) ||
-                       (o->precision != P->opt.precision) || (o->precond != P->opt.precond);
-  P->opt = *o;
-  P->opt.stream = P->stream;
+  const mc_options& cur = P->X.opt;
+  const bool rebuild = (o->scheme == MC_SCHEME_EX) != (cur.scheme == MC_SCHEME_EX) ||
+                       (o->precision != cur.precision) || (o->precond != cur.precond);
+  P->X.opt = *o;
+  P->X.opt.stream = P->X.stream;
   if (rebuild) mc::build_coefficients(P);
-  P->tables.clear();
+  mc::clear_tables(P);
   // the update tiling depends on the preconditioner: refresh the slot counts
   const size_t nb = (P->ncont + 1) * sizeof(SysState);
-  HIPCHK(hipMemcpy(P->h_sys, P->sys, nb, hipMemcpyDeviceToHost));
-  mc::set_slot_counts(P, P->h_sys);
-  HIPCHK(hipMemcpy(P->sys, P->h_sys, nb, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(P->X.h_sys, P->X.sys, nb, hipMemcpyDeviceToHost));
+  mc::set_slot_counts(P, P->X.h_sys);
+  HIPCHK(hipMemcpy(P->X.sys, P->X.h_sys, nb, hipMemcpyHostToDevice));
   return MC_OK;
   ABI_END(P)
 }
@@ -1301,31 +1591,119 @@ const char* mc_last_error(const mc_problem* P) {
   return mc::g_thread_error.c_str();
 }
 
-mc_status mc_profile(mc_problem* P, int32_t enable) {
-  if (!P) return MC_EINVAL;
-  ABI_BEGIN
-  HIPCHK(hipStreamSynchronize(P->stream));
-  mc::prof_harvest(P);
-  P->prof = enable != 0;
+static mc_status exec_profile(mc::Exec& X, int32_t enable) {
+  HIPCHK(hipStreamSynchronize(X.stream));
+  mc::prof_harvest(X);
+  X.prof = enable != 0;
   if (enable) {
-    P->prof_launch[0] = P->prof_launch[1] = 0;
-    P->prof_ms[0] = P->prof_ms[1] = 0;
-    P->prof_count[0] = P->prof_count[1] = 0;
-    P->prof_every = enable > 1 ? enable : 8;
+    X.prof_launch[0] = X.prof_launch[1] = 0;
+    X.prof_ms[0] = X.prof_ms[1] = 0;
+    X.prof_count[0] = X.prof_count[1] = 0;
+    X.prof_every = enable;
   }
   return MC_OK;
+}
+
+static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* launches,
+                                   double* total_ms) {
+  HIPCHK(hipStreamSynchronize(X.stream));
+  mc::prof_harvest(X);
+  if (launches) *launches = X.prof_launch[which];
+  if (total_ms) *total_ms = X.prof_ms[which];
+  return MC_OK;
+}
+
+mc_status mc_profile(mc_problem* P, int32_t enable) {
+  if (!P || enable < 0) return MC_EINVAL;
+  ABI_BEGIN
+  return exec_profile(P->X, enable);
   ABI_END(P)
 }
 
 mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* launches, double* total_ms) {
   if (!P || which < 0 || which > 1) return MC_EINVAL;
   ABI_BEGIN
-  HIPCHK(hipStreamSynchronize(P->stream));
-  mc::prof_harvest(P);
-  if (launches) *launches = P->prof_launch[which];
-  if (total_ms) *total_ms = P->prof_ms[which];
-  return MC_OK;
+  return exec_profile_read(P->X, which, launches, total_ms);
   ABI_END(P)
+}
+
+// ---- batches -------------------------------------------------------------------------
+mc_status mc_batch_create(const mc_options* o, mc_batch** out) {
+  if (!out) {
+    mc::g_thread_error = "out is NULL";
+    return MC_EINVAL;
+  }
+  *out = nullptr;
+  mc_options od;
+  mc_options_default(&od);
+  if (o) od = *o;
+  std::string m = mc::validate_options(od);
+  if (!m.empty()) {
+    mc::g_thread_error = m;
+    return MC_EINVAL;
+  }
+  if (od.scheme == MC_SCHEME_L || od.scheme == MC_SCHEME_U) {
+    mc::g_thread_error = "the L- and U-schemes are not batched";
+    return MC_EINVAL;
+  }
+  mc_batch* B = new mc_batch();
+  try {
+    B->X.opt = od;
+    mc::exec_init(B->X, od.stream);
+    B->X.opt.stream = B->X.stream;
+  } catch (const mc::Error& e) {
+    mc::g_thread_error = e.msg;
+    mc_batch_destroy(B);
+    return e.st;
+  }
+  *out = B;
+  return MC_OK;
+}
+
+mc_status mc_batch_destroy(mc_batch* B) {
+  if (!B) return MC_OK;
+  if (B->X.stream) (void)hipStreamSynchronize(B->X.stream);
+  for (auto& t : B->tab) mc::drop_graphs(t);
+  B->mem.release();
+  mc::exec_release(B->X);
+  delete B;
+  return MC_OK;
+}
+
+mc_status mc_batch_step(mc_batch* B, mc_problem* const* probs, int32_t n, int32_t n_steps,
+                        mc_report* reps) {
+  if (!B) return MC_EINVAL;
+  ABI_BEGIN
+  if (n_steps < 1) throw mc::Error{MC_EINVAL, "n_steps must be >= 1"};
+  mc::batch_check(B, probs, n);
+  auto t0 = std::chrono::steady_clock::now();
+  mc_status st = MC_OK;
+  for (int k = 0; k < n_steps && st == MC_OK; ++k) st = mc::batch_step_once(B, probs, n, reps);
+  const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (reps)
+    for (int i = 0; i < n; ++i) reps[i].seconds = sec;
+  return st;
+  ABI_END(B)
+}
+
+const char* mc_batch_last_error(const mc_batch* B) {
+  if (B) return B->err.c_str();
+  return mc::g_thread_error.c_str();
+}
+
+mc_status mc_batch_profile(mc_batch* B, int32_t enable) {
+  if (!B || enable < 0) return MC_EINVAL;
+  ABI_BEGIN
+  return exec_profile(B->X, enable);
+  ABI_END(B)
+}
+
+mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* launches,
+                                double* total_ms) {
+  if (!B || which < 0 || which > 1) return MC_EINVAL;
+  ABI_BEGIN
+  return exec_profile_read(B->X, which, launches, total_ms);
+  ABI_END(B)
 }
 
 }  // extern "C"

@@ -666,7 +666,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ part
 }
 
 // ------------------------------------------------------------------------------------
-// PCG.  Iteration k is the launch pair (k_pcg_A(k), k_pcg_B(k)); k is a launch argument.
+// PCG.  Iteration k is the launch pair (k_pcg_A, k_pcg_B); k lives in the system record.
 //   init   r = b - A x                               -> partB (rz, rr, bb)
 //   A(k)   from partB: stop test, beta; p_new = z + beta p_old; q = A p_new -> partA (pq)
 //   B(k)   from partA: alpha; x += alpha p; r -= alpha q; z = M^-1 r        -> partB (rz, rr)
@@ -759,8 +759,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 template <class T, int PREC, int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ parts,
                                                     const Tile* __restrict__ tiles,
-                                                    SysState* __restrict__ sys, int k,
-                                                    int outer_check) {
+                                                    SysState* __restrict__ sys) {
   constexpr int W = MC_TX + 2, H = MC_TY + 2;
   __shared__ T sp[KIND == PART_GRID ? W * H : 1];
   const Tile t = tiles[blockIdx.x];
@@ -768,7 +767,10 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
   if (ld_flag(&S.done)) return;
+  const int k = S.ka;
+  const bool outer_check = S.mixed && k == 0;   // first inner iteration after a residual
   const bool w0 = t.slot == 0;
+  if (w0 && threadIdx.x == 0) S.kb = k;
   double v[5];
   reduce_slots<5>(S.partB, S.nslotsB, v);
   if (outer_check) {   // first inner iteration after an FP64 residual: refinement test
@@ -894,12 +896,14 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
 template <class T, int PREC, int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_pcg_B(const PartD* __restrict__ parts,
                                                     const Tile* __restrict__ tiles,
-                                                    SysState* __restrict__ sys, int k) {
+                                                    SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
   if (ld_flag(&S.done)) return;
+  const int k = S.kb;
+  if (t.slot == 0 && threadIdx.x == 0) S.ka = k + 1;
   double v1[1];
   reduce_slots<1>(S.partA, S.nslotsA, v1);
   const double pq = v1[0];
@@ -991,7 +995,10 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   residual_and_precond<float, PREC, KIND>(parts, P, t, P.x64, r32, (float*)P.z, emit, v, true);
   v[2] = v[1];
   write_slot<5>(S.partB, t.slot, v);
-  if (t.slot == 0 && threadIdx.x == 0) st_flag(&S.done, 0);   // a new inner solve starts
+  if (t.slot == 0 && threadIdx.x == 0) {   // a new inner solve starts
+    S.ka = 0;
+    st_flag(&S.done, 0);
+  }
 }
 
 // x64 += (double) x32 for systems still refining; workgroup 0 counts the pass.
@@ -1074,6 +1081,8 @@ __global__ void k_reset(SysState* sys, int s0, int s1) {
     S.outer = 0;
     S.outer_done = 0;
     S.outer_status = ST_RUN;
+    S.ka = 0;
+    S.kb = 0;
   }
 }
 

@@ -107,6 +107,17 @@ mc_profile_read = _sig("mc_profile_read", C.c_int,
                        [_PROBLEM, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)])
 
 
+_BATCH = C.c_void_p
+mc_batch_create = _sig("mc_batch_create", C.c_int, [C.POINTER(Options), C.POINTER(_BATCH)])
+mc_batch_destroy = _sig("mc_batch_destroy", C.c_int, [_BATCH])
+mc_batch_step = _sig("mc_batch_step", C.c_int,
+                     [_BATCH, C.POINTER(_PROBLEM), C.c_int32, C.c_int32, C.POINTER(Report)])
+mc_batch_last_error = _sig("mc_batch_last_error", C.c_char_p, [_BATCH])
+mc_batch_profile = _sig("mc_batch_profile", C.c_int, [_BATCH, C.c_int32])
+mc_batch_profile_read = _sig("mc_batch_profile_read", C.c_int,
+                             [_BATCH, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)])
+
+
 class McError(RuntimeError):
     def __init__(self, status: int, msg: str, report: Optional[dict] = None):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -114,9 +125,9 @@ class McError(RuntimeError):
         self.report = report
 
 
-def _check(st, handle=None, report=None):
+def _check(st, handle=None, report=None, last_error=None):
     if st != MC_OK:
-        msg = mc_last_error(handle)
+        msg = (last_error or mc_last_error)(handle)
         raise McError(st, msg.decode() if msg else "", report)
 
 
@@ -321,8 +332,62 @@ class Problem:
         return n.value, ms.value
 
 
+class Batch:
+    """Executor that advances many resident problems together (wraps mc_batch): every PCG
+    launch covers all continua of all problems passed to `step`."""
+
+    def __init__(self, scheme="D", precision="fp64", precond="jacobi", tol=1e-10,
+                 max_iter=20000, stream="default", **kw):
+        if stream == "default":
+            stream = _default_stream()
+        self.opt = make_options(scheme, precision, precond, tol, max_iter, stream=stream, **kw)
+        h = _BATCH()
+        _check(mc_batch_create(C.byref(self.opt), C.byref(h)), None,
+               last_error=mc_batch_last_error)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            mc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, problems, n_steps: int = 1):
+        """Advance every Problem in `problems` by n_steps layers; one report dict each."""
+        n = len(problems)
+        arr = (_PROBLEM * n)(*[p.h for p in problems])
+        reps = (Report * n)()
+        st = mc_batch_step(self.h, arr, n, n_steps, reps)
+        out = [r.as_dict() for r in reps]
+        _check(st, self.h, out, last_error=mc_batch_last_error)
+        return out
+
+    def profile(self, enable: bool, every: int = 8):
+        _check(mc_batch_profile(self.h, max(1, int(every)) if enable else 0), self.h,
+               last_error=mc_batch_last_error)
+
+    def profile_read(self, which: int):
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(mc_batch_profile_read(self.h, which, C.byref(n), C.byref(ms)), self.h,
+               last_error=mc_batch_last_error)
+        return n.value, ms.value
+
+
 EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
            "mc_solve_continuum", "mc_apply_continuum", "mc_apply_coupled", "mc_assemble_rhs",
            "mc_apply_precond",
            "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
-           "mc_profile", "mc_profile_read"]
+           "mc_profile", "mc_profile_read", "mc_batch_create", "mc_batch_destroy",
+           "mc_batch_step", "mc_batch_last_error", "mc_batch_profile", "mc_batch_profile_read"]
