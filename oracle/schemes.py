@@ -40,14 +40,19 @@ class CertificationError(RuntimeError):
 class DirectSolver:
     """Sparse LU of an SPD matrix, with a residual certificate on every solve.
 
-    The certificate is the normwise backward error: ||b - K x|| <= CERT_TOL (||b|| +
-    ||K|| ||x||) with ||K|| bounded by the largest absolute row sum (K is symmetric)."""
+    Every system matrix of the schemes is symmetric positive definite (storage over tau
+    plus a symmetric nonnegative-definite flux and transfer part, Sections 3.1-3.3), so
+    the factorization keeps the symmetric fill-reducing order and takes its pivots from
+    the diagonal (no row interchanges).  The certificate is the normwise backward error:
+    ||b - K x|| <= CERT_TOL (||b|| + ||K|| ||x||) with ||K|| bounded by the largest
+    absolute row sum (K is symmetric)."""
 
     def __init__(self, K: sp.spmatrix):
         self.K = K.tocsr()
         self.knorm = float(abs(self.K).sum(axis=1).max()) if self.K.shape[0] else 0.0
         t = time.perf_counter()
-        self.lu = spla.splu(self.K.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        self.lu = spla.splu(self.K.tocsc(), permc_spec="MMD_AT_PLUS_A",
+                            diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
         self.factor_seconds = time.perf_counter() - t
 
     def solve(self, b: np.ndarray) -> np.ndarray:
