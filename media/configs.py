@@ -229,17 +229,35 @@ def _family_member(rng: np.random.Generator, n: int, three: bool, sigma_log: Opt
                          meta=dict(name=name, precond="jacobi", tol=1e-10, precision="mixed"))
 
 
-def c4_problems(count: int = 256, seed: int = 4, n_range=(128, 1024)) -> List[Problem]:
+def _c4_draw(ss, n_range):
+    rng = np.random.default_rng(ss)
+    three = bool(rng.integers(0, 2))
+    n = int(rng.integers(n_range[0], n_range[1] + 1))
+    sl = float(rng.uniform(0.5, 2.5))
+    nseg = int(rng.integers(20, 201))
+    return rng, three, n, sl, nseg
+
+
+def c4_problems(count: int = 256, seed: int = 4, n_range=(128, 1024),
+                only: Optional[List[int]] = None) -> List[Problem]:
     """Batched realizations: two- or three-continuum (1/2 each), side n ~ U{n_range},
-    lognormal matrix permeability with sigma_log ~ U[0.5, 2.5], 20..200 segments."""
+    lognormal matrix permeability with sigma_log ~ U[0.5, 2.5], 20..200 segments.
+    Realization i depends only on its own spawned seed; `only` builds a subset."""
     out = []
     for i, ss in enumerate(np.random.SeedSequence(seed).spawn(count)):
-        rng = np.random.default_rng(ss)
-        three = bool(rng.integers(0, 2))
-        n = int(rng.integers(n_range[0], n_range[1] + 1))
-        sl = float(rng.uniform(0.5, 2.5))
-        nseg = int(rng.integers(20, 201))
+        if only is not None and i not in only:
+            continue
+        rng, three, n, sl, nseg = _c4_draw(ss, n_range)
         out.append(_family_member(rng, n, three, sl, None, nseg, 50, f"C4[{i}]"))
+    return out
+
+
+def c4_shapes(count: int = 256, seed: int = 4, n_range=(128, 1024)):
+    """(n, three_continuum) of every realization, without building the fields."""
+    out = []
+    for ss in np.random.SeedSequence(seed).spawn(count):
+        _, three, n, _, _ = _c4_draw(ss, n_range)
+        out.append((n, three))
     return out
 
 

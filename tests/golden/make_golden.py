@@ -6,6 +6,7 @@ plus the full norms, so a GPU run at the same size can be checked entry by entry
 sample and by relative error on the norm.
 
     python tests/golden/make_golden.py C2        # about 5-10 minutes, ~20 GB RAM
+    python tests/golden/make_golden.py C4        # six realizations of the batch, ~1 minute
 """
 import os
 import sys
@@ -23,11 +24,11 @@ from oracle import schemes  # noqa: E402
 NSAMPLE = 20000
 
 
-def sample_indices(p, seed=99):
+def sample_indices(p, seed=99, nsample=NSAMPLE):
     rng = np.random.default_rng(seed)
     out = []
     for n in p.sizes():
-        out.append(np.sort(rng.choice(n, size=min(n, NSAMPLE), replace=False)).astype(np.int64))
+        out.append(np.sort(rng.choice(n, size=min(n, nsample), replace=False)).astype(np.int64))
     return out
 
 
@@ -55,10 +56,41 @@ def run(name, d_steps, c_steps):
     print("wrote", out, os.path.getsize(out), "bytes")
 
 
+# the three smallest two-continuum and three-continuum realizations of the batched workload
+C4_SUBSET = [168, 55, 253, 212, 105, 150]
+
+
+def run_c4(d_steps=(1, 50), c_steps=(1, 2)):
+    """Oracle states of a subset of the 256 batched realizations (each is independent, so a
+    subset of the batch is checked problem by problem)."""
+    data = {"problems": np.array(C4_SUBSET)}
+    for i, p in zip(sorted(C4_SUBSET), media.configs.c4_problems(only=C4_SUBSET)):
+        idx = sample_indices(p, seed=100 + i, nsample=3000)
+        for a in range(p.n_cont):
+            data[f"p{i}_idx{a}"] = idx[a]
+        for scheme, keep in (("D", d_steps), ("coupled", c_steps)):
+            t = time.time()
+            st = schemes.Stepper(p, None, scheme)
+            x = p.initial_state()
+            for n in range(1, max(keep) + 1):
+                x = st.step(x)
+                if n in keep:
+                    for a in range(p.n_cont):
+                        data[f"p{i}_{scheme}_s{n}_c{a}"] = x[a][idx[a]]
+            print(f"C4[{i}] n={p.nx} cont={p.n_cont} {scheme}: {time.time() - t:.1f}s", flush=True)
+    data["steps_D"] = np.array(d_steps)
+    data["steps_coupled"] = np.array(c_steps)
+    out = os.path.join(HERE, "c4_oracle.npz")
+    np.savez_compressed(out, **data)
+    print("wrote", out, os.path.getsize(out), "bytes")
+
+
 if __name__ == "__main__":
     name = sys.argv[1] if len(sys.argv) > 1 else "C2"
     if name == "C2":
         run("C2", d_steps=[1, 10, 100], c_steps=[1, 5, 100])
+    elif name == "C4":
+        run_c4()
     elif name == "C1":
         run("C1", d_steps=list(range(1, 21)), c_steps=list(range(1, 21)))
     else:
