@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the decoupled multicontinuum time step on one MI355X.
 
-Workload (default): the two-continuum fractured medium on a 2048 x 2048 grid (lognormal
-matrix permeability, 400 any-angle fracture segments, ~63k fracture cells), tau = 1e-3,
-100 backward-Euler time layers, D-scheme with per-continuum PCG to 1e-10, FP64.
+Workloads (``--workload``):
+  C2 (default)  two-continuum fractured medium on a 2048 x 2048 grid (lognormal matrix
+                permeability, 400 any-angle fracture segments, ~63k fracture cells),
+                tau = 1e-3, 100 backward-Euler layers, D-scheme, FP64, block IC(0) PCG to 1e-10.
+  C1            64 x 64 two-continuum medium, 20 layers, Jacobi PCG to 1e-12 (latency-bound).
+  C3            three continua on a 4096 x 4096 grid (~150k fracture cells), 50 layers,
+                FP32 inner PCG inside FP64 refinement to 1e-10.
+  C4            256 independent realizations of uneven size (128..1024 cells a side, two or
+                three continua), 50 layers, all advanced by shared launches in FP32 inner PCG
+                inside FP64 refinement.
 
-One "step" = one time layer of the whole hot path: transfer right-hand side assembly for
-every continuum plus every PCG iteration of every continuum.  The timed region starts with
-all inputs resident on the GPU and the state reset to the initial pressure, and covers
-exactly `--steps` layers.  Printed: one JSON line (metric, value = cell-updates/s, ...)
-with the roofline of the dominant kernel, the coupled-FP64 comparison on the same GPU,
-p50/p99 step latency, accuracy against stored oracle values, and the CPU oracle baseline.
+One "step" = one time layer of the whole hot path for the whole workload: transfer
+right-hand-side assembly of every continuum plus every PCG iteration (and refinement pass)
+of every continuum.  The timed region starts with all inputs resident on the GPU and the
+state reset to the initial pressure, and covers exactly `--steps` layers.  Printed: one JSON
+line (metric, value = cell-updates/s, ...) with the roofline of the dominant kernel (HIP
+events bound to sampled dispatches inside the timed region), the coupled-FP64 comparison on
+the same GPU, p50/p99 step latency, accuracy against stored oracle values, and the CPU
+oracle baseline on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -28,14 +38,23 @@ METRIC = ("cell-updates/s per decoupled time step vs coupled+FP64 at 1e-8 rel er
           "p50/p99 step latency")
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per dispatch of the grid operator kernel, from two rocprofv3 counter passes
+DEFAULTS = {
+    "C1": dict(precond="jacobi", precision="fp64", tol=1e-12, steps=20, coupled_steps=20),
+    "C2": dict(precond="bic0", precision="fp64", tol=1e-10, steps=100, coupled_steps=5),
+    "C3": dict(precond="bic0", precision="mixed", tol=1e-10, steps=50, coupled_steps=1),
+    "C4": dict(precond="bic0", precision="mixed", tol=1e-10, steps=50, coupled_steps=2),
+}
+
+# HBM bytes per dispatch of the grid PCG kernels, from two rocprofv3 counter passes
 # (FETCH_SIZE, then WRITE_SIZE) of `bench.py --steps 2 --warmup 0 --no-cpu --no-coupled
 # --calibrate-copy 4096`, each scaled by what the same counter reads for a 2 GiB sum (read
 # factor 1.9999) and a 2 GiB fill (write factor 0.9999).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "bic0"): {"sources": "7be7f8b36faa832f", "fetch_kib": 84047.2, "write_kib": 65600.4,
-                     "read_factor": 1.9999, "write_factor": 0.9999},
+    ("C2", "bic0", "A"): {"sources": "7be7f8b36faa832f", "fetch_kib": 84047.2,
+                          "write_kib": 65600.4, "read_factor": 1.9999, "write_factor": 0.9999},
+    ("C2", "bic0", "B"): {"sources": "7be7f8b36faa832f", "fetch_kib": 90328.5,
+                          "write_kib": 98320.0, "read_factor": 1.9999, "write_factor": 0.9999},
 }
 
 
@@ -43,18 +62,7 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def grid_A_bytes_per_cell(precision, precond, has_t):
-    """Algorithmic bytes the grid operator kernel (p_new = z + beta p_old, q = A p_new,
-    partial (p,q)) must move per cell: read r (or z), p_old, diag [, tx, ty]; write p_new,
-    q; Jacobi reads diag once for both z and the operator."""
-    w = 8 if precision == "fp64" else 4
-    reads = 3 + (2 if has_t else 0)
-    writes = 2
-    return (reads + writes) * w
-
-
 def kernel_sources_hash():
-    import hashlib
     h = hashlib.sha256()
     for f in ("kernels.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2209_01158_amd", "csrc", f), "rb") as fh:
@@ -62,104 +70,188 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precond):
-    m = MEASURED_TRAFFIC.get((workload, precond))
+def measured_traffic(workload, precond, kernel):
+    m = MEASURED_TRAFFIC.get((workload, precond, kernel))
     if m is None or m["sources"] != kernel_sources_hash():
         return None
     return (m["fetch_kib"] * m["read_factor"] + m["write_kib"] * m["write_factor"]) * 1024.0
 
 
-def golden_check(g, name, steps, scheme):
+def grid_bytes_per_cell(kernel, precision, precond, has_t):
+    """Algorithmic bytes a grid PCG kernel must move per cell (w = 4 or 8 byte words).
+
+    A (operator): read z (Jacobi: r), p_old, diag [, tx, ty]; write p_new, q.
+    B (update):   read x, p, r, q; write x, r; Jacobi also reads diag (z = r / diag is
+                  recomputed where needed, never stored); block IC(0) reads the FP32 copies
+                  of the inverse pivots and of tx, ty (4 bytes each) and writes z."""
+    w = 4 if precision == "mixed" else 8
+    if kernel == "A":
+        return (3 + (2 if has_t else 0) + 2) * w
+    if precond == "bic0":
+        return 7 * w + 3 * 4
+    return 7 * w
+
+
+def roofline(kind_time, bytes_total, precision, precond, workload):
+    """Roofline objects of the grid operator (A) and update (B) kernels; the one with more
+    total time is the dominant kernel.  Per-launch algorithmic bytes = total over the timed
+    layers (iterations x cells x bytes per cell of every grid system) / launches issued;
+    average duration from the sampled launches."""
+    out = {}
+    for k, (sampled, ms, issued) in kind_time.items():
+        if not sampled:
+            continue
+        avg_s = ms / sampled * 1e-3
+        per_launch = bytes_total[k] / max(issued, 1)
+        achieved = per_launch / avg_s / 1e9
+        tp = "float" if precision == "mixed" else "double"
+        pn = {"bic0": "BIC0", "jacobi": "JACOBI"}[precond]
+        name = (f"k_pcg_{k}<{tp},{pn},GRID> " +
+                ("(p = z + beta p; q = A p; partial p.q)" if k == "A" else
+                 "(x += alpha p; r -= alpha q; z = M^-1 r; partial r.z, r.r)"))
+        out[k] = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                  "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                  "traffic": measured_traffic(workload, precond, k),
+                  "traffic_unit": "bytes per launch",
+                  "algorithmic_bytes_per_launch": per_launch,
+                  "avg_launch_us": avg_s * 1e6, "sampled_launches": sampled,
+                  "issued_launches": issued, "total_ms_est": avg_s * issued * 1e3}
+    if not out:
+        return None, None
+    dom = max(out, key=lambda k: out[k]["total_ms_est"])
+    other = [k for k in out if k != dom]
+    return out[dom], (out[other[0]] if other else None)
+
+
+def golden_states(states_of, name, step, scheme):
+    """Relative L2 error on the stored oracle sample: states_of(a) -> state of continuum a."""
     path = os.path.join(ROOT, "tests", "golden", f"{name.lower()}_oracle.npz")
     if not os.path.exists(path):
         return None
     z = np.load(path, allow_pickle=False)
-    if steps not in list(z[f"steps_{scheme}"]):
+    if step not in list(z[f"steps_{scheme}"]):
         return None
     num = den = 0.0
-    maxrel = 0.0
-    for a in range(g.n_cont):
-        st = g.get_state(a)
+    a = 0
+    while f"idx{a}" in z:
         idx = z[f"idx{a}"]
-        ref = z[f"{scheme}_s{steps}_c{a}"]
-        d = st[idx] - ref
+        ref = z[f"{scheme}_s{step}_c{a}"]
+        d = states_of(a)[idx] - ref
         num += float(d @ d)
         den += float(ref @ ref)
-        maxrel = max(maxrel, float(np.max(np.abs(d)) / max(np.max(np.abs(ref)), 1e-300)))
-    return dict(rel_l2_sampled=float(np.sqrt(num / den)) if den > 0 else float(np.sqrt(num)),
-                max_abs_over_max=maxrel, reference=os.path.relpath(path, ROOT),
-                sample=f"{len(z['idx0'])} seeded cells per continuum, step {steps}")
+        a += 1
+    return dict(rel_l2_sampled=float(np.sqrt(num / den)), step=step, scheme=scheme,
+                reference=os.path.relpath(path, ROOT),
+                sample=f"{len(z['idx0'])} seeded cells per continuum")
 
 
-def cpu_baseline(n_cpu=1024, steps=5):
-    """The CPU oracle (SuperLU, one core) on a bounded sample of the workload's recipe."""
+def golden_c4(handles, step, scheme):
+    """Per-problem relative L2 error on the stored oracle samples of six realizations."""
+    path = os.path.join(ROOT, "tests", "golden", "c4_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    if step not in list(z[f"steps_{scheme}"]):
+        return None
+    per = {}
+    for i in z["problems"]:
+        i = int(i)
+        num = den = 0.0
+        a = 0
+        while f"p{i}_idx{a}" in z:
+            ref = z[f"p{i}_{scheme}_s{step}_c{a}"]
+            d = handles[i].get_state(a)[z[f"p{i}_idx{a}"]] - ref
+            num += float(d @ d)
+            den += float(ref @ ref)
+            a += 1
+        per[str(i)] = float(np.sqrt(num / den))
+    return dict(rel_l2_sampled_max=max(per.values()), per_problem=per, step=step,
+                scheme=scheme, reference=os.path.relpath(path, ROOT))
+
+
+def cpu_baseline(workload):
+    """The CPU oracle (SuperLU, one core) on a bounded sample of the workload's recipe;
+    rate per layer excludes the one-time factorization (reported beside it)."""
     import media
     from oracle import schemes
-    p = media.configs._c2(n=n_cpu, nseg=max(1, 400 * n_cpu // 2048))
-    t0 = time.perf_counter()
-    st = schemes.Stepper(p, None, "D")
-    t1 = time.perf_counter()
-    x = p.initial_state()
-    for _ in range(steps):
-        x = st.step(x)
-    t2 = time.perf_counter()
-    dof = p.dof()
-    return {"value": dof * steps / (t2 - t1), "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"C2 recipe at {n_cpu}x{n_cpu} ({p.nf} fracture cells), D-scheme, "
-                       f"{steps} steps after a one-time sparse LU factorization "
-                       f"({t1 - t0:.1f} s, excluded; including it: "
-                       f"{dof * steps / (t2 - t0):.3g} cell-updates/s); SuperLU is sequential"),
+    if workload == "C1":
+        probs, steps, what = [media.config_problem("C1")], 20, "the full C1 workload"
+    elif workload == "C2":
+        probs, steps = [media.configs._c2(n=1024, nseg=200)], 5
+        what = "C2 recipe at 1024x1024 (200 segments)"
+    elif workload == "C3":
+        probs, steps = [media.configs._c3(n=1024, min_cells=150_000 // 16)], 3
+        what = "C3 recipe at 1024x1024 (three continua)"
+    else:
+        probs, steps = media.configs.c4_problems(only=[55, 212]), 10
+        what = "realizations 55 and 212 of the batched workload"
+    tf = ts = 0.0
+    dof = 0
+    for p in probs:
+        t0 = time.perf_counter()
+        st = schemes.Stepper(p, None, "D")
+        t1 = time.perf_counter()
+        x = p.initial_state()
+        for _ in range(steps):
+            x = st.step(x)
+        t2 = time.perf_counter()
+        tf += t1 - t0
+        ts += t2 - t1
+        dof += p.dof()
+    return {"value": dof * steps / ts, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{what}, D-scheme, {steps} layers after a one-time sparse LU "
+                       f"factorization ({tf:.1f} s, excluded; including it: "
+                       f"{dof * steps / (ts + tf):.3g} cell-updates/s); SuperLU is sequential"),
             "host_cpu": platform.processor() or platform.machine(),
             "host_cpu_count": os.cpu_count()}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2")
-    ap.add_argument("--precond", default="bic0")
-    ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--coupled-steps", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-coupled", action="store_true")
-    ap.add_argument("--calibrate-copy", type=int, default=0,
-                    help="MiB written by a fill and read by a sum (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
+def step_bytes(p, rep, precision, precond):
+    """Algorithmic bytes of the grid A and B kernels for one layer of problem p."""
+    out = {"A": 0.0, "B": 0.0}
+    for c in range(p.n_omega):
+        has_t = p.omega[c].k is not None
+        for k in out:
+            out[k] += rep["iters"][c] * p.ncell * grid_bytes_per_cell(k, precision, precond,
+                                                                      has_t)
+    return out
 
+
+def options(args):
+    o = dict(scheme="D", precision=args.precision, precond=args.precond)
+    if args.precision == "mixed":
+        o.update(outer_tol=args.tol, inner_tol=1e-6)
+    else:
+        o.update(tol=args.tol)
+    return o
+
+
+def run_single(args, out):
     import torch
     import media
     from paper_2209_01158_amd import mcdec
-    assert torch.cuda.is_available(), "no GPU"
-    torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
-
     t = time.time()
     p = media.config_problem(args.workload)
-    log(f"workload {args.workload}: {p.nx}x{p.ny}, nf={p.nf}, dof={p.dof()} "
-        f"(generated in {time.time() - t:.1f}s)")
+    log(f"workload {args.workload}: {p.nx}x{p.ny}, {p.n_cont} continua, nf={p.nf}, "
+        f"dof={p.dof()} (generated in {time.time() - t:.1f}s)")
     dof = p.dof()
     p0 = p.initial_state()
-
     with torch.cuda.stream(stream):
         t = time.time()
-        g = mcdec.Problem(p, scheme="D", precision="fp64", precond=args.precond, tol=args.tol,
-                          stream=stream.cuda_stream)
-        inf = g.info()
-        log(f"setup {time.time() - t:.2f}s, device memory {inf.device_bytes / 2**20:.0f} MiB")
+        g = mcdec.Problem(p, stream=stream.cuda_stream, **options(args))
+        if args.autotune:
+            ta = time.time()
+            mcdec.autotune([g], iters=20)
+            log(f"autotune {time.time() - ta:.2f}s: {mcdec.tilings(g)}")
+        log(f"setup {time.time() - t:.2f}s, device memory {g.info().device_bytes / 2**20:.0f} MiB")
         for k in range(args.warmup):
             rep = g.step(1)
             log(f"warmup step {k + 1}: iters {rep['iters']}, {rep['seconds'] * 1e3:.2f} ms")
         g.set_states(p0)
-        g.profile(True)
-        lat = []
-        iters = []
+        g.profile(True, every=args.sample_every)
+        lat, iters = [], []
+        tot = {"A": 0.0, "B": 0.0}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -167,21 +259,23 @@ def main():
             rep = g.step(1)
             lat.append(time.perf_counter() - ts)
             iters.append(rep["iters"])
+            sb = step_bytes(p, rep, args.precision, args.precond)
+            tot["A"] += sb["A"]
+            tot["B"] += sb["B"]
             if (k + 1) % 20 == 0:
-                log(f"step {k + 1}/{args.steps}: iters {rep['iters']}")
+                log(f"step {k + 1}/{args.steps}: iters {rep['iters']} outer {rep['outer']}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        nA, msA = g.profile_read(0)
-        nB, msB = g.profile_read(1)
+        prof = {"A": g.profile_read(0), "B": g.profile_read(1)}
         g.profile(False)
         elapsed = t1 - t0
         value = dof * args.steps / elapsed
-        acc = golden_check(g, args.workload, args.steps, "D")
+        acc = golden_states(g.get_state, args.workload, args.steps, "D")
         log(f"decoupled: {value:.4g} cell-updates/s, {elapsed / args.steps * 1e3:.3f} ms/step")
 
         coupled = None
         if not args.no_coupled and args.coupled_steps > 0:
-            g.set_options(scheme="coupled")
+            g.set_options(scheme="coupled", precision="fp64", tol=min(args.tol, 1e-10))
             g.set_states(p0)
             torch.cuda.synchronize()
             c0 = time.perf_counter()
@@ -193,58 +287,217 @@ def main():
             torch.cuda.synchronize()
             c1 = time.perf_counter()
             cval = dof * args.coupled_steps / (c1 - c0)
-            cacc = golden_check(g, args.workload, args.coupled_steps, "coupled")
+            cacc = golden_states(g.get_state, args.workload, args.coupled_steps, "coupled")
             coupled = {"value": cval, "unit": "cell-updates/s", "steps": args.coupled_steps,
                        "ms_per_step": (c1 - c0) / args.coupled_steps * 1e3,
                        "pcg_iters_per_step": float(np.mean(citers)),
                        "decoupled_over_coupled": value / cval, "accuracy": cacc}
+        plain = None
+        if args.precision == "mixed" and not args.no_coupled:
+            # the plain FP64 form of the same decoupled scheme on the same GPU
+            g.set_options(scheme="D", precision="fp64", tol=args.tol)
+            g.set_states(p0)
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            ns = max(1, min(args.steps, 5))
+            for k in range(ns):
+                g.step(1)
+            torch.cuda.synchronize()
+            pv = dof * ns / (time.perf_counter() - c0)
+            plain = {"value": pv, "unit": "cell-updates/s", "steps": ns,
+                     "scheme": "D", "precision": "fp64", "tol": args.tol,
+                     "mixed_over_fp64": value / pv}
         g.close()
-        if args.calibrate_copy:
-            # known traffic for the HBM counters: a fill writes N bytes, a sum reads N bytes
-            n = args.calibrate_copy * 2**20 // 8
-            src = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
-            torch.cuda.synchronize()
-            tot = float(src.sum())
-            torch.cuda.synchronize()
-            log(f"calibration: filled and summed {args.calibrate_copy} MiB (sum {tot:.0f})")
+        calibrate(args)
 
     lat_ms = np.array(lat) * 1e3
     it = np.array(iters)
-    ncell_grid = p.nx * p.ny * p.n_omega
-    has_t = any(o.k is not None for o in p.omega)
-    bpc = grid_A_bytes_per_cell("fp64", args.precond, has_t)
-    avgA = msA / max(nA, 1) * 1e-3
-    achieved = ncell_grid * bpc / avgA / 1e9 if nA else None
-    pname = {"bic0": "BIC0", "jacobi": "JACOBI"}.get(args.precond, args.precond)
-    traffic = measured_traffic(args.workload, args.precond)
-    roof = {"bound": "hbm", "kernel": f"k_pcg_A<double,{pname},GRID> (p = z + beta p; q = A p; "
-            "partial p.q), grid continuum", "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": traffic, "traffic_unit": "bytes per launch",
-            "algorithmic_bytes_per_launch": ncell_grid * bpc,
-            "bytes_per_cell": bpc, "cells_per_launch": ncell_grid, "launches": nA,
-            "avg_launch_us": avgA * 1e6,
-            "update_kernel_avg_us": msB / max(nB, 1) * 1e3, "update_kernel_launches": nB}
-    out = {
-        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{args.workload}: two-continuum {p.nx}x{p.ny} lognormal "
-                   f"matrix + {p.nf} fracture cells, tau={p.tau}, D-scheme FP64, "
+    roof, roof2 = roofline(prof, tot, args.precision, args.precond, args.workload)
+    out.update({
+        "value": value, "ms_per_step": elapsed / args.steps * 1e3,
+        "config": {"workload": f"{args.workload}: {p.n_cont}-continuum {p.nx}x{p.ny} + "
+                   f"{p.nf} fracture cells, tau={p.tau}, D-scheme {args.precision}, "
                    f"PCG {args.precond} tol {args.tol}", "dof": dof,
-                   "precond": args.precond, "scheme": "D", "precision": "fp64"},
+                   "precond": args.precond, "scheme": "D", "precision": args.precision},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
-                       "p99": float(np.percentile(lat_ms, 99)),
-                       "max": float(lat_ms.max())},
+                       "p99": float(np.percentile(lat_ms, 99)), "max": float(lat_ms.max())},
         "pcg_iters_per_step": {"mean": it.mean(axis=0).tolist(), "max": it.max(axis=0).tolist()},
-        "accuracy_vs_oracle": acc,
-        "coupled_fp64": coupled,
-        "roofline": roof,
-    }
+        "accuracy_vs_oracle": acc, "coupled_fp64": coupled, "plain_fp64": plain,
+        "roofline": roof, "roofline_other_kernel": roof2,
+    })
+    if args.precision == "mixed":
+        out["dtype"] = "f32+f64"
+
+
+def run_batch(args, out):
+    import torch
+    import media
+    from paper_2209_01158_amd import mcdec
+    stream = torch.cuda.Stream()
+    t = time.time()
+    probs = media.configs.c4_problems(count=args.count)
+    dof = sum(p.dof() for p in probs)
+    log(f"workload C4: {len(probs)} problems, dof={dof} (generated in {time.time() - t:.1f}s)")
+    with torch.cuda.stream(stream):
+        t = time.time()
+        opt = options(args)
+        gs = [mcdec.Problem(p, stream=stream.cuda_stream, **opt) for p in probs]
+        mem = sum(g.info().device_bytes for g in gs)
+        log(f"setup {time.time() - t:.1f}s, device memory {mem / 2**30:.1f} GiB")
+        if args.autotune:
+            ta = time.time()
+            mcdec.autotune(gs, iters=10)
+            log(f"autotune {time.time() - ta:.1f}s")
+        b = mcdec.Batch(stream=stream.cuda_stream, **opt)
+        for k in range(args.warmup):
+            reps = b.step(gs, 1)
+            log(f"warmup step {k + 1}: {reps[0]['seconds'] * 1e3:.1f} ms")
+        for g, p in zip(gs, probs):
+            g.set_states(p.initial_state())
+        b.profile(True, every=args.sample_every)
+        lat = []
+        tot = {"A": 0.0, "B": 0.0}
+        iters_max = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ts = time.perf_counter()
+            reps = b.step(gs, 1)
+            lat.append(time.perf_counter() - ts)
+            for p, r in zip(probs, reps):
+                sb = step_bytes(p, r, args.precision, args.precond)
+                tot["A"] += sb["A"]
+                tot["B"] += sb["B"]
+            iters_max.append(max(max(r["iters"]) for r in reps))
+            if (k + 1) % 10 == 0:
+                log(f"step {k + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms, "
+                    f"max iters {iters_max[-1]}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prof = {"A": b.profile_read(0), "B": b.profile_read(1)}
+        b.profile(False)
+        elapsed = t1 - t0
+        value = dof * args.steps / elapsed
+        acc = golden_c4(dict(enumerate(gs)), args.steps, "D") if args.count == 256 else None
+        log(f"batched: {value:.4g} cell-updates/s, {elapsed / args.steps * 1e3:.1f} ms/step")
+        b.close()
+
+        plain = None
+        coupled = None
+        if not args.no_coupled:
+            # plain FP64 form: one problem at a time, FP64 PCG to the same tolerance
+            ns = 2
+            c0 = time.perf_counter()
+            for p in probs:
+                with mcdec.Problem(p, stream=stream.cuda_stream, scheme="D", precision="fp64",
+                                   precond=args.precond, tol=args.tol) as g:
+                    g.step(ns)
+            torch.cuda.synchronize()
+            pv = dof * ns / (time.perf_counter() - c0)
+            plain = {"value": pv, "unit": "cell-updates/s", "steps": ns,
+                     "form": "each problem alone, D-scheme FP64",
+                     "note": "includes per-problem setup (coefficients, factors)",
+                     "batched_mixed_over_plain": value / pv}
+            log(f"plain fp64 alone: {pv:.4g} cell-updates/s")
+            # coupled FP64, batched
+            cg = [mcdec.Problem(p, stream=stream.cuda_stream, scheme="coupled", precision="fp64",
+                                precond=args.precond, tol=args.tol) for p in probs]
+            for g in gs:
+                g.close()
+            gs = []
+            cb = mcdec.Batch(stream=stream.cuda_stream, scheme="coupled", precision="fp64",
+                             precond=args.precond, tol=args.tol)
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            for k in range(args.coupled_steps):
+                creps = cb.step(cg, 1)
+                log(f"coupled batch step {k + 1}: max iters "
+                    f"{max(r['iters'][0] for r in creps)}")
+            torch.cuda.synchronize()
+            cval = dof * args.coupled_steps / (time.perf_counter() - c0)
+            cacc = golden_c4(dict(enumerate(cg)), args.coupled_steps, "coupled") \
+                if args.count == 256 else None
+            coupled = {"value": cval, "unit": "cell-updates/s", "steps": args.coupled_steps,
+                       "form": "batched coupled FP64", "decoupled_over_coupled": value / cval,
+                       "accuracy": cacc}
+            cb.close()
+            for g in cg:
+                g.close()
+        for g in gs:
+            g.close()
+        calibrate(args)
+    lat_ms = np.array(lat) * 1e3
+    roof, roof2 = roofline(prof, tot, args.precision, args.precond, "C4")
+    out.update({
+        "value": value, "ms_per_step": elapsed / args.steps * 1e3, "dtype": "f32+f64",
+        "config": {"workload": f"C4: {len(probs)} realizations (two/three continua, sides "
+                   f"128..1024), tau=1e-3, batched D-scheme {args.precision}, "
+                   f"PCG {args.precond}, refinement to {args.tol}", "dof": dof,
+                   "problems": len(probs), "precond": args.precond, "scheme": "D",
+                   "precision": args.precision},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
+                       "p99": float(np.percentile(lat_ms, 99)), "max": float(lat_ms.max())},
+        "pcg_iters_max_per_step": {"mean": float(np.mean(iters_max)),
+                                   "max": int(np.max(iters_max))},
+        "accuracy_vs_oracle": acc, "coupled_fp64": coupled, "plain_fp64": plain,
+        "roofline": roof, "roofline_other_kernel": roof2,
+    })
+
+
+def calibrate(args):
+    if args.calibrate_copy:
+        import torch
+        # known traffic for the HBM counters: a fill writes N bytes, a sum reads N bytes
+        n = args.calibrate_copy * 2**20 // 8
+        src = torch.full((n,), 1.0, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        tot = float(src.sum())
+        torch.cuda.synchronize()
+        log(f"calibration: filled and summed {args.calibrate_copy} MiB (sum {tot:.0f})")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="C2", choices=sorted(DEFAULTS))
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precond", default=None, choices=["jacobi", "bic0"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--coupled-steps", type=int, default=None)
+    ap.add_argument("--count", type=int, default=256, help="C4: realizations in the batch")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--sample-every", type=int, default=32,
+                    help="time one grid PCG launch in this many (HIP events)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-coupled", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB written by a fill and read by a sum (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    d = DEFAULTS[args.workload]
+    for k in ("precond", "precision", "tol", "steps", "coupled_steps"):
+        if getattr(args, k) is None:
+            setattr(args, k, d[k])
+
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC, "value": None, "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generators of the workload recipe)"}
+    if args.workload == "C4":
+        run_batch(args, out)
+    else:
+        run_single(args, out)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -144,6 +144,10 @@ typedef struct {
   int64_t device_bytes;  /* device memory held by the problem                                  */
   int32_t grid_tiles;    /* grid tiles per Omega continuum                                     */
   int32_t n_chains;      /* fracture chains (blocks of the fracture preconditioner)            */
+  int32_t tiles[3];      /* work tiles per continuum (grid: 64 x 32 cells; fracture: whole
+                            chains of about 256 cells)                                          */
+  int32_t blocks[3][2];  /* workgroups per launch per continuum: [0] operator kernel,
+                            [1] update / residual kernels (equal to its partial-sum slots)      */
 } mc_info;
 
 typedef struct mc_problem mc_problem;
@@ -208,14 +212,31 @@ mc_status mc_get_info(const mc_problem *p, mc_info *info);
    failed mc_create_problem / server call.  Never NULL. */
 const char *mc_last_error(const mc_problem *p);
 
-/* Kernel timing on the problem's main stream: HIP events bound to the dispatch of sampled
-   launches of the grid PCG kernels (they time the kernel execution itself).  which: 0 = grid
-   operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z).  enable >= 1
-   starts recording and clears the totals, sampling one launch in `enable` (1 = every launch;
-   each sampled launch costs the stream a few microseconds); 0 stops.  While timing is on,
-   PCG iterations are launched one by one instead of replayed from captured graphs. */
+/* Kernel timing on the problem's streams: HIP events bound to the dispatch of sampled
+   launches of the grid PCG kernels time the kernel execution itself.  which: 0 = grid
+   operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z = M^-1 r).
+   enable >= 1 starts recording and clears the totals, sampling one launch in `enable`
+   (1 = every launch; each sampled launch costs the stream a few microseconds); 0 stops.
+   While timing is on, PCG iterations are launched one by one instead of replayed from
+   captured graphs.  mc_profile_read returns the number of sampled launches and their summed
+   duration, and the number of launches issued while timing was on (sampled or not). */
 mc_status mc_profile(mc_problem *p, int32_t enable);
-mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *launches, double *total_ms);
+mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *sampled, double *sampled_ms,
+                          int64_t *issued);
+
+/* Autotuner of the launch shapes.  For every size class (work tiles rounded down to a power
+   of two, per continuum kind, precision and preconditioner) present among probs[0..n), time
+   candidate workgroup counts of the PCG operator and update launches (1, 2 or 4 tiles per
+   workgroup; 2, 4 or 8 for the grid block IC(0) update, whose wavefronts each sweep 64 x 16
+   blocks) over `iters` (<= 0: 20) iterations of a real PCG run on one continuum of that class,
+   and keep the fastest.  The choices apply to these problems and to every problem created
+   later in the process; a problem's result then depends on its own size class only, so it is
+   still the same alone and in any batch.  Only scratch vectors are written (the state is
+   kept).  Problems must not be in use by another thread. */
+mc_status mc_autotune(mc_problem *const *probs, int32_t n, int32_t iters);
+
+/* Forget every tuned choice (problems created afterwards use the built-in shapes). */
+mc_status mc_autotune_clear(void);
 
 /* ---- batches: many problems advanced by shared launches ---------------------------------
  *
@@ -252,8 +273,8 @@ const char *mc_batch_last_error(const mc_batch *b);
 /* Kernel timing of the batch's grid PCG kernels, as mc_profile / mc_profile_read.  While
    timing is on, iterations are launched one by one instead of from graphs. */
 mc_status mc_batch_profile(mc_batch *b, int32_t enable);
-mc_status mc_batch_profile_read(mc_batch *b, int32_t which, int64_t *launches,
-                                double *total_ms);
+mc_status mc_batch_profile_read(mc_batch *b, int32_t which, int64_t *sampled,
+                                double *sampled_ms, int64_t *issued);
 
 #ifdef __cplusplus
 }

@@ -54,12 +54,31 @@ static int env_int(const char* name, int dflt) {
 }
 
 // Workgroups per launch over a continuum, for the operator tiling (fam 0) and for the
-// update / init / residual tiling (fam 1): one per tile up to a cap, beyond which each
-// workgroup takes a contiguous run of tiles.  With block IC(0) the update workgroups take
-// four tiles (eight 64 x 16 blocks) so that all four wavefronts sweep.  Depends only on the
-// continuum's size and the preconditioner, so the reduction order of a system never depends
-// on what else shares the launch.
-static int blocks_for(int ntiles, int kind, int fam, bool bic0) {
+// update / init / residual tiling (fam 1).  A tuned choice (tiles per workgroup, recorded
+// per size class by mc_autotune) wins; otherwise one workgroup per tile up to a cap, beyond
+// which each workgroup takes a contiguous run of tiles, and with block IC(0) the grid update
+// workgroups take four tiles (eight 64 x 16 blocks) so that all four wavefronts sweep.
+// Depends only on the continuum's size, kind and solver configuration, so the reduction order
+// of a system never depends on what else shares the launch.
+static std::mutex g_tune_mu;
+static std::map<std::vector<int>, int> g_tune;   // key -> tiles per workgroup
+
+static int size_class(int ntiles) {
+  int b = 0;
+  while ((2L << b) <= ntiles) ++b;
+  return b;   // floor(log2(ntiles))
+}
+
+static std::vector<int> tune_key(int ntiles, int kind, int fam, bool bic0, bool fp32) {
+  return {kind, fam, bic0 ? 1 : 0, fp32 ? 1 : 0, size_class(ntiles)};
+}
+
+static int blocks_for(int ntiles, int kind, int fam, bool bic0, bool fp32) {
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(ntiles, kind, fam, bic0, fp32));
+    if (it != g_tune.end()) return std::max(1, (ntiles + it->second - 1) / it->second);
+  }
   int cap;
   if (kind == PART_GRAPH) cap = env_int("MCDEC_GRAPH_BLOCKS", 256);
   else if (fam == 0) cap = env_int("MCDEC_GRID_BLOCKS_A", 2048);
@@ -653,11 +672,12 @@ static void build_coefficients(mc_problem* P) {
 // of the system records (in host memory `hs`).
 static void set_slot_counts(mc_problem* P, SysState* hs) {
   const bool bic0 = P->X.opt.precond == MC_BIC0;
+  const bool fp32 = P->X.opt.precision == MC_MIXED;
   int ca = 0, cb = 0;
   for (int c = 0; c < P->ncont; ++c) {
     Cont& C = P->cont[c];
-    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, bic0);
-    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, bic0);
+    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, bic0, fp32);
+    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, bic0, fp32);
     hs[c].nslotsA = C.blocks[0];
     hs[c].nslotsB = C.blocks[1];
     ca += C.blocks[0];
@@ -721,8 +741,8 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     C.kind = grid ? PART_GRID : PART_GRAPH;
     C.n = grid ? P->ncell : d.nf;
     C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY)) : P->ngtiles;
-    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, o.precond == MC_BIC0);
-    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, o.precond == MC_BIC0);
+    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, o.precond == MC_BIC0, o.precision == MC_MIXED);
+    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, o.precond == MC_BIC0, o.precision == MC_MIXED);
     C.diag = M.alloc<double>(C.n);
     C.F = M.alloc<double>(C.n);
     if (grid) {
@@ -892,13 +912,13 @@ static void launch2(const Group& G, int fam, KG kg, KF kf, A... args) {
                        G.T->parts, G.T->tiles[fam][PART_GRAPH], args...);
 }
 
-template <class KG, class KF>
-static void launch_all(hipStream_t s, Table& T, int fam, KG kg, KF kf) {
+template <class KG, class KF, class... A>
+static void launch_all(hipStream_t s, Table& T, int fam, KG kg, KF kf, A... args) {
   Group g;
   g.s = s;
   g.T = &T;
   g.kinds = 3;
-  launch2(g, fam, kg, kf);
+  launch2(g, fam, kg, kf, args...);
 }
 
 static void submit_poll(Exec& X, Group& G) {
@@ -1338,6 +1358,120 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
   return st;
 }
 
+// ------------------------------------------------------------------------------------
+// autotuner: workgroups per launch, chosen by timing
+// ------------------------------------------------------------------------------------
+// Median time (microseconds) of the operator (fam 0) or update (fam 1) kernel of continuum c
+// of P in its current tilings, over `iters` iterations of a real PCG run on the device (the
+// record's tolerance is 0, so the system never stops).  Only scratch vectors and the next
+// state buffer are written; the current state is untouched.
+template <class T, int PREC>
+static double time_tiling(mc_problem* P, int c, int fam, int iters) {
+  Exec& X = P->X;
+  Cont& C = P->cont[c];
+  const bool fp32 = sizeof(T) == 4;
+  hipStream_t s = X.stream;
+  Table& Tb = upload_table(P, "tune", decoupled_parts(P, {c}, fp32));
+  SysState S;
+  std::memset(&S, 0, sizeof(S));
+  S.partA = P->partA[c];
+  S.partB = P->partB[c];
+  S.nslotsA = C.blocks[0];
+  S.nslotsB = C.blocks[1];
+  S.max_iter = 1 << 30;
+  S.max_outer = 1;
+  S.done = 1;
+  HIPCHK(hipMemcpyAsync(X.sys + c, &S, sizeof(S), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, X.sys, c, c + 1);
+  launch_all(s, Tb, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+  if (fp32) launch_all(s, Tb, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+  else launch_all(s, Tb, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+  const int warm = 3, tot = warm + iters;
+  std::vector<hipEvent_t> ev(3 * tot, nullptr);
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  Group g;
+  g.s = s;
+  g.T = &Tb;
+  g.kinds = 3;
+  for (int j = 0; j < tot; ++j) {
+    HIPCHK(hipEventRecord(ev[3 * j], s));
+    launch2(g, 0, k_pcg_A<T, PREC, PART_GRID>, k_pcg_A<T, PREC, PART_GRAPH>, X.sys);
+    HIPCHK(hipEventRecord(ev[3 * j + 1], s));
+    launch2(g, 1, k_pcg_B<T, PREC, PART_GRID>, k_pcg_B<T, PREC, PART_GRAPH>, X.sys);
+    HIPCHK(hipEventRecord(ev[3 * j + 2], s));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<float> t;
+  for (int j = warm; j < tot; ++j) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev[3 * j + fam], ev[3 * j + fam + 1]));
+    t.push_back(ms);
+  }
+  for (auto e : ev) (void)hipEventDestroy(e);
+  std::sort(t.begin(), t.end());
+  return 1e3 * t[t.size() / 2];
+}
+
+static double time_tiling_any(mc_problem* P, int c, int fam, int iters) {
+  const bool fp32 = P->X.opt.precision == MC_MIXED, bic0 = P->X.opt.precond == MC_BIC0;
+  if (fp32) return bic0 ? time_tiling<float, PREC_BIC0>(P, c, fam, iters)
+                        : time_tiling<float, PREC_JACOBI>(P, c, fam, iters);
+  return bic0 ? time_tiling<double, PREC_BIC0>(P, c, fam, iters)
+              : time_tiling<double, PREC_JACOBI>(P, c, fam, iters);
+}
+
+// Re-derive every continuum's tilings (tuned choices included) and the records' slot counts.
+static void refresh_tilings(mc_problem* P) {
+  const size_t nb = (P->ncont + 1) * sizeof(SysState);
+  HIPCHK(hipMemcpy(P->X.h_sys, P->X.sys, nb, hipMemcpyDeviceToHost));
+  set_slot_counts(P, P->X.h_sys);
+  HIPCHK(hipMemcpy(P->X.sys, P->X.h_sys, nb, hipMemcpyHostToDevice));
+  clear_tables(P);
+}
+
+// For every size class present among the problems' continua, time candidate workgroup
+// counts of the operator tiling, then of the update tiling, on the first continuum of that
+// class, and record the fastest as tiles per workgroup for the class.
+static void autotune(mc_problem* const* probs, int n, int iters) {
+  std::vector<std::vector<int>> seen;
+  for (int i = 0; i < n; ++i) {
+    mc_problem* P = probs[i];
+    const bool bic0 = P->X.opt.precond == MC_BIC0, fp32 = P->X.opt.precision == MC_MIXED;
+    for (int c = 0; c < P->ncont; ++c) {
+      Cont& C = P->cont[c];
+      for (int fam = 0; fam < 2; ++fam) {
+        std::vector<int> key = tune_key(C.tiles, C.kind, fam, bic0, fp32);
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(key);
+        std::vector<int> tpw = (fam == 1 && bic0 && C.kind == PART_GRID)
+                                   ? std::vector<int>{2, 4, 8}
+                                   : std::vector<int>{1, 2, 4};
+        const int keep = C.blocks[fam];
+        double best = 1e300;
+        int best_b = keep;
+        std::vector<int> tried;
+        for (int t : tpw) {
+          const int b = std::max(1, (C.tiles + t - 1) / t);
+          if (std::find(tried.begin(), tried.end(), b) != tried.end()) continue;
+          tried.push_back(b);
+          C.blocks[fam] = b;
+          const double us = time_tiling_any(P, c, fam, iters);
+          if (us < best) {
+            best = us;
+            best_b = b;
+          }
+        }
+        C.blocks[fam] = best_b;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = (C.tiles + best_b - 1) / best_b;
+      }
+    }
+    clear_tables(P);
+  }
+  for (int i = 0; i < n; ++i) refresh_tilings(probs[i]);
+}
+
 }  // namespace mc
 
 // ======================================================================================
@@ -1583,6 +1717,11 @@ mc_status mc_get_info(const mc_problem* P, mc_info* info) {
   info->device_bytes = (int64_t)P->mem.bytes;
   info->grid_tiles = P->ncont ? P->cont[0].tiles : 0;
   info->n_chains = P->nchains;
+  for (int c = 0; c < P->ncont && c < 3; ++c) {
+    info->tiles[c] = P->cont[c].tiles;
+    info->blocks[c][0] = P->cont[c].blocks[0];
+    info->blocks[c][1] = P->cont[c].blocks[1];
+  }
   return MC_OK;
 }
 
@@ -1604,12 +1743,13 @@ static mc_status exec_profile(mc::Exec& X, int32_t enable) {
   return MC_OK;
 }
 
-static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* launches,
-                                   double* total_ms) {
+static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* sampled,
+                                   double* sampled_ms, int64_t* issued) {
   HIPCHK(hipStreamSynchronize(X.stream));
   mc::prof_harvest(X);
-  if (launches) *launches = X.prof_launch[which];
-  if (total_ms) *total_ms = X.prof_ms[which];
+  if (sampled) *sampled = X.prof_launch[which];
+  if (sampled_ms) *sampled_ms = X.prof_ms[which];
+  if (issued) *issued = X.prof_count[which];
   return MC_OK;
 }
 
@@ -1620,11 +1760,29 @@ mc_status mc_profile(mc_problem* P, int32_t enable) {
   ABI_END(P)
 }
 
-mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* launches, double* total_ms) {
+mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* sampled, double* sampled_ms,
+                          int64_t* issued) {
   if (!P || which < 0 || which > 1) return MC_EINVAL;
   ABI_BEGIN
-  return exec_profile_read(P->X, which, launches, total_ms);
+  return exec_profile_read(P->X, which, sampled, sampled_ms, issued);
   ABI_END(P)
+}
+
+mc_status mc_autotune(mc_problem* const* probs, int32_t n, int32_t iters) {
+  if (!probs || n < 1) return MC_EINVAL;
+  ABI_BEGIN
+  for (int i = 0; i < n; ++i)
+    if (!probs[i]) throw mc::Error{MC_EINVAL, "problem " + std::to_string(i) + " is NULL"};
+  if (iters < 1) iters = 20;
+  mc::autotune(probs, n, iters);
+  return MC_OK;
+  ABI_END(probs[0])
+}
+
+mc_status mc_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(mc::g_tune_mu);
+  mc::g_tune.clear();
+  return MC_OK;
 }
 
 // ---- batches -------------------------------------------------------------------------
@@ -1698,11 +1856,11 @@ mc_status mc_batch_profile(mc_batch* B, int32_t enable) {
   ABI_END(B)
 }
 
-mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* launches,
-                                double* total_ms) {
+mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* sampled,
+                                double* sampled_ms, int64_t* issued) {
   if (!B || which < 0 || which > 1) return MC_EINVAL;
   ABI_BEGIN
-  return exec_profile_read(B->X, which, launches, total_ms);
+  return exec_profile_read(B->X, which, sampled, sampled_ms, issued);
   ABI_END(B)
 }
 

@@ -72,7 +72,8 @@ class Report(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("n_cont", C.c_int32), ("sizes", C.c_int32 * 3), ("device_bytes", C.c_int64),
-                ("grid_tiles", C.c_int32), ("n_chains", C.c_int32)]
+                ("grid_tiles", C.c_int32), ("n_chains", C.c_int32), ("tiles", C.c_int32 * 3),
+                ("blocks", (C.c_int32 * 2) * 3)]
 
 
 _PROBLEM = C.c_void_p
@@ -104,8 +105,12 @@ mc_get_info = _sig("mc_get_info", C.c_int, [_PROBLEM, C.POINTER(Info)])
 mc_last_error = _sig("mc_last_error", C.c_char_p, [_PROBLEM])
 mc_profile = _sig("mc_profile", C.c_int, [_PROBLEM, C.c_int32])
 mc_profile_read = _sig("mc_profile_read", C.c_int,
-                       [_PROBLEM, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)])
+                       [_PROBLEM, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                        C.POINTER(C.c_int64)])
 
+
+mc_autotune = _sig("mc_autotune", C.c_int, [C.POINTER(_PROBLEM), C.c_int32, C.c_int32])
+mc_autotune_clear = _sig("mc_autotune_clear", C.c_int, [])
 
 _BATCH = C.c_void_p
 mc_batch_create = _sig("mc_batch_create", C.c_int, [C.POINTER(Options), C.POINTER(_BATCH)])
@@ -115,7 +120,8 @@ mc_batch_step = _sig("mc_batch_step", C.c_int,
 mc_batch_last_error = _sig("mc_batch_last_error", C.c_char_p, [_BATCH])
 mc_batch_profile = _sig("mc_batch_profile", C.c_int, [_BATCH, C.c_int32])
 mc_batch_profile_read = _sig("mc_batch_profile_read", C.c_int,
-                             [_BATCH, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)])
+                             [_BATCH, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                              C.POINTER(C.c_int64)])
 
 
 class McError(RuntimeError):
@@ -326,10 +332,30 @@ class Problem:
         _check(mc_profile(self.h, max(1, int(every)) if enable else 0), self.h)
 
     def profile_read(self, which: int):
+        """(sampled launches, their summed ms, launches issued) of grid kernel `which`."""
         n = C.c_int64()
         ms = C.c_double()
-        _check(mc_profile_read(self.h, which, C.byref(n), C.byref(ms)), self.h)
-        return n.value, ms.value
+        iss = C.c_int64()
+        _check(mc_profile_read(self.h, which, C.byref(n), C.byref(ms), C.byref(iss)), self.h)
+        return n.value, ms.value, iss.value
+
+
+def autotune(problems, iters: int = 20):
+    """Pick the PCG launch shapes per size class by timing (mc_autotune); applies to these
+    problems and to problems created later in the process."""
+    n = len(problems)
+    arr = (_PROBLEM * n)(*[p.h for p in problems])
+    _check(mc_autotune(arr, n, iters), problems[0].h)
+
+
+def autotune_clear():
+    _check(mc_autotune_clear())
+
+
+def tilings(problem):
+    """Work tiles and workgroups per launch [(tiles, operator, update)] per continuum."""
+    inf = problem.info()
+    return [(inf.tiles[c], inf.blocks[c][0], inf.blocks[c][1]) for c in range(inf.n_cont)]
 
 
 class Batch:
@@ -380,9 +406,10 @@ class Batch:
     def profile_read(self, which: int):
         n = C.c_int64()
         ms = C.c_double()
-        _check(mc_batch_profile_read(self.h, which, C.byref(n), C.byref(ms)), self.h,
-               last_error=mc_batch_last_error)
-        return n.value, ms.value
+        iss = C.c_int64()
+        _check(mc_batch_profile_read(self.h, which, C.byref(n), C.byref(ms), C.byref(iss)),
+               self.h, last_error=mc_batch_last_error)
+        return n.value, ms.value, iss.value
 
 
 EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
@@ -390,4 +417,5 @@ EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
            "mc_apply_precond",
            "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
            "mc_profile", "mc_profile_read", "mc_batch_create", "mc_batch_destroy",
-           "mc_batch_step", "mc_batch_last_error", "mc_batch_profile", "mc_batch_profile_read"]
+           "mc_batch_step", "mc_batch_last_error", "mc_batch_profile", "mc_batch_profile_read",
+           "mc_autotune", "mc_autotune_clear"]

@@ -194,3 +194,28 @@ def test_batch_rejects_mismatched_options():
         with pytest.raises(mcdec.McError) as ei:
             b.step([g, g], 1)
         assert ei.value.status == mcdec.MC_EINVAL and "twice" in str(ei.value)
+
+
+def test_autotune_keeps_state_and_batch_equals_alone():
+    mcdec.autotune_clear()
+    probs = family()
+    opt = OPTS["mixed_bic0"]
+    gs = [mcdec.Problem(p, **opt) for p in probs]
+    try:
+        before = [g.get_states() for g in gs]
+        mcdec.autotune(gs, iters=5)
+        assert_bitwise(before, [g.get_states() for g in gs])
+        til = [mcdec.tilings(g) for g in gs]
+        print(til, flush=True)
+        alone = alone_states(probs, 2, **opt)      # created after tuning: same tilings
+        with mcdec.Batch(**opt) as b:
+            b.step(gs, 2)
+        assert_bitwise(alone, [g.get_states() for g in gs])
+        with mcdec.Problem(probs[1], **opt) as g2:
+            assert mcdec.tilings(g2) == til[1]
+        ref = schemes.run(probs[4], "D", 2, keep="last")
+        assert rel(gs[4].get_states(), ref) < 1e-8
+    finally:
+        for g in gs:
+            g.close()
+        mcdec.autotune_clear()
