@@ -47,6 +47,7 @@ struct SysState {
   int ka, kb;
   int mixed;            // inner solve of FP64 refinement: iteration 0 first tests the outer residual
   int pad0;
+  double rscale;        // refinement: power-of-two scale of the FP32 residual of the inner solve
   int nslotsA;          // workgroups (partial slots) of this system in an operator launch
   int nslotsB;          // ... in an update / init / residual launch (its own tiling)
   double* partA;        // [nslotsA * MC_SLOT] written by operator kernels

@@ -462,6 +462,7 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
     q.fsig0 = P->sigma_f;
     q.fsig1 = P->n_omega > 1 ? P->sigma_f + P->nf : nullptr;
   }
+  q.r64 = C.r;   // FP64 residual of the refinement (the FP64 PCG vector r is idle then)
   q.pold = C.ps[P->cur];
   for (int b = 0; b < P->ncont; ++b) q.tsrc[b] = P->cont[b].ps[P->cur];
   q.b = C.b;
@@ -999,6 +1000,7 @@ static void advance_t(Exec& X, Group& G) {
     hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
                        G.s1);
     if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+    launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
     G.outer = 0;
     G.k = 0;
@@ -1015,6 +1017,7 @@ static void advance_t(Exec& X, Group& G) {
     // every unfinished system ended its inner solve: correct, new residual, restart
     if (G.outer > X.opt.max_outer + 1) throw Error{MC_EDEVICE, "refinement did not terminate"};
     launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, X.sys);
+    launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
     G.outer += 1;
     G.k = 0;
@@ -1384,8 +1387,13 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
   HIPCHK(hipMemcpyAsync(X.sys + c, &S, sizeof(S), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, X.sys, c, c + 1);
   launch_all(s, Tb, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-  if (fp32) launch_all(s, Tb, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
-  else launch_all(s, Tb, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+  if (fp32) {
+    launch_all(s, Tb, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
+    launch_all(s, Tb, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+  }
+  else {
+    launch_all(s, Tb, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+  }
   const int warm = 3, tot = warm + iters;
   std::vector<hipEvent_t> ev(3 * tot, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));

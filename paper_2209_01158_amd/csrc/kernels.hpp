@@ -671,30 +671,42 @@ __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ part
 //   A(k)   from partB: stop test, beta; p_new = z + beta p_old; q = A p_new -> partA (pq)
 //   B(k)   from partA: alpha; x += alpha p; r -= alpha q; z = M^-1 r        -> partB (rz, rr)
 // ------------------------------------------------------------------------------------
-// Shared by the FP64 initial residual and the refinement residual: computes
-// r = b - A x64 per cell (FP64), hands it to `emit(i, r, b)` which stores it in the solve's
-// precision and returns the stored value, then applies the preconditioner to the stored
-// residuals and accumulates (r,z), (r,r) into v[0], v[1].
-template <class T, int PREC, int KIND, class Emit>
-__device__ __forceinline__ void residual_and_precond(const PartD* parts, const PartD& P,
-                                                     const Tile& t, const double* x,
-                                                     T* __restrict__ rs, T* __restrict__ z,
-                                                     const Emit& emit, double (&v)[5],
-                                                     bool use_x64) {
-  auto xs = [&](long j) { return x[j]; };
-  auto xpart = [&](int pi, long j) {
+// FP64 residual b - A x of one cell (grid: res(cx, cy, i); graph: resg(l)), including the
+// transfer blocks of the coupled operator.
+struct Residual64 {
+  const PartD* parts;
+  const PartD& P;
+  const double* x;
+  bool use_x64;   // coupled parts read the other parts' x64 (else their x)
+  __device__ double xpart(int pi, long j) const {
     return use_x64 ? parts[pi].x64[j] : ((const double*)parts[pi].x)[j];
-  };
-  auto res = [&](int cx, int cy, long i) {
+  }
+  __device__ double res(int cx, int cy, long i) const {
+    auto xs = [&](long j) { return x[j]; };
+    auto xp = [&](int pi, long j) { return xpart(pi, j); };
     double ax = grid_Av<double>(P, cx, cy, i, x[i], xs);
-    if (P.coupled) ax += grid_coupling(parts, P, i, xpart);
+    if (P.coupled) ax += grid_coupling(parts, P, i, xp);
     return P.b[i] - ax;
-  };
-  auto resg = [&](int l) {
+  }
+  __device__ double resg(int l) const {
+    auto xs = [&](long j) { return x[j]; };
+    auto xp = [&](int pi, long j) { return xpart(pi, j); };
     double ax = graph_Av<double>(P, l, x[l], xs);
-    if (P.coupled) ax += graph_coupling(P, l, xpart);
+    if (P.coupled) ax += graph_coupling(P, l, xp);
     return P.b[l] - ax;
-  };
+  }
+};
+
+// Shared by the FP64 initial residual and the refinement residual: takes the FP64 residual
+// of every cell from `R` (R.res(cx, cy, i) / R.resg(l)), hands it to `emit(i, r, b)` which
+// stores it in the solve's precision and returns the stored value, then applies the
+// preconditioner to the stored residuals and accumulates (r,z), (r,r) into v[0], v[1].
+template <class T, int PREC, int KIND, class R, class Emit>
+__device__ __forceinline__ void residual_and_precond(const PartD& P, const Tile& t, const R& Rs,
+                                                     T* __restrict__ rs, T* __restrict__ z,
+                                                     const Emit& emit, double (&v)[5]) {
+  auto res = [&](int cx, int cy, long i) { return Rs.res(cx, cy, i); };
+  auto resg = [&](int l) { return Rs.resg(l); };
   const T* d = pick<T>(P.diag, P.diag32);
   if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
     auto rrow = [&](int, long i, bool act) -> T {
@@ -751,8 +763,8 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     v[2] += b * b;
     return ri;
   };
-  residual_and_precond<double, PREC, KIND>(parts, P, t, (const double*)P.x, r, (double*)P.z,
-                                           emit, v, false);
+  const Residual64 R{parts, P, (const double*)P.x, false};
+  residual_and_precond<double, PREC, KIND>(P, t, R, r, (double*)P.z, emit, v);
   write_slot<5>(S.partB, t.slot, v);
 }
 
@@ -970,8 +982,44 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 
 // ------------------------------------------------------------------------------------
 // mixed precision: FP64 residual of the FP64 iterate handed to the FP32 inner PCG
-//   r64 = b - A64 x64;  r32 = (float) r64;  x32 = 0   -> partB (rz32, rr32, rr32, rr64, bb)
+//   k_residual64  r64 = b - A64 x64 (FP64)                         -> partA (rr64, bb)
+//   k_residual    s = 2^-e with 2^e ~ rms(r64); r32 = (float)(s r64); x32 = 0;
+//                 z32 = M^-1 r32                                    -> partB (rz, rr, rr, rr64, bb)
+//   ... inner PCG on A d = s r64 ...
+//   k_correct     x64 += d / s
+// The scale keeps the FP32 residual near unit size whatever the magnitude of the FP64 one
+// (residuals far below FP32's normal range would otherwise round to zero); a power of two
+// makes scaling and unscaling exact.
 // ------------------------------------------------------------------------------------
+template <int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) k_residual64(const PartD* __restrict__ parts,
+                                                         const Tile* __restrict__ tiles,
+                                                         SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  SysState& S = sys[P.sys];
+  if (S.outer_done) return;
+  const Residual64 R{parts, P, P.x64, true};
+  double* r64 = P.r64;
+  double v[2] = {0.0, 0.0};
+  for_cells<KIND>(
+      P, t,
+      [&](int cx, int cy, long i) {
+        const double ri = R.res(cx, cy, i);
+        r64[i] = ri;
+        v[0] += ri * ri;
+        v[1] += P.b[i] * P.b[i];
+      },
+      [&](int l) {
+        const double ri = R.resg(l);
+        r64[l] = ri;
+        v[0] += ri * ri;
+        v[1] += P.b[l] * P.b[l];
+      });
+  write_slot<2>(S.partA, t.slot, v);
+}
+
 template <int PREC, int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_residual(const PartD* __restrict__ parts,
                                                        const Tile* __restrict__ tiles,
@@ -981,27 +1029,45 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
   if (S.outer_done) return;
+  double tot[2];
+  reduce_slots<2>(S.partA, S.nslotsA, tot);
+  const double orr = tot[0], obb = tot[1];
+  double sc = 1.0;
+  if (orr > 0.0 && finite(orr) && P.n > 0) {
+    int e = 0;
+    (void)frexp(sqrt(orr / (double)P.n), &e);
+    sc = ldexp(1.0, -e);
+  }
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   float* r32 = (float*)P.r;
   float* x32 = (float*)P.x;
-  auto emit = [&](long i, double ri, double bi) {
+  const double* r64 = P.r64;
+  struct Scaled {
+    const double* r64;
+    double sc;
+    __device__ double res(int, int, long i) const { return sc * r64[i]; }
+    __device__ double resg(int l) const { return sc * r64[l]; }
+  } R{r64, sc};
+  auto emit = [&](long i, double ri, double) {
     const float rf = (float)ri;
     r32[i] = rf;
     x32[i] = 0.0f;
-    v[3] += ri * ri;
-    v[4] += bi * bi;
     return rf;
   };
-  residual_and_precond<float, PREC, KIND>(parts, P, t, P.x64, r32, (float*)P.z, emit, v, true);
+  residual_and_precond<float, PREC, KIND>(P, t, R, r32, (float*)P.z, emit, v);
   v[2] = v[1];
+  const bool w0 = t.slot == 0 && threadIdx.x == 0;
+  v[3] = w0 ? orr : 0.0;   // the FP64 norms, once per system
+  v[4] = w0 ? obb : 0.0;
   write_slot<5>(S.partB, t.slot, v);
-  if (t.slot == 0 && threadIdx.x == 0) {   // a new inner solve starts
+  if (w0) {   // a new inner solve starts
+    S.rscale = sc;
     S.ka = 0;
     st_flag(&S.done, 0);
   }
 }
 
-// x64 += (double) x32 for systems still refining; workgroup 0 counts the pass.
+// x64 += (double) x32 / s for systems still refining; workgroup 0 counts the pass.
 template <int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) k_correct(const PartD* __restrict__ parts,
                                                       const Tile* __restrict__ tiles,
@@ -1011,10 +1077,11 @@ __global__ void __launch_bounds__(MC_BLOCK) k_correct(const PartD* __restrict__ 
   const PartD& P = parts[t.part];
   SysState& S = sys[P.sys];
   if (S.outer_done) return;
+  const double inv = 1.0 / S.rscale;   // exact: a power of two
   const float* d = (const float*)P.x;
   double* x = P.x64;
-  for_cells<KIND>(P, t, [&](int, int, long i) { x[i] += (double)d[i]; },
-                  [&](int l) { x[l] += (double)d[l]; });
+  for_cells<KIND>(P, t, [&](int, int, long i) { x[i] += (double)d[i] * inv; },
+                  [&](int l) { x[l] += (double)d[l] * inv; });
   if (t.slot == 0 && threadIdx.x == 0) S.outer += 1;
 }
 

@@ -67,3 +67,40 @@ def test_c2_mixed_precision(c2):
         err = sampled_error(g, z, "D", 10)
         print(f"mixed step 10 sampled rel L2 {err:.2e}, outer {rep['outer']}", flush=True)
         assert err < 1e-8
+
+
+def test_c4_batch_against_stored_oracle():
+    """The 256-realization batch in the benchmark's configuration (FP32 inner PCG with
+    block IC(0) inside FP64 refinement to 1e-10, 50 layers), checked on the six stored
+    realizations; every problem must converge at every layer."""
+    z = np.load(os.path.join(os.path.dirname(__file__), "golden", "c4_oracle.npz"),
+                allow_pickle=False)
+    probs = media.configs.c4_problems()
+    opt = dict(scheme="D", precision="mixed", precond="bic0", outer_tol=1e-10, inner_tol=1e-6)
+    gs = [mcdec.Problem(p, **opt) for p in probs]
+    try:
+        with mcdec.Batch(**opt) as b:
+            for n in range(1, 51):
+                reps = b.step(gs, 1)
+                assert all(all(c == 1 for c in r["converged"]) for r in reps)
+                if n % 10 == 0:
+                    print(f"layer {n}: max inner iters {max(max(r['iters']) for r in reps)}",
+                          flush=True)
+        worst = 0.0
+        for i in z["problems"]:
+            i = int(i)
+            num = den = 0.0
+            a = 0
+            while f"p{i}_idx{a}" in z:
+                ref = z[f"p{i}_D_s50_c{a}"]
+                d = gs[i].get_state(a)[z[f"p{i}_idx{a}"]] - ref
+                num += float(d @ d)
+                den += float(ref @ ref)
+                a += 1
+            err = np.sqrt(num / den)
+            print(f"realization {i}: sampled rel L2 {err:.2e}", flush=True)
+            worst = max(worst, err)
+        assert worst < 1e-8
+    finally:
+        for g in gs:
+            g.close()

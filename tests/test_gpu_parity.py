@@ -220,3 +220,19 @@ def test_mixed_precision_bic0(name):
         err = rel(g.get_states(), ref)
         print(name, rep, err)
         assert err < 1e-8
+
+
+@pytest.mark.parametrize("precond", ["bic0", "jacobi"])
+def test_mixed_precision_tiny_magnitudes(precond):
+    """Residuals far below FP32's normal range (pressures of order 1e-40) still refine to
+    the FP64 answer: the inner FP32 residual is scaled by a power of two."""
+    p = media.small_problem(n=64, seed=3, nseg=4)
+    p.bc_value = np.asarray(p.bc_value, float) * 1e-40
+    ref = schemes.run(p, "D", 3, keep="last")
+    with mcdec.Problem(p, precision="mixed", precond=precond, outer_tol=1e-11,
+                       inner_tol=1e-6) as g:
+        rep = g.step(3)
+        err = rel(g.get_states(), ref)
+        print(precond, rep, err)
+        assert err < 1e-8
+        assert all(c == 1 for c in rep["converged"])
