@@ -11,6 +11,10 @@ Workloads (``--workload``):
   C4            256 independent realizations of uneven size (128..1024 cells a side, two or
                 three continua), 50 layers, all advanced by shared launches in FP32 inner PCG
                 inside FP64 refinement.
+  C5            serving: a seeded Poisson trace of simulation requests (mean 40/s, sides
+                64..2048, 10..500 layers each) replayed in real time against the server
+                (admission by device-memory footprint, continuous batching); a "step" there is
+                one server step (one layer of every resident request).
 
 One "step" = one time layer of the whole hot path for the whole workload: transfer
 right-hand-side assembly of every continuum plus every PCG iteration (and refinement pass)
@@ -43,6 +47,7 @@ DEFAULTS = {
     "C2": dict(precond="bic0", precision="fp64", tol=1e-10, steps=100, coupled_steps=5),
     "C3": dict(precond="bic0", precision="mixed", tol=1e-10, steps=50, coupled_steps=1),
     "C4": dict(precond="bic0", precision="mixed", tol=1e-10, steps=50, coupled_steps=2),
+    "C5": dict(precond="bic0", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
 }
 
 # HBM bytes per dispatch of the grid PCG kernels, from two rocprofv3 counter passes
@@ -444,6 +449,86 @@ def run_batch(args, out):
     })
 
 
+def run_serve(args, out):
+    """Replays the seeded Poisson trace in real time against the server and reports the
+    served throughput with per-step and per-request latency percentiles."""
+    import threading
+    import media
+    from paper_2209_01158_amd import mcdec
+    trace = media.configs.c5_trace(count=args.count, rate=args.rate)
+    t = time.time()
+    probs = [media.configs.c5_problem(e) for e in trace]
+    steps = [e[4] for e in trace]
+    work = sum(p.dof() * n for p, n in zip(probs, steps))
+    log(f"workload C5: {len(trace)} requests over {trace[-1][0]:.1f}s, {work:.3g} cell-updates "
+        f"(built in {time.time() - t:.1f}s)")
+    budget = int(args.hbm_budget_gib * 2**30)
+    srv = mcdec.Server(budget, max_resident=args.max_resident,
+                       autotune=args.autotune, **options(args))
+    ids = [None] * len(trace)
+    t0 = time.perf_counter()
+
+    def feeder():
+        for k, (e, p, n) in enumerate(zip(trace, probs, steps)):
+            dt = e[0] - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            ids[k] = srv.submit(p, n)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    last = 0
+    while th.is_alive():
+        th.join(timeout=10)
+        st = srv.stats()
+        if st["finished"] != last:
+            last = st["finished"]
+            log(f"{time.perf_counter() - t0:.0f}s: finished {st['finished']}, resident "
+                f"{st['resident']}, queued {st['queued']}")
+    while True:
+        try:
+            srv.wait(timeout=10)
+            break
+        except mcdec.McError:
+            st = srv.stats()
+            log(f"{time.perf_counter() - t0:.0f}s: finished {st['finished']}, resident "
+                f"{st['resident']}, queued {st['queued']}")
+    infos = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    step_s = srv.step_seconds()
+    srv.close()
+    fin = [i for i in infos if i["state"] == "done"]
+    span = max(i["t_finish"] for i in fin) - min(i["t_submit"] for i in infos)
+    req_lat = np.array([i["t_finish"] - i["t_submit"] for i in fin])
+    queue = np.array([i["t_admit"] - i["t_submit"] for i in fin])
+    per_layer = np.array([(i["t_finish"] - i["t_admit"]) / i["n_steps"] for i in fin])
+    served = sum(p.dof() * n for p, n, i in zip(probs, steps, infos) if i["state"] == "done")
+    value = served / span
+    log(f"served {len(fin)}/{len(infos)}: {value:.4g} cell-updates/s over {span:.1f}s")
+    pct = lambda a, q: float(np.percentile(a, q))  # noqa: E731
+    out.update({
+        "value": value, "ms_per_step": float(np.mean(step_s)) * 1e3, "dtype": "f32+f64",
+        "steps": int(st["steps"]),
+        "config": {"workload": f"C5: {len(trace)} Poisson arrivals at {args.rate}/s, sides "
+                   f"64..2048, two/three continua, 10-500 layers, served with continuous "
+                   f"batching in {args.precision} PCG {args.precond}, HBM budget "
+                   f"{args.hbm_budget_gib} GiB", "requests": len(trace),
+                   "offered_cell_updates": work, "precond": args.precond,
+                   "precision": args.precision},
+        "latency_ms": {"p50": pct(step_s, 50) * 1e3, "p99": pct(step_s, 99) * 1e3,
+                       "max": float(step_s.max()) * 1e3,
+                       "what": "server step: one layer of every resident request"},
+        "request_latency_s": {"p50": pct(req_lat, 50), "p99": pct(req_lat, 99),
+                              "max": float(req_lat.max())},
+        "queueing_s": {"p50": pct(queue, 50), "p99": pct(queue, 99)},
+        "per_layer_latency_ms": {"p50": pct(per_layer, 50) * 1e3,
+                                 "p99": pct(per_layer, 99) * 1e3},
+        "served": {"finished": len(fin), "failed": int(st["failed"]),
+                   "makespan_s": span, "busy_s": st["busy_seconds"],
+                   "cell_updates_per_busy_s": st["cell_updates"] / max(st["busy_seconds"], 1e-9)},
+    })
+
+
 def calibrate(args):
     if args.calibrate_copy:
         import torch
@@ -466,7 +551,12 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--coupled-steps", type=int, default=None)
-    ap.add_argument("--count", type=int, default=256, help="C4: realizations in the batch")
+    ap.add_argument("--count", type=int, default=None,
+                    help="C4: realizations in the batch (256); C5: arrivals (400)")
+    ap.add_argument("--rate", type=float, default=40.0, help="C5: arrivals per second")
+    ap.add_argument("--hbm-budget-gib", type=float, default=128.0,
+                    help="C5: device memory the resident requests may hold")
+    ap.add_argument("--max-resident", type=int, default=0, help="C5: resident requests (0=256)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--sample-every", type=int, default=32,
                     help="time one grid PCG launch in this many (HIP events)")
@@ -491,11 +581,15 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": None,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic (seeded generators of the workload recipe)"}
+    if args.count is None:
+        args.count = 400 if args.workload == "C5" else 256
     if args.workload == "C4":
         run_batch(args, out)
+    elif args.workload == "C5":
+        run_serve(args, out)
     else:
         run_single(args, out)
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "C5":
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

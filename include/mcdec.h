@@ -50,7 +50,8 @@ typedef enum {
   MC_ENOCONV = -3,     /* PCG reached max_iter (or refinement max_outer) before tolerance     */
   MC_EBREAKDOWN = -4,  /* PCG breakdown: p.Ap <= 0 or a non-finite value                      */
   MC_EDEVICE = -5,     /* HIP runtime error                                                   */
-  MC_ENOTFOUND = -6    /* unknown request id (server)                                         */
+  MC_ENOTFOUND = -6,   /* unknown request id (server)                                         */
+  MC_ETIMEOUT = -7     /* server wait ended before the requests did                           */
 } mc_status;
 
 typedef enum {
@@ -224,13 +225,17 @@ mc_status mc_profile(mc_problem *p, int32_t enable);
 mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *sampled, double *sampled_ms,
                           int64_t *issued);
 
+/* Device bytes mc_create_problem allocates for *desc under *opt (NULL = defaults): an upper
+   bound computed from the sizes alone, used for admission by the server. */
+mc_status mc_footprint(const mc_problem_desc *desc, const mc_options *opt, int64_t *bytes);
+
 /* Autotuner of the launch shapes.  For every size class (work tiles rounded down to a power
    of two, per continuum kind, precision and preconditioner) present among probs[0..n), time
    candidate workgroup counts of the PCG operator and update launches (1, 2 or 4 tiles per
    workgroup; 2, 4 or 8 for the grid block IC(0) update, whose wavefronts each sweep 64 x 16
    blocks) over `iters` (<= 0: 20) iterations of a real PCG run on one continuum of that class,
-   and keep the fastest.  The choices apply to these problems and to every problem created
-   later in the process; a problem's result then depends on its own size class only, so it is
+   and keep the fastest (classes already tuned in this process are kept).  The choices apply
+   to these problems and to every problem created later in the process; a problem's result then depends on its own size class only, so it is
    still the same alone and in any batch.  Only scratch vectors are written (the state is
    kept).  Problems must not be in use by another thread. */
 mc_status mc_autotune(mc_problem *const *probs, int32_t n, int32_t iters);
@@ -275,6 +280,76 @@ const char *mc_batch_last_error(const mc_batch *b);
 mc_status mc_batch_profile(mc_batch *b, int32_t enable);
 mc_status mc_batch_profile_read(mc_batch *b, int32_t which, int64_t *sampled,
                                 double *sampled_ms, int64_t *issued);
+
+/* ---- serving: continuous batching of simulation requests ------------------------------
+ *
+ * A server owns a worker thread and a batch executor.  Requests (a problem descriptor and a
+ * number of time layers) are queued by mc_server_submit and admitted in arrival order while
+ * their device footprint (mc_footprint) fits the memory budget and a resident slot is free;
+ * a later request may bypass a waiting head that does not fit, at most max_bypass times per
+ * head.  Admitted requests are created on the device and stay resident; every server step
+ * advances all resident requests by one layer in shared launches (mc_batch_step).  A request
+ * that finishes copies its final state to host memory and frees its device memory, which
+ * admits the next ones.  Each request's result is the one mc_step gives the same problem
+ * alone with the server's options (per-problem tilings and reductions, see mc_batch_step).
+ * All server calls may be made from one client thread while the worker runs.
+ */
+typedef struct mc_server mc_server;
+
+typedef struct {
+  int64_t hbm_budget;    /* device bytes the resident requests may hold (> 0)                 */
+  int32_t max_resident;  /* resident requests at most (0 = 256)                               */
+  int32_t max_bypass;    /* times a waiting head request may be bypassed (>= 0)                */
+  int32_t autotune;      /* 1: run mc_autotune on each admitted request (new size classes only) */
+} mc_server_config;
+
+typedef struct {
+  int32_t state;         /* 0 queued, 1 running (or finishing), 2 done, 3 failed               */
+  int32_t status;        /* mc_status of a failed request                                      */
+  int32_t steps_done, n_steps;
+  int64_t bytes;         /* device bytes charged against the budget                            */
+  double t_submit, t_admit, t_finish;   /* seconds since the server started (-1: not yet)     */
+} mc_request_info;
+
+typedef struct {
+  int64_t submitted, finished, failed, queued, resident;
+  int64_t bytes_in_use, budget;
+  int64_t steps;         /* server steps (one layer of every resident request)                 */
+  double cell_updates;   /* unknowns advanced, summed over server steps                        */
+  double busy_seconds;   /* time inside server steps                                           */
+  double elapsed_seconds;/* since mc_server_create                                             */
+} mc_server_stats;
+
+/* opt: solver options of every request (scheme D or EX; NULL = defaults). */
+mc_status mc_server_create(const mc_server_config *cfg, const mc_options *opt, mc_server **out);
+
+/* Stops the worker after the current step and releases everything; NULL-safe. */
+mc_status mc_server_destroy(mc_server *s);
+
+/* Queue a request; *desc's arrays are copied before return.  MC_ENOMEM if its footprint
+   exceeds the whole budget (it could never be admitted). */
+mc_status mc_server_submit(mc_server *s, const mc_problem_desc *desc, int32_t n_steps,
+                           uint64_t *id);
+
+mc_status mc_server_poll(mc_server *s, uint64_t id, mc_request_info *info);
+
+/* Final state of continuum alpha of a done request (host array of that continuum's size). */
+mc_status mc_server_fetch(mc_server *s, uint64_t id, int32_t alpha, double *host_out);
+
+/* Forget a done or failed request and its host copy of the state. */
+mc_status mc_server_release(mc_server *s, uint64_t id);
+
+/* Block until no request is queued, running or finishing (timeout_s < 0: no limit);
+   MC_ETIMEOUT if the time ran out first. */
+mc_status mc_server_wait(mc_server *s, double timeout_s);
+
+mc_status mc_server_get_stats(mc_server *s, mc_server_stats *st);
+
+/* Durations of the server steps so far (seconds): *n receives the count, out (nullable)
+   the first min(cap, count) of them. */
+mc_status mc_server_step_seconds(mc_server *s, double *out, int64_t cap, int64_t *n);
+
+const char *mc_server_last_error(const mc_server *s);
 
 #ifdef __cplusplus
 }

@@ -1452,6 +1452,10 @@ static void autotune(mc_problem* const* probs, int n, int iters) {
         std::vector<int> key = tune_key(C.tiles, C.kind, fam, bic0, fp32);
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
+        {
+          std::lock_guard<std::mutex> lk(g_tune_mu);
+          if (g_tune.count(key)) continue;   // tuned earlier in this process
+        }
         std::vector<int> tpw = (fam == 1 && bic0 && C.kind == PART_GRID)
                                    ? std::vector<int>{2, 4, 8}
                                    : std::vector<int>{1, 2, 4};
@@ -1478,6 +1482,89 @@ static void autotune(mc_problem* const* probs, int n, int iters) {
     clear_tables(P);
   }
   for (int i = 0; i < n; ++i) refresh_tilings(probs[i]);
+}
+
+// Device bytes mc_create_problem allocates for a descriptor under options o (the sizes of
+// every array create() and build_coefficients() request; chains and fracture tiles are
+// bounded by nf + 1), plus launch tables and a rounding allowance per allocation.
+static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
+  const int64_t nc = (int64_t)d.nx * d.ny, nf = d.nf, ne = d.ne;
+  const int64_t gt = (int64_t)cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY);
+  const bool bic0 = o.precond == MC_BIC0, mixed = o.precision == MC_MIXED;
+  int64_t b = 0, nalloc = 0;
+  auto A = [&](int64_t bytes) {
+    b += std::max<int64_t>(bytes, 8);
+    nalloc += 1;
+  };
+  for (int a = 0; a < d.n_omega; ++a) {
+    if (d.omega[a].k) A(8 * nc);
+    if (d.omega[a].src) A(8 * nc);
+  }
+  if (nf) {
+    A(4 * nf);                    // host
+    A(8 * nf);                    // flen
+    A(8 * d.n_omega * nf);        // sigma_f
+    A(4 * (nf + 1));              // rowptr
+    A(4 * 2 * ne);                // col
+    A(4 * 2 * ne);                // eidx
+    A(8 * std::max<int64_t>(ne, 1));
+    A(4 * (nc + 1));              // hptr
+    A(4 * nf);                    // hidx
+    A(4 * (nf + 1));              // chain_ptr
+    A(4 * (nf + 1));              // gtile
+    A(4 * nf);                    // cidx
+    if (d.src_f) A(8 * nf);
+  }
+  const int ncont = d.n_omega + (nf ? 1 : 0);
+  int64_t ctiles = 0;
+  for (int c = 0; c < ncont; ++c) {
+    const bool grid = c < d.n_omega;
+    const int64_t n = grid ? nc : nf;
+    const int64_t tiles = grid ? gt : nf + 1;
+    ctiles += tiles;
+    A(8 * n);                     // diag
+    A(8 * n);                     // F
+    if (grid) {
+      A(8 * n);                   // tx
+      A(8 * n);                   // ty
+    } else {
+      A(8 * std::max<int64_t>(1, 2 * ne));
+      A(8 * n);                   // mt
+    }
+    for (int k = 0; k < 7; ++k) A(8 * n);   // two states, b, r, p, p2, q
+    A(8 * MC_SLOT * tiles);       // partials of its decoupled system
+    A(8 * MC_SLOT * tiles);
+    if (bic0) {
+      A(8 * n);                   // fdinv
+      A(8 * n);                   // z
+      if (grid) {
+        A(4 * n);                 // FP32 factor and conductances of the tile sweeps
+        A(4 * n);
+        A(4 * n);
+      } else {
+        A(8 * n);                 // cT
+      }
+    }
+    if (mixed) {
+      A(4 * n);                   // diag32
+      if (bic0) {
+        if (!grid) A(4 * n);      // fdinv32 (grid: above)
+        if (!grid) A(4 * n);      // cT32
+        A(4 * n);                 // z32
+      }
+      if (grid && !bic0) {
+        A(4 * n);                 // tx32
+        A(4 * n);                 // ty32
+      }
+      if (!grid) A(4 * std::max<int64_t>(1, 2 * ne));
+      for (int k = 0; k < 5; ++k) A(4 * n);   // x32, r32, p32, p232, q32
+    }
+  }
+  A(8 * MC_SLOT * ctiles);        // partials of the coupled system
+  A(8 * MC_SLOT * ctiles);
+  // launch tables: parts and tile lists of a few keys
+  b += 8 * (int64_t)(sizeof(PartD) * 8 + sizeof(Tile) * 4 * (ctiles + 64));
+  return b + nalloc * 4096 + (1 << 20);
 }
 
 }  // namespace mc
@@ -1774,6 +1861,15 @@ mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* sampled, double
   ABI_BEGIN
   return exec_profile_read(P->X, which, sampled, sampled_ms, issued);
   ABI_END(P)
+}
+
+mc_status mc_footprint(const mc_problem_desc* d, const mc_options* o, int64_t* bytes) {
+  if (!d || !bytes) return MC_EINVAL;
+  mc_options od;
+  mc_options_default(&od);
+  if (o) od = *o;
+  *bytes = mc::footprint(*d, od);
+  return MC_OK;
 }
 
 mc_status mc_autotune(mc_problem* const* probs, int32_t n, int32_t iters) {

@@ -25,10 +25,11 @@ if not os.path.exists(LIB_PATH):
                       "`python -m paper_2209_01158_amd.build` (hipcc, gfx950)")
 _lib = C.CDLL(LIB_PATH)
 
-MC_OK, MC_EINVAL, MC_ENOMEM, MC_ENOCONV, MC_EBREAKDOWN, MC_EDEVICE, MC_ENOTFOUND = \
-    0, -1, -2, -3, -4, -5, -6
+MC_OK, MC_EINVAL, MC_ENOMEM, MC_ENOCONV, MC_EBREAKDOWN, MC_EDEVICE, MC_ENOTFOUND, \
+    MC_ETIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENOCONV",
-                -4: "MC_EBREAKDOWN", -5: "MC_EDEVICE", -6: "MC_ENOTFOUND"}
+                -4: "MC_EBREAKDOWN", -5: "MC_EDEVICE", -6: "MC_ENOTFOUND", -7: "MC_ETIMEOUT"}
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 SCHEMES = {"D": 0, "coupled": 1, "L": 2, "U": 3, "EX": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 PRECONDS = {"jacobi": 0, "bic0": 1}
@@ -112,6 +113,43 @@ mc_profile_read = _sig("mc_profile_read", C.c_int,
 mc_autotune = _sig("mc_autotune", C.c_int, [C.POINTER(_PROBLEM), C.c_int32, C.c_int32])
 mc_autotune_clear = _sig("mc_autotune_clear", C.c_int, [])
 
+mc_footprint = _sig("mc_footprint", C.c_int,
+                    [C.POINTER(ProblemDesc), C.POINTER(Options), C.POINTER(C.c_int64)])
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_resident", C.c_int32),
+                ("max_bypass", C.c_int32), ("autotune", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("steps_done", C.c_int32),
+                ("n_steps", C.c_int32), ("bytes", C.c_int64), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_finish", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("finished", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int64), ("resident", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("budget", C.c_int64), ("steps", C.c_int64), ("cell_updates", C.c_double),
+                ("busy_seconds", C.c_double), ("elapsed_seconds", C.c_double)]
+
+
+_SERVER = C.c_void_p
+mc_server_create = _sig("mc_server_create", C.c_int,
+                        [C.POINTER(ServerConfig), C.POINTER(Options), C.POINTER(_SERVER)])
+mc_server_destroy = _sig("mc_server_destroy", C.c_int, [_SERVER])
+mc_server_submit = _sig("mc_server_submit", C.c_int,
+                        [_SERVER, C.POINTER(ProblemDesc), C.c_int32, C.POINTER(C.c_uint64)])
+mc_server_poll = _sig("mc_server_poll", C.c_int, [_SERVER, C.c_uint64, C.POINTER(RequestInfo)])
+mc_server_fetch = _sig("mc_server_fetch", C.c_int, [_SERVER, C.c_uint64, C.c_int32, _dp])
+mc_server_release = _sig("mc_server_release", C.c_int, [_SERVER, C.c_uint64])
+mc_server_wait = _sig("mc_server_wait", C.c_int, [_SERVER, C.c_double])
+mc_server_get_stats = _sig("mc_server_get_stats", C.c_int, [_SERVER, C.POINTER(ServerStats)])
+mc_server_step_seconds = _sig("mc_server_step_seconds", C.c_int,
+                              [_SERVER, _dp, C.c_int64, C.POINTER(C.c_int64)])
+mc_server_last_error = _sig("mc_server_last_error", C.c_char_p, [_SERVER])
+
 _BATCH = C.c_void_p
 mc_batch_create = _sig("mc_batch_create", C.c_int, [C.POINTER(Options), C.POINTER(_BATCH)])
 mc_batch_destroy = _sig("mc_batch_destroy", C.c_int, [_BATCH])
@@ -176,6 +214,62 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def describe(prob):
+    """mc_problem_desc of a media.Problem, plus the numpy arrays it points into (keep them
+    alive until the library has copied them)."""
+    keep = []
+    d = ProblemDesc()
+    d.nx, d.ny, d.h = prob.nx, prob.ny, prob.h
+    d.n_omega = len(prob.omega)
+    for a, o in enumerate(prob.omega):
+        od = d.omega[a]
+        od.c, od.k_const = o.c, o.k_const
+        if o.k is not None:
+            k = np.ascontiguousarray(o.k, np.float64).reshape(-1)
+            keep.append(k)
+            od.k = _ptr(k, C.c_double)
+        src = prob.source(a) if hasattr(prob, "source") else None
+        if src is not None:
+            src = np.ascontiguousarray(src, np.float64)
+            keep.append(src)
+            od.src = _ptr(src, C.c_double)
+        p0 = None if prob.p0 is None else prob.p0[a]
+        if p0 is not None:
+            p0 = np.ascontiguousarray(p0, np.float64).reshape(-1)
+            keep.append(p0)
+            od.p0 = _ptr(p0, C.c_double)
+    d.sigma_omega = prob.sigma_omega
+    nf = int(len(prob.host))
+    d.nf = nf
+    if nf:
+        host = np.ascontiguousarray(prob.host, np.int32)
+        flen = np.ascontiguousarray(prob.flen, np.float64)
+        sig = np.ascontiguousarray(prob.sigma_f, np.float64).reshape(-1)
+        edges = np.ascontiguousarray(prob.edges, np.int32).reshape(-1)
+        ed = np.ascontiguousarray(prob.edge_d, np.float64)
+        keep += [host, flen, sig, edges, ed]
+        d.host, d.flen, d.sigma_f = _ptr(host, C.c_int32), _ptr(flen, C.c_double), \
+            _ptr(sig, C.c_double)
+        d.ne = int(len(ed))
+        d.edges, d.edge_d = _ptr(edges, C.c_int32), _ptr(ed, C.c_double)
+        srcf = prob.source(d.n_omega) if hasattr(prob, "source") else None
+        if srcf is not None:
+            srcf = np.ascontiguousarray(srcf, np.float64)
+            keep.append(srcf)
+            d.src_f = _ptr(srcf, C.c_double)
+        p0f = None if prob.p0 is None else prob.p0[d.n_omega]
+        if p0f is not None:
+            p0f = np.ascontiguousarray(p0f, np.float64)
+            keep.append(p0f)
+            d.p0_f = _ptr(p0f, C.c_double)
+    d.k_f, d.c_f, d.aperture = prob.k_f, prob.c_f, prob.aperture
+    for s in range(4):
+        d.bc_type[s] = int(prob.bc_type[s])
+        d.bc_value[s] = float(prob.bc_value[s])
+    d.tau = prob.tau
+    return d, keep
+
+
 class Problem:
     """One multicontinuum problem resident on the GPU (wraps mc_problem)."""
 
@@ -183,56 +277,7 @@ class Problem:
                  max_iter=20000, stream="default", **kw):
         if stream == "default":
             stream = _default_stream()
-        self._keep = []
-        d = ProblemDesc()
-        d.nx, d.ny, d.h = prob.nx, prob.ny, prob.h
-        d.n_omega = len(prob.omega)
-        for a, o in enumerate(prob.omega):
-            od = d.omega[a]
-            od.c, od.k_const = o.c, o.k_const
-            if o.k is not None:
-                k = np.ascontiguousarray(o.k, np.float64).reshape(-1)
-                self._keep.append(k)
-                od.k = _ptr(k, C.c_double)
-            src = prob.source(a) if hasattr(prob, "source") else None
-            if src is not None:
-                src = np.ascontiguousarray(src, np.float64)
-                self._keep.append(src)
-                od.src = _ptr(src, C.c_double)
-            p0 = None if prob.p0 is None else prob.p0[a]
-            if p0 is not None:
-                p0 = np.ascontiguousarray(p0, np.float64).reshape(-1)
-                self._keep.append(p0)
-                od.p0 = _ptr(p0, C.c_double)
-        d.sigma_omega = prob.sigma_omega
-        nf = int(len(prob.host))
-        d.nf = nf
-        if nf:
-            host = np.ascontiguousarray(prob.host, np.int32)
-            flen = np.ascontiguousarray(prob.flen, np.float64)
-            sig = np.ascontiguousarray(prob.sigma_f, np.float64).reshape(-1)
-            edges = np.ascontiguousarray(prob.edges, np.int32).reshape(-1)
-            ed = np.ascontiguousarray(prob.edge_d, np.float64)
-            self._keep += [host, flen, sig, edges, ed]
-            d.host, d.flen, d.sigma_f = _ptr(host, C.c_int32), _ptr(flen, C.c_double), \
-                _ptr(sig, C.c_double)
-            d.ne = int(len(ed))
-            d.edges, d.edge_d = _ptr(edges, C.c_int32), _ptr(ed, C.c_double)
-            srcf = prob.source(d.n_omega) if hasattr(prob, "source") else None
-            if srcf is not None:
-                srcf = np.ascontiguousarray(srcf, np.float64)
-                self._keep.append(srcf)
-                d.src_f = _ptr(srcf, C.c_double)
-            p0f = None if prob.p0 is None else prob.p0[d.n_omega]
-            if p0f is not None:
-                p0f = np.ascontiguousarray(p0f, np.float64)
-                self._keep.append(p0f)
-                d.p0_f = _ptr(p0f, C.c_double)
-        d.k_f, d.c_f, d.aperture = prob.k_f, prob.c_f, prob.aperture
-        for s in range(4):
-            d.bc_type[s] = int(prob.bc_type[s])
-            d.bc_value[s] = float(prob.bc_value[s])
-        d.tau = prob.tau
+        d, self._keep = describe(prob)
         self.opt = make_options(scheme, precision, precond, tol, max_iter, stream=stream, **kw)
         h = _PROBLEM()
         _check(mc_create_problem(C.byref(d), C.byref(self.opt), C.byref(h)))
@@ -358,6 +403,92 @@ def tilings(problem):
     return [(inf.tiles[c], inf.blocks[c][0], inf.blocks[c][1]) for c in range(inf.n_cont)]
 
 
+def footprint(prob, **opt) -> int:
+    """Device bytes a problem would hold (mc_footprint upper bound)."""
+    d, keep = describe(prob)
+    o = make_options(**opt)
+    b = C.c_int64()
+    _check(mc_footprint(C.byref(d), C.byref(o), C.byref(b)))
+    return b.value
+
+
+class Server:
+    """Serving loop with continuous batching (wraps mc_server): requests are admitted by
+    device-memory footprint, stay resident, and advance one layer per batched step."""
+
+    def __init__(self, hbm_budget: int, max_resident: int = 0, max_bypass: int = 8,
+                 autotune: bool = False, scheme="D", precision="mixed", precond="bic0",
+                 tol=1e-10, max_iter=20000, stream=None, **kw):
+        self.opt = make_options(scheme, precision, precond, tol, max_iter, stream=stream, **kw)
+        cfg = ServerConfig(int(hbm_budget), int(max_resident), int(max_bypass), int(autotune))
+        h = _SERVER()
+        _check(mc_server_create(C.byref(cfg), C.byref(self.opt), C.byref(h)), None,
+               last_error=mc_server_last_error)
+        self.h = h
+        self.sizes = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            mc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, st):
+        _check(st, self.h, last_error=mc_server_last_error)
+
+    def submit(self, prob, n_steps: int) -> int:
+        d, keep = describe(prob)
+        rid = C.c_uint64()
+        self._chk(mc_server_submit(self.h, C.byref(d), int(n_steps), C.byref(rid)))
+        self.sizes[rid.value] = list(prob.sizes())
+        return rid.value
+
+    def poll(self, rid: int) -> dict:
+        i = RequestInfo()
+        self._chk(mc_server_poll(self.h, rid, C.byref(i)))
+        return dict(state=REQ_STATES.get(i.state, i.state), status=i.status,
+                    steps_done=i.steps_done, n_steps=i.n_steps, bytes=i.bytes,
+                    t_submit=i.t_submit, t_admit=i.t_admit, t_finish=i.t_finish)
+
+    def fetch(self, rid: int):
+        out = []
+        for a, n in enumerate(self.sizes[rid]):
+            v = np.empty(n)
+            self._chk(mc_server_fetch(self.h, rid, a, _ptr(v, C.c_double)))
+            out.append(v)
+        return out
+
+    def release(self, rid: int):
+        self._chk(mc_server_release(self.h, rid))
+        self.sizes.pop(rid, None)
+
+    def wait(self, timeout: float = -1.0):
+        self._chk(mc_server_wait(self.h, float(timeout)))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._chk(mc_server_get_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def step_seconds(self) -> np.ndarray:
+        n = C.c_int64()
+        self._chk(mc_server_step_seconds(self.h, None, 0, C.byref(n)))
+        out = np.empty(n.value)
+        self._chk(mc_server_step_seconds(self.h, _ptr(out, C.c_double), n.value, C.byref(n)))
+        return out
+
+
 class Batch:
     """Executor that advances many resident problems together (wraps mc_batch): every PCG
     launch covers all continua of all problems passed to `step`."""
@@ -418,4 +549,7 @@ EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
            "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
            "mc_profile", "mc_profile_read", "mc_batch_create", "mc_batch_destroy",
            "mc_batch_step", "mc_batch_last_error", "mc_batch_profile", "mc_batch_profile_read",
-           "mc_autotune", "mc_autotune_clear"]
+           "mc_autotune", "mc_autotune_clear", "mc_footprint", "mc_server_create",
+           "mc_server_destroy", "mc_server_submit", "mc_server_poll", "mc_server_fetch",
+           "mc_server_release", "mc_server_wait", "mc_server_get_stats",
+           "mc_server_step_seconds", "mc_server_last_error"]
