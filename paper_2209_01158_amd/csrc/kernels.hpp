@@ -477,28 +477,40 @@ __device__ void chain_solve(const T* __restrict__ rin, T* __restrict__ z,
   }
 }
 
-// Block IC(0) solve on one grid tile by one wavefront, entirely in registers (lane =
-// column).  rrow(y, i, act) returns this column's residual in tile row y (cell i; it may
-// update the iterate and store r on the way; 0 for cells outside the grid).  The inverse
-// pivots and face conductances are read once, as FP32 copies (a preconditioner needs no
-// more; PCG still converges to the FP64 solution).  Rows are swept in order; inside a row
-// the west (forward) or east (backward) coupling is a first-order recurrence across lanes,
-// solved by a 64-lane scan.  z is stored to zout.
+// One block of the grid block IC(0) preconditioner as seen by one wavefront: 64 columns
+// (lane = column) by MC_ICY rows.  cell(y) is a valid cell index for every lane (clamped
+// to the grid), act(y) says whether this lane's cell of row y exists.
+struct IcBlk {
+  int cx, cxs, y0, nx, ny;
+  bool colact;
+  __device__ IcBlk(const PartD& P, int unit) {
+    const int tile = unit / MC_ICB;   // unit = IC(0) block: tile and its band of MC_ICY rows
+    nx = P.nx;
+    ny = P.ny;
+    cx = (tile % P.tiles_x) * MC_TX + (int)(threadIdx.x & 63);
+    cxs = min(cx, nx - 1);
+    y0 = (tile / P.tiles_x) * MC_TY + (unit % MC_ICB) * MC_ICY;
+    colact = cx < nx;
+  }
+  __device__ bool act(int y) const { return colact && y0 + y < ny; }
+  __device__ long cell(int y) const { return (long)min(y0 + y, ny - 1) * nx + cxs; }
+};
+
+// Block IC(0) solve on one grid block by one wavefront, entirely in registers.  rv holds
+// this lane's residual in the block's rows (0 for cells outside the grid); the caller loads
+// it for all rows before the sweep, so every memory access of the block is issued before
+// the first dependent step.  The inverse pivots and face conductances are read once, as
+// FP32 copies (a preconditioner needs no more; PCG still converges to the FP64 solution).
+// Rows are swept in order; inside a row the west (forward) or east (backward) coupling is a
+// first-order recurrence across lanes, solved by a 64-lane scan.  z is stored to zout.
 // Dot products: with M = (D + E) D^-1 (D + E^T), the forward values u = (D + E)^-1 r and
 // z = M^-1 r satisfy (D + E^T) z = D u, hence (r, z) = (M z, z) = sum_i d_i u_i^2: both
 // (r,z) and (r,r) are complete after the forward sweep, so r never has to stay live.
-template <class T, bool HAS_T, class RR>
-__device__ __forceinline__ void ic0_column_sweep(const PartD& P, int unit, const RR& rrow,
-                                                 T* __restrict__ zout, double& rz,
-                                                 double& rr) {
+template <class T, bool HAS_T>
+__device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
+                                          const T (&rv)[MC_ICY], T* __restrict__ zout,
+                                          double& rz, double& rr) {
   const int lane = threadIdx.x & 63;
-  const int nx = P.nx, ny = P.ny;
-  const int tile = unit / MC_ICB;   // unit = IC(0) block: tile and its band of MC_ICY rows
-  const int x0 = (tile % P.tiles_x) * MC_TX;
-  const int y0 = (tile / P.tiles_x) * MC_TY + (unit % MC_ICB) * MC_ICY;
-  const int cx = x0 + lane;
-  const int cxs = min(cx, nx - 1);
-  const bool colact = cx < nx;
   const gconst<float> dinv = gc(P.fdinv32);
   const gconst<float> tx = gc(P.tx32);
   const gconst<float> ty = gc(P.ty32);
@@ -506,30 +518,26 @@ __device__ __forceinline__ void ic0_column_sweep(const PartD& P, int unit, const
   float dv[MC_ICY], te[MC_ICY], tn[MC_ICY];
 #pragma unroll
   for (int y = 0; y < MC_ICY; ++y) {
-    const int cy = y0 + y;
-    const bool act = colact && cy < ny;
-    const long i = (long)min(cy, ny - 1) * nx + cxs;   // a valid cell for every lane
+    const bool act = B.act(y);
+    const long i = B.cell(y);
     const float d = dinv[i];
     float e, n;
     if constexpr (HAS_T) {
       e = tx[i];
       n = ty[i];
     } else {
-      e = cx + 1 < nx ? tc : 0.0f;
-      n = cy + 1 < ny ? tc : 0.0f;
+      e = B.cx + 1 < B.nx ? tc : 0.0f;
+      n = B.y0 + y + 1 < B.ny ? tc : 0.0f;
     }
     dv[y] = act ? d : 0.0f;
     te[y] = act ? e : 0.0f;
-    tn[y] = act && y + 1 < MC_ICY ? n : 0.0f;   // couplings inside the tile only
+    tn[y] = act && y + 1 < MC_ICY ? n : 0.0f;   // couplings inside the block only
   }
   T u[MC_ICY];
   T uprev = (T)0;
 #pragma unroll
   for (int y = 0; y < MC_ICY; ++y) {
-    const int cy = y0 + y;
-    const bool act = colact && cy < ny;
-    const long i = (long)cy * nx + cx;
-    const T ri = rrow(y, i, act);
+    const T ri = rv[y];
     const T di = (T)dv[y];
     // west conductance = east conductance of the lane to the left (0 for lane 0)
     const float tw = __builtin_bit_cast(
@@ -542,7 +550,7 @@ __device__ __forceinline__ void ic0_column_sweep(const PartD& P, int unit, const
     u[y] = a;
     uprev = a;
     rr += (double)ri * (double)ri;
-    if (act) rz += (double)a * (double)a / (double)dv[y];
+    if (B.act(y)) rz += (double)a * (double)a / (double)dv[y];
   }
   T zabove = (T)0;
 #pragma unroll
@@ -553,16 +561,15 @@ __device__ __forceinline__ void ic0_column_sweep(const PartD& P, int unit, const
     T b = e * di;
     scan_maps_down(a, b);
     zabove = a;
-    const int cy = y0 + y;
-    if (colact && cy < ny) zout[(long)cy * nx + cx] = a;
+    if (B.act(y)) zout[B.cell(y)] = a;
   }
 }
 
-template <class T, class RR>
-__device__ __forceinline__ void ic0_column(const PartD& P, int unit, const RR& rrow,
-                                           T* __restrict__ zout, double& rz, double& rr) {
-  if (P.has_t) ic0_column_sweep<T, true>(P, unit, rrow, zout, rz, rr);
-  else ic0_column_sweep<T, false>(P, unit, rrow, zout, rz, rr);
+template <class T>
+__device__ __forceinline__ void ic0_block(const PartD& P, const IcBlk& B, const T (&rv)[MC_ICY],
+                                          T* __restrict__ zout, double& rz, double& rr) {
+  if (P.has_t) ic0_sweep<T, true>(P, B, rv, zout, rz, rr);
+  else ic0_sweep<T, false>(P, B, rv, zout, rz, rr);
 }
 
 // Runs f(unit) for the IC(0) blocks of the workgroup's tile run, one wavefront per block.
@@ -709,12 +716,18 @@ __device__ __forceinline__ void residual_and_precond(const PartD& P, const Tile&
   auto resg = [&](int l) { return Rs.resg(l); };
   const T* d = pick<T>(P.diag, P.diag32);
   if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
-    auto rrow = [&](int, long i, bool act) -> T {
-      if (!act) return (T)0;
-      const int cy = (int)(i / P.nx), cx = (int)(i - (long)cy * P.nx);
-      return emit(i, res(cx, cy, i), P.b[i]);
-    };
-    for_wave_tiles(t, [&](int tile) { ic0_column<T>(P, tile, rrow, z, v[0], v[1]); });
+    for_wave_tiles(t, [&](int unit) {
+      const IcBlk B(P, unit);
+      double r64[MC_ICY];
+#pragma unroll
+      for (int y = 0; y < MC_ICY; ++y)   // loads only: all rows in flight together
+        r64[y] = B.act(y) ? res(B.cxs, min(B.y0 + y, B.ny - 1), B.cell(y)) : 0.0;
+      T rs_[MC_ICY];
+#pragma unroll
+      for (int y = 0; y < MC_ICY; ++y)
+        rs_[y] = B.act(y) ? emit(B.cell(y), r64[y], P.b[B.cell(y)]) : (T)0;
+      ic0_block<T>(P, B, rs_, z, v[0], v[1]);
+    });
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     const T* dinv = pick<T>(P.fdinv, P.fdinv32);
     const T* cT = pick<T>(P.cT, P.cT32);
@@ -841,38 +854,76 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
   T* q = (T*)P.q;
   double pq = 0.0;
   if constexpr (KIND == PART_GRID) {
+    constexpr int WR = MC_TY / 4;                          // consecutive rows per wave
+    constexpr int NE = (W * H + MC_BLOCK - 1) / MC_BLOCK;  // staged cells per thread
     const int nx = P.nx, ny = P.ny;
-    const T* d = pick<T>(P.diag, P.diag32);
-    const T* tx = pick<T>(P.tx, P.tx32);
-    const T* ty = pick<T>(P.ty, P.ty32);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const gconst<T> d = gc(pick<T>(P.diag, P.diag32));
+    const gconst<T> tx = gc(pick<T>(P.tx, P.tx32));
+    const gconst<T> ty = gc(pick<T>(P.ty, P.ty32));
+    const gconst<T> zsrc = gc((const T*)(PREC == PREC_JACOBI ? P.r : P.z));
+    const gconst<T> pold = gc((const T*)(par ? P.p2 : P.p));
     const T tc = (T)P.tconst;
     for (int tile = t.t0; tile < t.t1; ++tile) {
       const int x0 = (tile % P.tiles_x) * MC_TX, y0 = (tile / P.tiles_x) * MC_TY;
-      // stage p_new on the tile and its one-cell halo (zero outside the grid)
-      for (int e = threadIdx.x; e < W * H; e += MC_BLOCK) {
-        const int gx = x0 + e % W - 1, gy = y0 + e / W - 1;
-        T val = (T)0;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) val = pn_of(P, (long)gy * nx + gx);
-        sp[e] = val;
+      const int cx = x0 + lane, cxs = min(cx, nx - 1);
+      const int r0 = y0 + wv * WR;   // first row of this wave
+      // every load of the tile is issued before the first dependent step: the wave's
+      // operator coefficients, then z (or r, diag) and p_old on the tile and its halo
+      T dv[WR], te[WR], tn[WR], tw[WR];
+      T ts0 = (T)0;
+#pragma unroll
+      for (int r = 0; r < WR; ++r) {
+        const long i = (long)min(r0 + r, ny - 1) * nx + cxs;
+        dv[r] = d[i];
+        if (P.has_t) {
+          te[r] = tx[i];
+          tn[r] = ty[i];
+          tw[r] = cx > 0 && cx < nx ? tx[i - 1] : (T)0;
+        }
+      }
+      if (P.has_t && r0 > 0) ts0 = ty[(long)min(r0 - 1, ny - 1) * nx + cxs];
+      T sz[NE], sd[NE], so[NE];
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int e = min((int)threadIdx.x + k * MC_BLOCK, W * H - 1);
+        const int gx = min(max(x0 + e % W - 1, 0), nx - 1);
+        const int gy = min(max(y0 + e / W - 1, 0), ny - 1);
+        const long j = (long)gy * nx + gx;
+        sz[k] = zsrc[j];
+        if (PREC == PREC_JACOBI) sd[k] = d[j];
+        so[k] = first ? (T)0 : pold[j];
+      }
+      // stage p_new = z + beta p_old on the tile and its one-cell halo (zero outside)
+#pragma unroll
+      for (int k = 0; k < NE; ++k) {
+        const int e = (int)threadIdx.x + k * MC_BLOCK;
+        if (e < W * H) {
+          const int gx = x0 + e % W - 1, gy = y0 + e / W - 1;
+          const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+          const T z = PREC == PREC_JACOBI ? sz[k] / sd[k] : sz[k];
+          sp[e] = in ? (first ? z : z + beta * so[k]) : (T)0;
+        }
       }
       __syncthreads();
-      const int lane = threadIdx.x & 63, cx = x0 + lane;
-      if (cx < nx) {
-        const int yend = min(y0 + MC_TY, ny);
-        for (int cy = y0 + (threadIdx.x >> 6); cy < yend; cy += 4) {
+#pragma unroll
+      for (int r = 0; r < WR; ++r) {
+        const int cy = r0 + r;
+        const int c = (r0 - y0 + r + 1) * W + lane + 1;
+        const T pc = sp[c];
+        T acc = dv[r] * pc;
+        if (P.has_t) {
+          // tx = 0 on the last column and ty = 0 on the last row, where the halo is 0 too
+          const T ts = r > 0 ? tn[r - 1] : ts0;
+          acc -= te[r] * sp[c + 1];
+          acc -= tw[r] * sp[c - 1];
+          acc -= tn[r] * sp[c + W];
+          acc -= ts * sp[c - W];
+        } else {
+          acc -= tc * ((sp[c - 1] + sp[c + 1]) + (sp[c - W] + sp[c + W]));
+        }
+        if (cx < nx && cy < ny) {
           const long i = (long)cy * nx + cx;
-          const int c = (cy - y0 + 1) * W + lane + 1;
-          const T pc = sp[c];
-          T acc = d[i] * pc;
-          if (P.has_t) {
-            // tx = 0 on the last column and ty = 0 on the last row, where the halo is 0 too
-            acc -= tx[i] * sp[c + 1];
-            if (cx > 0) acc -= tx[i - 1] * sp[c - 1];
-            acc -= ty[i] * sp[c + W];
-            if (cy > 0) acc -= ty[i - nx] * sp[c - W];
-          } else {
-            acc -= tc * ((sp[c - 1] + sp[c + 1]) + (sp[c - W] + sp[c + W]));
-          }
           if (P.coupled) {
             auto vp = [&](int pj, long j) { return (double)pn_of(parts[pj], j); };
             acc = (T)((double)acc + grid_coupling(parts, P, i, vp));
@@ -935,19 +986,35 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   T* z = (T*)P.z;
   const T* d = pick<T>(P.diag, P.diag32);
   if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
-    // one wavefront per tile: x and r are updated row by row inside the forward sweep
-    T* __restrict__ xw = x;
-    T* __restrict__ rw = r;
+    // one wavefront per IC(0) block: every load of the block is issued first, then x and r
+    // are updated and stored, then the sweep runs on r held in registers
+    const gconst<T> xg = gc((const T*)x);
     const gconst<T> pg = gc(p);
+    const gconst<T> rg = gc((const T*)r);
     const gconst<T> qg = gc(q);
-    auto rrow = [&](int, long i, bool act) -> T {
-      if (!act) return (T)0;
-      xw[i] = xw[i] + alpha * pg[i];
-      const T rn = rw[i] - alpha * qg[i];
-      rw[i] = rn;
-      return rn;
-    };
-    for_wave_tiles(t, [&](int tile) { ic0_column<T>(P, tile, rrow, z, o[0], o[1]); });
+    for_wave_tiles(t, [&](int unit) {
+      const IcBlk B(P, unit);
+      T xv[MC_ICY], pv[MC_ICY], rv[MC_ICY], qv[MC_ICY];
+#pragma unroll
+      for (int y = 0; y < MC_ICY; ++y) {
+        const long i = B.cell(y);
+        xv[y] = xg[i];
+        pv[y] = pg[i];
+        rv[y] = rg[i];
+        qv[y] = qg[i];
+      }
+#pragma unroll
+      for (int y = 0; y < MC_ICY; ++y) {
+        const T xn = xv[y] + alpha * pv[y];
+        const T rn = rv[y] - alpha * qv[y];
+        if (B.act(y)) {
+          x[B.cell(y)] = xn;
+          r[B.cell(y)] = rn;
+        }
+        rv[y] = B.act(y) ? rn : (T)0;
+      }
+      ic0_block<T>(P, B, rv, z, o[0], o[1]);
+    });
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     const T* dinv = pick<T>(P.fdinv, P.fdinv32);
     const T* cT = pick<T>(P.cT, P.cT32);
@@ -1121,8 +1188,13 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   double* z = (double*)P.z;
   if constexpr (PREC == PREC_BIC0 && KIND == PART_GRID) {
     double dz = 0.0, dr = 0.0;
-    auto rrow = [&](int, long i, bool act) { return act ? r[i] : 0.0; };
-    for_wave_tiles(t, [&](int tile) { ic0_column<double>(P, tile, rrow, z, dz, dr); });
+    for_wave_tiles(t, [&](int unit) {
+      const IcBlk B(P, unit);
+      double rv[MC_ICY];
+#pragma unroll
+      for (int y = 0; y < MC_ICY; ++y) rv[y] = B.act(y) ? r[B.cell(y)] : 0.0;
+      ic0_block<double>(P, B, rv, z, dz, dr);
+    });
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     for (int tile = t.t0; tile < t.t1; ++tile) {
       const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
