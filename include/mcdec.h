@@ -71,10 +71,13 @@ typedef enum {
 
 typedef enum {
   MC_JACOBI = 0, /* z = r / diag                                                               */
-  MC_BIC0 = 1    /* block incomplete Cholesky, zero fill: the grid split into 64-column x 16-row
-                    blocks and the fracture graph into its chains of consecutive connected cells;
-                    inside a block, IC(0) in natural order (exact Cholesky on a chain);
-                    couplings between blocks are dropped                                        */
+  MC_BIC0 = 1    /* grid: block incomplete Cholesky, zero fill, on 64-column x 16-row blocks
+                    (IC(0) in natural order inside a block, couplings between blocks dropped);
+                    fracture graph: an exact solve -- its chains cut at the crossing cells
+                    (cells joined to cells other than their chain neighbours) are tridiagonal
+                    blocks solved exactly, and the crossing cells are solved through the
+                    inverse of their Schur complement (formed once at setup, up to 6144
+                    crossing cells; beyond that the crossing couplings are dropped)            */
 } mc_precond;
 
 /* One continuum on the Omega grid. */
@@ -149,6 +152,8 @@ typedef struct {
                             chains of about 256 cells)                                          */
   int32_t blocks[3][2];  /* workgroups per launch per continuum: [0] operator kernel,
                             [1] update / residual kernels (equal to its partial-sum slots)      */
+  int32_t n_crossing;    /* fracture cells solved through the crossing-cell Schur complement
+                            (MC_BIC0; 0 with Jacobi, without crossings, or beyond 6144)         */
 } mc_info;
 
 typedef struct mc_problem mc_problem;

@@ -14,7 +14,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 instructions in any generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I" + os.path.join(ROOT, "include")]
+         "-I" + os.path.join(ROOT, "include"),
+         # dense SPD inverse of the crossing-cell Schur complement at setup
+         "-lrocsolver", "-lrocblas"]
 
 
 def build(verbose: bool = False) -> str:

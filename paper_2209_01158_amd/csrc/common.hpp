@@ -17,6 +17,8 @@
 #define MC_TY 32               // grid tile height (rows) of the LDS-staged operator
 #define MC_ICY 16              // rows of a grid block of the block IC(0) preconditioner
 #define MC_ICB (MC_TY / MC_ICY)  // IC(0) blocks per grid tile
+#define MC_SCHUR_ROWS 16       // rows of the crossing-cell inverse per workgroup
+#define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };
 enum { PREC_JACOBI = 0, PREC_BIC0 = 1 };
@@ -93,10 +95,27 @@ struct PartD {
   const float* fdinv32;
   const int* chain_ptr;    // (graph) chain boundaries [nchains+1]
   const int* gtile;        // (graph) work tiles as chain ranges [ntiles+1]
-  const double* cT;        // (graph) conductance between cell l and l-1 of its chain (0 at starts)
+  const double* cT;        // (graph) coupling of cell l to l-1 inside its block (0 at block starts)
   const float* cT32;
   int nchains;
-  int pad2;
+  // (graph) exact solve through the crossing cells: blocks are the runs of chains between
+  // crossing cells, the crossing cells are solved by the inverse of their Schur complement
+  int K;                   // crossing cells (0: none, or too many: crossings left out)
+  int slotS;               // first partial slot of the Schur product (after the update slots)
+  int pad3;
+  const int* xcells;       // [K] crossing cells, ascending
+  const int* xtile;        // [ntiles + 1] crossing cells of each work tile
+  const int* xlr;          // [2n] crossing neighbours (left, right) of each cell's block or -1
+  const double* cl;        // [n] responses of the block to its left / right crossing neighbour
+  const double* cr;
+  const float* cl32;
+  const float* cr32;
+  const double* cxl;       // [K] conductance of crossing cell k to its chain neighbours
+  const double* cxr;
+  const double* sinv;      // [K*K] inverse of the Schur complement (symmetric)
+  const float* sinv32;
+  void* gX;                // [K] crossing right-hand side g = r_X - A_XI y (launch precision)
+  void* zX;                // [K] crossing solution S^-1 g (launch precision)
   // transfer structure
   const int* hptr;         // (grid) [n+1] fracture cells hosted per cell (CSR)
   const int* hidx;         // (grid) [nf]   their fracture indices

@@ -3,6 +3,7 @@
 // problems advanced by shared launches, and the C ABI.
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -128,12 +129,13 @@ struct DevArena {
 struct Table {
   PartD* parts = nullptr;
   int pcap = 0;
-  Tile* tiles[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [tiling][kind]
-  int nblk[2][2] = {{0, 0}, {0, 0}};
-  int cap[2][2] = {{0, 0}, {0, 0}};
+  // [tiling][kind]; tiling 0: operator, 1: update / init / residual, 2: crossing-cell rows
+  Tile* tiles[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  int nblk[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int cap[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   int nparts = 0;
   std::vector<PartD> hparts;
-  std::vector<int> htil;                      // tiles, blocksA, blocksB per part
+  std::vector<int> htil;                      // tiles and the three workgroup counts per part
   std::map<long, hipGraphExec_t> graphs;
 };
 
@@ -142,19 +144,20 @@ static void drop_graphs(Table& T) {
   T.graphs.clear();
 }
 
-// Tiling of one part: its tiles and the workgroups of its operator / update launches.
+// Tiling of one part: its tiles and the workgroups of its operator / update launches and of
+// its crossing-cell product (one workgroup per MC_SCHUR_ROWS rows).
 struct PartTiling {
   int tiles;
-  int blocks[2];
+  int blocks[3];
 };
 
 static bool table_matches(const Table& T, const std::vector<PartD>& parts,
                           const std::vector<PartTiling>& til) {
-  if (T.hparts.size() != parts.size() || T.htil.size() != 3 * til.size()) return false;
+  if (T.hparts.size() != parts.size() || T.htil.size() != 4 * til.size()) return false;
   if (std::memcmp(T.hparts.data(), parts.data(), parts.size() * sizeof(PartD)) != 0) return false;
   for (size_t i = 0; i < til.size(); ++i)
-    if (T.htil[3 * i] != til[i].tiles || T.htil[3 * i + 1] != til[i].blocks[0] ||
-        T.htil[3 * i + 2] != til[i].blocks[1])
+    if (T.htil[4 * i] != til[i].tiles || T.htil[4 * i + 1] != til[i].blocks[0] ||
+        T.htil[4 * i + 2] != til[i].blocks[1] || T.htil[4 * i + 3] != til[i].blocks[2])
       return false;
   return true;
 }
@@ -170,15 +173,17 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
   HIPCHK(hipMemcpyAsync(T.parts, parts.data(), parts.size() * sizeof(PartD),
                         hipMemcpyHostToDevice, s));
   const bool xcd = env_flag("MCDEC_XCD", true);
-  std::vector<Tile> kept[2][2];
-  for (int fam = 0; fam < 2; ++fam)
+  std::vector<Tile> kept[3][2];
+  for (int fam = 0; fam < 3; ++fam)
     for (int kind = 0; kind < 2; ++kind) {
       std::vector<Tile>& tiles = kept[fam][kind];
       for (int pi = 0; pi < (int)parts.size(); ++pi) {
         const PartD& q = parts[pi];
         if (q.kind != kind) continue;
-        const int nt = til[pi].tiles, nb = til[pi].blocks[fam];
-        const int slot0 = fam == 0 ? q.slot0A : q.slot0B;
+        const int nb = til[pi].blocks[fam];
+        if (nb == 0) continue;
+        const int nt = fam == 2 ? nb : til[pi].tiles;
+        const int slot0 = fam == 0 ? q.slot0A : (fam == 1 ? q.slot0B : q.slotS);
         // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die
         // j of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
         std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
@@ -209,6 +214,7 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     T.htil.push_back(t.tiles);
     T.htil.push_back(t.blocks[0]);
     T.htil.push_back(t.blocks[1]);
+    T.htil.push_back(t.blocks[2]);
   }
 }
 
@@ -216,15 +222,23 @@ struct Cont {  // one continuum
   int kind;    // PART_GRID / PART_GRAPH
   long n;
   int tiles;      // tiles of its part
-  int blocks[2];  // workgroups (and partial slots) per launch: operator / update tiling
+  int blocks[3];  // workgroups (and partial slots) per launch: operator / update tiling /
+                  // crossing-cell product (graph with crossing cells only)
   // FP64 coefficients
   double *diag = nullptr, *tx = nullptr, *ty = nullptr, *F = nullptr, *val = nullptr,
          *mt = nullptr;
   float *diag32 = nullptr, *tx32 = nullptr, *ty32 = nullptr, *val32 = nullptr;
   double* fdinv = nullptr;   // block IC(0) inverse pivots
   float* fdinv32 = nullptr;
-  double* cT = nullptr;      // (graph) chain conductances to the previous cell
+  double* cT = nullptr;      // (graph) block couplings to the previous cell
   float* cT32 = nullptr;
+  // (graph) exact solve through the crossing cells
+  int K = 0;
+  int *xcells = nullptr, *xtile = nullptr, *xlr = nullptr;
+  double *cl = nullptr, *cr = nullptr, *cxl = nullptr, *cxr = nullptr, *sinv = nullptr;
+  float *cl32 = nullptr, *cr32 = nullptr, *sinv32 = nullptr;
+  double *gX = nullptr, *zX = nullptr;
+  float *gX32 = nullptr, *zX32 = nullptr;
   // state and PCG vectors
   double* ps[2] = {nullptr, nullptr};
   double *b = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *z = nullptr;
@@ -380,7 +394,10 @@ struct mc_problem {
   double* k[2] = {nullptr, nullptr};
   double* src[3] = {nullptr, nullptr, nullptr};
   int *host = nullptr, *rowptr = nullptr, *col = nullptr, *eidx = nullptr, *hptr = nullptr,
-      *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr, *cidx = nullptr;
+      *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr;
+  GraphCSR gh;                       // host copies of the fracture graph structure
+  std::vector<int> chains_h, gtile_h;
+  int K_all = 0;                     // crossing cells of the fracture graph
   double *flen = nullptr, *edge_d = nullptr, *sigma_f = nullptr;
   int nchains = 0, ngtiles = 0;
   // systems: 0..ncont-1 decoupled per continuum, ncont = coupled; their partial-sum slots
@@ -453,6 +470,21 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.gtile = P->gtile;
   q.cT = C.cT;
   q.cT32 = C.cT32;
+  q.K = C.K;
+  q.slotS = slot0B + C.blocks[1];
+  q.xcells = C.xcells;
+  q.xtile = C.xtile;
+  q.xlr = C.xlr;
+  q.cl = C.cl;
+  q.cr = C.cr;
+  q.cl32 = C.cl32;
+  q.cr32 = C.cr32;
+  q.cxl = C.cxl;
+  q.cxr = C.cxr;
+  q.sinv = C.sinv;
+  q.sinv32 = C.sinv32;
+  q.gX = fp32 ? (void*)C.gX32 : (void*)C.gX;
+  q.zX = fp32 ? (void*)C.zX32 : (void*)C.zX;
   if (C.kind == PART_GRID) {
     q.hptr = P->nf ? P->hptr : nullptr;
     q.hidx = P->hidx;
@@ -488,7 +520,7 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
 
 static PartTiling tiling_of(const mc_problem* P, int c) {
   const Cont& C = P->cont[c];
-  return PartTiling{C.tiles, {C.blocks[0], C.blocks[1]}};
+  return PartTiling{C.tiles, {C.blocks[0], C.blocks[1], C.blocks[2]}};
 }
 
 static Table& upload_table(mc_problem* P, const std::string& key, std::vector<PartD> parts) {
@@ -515,7 +547,7 @@ static std::vector<PartD> coupled_parts(mc_problem* P, int sysI, int base) {
   for (int c = 0; c < P->ncont; ++c) {
     PartD q = base_part(P, c, sysI, slotA, slotB, false);
     slotA += P->cont[c].blocks[0];
-    slotB += P->cont[c].blocks[1];
+    slotB += P->cont[c].blocks[1] + P->cont[c].blocks[2];
     q.coupled = 1;
     parts.push_back(q);
   }
@@ -534,6 +566,89 @@ static std::vector<PartD> coupled_parts(mc_problem* P, int sysI, int base) {
 // ------------------------------------------------------------------------------------
 // setup
 // ------------------------------------------------------------------------------------
+static std::mutex g_blas_mu;
+static rocblas_handle g_blas = nullptr;
+
+// In place: the K x K SPD matrix S (column-major, device) -> S^-1 (full, symmetric), by a
+// Cholesky factorization and its inverse (rocSOLVER potrf, potri) and a copy of the lower
+// triangle to the upper one.  Runs once per problem at setup.
+static void invert_spd(double* S, int K, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_blas_mu);
+  if (!g_blas && rocblas_create_handle(&g_blas) != rocblas_status_success) {
+    g_blas = nullptr;
+    throw Error{MC_EDEVICE, "rocblas_create_handle failed"};
+  }
+  if (rocblas_set_stream(g_blas, s) != rocblas_status_success)
+    throw Error{MC_EDEVICE, "rocblas_set_stream failed"};
+  rocblas_int* info = nullptr;
+  HIPCHK(hipMalloc((void**)&info, 2 * sizeof(rocblas_int)));
+  rocblas_status a = rocsolver_dpotrf(g_blas, rocblas_fill_lower, K, S, K, info);
+  rocblas_status b = rocsolver_dpotri(g_blas, rocblas_fill_lower, K, S, K, info + 1);
+  rocblas_int h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(info);
+  HIPCHK(e);
+  if (a != rocblas_status_success || b != rocblas_status_success || h[0] != 0 || h[1] != 0)
+    throw Error{MC_EDEVICE, "inverse of the crossing-cell Schur complement failed (status " +
+                                std::to_string((int)a) + "/" + std::to_string((int)b) +
+                                ", info " + std::to_string(h[0]) + "/" + std::to_string(h[1]) + ")"};
+  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv((long)K * K, 256)), dim3(256), 0, s, S, K);
+  HIPCHK(hipGetLastError());
+}
+
+// Fracture block preconditioner of the block IC(0) option: factors of the chain blocks cut at
+// the crossing cells and the inverse Schur complement of the crossing cells (an exact solve
+// of the fracture system), built on the host in FP64 from the device coefficients.
+static void setup_fracture_solve(mc_problem* P, Cont& C) {
+  hipStream_t s = P->X.stream;
+  const long nf = C.n, ne2 = 2L * P->ne;
+  std::vector<double> diag(nf), val(std::max<long>(ne2, 1));
+  HIPCHK(hipMemcpyAsync(diag.data(), C.diag, nf * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (ne2) HIPCHK(hipMemcpyAsync(val.data(), C.val, ne2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  SchurHost H = build_schur((int)nf, P->gh, P->chains_h, P->gtile_h, diag.data(), val.data(),
+                            MC_SCHUR_KMAX);
+  DevArena& M = P->mem;
+  if (!C.cT) C.cT = M.alloc<double>(nf);
+  HIPCHK(hipMemcpyAsync(C.fdinv, H.dinv.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.cT, H.cT.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+  C.K = H.K;
+  std::vector<int> xlr;
+  if (H.K > 0) {
+    const int K = H.K;
+    if (!C.xcells) {
+      C.xcells = M.alloc<int>(K);
+      C.xtile = M.alloc<int>(H.xtile.size());
+      C.xlr = M.alloc<int>(2 * nf);
+      C.cl = M.alloc<double>(nf);
+      C.cr = M.alloc<double>(nf);
+      C.cxl = M.alloc<double>(K);
+      C.cxr = M.alloc<double>(K);
+      C.sinv = M.alloc<double>((size_t)K * K);
+      C.gX = M.alloc<double>(K);
+      C.zX = M.alloc<double>(K);
+    }
+    xlr.resize(2 * nf);
+    for (long l = 0; l < nf; ++l) {
+      xlr[2 * l] = H.xl[l];
+      xlr[2 * l + 1] = H.xr[l];
+    }
+    HIPCHK(hipMemcpyAsync(C.xcells, H.xcells.data(), K * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.xtile, H.xtile.data(), H.xtile.size() * sizeof(int),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.xlr, xlr.data(), 2 * nf * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.cl, H.cl.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.cr, H.cr.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.cxl, H.cxl.data(), K * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.cxr, H.cxr.data(), K * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C.sinv, H.S.data(), (size_t)K * K * sizeof(double),
+                          hipMemcpyHostToDevice, s));
+    invert_spd(C.sinv, K, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
+}
+
 static void build_coefficients(mc_problem* P) {
   const bool ex = P->X.opt.scheme == MC_SCHEME_EX;
   const double h = P->d.h, tau = P->d.tau;
@@ -593,6 +708,7 @@ static void build_coefficients(mc_problem* P) {
     hipLaunchKernelGGL(k_setup_graph, dim3(cdiv(P->nf, 256)), dim3(256), 0, s, g);
   }
   HIPCHK(hipGetLastError());
+  for (auto& C : P->cont) C.K = 0;   // set again below for block IC(0)
   if (P->X.opt.precond == MC_BIC0) {
     for (auto& C : P->cont) {
       if (!C.fdinv) C.fdinv = P->mem.alloc<double>(C.n);
@@ -610,16 +726,7 @@ static void build_coefficients(mc_problem* P) {
         hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)C.tiles * MC_ICB, 64)), dim3(64),
                            0, s, g);
       } else {
-        if (!C.cT) C.cT = P->mem.alloc<double>(C.n);
-        ChainSetup g;
-        g.nchains = P->nchains;
-        g.chain_ptr = P->chain_ptr;
-        g.cidx = P->cidx;
-        g.val = C.val;
-        g.diag = C.diag;
-        g.cT = C.cT;
-        g.dinv = C.fdinv;
-        hipLaunchKernelGGL(k_setup_chains, dim3(cdiv(P->nchains, 64)), dim3(64), 0, s, g);
+        setup_fracture_solve(P, C);
       }
     }
     HIPCHK(hipGetLastError());
@@ -648,6 +755,15 @@ static void build_coefficients(mc_problem* P) {
         cv(C.fdinv, C.fdinv32, C.n);
         if (C.kind == PART_GRAPH) cv(C.cT, C.cT32, C.n);
         if (!C.z32) C.z32 = P->mem.alloc<float>(C.n);
+        if (C.kind == PART_GRAPH && C.K > 0) {
+          cv(C.cl, C.cl32, C.n);
+          cv(C.cr, C.cr32, C.n);
+          cv(C.sinv, C.sinv32, (long)C.K * C.K);
+          if (!C.gX32) {
+            C.gX32 = P->mem.alloc<float>(C.K);
+            C.zX32 = P->mem.alloc<float>(C.K);
+          }
+        }
       }
       if (C.kind == PART_GRID) {
         cv(C.tx, C.tx32, C.n);
@@ -679,10 +795,11 @@ static void set_slot_counts(mc_problem* P, SysState* hs) {
     Cont& C = P->cont[c];
     C.blocks[0] = blocks_for(C.tiles, C.kind, 0, bic0, fp32);
     C.blocks[1] = blocks_for(C.tiles, C.kind, 1, bic0, fp32);
+    C.blocks[2] = C.K > 0 ? (int)cdiv(C.K, MC_SCHUR_ROWS) : 0;
     hs[c].nslotsA = C.blocks[0];
-    hs[c].nslotsB = C.blocks[1];
+    hs[c].nslotsB = C.blocks[1] + C.blocks[2];
     ca += C.blocks[0];
-    cb += C.blocks[1];
+    cb += C.blocks[1] + C.blocks[2];
   }
   hs[P->ncont].nslotsA = ca;
   hs[P->ncont].nslotsB = cb;
@@ -728,10 +845,12 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     P->chain_ptr = M.upload(chains.data(), chains.size(), s);
     P->nchains = (int)chains.size() - 1;
     std::vector<int> gt = build_graph_tiles(chains, MC_GRAPH_ROWS);
-    std::vector<int> ce = chain_prev_entry(d.nf, g, chains);
     P->gtile = M.upload(gt.data(), gt.size(), s);
-    P->cidx = M.upload(ce.data(), ce.size(), s);
     P->ngtiles = (int)gt.size() - 1;
+    P->K_all = count_crossing_cells(d.nf, d.ne, d.edges);
+    P->gh = g;
+    P->chains_h = chains;
+    P->gtile_h = gt;
     if (d.src_f) P->src[d.n_omega] = M.upload(d.src_f, d.nf, s);
   }
   // continua
@@ -744,6 +863,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY)) : P->ngtiles;
     C.blocks[0] = blocks_for(C.tiles, C.kind, 0, o.precond == MC_BIC0, o.precision == MC_MIXED);
     C.blocks[1] = blocks_for(C.tiles, C.kind, 1, o.precond == MC_BIC0, o.precision == MC_MIXED);
+    C.blocks[2] = 0;
     C.diag = M.alloc<double>(C.n);
     C.F = M.alloc<double>(C.n);
     if (grid) {
@@ -770,10 +890,13 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   std::memset(hs.data(), 0, nsys * sizeof(SysState));
   // partial-slot arrays sized for one workgroup per tile (the most any tiling uses), so the
   // tilings can follow option changes
+  // (a fracture continuum adds the workgroups of its crossing-cell product)
+  const int kslots = P->K_all <= MC_SCHUR_KMAX ? (int)cdiv(P->K_all, MC_SCHUR_ROWS) : 0;
+  auto slots_of = [&](int c) { return P->cont[c].tiles + (P->cont[c].kind == PART_GRAPH ? kslots : 0); };
   int coupled_tiles = 0;
-  for (int c = 0; c < P->ncont; ++c) coupled_tiles += P->cont[c].tiles;
+  for (int c = 0; c < P->ncont; ++c) coupled_tiles += slots_of(c);
   for (int sI = 0; sI < nsys; ++sI) {
-    const int ns = sI < P->ncont ? P->cont[sI].tiles : coupled_tiles;
+    const int ns = sI < P->ncont ? slots_of(sI) : coupled_tiles;
     hs[sI].partA = M.alloc<double>((size_t)ns * MC_SLOT);
     hs[sI].partB = M.alloc<double>((size_t)ns * MC_SLOT);
     hs[sI].done = 1;
@@ -784,6 +907,9 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   HIPCHK(hipMemcpyAsync(P->X.sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   build_coefficients(P);
+  set_slot_counts(P, hs.data());   // the crossing-cell workgroups are known now
+  HIPCHK(hipMemcpyAsync(P->X.sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------------------------------
@@ -836,6 +962,15 @@ struct Group {
   bool inflight = false;
 };
 
+// z_X = S^-1 g for the fracture parts with crossing cells (after their update, init or
+// residual kernel), completing (r, z) in the update slots.
+template <class T>
+static void launch_schur(Exec& X, const Table& Tb, hipStream_t s) {
+  if (Tb.nblk[2][PART_GRAPH])
+    hipLaunchKernelGGL(k_schur<T>, dim3(Tb.nblk[2][PART_GRAPH]), dim3(MC_BLOCK), 0, s, Tb.parts,
+                       Tb.tiles[2][PART_GRAPH], X.sys);
+}
+
 // One PCG iteration over the group's tiles: operator kernels, then update kernels.
 template <class T, int PREC>
 static void launch_iter(Exec& X, Group& G, bool timed) {
@@ -860,6 +995,7 @@ static void launch_iter(Exec& X, Group& G, bool timed) {
   L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0);
   L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1);
   L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1);
+  if (G.kinds & 2) launch_schur<T>(X, Tb, G.s);
 }
 
 // Executable graph of K iterations over the group's tiles (captured on first use).  The
@@ -980,6 +1116,7 @@ static void advance_t(Exec& X, Group& G) {
                          G.s1);
       if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
       launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+      if (G.kinds & 2) launch_schur<double>(X, *G.T, G.s);
       G.k = 0;
       G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
       G.phase = 1;
@@ -1002,6 +1139,7 @@ static void advance_t(Exec& X, Group& G) {
     if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
     launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+    if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
     G.outer = 0;
     G.k = 0;
     G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
@@ -1019,6 +1157,7 @@ static void advance_t(Exec& X, Group& G) {
     launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, X.sys);
     launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+    if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
     G.outer += 1;
     G.k = 0;
     G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
@@ -1294,7 +1433,7 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
         for (int c = 0; c < P->ncont; ++c) {
           if ((P->cont[c].kind == PART_GRID) != (pass == 0)) continue;
           const int sI = (int)hs.size();
-          rec(P, c, P->cont[c].blocks[0], P->cont[c].blocks[1]);
+          rec(P, c, P->cont[c].blocks[0], P->cont[c].blocks[1] + P->cont[c].blocks[2]);
           parts.push_back(base_part(P, c, sI, 0, 0, mixed));
           til.push_back(tiling_of(P, c));
           sys_of[i].push_back(sI);
@@ -1308,7 +1447,7 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
       int nA = 0, nB = 0;
       for (auto& C : P->cont) {
         nA += C.blocks[0];
-        nB += C.blocks[1];
+        nB += C.blocks[1] + C.blocks[2];
       }
       rec(P, P->ncont, nA, nB);
       std::vector<PartD> cp = coupled_parts(P, sI, (int)parts.size());
@@ -1380,7 +1519,7 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
   S.partA = P->partA[c];
   S.partB = P->partB[c];
   S.nslotsA = C.blocks[0];
-  S.nslotsB = C.blocks[1];
+  S.nslotsB = C.blocks[1] + C.blocks[2];
   S.max_iter = 1 << 30;
   S.max_outer = 1;
   S.done = 1;
@@ -1390,9 +1529,11 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
   if (fp32) {
     launch_all(s, Tb, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch_all(s, Tb, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+    launch_schur<float>(X, Tb, s);
   }
   else {
     launch_all(s, Tb, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+    launch_schur<double>(X, Tb, s);
   }
   const int warm = 3, tot = warm + iters;
   std::vector<hipEvent_t> ev(3 * tot, nullptr);
@@ -1407,6 +1548,7 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
     HIPCHK(hipEventRecord(ev[3 * j + 1], s));
     launch2(g, 1, k_pcg_B<T, PREC, PART_GRID>, k_pcg_B<T, PREC, PART_GRAPH>, X.sys);
     HIPCHK(hipEventRecord(ev[3 * j + 2], s));
+    launch_schur<T>(X, Tb, s);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -1512,7 +1654,6 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
     A(4 * nf);                    // hidx
     A(4 * (nf + 1));              // chain_ptr
     A(4 * (nf + 1));              // gtile
-    A(4 * nf);                    // cidx
     if (d.src_f) A(8 * nf);
   }
   const int ncont = d.n_omega + (nf ? 1 : 0);
@@ -1558,6 +1699,35 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
       }
       if (!grid) A(4 * std::max<int64_t>(1, 2 * ne));
       for (int k = 0; k < 5; ++k) A(4 * n);   // x32, r32, p32, p232, q32
+    }
+  }
+  // exact fracture solve (block IC(0)): inverse Schur complement of the crossing cells,
+  // responses and indices
+  if (nf && bic0) {
+    const int64_t Kall = count_crossing_cells(d.nf, d.ne, d.edges);
+    const int64_t K = Kall <= MC_SCHUR_KMAX ? Kall : 0;
+    if (K > 0) {
+      A(4 * K);                   // xcells
+      A(4 * (nf + 2));            // xtile
+      A(8 * nf);                  // xlr
+      A(8 * nf);                  // cl
+      A(8 * nf);                  // cr
+      A(8 * K);                   // cxl
+      A(8 * K);                   // cxr
+      A(8 * K * K);               // S^-1
+      A(8 * K);                   // g
+      A(8 * K);                   // z_X
+      if (mixed) {
+        A(4 * nf);
+        A(4 * nf);
+        A(4 * K * K);
+        A(4 * K);
+        A(4 * K);
+      }
+      const int64_t ks = (K + MC_SCHUR_ROWS - 1) / MC_SCHUR_ROWS;
+      A(8 * MC_SLOT * ks);        // partial slots of the crossing product (decoupled and coupled)
+      A(8 * MC_SLOT * ks);
+      ctiles += ks;
     }
   }
   A(8 * MC_SLOT * ctiles);        // partials of the coupled system
@@ -1730,9 +1900,16 @@ mc_status mc_apply_precond(mc_problem* P, int32_t alpha, const double* r, double
   parts[0].r = const_cast<double*>(r);
   parts[0].z = z;
   mc::Table& T = mc::upload_table(P, "prec" + std::to_string(alpha), parts);
-  if (P->X.opt.precond == MC_BIC0)
+  if (P->X.opt.precond == MC_BIC0) {
     mc::launch_all(P->X.stream, T, 1, mc::k_precond<PREC_BIC0, PART_GRID>,
                    mc::k_precond<PREC_BIC0, PART_GRAPH>);
+    if (T.nblk[2][PART_GRAPH]) {   // fracture: crossing cells, then z = y + block responses
+      hipLaunchKernelGGL(mc::k_schur_apply, dim3(T.nblk[2][PART_GRAPH]), dim3(MC_BLOCK), 0,
+                         P->X.stream, T.parts, T.tiles[2][PART_GRAPH]);
+      hipLaunchKernelGGL(mc::k_schur_finish, dim3(T.nblk[1][PART_GRAPH]), dim3(MC_BLOCK), 0,
+                         P->X.stream, T.parts, T.tiles[1][PART_GRAPH]);
+    }
+  }
   else
     mc::launch_all(P->X.stream, T, 1, mc::k_precond<PREC_JACOBI, PART_GRID>,
                    mc::k_precond<PREC_JACOBI, PART_GRAPH>);
@@ -1812,6 +1989,7 @@ mc_status mc_get_info(const mc_problem* P, mc_info* info) {
   info->device_bytes = (int64_t)P->mem.bytes;
   info->grid_tiles = P->ncont ? P->cont[0].tiles : 0;
   info->n_chains = P->nchains;
+  info->n_crossing = P->ncont > P->n_omega ? P->cont[P->n_omega].K : 0;
   for (int c = 0; c < P->ncont && c < 3; ++c) {
     info->tiles[c] = P->cont[c].tiles;
     info->blocks[c][0] = P->cont[c].blocks[0];

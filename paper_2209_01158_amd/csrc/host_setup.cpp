@@ -159,19 +159,132 @@ std::vector<int> build_graph_tiles(const std::vector<int>& chain_ptr, int target
   return t;
 }
 
-std::vector<int> chain_prev_entry(int nf, const GraphCSR& g, const std::vector<int>& chain_ptr) {
-  std::vector<int> e(nf, -1);
+int count_crossing_cells(int nf, int ne, const int32_t* edges) {
+  std::vector<char> x(nf > 0 ? nf : 1, 0);
+  int K = 0;
+  for (int e = 0; e < ne; ++e) {
+    const int a = edges[2 * e], b = edges[2 * e + 1];
+    if (a - b == 1 || b - a == 1) continue;
+    if (!x[a]) x[a] = 1, ++K;
+    if (!x[b]) x[b] = 1, ++K;
+  }
+  return K;
+}
+
+SchurHost build_schur(int nf, const GraphCSR& g, const std::vector<int>& chain_ptr,
+                      const std::vector<int>& gtile, const double* diag, const double* val,
+                      int kmax) {
+  SchurHost H;
+  // conductance between l and l + 1 inside a chain (sum over parallel connections)
   std::vector<char> start(nf + 1, 0);
   for (size_t c = 0; c + 1 < chain_ptr.size(); ++c) start[chain_ptr[c]] = 1;
-  for (int l = 1; l < nf; ++l) {
-    if (start[l]) continue;
-    for (int j = g.rowptr[l]; j < g.rowptr[l + 1]; ++j)
-      if (g.col[j] == l - 1) {
-        e[l] = j;
-        break;
-      }
+  start[nf] = 1;
+  std::vector<double> link(nf, 0.0);
+  std::vector<int> xidx(nf, -1);
+  for (int l = 0; l < nf; ++l)
+    for (int j = g.rowptr[l]; j < g.rowptr[l + 1]; ++j) {
+      const int m = g.col[j];
+      if (m == l + 1 && !start[l + 1]) link[l] += val[j];
+      else if (m != l - 1 && m != l + 1) xidx[l] = 0;   // a crossing cell
+    }
+  for (int l = 0; l < nf; ++l)
+    if (xidx[l] == 0) H.K_all += 1;
+  const bool schur = H.K_all > 0 && H.K_all <= kmax;
+  int K = 0;
+  for (int l = 0; l < nf; ++l) {
+    if (schur && xidx[l] == 0) {
+      xidx[l] = K++;
+      H.xcells.push_back(l);
+    } else {
+      xidx[l] = -1;
+    }
   }
-  return e;
+  H.K = K;
+  H.dinv.assign(nf, 0.0);
+  H.cT.assign(nf, 0.0);
+  H.cl.assign(nf, 0.0);
+  H.cr.assign(nf, 0.0);
+  H.xl.assign(nf, -1);
+  H.xr.assign(nf, -1);
+  H.cxl.assign(K, 0.0);
+  H.cxr.assign(K, 0.0);
+  H.S.assign((size_t)K * K, 0.0);
+  auto Sref = [&](int r, int c) -> double& { return H.S[(size_t)c * K + r]; };
+  // A_XX
+  for (int k = 0; k < K; ++k) {
+    const int x = H.xcells[k];
+    Sref(k, k) += diag[x];
+    for (int j = g.rowptr[x]; j < g.rowptr[x + 1]; ++j) {
+      const int m = xidx[g.col[j]];
+      if (m >= 0) Sref(k, m) -= val[j];
+    }
+    H.cxl[k] = x > 0 && !start[x] ? link[x - 1] : 0.0;
+    H.cxr[k] = !start[x + 1] ? link[x] : 0.0;
+    H.xl[x] = k;
+    H.cl[x] = 1.0;
+  }
+  // sub-chain blocks: tridiagonal factor, responses, and their share of S
+  std::vector<double> u, v;
+  for (size_t c = 0; c + 1 < chain_ptr.size(); ++c) {
+    const int c0 = chain_ptr[c], c1 = chain_ptr[c + 1];
+    int a = c0;
+    while (a < c1) {
+      if (xidx[a] >= 0) {
+        ++a;
+        continue;
+      }
+      int b = a;
+      while (b + 1 < c1 && xidx[b + 1] < 0) ++b;
+      // factor of the block [a, b]: d_a = a_aa, d_l = a_ll - c^2 / d_{l-1}
+      H.cT[a] = 0.0;
+      H.dinv[a] = 1.0 / diag[a];
+      for (int l = a + 1; l <= b; ++l) {
+        H.cT[l] = link[l - 1];
+        H.dinv[l] = 1.0 / (diag[l] - H.cT[l] * H.cT[l] * H.dinv[l - 1]);
+      }
+      // T^-1 e_s by the same factor: forward u_l = (e_s + cT_l u_{l-1}) dinv_l, backward
+      // z_l = u_l + cT_{l+1} dinv_l z_{l+1}
+      auto col = [&](int s, std::vector<double>& z) {
+        z.assign(b - a + 1, 0.0);
+        double w = 0.0;
+        for (int l = a; l <= b; ++l) {
+          w = ((l == s ? 1.0 : 0.0) + (l > a ? H.cT[l] * w : 0.0)) * H.dinv[l];
+          z[l - a] = w;
+        }
+        for (int l = b - 1; l >= a; --l) z[l - a] += H.cT[l + 1] * H.dinv[l] * z[l + 1 - a];
+      };
+      const int kl = a > c0 ? xidx[a - 1] : -1;     // a block starts at a chain start or after X
+      const int kr = b + 1 < c1 ? xidx[b + 1] : -1;
+      const double clk = kl >= 0 ? link[a - 1] : 0.0, crk = kr >= 0 ? link[b] : 0.0;
+      if (kl >= 0) col(a, u);
+      if (kr >= 0) col(b, v);
+      for (int l = a; l <= b; ++l) {
+        if (kl >= 0) {
+          H.xl[l] = kl;
+          H.cl[l] = clk * u[l - a];
+        }
+        if (kr >= 0) {
+          H.xr[l] = kr;
+          H.cr[l] = crk * v[l - a];
+        }
+      }
+      if (kl >= 0) Sref(kl, kl) -= clk * clk * u[0];
+      if (kr >= 0) Sref(kr, kr) -= crk * crk * v[b - a];
+      if (kl >= 0 && kr >= 0) {
+        Sref(kl, kr) -= clk * crk * u[b - a];
+        Sref(kr, kl) -= clk * crk * u[b - a];
+      }
+      a = b + 1;
+    }
+  }
+  // crossing cells of every work tile (tiles are contiguous runs of whole chains)
+  const int nt = (int)gtile.size() - 1;
+  H.xtile.assign(nt + 1, 0);
+  for (int t = 0; t <= nt; ++t) {
+    const int l0 = chain_ptr[gtile[t]];
+    H.xtile[t] = (int)(std::lower_bound(H.xcells.begin(), H.xcells.end(), l0) - H.xcells.begin());
+  }
+  return H;
 }
 
 std::vector<int> xcd_order(int n, int nxcd) {

@@ -36,9 +36,38 @@ std::vector<int> build_chains(int nf, const GraphCSR& g);
 // `target` cells.  Returns chain boundaries of the tiles, [ntiles+1].
 std::vector<int> build_graph_tiles(const std::vector<int>& chain_ptr, int target);
 
-// For every fracture cell l that is not the first of its chain, the CSR entry of its
-// connection to l-1; -1 for chain starts.
-std::vector<int> chain_prev_entry(int nf, const GraphCSR& g, const std::vector<int>& chain_ptr);
+// Exact fracture solve by a Schur complement on the crossing cells.
+//
+// Cells with a connection to a cell other than their chain neighbours l-1, l+1 are the
+// crossing cells X (K of them); every other cell belongs to a sub-chain block I (a run of
+// a chain between crossing cells), whose matrix is tridiagonal.  With
+//   A = [A_II A_IX; A_XI A_XX],  S = A_XX - A_XI A_II^-1 A_IX  (K x K, SPD),
+// a solve A z = r is  y = A_II^-1 r_I  (y = 0 on X),  g = r_X - A_XI y,  z_X = S^-1 g,
+// z_I = y + A_II^-1 (-A_IX) z_X.  The last term is non-zero only on blocks next to a crossing
+// cell: z_l = y_l + cl_l z_X[xl_l] + cr_l z_X[xr_l], with cl, cr the responses of the block to
+// its left and right crossing neighbours.  Written so that a crossing cell x also fits:
+// y_x = 0, xl_x = its own index, cl_x = 1.
+struct SchurHost {
+  int K = 0;                       // crossing cells used (0 if none or more than kmax)
+  int K_all = 0;                   // crossing cells present
+  std::vector<int> xcells;         // [K] ascending
+  std::vector<double> dinv, cT;    // [nf] block factor: inverse pivots; coupling to l-1 (0 at block starts)
+  std::vector<double> cl, cr;      // [nf] responses to the left / right crossing neighbour
+  std::vector<int> xl, xr;         // [nf] their crossing indices, or -1
+  std::vector<double> cxl, cxr;    // [K] conductance of crossing cell k to its chain neighbours l-1, l+1
+  std::vector<int> xtile;          // [ntiles + 1] range of xcells in each fracture work tile
+  std::vector<double> S;           // [K * K] Schur complement, column-major
+};
+
+// diag: [nf] full diagonal of the fracture system; val: [2*ne] conductance of every CSR entry
+// of g.  Above kmax crossing cells no Schur complement is formed: the blocks are then the
+// whole chains and the crossing couplings are left out (an approximate inverse).
+SchurHost build_schur(int nf, const GraphCSR& g, const std::vector<int>& chain_ptr,
+                      const std::vector<int>& gtile, const double* diag, const double* val,
+                      int kmax);
+
+// Number of crossing cells of a connection list (cells joined to a cell other than l-1, l+1).
+int count_crossing_cells(int nf, int ne, const int32_t* edges);
 
 // Launch order of `n` work items such that hardware round-robin dispatch over `nxcd`
 // compute dies gives die j a contiguous range of items.  Entries of -1 are padding.

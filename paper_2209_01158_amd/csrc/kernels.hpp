@@ -189,6 +189,14 @@ __global__ void k_setup_graph(GraphSetup g) {
   g.F[l] = g.src ? g.src[l] * meas : 0.0;
 }
 
+// Copies the lower triangle of a column-major K x K matrix to its upper triangle.
+__global__ void k_symmetrize(double* __restrict__ a, int K) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)K * K) return;
+  const int r = (int)(idx % K), c = (int)(idx / K);
+  if (r < c) a[idx] = a[(long)r * K + c];
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long n) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) b[i] = (float)a[i];
@@ -267,32 +275,6 @@ __device__ __forceinline__ double graph_coupling(const PartD& P, int l, const VP
 // Grid blocks are the 64 x MC_TY tiles; fracture blocks are the chains (tridiagonal, so
 // IC(0) is their exact Cholesky factorization).
 // ------------------------------------------------------------------------------------
-struct ChainSetup {
-  int nchains;
-  const int* chain_ptr;
-  const int* cidx;     // CSR entry of (l, l-1), -1 at chain starts
-  const double* val;
-  const double* diag;
-  double* cT;
-  double* dinv;
-};
-
-__global__ void k_setup_chains(ChainSetup g) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.nchains) return;
-  const int l0 = g.chain_ptr[c], l1 = g.chain_ptr[c + 1];
-  double dprev = g.diag[l0];
-  g.cT[l0] = 0.0;
-  g.dinv[l0] = 1.0 / dprev;
-  for (int l = l0 + 1; l < l1; ++l) {
-    const double t = g.cidx[l] >= 0 ? g.val[g.cidx[l]] : 0.0;
-    const double d = g.diag[l] - t * t / dprev;
-    g.cT[l] = t;
-    g.dinv[l] = 1.0 / d;
-    dprev = d;
-  }
-}
-
 struct GridIC0Setup {
   int nx, ny, tiles_x, ntiles;
   const double* diag;
@@ -604,6 +586,9 @@ __device__ __forceinline__ void for_cells(const PartD& P, const Tile& t, const F
   }
 }
 
+// z = M^-1 r at cell i.  Jacobi: r / diag.  Block IC(0): the stored z; on a fracture graph
+// with crossing cells the stored vector is y = A_II^-1 r (0 on crossing cells) and the
+// crossing solution z_X enters through the responses of each block to its end cells.
 template <class T, int PREC>
 __device__ __forceinline__ T zval(const PartD& P, long i) {
   if (PREC == PREC_JACOBI) {
@@ -611,7 +596,28 @@ __device__ __forceinline__ T zval(const PartD& P, long i) {
     const T* d = pick<T>(P.diag, P.diag32);
     return r[i] / d[i];
   } else {
-    return ((const T*)P.z)[i];
+    T z = ((const T*)P.z)[i];
+    if (P.K > 0) {
+      const T* zX = (const T*)P.zX;
+      const int xl = P.xlr[2 * i], xr = P.xlr[2 * i + 1];
+      if (xl >= 0) z += pick<T>(P.cl, P.cl32)[i] * zX[xl];
+      if (xr >= 0) z += pick<T>(P.cr, P.cr32)[i] * zX[xr];
+    }
+    return z;
+  }
+}
+
+// g_k = r_x + c_(x,x-1) y_(x-1) + c_(x,x+1) y_(x+1) for the crossing cells x of a work tile
+// (their chain neighbours are in the same tile, and y vanishes on crossing cells).
+template <class T>
+__device__ __forceinline__ void schur_gather(const PartD& P, int tile, const T* r, const T* y) {
+  T* g = (T*)P.gX;
+  for (int k = P.xtile[tile] + (int)threadIdx.x; k < P.xtile[tile + 1]; k += MC_BLOCK) {
+    const int x = P.xcells[k];
+    T v = r[x];
+    if (P.cxl[k] != 0.0) v += (T)P.cxl[k] * y[x - 1];
+    if (P.cxr[k] != 0.0) v += (T)P.cxr[k] * y[x + 1];
+    g[k] = v;
   }
 }
 
@@ -739,8 +745,9 @@ __device__ __forceinline__ void residual_and_precond(const PartD& P, const Tile&
       for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
         chain_solve<T>(rs, z, dinv, cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
       __syncthreads();
+      if (P.K > 0) schur_gather<T>(P, tile, rs, z);
       for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
-        v[0] += (double)rs[l] * (double)z[l];
+        v[0] += (double)rs[l] * (double)z[l];   // (r_I, y_I); the Schur kernel adds g . z_X
         v[1] += (double)rs[l] * (double)rs[l];
       }
     }
@@ -1029,6 +1036,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
       for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
         chain_solve<T>(r, z, dinv, cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
       __syncthreads();
+      if (P.K > 0) schur_gather<T>(P, tile, (const T*)r, (const T*)z);
       for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
         o[0] += (double)r[l] * (double)z[l];
         o[1] += (double)r[l] * (double)r[l];
@@ -1200,11 +1208,77 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
       const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
       for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
         chain_solve<double>(r, z, P.fdinv, P.cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
+      __syncthreads();
+      if (P.K > 0) schur_gather<double>(P, tile, r, z);
     }
   } else {
     for_cells<KIND>(P, t, [&](int, int, long i) { z[i] = r[i] / P.diag[i]; },
                     [&](int l) { z[l] = r[l] / P.diag[l]; });
   }
+}
+
+// ------------------------------------------------------------------------------------
+// crossing cells of a fracture graph: z_X = S^-1 g (dense, symmetric), one workgroup per
+// MC_SCHUR_ROWS rows; in a PCG launch the partial g . z_X completes (r, z) in the update
+// slots that follow the graph update kernel's own.
+// ------------------------------------------------------------------------------------
+template <class T, bool PCG>
+__device__ __forceinline__ void schur_rows(const PartD& P, const Tile& t, double& gz) {
+  __shared__ T gs[MC_SCHUR_KMAX];
+  const int K = P.K;
+  const T* g = (const T*)P.gX;
+  for (int j = threadIdx.x; j < K; j += MC_BLOCK) gs[j] = g[j];
+  __syncthreads();
+  const gconst<T> Sv = gc(pick<T>(P.sinv, P.sinv32));
+  T* zX = (T*)P.zX;
+  const int lane = threadIdx.x & 63;
+  const int k1 = min(t.t1 * MC_SCHUR_ROWS, K);
+  for (int k = t.t0 * MC_SCHUR_ROWS + (int)(threadIdx.x >> 6); k < k1; k += 4) {
+    const long row = (long)k * K;
+    double acc = 0.0;
+    for (int j = lane; j < K; j += 64) acc += (double)Sv[row + j] * (double)gs[j];
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const T zk = (T)acc;
+      zX[k] = zk;
+      if (PCG) gz += (double)gs[k] * (double)zk;
+    }
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(MC_BLOCK) k_schur(const PartD* __restrict__ parts,
+                                                    const Tile* __restrict__ tiles,
+                                                    SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  SysState& S = sys[P.sys];
+  if (ld_flag(&S.done)) return;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  schur_rows<T, true>(P, t, v[0]);
+  write_slot<5>(S.partB, t.slot, v);
+}
+
+// boundary call z = M^-1 r: the crossing solution, then z = y + block responses in place
+__global__ void __launch_bounds__(MC_BLOCK) k_schur_apply(const PartD* __restrict__ parts,
+                                                          const Tile* __restrict__ tiles) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  double gz = 0.0;
+  schur_rows<double, false>(parts[t.part], t, gz);
+}
+
+__global__ void __launch_bounds__(MC_BLOCK) k_schur_finish(const PartD* __restrict__ parts,
+                                                           const Tile* __restrict__ tiles) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  if (P.K == 0) return;
+  double* z = (double*)P.z;
+  for_cells<PART_GRAPH>(P, t, [&](int, int, long) {}, [&](int l) {
+    z[l] = zval<double, PREC_BIC0>(P, l);
+  });
 }
 
 // Per-solve reset of the system records [s0, s1) (a kernel, so the sequence stays free of

@@ -74,7 +74,7 @@ class Report(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n_cont", C.c_int32), ("sizes", C.c_int32 * 3), ("device_bytes", C.c_int64),
                 ("grid_tiles", C.c_int32), ("n_chains", C.c_int32), ("tiles", C.c_int32 * 3),
-                ("blocks", (C.c_int32 * 2) * 3)]
+                ("blocks", (C.c_int32 * 2) * 3), ("n_crossing", C.c_int32)]
 
 
 _PROBLEM = C.c_void_p

@@ -39,6 +39,8 @@ CASES = {
     "three70": lambda: media.small_problem(n=70, seed=5, three=True, nseg=6, seg_len=(5, 40)),
     "tiny1": lambda: media.small_problem(n=1, seed=1, nseg=0, lognormal=False),
 }
+# a dense fracture network: hundreds of crossing cells on a 48 x 48 grid
+DENSE = lambda: media.small_problem(n=48, seed=13, nseg=40, seg_len=(10, 40))  # noqa: E731
 
 
 @pytest.fixture(scope="module", params=list(CASES))
@@ -161,28 +163,28 @@ def test_invalid_descriptor_rejected():
 from oracle import precond  # noqa: E402
 
 
-@pytest.mark.parametrize("name", ["ragged200", "three70", "c1"])
+@pytest.mark.parametrize("name", ["ragged200", "three70", "c1", "dense48"])
 def test_block_ic0_apply(name):
-    p = CASES[name]()
+    p = DENSE() if name == "dense48" else CASES[name]()
     asm = fv.assemble(p)
     rng = np.random.default_rng(4)
     with mcdec.Problem(p, precond="bic0") as g:
         for a in range(p.n_cont):
             K = schemes.continuum_matrix(asm, p.tau, a)
-            if a < p.n_omega:
-                facs = precond.block_precond(K, precond.grid_tile_blocks(p.nx, p.ny))
-            else:
-                facs = precond.block_precond(K, precond.chain_blocks(p.nf, p.edges),
-                                             tridiagonal=True)
             r = rng.standard_normal(p.sizes()[a])
             z = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
             g.apply_precond(a, T(r), z)
-            ref = precond.block_precond_apply(facs, r)
+            if a < p.n_omega:
+                facs = precond.block_precond(K, precond.grid_tile_blocks(p.nx, p.ny))
+                ref = precond.block_precond_apply(facs, r)
+                tol = 2e-6   # FP32 copies of the grid factor (about 6e-8 relative rounding)
+            else:
+                # fracture: chains cut at the crossing cells plus the crossing-cell Schur
+                # complement form an exact solve of the fracture system
+                ref = schemes.DirectSolver(K).solve(r)
+                tol = 1e-10
             err = rel(z.cpu().numpy(), ref)
-            print(name, a, err)
-            # grid blocks keep their factor and conductances as FP32 copies (about 6e-8
-            # relative rounding); the fracture chains use the FP64 factor
-            tol = 2e-6 if a < p.n_omega else 1e-12
+            print(name, a, err, g.info().n_crossing)
             assert err < tol, (name, a, err)
 
 
@@ -208,6 +210,27 @@ def test_chain_ic0_exact_without_crossings():
     with mcdec.Problem(p, precond="bic0", tol=1e-12) as g:
         rep = g.step(1)
     assert rep["iters"][-1] <= 1, rep
+
+
+@pytest.mark.parametrize("name", ["ragged200", "c1", "dense48"])
+def test_fracture_solve_exact_with_crossings(name):
+    """With crossing cells the fracture preconditioner is the exact inverse: the fracture
+    PCG stops after at most two iterations, in FP64 and inside FP32 refinement; the
+    trajectory still matches the oracle."""
+    p = DENSE() if name == "dense48" else CASES[name]()
+    with mcdec.Problem(p, precond="bic0", tol=1e-12) as g:
+        assert g.info().n_crossing > 0
+        for _ in range(3):
+            rep = g.step(1)
+            assert rep["iters"][-1] <= 2, rep
+    with mcdec.Problem(p, precond="bic0", precision="mixed", outer_tol=1e-11,
+                       inner_tol=1e-6) as g:
+        for _ in range(3):
+            rep = g.step(1)
+        print(rep)
+        assert rep["outer"][-1] <= 3 and rep["iters"][-1] <= 2 * rep["outer"][-1] + 2, rep
+        ref = schemes.run(p, "D", 3, keep="last")
+        assert rel(g.get_states(), ref) < 1e-8
 
 
 @pytest.mark.parametrize("name", ["ragged200", "three70"])

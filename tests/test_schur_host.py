@@ -1,0 +1,25 @@
+"""Host construction of the exact fracture solve (Schur complement on the crossing cells):
+checked against dense Gaussian elimination on random fracture graphs by a C++ self-test built
+with g++ (AddressSanitizer and UBSan when available).  No GPU."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = [os.path.join(ROOT, "tests", "schur_selftest.cpp"),
+       os.path.join(ROOT, "paper_2209_01158_amd", "csrc", "host_setup.cpp")]
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_schur_host_selftest(tmp_path):
+    exe = str(tmp_path / "schur")
+    base = ["g++", "-std=c++17", "-O1", "-g", "-I", os.path.join(ROOT, "include")]
+    res = subprocess.run(base + ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"] +
+                         SRC + ["-o", exe], capture_output=True, text=True)
+    if res.returncode != 0:
+        res = subprocess.run(base + SRC + ["-o", exe], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert run.returncode == 0 and run.stdout.strip().endswith("OK"), run.stdout + run.stderr
