@@ -53,15 +53,14 @@ DEFAULTS = {
 # HBM bytes per dispatch of the grid PCG kernels, from two rocprofv3 counter passes
 # (FETCH_SIZE, then WRITE_SIZE) of `bench.py --steps 2 --warmup 0 --no-cpu --no-coupled
 # --calibrate-copy 4096`, each scaled by what the same counter reads for a 2 GiB sum (read
-# factor 1.9999) and a 2 GiB fill (write factor 0.9999).  Valid only for the kernel sources
+# factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "bic0", "A"): {"sources": "7be7f8b36faa832f", "fetch_kib": 84047.2,
-                          "write_kib": 65600.4, "read_factor": 1.9999, "write_factor": 0.9999},
-    ("C2", "bic0", "B"): {"sources": "7be7f8b36faa832f", "fetch_kib": 90328.5,
-                          "write_kib": 98320.0, "read_factor": 1.9999, "write_factor": 0.9999},
+    ("C2", "bic0", "A"): {"sources": "f864dccc3e74b56a", "fetch_kib": 83496.2,
+                          "write_kib": 65604.0, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "bic0", "B"): {"sources": "f864dccc3e74b56a", "fetch_kib": 90336.7,
+                          "write_kib": 98320.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
-
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
