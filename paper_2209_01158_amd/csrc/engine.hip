@@ -347,6 +347,7 @@ static bool exec_sys_capacity(Exec& X, int n) {
     throw Error{MC_ENOMEM, "hipMalloc of the system records failed"};
   }
   HIPCHK(hipHostMalloc((void**)&X.h_sys, cap * sizeof(SysState), hipHostMallocDefault));
+  std::memset(X.h_sys, 0, cap * sizeof(SysState));
   X.sys_cap = cap;
   return true;
 }
@@ -1089,6 +1090,19 @@ static int next_chunk(const Group& G) {
   return std::max(2, std::min(K, 256));
 }
 
+// First chunk of a solve: nine tenths of the iterations the group's slowest system took in
+// its previous solve (consecutive time layers need nearly the same number), at least 8, so
+// that most solves need one or two host polls; a chunk that overshoots convergence costs
+// only launches whose workgroups return at once.
+static int first_chunk(const Exec& X, const Group& G) {
+  int prev = 0;
+  for (int k = 0; k < G.s1 - G.s0; ++k) {
+    const int it = G.hbuf[k].iter;   // last values polled for these records (any before use)
+    if (it > 0 && it <= X.opt.max_iter) prev = std::max(prev, it);
+  }
+  return std::max(8, std::min(256, (int)(0.9 * prev)));
+}
+
 static bool all_done(const Group& G, bool outer) {
   for (int k = 0; k < G.s1 - G.s0; ++k)
     if (!(outer ? G.hbuf[k].outer_done : G.hbuf[k].done)) return false;
@@ -1118,7 +1132,7 @@ static void advance_t(Exec& X, Group& G) {
       launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
       if (G.kinds & 2) launch_schur<double>(X, *G.T, G.s);
       G.k = 0;
-      G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
+      G.K = X.opt.check_every > 0 ? X.opt.check_every : first_chunk(X, G);
       G.phase = 1;
     } else {
       if (all_done(G, false)) {
