@@ -6,8 +6,8 @@ arithmetic of the method: transmissibilities, storage terms, transfer assembly a
 solve are computed separately by the oracle and by the HIP library from these arrays.
 """
 from .problem import OmegaContinuum, Problem, BC_NOFLOW, BC_DIRICHLET
-from .configs import (config_problem, CONFIG_NAMES, small_problem, c4_problems,
-                      c5_trace, lognormal_field)
+from .configs import (config_problem, CONFIG_NAMES, small_problem, rect_problem,
+                      c4_problems, c5_trace, lognormal_field)
 
 __all__ = ["OmegaContinuum", "Problem", "BC_NOFLOW", "BC_DIRICHLET", "config_problem",
-           "CONFIG_NAMES", "small_problem", "c4_problems", "c5_trace", "lognormal_field"]
+           "CONFIG_NAMES", "small_problem", "rect_problem", "c4_problems", "c5_trace", "lognormal_field"]

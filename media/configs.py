@@ -286,6 +286,26 @@ def c5_problem(entry) -> Problem:
     return _family_member(rng, n, three, None, K_F / contrast, nseg, ns, "C5")
 
 
+def rect_problem(nx: int, ny: int, seed: int = 7, lognormal: bool = True,
+                 sigma_log: float = 1.5, tau: float = 1e-3, nsteps: int = 3) -> Problem:
+    """A grid-only (no fracture) two-continuum problem on an nx x ny grid with h = 1/nx:
+    lognormal or constant matrix permeability, the C1 boundary conditions."""
+    rng = np.random.default_rng(seed)
+    if lognormal:
+        om = OmegaContinuum(c=1.0, k=lognormal_field(nx, rng, sigma_log=sigma_log, ny=ny))
+    else:
+        om = OmegaContinuum(c=1.0, k_const=1e-4)
+    bct, bcv = _bc_c1()
+    h = 1.0 / nx
+    p = Problem(nx=nx, ny=ny, h=h, omega=[om], sigma_omega=0.0,
+                sigma_f=np.zeros((1, 0)), bc_type=bct, bc_value=bcv, src=None, p0=None,
+                tau=tau, nsteps=nsteps,
+                meta=dict(name=f"rect{nx}x{ny}", precond="jacobi", tol=1e-12, precision="fp64",
+                          seg_id=np.zeros(0, np.int32)))
+    p.check()
+    return p
+
+
 def small_problem(n: int = 40, seed: int = 7, three: bool = False, nseg: int = 6,
                   lognormal: bool = True, axis: bool = False, tau: float = 1e-3,
                   nsteps: int = 5, sigma_log: float = 1.5, seg_len=(5, 30)) -> Problem:

@@ -104,3 +104,57 @@ def block_precond_apply(facs, r: np.ndarray) -> np.ndarray:
     for idx, rows in facs:
         z[idx] = ilu0_solve(rows, r[idx])
     return z
+
+
+# ------------------------------------------------------------------------------------
+# Multigrid V-cycle (the GPU path's MC_MG option).  Not from the paper: a second
+# preconditioner for the same SPD continuum systems, stated here by its textbook definition
+# (aggregation two-grid / V-cycle with a symmetric pre- and post-smoothing, e.g. Saad,
+# Iterative Methods for Sparse Linear Systems, multigrid chapter; Vanek, Mandel and Brezina
+# on aggregation) so that the GPU cycle can be compared with it.
+# ------------------------------------------------------------------------------------
+def aggregate_prolongator(nx: int, ny: int):
+    """Piecewise-constant prolongation over 2 x 2 cell aggregates (1-wide at an odd last
+    column or row): column J of P is the indicator of aggregate J, numbered row-major on the
+    coarse (ceil(nx/2) x ceil(ny/2)) grid.  Returns (P, cnx, cny)."""
+    cnx, cny = (nx + 1) // 2, (ny + 1) // 2
+    ys, xs = np.divmod(np.arange(nx * ny), nx)
+    J = (ys // 2) * cnx + xs // 2
+    P = sp.csr_matrix((np.ones(nx * ny), (np.arange(nx * ny), J)), shape=(nx * ny, cnx * cny))
+    return P, cnx, cny
+
+
+def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256):
+    """Levels of the V-cycle of the grid operator K (nx x ny cells, row-major): Galerkin
+    coarse operators P^T K P until at most `coarse` cells remain; block IC(0) factors on
+    64 x 16 blocks on every level above the coarsest; the coarsest level's dense inverse.
+    A grid of at most `coarse` cells has one level and the cycle is plain block IC(0)."""
+    K = sp.csr_matrix(K)
+    levels = [dict(K=K, nx=nx, ny=ny, facs=block_precond(K, grid_tile_blocks(nx, ny)))]
+    while nx * ny > coarse:
+        P, nx, ny = aggregate_prolongator(nx, ny)
+        levels[-1]["P"] = P
+        K = sp.csr_matrix(P.T @ K @ P)
+        lev = dict(K=K, nx=nx, ny=ny)
+        if nx * ny > coarse:
+            lev["facs"] = block_precond(K, grid_tile_blocks(nx, ny))
+        else:
+            lev["inv"] = np.linalg.inv(K.toarray())
+        levels.append(lev)
+    return levels
+
+
+def vcycle_apply(levels, r: np.ndarray, l: int = 0) -> np.ndarray:
+    """z = V r: pre-smoothing z_p = M^-1 r, coarse correction with the restricted residual
+    P^T (r - K z_p), post-smoothing with the same M (so V is symmetric)."""
+    L = levels[l]
+    r = np.asarray(r, np.float64)
+    if "inv" in L:
+        return L["inv"] @ r
+    if "P" not in L:
+        return block_precond_apply(L["facs"], r)
+    K, P = L["K"], L["P"]
+    zp = block_precond_apply(L["facs"], r)
+    e = vcycle_apply(levels, P.T @ (r - K @ zp), l + 1)
+    z1 = zp + P @ e
+    return z1 + block_precond_apply(L["facs"], r - K @ z1)

@@ -374,3 +374,87 @@ def test_block_partitions():
     assert b[0][:3].tolist() == [0, 1, 2] and b[0][64] == 130
     ch = precond.chain_blocks(6, np.array([[0, 1], [1, 2], [3, 4], [2, 5]]))
     assert [c.tolist() for c in ch] == [[0, 1, 2], [3, 4], [5]]
+
+
+# ------------------------------------------------------------------------------------
+# multigrid V-cycle (the GPU path's second preconditioner option)
+# ------------------------------------------------------------------------------------
+def test_aggregation_coarse_operator_by_counting():
+    """P^T K P on a homogeneous 9 x 7 grid, against counts done by hand: a coarse face
+    conductance is the fine conductance times the fine faces it covers (2, or 1 along the
+    1-wide last column / row of an odd grid), and a coarse row sum equals the sum of the
+    aggregate's fine row sums (P^T K 1 = P^T (K 1))."""
+    p = media.rect_problem(9, 7, seed=2, lognormal=False)
+    K = schemes.continuum_matrix(fv.assemble(p), p.tau, 0).tocsr()
+    nx, ny = p.nx, p.ny
+    assert K.shape[0] == nx * ny
+    t = -K[0, 1]
+    assert t > 0 and np.isclose(-K[0, nx], t)
+    P, cnx, cny = precond.aggregate_prolongator(nx, ny)
+    assert (cnx, cny) == (5, 4)
+    Kc = (P.T @ K @ P).toarray()
+    for Y in range(cny):
+        for X in range(cnx):
+            I = Y * cnx + X
+            rows = 2 if 2 * Y + 1 < ny else 1
+            cols = 2 if 2 * X + 1 < nx else 1
+            if X + 1 < cnx:
+                assert np.isclose(-Kc[I, I + 1], rows * t)
+            if Y + 1 < cny:
+                assert np.isclose(-Kc[I, I + cnx], cols * t)
+            nb = [J for J in range(cnx * cny) if J != I and Kc[I, J] != 0]
+            assert len(nb) == (X > 0) + (X + 1 < cnx) + (Y > 0) + (Y + 1 < cny)
+    fine_rowsum = np.asarray(K.sum(axis=1)).ravel()
+    np.testing.assert_allclose(Kc.sum(axis=1), P.T @ fine_rowsum, rtol=1e-12)
+
+
+def _dense_inverse_of(apply, n):
+    return np.column_stack([apply(e) for e in np.eye(n)])
+
+
+def test_two_grid_cycle_error_propagation():
+    """Two levels (20 x 18 cells, coarse 10 x 9 solved exactly): the cycle equals
+    (I - E) K^-1 with E = (I - M^-1 K)(I - P Kc^-1 P^T K)(I - M^-1 K), the product of the
+    smoothing and coarse-correction error propagators; V is symmetric and V K has its
+    spectrum in (0, 1]."""
+    p = media.rect_problem(20, 18, seed=9)
+    asm = fv.assemble(p)
+    K = schemes.continuum_matrix(asm, p.tau, 0).toarray()
+    n = K.shape[0]
+    assert n == 360
+    lev = precond.vcycle_setup(K, p.nx, p.ny)
+    assert len(lev) == 2 and "inv" in lev[1]
+    Minv = _dense_inverse_of(lambda e: precond.block_precond_apply(lev[0]["facs"], e), n)
+    P = lev[0]["P"].toarray()
+    Kc = P.T @ K @ P
+    I = np.eye(n)
+    S = I - Minv @ K
+    Cc = I - P @ np.linalg.solve(Kc, P.T @ K)
+    E = S @ Cc @ S
+    Vref = (I - E) @ np.linalg.inv(K)
+    V = _dense_inverse_of(lambda e: precond.vcycle_apply(lev, e), n)
+    assert np.abs(V - Vref).max() < 1e-10 * np.abs(Vref).max()
+    assert np.abs(V - V.T).max() < 1e-12 * np.abs(V).max()
+    ev = np.linalg.eigvals(V @ K).real
+    assert ev.min() > 0 and ev.max() < 1 + 1e-10
+
+
+def test_three_level_cycle_symmetric_positive():
+    """Three levels (36 x 32 -> 18 x 16 -> 9 x 8): (r1, V r2) = (r2, V r1), (r, V r) > 0."""
+    p = media.rect_problem(36, 32, seed=4)
+    K = schemes.continuum_matrix(fv.assemble(p), p.tau, 0)
+    lev = precond.vcycle_setup(K, p.nx, p.ny)
+    assert [(l["nx"], l["ny"]) for l in lev] == [(36, 32), (18, 16), (9, 8)]
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        a, b = rng.standard_normal((2, 36 * 32))
+        va, vb = precond.vcycle_apply(lev, a), precond.vcycle_apply(lev, b)
+        assert abs(a @ vb - b @ va) < 1e-12 * np.linalg.norm(a) * np.linalg.norm(vb)
+        assert a @ va > 0
+    p2 = media.rect_problem(16, 16, seed=4)
+    K2 = schemes.continuum_matrix(fv.assemble(p2), p2.tau, 0)
+    lev2 = precond.vcycle_setup(K2, 16, 16)   # 256 cells: plain block IC(0)
+    assert len(lev2) == 1
+    r = rng.standard_normal(256)
+    np.testing.assert_array_equal(precond.vcycle_apply(lev2, r),
+                                  precond.block_precond_apply(lev2[0]["facs"], r))
