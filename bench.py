@@ -91,7 +91,7 @@ def grid_bytes_per_cell(kernel, precision, precond, has_t):
     w = 4 if precision == "mixed" else 8
     if kernel == "A":
         return (3 + (2 if has_t else 0) + 2) * w
-    if precond == "bic0":
+    if precond in ("bic0", "mg"):   # mg: the same sweep is the finest pre-smoothing
         return 7 * w + 3 * 4
     return 7 * w
 
@@ -109,7 +109,7 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
         per_launch = bytes_total[k] / max(issued, 1)
         achieved = per_launch / avg_s / 1e9
         tp = "float" if precision == "mixed" else "double"
-        pn = {"bic0": "BIC0", "jacobi": "JACOBI"}[precond]
+        pn = {"bic0": "BIC0", "mg": "BIC0", "jacobi": "JACOBI"}[precond]
         name = (f"k_pcg_{k}<{tp},{pn},GRID> " +
                 ("(p = z + beta p; q = A p; partial p.q)" if k == "A" else
                  "(x += alpha p; r -= alpha q; z = M^-1 r; partial r.z, r.r)"))
@@ -546,7 +546,7 @@ def main():
     ap.add_argument("--workload", default="C2", choices=sorted(DEFAULTS))
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precond", default=None, choices=["jacobi", "bic0"])
+    ap.add_argument("--precond", default=None, choices=["jacobi", "bic0", "mg"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--coupled-steps", type=int, default=None)

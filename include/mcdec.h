@@ -71,13 +71,18 @@ typedef enum {
 
 typedef enum {
   MC_JACOBI = 0, /* z = r / diag                                                               */
-  MC_BIC0 = 1    /* grid: block incomplete Cholesky, zero fill, on 64-column x 16-row blocks
+  MC_BIC0 = 1,   /* grid: block incomplete Cholesky, zero fill, on 64-column x 16-row blocks
                     (IC(0) in natural order inside a block, couplings between blocks dropped);
                     fracture graph: an exact solve -- its chains cut at the crossing cells
                     (cells joined to cells other than their chain neighbours) are tridiagonal
                     blocks solved exactly, and the crossing cells are solved through the
                     inverse of their Schur complement (formed once at setup, up to 6144
                     crossing cells; beyond that the crossing couplings are dropped)            */
+  MC_MG = 2      /* grid: one symmetric multigrid V-cycle -- 2 x 2 cell aggregates, coarse
+                    operators P^T A P (again 5-point conductance stencils), block IC(0) as the
+                    pre- and post-smoother on every level, the coarsest level (at most 256
+                    cells) solved by its dense inverse; fracture graph: as MC_BIC0.  Grids of
+                    at most 256 cells use plain block IC(0)                                     */
 } mc_precond;
 
 /* One continuum on the Omega grid. */
@@ -153,7 +158,9 @@ typedef struct {
   int32_t blocks[3][2];  /* workgroups per launch per continuum: [0] operator kernel,
                             [1] update / residual kernels (equal to its partial-sum slots)      */
   int32_t n_crossing;    /* fracture cells solved through the crossing-cell Schur complement
-                            (MC_BIC0; 0 with Jacobi, without crossings, or beyond 6144)         */
+                            (MC_BIC0 / MC_MG; 0 with Jacobi, without crossings, or beyond 6144) */
+  int32_t mg_levels[3];  /* (MC_MG) coarse levels of each grid continuum's V-cycle, else 0;
+                            the last one holds at most 256 cells                               */
 } mc_info;
 
 typedef struct mc_problem mc_problem;

@@ -19,6 +19,7 @@
 #define MC_ICB (MC_TY / MC_ICY)  // IC(0) blocks per grid tile
 #define MC_SCHUR_ROWS 16       // rows of the crossing-cell inverse per workgroup
 #define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
+#define MC_MG_COARSE 256       // multigrid levels stop at this many cells (dense inverse there)
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };
 enum { PREC_JACOBI = 0, PREC_BIC0 = 1 };
@@ -116,6 +117,18 @@ struct PartD {
   const float* sinv32;
   void* gX;                // [K] crossing right-hand side g = r_X - A_XI y (launch precision)
   void* zX;                // [K] crossing solution S^-1 g (launch precision)
+  // (grid) multigrid V-cycle: this part is level mg_level of a continuum; coarser and finer
+  // levels are other parts of the same table
+  int mg_level;            // 0: the continuum itself
+  int mg_next;             // part of the next coarser level, -1 at the coarsest (or no V-cycle)
+  int mg_prev;             // part of the next finer level (levels >= 1)
+  int mg_slot;             // (level 0) first partial slot of the final smoothing
+  const double* mg_inv;    // (coarsest) dense inverse of the level operator [n*n]
+  const float* mg_inv32;
+  void* mg_r;              // right-hand side of the level (level 0: the PCG residual r)
+  void* mg_zp;             // level solution after pre-smoothing
+  void* mg_z;              // level solution after the coarse correction and post-smoothing
+                           // (level 0: the PCG vector z)
   // transfer structure
   const int* hptr;         // (grid) [n+1] fracture cells hosted per cell (CSR)
   const int* hidx;         // (grid) [nf]   their fracture indices

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -41,6 +42,9 @@ struct Error {
 static thread_local std::string g_thread_error = "";
 
 static inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+// Block IC(0) factors (grid) and the exact fracture solve are used by MC_BIC0 and MC_MG.
+static inline bool ic_precond(int p) { return p == MC_BIC0 || p == MC_MG; }
 
 static bool env_flag(const char* name, bool dflt) {
   const char* v = std::getenv(name);
@@ -136,6 +140,13 @@ struct Table {
   int nparts = 0;
   std::vector<PartD> hparts;
   std::vector<int> htil;                      // tiles and the three workgroup counts per part
+  // multigrid tile lists per level: [0] restrict into the level, [1] smoothing, [2] dense
+  // coarsest solve, [3] post-smoothing (level 0: the final one, writing partial slots)
+  struct List {
+    Tile* t = nullptr;
+    int n = 0, cap = 0;
+  };
+  std::vector<std::array<List, 4>> mg;
   std::map<long, hipGraphExec_t> graphs;
 };
 
@@ -181,7 +192,7 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
         const PartD& q = parts[pi];
         if (q.kind != kind) continue;
         const int nb = til[pi].blocks[fam];
-        if (nb == 0) continue;
+        if (nb == 0 || q.mg_level > 0 || (fam == 2 && kind == PART_GRID)) continue;
         const int nt = fam == 2 ? nb : til[pi].tiles;
         const int slot0 = fam == 0 ? q.slot0A : (fam == 1 ? q.slot0B : q.slotS);
         // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die
@@ -206,6 +217,50 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
                               hipMemcpyHostToDevice, s));
       T.nblk[fam][kind] = (int)tiles.size();
     }
+  // multigrid lists
+  int L = 0;
+  for (auto& q : parts)
+    if (q.kind == PART_GRID && (q.mg_next >= 0 || q.mg_level > 0)) L = std::max(L, q.mg_level + 1);
+  if ((int)T.mg.size() < L) T.mg.resize(L);
+  std::vector<std::vector<Tile>> mgv(4 * std::max(L, 1));
+  for (int pi = 0; pi < (int)parts.size(); ++pi) {
+    const PartD& q = parts[pi];
+    if (q.kind != PART_GRID || (q.mg_next < 0 && q.mg_level == 0)) continue;
+    const int l = q.mg_level;
+    const int nt = (int)(cdiv(q.nx, MC_TX) * cdiv(q.ny, MC_TY));
+    auto add = [&](int op, int nb, int ntile, int slot0) {
+      std::vector<Tile>& v = mgv[4 * l + op];
+      for (int b = 0; b < nb; ++b)
+        v.push_back(Tile{pi, slot0 + b, (int)((long)b * ntile / nb), (int)((long)(b + 1) * ntile / nb)});
+    };
+    if (l > 0) {                                     // restrict into l: the finer level's tiles
+      if (q.mg_prev < 0 || q.mg_prev >= (int)parts.size())
+        throw Error{MC_EDEVICE, "multigrid level without a finer level"};
+      const PartD& f = parts[q.mg_prev];
+      const int ntf = (int)(cdiv(f.nx, MC_TX) * cdiv(f.ny, MC_TY));
+      add(0, ntf, ntf, 0);
+    }
+    if (l > 0 && q.mg_next >= 0) add(1, (int)cdiv(nt, 2), nt, 0);         // smoothing
+    if (l > 0 && q.mg_next < 0) add(2, (int)cdiv(q.n, MC_SCHUR_ROWS), (int)cdiv(q.n, MC_SCHUR_ROWS), 0);
+    if (q.mg_next >= 0) {                                                  // post-smoothing
+      if (l == 0) add(3, til[pi].blocks[1], nt, q.mg_slot);
+      else add(3, (int)cdiv(nt, 2), nt, 0);
+    }
+  }
+  for (int l = 0; l < L; ++l)
+    for (int op = 0; op < 4; ++op) {
+      Table::List& li = T.mg[l][op];
+      const std::vector<Tile>& v = mgv[4 * l + op];
+      if (!v.empty() && (!li.t || li.cap < (int)v.size())) {
+        li.cap = (int)v.size() + 8;
+        li.t = M.alloc<Tile>(li.cap);
+      }
+      if (!v.empty())
+        HIPCHK(hipMemcpyAsync(li.t, v.data(), v.size() * sizeof(Tile), hipMemcpyHostToDevice, s));
+      li.n = (int)v.size();
+    }
+  for (int l = L; l < (int)T.mg.size(); ++l)
+    for (auto& li : T.mg[l]) li.n = 0;
   HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
   T.nparts = (int)parts.size();
   T.hparts = std::move(parts);
@@ -217,6 +272,19 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     T.htil.push_back(t.blocks[2]);
   }
 }
+
+// A coarse level of a grid continuum's V-cycle (level 0 is the continuum itself).
+struct MgLevel {
+  int nx = 0, ny = 0, tiles = 0;
+  long n = 0;
+  bool coarsest = false;
+  double *diag = nullptr, *tx = nullptr, *ty = nullptr, *fdinv = nullptr;
+  float *diag32 = nullptr, *tx32 = nullptr, *ty32 = nullptr, *fdinv32 = nullptr;
+  double *r = nullptr, *zp = nullptr, *z = nullptr;
+  float *r32 = nullptr, *zp32 = nullptr, *z32 = nullptr;
+  double* inv = nullptr;   // coarsest: dense inverse of the level operator
+  float* inv32 = nullptr;
+};
 
 struct Cont {  // one continuum
   int kind;    // PART_GRID / PART_GRAPH
@@ -239,6 +307,11 @@ struct Cont {  // one continuum
   float *cl32 = nullptr, *cr32 = nullptr, *sinv32 = nullptr;
   double *gX = nullptr, *zX = nullptr;
   float *gX32 = nullptr, *zX32 = nullptr;
+  // (grid) multigrid levels 1.. and the finest level's pre-smoothed solution
+  std::vector<MgLevel> mg;
+  bool mg_on = false;
+  double* zpre = nullptr;
+  float* zpre32 = nullptr;
   // state and PCG vectors
   double* ps[2] = {nullptr, nullptr};
   double *b = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *z = nullptr;
@@ -486,6 +559,11 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.sinv32 = C.sinv32;
   q.gX = fp32 ? (void*)C.gX32 : (void*)C.gX;
   q.zX = fp32 ? (void*)C.zX32 : (void*)C.zX;
+  q.mg_level = 0;
+  q.mg_next = -1;   // set by add_mg_levels when the continuum has a V-cycle
+  q.mg_prev = -1;
+  q.mg_slot = slot0B + C.blocks[1];
+  q.mg_zp = fp32 ? (void*)C.zpre32 : (void*)C.zpre;
   if (C.kind == PART_GRID) {
     q.hptr = P->nf ? P->hptr : nullptr;
     q.hidx = P->hidx;
@@ -533,15 +611,66 @@ static Table& upload_table(mc_problem* P, const std::string& key, std::vector<Pa
   return T;
 }
 
+// Appends the coarse levels of the V-cycle of grid part parts[i] (a continuum of P) and
+// links them to it (links are launch-table indices: vector index + base); nothing when the
+// option is off or the grid has no coarse level.
+static void add_mg_levels(mc_problem* P, std::vector<PartD>& parts, int i, bool fp32,
+                          int base = 0) {
+  const Cont& C = P->cont[parts[i].cont];
+  if (P->X.opt.precond != MC_MG || C.kind != PART_GRID || !C.mg_on) return;
+  int prev = i;
+  for (size_t l = 0; l < C.mg.size(); ++l) {
+    const MgLevel& L = C.mg[l];
+    PartD q;
+    std::memset(&q, 0, sizeof(q));
+    q.kind = PART_GRID;
+    q.sys = parts[i].sys;
+    q.cont = parts[i].cont;
+    q.n = (int)L.n;
+    q.nx = L.nx;
+    q.ny = L.ny;
+    q.tiles_x = (int)cdiv(L.nx, MC_TX);
+    q.has_t = 1;
+    q.other = -1;
+    q.frac = -1;
+    q.omg[0] = q.omg[1] = -1;
+    q.diag = L.diag;
+    q.tx = L.tx;
+    q.ty = L.ty;
+    q.diag32 = L.diag32;
+    q.tx32 = L.tx32;
+    q.ty32 = L.ty32;
+    q.fdinv = L.fdinv;
+    q.fdinv32 = L.fdinv32;
+    q.mg_level = (int)l + 1;
+    q.mg_prev = base + prev;
+    q.mg_next = -1;
+    q.mg_inv = L.inv;
+    q.mg_inv32 = L.inv32;
+    q.mg_r = fp32 ? (void*)L.r32 : (void*)L.r;
+    q.mg_zp = fp32 ? (void*)L.zp32 : (void*)L.zp;
+    q.mg_z = fp32 ? (void*)L.z32 : (void*)L.z;
+    const int idx = (int)parts.size();
+    parts[prev].mg_next = base + idx;
+    parts.push_back(q);
+    prev = idx;
+  }
+}
+
+// Parts of the decoupled systems of continua `conts` (system index = continuum index), with
+// the V-cycle levels appended after them unless `with_mg` is false.
 static std::vector<PartD> decoupled_parts(mc_problem* P, const std::vector<int>& conts,
-                                          bool fp32) {
+                                          bool fp32, bool with_mg = true) {
   std::vector<PartD> parts;
   for (int c : conts) parts.push_back(base_part(P, c, c, 0, 0, fp32));
+  if (with_mg)
+    for (int i = 0, n = (int)parts.size(); i < n; ++i) add_mg_levels(P, parts, i, fp32);
   return parts;
 }
 
-// Parts of the coupled system `sysI` of a problem; cross-part references are indices into
-// the returned vector plus `base` (the position of its first part in the launch table).
+// Parts of the coupled system `sysI` of a problem (the continua, then any V-cycle levels);
+// cross-part references are indices into the returned vector plus `base` (the position of
+// its first part in the launch table).
 static std::vector<PartD> coupled_parts(mc_problem* P, int sysI, int base) {
   std::vector<PartD> parts;
   int slotA = 0, slotB = 0;
@@ -561,6 +690,7 @@ static std::vector<PartD> coupled_parts(mc_problem* P, int sysI, int base) {
       parts[c].omg[1] = P->n_omega > 1 ? base + 1 : -1;
     }
   }
+  for (int c = 0; c < P->ncont; ++c) add_mg_levels(P, parts, c, false, base);
   return parts;
 }
 
@@ -650,6 +780,86 @@ static void setup_fracture_solve(mc_problem* P, Cont& C) {
   HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
 }
 
+// Levels of the V-cycle of grid continuum C (option MC_MG): 2 x 2 aggregation until at most
+// MC_MG_COARSE cells remain; Galerkin coarse operators, their block IC(0) factors (with the
+// FP32 copies the sweeps read) and the dense inverse of the coarsest operator.  Arrays are
+// allocated on the first call and refilled on later ones.
+static void setup_multigrid(mc_problem* P, Cont& C) {
+  hipStream_t s = P->X.stream;
+  DevArena& M = P->mem;
+  const bool mixed = P->X.opt.precision == MC_MIXED;
+  auto cv = [&](const double* a, float*& b, long n) {
+    if (!b) b = M.alloc<float>(n);
+    hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, s, a, b, n);
+  };
+  int nx = P->d.nx, ny = P->d.ny;
+  const double *fd = C.diag, *ftx = C.tx, *fty = C.ty;
+  size_t l = 0;
+  while ((long)nx * ny > MC_MG_COARSE) {
+    const int cnx = (nx + 1) / 2, cny = (ny + 1) / 2;
+    if (C.mg.size() <= l) C.mg.emplace_back();
+    MgLevel& L = C.mg[l];
+    L.nx = cnx;
+    L.ny = cny;
+    L.n = (long)cnx * cny;
+    L.tiles = (int)(cdiv(cnx, MC_TX) * cdiv(cny, MC_TY));
+    L.coarsest = L.n <= MC_MG_COARSE;
+    if (!L.diag) {
+      L.diag = M.alloc<double>(L.n);
+      L.tx = M.alloc<double>(L.n);
+      L.ty = M.alloc<double>(L.n);
+      L.fdinv = M.alloc<double>(L.n);
+      L.r = M.alloc<double>(L.n);
+      L.zp = M.alloc<double>(L.n);
+      L.z = M.alloc<double>(L.n);
+    }
+    if (mixed && !L.r32) {
+      L.r32 = M.alloc<float>(L.n);
+      L.zp32 = M.alloc<float>(L.n);
+      L.z32 = M.alloc<float>(L.n);
+    }
+    CoarsenSetup g{nx, ny, cnx, cny, fd, ftx, fty, L.diag, L.tx, L.ty};
+    hipLaunchKernelGGL(k_mg_coarsen, dim3(cdiv(L.n, 256)), dim3(256), 0, s, g);
+    if (!L.coarsest) {
+      GridIC0Setup gi;
+      gi.nx = cnx;
+      gi.ny = cny;
+      gi.tiles_x = (int)cdiv(cnx, MC_TX);
+      gi.ntiles = L.tiles;
+      gi.diag = L.diag;
+      gi.tx = L.tx;
+      gi.ty = L.ty;
+      gi.dinv = L.fdinv;
+      hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)L.tiles * MC_ICB, 64)), dim3(64), 0,
+                         s, gi);
+      cv(L.fdinv, L.fdinv32, L.n);
+    } else {
+      const long nn = L.n * L.n;
+      if (!L.inv) L.inv = M.alloc<double>(nn);
+      hipLaunchKernelGGL(k_fill0, dim3(cdiv(nn, 256)), dim3(256), 0, s, L.inv, nn);
+      hipLaunchKernelGGL(k_mg_dense_fill, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.diag, L.tx,
+                         L.ty, cnx, cny, L.inv);
+      HIPCHK(hipGetLastError());
+      invert_spd(L.inv, (int)L.n, s);
+      if (mixed) cv(L.inv, L.inv32, nn);
+    }
+    cv(L.diag, L.diag32, L.n);
+    cv(L.tx, L.tx32, L.n);
+    cv(L.ty, L.ty32, L.n);
+    HIPCHK(hipGetLastError());
+    fd = L.diag;
+    ftx = L.tx;
+    fty = L.ty;
+    nx = cnx;
+    ny = cny;
+    ++l;
+  }
+  C.mg.resize(l);
+  C.mg_on = l > 0;
+  if (C.mg_on && !C.zpre) C.zpre = M.alloc<double>(C.n);
+  if (C.mg_on && mixed && !C.zpre32) C.zpre32 = M.alloc<float>(C.n);
+}
+
 static void build_coefficients(mc_problem* P) {
   const bool ex = P->X.opt.scheme == MC_SCHEME_EX;
   const double h = P->d.h, tau = P->d.tau;
@@ -710,7 +920,7 @@ static void build_coefficients(mc_problem* P) {
   }
   HIPCHK(hipGetLastError());
   for (auto& C : P->cont) C.K = 0;   // set again below for block IC(0)
-  if (P->X.opt.precond == MC_BIC0) {
+  if (ic_precond(P->X.opt.precond)) {
     for (auto& C : P->cont) {
       if (!C.fdinv) C.fdinv = P->mem.alloc<double>(C.n);
       if (!C.z) C.z = P->mem.alloc<double>(C.n);
@@ -744,6 +954,12 @@ static void build_coefficients(mc_problem* P) {
     }
     HIPCHK(hipGetLastError());
   }
+  for (auto& C : P->cont) C.mg_on = false;
+  if (P->X.opt.precond == MC_MG) {
+    HIPCHK(hipStreamSynchronize(s));
+    for (auto& C : P->cont)
+      if (C.kind == PART_GRID) setup_multigrid(P, C);
+  }
   if (P->X.opt.precision == MC_MIXED) {
     for (auto& C : P->cont) {
       auto cv = [&](double* a, float*& b, long n) {
@@ -752,7 +968,7 @@ static void build_coefficients(mc_problem* P) {
         hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, s, a, b, n);
       };
       cv(C.diag, C.diag32, C.n);
-      if (P->X.opt.precond == MC_BIC0) {
+      if (ic_precond(P->X.opt.precond)) {
         cv(C.fdinv, C.fdinv32, C.n);
         if (C.kind == PART_GRAPH) cv(C.cT, C.cT32, C.n);
         if (!C.z32) C.z32 = P->mem.alloc<float>(C.n);
@@ -789,14 +1005,15 @@ static void build_coefficients(mc_problem* P) {
 // Workgroup counts of every continuum for the current preconditioner, and the slot counts
 // of the system records (in host memory `hs`).
 static void set_slot_counts(mc_problem* P, SysState* hs) {
-  const bool bic0 = P->X.opt.precond == MC_BIC0;
+  const bool bic0 = ic_precond(P->X.opt.precond);
   const bool fp32 = P->X.opt.precision == MC_MIXED;
   int ca = 0, cb = 0;
   for (int c = 0; c < P->ncont; ++c) {
     Cont& C = P->cont[c];
     C.blocks[0] = blocks_for(C.tiles, C.kind, 0, bic0, fp32);
     C.blocks[1] = blocks_for(C.tiles, C.kind, 1, bic0, fp32);
-    C.blocks[2] = C.K > 0 ? (int)cdiv(C.K, MC_SCHUR_ROWS) : 0;
+    // fracture: crossing-cell product; grid with a V-cycle: its final smoothing
+    C.blocks[2] = C.K > 0 ? (int)cdiv(C.K, MC_SCHUR_ROWS) : (C.mg_on ? C.blocks[1] : 0);
     hs[c].nslotsA = C.blocks[0];
     hs[c].nslotsB = C.blocks[1] + C.blocks[2];
     ca += C.blocks[0];
@@ -862,8 +1079,8 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     C.kind = grid ? PART_GRID : PART_GRAPH;
     C.n = grid ? P->ncell : d.nf;
     C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY)) : P->ngtiles;
-    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, o.precond == MC_BIC0, o.precision == MC_MIXED);
-    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, o.precond == MC_BIC0, o.precision == MC_MIXED);
+    C.blocks[0] = blocks_for(C.tiles, C.kind, 0, ic_precond(o.precond), o.precision == MC_MIXED);
+    C.blocks[1] = blocks_for(C.tiles, C.kind, 1, ic_precond(o.precond), o.precision == MC_MIXED);
     C.blocks[2] = 0;
     C.diag = M.alloc<double>(C.n);
     C.F = M.alloc<double>(C.n);
@@ -893,7 +1110,10 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   // tilings can follow option changes
   // (a fracture continuum adds the workgroups of its crossing-cell product)
   const int kslots = P->K_all <= MC_SCHUR_KMAX ? (int)cdiv(P->K_all, MC_SCHUR_ROWS) : 0;
-  auto slots_of = [&](int c) { return P->cont[c].tiles + (P->cont[c].kind == PART_GRAPH ? kslots : 0); };
+  // (a grid continuum with a V-cycle adds the workgroups of its final smoothing)
+  auto slots_of = [&](int c) {
+    return P->cont[c].tiles + (P->cont[c].kind == PART_GRAPH ? kslots : P->cont[c].tiles);
+  };
   int coupled_tiles = 0;
   for (int c = 0; c < P->ncont; ++c) coupled_tiles += slots_of(c);
   for (int sI = 0; sI < nsys; ++sI) {
@@ -972,6 +1192,27 @@ static void launch_schur(Exec& X, const Table& Tb, hipStream_t s) {
                        Tb.tiles[2][PART_GRAPH], X.sys);
 }
 
+// V-cycle of the grid parts that have coarse levels, after the kernel that wrote their
+// finest pre-smoothed z_p: restriction, smoothing and coarsest solves going down, the
+// corrections with post-smoothing going up.  The finest post-smoothing writes z and, when
+// `final`, (r, z) to the update slots.  `sys` null: no test of the solve's end.
+template <class T>
+static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool final) {
+  const int L = (int)Tb.mg.size();
+  if (L == 0 || Tb.mg[0][3].n == 0) return;
+  auto go = [&](auto kern, const Table::List& li) {
+    if (li.n) hipLaunchKernelGGL(kern, dim3(li.n), dim3(MC_BLOCK), 0, s, Tb.parts, li.t, sys);
+  };
+  for (int l = 1; l < L; ++l) {
+    go(k_mg_restrict<T>, Tb.mg[l][0]);
+    go(k_mg_smooth<T>, Tb.mg[l][1]);
+    go(k_mg_dense<T>, Tb.mg[l][2]);
+  }
+  for (int l = L - 2; l >= 1; --l) go(k_mg_post<T, false>, Tb.mg[l][3]);
+  if (final) go(k_mg_post<T, true>, Tb.mg[0][3]);
+  else go(k_mg_post<T, false>, Tb.mg[0][3]);
+}
+
 // One PCG iteration over the group's tiles: operator kernels, then update kernels.
 template <class T, int PREC>
 static void launch_iter(Exec& X, Group& G, bool timed) {
@@ -995,6 +1236,7 @@ static void launch_iter(Exec& X, Group& G, bool timed) {
   L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0);
   L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0);
   L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1);
+  if (G.kinds & 1) launch_vcycle<T>(Tb, G.s, X.sys, true);
   L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1);
   if (G.kinds & 2) launch_schur<T>(X, Tb, G.s);
 }
@@ -1130,6 +1372,7 @@ static void advance_t(Exec& X, Group& G) {
                          G.s1);
       if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
       launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+      if (G.kinds & 1) launch_vcycle<double>(*G.T, G.s, X.sys, true);
       if (G.kinds & 2) launch_schur<double>(X, *G.T, G.s);
       G.k = 0;
       G.K = X.opt.check_every > 0 ? X.opt.check_every : first_chunk(X, G);
@@ -1153,6 +1396,7 @@ static void advance_t(Exec& X, Group& G) {
     if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
     launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+    if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
     if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
     G.outer = 0;
     G.k = 0;
@@ -1171,6 +1415,7 @@ static void advance_t(Exec& X, Group& G) {
     launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, X.sys);
     launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+    if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
     if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
     G.outer += 1;
     G.k = 0;
@@ -1184,7 +1429,7 @@ static void advance_t(Exec& X, Group& G) {
 }
 
 static void advance(Exec& X, Group& G) {
-  if (X.opt.precond == MC_BIC0) advance_t<PREC_BIC0>(X, G);
+  if (ic_precond(X.opt.precond)) advance_t<PREC_BIC0>(X, G);
   else advance_t<PREC_JACOBI>(X, G);
 }
 
@@ -1290,7 +1535,7 @@ static void solve_table(Exec& X, Table& Tb, int s0, int s1, bool assemble, bool 
   };
   if (split_kinds && Tb.nblk[0][PART_GRID] && Tb.nblk[0][PART_GRAPH]) {
     int ngrid = 0;
-    for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID;
+    for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID && q.mg_level == 0;
     const bool one = env_flag("MCDEC_ONE_STREAM", false);
     if (!one) exec_side_streams(X);
     const bool part = X.stream_grid && !one;
@@ -1429,6 +1674,7 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
   std::vector<PartTiling> til;
   std::vector<SysState> hs;
   std::vector<std::vector<int>> sys_of(n), cont_of(n);
+  std::vector<mc_problem*> owner;
   auto rec = [&](mc_problem* P, int sI, int nA, int nB) {
     SysState S;
     std::memset(&S, 0, sizeof(S));
@@ -1450,10 +1696,16 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
           rec(P, c, P->cont[c].blocks[0], P->cont[c].blocks[1] + P->cont[c].blocks[2]);
           parts.push_back(base_part(P, c, sI, 0, 0, mixed));
           til.push_back(tiling_of(P, c));
+          owner.push_back(P);
           sys_of[i].push_back(sI);
           cont_of[i].push_back(c);
         }
       }
+    for (int j = 0, np = (int)parts.size(); j < np; ++j) {   // V-cycle levels after all parts
+      const size_t before = parts.size();
+      add_mg_levels(owner[j], parts, j, mixed);
+      for (size_t k = before; k < parts.size(); ++k) til.push_back(tiling_of(owner[j], parts[k].cont));
+    }
   } else {
     for (int i = 0; i < n; ++i) {
       mc_problem* P = probs[i];
@@ -1465,9 +1717,9 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
       }
       rec(P, P->ncont, nA, nB);
       std::vector<PartD> cp = coupled_parts(P, sI, (int)parts.size());
-      for (int c = 0; c < P->ncont; ++c) {
-        parts.push_back(cp[c]);
-        til.push_back(tiling_of(P, c));
+      for (auto& q : cp) {
+        parts.push_back(q);
+        til.push_back(tiling_of(P, q.cont));
       }
       sys_of[i].push_back(sI);
       cont_of[i].push_back(0);
@@ -1527,13 +1779,13 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
   Cont& C = P->cont[c];
   const bool fp32 = sizeof(T) == 4;
   hipStream_t s = X.stream;
-  Table& Tb = upload_table(P, "tune", decoupled_parts(P, {c}, fp32));
+  Table& Tb = upload_table(P, "tune", decoupled_parts(P, {c}, fp32, false));
   SysState S;
   std::memset(&S, 0, sizeof(S));
   S.partA = P->partA[c];
   S.partB = P->partB[c];
   S.nslotsA = C.blocks[0];
-  S.nslotsB = C.blocks[1] + C.blocks[2];
+  S.nslotsB = C.blocks[1] + (C.kind == PART_GRAPH ? C.blocks[2] : 0);   // no V-cycle here
   S.max_iter = 1 << 30;
   S.max_outer = 1;
   S.done = 1;
@@ -1578,7 +1830,7 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
 }
 
 static double time_tiling_any(mc_problem* P, int c, int fam, int iters) {
-  const bool fp32 = P->X.opt.precision == MC_MIXED, bic0 = P->X.opt.precond == MC_BIC0;
+  const bool fp32 = P->X.opt.precision == MC_MIXED, bic0 = ic_precond(P->X.opt.precond);
   if (fp32) return bic0 ? time_tiling<float, PREC_BIC0>(P, c, fam, iters)
                         : time_tiling<float, PREC_JACOBI>(P, c, fam, iters);
   return bic0 ? time_tiling<double, PREC_BIC0>(P, c, fam, iters)
@@ -1601,7 +1853,7 @@ static void autotune(mc_problem* const* probs, int n, int iters) {
   std::vector<std::vector<int>> seen;
   for (int i = 0; i < n; ++i) {
     mc_problem* P = probs[i];
-    const bool bic0 = P->X.opt.precond == MC_BIC0, fp32 = P->X.opt.precision == MC_MIXED;
+    const bool bic0 = ic_precond(P->X.opt.precond), fp32 = P->X.opt.precision == MC_MIXED;
     for (int c = 0; c < P->ncont; ++c) {
       Cont& C = P->cont[c];
       for (int fam = 0; fam < 2; ++fam) {
@@ -1646,7 +1898,7 @@ static void autotune(mc_problem* const* probs, int n, int iters) {
 static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
   const int64_t nc = (int64_t)d.nx * d.ny, nf = d.nf, ne = d.ne;
   const int64_t gt = (int64_t)cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY);
-  const bool bic0 = o.precond == MC_BIC0, mixed = o.precision == MC_MIXED;
+  const bool bic0 = ic_precond(o.precond), mixed = o.precision == MC_MIXED;
   int64_t b = 0, nalloc = 0;
   auto A = [&](int64_t bytes) {
     b += std::max<int64_t>(bytes, 8);
@@ -1676,7 +1928,8 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
     const bool grid = c < d.n_omega;
     const int64_t n = grid ? nc : nf;
     const int64_t tiles = grid ? gt : nf + 1;
-    ctiles += tiles;
+    const int64_t slots = grid ? 2 * tiles : tiles;   // grid: room for a V-cycle's slots
+    ctiles += slots;
     A(8 * n);                     // diag
     A(8 * n);                     // F
     if (grid) {
@@ -1687,8 +1940,28 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
       A(8 * n);                   // mt
     }
     for (int k = 0; k < 7; ++k) A(8 * n);   // two states, b, r, p, p2, q
-    A(8 * MC_SLOT * tiles);       // partials of its decoupled system
-    A(8 * MC_SLOT * tiles);
+    A(8 * MC_SLOT * slots);       // partials of its decoupled system
+    A(8 * MC_SLOT * slots);
+    if (grid && o.precond == MC_MG) {   // V-cycle levels
+      int64_t lx = d.nx, ly = d.ny;
+      if (lx * ly > MC_MG_COARSE) {
+        A(8 * n);                 // pre-smoothed z of the finest level
+        if (mixed) A(4 * n);
+      }
+      while (lx * ly > MC_MG_COARSE) {
+        lx = (lx + 1) / 2;
+        ly = (ly + 1) / 2;
+        const int64_t m = lx * ly;
+        for (int k = 0; k < 7; ++k) A(8 * m);   // operator, factor, r, z_p, z
+        for (int k = 0; k < 3; ++k) A(4 * m);   // FP32 operator copies
+        if (m > MC_MG_COARSE) A(4 * m);          // FP32 factor
+        else {
+          A(8 * m * m);                          // dense inverse
+          if (mixed) A(4 * m * m);
+        }
+        if (mixed) for (int k = 0; k < 3; ++k) A(4 * m);
+      }
+    }
     if (bic0) {
       A(8 * n);                   // fdinv
       A(8 * n);                   // z
@@ -1914,9 +2187,10 @@ mc_status mc_apply_precond(mc_problem* P, int32_t alpha, const double* r, double
   parts[0].r = const_cast<double*>(r);
   parts[0].z = z;
   mc::Table& T = mc::upload_table(P, "prec" + std::to_string(alpha), parts);
-  if (P->X.opt.precond == MC_BIC0) {
+  if (mc::ic_precond(P->X.opt.precond)) {
     mc::launch_all(P->X.stream, T, 1, mc::k_precond<PREC_BIC0, PART_GRID>,
                    mc::k_precond<PREC_BIC0, PART_GRAPH>);
+    mc::launch_vcycle<double>(T, P->X.stream, nullptr, false);
     if (T.nblk[2][PART_GRAPH]) {   // fracture: crossing cells, then z = y + block responses
       hipLaunchKernelGGL(mc::k_schur_apply, dim3(T.nblk[2][PART_GRAPH]), dim3(MC_BLOCK), 0,
                          P->X.stream, T.parts, T.tiles[2][PART_GRAPH]);
@@ -2008,6 +2282,7 @@ mc_status mc_get_info(const mc_problem* P, mc_info* info) {
     info->tiles[c] = P->cont[c].tiles;
     info->blocks[c][0] = P->cont[c].blocks[0];
     info->blocks[c][1] = P->cont[c].blocks[1];
+    info->mg_levels[c] = P->cont[c].mg_on ? (int32_t)P->cont[c].mg.size() : 0;
   }
   return MC_OK;
 }

@@ -80,7 +80,8 @@ std::string validate_desc(const mc_problem_desc& d) {
 std::string validate_options(const mc_options& o) {
   if (o.scheme < MC_SCHEME_D || o.scheme > MC_SCHEME_EX) return "unknown scheme";
   if (o.precision != MC_FP64 && o.precision != MC_MIXED) return "unknown precision";
-  if (o.precond != MC_JACOBI && o.precond != MC_BIC0) return "unknown preconditioner";
+  if (o.precond != MC_JACOBI && o.precond != MC_BIC0 && o.precond != MC_MG)
+    return "unknown preconditioner";
   if (!(o.tol > 0 && o.tol < 1)) return "tol must be in (0, 1)";
   if (o.max_iter < 1) return "max_iter must be >= 1";
   if (o.precision == MC_MIXED) {

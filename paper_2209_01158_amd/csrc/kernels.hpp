@@ -488,9 +488,9 @@ struct IcBlk {
 // Dot products: with M = (D + E) D^-1 (D + E^T), the forward values u = (D + E)^-1 r and
 // z = M^-1 r satisfy (D + E^T) z = D u, hence (r, z) = (M z, z) = sum_i d_i u_i^2: both
 // (r,z) and (r,r) are complete after the forward sweep, so r never has to stay live.
-template <class T, bool HAS_T>
+template <class T, bool HAS_T, class EZ>
 __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
-                                          const T (&rv)[MC_ICY], T* __restrict__ zout,
+                                          const T (&rv)[MC_ICY], const EZ& emit_z,
                                           double& rz, double& rr) {
   const int lane = threadIdx.x & 63;
   const gconst<float> dinv = gc(P.fdinv32);
@@ -543,15 +543,25 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
     T b = e * di;
     scan_maps_down(a, b);
     zabove = a;
-    if (B.act(y)) zout[B.cell(y)] = a;
+    emit_z(y, a);
   }
+}
+
+// z = M^-1 r on one block, handing each z value to emit_z(row, value)
+template <class T, class EZ>
+__device__ __forceinline__ void ic0_block_f(const PartD& P, const IcBlk& B,
+                                            const T (&rv)[MC_ICY], const EZ& emit_z, double& rz,
+                                            double& rr) {
+  if (P.has_t) ic0_sweep<T, true>(P, B, rv, emit_z, rz, rr);
+  else ic0_sweep<T, false>(P, B, rv, emit_z, rz, rr);
 }
 
 template <class T>
 __device__ __forceinline__ void ic0_block(const PartD& P, const IcBlk& B, const T (&rv)[MC_ICY],
                                           T* __restrict__ zout, double& rz, double& rr) {
-  if (P.has_t) ic0_sweep<T, true>(P, B, rv, zout, rz, rr);
-  else ic0_sweep<T, false>(P, B, rv, zout, rz, rr);
+  ic0_block_f<T>(P, B, rv, [&](int y, T a) {
+    if (B.act(y)) zout[B.cell(y)] = a;
+  }, rz, rr);
 }
 
 // Runs f(unit) for the IC(0) blocks of the workgroup's tile run, one wavefront per block.
@@ -732,8 +742,10 @@ __device__ __forceinline__ void residual_and_precond(const PartD& P, const Tile&
 #pragma unroll
       for (int y = 0; y < MC_ICY; ++y)
         rs_[y] = B.act(y) ? emit(B.cell(y), r64[y], P.b[B.cell(y)]) : (T)0;
-      ic0_block<T>(P, B, rs_, z, v[0], v[1]);
+      // under a V-cycle this is the pre-smoothing of the finest level
+      ic0_block<T>(P, B, rs_, P.mg_next >= 0 ? (T*)P.mg_zp : z, v[0], v[1]);
     });
+    if (P.mg_next >= 0) v[0] = 0.0;   // (r, z) comes from the final smoothing
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     const T* dinv = pick<T>(P.fdinv, P.fdinv32);
     const T* cT = pick<T>(P.cT, P.cT32);
@@ -1020,8 +1032,10 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
         }
         rv[y] = B.act(y) ? rn : (T)0;
       }
-      ic0_block<T>(P, B, rv, z, o[0], o[1]);
+      // under a V-cycle this is the pre-smoothing of the finest level
+      ic0_block<T>(P, B, rv, P.mg_next >= 0 ? (T*)P.mg_zp : z, o[0], o[1]);
     });
+    if (P.mg_next >= 0) o[0] = 0.0;   // (r, z) comes from the final smoothing
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     const T* dinv = pick<T>(P.fdinv, P.fdinv32);
     const T* cT = pick<T>(P.cT, P.cT32);
@@ -1201,7 +1215,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
       double rv[MC_ICY];
 #pragma unroll
       for (int y = 0; y < MC_ICY; ++y) rv[y] = B.act(y) ? r[B.cell(y)] : 0.0;
-      ic0_block<double>(P, B, rv, z, dz, dr);
+      ic0_block<double>(P, B, rv, P.mg_next >= 0 ? (double*)P.mg_zp : z, dz, dr);
     });
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     for (int tile = t.t0; tile < t.t1; ++tile) {
@@ -1279,6 +1293,302 @@ __global__ void __launch_bounds__(MC_BLOCK) k_schur_finish(const PartD* __restri
   for_cells<PART_GRAPH>(P, t, [&](int, int, long) {}, [&](int l) {
     z[l] = zval<double, PREC_BIC0>(P, l);
   });
+}
+
+// ------------------------------------------------------------------------------------
+// multigrid V-cycle on a grid continuum (preconditioner option MC_MG)
+//   levels: 2 x 2 aggregates of cells (ragged at odd sizes); coarse operator = P^T A P with
+//   P piecewise constant, again a 5-point operator with face conductances; the coarsest level
+//   (at most MC_MG_COARSE cells) is solved by its dense inverse.
+//   V(r): z_p = M^-1 r (block IC(0)); r_c = P^T (r - A z_p); e = V_c(r_c);
+//         z = (z_p + P e) + M^-1 (r - A (z_p + P e)).   Symmetric, as PCG needs.
+// ------------------------------------------------------------------------------------
+struct CoarsenSetup {
+  int nx, ny, cnx, cny;      // fine and coarse grid
+  const double* diag;        // fine operator
+  const double* tx;
+  const double* ty;
+  double* cdiag;             // coarse operator
+  double* ctx;
+  double* cty;
+};
+
+// Coarse operator P^T A P for 2 x 2 aggregates: the diagonal sums the aggregate's diagonal
+// entries and subtracts twice its internal face conductances; a coarse face conductance
+// sums the fine faces it covers.
+__global__ void k_mg_coarsen(CoarsenSetup g) {
+  const long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= (long)g.cnx * g.cny) return;
+  const int X = (int)(I % g.cnx), Y = (int)(I / g.cnx);
+  double d = 0.0, e = 0.0, n = 0.0;
+  for (int b = 0; b < 2; ++b) {
+    const int y = 2 * Y + b;
+    if (y >= g.ny) continue;
+    for (int a = 0; a < 2; ++a) {
+      const int x = 2 * X + a;
+      if (x >= g.nx) continue;
+      const long i = (long)y * g.nx + x;
+      d += g.diag[i];
+      if (a == 0 && x + 1 < g.nx) d -= 2.0 * g.tx[i];   // face inside the aggregate
+      if (b == 0 && y + 1 < g.ny) d -= 2.0 * g.ty[i];
+      if (a == 1 || x + 1 == g.nx) e += g.tx[i];        // east faces of the aggregate
+      if (b == 1 || y + 1 == g.ny) n += g.ty[i];        // north faces
+    }
+  }
+  g.cdiag[I] = d;
+  g.ctx[I] = X + 1 < g.cnx ? e : 0.0;
+  g.cty[I] = Y + 1 < g.cny ? n : 0.0;
+}
+
+// Dense symmetric matrix of a 5-point operator (n = nx * ny; a must be zero on entry).
+__global__ void k_mg_dense_fill(const double* __restrict__ diag, const double* __restrict__ tx,
+                                const double* __restrict__ ty, int nx, int ny,
+                                double* __restrict__ a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long n = (long)nx * ny;
+  if (i >= n) return;
+  const int x = (int)(i % nx), y = (int)(i / nx);
+  a[i * n + i] = diag[i];
+  if (x + 1 < nx) {
+    a[i * n + i + 1] = -tx[i];
+    a[(i + 1) * n + i] = -tx[i];
+  }
+  if (y + 1 < ny) {
+    a[i * n + i + nx] = -ty[i];
+    a[(i + nx) * n + i] = -ty[i];
+  }
+}
+
+__global__ void k_fill0(double* __restrict__ a, long n) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
+// Row-wise 5-point product on a wavefront whose lane l holds column x = x0 + l of one row:
+// (A v)_x with the west / east values of v from the neighbouring lanes and, at lanes 0 and
+// 63, from `vh` (the lane's halo value: column x0 - 1 at lane 0, x0 + 64 at lane 63).
+// te: this column's east face conductance; th: the halo column's (lane 0 takes it as its
+// west face); ts / tn: south / north faces.  Without a conductance field every face is tc.
+// Every lane must call it (the lane moves are wave-wide).
+template <class T, bool HAS_T>
+__device__ __forceinline__ T row_Av(int x, int nx, bool south, bool north, T d, T vc, T vh,
+                                    T vs, T vn, T te, T th, T ts, T tn, T tc) {
+  const T vw = dpp_d<0x138, 0xF>(vh, vc);   // wave_shr:1, lane 0 keeps vh
+  const T ve = dpp_d<0x130, 0xF>(vh, vc);   // wave_shl:1, lane 63 keeps vh
+  T acc = d * vc;
+  if constexpr (HAS_T) {
+    const T tw = dpp_d<0x138, 0xF>(th, te);
+    if (x > 0) acc -= tw * vw;
+    if (x + 1 < nx) acc -= te * ve;
+    if (south) acc -= ts * vs;
+    if (north) acc -= tn * vn;
+  } else {
+    T sum = (T)0;
+    if (x > 0) sum += vw;
+    if (x + 1 < nx) sum += ve;
+    if (south) sum += vs;
+    if (north) sum += vn;
+    acc -= tc * sum;
+  }
+  return acc;
+}
+
+// r_c = P^T (r - A z_p) of the finer level F, swept over F's tiles: a wavefront takes
+// MC_TY / 4 consecutive fine rows of a 64-column band (lane = fine column), loads every
+// value it needs first, forms the fine residuals, and sums each 2 x 2 aggregate over a row
+// pair and a lane pair (tiles start at even columns and rows, so no aggregate straddles
+// two wavefronts).
+template <class T, bool HAS_T>
+__device__ __forceinline__ void restrict_tiles(const PartD& F, const PartD& C, const Tile& t) {
+  constexpr int R = MC_TY / 4;   // fine rows per wavefront (even)
+  const T* rf = (const T*)(F.mg_level == 0 ? F.r : F.mg_r);   // level 0: the PCG residual
+  const T* zf = (const T*)F.mg_zp;
+  T* rc = (T*)C.mg_r;
+  const T* d = pick<T>(F.diag, F.diag32);
+  const T* txp = pick<T>(F.tx, F.tx32);
+  const T* typ = pick<T>(F.ty, F.ty32);
+  const T tc = (T)F.tconst;
+  const int lane = threadIdx.x & 63, nx = F.nx, ny = F.ny, cnx = C.nx;
+  for (int tile = t.t0; tile < t.t1; ++tile) {
+    const int x0 = (tile % F.tiles_x) * MC_TX;
+    const int ya = (tile / F.tiles_x) * MC_TY + (int)(threadIdx.x >> 6) * R;
+    if (ya >= ny) continue;   // wave-uniform
+    const int x = x0 + lane, xs = min(x, nx - 1);
+    const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : xs);
+    auto row = [&](int j) { return (long)min(max(ya + j, 0), ny - 1) * nx; };
+    T z[R + 2], zh[R], rv[R], dv[R], te[R], th[R], ty[R + 1];
+#pragma unroll
+    for (int j = 0; j < R + 2; ++j) z[j] = zf[row(j - 1) + xs];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const long o = row(j);
+      zh[j] = zf[o + hx];
+      rv[j] = rf[o + xs];
+      dv[j] = d[o + xs];
+      te[j] = HAS_T ? txp[o + xs] : (T)0;
+      th[j] = HAS_T ? txp[o + hx] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < R + 1; ++j) ty[j] = HAS_T ? typ[row(j - 1) + xs] : (T)0;
+    double s[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int y = ya + j;
+      const T a = row_Av<T, HAS_T>(x, nx, y > 0, y + 1 < ny, dv[j], z[j + 1], zh[j], z[j],
+                                   z[j + 2], te[j], th[j], ty[j], ty[j + 1], tc);
+      s[j] = (x < nx && y < ny) ? (double)rv[j] - (double)a : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < R; j += 2) {
+      double v = s[j] + s[j + 1];
+      v += __shfl_xor(v, 1, 64);
+      if (!(lane & 1) && x < nx && ya + j < ny)
+        rc[(long)((ya + j) >> 1) * cnx + (x >> 1)] = (T)v;
+    }
+  }
+}
+
+// (Every V-cycle kernel skips systems whose solve has ended; `sys` is null for a plain
+// application of the preconditioner.)
+template <class T>
+__global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restrict__ parts,
+                                                          const Tile* __restrict__ tiles,
+                                                          SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& C = parts[t.part];
+  if (sys && ld_flag(&sys[C.sys].done)) return;
+  const PartD& F = parts[C.mg_prev];
+  if (F.has_t) restrict_tiles<T, true>(F, C, t);
+  else restrict_tiles<T, false>(F, C, t);
+}
+
+// z_p = M^-1 r on a level with a coarser one (block IC(0))
+template <class T>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_mg_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
+            SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  if (sys && ld_flag(&sys[P.sys].done)) return;
+  const T* r = (const T*)P.mg_r;
+  double dz = 0.0, dr = 0.0;
+  for_wave_tiles(t, [&](int unit) {
+    const IcBlk B(P, unit);
+    T rv[MC_ICY];
+#pragma unroll
+    for (int y = 0; y < MC_ICY; ++y) rv[y] = B.act(y) ? r[B.cell(y)] : (T)0;
+    ic0_block<T>(P, B, rv, (T*)P.mg_zp, dz, dr);
+  });
+}
+
+// coarsest level: z = A^-1 r by its dense inverse, one workgroup per MC_SCHUR_ROWS rows
+template <class T>
+__global__ void __launch_bounds__(MC_BLOCK) k_mg_dense(const PartD* __restrict__ parts,
+                                                       const Tile* __restrict__ tiles,
+                                                       SysState* __restrict__ sys) {
+  __shared__ T rs[MC_MG_COARSE];
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  if (sys && ld_flag(&sys[P.sys].done)) return;
+  const int n = P.n;
+  const T* r = (const T*)P.mg_r;
+  for (int j = threadIdx.x; j < n; j += MC_BLOCK) rs[j] = r[j];
+  __syncthreads();
+  const gconst<T> inv = gc(pick<T>(P.mg_inv, P.mg_inv32));
+  T* z = (T*)P.mg_z;
+  const int lane = threadIdx.x & 63;
+  const int k1 = min(t.t1 * MC_SCHUR_ROWS, n);
+  for (int k = t.t0 * MC_SCHUR_ROWS + (int)(threadIdx.x >> 6); k < k1; k += 4) {
+    const long row = (long)k * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc += (double)inv[row + j] * (double)rs[j];
+    acc = wave_sum(acc);
+    if (lane == 0) z[k] = (T)acc;
+  }
+}
+
+// z = (z_p + P e) + M^-1 (r - A (z_p + P e)) with e the coarser level's solution, one
+// wavefront per IC(0) block: z_p + P e on the block's rows and the rows above and below
+// (west / east values from the neighbouring lanes, the band's edge columns loaded by lanes
+// 0 and 63), the residual of each half of the block from values loaded first, then the
+// sweep.  At the finest level of a PCG solve (FINAL) the result is the PCG vector z and the
+// workgroup adds (r, z) to its partial slot.
+template <class T, bool FINAL, bool HAS_T>
+__device__ __forceinline__ void post_blocks(const PartD* __restrict__ parts, const PartD& P,
+                                            const Tile& t, double& rz) {
+  const PartD& Cp = parts[P.mg_next];
+  const T* zp = (const T*)P.mg_zp;
+  const T* e = (const T*)Cp.mg_z;
+  const T* r = (const T*)(P.mg_level == 0 ? P.r : P.mg_r);   // level 0: the PCG vectors
+  T* out = (T*)(P.mg_level == 0 ? P.z : P.mg_z);
+  const T* d = pick<T>(P.diag, P.diag32);
+  const T* txp = pick<T>(P.tx, P.tx32);
+  const T* typ = pick<T>(P.ty, P.ty32);
+  const T tc = (T)P.tconst;
+  const int nx = P.nx, ny = P.ny, cnx = Cp.nx, lane = threadIdx.x & 63;
+  for_wave_tiles(t, [&](int unit) {
+    const IcBlk B(P, unit);
+    const int x0 = B.cx - lane;
+    const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
+    auto rowy = [&](int j) { return min(max(B.y0 + j, 0), ny - 1); };
+    auto zfull = [&](int y, int x) {
+      return zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)];
+    };
+    T zo[MC_ICY + 2];
+#pragma unroll
+    for (int j = 0; j < MC_ICY + 2; ++j) zo[j] = zfull(rowy(j - 1), B.cxs);
+    T rl[MC_ICY], rv[MC_ICY];
+    constexpr int H = MC_ICY / 2;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      T zh[H], rr[H], dv[H], te[H], th[H], ty[H + 1];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int y = rowy(h * H + j);
+        const long o = (long)y * nx;
+        zh[j] = zfull(y, hx);
+        rr[j] = r[o + B.cxs];
+        dv[j] = d[o + B.cxs];
+        te[j] = HAS_T ? txp[o + B.cxs] : (T)0;
+        th[j] = HAS_T ? txp[o + hx] : (T)0;
+      }
+#pragma unroll
+      for (int j = 0; j < H + 1; ++j) ty[j] = HAS_T ? typ[(long)rowy(h * H + j - 1) * nx + B.cxs] : (T)0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int jj = h * H + j, y = B.y0 + jj;
+        const T a = row_Av<T, HAS_T>(B.cx, nx, y > 0, y + 1 < ny, dv[j], zo[jj + 1], zh[j],
+                                     zo[jj], zo[jj + 2], te[j], th[j], ty[j], ty[j + 1], tc);
+        rl[jj] = rr[j];
+        rv[jj] = B.act(jj) ? rr[j] - a : (T)0;
+      }
+    }
+    double dz = 0.0, dr = 0.0;
+    ic0_block_f<T>(P, B, rv, [&](int y, T a) {
+      if (B.act(y)) {
+        const T zf = zo[y + 1] + a;
+        out[B.cell(y)] = zf;
+        if (FINAL) rz += (double)rl[y] * (double)zf;
+      }
+    }, dz, dr);
+  });
+}
+
+template <class T, bool FINAL>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_mg_post(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
+          SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  if (sys && ld_flag(&sys[P.sys].done)) return;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (P.has_t) post_blocks<T, FINAL, true>(parts, P, t, v[0]);
+  else post_blocks<T, FINAL, false>(parts, P, t, v[0]);
+  if (FINAL) write_slot<5>(sys[P.sys].partB, t.slot, v);
 }
 
 // Per-solve reset of the system records [s0, s1) (a kernel, so the sequence stays free of

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "MC_OK", -1: "MC_EINVAL", -2: "MC_ENOMEM", -3: "MC_ENOCONV",
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 SCHEMES = {"D": 0, "coupled": 1, "L": 2, "U": 3, "EX": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
-PRECONDS = {"jacobi": 0, "bic0": 1}
+PRECONDS = {"jacobi": 0, "bic0": 1, "mg": 2}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -74,7 +74,8 @@ class Report(C.Structure):
 class Info(C.Structure):
     _fields_ = [("n_cont", C.c_int32), ("sizes", C.c_int32 * 3), ("device_bytes", C.c_int64),
                 ("grid_tiles", C.c_int32), ("n_chains", C.c_int32), ("tiles", C.c_int32 * 3),
-                ("blocks", (C.c_int32 * 2) * 3), ("n_crossing", C.c_int32)]
+                ("blocks", (C.c_int32 * 2) * 3), ("n_crossing", C.c_int32),
+                ("mg_levels", C.c_int32 * 3)]
 
 
 _PROBLEM = C.c_void_p

@@ -78,6 +78,10 @@ OPTS = {
     "mixed_jacobi": dict(scheme="D", precision="mixed", precond="jacobi", outer_tol=1e-11,
                          inner_tol=1e-5),
     "coupled": dict(scheme="coupled", precision="fp64", precond="bic0", tol=1e-12),
+    "fp64_mg": dict(scheme="D", precision="fp64", precond="mg", tol=1e-12),
+    "mixed_mg": dict(scheme="D", precision="mixed", precond="mg", outer_tol=1e-11,
+                     inner_tol=1e-5),
+    "coupled_mg": dict(scheme="coupled", precision="fp64", precond="mg", tol=1e-12),
 }
 
 
@@ -91,13 +95,13 @@ def test_batch_equals_alone_bitwise(key):
     assert_bitwise(alone, mixed)
 
 
-@pytest.mark.parametrize("key", ["fp64_bic0", "mixed_bic0"])
+@pytest.mark.parametrize("key", ["fp64_bic0", "mixed_bic0", "fp64_mg", "mixed_mg"])
 def test_batch_matches_oracle(key):
     print(f"\n[batch oracle {key}]", flush=True)
     probs = family()
     nsteps = 3
     opt = dict(OPTS[key])
-    if key == "fp64_bic0":
+    if opt["precision"] == "fp64":
         opt["tol"] = 1e-14
     got, reps = batch_states(probs, nsteps, **opt)
     gate = 1e-10 if opt["precision"] == "fp64" else 1e-8
