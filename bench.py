@@ -87,20 +87,33 @@ def grid_bytes_per_cell(kernel, precision, precond, has_t):
     A (operator): read z (Jacobi: r), p_old, diag [, tx, ty]; write p_new, q.
     B (update):   read x, p, r, q; write x, r; Jacobi also reads diag (z = r / diag is
                   recomputed where needed, never stored); block IC(0) reads the FP32 copies
-                  of the inverse pivots and of tx, ty (4 bytes each) and writes z."""
+                  of the inverse pivots and of tx, ty (4 bytes each) and writes z (under mg
+                  the same sweep is the finest pre-smoothing and writes z_p).
+    P (mg: finest correction + post-smoothing): read z_p, r, the coarse correction e (one
+                  word per 2 x 2 cells), the FP32 diagonal, the FP32 inverse pivots [and
+                  FP32 tx, ty, shared by the residual and the sweep]; write z."""
     w = 4 if precision == "mixed" else 8
     if kernel == "A":
         return (3 + (2 if has_t else 0) + 2) * w
-    if precond in ("bic0", "mg"):   # mg: the same sweep is the finest pre-smoothing
+    if kernel == "P":
+        return 3 * w + w / 4 + (2 + (2 if has_t else 0)) * 4
+    if precond in ("bic0", "mg"):
         return 7 * w + 3 * 4
     return 7 * w
 
 
+KERNEL_NAMES = {
+    "A": "k_pcg_A<{tp},{pn},GRID> (p = z + beta p; q = A p; partial p.q)",
+    "B": "k_pcg_B<{tp},{pn},GRID> (x += alpha p; r -= alpha q; z = M^-1 r; partial r.z, r.r)",
+    "P": "k_mg_post<{tp},FINAL> (z = z_p + P e + M^-1 (r - A (z_p + P e)); partial r.z)",
+}
+
+
 def roofline(kind_time, bytes_total, precision, precond, workload):
-    """Roofline objects of the grid operator (A) and update (B) kernels; the one with more
-    total time is the dominant kernel.  Per-launch algorithmic bytes = total over the timed
-    layers (iterations x cells x bytes per cell of every grid system) / launches issued;
-    average duration from the sampled launches."""
+    """Roofline objects of the grid operator (A), update (B) and (mg) finest post-smoothing
+    (P) kernels; the one with the most total time is the dominant kernel.  Per-launch
+    algorithmic bytes = total over the timed layers (iterations x cells x bytes per cell of
+    every grid system) / launches issued; average duration from the sampled launches."""
     out = {}
     for k, (sampled, ms, issued) in kind_time.items():
         if not sampled:
@@ -110,9 +123,7 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
         achieved = per_launch / avg_s / 1e9
         tp = "float" if precision == "mixed" else "double"
         pn = {"bic0": "BIC0", "mg": "BIC0", "jacobi": "JACOBI"}[precond]
-        name = (f"k_pcg_{k}<{tp},{pn},GRID> " +
-                ("(p = z + beta p; q = A p; partial p.q)" if k == "A" else
-                 "(x += alpha p; r -= alpha q; z = M^-1 r; partial r.z, r.r)"))
+        name = KERNEL_NAMES[k].format(tp=tp, pn=pn)
         out[k] = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                   "traffic": measured_traffic(workload, precond, k),
@@ -122,9 +133,8 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
                   "issued_launches": issued, "total_ms_est": avg_s * issued * 1e3}
     if not out:
         return None, None
-    dom = max(out, key=lambda k: out[k]["total_ms_est"])
-    other = [k for k in out if k != dom]
-    return out[dom], (out[other[0]] if other else None)
+    order = sorted(out, key=lambda k: -out[k]["total_ms_est"])
+    return out[order[0]], [out[k] for k in order[1:]]
 
 
 def golden_states(states_of, name, step, scheme):
@@ -210,9 +220,14 @@ def cpu_baseline(workload):
             "host_cpu_count": os.cpu_count()}
 
 
+def kernels_of(precond):
+    """Timed grid kernels, in the library's profile order (0 = A, 1 = B, 2 = P)."""
+    return ("A", "B", "P") if precond == "mg" else ("A", "B")
+
+
 def step_bytes(p, rep, precision, precond):
-    """Algorithmic bytes of the grid A and B kernels for one layer of problem p."""
-    out = {"A": 0.0, "B": 0.0}
+    """Algorithmic bytes of the grid A, B (and mg: P) kernels for one layer of problem p."""
+    out = {"A": 0.0, "B": 0.0} if precond != "mg" else {"A": 0.0, "B": 0.0, "P": 0.0}
     for c in range(p.n_omega):
         has_t = p.omega[c].k is not None
         for k in out:
@@ -255,7 +270,7 @@ def run_single(args, out):
         g.set_states(p0)
         g.profile(True, every=args.sample_every)
         lat, iters = [], []
-        tot = {"A": 0.0, "B": 0.0}
+        tot = {k: 0.0 for k in kernels_of(args.precond)}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -264,13 +279,13 @@ def run_single(args, out):
             lat.append(time.perf_counter() - ts)
             iters.append(rep["iters"])
             sb = step_bytes(p, rep, args.precision, args.precond)
-            tot["A"] += sb["A"]
-            tot["B"] += sb["B"]
+            for kk in tot:
+                tot[kk] += sb[kk]
             if (k + 1) % 20 == 0:
                 log(f"step {k + 1}/{args.steps}: iters {rep['iters']} outer {rep['outer']}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = {"A": g.profile_read(0), "B": g.profile_read(1)}
+        prof = {k: g.profile_read(i) for i, k in enumerate(kernels_of(args.precond))}
         g.profile(False)
         elapsed = t1 - t0
         value = dof * args.steps / elapsed
@@ -327,7 +342,7 @@ def run_single(args, out):
                        "p99": float(np.percentile(lat_ms, 99)), "max": float(lat_ms.max())},
         "pcg_iters_per_step": {"mean": it.mean(axis=0).tolist(), "max": it.max(axis=0).tolist()},
         "accuracy_vs_oracle": acc, "coupled_fp64": coupled, "plain_fp64": plain,
-        "roofline": roof, "roofline_other_kernel": roof2,
+        "roofline": roof, "roofline_other_kernels": roof2,
     })
     if args.precision == "mixed":
         out["dtype"] = "f32+f64"
@@ -360,7 +375,7 @@ def run_batch(args, out):
             g.set_states(p.initial_state())
         b.profile(True, every=args.sample_every)
         lat = []
-        tot = {"A": 0.0, "B": 0.0}
+        tot = {k: 0.0 for k in kernels_of(args.precond)}
         iters_max = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -370,15 +385,15 @@ def run_batch(args, out):
             lat.append(time.perf_counter() - ts)
             for p, r in zip(probs, reps):
                 sb = step_bytes(p, r, args.precision, args.precond)
-                tot["A"] += sb["A"]
-                tot["B"] += sb["B"]
+                for kk in tot:
+                    tot[kk] += sb[kk]
             iters_max.append(max(max(r["iters"]) for r in reps))
             if (k + 1) % 10 == 0:
                 log(f"step {k + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms, "
                     f"max iters {iters_max[-1]}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = {"A": b.profile_read(0), "B": b.profile_read(1)}
+        prof = {k: b.profile_read(i) for i, k in enumerate(kernels_of(args.precond))}
         b.profile(False)
         elapsed = t1 - t0
         value = dof * args.steps / elapsed
@@ -444,7 +459,7 @@ def run_batch(args, out):
         "pcg_iters_max_per_step": {"mean": float(np.mean(iters_max)),
                                    "max": int(np.max(iters_max))},
         "accuracy_vs_oracle": acc, "coupled_fp64": coupled, "plain_fp64": plain,
-        "roofline": roof, "roofline_other_kernel": roof2,
+        "roofline": roof, "roofline_other_kernels": roof2,
     })
 
 

@@ -227,12 +227,15 @@ const char *mc_last_error(const mc_problem *p);
 
 /* Kernel timing on the problem's streams: HIP events bound to the dispatch of sampled
    launches of the grid PCG kernels time the kernel execution itself.  which: 0 = grid
-   operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z = M^-1 r).
-   enable >= 1 starts recording and clears the totals, sampling one launch in `enable`
-   (1 = every launch; each sampled launch costs the stream a few microseconds); 0 stops.
-   While timing is on, PCG iterations are launched one by one instead of replayed from
-   captured graphs.  mc_profile_read returns the number of sampled launches and their summed
-   duration, and the number of launches issued while timing was on (sampled or not). */
+   operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z = M^-1 r;
+   under MC_MG its sweep is the finest pre-smoothing), 2 = (MC_MG) the finest level's
+   correction and post-smoothing, which writes z.  enable >= 1 starts recording and clears
+   the totals, sampling the kernels of one PCG iteration in `enable` (1 = every iteration;
+   each sampled launch costs the stream a few microseconds); 0 stops.  Sampled iterations
+   are launched one by one, the others still replayed from captured graphs.
+   mc_profile_read returns the number of sampled launches and their summed duration, and
+   the number of launches issued while timing was on (sampled or not); which outside 0..2
+   gives MC_EINVAL. */
 mc_status mc_profile(mc_problem *p, int32_t enable);
 mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *sampled, double *sampled_ms,
                           int64_t *issued);

@@ -124,11 +124,12 @@ def aggregate_prolongator(nx: int, ny: int):
     return P, cnx, cny
 
 
-def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256):
+def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256, coarse_rows: int = 4):
     """Levels of the V-cycle of the grid operator K (nx x ny cells, row-major): Galerkin
     coarse operators P^T K P until at most `coarse` cells remain; block IC(0) factors on
-    64 x 16 blocks on every level above the coarsest; the coarsest level's dense inverse.
-    A grid of at most `coarse` cells has one level and the cycle is plain block IC(0)."""
+    64 x 16 blocks on the finest level and 64 x `coarse_rows` blocks on the coarse levels
+    above the coarsest; the coarsest level's dense inverse.  A grid of at most `coarse`
+    cells has one level and the cycle is plain block IC(0)."""
     K = sp.csr_matrix(K)
     levels = [dict(K=K, nx=nx, ny=ny, facs=block_precond(K, grid_tile_blocks(nx, ny)))]
     while nx * ny > coarse:
@@ -137,7 +138,7 @@ def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256):
         K = sp.csr_matrix(P.T @ K @ P)
         lev = dict(K=K, nx=nx, ny=ny)
         if nx * ny > coarse:
-            lev["facs"] = block_precond(K, grid_tile_blocks(nx, ny))
+            lev["facs"] = block_precond(K, grid_tile_blocks(nx, ny, ty=coarse_rows))
         else:
             lev["inv"] = np.linalg.inv(K.toarray())
         levels.append(lev)

@@ -17,9 +17,12 @@
 #define MC_TY 32               // grid tile height (rows) of the LDS-staged operator
 #define MC_ICY 16              // rows of a grid block of the block IC(0) preconditioner
 #define MC_ICB (MC_TY / MC_ICY)  // IC(0) blocks per grid tile
+#define MC_ICYC 4              // rows of an IC(0) block on the coarse levels of a V-cycle
 #define MC_SCHUR_ROWS 16       // rows of the crossing-cell inverse per workgroup
 #define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
 #define MC_MG_COARSE 256       // multigrid levels stop at this many cells (dense inverse there)
+#define MC_MG_TAIL 4096        // levels of at most this many cells run in one workgroup
+#define MC_TAIL_THREADS 512    // threads of that workgroup
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };
 enum { PREC_JACOBI = 0, PREC_BIC0 = 1 };

@@ -140,8 +140,9 @@ struct Table {
   int nparts = 0;
   std::vector<PartD> hparts;
   std::vector<int> htil;                      // tiles and the three workgroup counts per part
-  // multigrid tile lists per level: [0] restrict into the level, [1] smoothing, [2] dense
-  // coarsest solve, [3] post-smoothing (level 0: the final one, writing partial slots)
+  // multigrid tile lists per level: [0] restriction into the level, [1] smoothing, [2] the
+  // small levels from this one down in one workgroup, [3] post-smoothing (level 0: the final
+  // one, writing partial slots)
   struct List {
     Tile* t = nullptr;
     int n = 0, cap = 0;
@@ -223,6 +224,11 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     if (q.kind == PART_GRID && (q.mg_next >= 0 || q.mg_level > 0)) L = std::max(L, q.mg_level + 1);
   if ((int)T.mg.size() < L) T.mg.resize(L);
   std::vector<std::vector<Tile>> mgv(4 * std::max(L, 1));
+  // a coarse level of at most MC_MG_TAIL cells belongs to its chain's tail (a suffix of the
+  // levels), which one workgroup runs from the tail's first level down and back up
+  // (MCDEC_MG_TAIL overrides the size; the coarsest level is always in the tail)
+  static const long tail_n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
+  auto in_tail = [&](const PartD& q) { return q.mg_level > 0 && (long)q.n <= tail_n; };
   for (int pi = 0; pi < (int)parts.size(); ++pi) {
     const PartD& q = parts[pi];
     if (q.kind != PART_GRID || (q.mg_next < 0 && q.mg_level == 0)) continue;
@@ -233,19 +239,27 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
       for (int b = 0; b < nb; ++b)
         v.push_back(Tile{pi, slot0 + b, (int)((long)b * ntile / nb), (int)((long)(b + 1) * ntile / nb)});
     };
-    if (l > 0) {                                     // restrict into l: the finer level's tiles
+    bool tail_start = false;
+    if (l > 0) {
       if (q.mg_prev < 0 || q.mg_prev >= (int)parts.size())
         throw Error{MC_EDEVICE, "multigrid level without a finer level"};
       const PartD& f = parts[q.mg_prev];
+      if (in_tail(q) && in_tail(f)) continue;          // run inside its tail's workgroup
+      if (!in_tail(q) && q.mg_next < 0)
+        throw Error{MC_EDEVICE, "coarsest multigrid level outside the small-level tail"};
+      tail_start = in_tail(q);
       const int ntf = (int)(cdiv(f.nx, MC_TX) * cdiv(f.ny, MC_TY));
-      add(0, ntf, ntf, 0);
+      add(0, ntf, ntf, 0);                             // restriction into l: finer tiles
     }
-    if (l > 0 && q.mg_next >= 0) add(1, (int)cdiv(nt, 2), nt, 0);         // smoothing
-    if (l > 0 && q.mg_next < 0) add(2, (int)cdiv(q.n, MC_SCHUR_ROWS), (int)cdiv(q.n, MC_SCHUR_ROWS), 0);
-    if (q.mg_next >= 0) {                                                  // post-smoothing
-      if (l == 0) add(3, til[pi].blocks[1], nt, q.mg_slot);
-      else add(3, (int)cdiv(nt, 2), nt, 0);
+    if (tail_start) {
+      add(2, 1, 1, 0);
+      continue;
     }
+    // coarse levels: ranges of IC(0) blocks (MC_ICYC rows), one per wavefront
+    const int units = nt * (MC_TY / MC_ICYC);
+    if (l > 0) add(1, (int)cdiv(units, 4), units, 0);  // smoothing
+    if (l == 0) add(3, til[pi].blocks[1], nt, q.mg_slot);
+    else add(3, (int)cdiv(units, 4), units, 0);        // post-smoothing
   }
   for (int l = 0; l < L; ++l)
     for (int op = 0; op < 4; ++op) {
@@ -342,9 +356,10 @@ struct Exec {
   bool prof = false;
   struct Ev { hipEvent_t a, b; int which; };
   std::vector<Ev> ev_free, ev_pending;
-  long prof_launch[2] = {0, 0};
-  double prof_ms[2] = {0, 0};
-  long prof_count[2] = {0, 0};
+  // [0] grid operator, [1] grid update, [2] finest V-cycle post-smoothing kernel
+  long prof_launch[3] = {0, 0, 0};
+  double prof_ms[3] = {0, 0, 0};
+  long prof_count[3] = {0, 0, 0};
   int prof_every = 8;
 };
 
@@ -830,8 +845,9 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
       gi.tx = L.tx;
       gi.ty = L.ty;
       gi.dinv = L.fdinv;
-      hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)L.tiles * MC_ICB, 64)), dim3(64), 0,
-                         s, gi);
+      gi.rows = MC_ICYC;
+      hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)L.tiles * (MC_TY / MC_ICYC), 64)),
+                         dim3(64), 0, s, gi);
       cv(L.fdinv, L.fdinv32, L.n);
     } else {
       const long nn = L.n * L.n;
@@ -934,6 +950,7 @@ static void build_coefficients(mc_problem* P) {
         g.tx = C.tx;
         g.ty = C.ty;
         g.dinv = C.fdinv;
+        g.rows = MC_ICY;
         hipLaunchKernelGGL(k_setup_grid_ic0, dim3(cdiv((long)C.tiles * MC_ICB, 64)), dim3(64),
                            0, s, g);
       } else {
@@ -956,6 +973,13 @@ static void build_coefficients(mc_problem* P) {
   }
   for (auto& C : P->cont) C.mg_on = false;
   if (P->X.opt.precond == MC_MG) {
+    for (auto& C : P->cont)   // the V-cycle's residuals use the operator's FP32 copies
+      if (C.kind == PART_GRID) {
+        if (!C.diag32) C.diag32 = P->mem.alloc<float>(C.n);
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(C.n, 256)), dim3(256), 0, s, C.diag, C.diag32,
+                           C.n);
+      }
+    HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     for (auto& C : P->cont)
       if (C.kind == PART_GRID) setup_multigrid(P, C);
@@ -1193,11 +1217,13 @@ static void launch_schur(Exec& X, const Table& Tb, hipStream_t s) {
 }
 
 // V-cycle of the grid parts that have coarse levels, after the kernel that wrote their
-// finest pre-smoothed z_p: restriction, smoothing and coarsest solves going down, the
-// corrections with post-smoothing going up.  The finest post-smoothing writes z and, when
+// finest pre-smoothed z_p: restriction and smoothing going down (the small levels, the
+// coarsest solve among them, in one workgroup per chain), the corrections with
+// post-smoothing going up.  The finest post-smoothing writes z and, when
 // `final`, (r, z) to the update slots.  `sys` null: no test of the solve's end.
 template <class T>
-static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool final) {
+static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool final,
+                          Exec* X = nullptr) {
   const int L = (int)Tb.mg.size();
   if (L == 0 || Tb.mg[0][3].n == 0) return;
   auto go = [&](auto kern, const Table::List& li) {
@@ -1205,12 +1231,22 @@ static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool fi
   };
   for (int l = 1; l < L; ++l) {
     go(k_mg_restrict<T>, Tb.mg[l][0]);
+    if (Tb.mg[l][2].n)
+      hipLaunchKernelGGL(k_mg_tail<T>, dim3(Tb.mg[l][2].n), dim3(MC_TAIL_THREADS), 0, s,
+                         Tb.parts, Tb.mg[l][2].t, sys);
     go(k_mg_smooth<T>, Tb.mg[l][1]);
-    go(k_mg_dense<T>, Tb.mg[l][2]);
   }
-  for (int l = L - 2; l >= 1; --l) go(k_mg_post<T, false>, Tb.mg[l][3]);
-  if (final) go(k_mg_post<T, true>, Tb.mg[0][3]);
-  else go(k_mg_post<T, false>, Tb.mg[0][3]);
+  for (int l = L - 2; l >= 1; --l) go(k_mg_post_c<T>, Tb.mg[l][3]);
+  if (!final) {
+    go(k_mg_post<T, false>, Tb.mg[0][3]);
+  } else if (X && X->prof && (X->prof_count[2]++ % X->prof_every) == 0) {
+    Exec::Ev e = prof_take(*X, 2);   // timed like the PCG kernels
+    hipExtLaunchKernelGGL(k_mg_post<T, true>, dim3(Tb.mg[0][3].n), dim3(MC_BLOCK), 0, s, e.a,
+                          e.b, 0, Tb.parts, Tb.mg[0][3].t, sys);
+    X->ev_pending.push_back(e);
+  } else {
+    go(k_mg_post<T, true>, Tb.mg[0][3]);
+  }
 }
 
 // One PCG iteration over the group's tiles: operator kernels, then update kernels.
@@ -1236,7 +1272,7 @@ static void launch_iter(Exec& X, Group& G, bool timed) {
   L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0);
   L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0);
   L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1);
-  if (G.kinds & 1) launch_vcycle<T>(Tb, G.s, X.sys, true);
+  if (G.kinds & 1) launch_vcycle<T>(Tb, G.s, X.sys, true, timed ? &X : nullptr);
   L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1);
   if (G.kinds & 2) launch_schur<T>(X, Tb, G.s);
 }
@@ -1268,16 +1304,39 @@ static hipGraphExec_t chunk_graph(Exec& X, Group& G, int K) {
   return e;
 }
 
-// K iterations: replayed from captured graphs of power-of-two lengths, or launched one by
-// one while kernel timing is on (or graphs are switched off).
+// K iterations: replayed from captured graphs of power-of-two lengths (or launched one by one
+// when graphs are switched off).  While kernel timing is on, the iterations whose grid
+// kernels are due for a sample (one in prof_every) are launched one by one with timing
+// events, the others still replayed; the issue counters count both.
 template <class T, int PREC>
 static void launch_chunk(Exec& X, Group& G, int K) {
-  if (!X.graphs || X.prof) {
+  if (!X.graphs) {
     for (int j = 0; j < K; ++j) launch_iter<T, PREC>(X, G, true);
     return;
   }
-  for (int b = 0; (1 << b) <= K; ++b)
-    if (K >> b & 1) HIPCHK(hipGraphLaunch(chunk_graph<T, PREC>(X, G, 1 << b), G.s));
+  auto replay = [&](int m) {
+    for (int b = 0; (1 << b) <= m; ++b)
+      if (m >> b & 1) HIPCHK(hipGraphLaunch(chunk_graph<T, PREC>(X, G, 1 << b), G.s));
+  };
+  const bool grid = (G.kinds & 1) && G.T->nblk[0][PART_GRID] > 0;
+  if (!X.prof || !grid) {
+    replay(K);
+    return;
+  }
+  const bool post = G.T->mg.size() > 0 && G.T->mg[0][3].n > 0;
+  while (K > 0) {
+    const long c = X.prof_count[1];
+    if (c % X.prof_every == 0) {
+      launch_iter<T, PREC>(X, G, true);
+      --K;
+      continue;
+    }
+    const int m = (int)std::min<long>(K, X.prof_every - c % X.prof_every);
+    replay(m);
+    for (int w = 0; w < 3; ++w)
+      if (w < 2 || post) X.prof_count[w] += m;
+    K -= m;
+  }
 }
 
 // launch the grid-kind kernel over the grid tiles and the graph-kind kernel over the graph
@@ -1943,6 +2002,7 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
     A(8 * MC_SLOT * slots);       // partials of its decoupled system
     A(8 * MC_SLOT * slots);
     if (grid && o.precond == MC_MG) {   // V-cycle levels
+      if (!mixed) A(4 * n);               // FP32 diagonal of the V-cycle's residuals
       int64_t lx = d.nx, ly = d.ny;
       if (lx * ly > MC_MG_COARSE) {
         A(8 * n);                 // pre-smoothed z of the finest level
@@ -2297,9 +2357,11 @@ static mc_status exec_profile(mc::Exec& X, int32_t enable) {
   mc::prof_harvest(X);
   X.prof = enable != 0;
   if (enable) {
-    X.prof_launch[0] = X.prof_launch[1] = 0;
-    X.prof_ms[0] = X.prof_ms[1] = 0;
-    X.prof_count[0] = X.prof_count[1] = 0;
+    for (int k = 0; k < 3; ++k) {
+      X.prof_launch[k] = 0;
+      X.prof_ms[k] = 0;
+      X.prof_count[k] = 0;
+    }
     X.prof_every = enable;
   }
   return MC_OK;
@@ -2307,6 +2369,7 @@ static mc_status exec_profile(mc::Exec& X, int32_t enable) {
 
 static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* sampled,
                                    double* sampled_ms, int64_t* issued) {
+  if (which < 0 || which > 2) return MC_EINVAL;
   HIPCHK(hipStreamSynchronize(X.stream));
   mc::prof_harvest(X);
   if (sampled) *sampled = X.prof_launch[which];
@@ -2324,7 +2387,7 @@ mc_status mc_profile(mc_problem* P, int32_t enable) {
 
 mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* sampled, double* sampled_ms,
                           int64_t* issued) {
-  if (!P || which < 0 || which > 1) return MC_EINVAL;
+  if (!P || which < 0 || which > 2) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read(P->X, which, sampled, sampled_ms, issued);
   ABI_END(P)
@@ -2429,7 +2492,7 @@ mc_status mc_batch_profile(mc_batch* B, int32_t enable) {
 
 mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* sampled,
                                 double* sampled_ms, int64_t* issued) {
-  if (!B || which < 0 || which > 1) return MC_EINVAL;
+  if (!B || which < 0 || which > 2) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read(B->X, which, sampled, sampled_ms, issued);
   ABI_END(B)

@@ -277,21 +277,23 @@ __device__ __forceinline__ double graph_coupling(const PartD& P, int l, const VP
 // ------------------------------------------------------------------------------------
 struct GridIC0Setup {
   int nx, ny, tiles_x, ntiles;
+  int rows;       // block height: MC_ICY (a continuum) or MC_ICYC (a coarse level)
   const double* diag;
   const double* tx;
   const double* ty;
   double* dinv;   // first holds d, then 1/d
 };
 
-// One thread per IC(0) block (64 columns x MC_ICY rows): pivots in natural order (row by
+// One thread per IC(0) block (64 columns x g.rows rows): pivots in natural order (row by
 // row, west to east) with the west and south couplings that stay inside the block.
 __global__ void k_setup_grid_ic0(GridIC0Setup g) {
+  const int per = MC_TY / g.rows;   // blocks per tile
   const int unit = blockIdx.x * blockDim.x + threadIdx.x;
-  if (unit >= g.ntiles * MC_ICB) return;
-  const int tile = unit / MC_ICB;
+  if (unit >= g.ntiles * per) return;
+  const int tile = unit / per;
   const int x0 = (tile % g.tiles_x) * MC_TX;
-  const int y0 = (tile / g.tiles_x) * MC_TY + (unit % MC_ICB) * MC_ICY;
-  const int x1 = min(x0 + MC_TX, g.nx), y1 = min(y0 + MC_ICY, g.ny);
+  const int y0 = (tile / g.tiles_x) * MC_TY + (unit % per) * g.rows;
+  const int x1 = min(x0 + MC_TX, g.nx), y1 = min(y0 + g.rows, g.ny);
   if (y0 >= g.ny) return;
   for (int y = y0; y < y1; ++y)
     for (int x = x0; x < x1; ++x) {
@@ -337,6 +339,17 @@ __device__ __forceinline__ void combine_dpp(T& A, T& B) {
   A = A + B * Ap;
   B = B * Bp;
 }
+// value of lane l (wave-uniform result)
+__device__ __forceinline__ double readlane_t(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ float readlane_t(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
 // Inclusive prefix over the 64 lanes, lane 0 applied first: row_shr 1,2,4,8 inside each
 // row of 16 lanes, then row_bcast:15 (rows 1, 3 take the end of the row before) and
 // row_bcast:31 (rows 2, 3 take lane 31).
@@ -358,22 +371,21 @@ __device__ __forceinline__ void scan_maps_down(T& A, T& B) {
   combine_dpp<0x104, 0xF>(A, B);
   combine_dpp<0x108, 0xF>(A, B);
   const int lane = threadIdx.x & 63, row = lane >> 4;
-  // the shuffles run on every lane (a lane can only read lanes that execute them); the
-  // lanes that do not take a value then combine with the identity
+  // the values crossing rows come from single lanes (16, 48, then 32): lane reads into
+  // scalar registers; the lanes that take no value combine with the identity
   {
-    const int src = ((row + 1) << 4) & 63;
-    const bool take = row == 0 || row == 2;
-    T Ap = __shfl(A, src, 64), Bp = __shfl(B, src, 64);
-    Ap = take ? Ap : (T)0;
-    Bp = take ? Bp : (T)1;
+    const T A16 = readlane_t(A, 16), B16 = readlane_t(B, 16);
+    const T A48 = readlane_t(A, 48), B48 = readlane_t(B, 48);
+    const T Ap = row == 0 ? A16 : (row == 2 ? A48 : (T)0);
+    const T Bp = row == 0 ? B16 : (row == 2 ? B48 : (T)1);
     A = A + B * Ap;
     B = B * Bp;
   }
   {
     const bool take = row < 2;
-    T Ap = __shfl(A, 32, 64), Bp = __shfl(B, 32, 64);
-    Ap = take ? Ap : (T)0;
-    Bp = take ? Bp : (T)1;
+    const T A32 = readlane_t(A, 32), B32 = readlane_t(B, 32);
+    const T Ap = take ? A32 : (T)0;
+    const T Bp = take ? B32 : (T)1;
     A = A + B * Ap;
     B = B * Bp;
   }
@@ -460,23 +472,28 @@ __device__ void chain_solve(const T* __restrict__ rin, T* __restrict__ z,
 }
 
 // One block of the grid block IC(0) preconditioner as seen by one wavefront: 64 columns
-// (lane = column) by MC_ICY rows.  cell(y) is a valid cell index for every lane (clamped
-// to the grid), act(y) says whether this lane's cell of row y exists.
-struct IcBlk {
+// (lane = column) by R rows (MC_ICY on a continuum, MC_ICYC on the coarse levels of a
+// V-cycle).  cell(y) is a valid cell index for every lane (clamped to the grid), act(y)
+// says whether this lane's cell of row y exists.
+template <int R>
+struct IcBlkR {
+  static constexpr int rows = R;
   int cx, cxs, y0, nx, ny;
   bool colact;
-  __device__ IcBlk(const PartD& P, int unit) {
-    const int tile = unit / MC_ICB;   // unit = IC(0) block: tile and its band of MC_ICY rows
+  __device__ IcBlkR(const PartD& P, int unit) {
+    constexpr int per = MC_TY / R;   // unit = IC(0) block: tile and its band of R rows
+    const int tile = unit / per;
     nx = P.nx;
     ny = P.ny;
     cx = (tile % P.tiles_x) * MC_TX + (int)(threadIdx.x & 63);
     cxs = min(cx, nx - 1);
-    y0 = (tile / P.tiles_x) * MC_TY + (unit % MC_ICB) * MC_ICY;
+    y0 = (tile / P.tiles_x) * MC_TY + (unit % per) * R;
     colact = cx < nx;
   }
   __device__ bool act(int y) const { return colact && y0 + y < ny; }
   __device__ long cell(int y) const { return (long)min(y0 + y, ny - 1) * nx + cxs; }
 };
+using IcBlk = IcBlkR<MC_ICY>;
 
 // Block IC(0) solve on one grid block by one wavefront, entirely in registers.  rv holds
 // this lane's residual in the block's rows (0 for cells outside the grid); the caller loads
@@ -488,18 +505,18 @@ struct IcBlk {
 // Dot products: with M = (D + E) D^-1 (D + E^T), the forward values u = (D + E)^-1 r and
 // z = M^-1 r satisfy (D + E^T) z = D u, hence (r, z) = (M z, z) = sum_i d_i u_i^2: both
 // (r,z) and (r,r) are complete after the forward sweep, so r never has to stay live.
-template <class T, bool HAS_T, class EZ>
-__device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
-                                          const T (&rv)[MC_ICY], const EZ& emit_z,
+template <class T, bool HAS_T, int R, class EZ>
+__device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlkR<R>& B,
+                                          const T (&rv)[R], const EZ& emit_z,
                                           double& rz, double& rr) {
   const int lane = threadIdx.x & 63;
   const gconst<float> dinv = gc(P.fdinv32);
   const gconst<float> tx = gc(P.tx32);
   const gconst<float> ty = gc(P.ty32);
   const float tc = (float)P.tconst;
-  float dv[MC_ICY], te[MC_ICY], tn[MC_ICY];
+  float dv[R], te[R], tn[R];
 #pragma unroll
-  for (int y = 0; y < MC_ICY; ++y) {
+  for (int y = 0; y < R; ++y) {
     const bool act = B.act(y);
     const long i = B.cell(y);
     const float d = dinv[i];
@@ -513,12 +530,12 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
     }
     dv[y] = act ? d : 0.0f;
     te[y] = act ? e : 0.0f;
-    tn[y] = act && y + 1 < MC_ICY ? n : 0.0f;   // couplings inside the block only
+    tn[y] = act && y + 1 < R ? n : 0.0f;   // couplings inside the block only
   }
-  T u[MC_ICY];
+  T u[R];
   T uprev = (T)0;
 #pragma unroll
-  for (int y = 0; y < MC_ICY; ++y) {
+  for (int y = 0; y < R; ++y) {
     const T ri = rv[y];
     const T di = (T)dv[y];
     // west conductance = east conductance of the lane to the left (0 for lane 0)
@@ -536,7 +553,7 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
   }
   T zabove = (T)0;
 #pragma unroll
-  for (int y = MC_ICY - 1; y >= 0; --y) {
+  for (int y = R - 1; y >= 0; --y) {
     const T di = (T)dv[y];
     const T e = lane < 63 ? (T)te[y] : (T)0;
     T a = u[y] + (T)tn[y] * zabove * di;
@@ -548,18 +565,18 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlk& B,
 }
 
 // z = M^-1 r on one block, handing each z value to emit_z(row, value)
-template <class T, class EZ>
-__device__ __forceinline__ void ic0_block_f(const PartD& P, const IcBlk& B,
-                                            const T (&rv)[MC_ICY], const EZ& emit_z, double& rz,
+template <class T, int R, class EZ>
+__device__ __forceinline__ void ic0_block_f(const PartD& P, const IcBlkR<R>& B,
+                                            const T (&rv)[R], const EZ& emit_z, double& rz,
                                             double& rr) {
-  if (P.has_t) ic0_sweep<T, true>(P, B, rv, emit_z, rz, rr);
-  else ic0_sweep<T, false>(P, B, rv, emit_z, rz, rr);
+  if (P.has_t) ic0_sweep<T, true, R>(P, B, rv, emit_z, rz, rr);
+  else ic0_sweep<T, false, R>(P, B, rv, emit_z, rz, rr);
 }
 
-template <class T>
-__device__ __forceinline__ void ic0_block(const PartD& P, const IcBlk& B, const T (&rv)[MC_ICY],
+template <class T, int R>
+__device__ __forceinline__ void ic0_block(const PartD& P, const IcBlkR<R>& B, const T (&rv)[R],
                                           T* __restrict__ zout, double& rz, double& rr) {
-  ic0_block_f<T>(P, B, rv, [&](int y, T a) {
+  ic0_block_f<T, R>(P, B, rv, [&](int y, T a) {
     if (B.act(y)) zout[B.cell(y)] = a;
   }, rz, rr);
 }
@@ -1364,24 +1381,25 @@ __global__ void k_fill0(double* __restrict__ a, long n) {
   if (i < n) a[i] = 0.0;
 }
 
-// Row-wise 5-point product on a wavefront whose lane l holds column x = x0 + l of one row:
+// Row-wise 5-point product on a wavefront whose lane l holds column x = x0 + l of one row
+// (the operator's FP32 copies: inside the preconditioner they need no more):
 // (A v)_x with the west / east values of v from the neighbouring lanes and, at lanes 0 and
 // 63, from `vh` (the lane's halo value: column x0 - 1 at lane 0, x0 + 64 at lane 63).
 // te: this column's east face conductance; th: the halo column's (lane 0 takes it as its
 // west face); ts / tn: south / north faces.  Without a conductance field every face is tc.
 // Every lane must call it (the lane moves are wave-wide).
 template <class T, bool HAS_T>
-__device__ __forceinline__ T row_Av(int x, int nx, bool south, bool north, T d, T vc, T vh,
-                                    T vs, T vn, T te, T th, T ts, T tn, T tc) {
+__device__ __forceinline__ T row_Av(int x, int nx, bool south, bool north, float d, T vc, T vh,
+                                    T vs, T vn, float te, float th, float ts, float tn, T tc) {
   const T vw = dpp_d<0x138, 0xF>(vh, vc);   // wave_shr:1, lane 0 keeps vh
   const T ve = dpp_d<0x130, 0xF>(vh, vc);   // wave_shl:1, lane 63 keeps vh
-  T acc = d * vc;
+  T acc = (T)d * vc;
   if constexpr (HAS_T) {
-    const T tw = dpp_d<0x138, 0xF>(th, te);
-    if (x > 0) acc -= tw * vw;
-    if (x + 1 < nx) acc -= te * ve;
-    if (south) acc -= ts * vs;
-    if (north) acc -= tn * vn;
+    const float tw = dpp_d<0x138, 0xF>(th, te);
+    if (x > 0) acc -= (T)tw * vw;
+    if (x + 1 < nx) acc -= (T)te * ve;
+    if (south) acc -= (T)ts * vs;
+    if (north) acc -= (T)tn * vn;
   } else {
     T sum = (T)0;
     if (x > 0) sum += vw;
@@ -1393,63 +1411,157 @@ __device__ __forceinline__ T row_Av(int x, int nx, bool south, bool north, T d, 
   return acc;
 }
 
-// r_c = P^T (r - A z_p) of the finer level F, swept over F's tiles: a wavefront takes
-// MC_TY / 4 consecutive fine rows of a 64-column band (lane = fine column), loads every
-// value it needs first, forms the fine residuals, and sums each 2 x 2 aggregate over a row
-// pair and a lane pair (tiles start at even columns and rows, so no aggregate straddles
-// two wavefronts).
+// r_c = P^T (r - A z_p) of the finer level F on one band of MC_TY / 4 fine rows of fine tile
+// `tile` (band 0..3), by one wavefront (lane = fine column): every value it needs is loaded
+// first, then the fine residuals are formed and each 2 x 2 aggregate is summed over a row
+// pair and a lane pair (tiles and bands start at even columns and rows, so no aggregate
+// straddles two wavefronts).
 template <class T, bool HAS_T>
-__device__ __forceinline__ void restrict_tiles(const PartD& F, const PartD& C, const Tile& t) {
-  constexpr int R = MC_TY / 4;   // fine rows per wavefront (even)
+__device__ __forceinline__ void restrict_band(const PartD& F, const PartD& C, int tile,
+                                              int band) {
+  constexpr int R = MC_TY / 4;   // fine rows per band (even)
+  const int nx = F.nx, ny = F.ny, cnx = C.nx, lane = threadIdx.x & 63;
+  const int x0 = (tile % F.tiles_x) * MC_TX;
+  const int ya = (tile / F.tiles_x) * MC_TY + band * R;
+  if (ya >= ny) return;   // wave-uniform
   const T* rf = (const T*)(F.mg_level == 0 ? F.r : F.mg_r);   // level 0: the PCG residual
   const T* zf = (const T*)F.mg_zp;
   T* rc = (T*)C.mg_r;
-  const T* d = pick<T>(F.diag, F.diag32);
-  const T* txp = pick<T>(F.tx, F.tx32);
-  const T* typ = pick<T>(F.ty, F.ty32);
+  const float* d = F.diag32;
+  const float* txp = F.tx32;
+  const float* typ = F.ty32;
   const T tc = (T)F.tconst;
-  const int lane = threadIdx.x & 63, nx = F.nx, ny = F.ny, cnx = C.nx;
-  for (int tile = t.t0; tile < t.t1; ++tile) {
-    const int x0 = (tile % F.tiles_x) * MC_TX;
-    const int ya = (tile / F.tiles_x) * MC_TY + (int)(threadIdx.x >> 6) * R;
-    if (ya >= ny) continue;   // wave-uniform
-    const int x = x0 + lane, xs = min(x, nx - 1);
-    const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : xs);
-    auto row = [&](int j) { return (long)min(max(ya + j, 0), ny - 1) * nx; };
-    T z[R + 2], zh[R], rv[R], dv[R], te[R], th[R], ty[R + 1];
+  const int x = x0 + lane, xs = min(x, nx - 1);
+  const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : xs);
+  auto row = [&](int j) { return (long)min(max(ya + j, 0), ny - 1) * nx; };
+  T z[R + 2], zh[R], rv[R];
+  float dv[R], te[R], th[R], ty[R + 1];
 #pragma unroll
-    for (int j = 0; j < R + 2; ++j) z[j] = zf[row(j - 1) + xs];
+  for (int j = 0; j < R + 2; ++j) z[j] = zf[row(j - 1) + xs];
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const long o = row(j);
-      zh[j] = zf[o + hx];
-      rv[j] = rf[o + xs];
-      dv[j] = d[o + xs];
-      te[j] = HAS_T ? txp[o + xs] : (T)0;
-      th[j] = HAS_T ? txp[o + hx] : (T)0;
+  for (int j = 0; j < R; ++j) {
+    const long o = row(j);
+    zh[j] = zf[o + hx];
+    rv[j] = rf[o + xs];
+    dv[j] = d[o + xs];
+    te[j] = HAS_T ? txp[o + xs] : 0.0f;
+    th[j] = HAS_T ? txp[o + hx] : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < R + 1; ++j) ty[j] = HAS_T ? typ[row(j - 1) + xs] : 0.0f;
+  double s[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int y = ya + j;
+    const T a = row_Av<T, HAS_T>(x, nx, y > 0, y + 1 < ny, dv[j], z[j + 1], zh[j], z[j],
+                                 z[j + 2], te[j], th[j], ty[j], ty[j + 1], tc);
+    s[j] = (x < nx && y < ny) ? (double)rv[j] - (double)a : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < R; j += 2) {
+    double v = s[j] + s[j + 1];
+    v += __shfl_xor(v, 1, 64);
+    if (!(lane & 1) && x < nx && ya + j < ny) rc[(long)((ya + j) >> 1) * cnx + (x >> 1)] = (T)v;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void restrict_band_any(const PartD& F, const PartD& C, int tile,
+                                                  int band) {
+  if (F.has_t) restrict_band<T, true>(F, C, tile, band);
+  else restrict_band<T, false>(F, C, tile, band);
+}
+
+// z_p = M^-1 r on IC(0) block `unit` of a coarse level (one wavefront)
+template <class T>
+__device__ __forceinline__ void smooth_unit(const PartD& P, int unit) {
+  const T* r = (const T*)P.mg_r;
+  const IcBlkR<MC_ICYC> B(P, unit);
+  T rv[MC_ICYC];
+#pragma unroll
+  for (int y = 0; y < MC_ICYC; ++y) rv[y] = B.act(y) ? r[B.cell(y)] : (T)0;
+  double dz = 0.0, dr = 0.0;
+  ic0_block<T>(P, B, rv, (T*)P.mg_zp, dz, dr);
+}
+
+// z = (z_p + P e) + M^-1 (r - A (z_p + P e)) on IC(0) block `unit`, e the coarser level's
+// solution, by one wavefront: z_p + P e on the block's rows and the rows above and below
+// (west / east values from the neighbouring lanes, the band's edge columns loaded by lanes
+// 0 and 63), the residual of each half of the block from values loaded first, then the
+// sweep.  At the finest level of a PCG solve (FINAL) the result is the PCG vector z and
+// (r, z) is added to rz.
+template <class T, bool FINAL, bool HAS_T, int R>
+__device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const PartD& P,
+                                          int unit, double& rz) {
+  const PartD& Cp = parts[P.mg_next];
+  const T* zp = (const T*)P.mg_zp;
+  const T* e = (const T*)Cp.mg_z;
+  const T* r = (const T*)(P.mg_level == 0 ? P.r : P.mg_r);   // level 0: the PCG vectors
+  T* out = (T*)(P.mg_level == 0 ? P.z : P.mg_z);
+  const float* d = P.diag32;
+  const float* txp = P.tx32;
+  const float* typ = P.ty32;
+  const T tc = (T)P.tconst;
+  const int nx = P.nx, ny = P.ny, cnx = Cp.nx, lane = threadIdx.x & 63;
+  const IcBlkR<R> B(P, unit);
+  const int x0 = B.cx - lane;
+  const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
+  auto rowy = [&](int j) { return min(max(B.y0 + j, 0), ny - 1); };
+  auto zfull = [&](int y, int x) {
+    return zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)];
+  };
+  T zo[R + 2];
+#pragma unroll
+  for (int j = 0; j < R + 2; ++j) zo[j] = zfull(rowy(j - 1), B.cxs);
+  T rl[R], rv[R];
+  constexpr int H = R / 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    T zh[H], rr[H];
+    float dv[H], te[H], th[H], ty[H + 1];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int y = rowy(h * H + j);
+      const long o = (long)y * nx;
+      zh[j] = zfull(y, hx);
+      rr[j] = r[o + B.cxs];
+      dv[j] = d[o + B.cxs];
+      te[j] = HAS_T ? txp[o + B.cxs] : 0.0f;
+      th[j] = HAS_T ? txp[o + hx] : 0.0f;
     }
 #pragma unroll
-    for (int j = 0; j < R + 1; ++j) ty[j] = HAS_T ? typ[row(j - 1) + xs] : (T)0;
-    double s[R];
+    for (int j = 0; j < H + 1; ++j)
+      ty[j] = HAS_T ? typ[(long)rowy(h * H + j - 1) * nx + B.cxs] : 0.0f;
 #pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int y = ya + j;
-      const T a = row_Av<T, HAS_T>(x, nx, y > 0, y + 1 < ny, dv[j], z[j + 1], zh[j], z[j],
-                                   z[j + 2], te[j], th[j], ty[j], ty[j + 1], tc);
-      s[j] = (x < nx && y < ny) ? (double)rv[j] - (double)a : 0.0;
-    }
-#pragma unroll
-    for (int j = 0; j < R; j += 2) {
-      double v = s[j] + s[j + 1];
-      v += __shfl_xor(v, 1, 64);
-      if (!(lane & 1) && x < nx && ya + j < ny)
-        rc[(long)((ya + j) >> 1) * cnx + (x >> 1)] = (T)v;
+    for (int j = 0; j < H; ++j) {
+      const int jj = h * H + j, y = B.y0 + jj;
+      const T a = row_Av<T, HAS_T>(B.cx, nx, y > 0, y + 1 < ny, dv[j], zo[jj + 1], zh[j],
+                                   zo[jj], zo[jj + 2], te[j], th[j], ty[j], ty[j + 1], tc);
+      rl[jj] = rr[j];
+      rv[jj] = B.act(jj) ? rr[j] - a : (T)0;
     }
   }
+  double dz = 0.0, dr = 0.0;
+  ic0_block_f<T, R>(P, B, rv, [&](int y, T a) {
+    if (B.act(y)) {
+      const T zf = zo[y + 1] + a;
+      out[B.cell(y)] = zf;
+      if (FINAL) rz += (double)rl[y] * (double)zf;
+    }
+  }, dz, dr);
+}
+
+template <class T, bool FINAL, int R>
+__device__ __forceinline__ void post_unit_any(const PartD* __restrict__ parts, const PartD& P,
+                                              int unit, double& rz) {
+  if (P.has_t) post_unit<T, FINAL, true, R>(parts, P, unit, rz);
+  else post_unit<T, FINAL, false, R>(parts, P, unit, rz);
 }
 
 // (Every V-cycle kernel skips systems whose solve has ended; `sys` is null for a plain
 // application of the preconditioner.)
+
+// restriction into a level: the workgroup's tiles of the finer level, one band per wavefront
 template <class T>
 __global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restrict__ parts,
                                                           const Tile* __restrict__ tiles,
@@ -1459,11 +1571,12 @@ __global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restric
   const PartD& C = parts[t.part];
   if (sys && ld_flag(&sys[C.sys].done)) return;
   const PartD& F = parts[C.mg_prev];
-  if (F.has_t) restrict_tiles<T, true>(F, C, t);
-  else restrict_tiles<T, false>(F, C, t);
+  for (int tile = t.t0; tile < t.t1; ++tile)
+    restrict_band_any<T>(F, C, tile, (int)(threadIdx.x >> 6));
 }
 
-// z_p = M^-1 r on a level with a coarser one (block IC(0))
+// pre-smoothing on a coarse level with a coarser one; the list entry holds a range of IC(0)
+// blocks (units), one per wavefront
 template <class T>
 __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_mg_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
@@ -1472,111 +1585,25 @@ k_mg_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   if (t.part < 0) return;
   const PartD& P = parts[t.part];
   if (sys && ld_flag(&sys[P.sys].done)) return;
-  const T* r = (const T*)P.mg_r;
-  double dz = 0.0, dr = 0.0;
-  for_wave_tiles(t, [&](int unit) {
-    const IcBlk B(P, unit);
-    T rv[MC_ICY];
-#pragma unroll
-    for (int y = 0; y < MC_ICY; ++y) rv[y] = B.act(y) ? r[B.cell(y)] : (T)0;
-    ic0_block<T>(P, B, rv, (T*)P.mg_zp, dz, dr);
-  });
+  for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) smooth_unit<T>(P, u);
 }
 
-// coarsest level: z = A^-1 r by its dense inverse, one workgroup per MC_SCHUR_ROWS rows
+// coarse correction and post-smoothing on a coarse level (unit ranges, as above)
 template <class T>
-__global__ void __launch_bounds__(MC_BLOCK) k_mg_dense(const PartD* __restrict__ parts,
-                                                       const Tile* __restrict__ tiles,
-                                                       SysState* __restrict__ sys) {
-  __shared__ T rs[MC_MG_COARSE];
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_mg_post_c(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
+            SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
   const PartD& P = parts[t.part];
   if (sys && ld_flag(&sys[P.sys].done)) return;
-  const int n = P.n;
-  const T* r = (const T*)P.mg_r;
-  for (int j = threadIdx.x; j < n; j += MC_BLOCK) rs[j] = r[j];
-  __syncthreads();
-  const gconst<T> inv = gc(pick<T>(P.mg_inv, P.mg_inv32));
-  T* z = (T*)P.mg_z;
-  const int lane = threadIdx.x & 63;
-  const int k1 = min(t.t1 * MC_SCHUR_ROWS, n);
-  for (int k = t.t0 * MC_SCHUR_ROWS + (int)(threadIdx.x >> 6); k < k1; k += 4) {
-    const long row = (long)k * n;
-    double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc += (double)inv[row + j] * (double)rs[j];
-    acc = wave_sum(acc);
-    if (lane == 0) z[k] = (T)acc;
-  }
+  double unused = 0.0;
+  for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4)
+    post_unit_any<T, false, MC_ICYC>(parts, P, u, unused);
 }
 
-// z = (z_p + P e) + M^-1 (r - A (z_p + P e)) with e the coarser level's solution, one
-// wavefront per IC(0) block: z_p + P e on the block's rows and the rows above and below
-// (west / east values from the neighbouring lanes, the band's edge columns loaded by lanes
-// 0 and 63), the residual of each half of the block from values loaded first, then the
-// sweep.  At the finest level of a PCG solve (FINAL) the result is the PCG vector z and the
-// workgroup adds (r, z) to its partial slot.
-template <class T, bool FINAL, bool HAS_T>
-__device__ __forceinline__ void post_blocks(const PartD* __restrict__ parts, const PartD& P,
-                                            const Tile& t, double& rz) {
-  const PartD& Cp = parts[P.mg_next];
-  const T* zp = (const T*)P.mg_zp;
-  const T* e = (const T*)Cp.mg_z;
-  const T* r = (const T*)(P.mg_level == 0 ? P.r : P.mg_r);   // level 0: the PCG vectors
-  T* out = (T*)(P.mg_level == 0 ? P.z : P.mg_z);
-  const T* d = pick<T>(P.diag, P.diag32);
-  const T* txp = pick<T>(P.tx, P.tx32);
-  const T* typ = pick<T>(P.ty, P.ty32);
-  const T tc = (T)P.tconst;
-  const int nx = P.nx, ny = P.ny, cnx = Cp.nx, lane = threadIdx.x & 63;
-  for_wave_tiles(t, [&](int unit) {
-    const IcBlk B(P, unit);
-    const int x0 = B.cx - lane;
-    const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
-    auto rowy = [&](int j) { return min(max(B.y0 + j, 0), ny - 1); };
-    auto zfull = [&](int y, int x) {
-      return zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)];
-    };
-    T zo[MC_ICY + 2];
-#pragma unroll
-    for (int j = 0; j < MC_ICY + 2; ++j) zo[j] = zfull(rowy(j - 1), B.cxs);
-    T rl[MC_ICY], rv[MC_ICY];
-    constexpr int H = MC_ICY / 2;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      T zh[H], rr[H], dv[H], te[H], th[H], ty[H + 1];
-#pragma unroll
-      for (int j = 0; j < H; ++j) {
-        const int y = rowy(h * H + j);
-        const long o = (long)y * nx;
-        zh[j] = zfull(y, hx);
-        rr[j] = r[o + B.cxs];
-        dv[j] = d[o + B.cxs];
-        te[j] = HAS_T ? txp[o + B.cxs] : (T)0;
-        th[j] = HAS_T ? txp[o + hx] : (T)0;
-      }
-#pragma unroll
-      for (int j = 0; j < H + 1; ++j) ty[j] = HAS_T ? typ[(long)rowy(h * H + j - 1) * nx + B.cxs] : (T)0;
-#pragma unroll
-      for (int j = 0; j < H; ++j) {
-        const int jj = h * H + j, y = B.y0 + jj;
-        const T a = row_Av<T, HAS_T>(B.cx, nx, y > 0, y + 1 < ny, dv[j], zo[jj + 1], zh[j],
-                                     zo[jj], zo[jj + 2], te[j], th[j], ty[j], ty[j + 1], tc);
-        rl[jj] = rr[j];
-        rv[jj] = B.act(jj) ? rr[j] - a : (T)0;
-      }
-    }
-    double dz = 0.0, dr = 0.0;
-    ic0_block_f<T>(P, B, rv, [&](int y, T a) {
-      if (B.act(y)) {
-        const T zf = zo[y + 1] + a;
-        out[B.cell(y)] = zf;
-        if (FINAL) rz += (double)rl[y] * (double)zf;
-      }
-    }, dz, dr);
-  });
-}
-
+// coarse correction and post-smoothing on the finest level (tile ranges of the continuum's
+// update tiling); FINAL (inside a PCG solve) adds (r, z) to the workgroup's partial slot
 template <class T, bool FINAL>
 __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_mg_post(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
@@ -1586,9 +1613,67 @@ k_mg_post(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   const PartD& P = parts[t.part];
   if (sys && ld_flag(&sys[P.sys].done)) return;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (P.has_t) post_blocks<T, FINAL, true>(parts, P, t, v[0]);
-  else post_blocks<T, FINAL, false>(parts, P, t, v[0]);
+  for_wave_tiles(t, [&](int unit) { post_unit_any<T, FINAL, MC_ICY>(parts, P, unit, v[0]); });
   if (FINAL) write_slot<5>(sys[P.sys].partB, t.slot, v);
+}
+
+// The small levels of a V-cycle in one workgroup: starting at level part t.part (whose
+// right-hand side is in place), smoothing and restriction down to the coarsest level, its
+// dense solve, then the corrections and post-smoothing back up to the starting level.  The
+// phases are separated by workgroup barriers instead of kernel boundaries.
+template <class T>
+__global__ void __launch_bounds__(MC_TAIL_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
+          SysState* __restrict__ sys) {
+  constexpr int NW = MC_TAIL_THREADS / 64;
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD* P0 = &parts[t.part];
+  if (sys && ld_flag(&sys[P0->sys].done)) return;
+  static_assert(MC_TAIL_THREADS % MC_MG_COARSE == 0, "tail threads: whole columns");
+  const int wave = (int)(threadIdx.x >> 6);
+  const PartD* P = P0;
+  while (P->mg_next >= 0) {
+    const int ntiles = (int)(((P->nx + MC_TX - 1) / MC_TX) * ((P->ny + MC_TY - 1) / MC_TY));
+    for (int u = wave; u < ntiles * (MC_TY / MC_ICYC); u += NW) smooth_unit<T>(*P, u);
+    __syncthreads();
+    const PartD& C = parts[P->mg_next];
+    for (int k = wave; k < ntiles * 4; k += NW) restrict_band_any<T>(*P, C, k >> 2, k & 3);
+    __syncthreads();
+    P = &C;
+  }
+  {   // coarsest: z = A^-1 r by the dense (symmetric) inverse; thread k reads column k, so
+      // each step j reads consecutive entries; the two halves of the sum meet in LDS
+    constexpr int H = MC_TAIL_THREADS / MC_MG_COARSE;
+    __shared__ double part[MC_TAIL_THREADS];
+    const int n = P->n;
+    const T* r = (const T*)P->mg_r;
+    const gconst<T> inv = gc(pick<T>(P->mg_inv, P->mg_inv32));
+    T* z = (T*)P->mg_z;
+    const int k = (int)threadIdx.x % MC_MG_COARSE, h = (int)threadIdx.x / MC_MG_COARSE;
+    const int j0 = h * n / H, j1 = (h + 1) * n / H;
+    double acc = 0.0;
+    if (k < n) {
+#pragma unroll 8
+      for (int j = j0; j < j1; ++j) acc += (double)inv[(long)j * n + k] * (double)r[j];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (h == 0 && k < n) {
+      double s = part[k];
+      for (int q = 1; q < H; ++q) s += part[q * MC_MG_COARSE + k];
+      z[k] = (T)s;
+    }
+    __syncthreads();
+  }
+  while (P != P0) {
+    P = &parts[P->mg_prev];
+    const int ntiles = (int)(((P->nx + MC_TX - 1) / MC_TX) * ((P->ny + MC_TY - 1) / MC_TY));
+    double unused = 0.0;
+    for (int u = wave; u < ntiles * (MC_TY / MC_ICYC); u += NW)
+      post_unit_any<T, false, MC_ICYC>(parts, *P, u, unused);
+    __syncthreads();
+  }
 }
 
 // Per-solve reset of the system records [s0, s1) (a kernel, so the sequence stays free of

@@ -341,3 +341,31 @@ def test_mg_fewer_iterations_than_block_ic0():
             its[pc] = g.step(1)["iters"][0]
     print(its)
     assert its["mg"] * 2 < its["bic0"], its
+
+
+def test_kernel_timing_samples_and_keeps_results():
+    """Kernel timing (one iteration in 4 launched with events, the rest replayed from graphs)
+    counts every issued launch, samples the grid operator, update and (mg) finest
+    post-smoothing kernels, and leaves the trajectory bitwise unchanged."""
+    p = MG_CASES["rect300x270"]()
+    with mcdec.Problem(p, precond="mg", tol=1e-12) as g:
+        g.step(2)
+        ref = g.get_states()
+    with mcdec.Problem(p, precond="mg", tol=1e-12) as g:
+        g.profile(True, every=4)
+        rep = g.step(2)
+        reads = [g.profile_read(w) for w in range(3)]
+        g.profile(False)
+        got = g.get_states()
+    print(rep, reads)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+    for sampled, ms, issued in reads:
+        assert sampled >= 1 and ms > 0 and issued >= sum(rep["iters"][:1])
+        assert sampled <= issued // 4 + 2
+    with pytest.raises(mcdec.McError):
+        g2 = mcdec.Problem(p, precond="mg")
+        try:
+            g2.profile_read(3)
+        finally:
+            g2.close()
