@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 
 DEFAULTS = {
     "C1": dict(precond="jacobi", precision="fp64", tol=1e-12, steps=20, coupled_steps=20),
-    "C2": dict(precond="bic0", precision="fp64", tol=1e-10, steps=100, coupled_steps=5),
-    "C3": dict(precond="bic0", precision="mixed", tol=1e-10, steps=50, coupled_steps=1),
-    "C4": dict(precond="bic0", precision="mixed", tol=1e-10, steps=50, coupled_steps=2),
-    "C5": dict(precond="bic0", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
+    "C2": dict(precond="mg", precision="fp64", tol=1e-10, steps=100, coupled_steps=5),
+    "C3": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=1),
+    "C4": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=2),
+    "C5": dict(precond="mg", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
 }
 
 # HBM bytes per dispatch of the grid PCG kernels, from two rocprofv3 counter passes

@@ -22,7 +22,7 @@
 #define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
 #define MC_MG_COARSE 256       // multigrid levels stop at this many cells (dense inverse there)
 #define MC_MG_TAIL 4096        // levels of at most this many cells run in one workgroup
-#define MC_TAIL_THREADS 512    // threads of that workgroup
+#define MC_TAIL_THREADS 1024   // threads of that workgroup
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };
 enum { PREC_JACOBI = 0, PREC_BIC0 = 1 };

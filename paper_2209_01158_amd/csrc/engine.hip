@@ -718,7 +718,8 @@ static rocblas_handle g_blas = nullptr;
 // In place: the K x K SPD matrix S (column-major, device) -> S^-1 (full, symmetric), by a
 // Cholesky factorization and its inverse (rocSOLVER potrf, potri) and a copy of the lower
 // triangle to the upper one.  Runs once per problem at setup.
-static void invert_spd(double* S, int K, hipStream_t s) {
+static void invert_spd(double* S, int K, hipStream_t s, int lda = 0) {
+  if (lda < K) lda = K;
   std::lock_guard<std::mutex> lk(g_blas_mu);
   if (!g_blas && rocblas_create_handle(&g_blas) != rocblas_status_success) {
     g_blas = nullptr;
@@ -728,8 +729,8 @@ static void invert_spd(double* S, int K, hipStream_t s) {
     throw Error{MC_EDEVICE, "rocblas_set_stream failed"};
   rocblas_int* info = nullptr;
   HIPCHK(hipMalloc((void**)&info, 2 * sizeof(rocblas_int)));
-  rocblas_status a = rocsolver_dpotrf(g_blas, rocblas_fill_lower, K, S, K, info);
-  rocblas_status b = rocsolver_dpotri(g_blas, rocblas_fill_lower, K, S, K, info + 1);
+  rocblas_status a = rocsolver_dpotrf(g_blas, rocblas_fill_lower, K, S, lda, info);
+  rocblas_status b = rocsolver_dpotri(g_blas, rocblas_fill_lower, K, S, lda, info + 1);
   rocblas_int h[2] = {0, 0};
   hipError_t e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -739,7 +740,7 @@ static void invert_spd(double* S, int K, hipStream_t s) {
     throw Error{MC_EDEVICE, "inverse of the crossing-cell Schur complement failed (status " +
                                 std::to_string((int)a) + "/" + std::to_string((int)b) +
                                 ", info " + std::to_string(h[0]) + "/" + std::to_string(h[1]) + ")"};
-  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv((long)K * K, 256)), dim3(256), 0, s, S, K);
+  hipLaunchKernelGGL(k_symmetrize, dim3(cdiv((long)K * K, 256)), dim3(256), 0, s, S, K, lda);
   HIPCHK(hipGetLastError());
 }
 
@@ -850,14 +851,16 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
                          dim3(64), 0, s, gi);
       cv(L.fdinv, L.fdinv32, L.n);
     } else {
-      const long nn = L.n * L.n;
+      // even leading dimension, zero padding: the product reads rows in pairs
+      const int ld = (int)(L.n + (L.n & 1));
+      const long nn = (long)ld * ld;
       if (!L.inv) L.inv = M.alloc<double>(nn);
       hipLaunchKernelGGL(k_fill0, dim3(cdiv(nn, 256)), dim3(256), 0, s, L.inv, nn);
       hipLaunchKernelGGL(k_mg_dense_fill, dim3(cdiv(L.n, 256)), dim3(256), 0, s, L.diag, L.tx,
-                         L.ty, cnx, cny, L.inv);
+                         L.ty, cnx, cny, ld, L.inv);
       HIPCHK(hipGetLastError());
-      invert_spd(L.inv, (int)L.n, s);
-      if (mixed) cv(L.inv, L.inv32, nn);
+      invert_spd(L.inv, (int)L.n, s, ld);
+      cv(L.inv, L.inv32, nn);   // the cycle reads the FP32 copy
     }
     cv(L.diag, L.diag32, L.n);
     cv(L.tx, L.tx32, L.n);
@@ -2016,8 +2019,9 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
         for (int k = 0; k < 3; ++k) A(4 * m);   // FP32 operator copies
         if (m > MC_MG_COARSE) A(4 * m);          // FP32 factor
         else {
-          A(8 * m * m);                          // dense inverse
-          if (mixed) A(4 * m * m);
+          const int64_t ld = m + (m & 1);
+          A(8 * ld * ld);                        // dense inverse (even leading dimension)
+          A(4 * ld * ld);                        // its FP32 copy
         }
         if (mixed) for (int k = 0; k < 3; ++k) A(4 * m);
       }

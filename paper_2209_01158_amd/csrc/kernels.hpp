@@ -190,11 +190,11 @@ __global__ void k_setup_graph(GraphSetup g) {
 }
 
 // Copies the lower triangle of a column-major K x K matrix to its upper triangle.
-__global__ void k_symmetrize(double* __restrict__ a, int K) {
+__global__ void k_symmetrize(double* __restrict__ a, int K, int lda) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long)K * K) return;
   const int r = (int)(idx % K), c = (int)(idx / K);
-  if (r < c) a[idx] = a[(long)r * K + c];
+  if (r < c) a[(long)c * lda + r] = a[(long)r * lda + c];
 }
 
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, long n) {
@@ -1357,22 +1357,23 @@ __global__ void k_mg_coarsen(CoarsenSetup g) {
   g.cty[I] = Y + 1 < g.cny ? n : 0.0;
 }
 
-// Dense symmetric matrix of a 5-point operator (n = nx * ny; a must be zero on entry).
+// Dense symmetric matrix of a 5-point operator (n = nx * ny, leading dimension ld >= n; a
+// must be zero on entry).
 __global__ void k_mg_dense_fill(const double* __restrict__ diag, const double* __restrict__ tx,
-                                const double* __restrict__ ty, int nx, int ny,
+                                const double* __restrict__ ty, int nx, int ny, int ld,
                                 double* __restrict__ a) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long n = (long)nx * ny;
   if (i >= n) return;
   const int x = (int)(i % nx), y = (int)(i / nx);
-  a[i * n + i] = diag[i];
+  a[i * ld + i] = diag[i];
   if (x + 1 < nx) {
-    a[i * n + i + 1] = -tx[i];
-    a[(i + 1) * n + i] = -tx[i];
+    a[i * ld + i + 1] = -tx[i];
+    a[(i + 1) * ld + i] = -tx[i];
   }
   if (y + 1 < ny) {
-    a[i * n + i + nx] = -ty[i];
-    a[(i + nx) * n + i] = -ty[i];
+    a[i * ld + i + nx] = -ty[i];
+    a[(i + nx) * ld + i] = -ty[i];
   }
 }
 
@@ -1411,15 +1412,15 @@ __device__ __forceinline__ T row_Av(int x, int nx, bool south, bool north, float
   return acc;
 }
 
-// r_c = P^T (r - A z_p) of the finer level F on one band of MC_TY / 4 fine rows of fine tile
-// `tile` (band 0..3), by one wavefront (lane = fine column): every value it needs is loaded
+// r_c = P^T (r - A z_p) of the finer level F on one band of R fine rows of fine tile `tile`
+// (band 0..MC_TY/R-1), by one wavefront (lane = fine column): every value it needs is loaded
 // first, then the fine residuals are formed and each 2 x 2 aggregate is summed over a row
 // pair and a lane pair (tiles and bands start at even columns and rows, so no aggregate
 // straddles two wavefronts).
-template <class T, bool HAS_T>
+template <class T, bool HAS_T, int R>
 __device__ __forceinline__ void restrict_band(const PartD& F, const PartD& C, int tile,
                                               int band) {
-  constexpr int R = MC_TY / 4;   // fine rows per band (even)
+  static_assert(R % 2 == 0 && MC_TY % R == 0, "bands of whole row pairs");
   const int nx = F.nx, ny = F.ny, cnx = C.nx, lane = threadIdx.x & 63;
   const int x0 = (tile % F.tiles_x) * MC_TX;
   const int ya = (tile / F.tiles_x) * MC_TY + band * R;
@@ -1465,11 +1466,11 @@ __device__ __forceinline__ void restrict_band(const PartD& F, const PartD& C, in
   }
 }
 
-template <class T>
+template <class T, int R>
 __device__ __forceinline__ void restrict_band_any(const PartD& F, const PartD& C, int tile,
                                                   int band) {
-  if (F.has_t) restrict_band<T, true>(F, C, tile, band);
-  else restrict_band<T, false>(F, C, tile, band);
+  if (F.has_t) restrict_band<T, true, R>(F, C, tile, band);
+  else restrict_band<T, false, R>(F, C, tile, band);
 }
 
 // z_p = M^-1 r on IC(0) block `unit` of a coarse level (one wavefront)
@@ -1572,7 +1573,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restric
   if (sys && ld_flag(&sys[C.sys].done)) return;
   const PartD& F = parts[C.mg_prev];
   for (int tile = t.t0; tile < t.t1; ++tile)
-    restrict_band_any<T>(F, C, tile, (int)(threadIdx.x >> 6));
+    restrict_band_any<T, MC_TY / 4>(F, C, tile, (int)(threadIdx.x >> 6));
 }
 
 // pre-smoothing on a coarse level with a coarser one; the list entry holds a range of IC(0)
@@ -1630,39 +1631,61 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   if (t.part < 0) return;
   const PartD* P0 = &parts[t.part];
   if (sys && ld_flag(&sys[P0->sys].done)) return;
-  static_assert(MC_TAIL_THREADS % MC_MG_COARSE == 0, "tail threads: whole columns");
+  static_assert(MC_TAIL_THREADS % (MC_MG_COARSE / 2) == 0, "tail threads: whole row pairs");
   const int wave = (int)(threadIdx.x >> 6);
+  {   // pull the coarsest inverse towards this CU while the levels above are smoothed: one
+      // 16-byte load per thread and step, folded into a value that is never stored
+    const PartD* Q = P0;
+    while (Q->mg_next >= 0) Q = &parts[Q->mg_next];
+    const long nq = (long)(Q->n + (Q->n & 1)) * (Q->n + (Q->n & 1)) / 4;   // float4 count
+    const float4* w = (const float4*)Q->mg_inv32;
+    float acc = 0.0f;
+    for (long k = threadIdx.x; k < nq; k += MC_TAIL_THREADS) acc += w[k].x;
+    if (acc == 1.2345e-30f) ((float*)Q->mg_z)[0] = acc;   // keeps the loads; never true
+  }
   const PartD* P = P0;
   while (P->mg_next >= 0) {
     const int ntiles = (int)(((P->nx + MC_TX - 1) / MC_TX) * ((P->ny + MC_TY - 1) / MC_TY));
     for (int u = wave; u < ntiles * (MC_TY / MC_ICYC); u += NW) smooth_unit<T>(*P, u);
     __syncthreads();
     const PartD& C = parts[P->mg_next];
-    for (int k = wave; k < ntiles * 4; k += NW) restrict_band_any<T>(*P, C, k >> 2, k & 3);
+    for (int k = wave; k < ntiles * 8; k += NW) restrict_band_any<T, MC_TY / 8>(*P, C, k >> 3, k & 7);
     __syncthreads();
     P = &C;
   }
-  {   // coarsest: z = A^-1 r by the dense (symmetric) inverse; thread k reads column k, so
-      // each step j reads consecutive entries; the two halves of the sum meet in LDS
-    constexpr int H = MC_TAIL_THREADS / MC_MG_COARSE;
-    __shared__ double part[MC_TAIL_THREADS];
-    const int n = P->n;
+  {   // coarsest: z = A^-1 r by the FP32 copy of the dense (symmetric) inverse, stored with
+      // an even leading dimension ld (zero padding): thread (pair p, chunk c) reads rows 2p,
+      // 2p+1 of column j (one 2-wide load, consecutive across threads) for the chunk's j; the
+      // chunks' FP64 sums meet in LDS.  The inverse was prefetched at the start.
+    constexpr int NP = MC_MG_COARSE / 2, H = MC_TAIL_THREADS / NP;
+    __shared__ double part[2][MC_TAIL_THREADS];
+    const int n = P->n, ld = n + (n & 1);
     const T* r = (const T*)P->mg_r;
-    const gconst<T> inv = gc(pick<T>(P->mg_inv, P->mg_inv32));
+    const float2* inv = (const float2*)P->mg_inv32;   // FP32 copy: half the bytes
     T* z = (T*)P->mg_z;
-    const int k = (int)threadIdx.x % MC_MG_COARSE, h = (int)threadIdx.x / MC_MG_COARSE;
-    const int j0 = h * n / H, j1 = (h + 1) * n / H;
-    double acc = 0.0;
-    if (k < n) {
+    const int pr = (int)threadIdx.x % NP, c = (int)threadIdx.x / NP;
+    const int j0 = c * n / H, j1 = (c + 1) * n / H;
+    double a0 = 0.0, a1 = 0.0;
+    if (2 * pr < n) {
 #pragma unroll 8
-      for (int j = j0; j < j1; ++j) acc += (double)inv[(long)j * n + k] * (double)r[j];
+      for (int j = j0; j < j1; ++j) {
+        const float2 w = inv[(long)j * (ld / 2) + pr];
+        const double rj = (double)r[j];
+        a0 += (double)w.x * rj;
+        a1 += (double)w.y * rj;
+      }
     }
-    part[threadIdx.x] = acc;
+    part[0][threadIdx.x] = a0;
+    part[1][threadIdx.x] = a1;
     __syncthreads();
-    if (h == 0 && k < n) {
-      double s = part[k];
-      for (int q = 1; q < H; ++q) s += part[q * MC_MG_COARSE + k];
-      z[k] = (T)s;
+    if (c == 0 && 2 * pr < n) {
+      double s0 = part[0][pr], s1 = part[1][pr];
+      for (int q = 1; q < H; ++q) {
+        s0 += part[0][q * NP + pr];
+        s1 += part[1][q * NP + pr];
+      }
+      z[2 * pr] = (T)s0;
+      if (2 * pr + 1 < n) z[2 * pr + 1] = (T)s1;
     }
     __syncthreads();
   }

@@ -1,5 +1,6 @@
 """Full-size parity: the 2048 x 2048 two-continuum workload in the launch configuration the
-benchmark times (D-scheme, FP64, block IC(0) PCG), checked against stored oracle values on a
+benchmark times (D-scheme, FP64 PCG with the multigrid V-cycle, and with block IC(0)), checked
+against stored oracle values on a
 seeded sample of cells (tests/golden/c2_oracle.npz, written by tests/golden/make_golden.py
 from the CPU oracle alone).  PCG tolerance: 1e-10 as in the workload, and 1e-13 for the
 1e-10 parity gate (the stopping test bounds the residual, the error can be up to kappa
@@ -35,10 +36,12 @@ def c2():
     return media.config_problem("C2"), np.load(GOLD, allow_pickle=False)
 
 
+@pytest.mark.parametrize("precond", ["mg", "bic0"])
 @pytest.mark.parametrize("tol,gate", [(1e-13, 1e-10), (1e-10, 1e-8)])
-def test_c2_decoupled_trajectory(c2, tol, gate):
+def test_c2_decoupled_trajectory(c2, tol, gate, precond):
     p, z = c2
-    with mcdec.Problem(p, scheme="D", precond="bic0", tol=tol) as g:
+    print(f"\n[c2 {precond} tol {tol}]", flush=True)
+    with mcdec.Problem(p, scheme="D", precond=precond, tol=tol) as g:
         for n in range(1, 101):
             g.step(1)
             if n in (1, 10, 100):
@@ -58,9 +61,10 @@ def test_c2_coupled_steps(c2):
                 assert err < 1e-10
 
 
-def test_c2_mixed_precision(c2):
+@pytest.mark.parametrize("precond", ["mg", "bic0"])
+def test_c2_mixed_precision(c2, precond):
     p, z = c2
-    with mcdec.Problem(p, scheme="D", precision="mixed", precond="bic0", outer_tol=1e-12,
+    with mcdec.Problem(p, scheme="D", precision="mixed", precond=precond, outer_tol=1e-12,
                        inner_tol=1e-4) as g:
         for n in range(1, 11):
             rep = g.step(1)
@@ -69,14 +73,16 @@ def test_c2_mixed_precision(c2):
         assert err < 1e-8
 
 
-def test_c4_batch_against_stored_oracle():
-    """The 256-realization batch in the benchmark's configuration (FP32 inner PCG with
-    block IC(0) inside FP64 refinement to 1e-10, 50 layers), checked on the six stored
-    realizations; every problem must converge at every layer."""
+@pytest.mark.parametrize("precond", ["mg", "bic0"])
+def test_c4_batch_against_stored_oracle(precond):
+    """The 256-realization batch in the benchmark's configuration (FP32 inner PCG with the
+    V-cycle, and with block IC(0), inside FP64 refinement to 1e-10, 50 layers), checked on
+    the six stored realizations; every problem must converge at every layer."""
+    print(f"\n[c4 batch {precond}]", flush=True)
     z = np.load(os.path.join(os.path.dirname(__file__), "golden", "c4_oracle.npz"),
                 allow_pickle=False)
     probs = media.configs.c4_problems()
-    opt = dict(scheme="D", precision="mixed", precond="bic0", outer_tol=1e-10, inner_tol=1e-6)
+    opt = dict(scheme="D", precision="mixed", precond=precond, outer_tol=1e-10, inner_tol=1e-6)
     gs = [mcdec.Problem(p, **opt) for p in probs]
     try:
         with mcdec.Batch(**opt) as b:
