@@ -17,6 +17,8 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <condition_variable>
+#include <functional>
 #include <thread>
 #include <vector>
 
@@ -361,7 +363,61 @@ struct Exec {
   double prof_ms[3] = {0, 0, 0};
   long prof_count[3] = {0, 0, 0};
   int prof_every = 8;
+  // host threads that drive the extra groups of a solve (kept for the problem's lifetime)
+  struct Worker {
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::function<void()> job;
+    bool quit = false;
+  };
+  std::vector<std::unique_ptr<Worker>> workers;
 };
+
+static void worker_loop(Exec::Worker* w) {
+  std::unique_lock<std::mutex> lk(w->mu);
+  for (;;) {
+    w->cv.wait(lk, [&] { return w->quit || (bool)w->job; });
+    if (w->quit) return;
+    std::function<void()> job = std::move(w->job);
+    w->job = nullptr;
+    lk.unlock();
+    job();
+    lk.lock();
+    w->cv.notify_all();
+  }
+}
+
+// Runs job(k) for k = 1..n-1 on the Exec's worker threads and job(0) on the caller, and
+// returns once all have finished.
+static void run_on_workers(Exec& X, int n, const std::function<void(int)>& job) {
+  while ((int)X.workers.size() < n - 1) {
+    X.workers.emplace_back(new Exec::Worker());
+    Exec::Worker* w = X.workers.back().get();
+    w->th = std::thread(worker_loop, w);
+  }
+  std::vector<bool> done(n, false);
+  std::mutex dm;
+  std::condition_variable dcv;
+  for (int k = 1; k < n; ++k) {
+    Exec::Worker* w = X.workers[k - 1].get();
+    std::lock_guard<std::mutex> lk(w->mu);
+    w->job = [&, k] {
+      job(k);
+      std::lock_guard<std::mutex> g(dm);
+      done[k] = true;
+      dcv.notify_all();
+    };
+    w->cv.notify_all();
+  }
+  job(0);
+  std::unique_lock<std::mutex> lk(dm);
+  dcv.wait(lk, [&] {
+    for (int k = 1; k < n; ++k)
+      if (!done[k]) return false;
+    return true;
+  });
+}
 
 static void exec_init(Exec& X, void* user_stream) {
   if (user_stream) {
@@ -441,6 +497,15 @@ static bool exec_sys_capacity(Exec& X, int n) {
 }
 
 static void exec_release(Exec& X) {
+  for (auto& w : X.workers) {
+    {
+      std::lock_guard<std::mutex> lk(w->mu);
+      w->quit = true;
+    }
+    w->cv.notify_all();
+    if (w->th.joinable()) w->th.join();
+  }
+  X.workers.clear();
   if (X.stream) (void)hipStreamSynchronize(X.stream);
   for (hipStream_t st : {X.stream2, X.stream_grid, X.stream_frac})
     if (st) (void)hipStreamSynchronize(st);
@@ -1413,6 +1478,44 @@ static bool all_done(const Group& G, bool outer) {
   return true;
 }
 
+// Runs a fixed launch sequence of the group (solve start, refinement restart) from a
+// captured graph cached with the table, or eagerly while graphs are off.  `tag` names the
+// sequence; the key also holds the group's kinds and record range.
+template <class F>
+static void launch_seq(Exec& X, Group& G, long tag, const F& seq) {
+  if (!X.graphs) {
+    seq();
+    return;
+  }
+  const long key = (1L << 62) | (tag << 48) | ((long)G.kinds << 44) | ((long)G.s0 << 22) |
+                   (long)G.s1;
+  hipGraphExec_t e = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(X.graph_mu);
+    auto it = G.T->graphs.find(key);
+    if (it != G.T->graphs.end()) {
+      e = it->second;
+    } else {
+      hipGraph_t g = nullptr;
+      HIPCHK(hipStreamBeginCapture(G.s, hipStreamCaptureModeThreadLocal));
+      seq();
+      hipError_t le = hipGetLastError();
+      hipError_t ce = hipStreamEndCapture(G.s, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        throw Error{MC_EDEVICE, std::string("graph capture failed: ") +
+                                    hipGetErrorString(le != hipSuccess ? le : ce)};
+      }
+      hipError_t ie = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess)
+        throw Error{MC_EDEVICE, std::string("graph instantiate failed: ") + hipGetErrorString(ie)};
+      G.T->graphs[key] = e;
+    }
+  }
+  HIPCHK(hipGraphLaunch(e, G.s));
+}
+
 template <int PREC>
 static void advance_t(Exec& X, Group& G) {
   const int max_iter = X.opt.max_iter;
@@ -1430,12 +1533,14 @@ static void advance_t(Exec& X, Group& G) {
   };
   if (!G.mixed) {
     if (G.phase == 0) {
-      hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
-                         G.s1);
-      if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-      launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
-      if (G.kinds & 1) launch_vcycle<double>(*G.T, G.s, X.sys, true);
-      if (G.kinds & 2) launch_schur<double>(X, *G.T, G.s);
+      launch_seq(X, G, (long)PREC << 3 | (long)G.assemble << 2 | 0, [&] {
+        hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys,
+                           G.s0, G.s1);
+        if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+        launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
+        if (G.kinds & 1) launch_vcycle<double>(*G.T, G.s, X.sys, true);
+        if (G.kinds & 2) launch_schur<double>(X, *G.T, G.s);
+      });
       G.k = 0;
       G.K = X.opt.check_every > 0 ? X.opt.check_every : first_chunk(X, G);
       G.phase = 1;
@@ -1453,13 +1558,15 @@ static void advance_t(Exec& X, Group& G) {
   }
   // mixed precision: FP64 residual -> FP32 inner PCG -> FP64 correction, repeated
   if (G.phase == 0) {
-    hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
-                       G.s1);
-    if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-    launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
-    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
-    if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
-    if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
+    launch_seq(X, G, (long)PREC << 3 | (long)G.assemble << 2 | 1, [&] {
+      hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
+                         G.s1);
+      if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+      launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
+      launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+      if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
+      if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
+    });
     G.outer = 0;
     G.k = 0;
     G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
@@ -1474,11 +1581,13 @@ static void advance_t(Exec& X, Group& G) {
   if (all_done(G, false)) {
     // every unfinished system ended its inner solve: correct, new residual, restart
     if (G.outer > X.opt.max_outer + 1) throw Error{MC_EDEVICE, "refinement did not terminate"};
-    launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, X.sys);
-    launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
-    launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
-    if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
-    if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
+    launch_seq(X, G, (long)PREC << 3 | 2, [&] {
+      launch2(G, 0, k_correct<PART_GRID>, k_correct<PART_GRAPH>, X.sys);
+      launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
+      launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
+      if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
+      if (G.kinds & 2) launch_schur<float>(X, *G.T, G.s);
+    });
     G.outer += 1;
     G.k = 0;
     G.K = X.opt.check_every > 0 ? X.opt.check_every : 8;
@@ -1531,25 +1640,15 @@ static void run_groups(Exec& X, std::vector<Group>& G) {
     drive_group(X, G[0]);
   } else {
     std::vector<Error> errs(G.size(), Error{MC_OK, ""});
-    std::vector<std::thread> th;
-    for (size_t k = 1; k < G.size(); ++k)
-      th.emplace_back([&, k] {
-        try {
-          drive_group(X, G[k]);
-        } catch (const Error& e) {
-          errs[k] = e;
-        } catch (const std::exception& e) {
-          errs[k] = Error{MC_EDEVICE, e.what()};
-        }
-      });
-    try {
-      drive_group(X, G[0]);
-    } catch (const Error& e) {
-      errs[0] = e;
-    } catch (const std::exception& e) {
-      errs[0] = Error{MC_EDEVICE, e.what()};
-    }
-    for (auto& t : th) t.join();
+    run_on_workers(X, (int)G.size(), [&](int k) {
+      try {
+        drive_group(X, G[k]);
+      } catch (const Error& e) {
+        errs[k] = e;
+      } catch (const std::exception& e) {
+        errs[k] = Error{MC_EDEVICE, e.what()};
+      }
+    });
     for (auto& e : errs)
       if (e.st != MC_OK) throw e;
   }
@@ -1568,17 +1667,18 @@ static void sys_params(const Exec& X, SysState& S, double tol, bool mixed) {
   S.mixed = mixed ? 1 : 0;
 }
 
+// Solve parameters of the records [s0, s1), set by a kernel in stream order (no host wait).
 static void set_sys_params(Exec& X, int s0, int s1, double tol, bool mixed) {
-  HIPCHK(hipMemcpyAsync(X.h_sys + s0, X.sys + s0, (s1 - s0) * sizeof(SysState),
-                        hipMemcpyDeviceToHost, X.stream));
-  HIPCHK(hipStreamSynchronize(X.stream));
-  for (int sI = s0; sI < s1; ++sI) sys_params(X, X.h_sys[sI], tol, mixed);
-  HIPCHK(hipMemcpyAsync(X.sys + s0, X.h_sys + s0, (s1 - s0) * sizeof(SysState),
-                        hipMemcpyHostToDevice, X.stream));
-  HIPCHK(hipStreamSynchronize(X.stream));
+  SysState S;
+  std::memset(&S, 0, sizeof(S));
+  sys_params(X, S, tol, mixed);
+  hipLaunchKernelGGL(k_set_params, dim3(cdiv(s1 - s0, 64)), dim3(64), 0, X.stream, X.sys, s0,
+                     s1, S.tol2, S.otol2, S.max_iter, S.max_outer, S.mixed);
+  HIPCHK(hipGetLastError());
 }
 
-// Solve the systems [s0, s1) of table Tb (system parameters already set).  Decoupled
+// Solve the systems [s0, s1) of table Tb (system parameters already set).  On return the
+// pinned mirror X.h_sys holds the final records of [s0, s1) (the groups' last polls).  Decoupled
 // tables (split_kinds) number their grid systems first: they form one group on the main
 // stream and the fracture systems a second group on the side stream.
 static void solve_table(Exec& X, Table& Tb, int s0, int s1, bool assemble, bool mixed,
@@ -1607,12 +1707,6 @@ static void solve_table(Exec& X, Table& Tb, int s0, int s1, bool assemble, bool 
     mk(3, s0, s1, X.stream);
   }
   run_groups(X, G);
-}
-
-static void read_sys(Exec& X) {
-  HIPCHK(hipMemcpyAsync(X.h_sys, X.sys, X.nsys * sizeof(SysState), hipMemcpyDeviceToHost,
-                        X.stream));
-  HIPCHK(hipStreamSynchronize(X.stream));
 }
 
 // Fills the report from the (already read) system records; returns the first failing
@@ -1662,7 +1756,6 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
     Table& T = upload_table(P, "coupled" + std::to_string(P->cur), coupled_parts(P, P->ncont, 0));
     set_sys_params(X, P->ncont, P->ncont + 1, X.opt.tol, false);
     solve_table(X, T, P->ncont, P->ncont + 1, true, false, false);
-    read_sys(X);
     st = fill_report(X, {P->ncont}, {0}, rep, false);
     fill_coupled_report(P->ncont, rep);
   } else if (sch == MC_SCHEME_D || sch == MC_SCHEME_EX) {
@@ -1670,7 +1763,6 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
                             decoupled_parts(P, all, mixed));
     set_sys_params(X, 0, P->ncont, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
     solve_table(X, T, 0, P->ncont, true, mixed, true);
-    read_sys(X);
     st = fill_report(X, all, all, rep, mixed);
   } else {
     // L: ascending index order, each continuum sees the new values of those before it;
@@ -1686,7 +1778,6 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
                                      std::to_string(P->cur), parts);
       set_sys_params(X, c, c + 1, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
       solve_table(X, T, c, c + 1, true, mixed, false);
-      read_sys(X);
       mc_status s1 = fill_report(X, {c}, {c}, rep, mixed);
       if (s1 != MC_OK) {
         st = s1;
@@ -1804,7 +1895,6 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
   }
   HIPCHK(hipStreamSynchronize(X.stream));
   solve_table(X, *T, 0, nsys, true, mixed, !coupled);
-  read_sys(X);
   mc_status st = MC_OK;
   for (int i = 0; i < n; ++i) {
     mc_problem* P = probs[i];
@@ -2195,7 +2285,6 @@ mc_status mc_solve_continuum(mc_problem* P, int32_t alpha, const double* rhs, do
   mc::Table& T = mc::upload_table(P, "solve" + std::to_string(alpha), parts);
   mc::set_sys_params(P->X, alpha, alpha + 1, P->X.opt.tol, false);
   mc::solve_table(P->X, T, alpha, alpha + 1, false, false, false);
-  mc::read_sys(P->X);
   mc_report r;
   std::memset(&r, 0, sizeof(r));
   r.n_cont = P->ncont;

@@ -1699,6 +1699,20 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   }
 }
 
+// Solve parameters of the system records [s0, s1)
+__global__ void k_set_params(SysState* sys, int s0, int s1, double tol2, double otol2,
+                             int max_iter, int max_outer, int mixed) {
+  const int s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < s1) {
+    SysState& S = sys[s];
+    S.tol2 = tol2;
+    S.otol2 = otol2;
+    S.max_iter = max_iter;
+    S.max_outer = max_outer;
+    S.mixed = mixed;
+  }
+}
+
 // Per-solve reset of the system records [s0, s1) (a kernel, so the sequence stays free of
 // memset nodes).
 __global__ void k_reset(SysState* sys, int s0, int s1) {
