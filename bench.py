@@ -56,10 +56,12 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "bic0", "A"): {"sources": "f864dccc3e74b56a", "fetch_kib": 83496.2,
-                          "write_kib": 65604.0, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "bic0", "B"): {"sources": "f864dccc3e74b56a", "fetch_kib": 90336.7,
-                          "write_kib": 98320.0, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "A"): {"sources": "a0ebdb2023ca3a3a", "fetch_kib": 83471.9,
+                        "write_kib": 65602.9, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "a0ebdb2023ca3a3a", "fetch_kib": 90352.8,
+                        "write_kib": 98320.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "a0ebdb2023ca3a3a", "fetch_kib": 82651.8,
+                        "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
 def log(*a):

@@ -505,16 +505,18 @@ using IcBlk = IcBlkR<MC_ICY>;
 // Dot products: with M = (D + E) D^-1 (D + E^T), the forward values u = (D + E)^-1 r and
 // z = M^-1 r satisfy (D + E^T) z = D u, hence (r, z) = (M z, z) = sum_i d_i u_i^2: both
 // (r,z) and (r,r) are complete after the forward sweep, so r never has to stay live.
-template <class T, bool HAS_T, int R, class EZ>
-__device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlkR<R>& B,
-                                          const T (&rv)[R], const EZ& emit_z,
-                                          double& rz, double& rr) {
-  const int lane = threadIdx.x & 63;
+// Factor values of a block as the sweep uses them: inverse pivots dv, east and north
+// conductances te, tn, zero outside the grid and tn zero on the block's last row (couplings
+// inside the block only).  ex / nx_: this lane's east and north face conductances per row
+// when the caller has them already (HAS_T), else they are loaded.
+template <bool HAS_T, int R, bool LOADED = false>
+__device__ __forceinline__ void ic0_coefs(const PartD& P, const IcBlkR<R>& B, float (&dv)[R],
+                                          float (&te)[R], float (&tn)[R],
+                                          const float* ex = nullptr, const float* nx_ = nullptr) {
   const gconst<float> dinv = gc(P.fdinv32);
   const gconst<float> tx = gc(P.tx32);
   const gconst<float> ty = gc(P.ty32);
   const float tc = (float)P.tconst;
-  float dv[R], te[R], tn[R];
 #pragma unroll
   for (int y = 0; y < R; ++y) {
     const bool act = B.act(y);
@@ -522,8 +524,8 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlkR<R>& B,
     const float d = dinv[i];
     float e, n;
     if constexpr (HAS_T) {
-      e = tx[i];
-      n = ty[i];
+      e = LOADED ? ex[y] : tx[i];
+      n = LOADED ? nx_[y] : ty[i];
     } else {
       e = B.cx + 1 < B.nx ? tc : 0.0f;
       n = B.y0 + y + 1 < B.ny ? tc : 0.0f;
@@ -532,6 +534,15 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlkR<R>& B,
     te[y] = act ? e : 0.0f;
     tn[y] = act && y + 1 < R ? n : 0.0f;   // couplings inside the block only
   }
+}
+
+// The sweep on factor values prepared by ic0_coefs.
+template <class T, int R, class EZ>
+__device__ __forceinline__ void ic0_sweep_core(const IcBlkR<R>& B, const T (&rv)[R],
+                                               const float (&dv)[R], const float (&te)[R],
+                                               const float (&tn)[R], const EZ& emit_z,
+                                               double& rz, double& rr) {
+  const int lane = threadIdx.x & 63;
   T u[R];
   T uprev = (T)0;
 #pragma unroll
@@ -562,6 +573,15 @@ __device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlkR<R>& B,
     zabove = a;
     emit_z(y, a);
   }
+}
+
+template <class T, bool HAS_T, int R, class EZ>
+__device__ __forceinline__ void ic0_sweep(const PartD& P, const IcBlkR<R>& B,
+                                          const T (&rv)[R], const EZ& emit_z,
+                                          double& rz, double& rr) {
+  float dv[R], te[R], tn[R];
+  ic0_coefs<HAS_T, R>(P, B, dv, te, tn);
+  ic0_sweep_core<T, R>(B, rv, dv, te, tn, emit_z, rz, rr);
 }
 
 // z = M^-1 r on one block, handing each z value to emit_z(row, value)
@@ -1515,6 +1535,7 @@ __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const
 #pragma unroll
   for (int j = 0; j < R + 2; ++j) zo[j] = zfull(rowy(j - 1), B.cxs);
   T rl[R], rv[R];
+  float ef[R], nf[R];   // this lane's east / north faces, handed on to the sweep
   constexpr int H = R / 2;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -1540,10 +1561,14 @@ __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const
                                    zo[jj], zo[jj + 2], te[j], th[j], ty[j], ty[j + 1], tc);
       rl[jj] = rr[j];
       rv[jj] = B.act(jj) ? rr[j] - a : (T)0;
+      ef[jj] = te[j];
+      nf[jj] = ty[j + 1];
     }
   }
   double dz = 0.0, dr = 0.0;
-  ic0_block_f<T, R>(P, B, rv, [&](int y, T a) {
+  float dv[R], te[R], tn[R];
+  ic0_coefs<HAS_T, R, true>(P, B, dv, te, tn, ef, nf);
+  ic0_sweep_core<T, R>(B, rv, dv, te, tn, [&](int y, T a) {
     if (B.act(y)) {
       const T zf = zo[y + 1] + a;
       out[B.cell(y)] = zf;
