@@ -1658,13 +1658,19 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   if (sys && ld_flag(&sys[P0->sys].done)) return;
   static_assert(MC_TAIL_THREADS % (MC_MG_COARSE / 2) == 0, "tail threads: whole row pairs");
   const int wave = (int)(threadIdx.x >> 6);
-  {   // pull the coarsest inverse towards this CU while the levels above are smoothed: one
-      // 16-byte load per thread and step, folded into a value that is never stored
+  {   // pull the levels' FP32 coefficients and the coarsest inverse into the cache while the
+      // first level is smoothed: loads folded into a value that is never stored
     const PartD* Q = P0;
-    while (Q->mg_next >= 0) Q = &parts[Q->mg_next];
+    float acc = 0.0f;
+    for (;;) {
+      const int n = Q->n;
+      for (int k = threadIdx.x; k < n; k += MC_TAIL_THREADS)
+        acc += Q->diag32[k] + Q->tx32[k] + Q->ty32[k] + (Q->mg_next >= 0 ? Q->fdinv32[k] : 0.0f);
+      if (Q->mg_next < 0) break;
+      Q = &parts[Q->mg_next];
+    }
     const long nq = (long)(Q->n + (Q->n & 1)) * (Q->n + (Q->n & 1)) / 4;   // float4 count
     const float4* w = (const float4*)Q->mg_inv32;
-    float acc = 0.0f;
     for (long k = threadIdx.x; k < nq; k += MC_TAIL_THREADS) acc += w[k].x;
     if (acc == 1.2345e-30f) ((float*)Q->mg_z)[0] = acc;   // keeps the loads; never true
   }
