@@ -21,7 +21,7 @@
 #define MC_SCHUR_ROWS 16       // rows of the crossing-cell inverse per workgroup
 #define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
 #define MC_MG_COARSE 256       // multigrid levels stop at this many cells (dense inverse there)
-#define MC_MG_TAIL 4096        // levels of at most this many cells run in one workgroup
+#define MC_MG_TAIL 1024        // levels of at most this many cells run in one workgroup
 #define MC_TAIL_THREADS 1024   // threads of that workgroup
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };
