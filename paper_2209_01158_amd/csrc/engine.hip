@@ -142,7 +142,8 @@ struct Table {
   int nparts = 0;
   std::vector<PartD> hparts;
   std::vector<int> htil;                      // tiles and the three workgroup counts per part
-  // multigrid tile lists per level: [0] restriction into the level, [1] smoothing, [2] the
+  // multigrid tile lists per level: [0] restriction into the level when it starts the tail,
+  // [1] restriction into the level with its pre-smoothing (the other coarse levels), [2] the
   // small levels from this one down in one workgroup, [3] post-smoothing (level 0: the final
   // one, writing partial slots)
   struct List {
@@ -250,8 +251,10 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
       if (!in_tail(q) && q.mg_next < 0)
         throw Error{MC_EDEVICE, "coarsest multigrid level outside the small-level tail"};
       tail_start = in_tail(q);
-      const int ntf = (int)(cdiv(f.nx, MC_TX) * cdiv(f.ny, MC_TY));
-      add(0, ntf, ntf, 0);                             // restriction into l: finer tiles
+      if (tail_start) {                                // restriction into l: finer tiles
+        const int ntf = (int)(cdiv(f.nx, MC_TX) * cdiv(f.ny, MC_TY));
+        add(0, ntf, ntf, 0);
+      }
     }
     if (tail_start) {
       add(2, 1, 1, 0);
@@ -259,7 +262,7 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     }
     // coarse levels: ranges of IC(0) blocks (MC_ICYC rows), one per wavefront
     const int units = nt * (MC_TY / MC_ICYC);
-    if (l > 0) add(1, (int)cdiv(units, 4), units, 0);  // smoothing
+    if (l > 0) add(1, (int)cdiv(units, 4), units, 0);  // restriction + pre-smoothing
     if (l == 0) add(3, til[pi].blocks[1], nt, q.mg_slot);
     else add(3, (int)cdiv(units, 4), units, 0);        // post-smoothing
   }
@@ -1298,11 +1301,11 @@ static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool fi
     if (li.n) hipLaunchKernelGGL(kern, dim3(li.n), dim3(MC_BLOCK), 0, s, Tb.parts, li.t, sys);
   };
   for (int l = 1; l < L; ++l) {
+    go(k_mg_restrict_smooth<T>, Tb.mg[l][1]);
     go(k_mg_restrict<T>, Tb.mg[l][0]);
     if (Tb.mg[l][2].n)
       hipLaunchKernelGGL(k_mg_tail<T>, dim3(Tb.mg[l][2].n), dim3(MC_TAIL_THREADS), 0, s,
                          Tb.parts, Tb.mg[l][2].t, sys);
-    go(k_mg_smooth<T>, Tb.mg[l][1]);
   }
   for (int l = L - 2; l >= 1; --l) go(k_mg_post_c<T>, Tb.mg[l][3]);
   if (!final) {

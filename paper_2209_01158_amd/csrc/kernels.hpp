@@ -1584,6 +1584,126 @@ __device__ __forceinline__ void post_unit_any(const PartD* __restrict__ parts, c
   else post_unit<T, FINAL, false, R>(parts, P, unit, rz);
 }
 
+// Restriction into coarse level C and its pre-smoothing in one pass, on IC(0) block `unit`
+// of C (64 coarse columns x MC_ICYC coarse rows; one wavefront, lane = coarse column X).
+// The lane forms the fine residual r - A z_p of its two fine columns 2X, 2X+1 over the
+// block's 2 * MC_ICYC fine rows (the west / east fine neighbours come from the neighbouring
+// lanes, the band's edge columns are loaded by lanes 0 and 63), sums each 2 x 2 aggregate in
+// registers, stores r_c and sweeps it at once: z_p = M^-1 r_c.  Half of the fine rows at a
+// time keeps the registers bounded.
+template <class T, bool HAS_T>
+__device__ __forceinline__ void restrict_smooth_unit(const PartD& F, const PartD& C, int unit) {
+  constexpr int R = MC_ICYC, FR = 2 * R, H = FR / 2;   // coarse rows, fine rows, half
+  const IcBlkR<R> B(C, unit);
+  const int lane = threadIdx.x & 63;
+  const int nx = F.nx, ny = F.ny;
+  const T* rf = (const T*)(F.mg_level == 0 ? F.r : F.mg_r);   // level 0: the PCG residual
+  const T* zf = (const T*)F.mg_zp;
+  const float* d = F.diag32;
+  const float* txp = F.tx32;
+  const float* typ = F.ty32;
+  const T tc = (T)F.tconst;
+  const int X = B.cx;                       // coarse column (may be past the grid)
+  const int fx0 = min(2 * X, nx - 1), fx1 = min(2 * X + 1, nx - 1);
+  const bool c0 = 2 * X < nx, c1 = 2 * X + 1 < nx;
+  const int fxb = 2 * (B.cx - lane);        // first fine column of the band
+  const int hx = lane == 0 ? max(fxb - 1, 0) : (lane == 63 ? min(fxb + 2 * MC_TX, nx - 1) : fx0);
+  const int fy0 = 2 * B.y0;                 // first fine row of the block
+  auto row = [&](int j) { return (long)min(max(fy0 + j, 0), ny - 1) * nx; };
+  double rc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) rc[k] = 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j0 = h * H;
+    T z0[H + 2], z1[H + 2], zh[H], r0[H], r1[H];
+    float d0[H], d1[H], e0[H], e1[H], eh[H], n0[H + 1], n1[H + 1];
+#pragma unroll
+    for (int j = 0; j < H + 2; ++j) {
+      const long o = row(j0 + j - 1);
+      z0[j] = zf[o + fx0];
+      z1[j] = zf[o + fx1];
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const long o = row(j0 + j);
+      zh[j] = zf[o + hx];
+      r0[j] = rf[o + fx0];
+      r1[j] = rf[o + fx1];
+      d0[j] = d[o + fx0];
+      d1[j] = d[o + fx1];
+      e0[j] = HAS_T ? txp[o + fx0] : 0.0f;
+      e1[j] = HAS_T ? txp[o + fx1] : 0.0f;
+      eh[j] = HAS_T ? txp[o + hx] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < H + 1; ++j) {
+      const long o = row(j0 + j - 1);
+      n0[j] = HAS_T ? typ[o + fx0] : 0.0f;
+      n1[j] = HAS_T ? typ[o + fx1] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const int fy = fy0 + j0 + j;
+      const bool south = fy > 0, north = fy + 1 < ny;
+      // west of column 2X is column 2X-1 (the left lane's second column); east of 2X+1 is
+      // 2X+2 (the right lane's first column)
+      const T zw = dpp_d<0x138, 0xF>(zh[j], z1[j + 1]);
+      const T ze = dpp_d<0x130, 0xF>(zh[j], z0[j + 1]);
+      T a0 = (T)d0[j] * z0[j + 1], a1 = (T)d1[j] * z1[j + 1];
+      if constexpr (HAS_T) {
+        const float tw = dpp_d<0x138, 0xF>(eh[j], e1[j]);   // face between 2X-1 and 2X
+        if (2 * X > 0) a0 -= (T)tw * zw;
+        if (c1) {                                            // face between 2X and 2X+1
+          a0 -= (T)e0[j] * z1[j + 1];
+          a1 -= (T)e0[j] * z0[j + 1];
+        }
+        if (2 * X + 2 < nx) a1 -= (T)e1[j] * ze;
+        if (south) {
+          a0 -= (T)n0[j] * z0[j];
+          a1 -= (T)n1[j] * z1[j];
+        }
+        if (north) {
+          a0 -= (T)n0[j + 1] * z0[j + 2];
+          a1 -= (T)n1[j + 1] * z1[j + 2];
+        }
+      } else {
+        T s0 = (T)0, s1 = (T)0;
+        if (2 * X > 0) s0 += zw;
+        if (c1) {
+          s0 += z1[j + 1];
+          s1 += z0[j + 1];
+        }
+        if (2 * X + 2 < nx) s1 += ze;
+        if (south) {
+          s0 += z0[j];
+          s1 += z1[j];
+        }
+        if (north) {
+          s0 += z0[j + 2];
+          s1 += z1[j + 2];
+        }
+        a0 -= tc * s0;
+        a1 -= tc * s1;
+      }
+      const bool in = fy < ny;
+      double v = 0.0;
+      if (in && c0) v += (double)r0[j] - (double)a0;
+      if (in && c1) v += (double)r1[j] - (double)a1;
+      rc[(j0 + j) >> 1] += v;
+    }
+  }
+  T* rcp = (T*)C.mg_r;
+  T rv[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    rv[k] = B.act(k) ? (T)rc[k] : (T)0;
+    if (B.act(k)) rcp[B.cell(k)] = rv[k];
+  }
+  double dz = 0.0, dr = 0.0;
+  ic0_block<T, R>(C, B, rv, (T*)C.mg_zp, dz, dr);
+}
+
 // (Every V-cycle kernel skips systems whose solve has ended; `sys` is null for a plain
 // application of the preconditioner.)
 
@@ -1599,6 +1719,23 @@ __global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restric
   const PartD& F = parts[C.mg_prev];
   for (int tile = t.t0; tile < t.t1; ++tile)
     restrict_band_any<T, MC_TY / 4>(F, C, tile, (int)(threadIdx.x >> 6));
+}
+
+// restriction into a coarse level fused with its pre-smoothing (ranges of the coarse
+// level's IC(0) blocks, one per wavefront)
+template <class T>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_mg_restrict_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
+                     SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& C = parts[t.part];
+  if (sys && ld_flag(&sys[C.sys].done)) return;
+  const PartD& F = parts[C.mg_prev];
+  for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) {
+    if (F.has_t) restrict_smooth_unit<T, true>(F, C, u);
+    else restrict_smooth_unit<T, false>(F, C, u);
+  }
 }
 
 // pre-smoothing on a coarse level with a coarser one; the list entry holds a range of IC(0)
