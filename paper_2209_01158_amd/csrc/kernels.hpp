@@ -1738,20 +1738,8 @@ k_mg_restrict_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ t
   }
 }
 
-// pre-smoothing on a coarse level with a coarser one; the list entry holds a range of IC(0)
-// blocks (units), one per wavefront
-template <class T>
-__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-k_mg_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
-            SysState* __restrict__ sys) {
-  const Tile t = tiles[blockIdx.x];
-  if (t.part < 0) return;
-  const PartD& P = parts[t.part];
-  if (sys && ld_flag(&sys[P.sys].done)) return;
-  for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) smooth_unit<T>(P, u);
-}
-
-// coarse correction and post-smoothing on a coarse level (unit ranges, as above)
+// coarse correction and post-smoothing on a coarse level; the list entry holds a range of
+// IC(0) blocks (units), one per wavefront
 template <class T>
 __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 k_mg_post_c(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
