@@ -131,6 +131,19 @@ struct PartD {
   void* mg_r;              // right-hand side of the level (level 0: the PCG residual r)
   void* mg_zp;             // level solution after pre-smoothing
   void* mg_z;              // level solution after the coarse correction and post-smoothing
+  // copies of the neighbouring levels' fields the V-cycle kernels read, filled when the
+  // launch table is built, so that a kernel needs this one descriptor: the coarser level's
+  // solution and width (post-smoothing), the finer level's vectors, FP32 operator and shape
+  // (restriction)
+  const void* mg_e;        // coarser level's z
+  int mg_cnx;              // coarser level's nx
+  int mg_fnx, mg_fny, mg_ftiles_x, mg_fhas_t, mg_pad;
+  double mg_ftc;           // finer level's constant conductance (no conductance field)
+  const void* mg_fr;       // finer level's right-hand side (level 0: the PCG residual)
+  const void* mg_fzp;      // finer level's z_p
+  const float* mg_fd32;    // finer level's FP32 diagonal and face conductances
+  const float* mg_ftx32;
+  const float* mg_fty32;
                            // (level 0: the PCG vector z)
   // transfer structure
   const int* hptr;         // (grid) [n+1] fracture cells hosted per cell (CSR)

@@ -680,12 +680,42 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   return q;
 }
 
+// Fills the copies of neighbouring V-cycle levels' fields in every level part (after the
+// parts' own pointers are final: a caller may have redirected r or z of a finest part).
+static void link_mg(std::vector<PartD>& parts) {
+  for (auto& q : parts) {
+    if (q.kind != PART_GRID) continue;
+    const int n = (int)parts.size();
+    if ((q.mg_next >= n) || (q.mg_level > 0 && (q.mg_prev < 0 || q.mg_prev >= n)))
+      throw Error{MC_EDEVICE, "multigrid level link outside the launch table"};
+    if (q.mg_next >= 0) {
+      const PartD& c = parts[q.mg_next];
+      q.mg_e = c.mg_z;
+      q.mg_cnx = c.nx;
+    }
+    if (q.mg_level > 0) {
+      const PartD& f = parts[q.mg_prev];
+      q.mg_fnx = f.nx;
+      q.mg_fny = f.ny;
+      q.mg_ftiles_x = f.tiles_x;
+      q.mg_fhas_t = f.has_t;
+      q.mg_ftc = f.tconst;
+      q.mg_fr = f.mg_level == 0 ? f.r : f.mg_r;
+      q.mg_fzp = f.mg_zp;
+      q.mg_fd32 = f.diag32;
+      q.mg_ftx32 = f.tx32;
+      q.mg_fty32 = f.ty32;
+    }
+  }
+}
+
 static PartTiling tiling_of(const mc_problem* P, int c) {
   const Cont& C = P->cont[c];
   return PartTiling{C.tiles, {C.blocks[0], C.blocks[1], C.blocks[2]}};
 }
 
 static Table& upload_table(mc_problem* P, const std::string& key, std::vector<PartD> parts) {
+  link_mg(parts);
   std::vector<PartTiling> til;
   for (auto& q : parts) til.push_back(tiling_of(P, q.cont));
   Table& T = P->tables[key];
@@ -1888,6 +1918,7 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
   }
   HIPCHK(hipMemcpyAsync(X.sys, hs.data(), nsys * sizeof(SysState), hipMemcpyHostToDevice,
                         X.stream));
+  link_mg(parts);
   Table* T = nullptr;
   for (auto& t : B->tab)
     if (table_matches(t, parts, til)) T = &t;

@@ -850,8 +850,9 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
   if (ld_flag(&S.done)) return;
   const int k = S.ka;
   const bool outer_check = S.mixed && k == 0;   // first inner iteration after a residual
-  const bool w0 = t.slot == 0;
-  if (w0 && threadIdx.x == 0) S.kb = k;
+  // one thread writes the record (total_iter is a read-modify-write)
+  const bool w0 = t.slot == 0 && threadIdx.x == 0;
+  if (w0) S.kb = k;
   double v[5];
   reduce_slots<5>(S.partB, S.nslotsB, v);
   if (outer_check) {   // first inner iteration after an FP64 residual: refinement test
@@ -1438,20 +1439,19 @@ __device__ __forceinline__ T row_Av(int x, int nx, bool south, bool north, float
 // pair and a lane pair (tiles and bands start at even columns and rows, so no aggregate
 // straddles two wavefronts).
 template <class T, bool HAS_T, int R>
-__device__ __forceinline__ void restrict_band(const PartD& F, const PartD& C, int tile,
-                                              int band) {
+__device__ __forceinline__ void restrict_band(const PartD& C, int tile, int band) {
   static_assert(R % 2 == 0 && MC_TY % R == 0, "bands of whole row pairs");
-  const int nx = F.nx, ny = F.ny, cnx = C.nx, lane = threadIdx.x & 63;
-  const int x0 = (tile % F.tiles_x) * MC_TX;
-  const int ya = (tile / F.tiles_x) * MC_TY + band * R;
+  const int nx = C.mg_fnx, ny = C.mg_fny, cnx = C.nx, lane = threadIdx.x & 63;
+  const int x0 = (tile % C.mg_ftiles_x) * MC_TX;
+  const int ya = (tile / C.mg_ftiles_x) * MC_TY + band * R;
   if (ya >= ny) return;   // wave-uniform
-  const T* rf = (const T*)(F.mg_level == 0 ? F.r : F.mg_r);   // level 0: the PCG residual
-  const T* zf = (const T*)F.mg_zp;
+  const T* rf = (const T*)C.mg_fr;   // the finer level's right-hand side (level 0: PCG r)
+  const T* zf = (const T*)C.mg_fzp;
   T* rc = (T*)C.mg_r;
-  const float* d = F.diag32;
-  const float* txp = F.tx32;
-  const float* typ = F.ty32;
-  const T tc = (T)F.tconst;
+  const float* d = C.mg_fd32;
+  const float* txp = C.mg_ftx32;
+  const float* typ = C.mg_fty32;
+  const T tc = (T)C.mg_ftc;
   const int x = x0 + lane, xs = min(x, nx - 1);
   const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : xs);
   auto row = [&](int j) { return (long)min(max(ya + j, 0), ny - 1) * nx; };
@@ -1487,10 +1487,9 @@ __device__ __forceinline__ void restrict_band(const PartD& F, const PartD& C, in
 }
 
 template <class T, int R>
-__device__ __forceinline__ void restrict_band_any(const PartD& F, const PartD& C, int tile,
-                                                  int band) {
-  if (F.has_t) restrict_band<T, true, R>(F, C, tile, band);
-  else restrict_band<T, false, R>(F, C, tile, band);
+__device__ __forceinline__ void restrict_band_any(const PartD& C, int tile, int band) {
+  if (C.mg_fhas_t) restrict_band<T, true, R>(C, tile, band);
+  else restrict_band<T, false, R>(C, tile, band);
 }
 
 // z_p = M^-1 r on IC(0) block `unit` of a coarse level (one wavefront)
@@ -1514,16 +1513,15 @@ __device__ __forceinline__ void smooth_unit(const PartD& P, int unit) {
 template <class T, bool FINAL, bool HAS_T, int R>
 __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const PartD& P,
                                           int unit, double& rz) {
-  const PartD& Cp = parts[P.mg_next];
   const T* zp = (const T*)P.mg_zp;
-  const T* e = (const T*)Cp.mg_z;
+  const T* e = (const T*)P.mg_e;   // the coarser level's solution
   const T* r = (const T*)(P.mg_level == 0 ? P.r : P.mg_r);   // level 0: the PCG vectors
   T* out = (T*)(P.mg_level == 0 ? P.z : P.mg_z);
   const float* d = P.diag32;
   const float* txp = P.tx32;
   const float* typ = P.ty32;
   const T tc = (T)P.tconst;
-  const int nx = P.nx, ny = P.ny, cnx = Cp.nx, lane = threadIdx.x & 63;
+  const int nx = P.nx, ny = P.ny, cnx = P.mg_cnx, lane = threadIdx.x & 63;
   const IcBlkR<R> B(P, unit);
   const int x0 = B.cx - lane;
   const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
@@ -1592,17 +1590,17 @@ __device__ __forceinline__ void post_unit_any(const PartD* __restrict__ parts, c
 // registers, stores r_c and sweeps it at once: z_p = M^-1 r_c.  Half of the fine rows at a
 // time keeps the registers bounded.
 template <class T, bool HAS_T>
-__device__ __forceinline__ void restrict_smooth_unit(const PartD& F, const PartD& C, int unit) {
+__device__ __forceinline__ void restrict_smooth_unit(const PartD& C, int unit) {
   constexpr int R = MC_ICYC, FR = 2 * R, H = FR / 2;   // coarse rows, fine rows, half
   const IcBlkR<R> B(C, unit);
   const int lane = threadIdx.x & 63;
-  const int nx = F.nx, ny = F.ny;
-  const T* rf = (const T*)(F.mg_level == 0 ? F.r : F.mg_r);   // level 0: the PCG residual
-  const T* zf = (const T*)F.mg_zp;
-  const float* d = F.diag32;
-  const float* txp = F.tx32;
-  const float* typ = F.ty32;
-  const T tc = (T)F.tconst;
+  const int nx = C.mg_fnx, ny = C.mg_fny;   // the finer level (copied fields)
+  const T* rf = (const T*)C.mg_fr;
+  const T* zf = (const T*)C.mg_fzp;
+  const float* d = C.mg_fd32;
+  const float* txp = C.mg_ftx32;
+  const float* typ = C.mg_fty32;
+  const T tc = (T)C.mg_ftc;
   const int X = B.cx;                       // coarse column (may be past the grid)
   const int fx0 = min(2 * X, nx - 1), fx1 = min(2 * X + 1, nx - 1);
   const bool c0 = 2 * X < nx, c1 = 2 * X + 1 < nx;
@@ -1704,8 +1702,9 @@ __device__ __forceinline__ void restrict_smooth_unit(const PartD& F, const PartD
   ic0_block<T, R>(C, B, rv, (T*)C.mg_zp, dz, dr);
 }
 
-// (Every V-cycle kernel skips systems whose solve has ended; `sys` is null for a plain
-// application of the preconditioner.)
+// (The finest level's V-cycle kernels and the restriction from it skip systems whose solve
+// has ended; the coarser ones only touch level scratch and run regardless, which saves a
+// dependent load.  `sys` is null for a plain application of the preconditioner.)
 
 // restriction into a level: the workgroup's tiles of the finer level, one band per wavefront
 template <class T>
@@ -1714,11 +1713,9 @@ __global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restric
                                                           SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& C = parts[t.part];
-  if (sys && ld_flag(&sys[C.sys].done)) return;
-  const PartD& F = parts[C.mg_prev];
+  const PartD& C = parts[t.part];   // (coarse levels only touch level scratch: no end test)
   for (int tile = t.t0; tile < t.t1; ++tile)
-    restrict_band_any<T, MC_TY / 4>(F, C, tile, (int)(threadIdx.x >> 6));
+    restrict_band_any<T, MC_TY / 4>(C, tile, (int)(threadIdx.x >> 6));
 }
 
 // restriction into a coarse level fused with its pre-smoothing (ranges of the coarse
@@ -1730,11 +1727,12 @@ k_mg_restrict_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ t
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
   const PartD& C = parts[t.part];
-  if (sys && ld_flag(&sys[C.sys].done)) return;
-  const PartD& F = parts[C.mg_prev];
+  // the restriction from the finest level reads a full set of its vectors: skip ended solves
+  // (below, only level scratch is touched and the test would cost a dependent load)
+  if (sys && C.mg_level == 1 && ld_flag(&sys[C.sys].done)) return;
   for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) {
-    if (F.has_t) restrict_smooth_unit<T, true>(F, C, u);
-    else restrict_smooth_unit<T, false>(F, C, u);
+    if (C.mg_fhas_t) restrict_smooth_unit<T, true>(C, u);
+    else restrict_smooth_unit<T, false>(C, u);
   }
 }
 
@@ -1746,8 +1744,7 @@ k_mg_post_c(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
             SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& P = parts[t.part];
-  if (sys && ld_flag(&sys[P.sys].done)) return;
+  const PartD& P = parts[t.part];   // (coarse levels only touch level scratch: no end test)
   double unused = 0.0;
   for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4)
     post_unit_any<T, false, MC_ICYC>(parts, P, u, unused);
@@ -1779,8 +1776,7 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   constexpr int NW = MC_TAIL_THREADS / 64;
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD* P0 = &parts[t.part];
-  if (sys && ld_flag(&sys[P0->sys].done)) return;
+  const PartD* P0 = &parts[t.part];   // (only level scratch is touched: no end test)
   static_assert(MC_TAIL_THREADS % (MC_MG_COARSE / 2) == 0, "tail threads: whole row pairs");
   const int wave = (int)(threadIdx.x >> 6);
   {   // pull the levels' FP32 coefficients and the coarsest inverse into the cache while the
@@ -1805,7 +1801,7 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
     for (int u = wave; u < ntiles * (MC_TY / MC_ICYC); u += NW) smooth_unit<T>(*P, u);
     __syncthreads();
     const PartD& C = parts[P->mg_next];
-    for (int k = wave; k < ntiles * 8; k += NW) restrict_band_any<T, MC_TY / 8>(*P, C, k >> 3, k & 7);
+    for (int k = wave; k < ntiles * 8; k += NW) restrict_band_any<T, MC_TY / 8>(C, k >> 3, k & 7);
     __syncthreads();
     P = &C;
   }

@@ -369,3 +369,21 @@ def test_kernel_timing_samples_and_keeps_results():
             g2.profile_read(3)
         finally:
             g2.close()
+
+
+def test_reports_are_deterministic():
+    """Two identical runs give bitwise the same states and the same per-layer reports
+    (iteration and refinement-pass counts), in FP64 and in FP32 refinement, with three
+    continua solved by concurrent groups."""
+    p = CASES["three70"]()
+    for opt in (dict(precond="mg", tol=1e-12),
+                dict(precond="mg", precision="mixed", outer_tol=1e-11, inner_tol=1e-4),
+                dict(precond="bic0", precision="mixed", outer_tol=1e-11, inner_tol=1e-6)):
+        runs = []
+        for _ in range(2):
+            with mcdec.Problem(p, **opt) as g:
+                reps = [g.step(1) for _ in range(4)]
+                runs.append(([(r["iters"], r["outer"]) for r in reps], g.get_states()))
+        assert runs[0][0] == runs[1][0], (opt, runs[0][0], runs[1][0])
+        for a, b in zip(runs[0][1], runs[1][1]):
+            assert np.array_equal(a, b)
