@@ -239,7 +239,8 @@ def step_bytes(p, rep, precision, precond):
 
 
 def options(args):
-    o = dict(scheme="D", precision=args.precision, precond=args.precond)
+    o = dict(scheme="D", precision=args.precision, precond=args.precond,
+             warm_start=args.warm_start)
     if args.precision == "mixed":
         o.update(outer_tol=args.tol, inner_tol=args.inner_tol)
     else:
@@ -340,6 +341,7 @@ def run_single(args, out):
                    f"{p.nf} fracture cells, tau={p.tau}, D-scheme {args.precision}, "
                    f"PCG {args.precond} tol {args.tol}", "dof": dof,
                    "precond": args.precond, "scheme": "D", "precision": args.precision,
+                   "warm_start": args.warm_start,
                    **({"inner_tol": args.inner_tol} if args.precision == "mixed" else {})},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)), "max": float(lat_ms.max())},
@@ -456,7 +458,7 @@ def run_batch(args, out):
                    f"128..1024), tau=1e-3, batched D-scheme {args.precision}, "
                    f"PCG {args.precond}, refinement to {args.tol}", "dof": dof,
                    "problems": len(probs), "precond": args.precond, "scheme": "D",
-                   "precision": args.precision,
+                   "precision": args.precision, "warm_start": args.warm_start,
                    **({"inner_tol": args.inner_tol} if args.precision == "mixed" else {})},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)), "max": float(lat_ms.max())},
@@ -532,7 +534,7 @@ def run_serve(args, out):
                    f"batching in {args.precision} PCG {args.precond}, HBM budget "
                    f"{args.hbm_budget_gib} GiB", "requests": len(trace),
                    "offered_cell_updates": work, "precond": args.precond,
-                   "precision": args.precision,
+                   "precision": args.precision, "warm_start": args.warm_start,
                    **({"inner_tol": args.inner_tol} if args.precision == "mixed" else {})},
         "latency_ms": {"p50": pct(step_s, 50) * 1e3, "p99": pct(step_s, 99) * 1e3,
                        "max": float(step_s.max()) * 1e3,
@@ -569,6 +571,9 @@ def main():
     ap.add_argument("--precond", default=None, choices=["jacobi", "bic0", "mg"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--warm-start", default=None, choices=["extrapolate", "previous"],
+                    help="PCG initial guess: linear extrapolation of the last two layers "
+                         "(default) or the previous layer")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="mixed: inner FP32 PCG tolerance relative to the outer residual "
                          "(default 1e-4 with the V-cycle, whose passes are bounded by FP32 "
@@ -598,6 +603,8 @@ def main():
             setattr(args, k, d[k])
     if args.inner_tol is None:
         args.inner_tol = 1e-4 if args.precond == "mg" else 1e-6
+    if args.warm_start is None:
+        args.warm_start = "extrapolate"
 
     import torch
     assert torch.cuda.is_available(), "no GPU"

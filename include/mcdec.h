@@ -132,6 +132,10 @@ typedef struct {
                             estimated from the observed residual decrease); the device stops
                             each system at its own tolerance either way                        */
   int32_t tile_rows;     /* grid tile height in rows: 0 (default) or 32                         */
+  int32_t warm_start;    /* PCG initial guess of a layer: 0 (default) linear extrapolation
+                            2 p^{n-1} - p^{n-2} once the previous two layers were computed by
+                            this problem (else p^{n-1}); 1 always p^{n-1}.  Changes iteration
+                            counts only, never the tolerance the solution meets             */
   void *stream;          /* hipStream_t to order all work on, or NULL (library-owned stream)   */
 } mc_options;
 

@@ -72,6 +72,7 @@ struct PartD {
   int slot0A, slot0B; // first partial slot of this part inside its system (per tiling)
   int coupled;       // operator includes the off-diagonal transfer blocks (coupled scheme)
   int ex;            // EX split: diagonal excludes S, RHS subtracts S p^{n-1}
+  int extrap;        // initial guess 2 p^{n-1} - p^{n-2} (x holds p^{n-2} on entry), else p^{n-1}
   int has_t;         // grid: per-face conductance arrays (0 = constant tconst)
   int n_omega;
   int other;         // (grid, 3C) part index of the other Omega continuum in this table or -1

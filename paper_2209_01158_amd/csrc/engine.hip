@@ -561,6 +561,8 @@ struct mc_problem {
   std::vector<double*> partA, partB;
   int cur = 0;                   // state ping-pong index
   long step_count = 0;
+  int hist = 0;   // consecutive layers computed since creation / the last state change: with
+                  // hist >= 1 the other state buffer holds the layer before the current one
   std::map<std::string, Table> tables;
   std::string err;
 };
@@ -600,6 +602,7 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.slot0A = slot0A;
   q.slot0B = slot0B;
   q.ex = P->X.opt.scheme == MC_SCHEME_EX;
+  q.extrap = P->X.opt.warm_start == 0 && P->hist >= 1;
   q.has_t = C.has_t;
   q.n_omega = P->n_omega;
   q.other = -1;
@@ -1821,6 +1824,9 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
   if (st == MC_OK) {
     P->cur ^= 1;
     P->step_count += 1;
+    P->hist += 1;
+  } else {
+    P->hist = 0;   // a failed layer may have overwritten the other state buffer
   }
   return st;
 }
@@ -1942,7 +1948,11 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
     if (si == MC_OK) {
       P->cur ^= 1;
       P->step_count += 1;
-    } else if (st == MC_OK) {
+      P->hist += 1;
+    } else {
+      P->hist = 0;
+    }
+    if (si != MC_OK && st == MC_OK) {
       st = si;
       B->err = "problem " + std::to_string(i) + " failed in continuum " +
                std::to_string(r ? r->failed : -1);
@@ -2402,6 +2412,7 @@ mc_status mc_assemble_rhs(mc_problem* P, int32_t alpha, double* b) {
   std::vector<PartD> parts = mc::decoupled_parts(P, {alpha}, false);
   parts[0].b = b;
   parts[0].x64 = P->cont[alpha].r;    // warm-start copy goes to scratch
+  parts[0].extrap = 0;
   parts[0].coupled = 0;
   mc::Table& T = mc::upload_table(P, "rhs" + std::to_string(alpha), parts);
   mc::launch_all(P->X.stream, T, 0, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
@@ -2426,6 +2437,7 @@ mc_status mc_set_state(mc_problem* P, int32_t alpha, const double* in) {
   if (!P) return MC_EINVAL;
   ABI_BEGIN
   if (alpha < 0 || alpha >= P->ncont || !in) throw mc::Error{MC_EINVAL, "bad argument"};
+  P->hist = 0;   // the layer history no longer describes the state
   HIPCHK(hipMemcpyAsync(P->cont[alpha].ps[P->cur], in, P->cont[alpha].n * sizeof(double),
                         hipMemcpyHostToDevice, P->X.stream));
   HIPCHK(hipStreamSynchronize(P->X.stream));

@@ -672,7 +672,8 @@ __device__ __forceinline__ void schur_gather(const PartD& P, int tile, const T* 
 // right-hand side assembly, always FP64 (Section 3.3, D-scheme; Section 3.2, coupled):
 // decoupled  b = M/tau p_old + F + sum_b Q_ab p_b   [EX: - S p_old]
 // coupled    b = M/tau p_old + F
-// and the warm start x = p_old
+// and the warm start x = p_old, or 2 p_old - p_(n-2) when extrapolating (x holds p_(n-2) on
+// entry)
 // ------------------------------------------------------------------------------------
 template <int KIND>
 __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ parts,
@@ -704,7 +705,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ part
           if (P.ex) b -= S * po;
         }
         P.b[i] = b;
-        x[i] = po;
+        x[i] = P.extrap ? 2.0 * po - x[i] : po;
       },
       [&](int l) {
         const double po = P.pold[l];
@@ -721,7 +722,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ part
           if (P.ex) b -= S * po;
         }
         P.b[l] = b;
-        x[l] = po;
+        x[l] = P.extrap ? 2.0 * po - x[l] : po;
       });
 }
 

@@ -33,6 +33,7 @@ REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 SCHEMES = {"D": 0, "coupled": 1, "L": 2, "U": 3, "EX": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 PRECONDS = {"jacobi": 0, "bic0": 1, "mg": 2}
+WARM_STARTS = {"extrapolate": 0, "previous": 1}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -56,7 +57,8 @@ class Options(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("precision", C.c_int32), ("precond", C.c_int32),
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("outer_tol", C.c_double),
                 ("max_outer", C.c_int32), ("inner_tol", C.c_double),
-                ("check_every", C.c_int32), ("tile_rows", C.c_int32), ("stream", C.c_void_p)]
+                ("check_every", C.c_int32), ("tile_rows", C.c_int32), ("warm_start", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class Report(C.Structure):
@@ -182,7 +184,7 @@ def _ptr(a, ctype):
 
 def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_iter=20000,
                  outer_tol=1e-10, max_outer=30, inner_tol=1e-6, check_every=0, tile_rows=0,
-                 stream=None) -> Options:
+                 warm_start="extrapolate", stream=None) -> Options:
     o = Options()
     _check(mc_options_default(C.byref(o)))
     o.scheme = SCHEMES[scheme]
@@ -191,6 +193,7 @@ def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_
     o.tol, o.max_iter = tol, max_iter
     o.outer_tol, o.max_outer, o.inner_tol = outer_tol, max_outer, inner_tol
     o.check_every, o.tile_rows = check_every, tile_rows
+    o.warm_start = WARM_STARTS[warm_start]
     o.stream = stream
     return o
 
@@ -362,6 +365,7 @@ class Problem:
                    tol=self.opt.tol, max_iter=self.opt.max_iter, outer_tol=self.opt.outer_tol,
                    max_outer=self.opt.max_outer, inner_tol=self.opt.inner_tol,
                    check_every=self.opt.check_every, tile_rows=self.opt.tile_rows,
+                   warm_start={v: k for k, v in WARM_STARTS.items()}[self.opt.warm_start],
                    stream=self.opt.stream)
         cur.update(kw)
         o = make_options(**cur)
