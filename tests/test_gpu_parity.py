@@ -387,3 +387,24 @@ def test_reports_are_deterministic():
         assert runs[0][0] == runs[1][0], (opt, runs[0][0], runs[1][0])
         for a, b in zip(runs[0][1], runs[1][1]):
             assert np.array_equal(a, b)
+
+
+def test_warm_start_modes_and_history_reset():
+    """The extrapolated initial guess (default) and the previous-layer guess both meet the
+    oracle trajectory; a state change resets the layer history, so stepping after
+    set_states(p0) gives bitwise the layers of a fresh problem."""
+    p = CASES["ragged200"]()
+    ref = schemes.run(p, "D", 3, keep="all")
+    for ws in ("extrapolate", "previous"):
+        with mcdec.Problem(p, precond="mg", tol=1e-14, warm_start=ws) as g:
+            for n in range(1, 4):
+                g.step(1)
+                assert rel(g.get_states(), ref[n]) < 1e-10, (ws, n)
+    with mcdec.Problem(p, precond="mg", tol=1e-12) as a, \
+            mcdec.Problem(p, precond="mg", tol=1e-12) as b:
+        a.step(3)
+        a.set_states(p.initial_state())
+        a.step(2)
+        b.step(2)
+        for x, y in zip(a.get_states(), b.get_states()):
+            assert np.array_equal(x, y)
