@@ -56,11 +56,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "a0ebdb2023ca3a3a", "fetch_kib": 83471.9,
-                        "write_kib": 65602.9, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "a0ebdb2023ca3a3a", "fetch_kib": 90352.8,
-                        "write_kib": 98320.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "a0ebdb2023ca3a3a", "fetch_kib": 82651.8,
+    ("C2", "mg", "A"): {"sources": "26dd6045a3ed2464", "fetch_kib": 83432.6,
+                        "write_kib": 65602.7, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "26dd6045a3ed2464", "fetch_kib": 90351.9,
+                        "write_kib": 98320.4, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "26dd6045a3ed2464", "fetch_kib": 82690.4,
                         "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
@@ -113,15 +113,21 @@ KERNEL_NAMES = {
 
 def roofline(kind_time, bytes_total, precision, precond, workload):
     """Roofline objects of the grid operator (A), update (B) and (mg) finest post-smoothing
-    (P) kernels; the one with the most total time is the dominant kernel.  Per-launch
-    algorithmic bytes = total over the timed layers (iterations x cells x bytes per cell of
-    every grid system) / launches issued; average duration from the sampled launches."""
+    (P) kernels; the one with the most total time is the dominant kernel.
+
+    kind_time[k] = (sampled, summed ms, issued, working sampled, working summed ms), where the
+    working samples are those of at least a quarter of the mean sample (the others are
+    launches whose systems had all converged; they return at once and move no bytes).
+    Average duration = mean working sample; working launches = issued x working share of
+    the samples; algorithmic bytes per launch = total over the timed layers (iterations x
+    cells x bytes per cell of every grid system) / working launches."""
     out = {}
-    for k, (sampled, ms, issued) in kind_time.items():
-        if not sampled:
+    for k, (sampled, ms, issued, wn, wms) in kind_time.items():
+        if not sampled or not wn:
             continue
-        avg_s = ms / sampled * 1e-3
-        per_launch = bytes_total[k] / max(issued, 1)
+        avg_s = wms / wn * 1e-3
+        working = issued * wn / sampled
+        per_launch = bytes_total[k] / max(working, 1)
         achieved = per_launch / avg_s / 1e9
         tp = "float" if precision == "mixed" else "double"
         pn = {"bic0": "BIC0", "mg": "BIC0", "jacobi": "JACOBI"}[precond]
@@ -132,7 +138,9 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
                   "traffic_unit": "bytes per launch",
                   "algorithmic_bytes_per_launch": per_launch,
                   "avg_launch_us": avg_s * 1e6, "sampled_launches": sampled,
-                  "issued_launches": issued, "total_ms_est": avg_s * issued * 1e3}
+                  "sampled_working_launches": wn, "issued_launches": issued,
+                  "all_samples_avg_us": ms / sampled * 1e3,
+                  "total_ms_est": ms / sampled * issued}
     if not out:
         return None, None
     order = sorted(out, key=lambda k: -out[k]["total_ms_est"])
@@ -222,6 +230,16 @@ def cpu_baseline(workload):
             "host_cpu_count": os.cpu_count()}
 
 
+def read_profile(h, kernels):
+    """(sampled, ms, issued, working sampled, working ms) per timed kernel of handle h."""
+    out = {}
+    for i, k in enumerate(kernels):
+        n, ms, iss = h.profile_read(i)
+        wn, wms = h.profile_read_above(i, 0.25 * ms / n) if n else (0, 0.0)
+        out[k] = (n, ms, iss, wn, wms)
+    return out
+
+
 def kernels_of(precond):
     """Timed grid kernels, in the library's profile order (0 = A, 1 = B, 2 = P)."""
     return ("A", "B", "P") if precond == "mg" else ("A", "B")
@@ -288,7 +306,7 @@ def run_single(args, out):
                 log(f"step {k + 1}/{args.steps}: iters {rep['iters']} outer {rep['outer']}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = {k: g.profile_read(i) for i, k in enumerate(kernels_of(args.precond))}
+        prof = read_profile(g, kernels_of(args.precond))
         g.profile(False)
         elapsed = t1 - t0
         value = dof * args.steps / elapsed
@@ -398,7 +416,7 @@ def run_batch(args, out):
                     f"max iters {iters_max[-1]}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = {k: b.profile_read(i) for i, k in enumerate(kernels_of(args.precond))}
+        prof = read_profile(b, kernels_of(args.precond))
         b.profile(False)
         elapsed = t1 - t0
         value = dof * args.steps / elapsed

@@ -244,6 +244,12 @@ mc_status mc_profile(mc_problem *p, int32_t enable);
 mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *sampled, double *sampled_ms,
                           int64_t *issued);
 
+/* As mc_profile_read, restricted to the sampled launches that lasted at least min_ms (for
+   instance to leave out launches that returned at once because their systems had already
+   converged): their number and summed duration. */
+mc_status mc_profile_read_above(mc_problem *p, int32_t which, double min_ms, int64_t *sampled,
+                                double *sampled_ms);
+
 /* Device bytes mc_create_problem allocates for *desc under *opt (NULL = defaults): an upper
    bound computed from the sizes alone, used for admission by the server. */
 mc_status mc_footprint(const mc_problem_desc *desc, const mc_options *opt, int64_t *bytes);
@@ -294,11 +300,13 @@ mc_status mc_batch_step(mc_batch *b, mc_problem *const *probs, int32_t n, int32_
 
 const char *mc_batch_last_error(const mc_batch *b);
 
-/* Kernel timing of the batch's grid PCG kernels, as mc_profile / mc_profile_read.  While
-   timing is on, iterations are launched one by one instead of from graphs. */
+/* Kernel timing of the batch's grid PCG kernels, as mc_profile / mc_profile_read /
+   mc_profile_read_above. */
 mc_status mc_batch_profile(mc_batch *b, int32_t enable);
 mc_status mc_batch_profile_read(mc_batch *b, int32_t which, int64_t *sampled,
                                 double *sampled_ms, int64_t *issued);
+mc_status mc_batch_profile_read_above(mc_batch *b, int32_t which, double min_ms,
+                                      int64_t *sampled, double *sampled_ms);
 
 /* ---- serving: continuous batching of simulation requests ------------------------------
  *

@@ -365,6 +365,7 @@ struct Exec {
   long prof_launch[3] = {0, 0, 0};
   double prof_ms[3] = {0, 0, 0};
   long prof_count[3] = {0, 0, 0};
+  std::vector<float> prof_samples[3];   // every sampled duration (ms)
   int prof_every = 8;
   // host threads that drive the extra groups of a solve (kept for the problem's lifetime)
   struct Worker {
@@ -1283,6 +1284,7 @@ static void prof_harvest(Exec& X) {
     HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
     X.prof_ms[e.which] += ms;
     X.prof_launch[e.which] += 1;
+    X.prof_samples[e.which].push_back(ms);
     X.ev_free.push_back(e);
   }
   X.ev_pending.clear();
@@ -2500,6 +2502,7 @@ static mc_status exec_profile(mc::Exec& X, int32_t enable) {
       X.prof_launch[k] = 0;
       X.prof_ms[k] = 0;
       X.prof_count[k] = 0;
+      X.prof_samples[k].clear();
     }
     X.prof_every = enable;
   }
@@ -2517,6 +2520,23 @@ static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* sampled,
   return MC_OK;
 }
 
+static mc_status exec_profile_read_above(mc::Exec& X, int32_t which, double min_ms,
+                                        int64_t* sampled, double* sampled_ms) {
+  if (which < 0 || which > 2) return MC_EINVAL;
+  HIPCHK(hipStreamSynchronize(X.stream));
+  mc::prof_harvest(X);
+  int64_t n = 0;
+  double sum = 0.0;
+  for (float ms : X.prof_samples[which])
+    if (ms >= min_ms) {
+      n += 1;
+      sum += ms;
+    }
+  if (sampled) *sampled = n;
+  if (sampled_ms) *sampled_ms = sum;
+  return MC_OK;
+}
+
 mc_status mc_profile(mc_problem* P, int32_t enable) {
   if (!P || enable < 0) return MC_EINVAL;
   ABI_BEGIN
@@ -2529,6 +2549,14 @@ mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* sampled, double
   if (!P || which < 0 || which > 2) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read(P->X, which, sampled, sampled_ms, issued);
+  ABI_END(P)
+}
+
+mc_status mc_profile_read_above(mc_problem* P, int32_t which, double min_ms, int64_t* sampled,
+                                double* sampled_ms) {
+  if (!P || which < 0 || which > 2) return MC_EINVAL;
+  ABI_BEGIN
+  return exec_profile_read_above(P->X, which, min_ms, sampled, sampled_ms);
   ABI_END(P)
 }
 
@@ -2634,6 +2662,14 @@ mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* sampled,
   if (!B || which < 0 || which > 2) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read(B->X, which, sampled, sampled_ms, issued);
+  ABI_END(B)
+}
+
+mc_status mc_batch_profile_read_above(mc_batch* B, int32_t which, double min_ms,
+                                      int64_t* sampled, double* sampled_ms) {
+  if (!B || which < 0 || which > 2) return MC_EINVAL;
+  ABI_BEGIN
+  return exec_profile_read_above(B->X, which, min_ms, sampled, sampled_ms);
   ABI_END(B)
 }
 

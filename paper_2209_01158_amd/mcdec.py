@@ -111,6 +111,9 @@ mc_profile = _sig("mc_profile", C.c_int, [_PROBLEM, C.c_int32])
 mc_profile_read = _sig("mc_profile_read", C.c_int,
                        [_PROBLEM, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                         C.POINTER(C.c_int64)])
+mc_profile_read_above = _sig("mc_profile_read_above", C.c_int,
+                             [_PROBLEM, C.c_int32, C.c_double, C.POINTER(C.c_int64),
+                              C.POINTER(C.c_double)])
 
 
 mc_autotune = _sig("mc_autotune", C.c_int, [C.POINTER(_PROBLEM), C.c_int32, C.c_int32])
@@ -163,6 +166,9 @@ mc_batch_profile = _sig("mc_batch_profile", C.c_int, [_BATCH, C.c_int32])
 mc_batch_profile_read = _sig("mc_batch_profile_read", C.c_int,
                              [_BATCH, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                               C.POINTER(C.c_int64)])
+mc_batch_profile_read_above = _sig("mc_batch_profile_read_above", C.c_int,
+                                   [_BATCH, C.c_int32, C.c_double, C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double)])
 
 
 class McError(RuntimeError):
@@ -389,6 +395,14 @@ class Problem:
         _check(mc_profile_read(self.h, which, C.byref(n), C.byref(ms), C.byref(iss)), self.h)
         return n.value, ms.value, iss.value
 
+    def profile_read_above(self, which: int, min_ms: float):
+        """(sampled launches of at least min_ms, their summed ms) of grid kernel `which`."""
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(mc_profile_read_above(self.h, which, float(min_ms), C.byref(n), C.byref(ms)),
+               self.h)
+        return n.value, ms.value
+
 
 def autotune(problems, iters: int = 20):
     """Pick the PCG launch shapes per size class by timing (mc_autotune); applies to these
@@ -547,13 +561,21 @@ class Batch:
                self.h, last_error=mc_batch_last_error)
         return n.value, ms.value, iss.value
 
+    def profile_read_above(self, which: int, min_ms: float):
+        n = C.c_int64()
+        ms = C.c_double()
+        _check(mc_batch_profile_read_above(self.h, which, float(min_ms), C.byref(n),
+                                           C.byref(ms)), self.h, last_error=mc_batch_last_error)
+        return n.value, ms.value
+
 
 EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
            "mc_solve_continuum", "mc_apply_continuum", "mc_apply_coupled", "mc_assemble_rhs",
            "mc_apply_precond",
            "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
-           "mc_profile", "mc_profile_read", "mc_batch_create", "mc_batch_destroy",
-           "mc_batch_step", "mc_batch_last_error", "mc_batch_profile", "mc_batch_profile_read",
+           "mc_profile", "mc_profile_read", "mc_profile_read_above", "mc_batch_create",
+           "mc_batch_destroy", "mc_batch_step", "mc_batch_last_error", "mc_batch_profile",
+           "mc_batch_profile_read", "mc_batch_profile_read_above",
            "mc_autotune", "mc_autotune_clear", "mc_footprint", "mc_server_create",
            "mc_server_destroy", "mc_server_submit", "mc_server_poll", "mc_server_fetch",
            "mc_server_release", "mc_server_wait", "mc_server_get_stats",
