@@ -59,6 +59,10 @@ class Problem:
     bc_value: np.ndarray = field(default_factory=lambda: np.zeros(4))
     src: Optional[List[Optional[np.ndarray]]] = None    # per continuum, per unit measure
     p0: Optional[List[Optional[np.ndarray]]] = None     # per continuum initial pressure
+    # wells on fracture cells (Section 5): a source q_w (p_w - p_f) per unit measure, taken
+    # implicitly; q_w = 0 where there is no well
+    well_q: Optional[np.ndarray] = None                 # [nf] q_w >= 0, or None
+    well_p: Optional[np.ndarray] = None                 # [nf] p_w, or None (= 0)
     tau: float = 1e-3
     nsteps: int = 1
     meta: dict = field(default_factory=dict)
@@ -118,6 +122,12 @@ class Problem:
             assert self.edges.min() >= 0 and self.edges.max() < nf
             assert np.all(self.edges[:, 0] != self.edges[:, 1])
             assert np.all(self.edge_d > 0)
+        if self.well_q is not None:
+            q = np.asarray(self.well_q, np.float64)
+            assert q.shape == (nf,) and np.all(np.isfinite(q)) and np.all(q >= 0)
+        if self.well_p is not None:
+            w = np.asarray(self.well_p, np.float64)
+            assert w.shape == (nf,) and np.all(np.isfinite(w))
         for o in self.omega:
             assert o.c > 0
             k = o.k_field(self.nx, self.ny)

@@ -3,7 +3,8 @@
 Builds the coupled matrix M/tau + A row by row from the semi-discrete balance of each cell
 (Section 3.1, eqs. app-md / app-tc / app): storage c|cell|/tau on the diagonal, one
 two-point flux term T (p_i - p_j) per face or fracture connection, one transfer term
-sigma (p_i - p_j) per matrix-fracture or matrix-natural-fracture pair.  Written as plain
+sigma (p_i - p_j) per matrix-fracture or matrix-natural-fracture pair, one exchange
+q_w |cell| (p_l - p_w) per fracture well (Section 5, physical sign).  Written as plain
 Python loops over cells and faces, independently of the vectorized sparse assembly.
 """
 from __future__ import annotations
@@ -58,6 +59,12 @@ def coupled_dense(prob, tau: float):
             src = prob.source(no)
             if src is not None:
                 rhs_f[fo + l] += src[l] * meas
+            wq = getattr(prob, "well_q", None)
+            if wq is not None:
+                # a well exchanges with a reservoir held at p_w, like a Dirichlet face
+                t = float(wq[l]) * meas
+                K[fo + l, fo + l] += t
+                rhs_f[fo + l] += t * (0.0 if prob.well_p is None else float(prob.well_p[l]))
         for e in range(len(prob.edges)):
             l, m = int(prob.edges[e, 0]), int(prob.edges[e, 1])
             t = prob.k_f * prob.aperture / prob.edge_d[e]

@@ -18,7 +18,12 @@ Readings where the paper is silent (each is also listed in the design notes):
   sides) is a half-cell conductance T_b = 2 k_i added to a_ii, with T_b p_D added to F;
 * fracture cell measure |iota_l| = aperture * len_l; fracture connection
   T_e = k_f * aperture / d_e; the discrete matrix-fracture coefficients sigma_il are inputs;
-* the Omega-Omega transfer of the three-continuum model is sigma_12 |cell| per cell.
+* the Omega-Omega transfer of the three-continuum model is sigma_12 |cell| per cell;
+* the wells of the numerical results (Section 5) are a fracture source q_w (p_w - p_f) per
+  unit measure: the paper prints q_w (p - p_w), which with q_w = 1e5 on the right-hand side
+  would be an anti-diffusive term that makes the system indefinite, so the physical sign is
+  taken.  The term is implicit: q_w |iota_l| joins the diagonal of the fracture operator D_f
+  and q_w p_w |iota_l| joins F_f.
 """
 from __future__ import annotations
 
@@ -106,7 +111,8 @@ def fracture_diffusion(nf: int, edges: np.ndarray, edge_d: np.ndarray, k_f: floa
 @dataclass
 class Assembled:
     """All blocks of M dp/dt + (D + Q) p = F for one problem (continuum order: Omega
-    continua, then the fracture)."""
+    continua, then the fracture).  D_f carries the implicit well term besides the fracture
+    diffusion."""
     sizes: List[int]
     M: List[np.ndarray]                         # diagonal of M_a
     D: List[sp.csr_matrix]                      # D_a
@@ -163,9 +169,18 @@ def assemble(prob) -> Assembled:
     if nf > 0:
         meas = prob.aperture * np.asarray(prob.flen, np.float64)
         M.append(prob.c_f * meas)
-        D.append(fracture_diffusion(nf, prob.edges, prob.edge_d, prob.k_f, prob.aperture))
+        Df = fracture_diffusion(nf, prob.edges, prob.edge_d, prob.k_f, prob.aperture)
         src = prob.source(no)
-        F.append(np.zeros(nf) if src is None else src * meas)
+        Ff = np.zeros(nf) if src is None else src * meas
+        wq = getattr(prob, "well_q", None)
+        if wq is not None:
+            wq = np.asarray(wq, np.float64)
+            wp = getattr(prob, "well_p", None)
+            wp = np.zeros(nf) if wp is None else np.asarray(wp, np.float64)
+            Df = (Df + sp.diags(wq * meas)).tocsr()
+            Ff = Ff + wq * wp * meas
+        D.append(Df)
+        F.append(Ff)
     Q: Dict[Tuple[int, int], sp.csr_matrix] = {}
     if no == 2 and prob.sigma_omega != 0.0:
         q = sp.diags(np.full(nc, prob.sigma_omega * h * h)).tocsr()

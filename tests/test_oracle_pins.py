@@ -160,9 +160,13 @@ def test_EX_unstable_where_D_is_not():
     assert abs(d[0][0] - d[1][0]) < 1.5
 
 
+@pytest.mark.parametrize("wells", [False, True])
 @pytest.mark.parametrize("three", [False, True])
-def test_dense_brute_force(three):
+def test_dense_brute_force(three, wells):
     p = _tiny(n=4, ny=3, three=three, nfc=4, seed=11, tau=0.05)
+    if wells:
+        p.well_q = np.array([3.0, 0.0, 40.0, 0.5])
+        p.well_p = np.array([1.2, 7.0, -0.3, 2.0])
     K, mdiag, rf, _ = dense.coupled_dense(p, p.tau)
     asm = fv.assemble(p)
     np.testing.assert_allclose(schemes.coupled_matrix(asm, p.tau).toarray(), K, rtol=1e-14,
@@ -271,6 +275,63 @@ def test_mass_identities():
                 qc = q.tocoo()
                 pred -= p.tau * np.sum(qc.data * ((s1[a] - s0[a])[qc.row] + (s1[b] - s0[b])[qc.col]))
         assert abs(dm - pred) < 1e-13
+
+
+# ------------------------------------------------------------------------------------
+# wells of the numerical results (Section 5): source q_w (p_w - p_f) per unit measure on
+# fracture cells, implicit
+def test_well_isolated_cell_recurrence():
+    """A fracture cell with no transfer and no connections, holding a well: the balance
+    c_f m (p^n - p^{n-1}) / tau = q_w m (p_w - p^n) gives p^n - p_w = (p^0 - p_w) / (1 + q_w
+    tau / c_f)^n in every scheme, and the Omega cell does not move."""
+    cf, q, pw, tau = 0.3, 7.0, 1.2, 0.05
+    p = Problem(nx=1, ny=1, h=0.5, omega=[OmegaContinuum(c=1.0, k_const=1.0)],
+                host=np.array([0], np.int32), flen=np.array([0.37]), k_f=1.0, c_f=cf,
+                aperture=0.02, sigma_f=np.array([[0.0]]), tau=tau,
+                p0=[np.array([0.4]), np.array([1.0])],
+                well_q=np.array([q]), well_p=np.array([pw]))
+    for scheme in ("coupled", "D", "L", "U"):
+        hist = schemes.run(p, scheme, 6)
+        for n, st in enumerate(hist):
+            assert abs(st[1][0] - (pw + (1.0 - pw) / (1 + q * tau / cf) ** n)) < 1e-14
+            assert st[0][0] == 0.4
+
+
+@pytest.mark.parametrize("three", [False, True])
+def test_well_steady_state_is_well_pressure(three):
+    """With no-flow sides the operator annihilates constants, so the steady state of wells
+    sharing one p_w is p = p_w in every continuum: one coupled step with a huge tau lands
+    there, and short steps from p = 1 move monotonically toward p_w = 1.2 (discrete maximum
+    principle)."""
+    p = _tiny(n=5, three=three, nfc=6, seed=4, bc=(0, 0, 0, 0), tau=1e12, lognormal=False)
+    p.well_q = np.array([0.0, 2.0, 0.0, 0.0, 5.0, 0.0])
+    p.well_p = np.full(6, 1.2)
+    p.p0 = [np.ones(s) for s in p.sizes()]
+    x = schemes.run(p, "coupled", 1)[-1]
+    for v in x:
+        assert np.max(np.abs(v - 1.2)) < 1e-9
+    hist = schemes.run(p, "coupled", 5, tau=0.01)
+    for s0, s1 in zip(hist[:-1], hist[1:]):
+        for a, b in zip(s0, s1):
+            assert np.all(b >= a - 1e-15) and np.all(b <= 1.2 + 1e-15)
+    assert hist[1][-1][1] > 1.0 and hist[1][-1][4] > 1.0
+
+
+def test_well_mass_balance():
+    """Coupled scheme, no-flow sides: the stored mass changes by what the wells inject,
+    sum_a M_a (p^n - p^{n-1}) = tau sum_l q_l a len_l (p_w,l - p_l^n)."""
+    p = _tiny(n=6, three=True, nfc=8, seed=8, bc=(0, 0, 0, 0), tau=0.3)
+    rng = np.random.default_rng(3)
+    p.p0 = [rng.random(s) for s in p.sizes()]
+    p.well_q = np.where(rng.random(8) < 0.5, rng.uniform(1, 50, 8), 0.0)
+    p.well_p = rng.uniform(-1, 2, 8)
+    asm = fv.assemble(p)
+    hist = schemes.run(p, "coupled", 4)
+    meas = p.aperture * p.flen
+    for s0, s1 in zip(hist[:-1], hist[1:]):
+        dm = sum(float(asm.M[a] @ (s1[a] - s0[a])) for a in range(asm.L))
+        inj = p.tau * float(np.sum(p.well_q * meas * (p.well_p - s1[-1])))
+        assert abs(dm - inj) < 1e-12 * max(1.0, abs(inj))
 
 
 def test_first_order_in_tau():
