@@ -117,6 +117,11 @@ typedef struct {
                             half-cell conductance 2 k_i; fracture tips are always no-flow      */
   double bc_value[4];    /* Dirichlet pressures                                                */
   double tau;            /* time step (> 0)                                                    */
+  const double *well_q;  /* [nf] well coefficient q_w >= 0 per unit measure, or NULL (no wells).
+                            Each fracture cell l gets the source q_w,l (p_w,l - p_f,l) per unit
+                            measure (the wells of Section 5, with the sign that injects when
+                            p_f < p_w), treated implicitly in every scheme                      */
+  const double *well_p;  /* [nf] well pressure p_w, or NULL (= 0); read only with well_q         */
 } mc_problem_desc;
 
 typedef struct {

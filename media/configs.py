@@ -326,3 +326,102 @@ def small_problem(n: int = 40, seed: int = 7, three: bool = False, nseg: int = 6
                          sigma_omega=SIGMA_NAT if three else 0.0,
                          meta=dict(name=f"small{n}", precond="jacobi", tol=1e-12,
                                    precision="fp64"))
+
+
+# --------------------------------------------------------------------------------------
+# the paper's own test problems (Section 5): 2C and 3C with wells
+# --------------------------------------------------------------------------------------
+WELL_BOXES = ((0.10, 0.15, 0.10, 0.15), (0.60, 0.65, 0.85, 0.90))   # x0, x1, y0, y1
+WELL_Q, WELL_P, PAPER_T, PAPER_STEPS = 1e5, 1.2, 0.002, 50
+PAPER_FRACTURE_CELLS = 2684
+
+
+def _rays(n: int, mids: np.ndarray, dirs: np.ndarray, lens: np.ndarray) -> List[np.ndarray]:
+    """Segments of lens[s] cells of length h centred on mids[s] along dirs[s] (cells whose
+    centre leaves the open unit square are dropped), as host-cell lists."""
+    h = 1.0 / n
+    out = []
+    for m, d, L in zip(mids, dirs, lens):
+        j = np.arange(int(L)) - (int(L) - 1) / 2.0
+        cx, cy = m[0] + j * h * d[0], m[1] + j * h * d[1]
+        keep = (cx > 0) & (cx < 1) & (cy > 0) & (cy < 1)
+        ix = np.minimum(np.floor(cx[keep] / h).astype(np.int64), n - 1)
+        iy = np.minimum(np.floor(cy[keep] / h).astype(np.int64), n - 1)
+        if len(ix):
+            out.append(iy * n + ix)
+    return out
+
+
+def _paper_network(n: int, nseg: int, total: int, rng: np.random.Generator) -> List[np.ndarray]:
+    """A stand-in for the paper's 25-line network (its geometry is only drawn): nseg
+    any-angle segments, the first two centred inside the two well boxes so that both boxes
+    hold fracture cells, the others centred uniformly; relative lengths U[0.3, 1] scaled by
+    one common factor (bisection) so that the network has `total` cells after clipping, the
+    last segment's length then adjusted by whole cells towards that count."""
+    mids = rng.random((nseg, 2))
+    for b, (x0, x1, y0, y1) in enumerate(WELL_BOXES[:min(2, nseg)]):
+        mids[b] = (x0 + (x1 - x0) * rng.random(), y0 + (y1 - y0) * rng.random())
+    th = rng.random(nseg) * np.pi
+    dirs = np.stack([np.cos(th), np.sin(th)], axis=1)
+    w = rng.uniform(0.3, 1.0, nseg)
+    count = lambda lens: sum(len(s) for s in _rays(n, mids, dirs, lens))  # noqa: E731
+    lo, hi = 0.0, 4.0 * total / w.sum()
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if count(np.maximum(1, np.round(w * mid))) < total:
+            lo = mid
+        else:
+            hi = mid
+    lens = np.maximum(1, np.round(w * hi)).astype(np.int64)
+    best = (abs(count(lens) - total), lens[-1])
+    for L in range(max(1, int(lens[-1]) - 40), int(lens[-1]) + 41):
+        lens[-1] = L
+        best = min(best, (abs(count(lens) - total), L))
+    lens[-1] = best[1]
+    return _rays(n, mids, dirs, lens)
+
+
+def paper_problem(case: str = "2C", n: int = 200, seed: int = 11,
+                  nsteps: int = PAPER_STEPS) -> Problem:
+    """The test problems of the paper's numerical results on an n x n grid (200 there).
+
+    2C: matrix c = 0.1, k = 1; explicit fractures c = 1, k = 1e6.  3C: matrix c = 0.05,
+    k = 1e-3; natural fractures c = 0.1, k = 1; explicit fractures c = 1, k = 1e6.  No-flow
+    sides, p0 = 1 everywhere, T = 0.002 in 50 layers, wells q_w = 1e5, p_w = 1.2 on the
+    fracture cells whose host cell centre lies in one of the two boxes.  The paper leaves
+    the network geometry to a figure and sigma and the aperture unstated; here: a synthetic
+    25-segment network of about 2684 cells, aperture 1 (the fracture measure is the cell
+    length, as in the paper's 1-D fracture balance), matrix-fracture sigma_il = k_a len_l /
+    h, and in 3C a matrix-natural-fracture coefficient sigma_12 = k_1 / h^2 per unit area
+    (sigma_12 |cell| = k_1: the two-point conductance of co-located cells at distance h).
+    """
+    if case not in ("2C", "3C"):
+        raise ValueError(case)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    total = int(round(PAPER_FRACTURE_CELLS * (n / 200.0)))
+    segs = _paper_network(n, 25, total, rng)
+    if case == "2C":
+        omega = [OmegaContinuum(c=0.1, k_const=1.0)]
+        sig12 = 0.0
+    else:
+        omega = [OmegaContinuum(c=0.05, k_const=1e-3), OmegaContinuum(c=0.1, k_const=1.0)]
+        sig12 = 1e-3 / h ** 2
+    host, flen, edges, edge_d, seg_id = _fracture_arrays(segs, h)
+    nf = len(host)
+    hx = (host % n + 0.5) * h
+    hy = (host // n + 0.5) * h
+    inbox = np.zeros(nf, bool)
+    for (x0, x1, y0, y1) in WELL_BOXES:
+        inbox |= (hx >= x0) & (hx <= x1) & (hy >= y0) & (hy <= y1)
+    p = Problem(nx=n, ny=n, h=h, omega=omega, sigma_omega=sig12, host=host, flen=flen,
+                edges=edges, edge_d=edge_d, k_f=1e6, c_f=1.0, aperture=1.0,
+                sigma_f=_sigma_f(omega, host, flen, n, h),
+                bc_type=np.zeros(4, np.int32), bc_value=np.zeros(4),
+                src=None, p0=[np.ones(n * n)] * len(omega) + [np.ones(nf)],
+                well_q=np.where(inbox, WELL_Q, 0.0), well_p=np.full(nf, WELL_P),
+                tau=PAPER_T / PAPER_STEPS, nsteps=nsteps,
+                meta=dict(name=case, precond="mg", tol=1e-10, precision="fp64",
+                          seg_id=seg_id, wells=int(inbox.sum())))
+    p.check()
+    return p

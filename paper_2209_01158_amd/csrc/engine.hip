@@ -551,6 +551,8 @@ struct mc_problem {
   // inputs kept on the device (for re-setup)
   double* k[2] = {nullptr, nullptr};
   double* src[3] = {nullptr, nullptr, nullptr};
+  double* well_q = nullptr;   // [nf] or null
+  double* well_p = nullptr;   // [nf] or null (only with well_q)
   int *host = nullptr, *rowptr = nullptr, *col = nullptr, *eidx = nullptr, *hptr = nullptr,
       *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr;
   GraphCSR gh;                       // host copies of the fracture graph structure
@@ -1028,6 +1030,8 @@ static void build_coefficients(mc_problem* P) {
     g.sig0 = P->sigma_f;
     g.sig1 = P->n_omega > 1 ? P->sigma_f + P->nf : nullptr;
     g.src = P->src[P->n_omega];
+    g.wq = P->well_q;
+    g.wp = P->well_q ? P->well_p : nullptr;
     g.k_f = P->d.k_f;
     g.c_f = P->d.c_f;
     g.aperture = P->d.aperture;
@@ -1199,6 +1203,8 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     P->chains_h = chains;
     P->gtile_h = gt;
     if (d.src_f) P->src[d.n_omega] = M.upload(d.src_f, d.nf, s);
+    if (d.well_q) P->well_q = M.upload(d.well_q, d.nf, s);
+    if (d.well_q && d.well_p) P->well_p = M.upload(d.well_p, d.nf, s);
   }
   // continua
   P->cont.resize(P->ncont);
@@ -2119,6 +2125,8 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
     A(4 * (nf + 1));              // chain_ptr
     A(4 * (nf + 1));              // gtile
     if (d.src_f) A(8 * nf);
+    if (d.well_q) A(8 * nf);
+    if (d.well_q && d.well_p) A(8 * nf);
   }
   const int ncont = d.n_omega + (nf ? 1 : 0);
   int64_t ctiles = 0;

@@ -63,6 +63,12 @@ std::string validate_desc(const mc_problem_desc& d) {
     if (d.p0_f)
       for (int l = 0; l < d.nf; ++l)
         if (!fin(d.p0_f[l])) return fmt("p0_f[%ld] not finite", l);
+    if (d.well_q)
+      for (int l = 0; l < d.nf; ++l)
+        if (!(d.well_q[l] >= 0) || !fin(d.well_q[l])) return fmt("well_q[%ld] must be finite and >= 0", l);
+    if (d.well_p)
+      for (int l = 0; l < d.nf; ++l)
+        if (!fin(d.well_p[l])) return fmt("well_p[%ld] not finite", l);
   }
   if (d.ne < 0) return "ne must be >= 0";
   if (d.ne > 0) {

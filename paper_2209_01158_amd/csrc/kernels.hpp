@@ -167,6 +167,8 @@ struct GraphSetup {
   const double* sig0;
   const double* sig1;
   const double* src;
+  const double* wq;    // well q_w per unit measure, or null
+  const double* wp;    // well pressure p_w, or null
   double k_f, c_f, aperture, tau;
   int ex;
   double *val, *diag, *mt, *F;
@@ -184,9 +186,11 @@ __global__ void k_setup_graph(GraphSetup g) {
   const double meas = g.aperture * g.flen[l];
   const double mt = g.c_f * meas / g.tau;
   double S = g.sig0[l] + (g.n_omega > 1 ? g.sig1[l] : 0.0);
+  // a well q_w (p_w - p) is implicit in every scheme: q_w |iota_l| on the diagonal
+  const double w = g.wq ? g.wq[l] * meas : 0.0;
   g.mt[l] = mt;
-  g.diag[l] = mt + s + (g.ex ? 0.0 : S);
-  g.F[l] = g.src ? g.src[l] * meas : 0.0;
+  g.diag[l] = mt + s + w + (g.ex ? 0.0 : S);
+  g.F[l] = (g.src ? g.src[l] * meas : 0.0) + (g.wp ? w * g.wp[l] : 0.0);
 }
 
 // Copies the lower triangle of a column-major K x K matrix to its upper triangle.

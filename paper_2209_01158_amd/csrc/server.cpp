@@ -24,7 +24,7 @@ namespace {
 // Owned copy of a descriptor's arrays (the caller's arrays are valid only during submit).
 struct HostDesc {
   mc_problem_desc d{};
-  std::vector<double> k[2], src[2], p0[2], flen, edge_d, sigma_f, src_f, p0_f;
+  std::vector<double> k[2], src[2], p0[2], flen, edge_d, sigma_f, src_f, p0_f, well_q, well_p;
   std::vector<int32_t> host, edges;
 
   void take(const mc_problem_desc& in) {
@@ -54,6 +54,8 @@ struct HostDesc {
     d.sigma_f = cp(sigma_f, in.sigma_f, (size_t)(in.n_omega > 0 ? in.n_omega : 0) * nf);
     d.src_f = cp(src_f, in.src_f, nf);
     d.p0_f = cp(p0_f, in.p0_f, nf);
+    d.well_q = cp(well_q, in.well_q, nf);
+    d.well_p = cp(well_p, in.well_p, nf);
   }
 };
 

@@ -50,7 +50,8 @@ class ProblemDesc(C.Structure):
                 ("nf", C.c_int32), ("host", _ip), ("flen", _dp), ("ne", C.c_int32),
                 ("edges", _ip), ("edge_d", _dp), ("k_f", C.c_double), ("c_f", C.c_double),
                 ("aperture", C.c_double), ("sigma_f", _dp), ("src_f", _dp), ("p0_f", _dp),
-                ("bc_type", C.c_int32 * 4), ("bc_value", C.c_double * 4), ("tau", C.c_double)]
+                ("bc_type", C.c_int32 * 4), ("bc_value", C.c_double * 4), ("tau", C.c_double),
+                ("well_q", _dp), ("well_p", _dp)]
 
 
 class Options(C.Structure):
@@ -272,6 +273,16 @@ def describe(prob):
             p0f = np.ascontiguousarray(p0f, np.float64)
             keep.append(p0f)
             d.p0_f = _ptr(p0f, C.c_double)
+        wq = getattr(prob, "well_q", None)
+        if wq is not None:
+            wq = np.ascontiguousarray(wq, np.float64).reshape(-1)
+            keep.append(wq)
+            d.well_q = _ptr(wq, C.c_double)
+            wp = getattr(prob, "well_p", None)
+            if wp is not None:
+                wp = np.ascontiguousarray(wp, np.float64).reshape(-1)
+                keep.append(wp)
+                d.well_p = _ptr(wp, C.c_double)
     d.k_f, d.c_f, d.aperture = prob.k_f, prob.c_f, prob.aperture
     for s in range(4):
         d.bc_type[s] = int(prob.bc_type[s])

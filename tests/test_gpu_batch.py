@@ -31,16 +31,20 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
-def family():
+def family(paper=False):
     """Uneven sizes (ragged tiles), two and three continua, lognormal and constant k,
-    with and without fractures."""
-    return [
+    with and without fractures; with `paper`, also the numerical-results problem with
+    wells on a 100 x 100 grid."""
+    out = [
         media.small_problem(n=70, seed=5, three=True, nseg=6, seg_len=(5, 40)),
         media.small_problem(n=130, seed=8, nseg=10, seg_len=(10, 60)),
         media.small_problem(n=40, seed=2, nseg=4),
         media.small_problem(n=97, seed=9, three=True, nseg=0, lognormal=False),
         media.small_problem(n=200, seed=11, nseg=12, seg_len=(10, 80)),
     ]
+    if paper:
+        out.append(media.paper_problem("3C", n=100))
+    return out
 
 
 def alone_states(probs, nsteps, **opt):
@@ -88,7 +92,7 @@ OPTS = {
 @pytest.mark.parametrize("key", list(OPTS))
 def test_batch_equals_alone_bitwise(key):
     print(f"\n[batch {key}]", flush=True)
-    probs = family()
+    probs = family(paper=True)
     opt = OPTS[key]
     alone = alone_states(probs, 3, **opt)
     mixed, reps = batch_states(probs, 3, **opt)
@@ -98,7 +102,7 @@ def test_batch_equals_alone_bitwise(key):
 @pytest.mark.parametrize("key", ["fp64_bic0", "mixed_bic0", "fp64_mg", "mixed_mg"])
 def test_batch_matches_oracle(key):
     print(f"\n[batch oracle {key}]", flush=True)
-    probs = family()
+    probs = family(paper=True)
     nsteps = 3
     opt = dict(OPTS[key])
     if opt["precision"] == "fp64":

@@ -1,0 +1,73 @@
+"""The paper's own test problems (numerical results, 2C and 3C with wells) on the GPU.
+
+Every layer of the 50-layer runs matches the oracle (relative L2 <= 1e-10 at PCG tolerance
+1e-14), so the decoupling errors e_h of the L-, D- and U-schemes against the coupled scheme
+come out as the oracle's; their order U < L < D is the paper's observation.
+"""
+import numpy as np
+import pytest
+
+import media
+from oracle import schemes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2209_01158_amd import mcdec  # noqa: E402
+
+SCHEMES = ("coupled", "L", "D", "U")
+
+
+def rel(a, b):
+    a = np.concatenate([np.ravel(v) for v in a])
+    b = np.concatenate([np.ravel(v) for v in b])
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module", params=["2C", "3C"])
+def paper(request):
+    print(f"\n[paper problem {request.param}]", flush=True)
+    p = media.paper_problem(request.param)
+    ref = {s: schemes.run(p, s, keep="all") for s in SCHEMES}
+    return request.param, p, ref, {}
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_paper_trajectory(paper, scheme):
+    name, p, ref, gpu = paper
+    print(f"[{name} {scheme}]", flush=True)
+    hist = []
+    with mcdec.Problem(p, scheme=scheme, precond="mg", tol=1e-14) as g:
+        for n in range(1, p.nsteps + 1):
+            rep = g.step(1)
+            st = g.get_states()
+            err = rel(st, ref[scheme][n])
+            assert err < 1e-10, (name, scheme, n, err, rep)
+            hist.append(st)
+    gpu[scheme] = hist
+
+
+def test_paper_scheme_errors(paper):
+    name, p, ref, gpu = paper
+    if set(gpu) != set(SCHEMES):
+        pytest.skip("needs every trajectory")
+    e_final = {}
+    for s in ("L", "D", "U"):
+        e_gpu = [rel(a, b) for a, b in zip(gpu[s], gpu["coupled"])]
+        e_ora = [rel(a, b) for a, b in zip(ref[s][1:], ref["coupled"][1:])]
+        np.testing.assert_allclose(e_gpu, e_ora, rtol=1e-6, atol=1e-12)
+        e_final[s] = e_gpu[-1]
+        print(name, s, "e_h(T) = %.3f %%" % (100 * e_gpu[-1]), flush=True)
+    assert e_final["U"] < e_final["L"] < e_final["D"] < 0.01
+
+
+def test_well_descriptor_checked():
+    p = media.paper_problem("2C", n=40)
+    p.well_q = p.well_q.copy()
+    p.well_q[0] = -1.0
+    with pytest.raises(mcdec.McError) as ei:
+        mcdec.Problem(p)
+    assert ei.value.status == mcdec.MC_EINVAL and "well_q" in str(ei.value)

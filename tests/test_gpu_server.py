@@ -27,6 +27,7 @@ def requests():
         (media.small_problem(n=40, seed=2, nseg=4), 7),
         (media.small_problem(n=97, seed=9, three=True, nseg=0, lognormal=False), 5),
         (media.small_problem(n=160, seed=12, three=True, nseg=8, seg_len=(10, 60)), 2),
+        (media.paper_problem("3C", n=60), 5),          # wells
     ]
 
 

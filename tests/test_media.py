@@ -65,3 +65,25 @@ def test_c4_c5_families():
     t = np.array([e[0] for e in tr])
     assert np.all(np.diff(t) > 0)
     assert all(64 <= e[1] <= 2048 and 10 <= e[4] <= 500 for e in tr)
+
+
+@pytest.mark.parametrize("case,dof", [("2C", 42684), ("3C", 82684)])
+def test_paper_problem_shape(case, dof):
+    """The numerical-results test problems: 200 x 200 grid, 2684 fracture cells (the DOF
+    counts the paper states), wells in both boxes, no-flow sides, p0 = 1, T = 0.002 / 50."""
+    p = media.paper_problem(case)
+    assert (p.nx, p.ny, p.nf, p.dof()) == (200, 200, 2684, dof)
+    assert p.n_omega == (1 if case == "2C" else 2)
+    assert len(np.unique(p.meta["seg_id"])) == 25
+    assert np.all(p.bc_type == 0)
+    assert abs(p.tau * p.nsteps - 0.002) < 1e-15 and p.nsteps == 50
+    assert all(np.all(v == 1.0) for v in p.initial_state())
+    wells = np.flatnonzero(p.well_q)
+    assert np.all(p.well_q[wells] == 1e5) and np.all(p.well_p == 1.2)
+    h = p.h
+    x = (p.host[wells] % p.nx + 0.5) * h
+    y = (p.host[wells] // p.nx + 0.5) * h
+    low = (x <= 0.15) & (y <= 0.15)
+    high = (x >= 0.6) & (y >= 0.85)
+    assert low.any() and high.any() and np.all(low | high)
+    assert np.all((x >= 0.1) & (x <= 0.65) & (y >= 0.1) & (y <= 0.9))
