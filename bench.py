@@ -56,11 +56,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "26dd6045a3ed2464", "fetch_kib": 83432.6,
-                        "write_kib": 65602.7, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "26dd6045a3ed2464", "fetch_kib": 90351.9,
+    ("C2", "mg", "A"): {"sources": "5d12a9046f543a3d", "fetch_kib": 83522.7,
+                        "write_kib": 65603.2, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "5d12a9046f543a3d", "fetch_kib": 90351.9,
                         "write_kib": 98320.4, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "26dd6045a3ed2464", "fetch_kib": 82690.4,
+    ("C2", "mg", "P"): {"sources": "5d12a9046f543a3d", "fetch_kib": 82667.2,
                         "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
