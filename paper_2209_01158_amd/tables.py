@@ -5,6 +5,7 @@ layer against the coupled solution (in percent, over all continua), and the aver
 of PCG iterations per layer of every continuum.
 
     python -m paper_2209_01158_amd.tables [--precond mg|bic0|jacobi] [--tol 1e-10]
+                                          [--precision fp64|mixed] [--outer-tol 1e-9]
 
 The network geometry, sigma and the aperture are synthetic stand-ins (media.paper_problem),
 so the errors are comparable with the paper's in size and order, not digit for digit.
@@ -32,11 +33,15 @@ def _sync():
         torch.cuda.synchronize()
 
 
-def run_case(case: str, precond: str = "mg", tol: float = 1e-10, n: int = 200):
+def run_case(case: str, precond: str = "mg", tol: float = 1e-10, n: int = 200,
+             precision: str = "fp64", outer_tol: float = 1e-9):
     p = media.paper_problem(case, n=n)
     out, states = {}, {}
     for scheme in ("coupled", "L", "D", "U"):
-        with mcdec.Problem(p, scheme=scheme, precond=precond, tol=tol) as g:
+        # the coupled scheme is FP64 only; the decoupled ones take the chosen precision
+        prec = "fp64" if scheme == "coupled" else precision
+        with mcdec.Problem(p, scheme=scheme, precond=precond, tol=tol, precision=prec,
+                           outer_tol=outer_tol) as g:
             g.step(1)                       # first layer outside the clock (setup, graphs)
             g.set_states(p.initial_state())
             _sync()
@@ -54,7 +59,8 @@ def run_case(case: str, precond: str = "mg", tol: float = 1e-10, n: int = 200):
         x = np.concatenate([np.ravel(v) for v in states[scheme]])
         out[scheme]["e_h_percent"] = 100.0 * float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
     return dict(case=case, dof=p.dof(), sizes=p.sizes(), wells=int(np.count_nonzero(p.well_q)),
-                precond=precond, tol=tol, schemes=out)
+                precond=precond, tol=tol, precision=precision,
+                outer_tol=outer_tol if precision == "mixed" else None, schemes=out)
 
 
 def main(argv=None):
@@ -62,9 +68,13 @@ def main(argv=None):
     ap.add_argument("--precond", default="mg", choices=list(mcdec.PRECONDS))
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--n", type=int, default=200)
+    ap.add_argument("--precision", default="fp64", choices=list(mcdec.PRECISIONS))
+    ap.add_argument("--outer-tol", type=float, default=1e-9,
+                    help="mixed precision: FP64 refinement tolerance (the FP64 residual floor "
+                         "of these fracture systems is near 1e-10)")
     a = ap.parse_args(argv)
     for case in ("2C", "3C"):
-        r = run_case(case, a.precond, a.tol, a.n)
+        r = run_case(case, a.precond, a.tol, a.n, a.precision, a.outer_tol)
         print(json.dumps(r), flush=True)
         print(f"{case}: DOF {r['dof']} {r['sizes']}, {r['wells']} well cells", flush=True)
         for s, v in r["schemes"].items():
