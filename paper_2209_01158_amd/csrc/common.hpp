@@ -168,9 +168,12 @@ struct PartD {
   double* x64;             // FP64 iterate (refinement)
 };
 
-// One workgroup's work: tiles [t0, t1) of a part, reporting into partial slot `slot`.
+// One workgroup's work: tiles [t0, t1) of a part, reporting into partial slot `slot`.  The
+// owning system is copied here so that a kernel's end test loads the system's done flag
+// straight from the tile, without waiting for the part's descriptor.
 struct Tile {
   int part;   // -1: padding workgroup (does nothing)
   int slot;
   int t0, t1;
+  int sys;    // parts[part].sys
 };

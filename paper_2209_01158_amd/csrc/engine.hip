@@ -204,13 +204,13 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
         std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
         for (int b : ord) {
           if (b < 0) {
-            tiles.push_back(Tile{-1, 0, 0, 0});
+            tiles.push_back(Tile{-1, 0, 0, 0, 0});
             continue;
           }
           const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
-          tiles.push_back(Tile{pi, slot0 + b, t0, t1});
+          tiles.push_back(Tile{pi, slot0 + b, t0, t1, q.sys});
         }
-        while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0});
+        while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0, 0});
       }
       if (!tiles.empty() && (!T.tiles[fam][kind] || T.cap[fam][kind] < (int)tiles.size())) {
         T.cap[fam][kind] = (int)tiles.size() + 8;
@@ -240,7 +240,8 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     auto add = [&](int op, int nb, int ntile, int slot0) {
       std::vector<Tile>& v = mgv[4 * l + op];
       for (int b = 0; b < nb; ++b)
-        v.push_back(Tile{pi, slot0 + b, (int)((long)b * ntile / nb), (int)((long)(b + 1) * ntile / nb)});
+        v.push_back(Tile{pi, slot0 + b, (int)((long)b * ntile / nb),
+                         (int)((long)(b + 1) * ntile / nb), q.sys});
     };
     bool tail_start = false;
     if (l > 0) {

@@ -850,9 +850,9 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
   __shared__ T sp[KIND == PART_GRID ? W * H : 1];
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& P = parts[t.part];
-  SysState& S = sys[P.sys];
+  SysState& S = sys[t.sys];
   if (ld_flag(&S.done)) return;
+  const PartD& P = parts[t.part];
   const int k = S.ka;
   const bool outer_check = S.mixed && k == 0;   // first inner iteration after a residual
   // one thread writes the record (total_iter is a read-modify-write)
@@ -1024,9 +1024,9 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
                                                     SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& P = parts[t.part];
-  SysState& S = sys[P.sys];
+  SysState& S = sys[t.sys];
   if (ld_flag(&S.done)) return;
+  const PartD& P = parts[t.part];
   const int k = S.kb;
   if (t.slot == 0 && threadIdx.x == 0) S.ka = k + 1;
   double v1[1];
@@ -1309,9 +1309,9 @@ __global__ void __launch_bounds__(MC_BLOCK) k_schur(const PartD* __restrict__ pa
                                                     SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& P = parts[t.part];
-  SysState& S = sys[P.sys];
+  SysState& S = sys[t.sys];
   if (ld_flag(&S.done)) return;
+  const PartD& P = parts[t.part];
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   schur_rows<T, true>(P, t, v[0]);
   write_slot<5>(S.partB, t.slot, v);
@@ -1707,9 +1707,9 @@ __device__ __forceinline__ void restrict_smooth_unit(const PartD& C, int unit) {
   ic0_block<T, R>(C, B, rv, (T*)C.mg_zp, dz, dr);
 }
 
-// (The finest level's V-cycle kernels and the restriction from it skip systems whose solve
-// has ended; the coarser ones only touch level scratch and run regardless, which saves a
-// dependent load.  `sys` is null for a plain application of the preconditioner.)
+// (Every V-cycle kernel skips systems whose solve has ended: the iterations launched past
+// convergence in a replayed chunk then cost only their launches.  The done flag is found
+// from the tile alone.  `sys` is null for a plain application of the preconditioner.)
 
 // restriction into a level: the workgroup's tiles of the finer level, one band per wavefront
 template <class T>
@@ -1718,7 +1718,8 @@ __global__ void __launch_bounds__(MC_BLOCK) k_mg_restrict(const PartD* __restric
                                                           SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& C = parts[t.part];   // (coarse levels only touch level scratch: no end test)
+  if (sys && ld_flag(&sys[t.sys].done)) return;
+  const PartD& C = parts[t.part];
   for (int tile = t.t0; tile < t.t1; ++tile)
     restrict_band_any<T, MC_TY / 4>(C, tile, (int)(threadIdx.x >> 6));
 }
@@ -1731,10 +1732,8 @@ k_mg_restrict_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ t
                      SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
+  if (sys && ld_flag(&sys[t.sys].done)) return;
   const PartD& C = parts[t.part];
-  // the restriction from the finest level reads a full set of its vectors: skip ended solves
-  // (below, only level scratch is touched and the test would cost a dependent load)
-  if (sys && C.mg_level == 1 && ld_flag(&sys[C.sys].done)) return;
   for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) {
     if (C.mg_fhas_t) restrict_smooth_unit<T, true>(C, u);
     else restrict_smooth_unit<T, false>(C, u);
@@ -1749,7 +1748,8 @@ k_mg_post_c(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
             SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD& P = parts[t.part];   // (coarse levels only touch level scratch: no end test)
+  if (sys && ld_flag(&sys[t.sys].done)) return;
+  const PartD& P = parts[t.part];
   double unused = 0.0;
   for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4)
     post_unit_any<T, false, MC_ICYC>(parts, P, u, unused);
@@ -1763,8 +1763,8 @@ k_mg_post(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
           SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
+  if (sys && ld_flag(&sys[t.sys].done)) return;
   const PartD& P = parts[t.part];
-  if (sys && ld_flag(&sys[P.sys].done)) return;
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for_wave_tiles(t, [&](int unit) { post_unit_any<T, FINAL, MC_ICY>(parts, P, unit, v[0]); });
   if (FINAL) write_slot<5>(sys[P.sys].partB, t.slot, v);
@@ -1781,7 +1781,8 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   constexpr int NW = MC_TAIL_THREADS / 64;
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
-  const PartD* P0 = &parts[t.part];   // (only level scratch is touched: no end test)
+  if (sys && ld_flag(&sys[t.sys].done)) return;
+  const PartD* P0 = &parts[t.part];
   static_assert(MC_TAIL_THREADS % (MC_MG_COARSE / 2) == 0, "tail threads: whole row pairs");
   const int wave = (int)(threadIdx.x >> 6);
   {   // pull the levels' FP32 coefficients and the coarsest inverse into the cache while the
