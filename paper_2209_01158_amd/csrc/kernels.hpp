@@ -1785,22 +1785,6 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   const PartD* P0 = &parts[t.part];
   static_assert(MC_TAIL_THREADS % (MC_MG_COARSE / 2) == 0, "tail threads: whole row pairs");
   const int wave = (int)(threadIdx.x >> 6);
-  {   // pull the levels' FP32 coefficients and the coarsest inverse into the cache while the
-      // first level is smoothed: loads folded into a value that is never stored
-    const PartD* Q = P0;
-    float acc = 0.0f;
-    for (;;) {
-      const int n = Q->n;
-      for (int k = threadIdx.x; k < n; k += MC_TAIL_THREADS)
-        acc += Q->diag32[k] + Q->tx32[k] + Q->ty32[k] + (Q->mg_next >= 0 ? Q->fdinv32[k] : 0.0f);
-      if (Q->mg_next < 0) break;
-      Q = &parts[Q->mg_next];
-    }
-    const long nq = (long)(Q->n + (Q->n & 1)) * (Q->n + (Q->n & 1)) / 4;   // float4 count
-    const float4* w = (const float4*)Q->mg_inv32;
-    for (long k = threadIdx.x; k < nq; k += MC_TAIL_THREADS) acc += w[k].x;
-    if (acc == 1.2345e-30f) ((float*)Q->mg_z)[0] = acc;   // keeps the loads; never true
-  }
   const PartD* P = P0;
   while (P->mg_next >= 0) {
     const int ntiles = (int)(((P->nx + MC_TX - 1) / MC_TX) * ((P->ny + MC_TY - 1) / MC_TY));
@@ -1814,7 +1798,7 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   {   // coarsest: z = A^-1 r by the FP32 copy of the dense (symmetric) inverse, stored with
       // an even leading dimension ld (zero padding): thread (pair p, chunk c) reads rows 2p,
       // 2p+1 of column j (one 2-wide load, consecutive across threads) for the chunk's j; the
-      // chunks' FP64 sums meet in LDS.  The inverse was prefetched at the start.
+      // chunks' FP64 sums meet in LDS.
     constexpr int NP = MC_MG_COARSE / 2, H = MC_TAIL_THREADS / NP;
     __shared__ double part[2][MC_TAIL_THREADS];
     const int n = P->n, ld = n + (n & 1);
