@@ -408,3 +408,56 @@ def test_warm_start_modes_and_history_reset():
         b.step(2)
         for x, y in zip(a.get_states(), b.get_states()):
             assert np.array_equal(x, y)
+
+
+# ------------------------------------------------------------------------------------
+# degenerate inputs
+# ------------------------------------------------------------------------------------
+def _no_transfer():
+    p = media.small_problem(n=70, seed=5, three=True, nseg=6, seg_len=(5, 40))
+    p.sigma_f = np.zeros_like(p.sigma_f)
+    p.sigma_omega = 0.0
+    return p
+
+
+def _zero_k():
+    # a quarter of the matrix cells impermeable (their faces carry no flux) and an
+    # impermeable natural-fracture continuum
+    p = media.small_problem(n=90, seed=6, three=True, nseg=5, seg_len=(5, 40))
+    k = p.omega[0].k.copy()
+    k[np.random.default_rng(1).random(k.shape) < 0.25] = 0.0
+    p.omega[0].k = k
+    p.omega[1].k_const = 0.0
+    return p
+
+
+def _isolated_fracture():
+    # fracture cells with no fracture-fracture connections at all
+    p = media.small_problem(n=64, seed=8, nseg=5, seg_len=(5, 30))
+    p.edges = np.zeros((0, 2), np.int32)
+    p.edge_d = np.zeros(0)
+    return p
+
+
+DEGENERATE = {"no_transfer": _no_transfer, "zero_k": _zero_k,
+              "isolated_fracture": _isolated_fracture}
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "bic0", "mg"])
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_degenerate_inputs(name, precond):
+    print(f"\n[degenerate {name} {precond}]", flush=True)
+    p = DEGENERATE[name]()
+    p.check()
+    for scheme in ("D", "coupled", "U"):
+        ref = schemes.run(p, scheme, 3, keep="all")
+        with mcdec.Problem(p, scheme=scheme, precond=precond, tol=1e-14) as g:
+            for n in range(1, 4):
+                rep = g.step(1)
+                err = rel(g.get_states(), ref[n])
+                assert err < 1e-10, (name, precond, scheme, n, err, rep)
+    if name == "no_transfer":
+        # with no transfer the continua are independent: every scheme is the coupled one
+        d = schemes.run(p, "D", 3, keep="last")
+        c = schemes.run(p, "coupled", 3, keep="last")
+        assert rel(d, c) < 1e-13
