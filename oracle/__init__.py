@@ -8,7 +8,8 @@ Contents
 --------
 fv        explicit sparse assembly of M, D, Q, F (Section 3.1: the two-point-flux
           semi-discrete forms for the two- and three-continuum and general models,
-          and the block matrix form M dp/dt + A p = F with A = D + Q)
+          and the block matrix form M dp/dt + A p = F with A = D + Q), with the implicit
+          fracture wells of Section 5
 schemes   time stepping: coupled backward Euler (Section 3.2) and the decoupled
           D-, L-, U-schemes (Section 3.3), plus the fully-lagged "EX" split, each system
           solved by sparse LU (SuperLU) with a certified residual
@@ -18,6 +19,7 @@ dense     a loop-by-loop dense assembler for tiny problems (brute-force cross-ch
 
 Every function is pinned by ``tests/test_oracle_pins.py`` against closed forms,
 invariants stated in the paper (Theorems 2 and 3, symmetry of A, Q_ab = Q_ba^T),
-textbook special cases and brute force.  Parity unpinned: nothing (the paper's own
-tables cannot be reproduced because its fracture geometry exists only in a figure).
+textbook special cases and brute force.  The paper's own table values are not pinned:
+its fracture geometry exists only in a figure and sigma and the aperture are not given,
+so its 2C / 3C errors can be compared for size and order only.
 """
