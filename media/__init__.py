@@ -7,8 +7,9 @@ solve are computed separately by the oracle and by the HIP library from these ar
 """
 from .problem import OmegaContinuum, Problem, BC_NOFLOW, BC_DIRICHLET
 from .configs import (config_problem, CONFIG_NAMES, small_problem, rect_problem,
-                      c4_problems, c5_trace, lognormal_field, paper_problem)
+                      c4_problems, c5_trace, lognormal_field, paper_problem,
+                      box_problem)
 
 __all__ = ["OmegaContinuum", "Problem", "BC_NOFLOW", "BC_DIRICHLET", "config_problem",
            "CONFIG_NAMES", "small_problem", "rect_problem", "c4_problems", "c5_trace", "lognormal_field",
-           "paper_problem"]
+           "paper_problem", "box_problem"]

@@ -425,3 +425,91 @@ def paper_problem(case: str = "2C", n: int = 200, seed: int = 11,
                           seg_id=seg_id, wells=int(inbox.sum())))
     p.check()
     return p
+
+
+# --------------------------------------------------------------------------------------
+# 3-D problems (the paper's stated extension): stacked planes, fracture planes
+# --------------------------------------------------------------------------------------
+def _fracture_planes(n: int, nz: int, nplane: int, lmin: int, lmax: int,
+                     rng: np.random.Generator) -> List[np.ndarray]:
+    """Axis-aligned fracture rectangles through cell centres of an n x n x nz grid, each a
+    list of host cells (in-plane row-major order) with its in-plane shape: normal ~ U{x, y,
+    z}; position ~ U over the cells along the normal; side lengths ~ U{lmin..lmax} cells
+    (clipped to the grid); corner ~ U."""
+    dims = (n, n, nz)   # cells along x, y, z
+    out = []
+    for _ in range(nplane):
+        normal = int(rng.integers(0, 3))
+        ax = [a for a in range(3) if a != normal]
+        pos = int(rng.integers(0, dims[normal]))
+        L = [min(int(rng.integers(lmin, lmax + 1)), dims[a]) for a in ax]
+        c0 = [int(rng.integers(0, dims[a] - L[k] + 1)) for k, a in enumerate(ax)]
+        u, v = np.meshgrid(np.arange(c0[0], c0[0] + L[0]), np.arange(c0[1], c0[1] + L[1]))
+        xyz = [None, None, None]
+        xyz[normal] = np.full(u.size, pos)
+        xyz[ax[0]] = u.ravel()
+        xyz[ax[1]] = v.ravel()
+        host = (xyz[2] * n + xyz[1]) * n + xyz[0]
+        out.append((host.astype(np.int64), (L[1], L[0])))   # rows along ax[1], columns ax[0]
+    return out
+
+
+def box_problem(n: int = 24, nz: int = 12, seed: int = 7, three: bool = False,
+                nplane: int = 4, lognormal: bool = True, tau: float = 1e-3, nsteps: int = 5,
+                plane_len=(4, 16)) -> Problem:
+    """A 3-D problem on an n x n x nz grid of cubes (h = 1/n): lognormal matrix permeability
+    (independent 2-D fields per plane, correlated in x and y) or constant 1e-4, the optional
+    natural-fracture continuum, and axis-aligned fracture planes cut into h x h cells
+    (measure aperture * h^2).  Fracture cells connect to their in-plane neighbours and,
+    where planes meet in a host cell, to each other; a connection's `edge_d` is the centre
+    distance over the interface measure, h / h = 1 here.  sigma_f = k_a(host) * area / h.
+    Dirichlet p = 1 on the west side, p = 0 on the east side, no-flow elsewhere."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    if lognormal:
+        k = np.stack([lognormal_field(n, rng, sigma_log=1.0) for _ in range(nz)])
+        omega = [OmegaContinuum(c=1.0, k=k)]
+    else:
+        omega = [OmegaContinuum(c=1.0, k_const=1e-4)]
+    if three:
+        omega.append(OmegaContinuum(c=C_NAT, k_const=K_NAT))
+    planes = _fracture_planes(n, nz, nplane, plane_len[0], plane_len[1], rng)
+    host = np.concatenate([p[0] for p in planes]) if planes else np.zeros(0, np.int64)
+    nf = len(host)
+    edges = []
+    off = 0
+    seg_id = []
+    for s, (hp, (rows, cols)) in enumerate(planes):
+        idx = off + np.arange(rows * cols).reshape(rows, cols)
+        edges.append(np.stack([idx[:, :-1].ravel(), idx[:, 1:].ravel()], axis=1))
+        edges.append(np.stack([idx[:-1, :].ravel(), idx[1:, :].ravel()], axis=1))
+        seg_id.append(np.full(rows * cols, s))
+        off += rows * cols
+    seg_id = np.concatenate(seg_id) if seg_id else np.zeros(0, np.int64)
+    order = np.lexsort((np.arange(nf), host))
+    hs = host[order]
+    starts = np.flatnonzero(np.r_[True, hs[1:] != hs[:-1]]) if nf else np.zeros(0, int)
+    ends = np.r_[starts[1:], nf]
+    cross = []
+    for s0, e0 in zip(starts, ends):
+        grp = order[s0:e0]
+        for i in range(len(grp)):
+            for j in range(i + 1, len(grp)):
+                a, b = int(grp[i]), int(grp[j])
+                if seg_id[a] != seg_id[b]:
+                    cross.append((min(a, b), max(a, b)))
+    edges.append(np.array(sorted(cross), np.int64).reshape(-1, 2))
+    edges = np.concatenate(edges).astype(np.int32) if nf else np.zeros((0, 2), np.int32)
+    flen = np.full(nf, h * h)
+    sig = np.zeros((len(omega), nf))
+    for a, o in enumerate(omega):
+        sig[a] = o.k_field(n, n, nz).reshape(-1)[host] * flen / h
+    bct, bcv = _bc_c1()
+    p = Problem(nx=n, ny=n, nz=nz, h=h, omega=omega, sigma_omega=SIGMA_NAT if three else 0.0,
+                host=host.astype(np.int32), flen=flen, edges=edges,
+                edge_d=np.ones(len(edges)), k_f=K_F, c_f=C_F, aperture=APERTURE,
+                sigma_f=sig, bc_type=bct, bc_value=bcv, src=None, p0=None, tau=tau,
+                nsteps=nsteps, meta=dict(name=f"box{n}x{n}x{nz}", precond="jacobi",
+                                         tol=1e-12, precision="fp64", seg_id=seg_id))
+    p.check()
+    return p

@@ -10,10 +10,14 @@ the time step tau and the initial pressures.
 Index conventions
 -----------------
 * Omega cells are row-major: cell (x, y) with column x in [0, nx) (west -> east) and row
-  y in [0, ny) (south -> north) has index y * nx + x.
+  y in [0, ny) (south -> north) has index y * nx + x.  A 3-D problem (nz > 1) stacks nz such
+  planes bottom to top: cell (x, y, z) has index (z * ny + y) * nx + x.  Cells are squares
+  (cubes in 3-D) of side h; a fracture cell's `flen` is its measure per unit aperture (its
+  length for the 1-D fractures of a 2-D problem, its area for fracture planes in 3-D).
 * Continua are ordered Omega continua first (ascending permeability: matrix, then the
   natural-fracture continuum in three-continuum media), then the explicit fracture.
-* Boundary sides are ordered W, E, S, N.
+* Boundary sides are ordered W, E, S, N, and in 3-D the bottom and top sides follow
+  (bc_type_z / bc_value_z).
 """
 from __future__ import annotations
 
@@ -33,10 +37,11 @@ class OmegaContinuum:
     k_const: float = 0.0
     k: Optional[np.ndarray] = None          # (ny, nx) float64 cell permeability, or None = k_const
 
-    def k_field(self, nx: int, ny: int) -> np.ndarray:
+    def k_field(self, nx: int, ny: int, nz: int = 1) -> np.ndarray:
+        shape = (ny, nx) if nz == 1 else (nz, ny, nx)
         if self.k is not None:
-            return np.asarray(self.k, dtype=np.float64).reshape(ny, nx)
-        return np.full((ny, nx), float(self.k_const))
+            return np.asarray(self.k, dtype=np.float64).reshape(shape)
+        return np.full(shape, float(self.k_const))
 
 
 @dataclass
@@ -66,6 +71,10 @@ class Problem:
     tau: float = 1e-3
     nsteps: int = 1
     meta: dict = field(default_factory=dict)
+    # 3-D: planes stacked in z (1 = the 2-D model), bottom and top boundary sides
+    nz: int = 1
+    bc_type_z: np.ndarray = field(default_factory=lambda: np.zeros(2, np.int32))
+    bc_value_z: np.ndarray = field(default_factory=lambda: np.zeros(2))
 
     # ---- sizes -----------------------------------------------------------------------
     @property
@@ -78,7 +87,11 @@ class Problem:
 
     @property
     def ncell(self) -> int:
-        return self.nx * self.ny
+        return self.nx * self.ny * self.nz
+
+    @property
+    def dim(self) -> int:
+        return 3 if self.nz > 1 else 2
 
     @property
     def n_cont(self) -> int:
@@ -109,7 +122,8 @@ class Problem:
 
     def check(self) -> None:
         """Shape and range checks on the raw input arrays (no physics)."""
-        assert self.nx >= 1 and self.ny >= 1 and self.h > 0 and self.tau > 0
+        assert self.nx >= 1 and self.ny >= 1 and self.nz >= 1 and self.h > 0 and self.tau > 0
+        assert len(self.bc_type_z) == 2 and len(self.bc_value_z) == 2
         assert self.n_omega in (1, 2)
         nf = self.nf
         assert self.flen.shape == (nf,)
@@ -130,5 +144,5 @@ class Problem:
             assert w.shape == (nf,) and np.all(np.isfinite(w))
         for o in self.omega:
             assert o.c > 0
-            k = o.k_field(self.nx, self.ny)
+            k = o.k_field(self.nx, self.ny, self.nz)
             assert np.all(np.isfinite(k)) and np.all(k >= 0)

@@ -19,6 +19,10 @@ Readings where the paper is silent (each is also listed in the design notes):
 * fracture cell measure |iota_l| = aperture * len_l; fracture connection
   T_e = k_f * aperture / d_e; the discrete matrix-fracture coefficients sigma_il are inputs;
 * the Omega-Omega transfer of the three-continuum model is sigma_12 |cell| per cell;
+* 3-D (the paper's stated extension, nz > 1 stacked planes): cubic cells of side h, so
+  |cell| = h^3 and |E| / d = h for interior faces (T = k h, harmonic mean for a cellwise k),
+  a Dirichlet side face T_b = 2 k_i h, and fracture planes whose cells have measure
+  aperture * area;
 * the wells of the numerical results (Section 5) are a fracture source q_w (p_w - p_f) per
   unit measure: the paper prints q_w (p - p_w), which with q_w = 1e5 on the right-hand side
   would be an anti-diffusive term that makes the system indefinite, so the physical sign is
@@ -53,6 +57,52 @@ def omega_transmissibilities(k: np.ndarray):
     tx = harm(k[:, :-1], k[:, 1:])
     ty = harm(k[:-1, :], k[1:, :])
     return tx, ty
+
+
+def _harm(a, b):
+    s = a + b
+    out = np.zeros_like(s)
+    nz = s > 0
+    out[nz] = 2.0 * a[nz] * b[nz] / s[nz]
+    return out
+
+
+def omega_diffusion_3d(k: np.ndarray, h: float, bc_type, bc_value, bc_type_z,
+                       bc_value_z) -> Tuple[sp.csr_matrix, np.ndarray]:
+    """D_a of an nz x ny x nx grid of cubes of side h (cells (z*ny + y)*nx + x): every interior
+    face T = h * harmonic mean of k, each Dirichlet side face T_b = 2 k_i h.  Sides W, E, S, N
+    from bc_type / bc_value, bottom and top from bc_type_z / bc_value_z."""
+    nz_, ny, nx = k.shape
+    n = nx * ny * nz_
+    idx = np.arange(n).reshape(nz_, ny, nx)
+    faces = ((h * _harm(k[:, :, :-1], k[:, :, 1:]), idx[:, :, :-1], idx[:, :, 1:]),
+             (h * _harm(k[:, :-1, :], k[:, 1:, :]), idx[:, :-1, :], idx[:, 1:, :]),
+             (h * _harm(k[:-1], k[1:]), idx[:-1], idx[1:]))
+    rows, cols, vals = [], [], []
+    diag = np.zeros(n)
+    for t, a, b in faces:
+        t, a, b = t.ravel(), a.ravel(), b.ravel()
+        rows += [a, b]
+        cols += [b, a]
+        vals += [-t, -t]
+        np.add.at(diag, a, t)
+        np.add.at(diag, b, t)
+    fb = np.zeros(n)
+    kf = k.ravel()
+    sides = [(idx[:, :, 0], bc_type[0], bc_value[0]), (idx[:, :, -1], bc_type[1], bc_value[1]),
+             (idx[:, 0, :], bc_type[2], bc_value[2]), (idx[:, -1, :], bc_type[3], bc_value[3]),
+             (idx[0], bc_type_z[0], bc_value_z[0]), (idx[-1], bc_type_z[1], bc_value_z[1])]
+    for cells, bt, bv in sides:
+        if int(bt) == BC_DIRICHLET:
+            cells = cells.ravel()
+            tb = 2.0 * kf[cells] * h
+            np.add.at(diag, cells, tb)
+            np.add.at(fb, cells, tb * float(bv))
+    rows.append(np.arange(n)); cols.append(np.arange(n)); vals.append(diag)
+    D = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    D.sum_duplicates()
+    return D, fb
 
 
 def omega_diffusion(k: np.ndarray, bc_type, bc_value) -> Tuple[sp.csr_matrix, np.ndarray]:
@@ -154,18 +204,23 @@ class Assembled:
 def assemble(prob) -> Assembled:
     """Assemble M, D, Q, F for a ``media.Problem``."""
     nx, ny, h = prob.nx, prob.ny, prob.h
-    nc = nx * ny
+    nz = getattr(prob, "nz", 1)
+    nc = nx * ny * nz
+    vol = h ** (3 if nz > 1 else 2)      # cell measure
     no = prob.n_omega
     nf = prob.nf
     sizes = [nc] * no + ([nf] if nf > 0 else [])
     M, D, F = [], [], []
     for a, o in enumerate(prob.omega):
-        k = o.k_field(nx, ny)
-        Da, fb = omega_diffusion(k, prob.bc_type, prob.bc_value)
+        if nz > 1:
+            Da, fb = omega_diffusion_3d(o.k_field(nx, ny, nz), h, prob.bc_type, prob.bc_value,
+                                        prob.bc_type_z, prob.bc_value_z)
+        else:
+            Da, fb = omega_diffusion(o.k_field(nx, ny), prob.bc_type, prob.bc_value)
         D.append(Da)
-        M.append(np.full(nc, o.c * h * h))
+        M.append(np.full(nc, o.c * vol))
         src = prob.source(a)
-        F.append(fb + (0.0 if src is None else src * h * h))
+        F.append(fb + (0.0 if src is None else src * vol))
     if nf > 0:
         meas = prob.aperture * np.asarray(prob.flen, np.float64)
         M.append(prob.c_f * meas)
@@ -183,7 +238,7 @@ def assemble(prob) -> Assembled:
         F.append(Ff)
     Q: Dict[Tuple[int, int], sp.csr_matrix] = {}
     if no == 2 and prob.sigma_omega != 0.0:
-        q = sp.diags(np.full(nc, prob.sigma_omega * h * h)).tocsr()
+        q = sp.diags(np.full(nc, prob.sigma_omega * vol)).tocsr()
         Q[(0, 1)] = q
         Q[(1, 0)] = q.T.tocsr()
     if nf > 0:

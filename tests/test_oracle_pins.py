@@ -85,6 +85,70 @@ def test_stencil_eigenvalues_textbook(bc):
     np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("bc", [(1, 1, 0, 0, 0, 0), (0, 0, 0, 0, 1, 1), (0, 0, 0, 0, 0, 0),
+                                (1, 1, 1, 1, 1, 1), (0, 0, 1, 1, 1, 0)])
+def test_stencil_eigenvalues_textbook_3d(bc):
+    """Constant-k 7-point operator on cubes of side h: eigenvalues k h (4 sin^2(pi i/2nx) +
+    4 sin^2(pi j/2ny) + 4 sin^2(pi l/2nz)); a Dirichlet pair of ends shifts an axis's indices
+    to 1..n, one Dirichlet end to half-integers (i + 1/2)."""
+    nx, ny, nz, k, h = 5, 4, 3, 0.37, 0.25
+    D, _ = fv.omega_diffusion_3d(np.full((nz, ny, nx), k), h, bc[:4], (0, 0, 0, 0), bc[4:],
+                                 (0, 0))
+    ev = np.sort(np.linalg.eigvalsh(D.toarray()))
+
+    def axis(n, lo, hi):
+        i = np.arange(n, dtype=float)
+        if lo and hi:
+            i = i + 1
+        elif lo or hi:
+            i = i + 0.5
+        return 4 * np.sin(np.pi * i / (2 * n)) ** 2
+
+    lx, ly, lz = axis(nx, bc[0], bc[1]), axis(ny, bc[2], bc[3]), axis(nz, bc[4], bc[5])
+    ref = np.sort((k * h * (lx[None, None, :] + ly[None, :, None] + lz[:, None, None])).ravel())
+    np.testing.assert_allclose(ev, ref, rtol=0, atol=1e-13)
+
+
+def test_layered_medium_series_resistance_z():
+    """Steady flow up a column of layers k_0..k_{n-1} between p = 1 (bottom) and p = 0 (top):
+    the profile of 1-D conductances in series, the same in every column."""
+    rng = np.random.default_rng(4)
+    nz, m = 7, 3
+    kl = np.exp(rng.normal(0, 1.5, nz))
+    k = np.broadcast_to(kl[:, None, None], (nz, m, m)).copy()
+    p = Problem(nx=m, ny=m, nz=nz, h=1.0 / m, omega=[OmegaContinuum(c=1.0, k=k)],
+                bc_type=np.zeros(4, np.int32), bc_value=np.zeros(4),
+                bc_type_z=np.array([1, 1], np.int32), bc_value_z=np.array([1.0, 0.0]),
+                tau=1e18)
+    x = schemes.run(p, "coupled", 1)[-1][0].reshape(nz, m * m)
+    flux = 1.0 / np.sum(1.0 / kl)
+    ref = 1.0 - flux * (np.concatenate([[0], np.cumsum(1.0 / kl)[:-1]]) + 0.5 / kl)
+    np.testing.assert_allclose(x, np.repeat(ref[:, None], m * m, axis=1), rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("scheme", ["coupled", "D", "L", "U"])
+def test_3d_constant_state_energy_and_mass(scheme):
+    """3-D: a constant state equal to every Dirichlet value stays put; with no-flow sides and
+    no sources the A-energy does not grow (Theorems 2 and 3), and the coupled scheme keeps
+    the mass."""
+    p = _tiny3d(three=True, bc=(1, 1, 1, 1), bcv=(0.7, 0.7, 0.7, 0.7), bcz=(1, 1),
+                bcvz=(0.7, 0.7), tau=0.1)
+    p.p0 = [np.full(s, 0.7) for s in p.sizes()]
+    for st in schemes.run(p, scheme, 3):
+        for v in st:
+            np.testing.assert_allclose(v, 0.7, rtol=0, atol=1e-13)
+    q = _tiny3d(three=True, bc=(0, 0, 0, 0), bcz=(0, 0), tau=0.3)
+    rng = np.random.default_rng(6)
+    q.p0 = [rng.normal(size=s) for s in q.sizes()]
+    asm = fv.assemble(q)
+    hist = schemes.run(q, scheme, 5)
+    e = [schemes.energy(asm, st) for st in hist]
+    assert all(e[i + 1] <= e[i] + 1e-14 * e[0] for i in range(len(e) - 1)), e
+    if scheme == "coupled":
+        mass = [sum(float(asm.M[a] @ st[a]) for a in range(asm.L)) for st in hist]
+        np.testing.assert_allclose(mass, mass[0], rtol=1e-13)
+
+
 @pytest.mark.parametrize("axis", ["x", "y"])
 def test_layered_medium_series_resistance(axis):
     """Steady flow through layers k_0..k_{n-1} between p=1 and p=0 half-cell faces: flux
@@ -160,13 +224,43 @@ def test_EX_unstable_where_D_is_not():
     assert abs(d[0][0] - d[1][0]) < 1.5
 
 
+def _tiny3d(three=False, seed=5, bc=(1, 1, 0, 0), bcv=(1.0, 0.0, 0, 0), bcz=(1, 0),
+            bcvz=(0.4, 0.0), tau=0.05):
+    """3 x 4 x 2 cubes (h = 0.5) with a lognormal k, and two fracture planes meeting in a
+    host cell (a 2 x 2 plane normal to z and a 2 x 1 plane normal to x)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz, h = 3, 4, 2, 0.5
+    k = np.exp(rng.normal(np.log(1e-1), 1.0, (nz, ny, nx)))
+    om = [OmegaContinuum(c=1.0, k=k)]
+    if three:
+        om.append(OmegaContinuum(c=0.05, k_const=2.0))
+    cell = lambda x, y, z: (z * ny + y) * nx + x  # noqa: E731
+    host = np.array([cell(0, 1, 1), cell(1, 1, 1), cell(0, 2, 1), cell(1, 2, 1),
+                     cell(1, 1, 0), cell(1, 1, 1)], np.int32)
+    edges = np.array([[0, 1], [2, 3], [0, 2], [1, 3], [4, 5], [1, 5]], np.int32)
+    p = Problem(nx=nx, ny=ny, nz=nz, h=h, omega=om, sigma_omega=3.0 if three else 0.0,
+                host=host, flen=np.full(6, h * h), edges=edges,
+                edge_d=rng.uniform(0.5, 1.5, len(edges)), k_f=5.0, c_f=0.1, aperture=0.2,
+                sigma_f=rng.uniform(0.1, 1.0, (len(om), 6)),
+                bc_type=np.array(bc, np.int32), bc_value=np.array(bcv, float),
+                bc_type_z=np.array(bcz, np.int32), bc_value_z=np.array(bcvz, float), tau=tau)
+    p.check()
+    return p
+
+
 @pytest.mark.parametrize("wells", [False, True])
 @pytest.mark.parametrize("three", [False, True])
-def test_dense_brute_force(three, wells):
-    p = _tiny(n=4, ny=3, three=three, nfc=4, seed=11, tau=0.05)
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dense_brute_force(three, wells, dim):
+    if dim == 2:
+        p = _tiny(n=4, ny=3, three=three, nfc=4, seed=11, tau=0.05)
+        wq, wp = [3.0, 0.0, 40.0, 0.5], [1.2, 7.0, -0.3, 2.0]
+    else:
+        p = _tiny3d(three=three)
+        wq, wp = [3.0, 0.0, 40.0, 0.5, 0.0, 2.0], [1.2, 7.0, -0.3, 2.0, 0.0, 0.9]
     if wells:
-        p.well_q = np.array([3.0, 0.0, 40.0, 0.5])
-        p.well_p = np.array([1.2, 7.0, -0.3, 2.0])
+        p.well_q = np.array(wq)
+        p.well_p = np.array(wp)
     K, mdiag, rf, _ = dense.coupled_dense(p, p.tau)
     asm = fv.assemble(p)
     np.testing.assert_allclose(schemes.coupled_matrix(asm, p.tau).toarray(), K, rtol=1e-14,
