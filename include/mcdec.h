@@ -82,7 +82,7 @@ typedef enum {
                     operators P^T A P (again 5-point conductance stencils), block IC(0) as the
                     pre- and post-smoother on every level, the coarsest level (at most 256
                     cells) solved by its dense inverse; fracture graph: as MC_BIC0.  Grids of
-                    at most 256 cells use plain block IC(0)                                     */
+                    at most 256 cells use plain block IC(0).  2-D grids only (nz <= 1)    */
 } mc_precond;
 
 /* One continuum on the Omega grid. */
@@ -90,7 +90,7 @@ typedef struct {
   double c;              /* storage coefficient c_a > 0                                       */
   double k_const;        /* permeability when k == NULL (>= 0)                                */
   const double *k;       /* [ny*nx] cell permeability (>= 0, finite) or NULL                  */
-  const double *src;     /* [ny*nx] source f_a per unit area, or NULL (= 0)                   */
+  const double *src;     /* [ny*nx] source f_a per unit area (volume in 3-D), or NULL (= 0)    */
   const double *p0;      /* [ny*nx] initial pressure, or NULL (= 0)                           */
 } mc_omega_desc;
 
@@ -122,6 +122,16 @@ typedef struct {
                             measure (the wells of Section 5, with the sign that injects when
                             p_f < p_w), treated implicitly in every scheme                      */
   const double *well_p;  /* [nf] well pressure p_w, or NULL (= 0); read only with well_q         */
+  int32_t nz;            /* 3-D grid (the extension the paper names as future work): nz > 1
+                            planes of nx*ny cubes of side h stacked bottom to top, cell (x,y,z)
+                            at (z*ny + y)*nx + x; every per-cell array then holds nz*ny*nx
+                            values and host indexes them.  Faces have |E|/d = h (conductance
+                            k h, Dirichlet side 2 k h), cells |cell| = h^3 (storage, sources,
+                            sigma_omega h^3).  Fracture cells are then cells of fracture planes:
+                            flen is their area, edge_d the centre distance over the interface
+                            length.  0 or 1: the 2-D model.  MC_MG needs a 2-D grid           */
+  int32_t bc_type_z[2];  /* (nz > 1) bottom (z = 0) and top (z = nz-1) sides: as bc_type       */
+  double bc_value_z[2];
 } mc_problem_desc;
 
 typedef struct {

@@ -67,7 +67,7 @@ struct PartD {
   int sys;           // owning system
   int cont;          // continuum index inside the problem
   int n;             // unknowns
-  int nx, ny;        // grid shape
+  int nx, ny;        // grid shape (3-D: ny counts the rows of all planes, stacked in z)
   int tiles_x;       // grid tiles per row of tiles
   int slot0A, slot0B; // first partial slot of this part inside its system (per tiling)
   int coupled;       // operator includes the off-diagonal transfer blocks (coupled scheme)
@@ -79,12 +79,14 @@ struct PartD {
   int frac;          // (grid) part index of the fracture part in this table or -1
   int omg[2];        // (graph) part indices of the Omega parts in this table or -1
   double tconst, tconst32pad;
+  long plane;        // (3-D grid) cells per plane, the index step in z; 0 for a 2-D grid
   double mtau;       // grid storage over tau: c h^2 / tau
   double s12;        // Omega-Omega discrete transfer sigma_omega h^2
   // FP64 coefficients
   const double* diag;      // [n] full system diagonal (storage/tau + conductances + S unless ex)
   const double* tx;        // [n] conductance to the east neighbour (0 on the last column)
   const double* ty;        // [n] conductance to the north neighbour (0 on the last row)
+  const double* tz;        // (3-D) [n] conductance to the cell above (0 on the top plane)
   const double* F;         // [n] sources and Dirichlet terms (may be null)
   const int* rowptr;       // graph CSR of off-diagonal conductances (positive values)
   const int* col;
@@ -94,6 +96,7 @@ struct PartD {
   const float* diag32;
   const float* tx32;
   const float* ty32;
+  const float* tz32;
   const float* val32;
   // IC(0) block factors (inverse pivots)
   const double* fdinv;

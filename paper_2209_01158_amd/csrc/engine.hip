@@ -316,6 +316,8 @@ struct Cont {  // one continuum
   double *diag = nullptr, *tx = nullptr, *ty = nullptr, *F = nullptr, *val = nullptr,
          *mt = nullptr;
   float *diag32 = nullptr, *tx32 = nullptr, *ty32 = nullptr, *val32 = nullptr;
+  double* tz = nullptr;      // (3-D grid) conductance to the cell above
+  float* tz32 = nullptr;
   double* fdinv = nullptr;   // block IC(0) inverse pivots
   float* fdinv32 = nullptr;
   double* cT = nullptr;      // (graph) block couplings to the previous cell
@@ -547,6 +549,7 @@ struct mc_problem {
   Exec X;                // X.opt: the problem's options
   int ncont = 0, n_omega = 0, nf = 0, ne = 0;
   long ncell = 0;
+  int nz = 1;            // planes of a 3-D grid (1: 2-D)
   DevArena mem;
   std::vector<Cont> cont;
   // inputs kept on the device (for re-setup)
@@ -589,6 +592,12 @@ static void clear_tables(mc_problem* P) {
   P->tables.clear();
 }
 
+// Omega-Omega transfer coefficient of one cell pair: sigma_omega |cell| (h^2, or h^3 in 3-D).
+static double omega_transfer(const mc_problem* P) {
+  const double h = P->d.h;
+  return P->nz > 1 ? P->d.sigma_omega * h * h * h : P->d.sigma_omega * h * h;
+}
+
 // ------------------------------------------------------------------------------------
 // parts of a problem
 // ------------------------------------------------------------------------------------
@@ -601,8 +610,9 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.cont = c;
   q.n = (int)C.n;
   q.nx = P->d.nx;
-  q.ny = P->d.ny;
+  q.ny = P->d.ny * P->nz;   // 3-D: the planes' rows stacked
   q.tiles_x = (int)cdiv(P->d.nx, MC_TX);
+  q.plane = P->nz > 1 && C.kind == PART_GRID ? (long)P->d.nx * P->d.ny : 0;
   q.slot0A = slot0A;
   q.slot0B = slot0B;
   q.ex = P->X.opt.scheme == MC_SCHEME_EX;
@@ -614,10 +624,12 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.omg[0] = q.omg[1] = -1;
   q.tconst = C.tconst;
   q.mtau = C.mtau;
-  q.s12 = P->n_omega == 2 ? P->d.sigma_omega * P->d.h * P->d.h : 0.0;
+  q.s12 = P->n_omega == 2 ? omega_transfer(P) : 0.0;
   q.diag = C.diag;
   q.tx = C.tx;
   q.ty = C.ty;
+  q.tz = C.tz;
+  q.tz32 = C.tz32;
   q.F = C.F;
   q.rowptr = P->rowptr;
   q.col = P->col;
@@ -994,15 +1006,20 @@ static void build_coefficients(mc_problem* P) {
     std::memset(&g, 0, sizeof(g));
     g.nx = P->d.nx;
     g.ny = P->d.ny;
+    g.nz = P->nz;
     g.k = P->k[a];
     g.kc = P->d.omega[a].k_const;
     g.c = P->d.omega[a].c;
     g.h = h;
     g.tau = tau;
-    g.s12 = P->n_omega == 2 ? P->d.sigma_omega * h * h : 0.0;
+    g.s12 = P->n_omega == 2 ? omega_transfer(P) : 0.0;
     for (int k = 0; k < 4; ++k) {
       g.bc_type[k] = P->d.bc_type[k];
       g.bc_value[k] = P->d.bc_value[k];
+    }
+    for (int k = 0; k < 2; ++k) {
+      g.bc_type_z[k] = P->d.bc_type_z[k];
+      g.bc_value_z[k] = P->d.bc_value_z[k];
     }
     g.src = P->src[a];
     g.hptr = P->nf ? P->hptr : nullptr;
@@ -1012,10 +1029,12 @@ static void build_coefficients(mc_problem* P) {
     g.diag = C.diag;
     g.tx = C.tx;
     g.ty = C.ty;
+    g.tz = C.tz;
     g.F = C.F;
     hipLaunchKernelGGL(k_setup_grid, dim3(cdiv(C.n, 256)), dim3(256), 0, s, g);
-    C.mtau = P->d.omega[a].c * h * h / tau;
-    C.has_t = P->k[a] != nullptr;
+    C.mtau = (P->nz > 1 ? P->d.omega[a].c * h * h * h : P->d.omega[a].c * h * h) / tau;
+    // a 3-D grid always uses the conductance arrays (ty is 0 across plane boundaries)
+    C.has_t = P->k[a] != nullptr || P->nz > 1;
     C.tconst = P->d.omega[a].k_const;
   }
   if (P->nf) {
@@ -1053,7 +1072,7 @@ static void build_coefficients(mc_problem* P) {
       if (C.kind == PART_GRID) {
         GridIC0Setup g;
         g.nx = P->d.nx;
-        g.ny = P->d.ny;
+        g.ny = P->d.ny * P->nz;
         g.tiles_x = (int)cdiv(P->d.nx, MC_TX);
         g.ntiles = C.tiles;
         g.diag = C.diag;
@@ -1119,6 +1138,7 @@ static void build_coefficients(mc_problem* P) {
       if (C.kind == PART_GRID) {
         cv(C.tx, C.tx32, C.n);
         cv(C.ty, C.ty32, C.n);
+        if (C.tz) cv(C.tz, C.tz32, C.n);
       } else {
         cv(C.val, C.val32, 2L * P->ne);
       }
@@ -1167,7 +1187,10 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   P->n_omega = d.n_omega;
   P->nf = d.nf;
   P->ne = d.ne;
-  P->ncell = (long)d.nx * d.ny;
+  P->nz = d.nz > 1 ? d.nz : 1;
+  P->ncell = (long)d.nx * d.ny * P->nz;
+  if (P->nz > 1 && o.precond == MC_MG)
+    fail("the multigrid preconditioner needs a 2-D grid (nz <= 1); use MC_JACOBI or MC_BIC0");
   P->ncont = d.n_omega + (d.nf > 0 ? 1 : 0);
   exec_init(P->X, o.stream);
   P->X.opt.stream = P->X.stream;
@@ -1214,7 +1237,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     const bool grid = c < d.n_omega;
     C.kind = grid ? PART_GRID : PART_GRAPH;
     C.n = grid ? P->ncell : d.nf;
-    C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY)) : P->ngtiles;
+    C.tiles = grid ? (int)(cdiv(d.nx, MC_TX) * cdiv((long)d.ny * P->nz, MC_TY)) : P->ngtiles;
     C.blocks[0] = blocks_for(C.tiles, C.kind, 0, ic_precond(o.precond), o.precision == MC_MIXED);
     C.blocks[1] = blocks_for(C.tiles, C.kind, 1, ic_precond(o.precond), o.precision == MC_MIXED);
     C.blocks[2] = 0;
@@ -1223,6 +1246,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     if (grid) {
       C.tx = M.alloc<double>(C.n);
       C.ty = M.alloc<double>(C.n);
+      if (P->nz > 1) C.tz = M.alloc<double>(C.n);
     } else {
       C.val = M.alloc<double>(std::max<long>(1, 2L * d.ne));
       C.mt = M.alloc<double>(C.n);
@@ -2101,8 +2125,9 @@ static void autotune(mc_problem* const* probs, int n, int iters) {
 // every array create() and build_coefficients() request; chains and fracture tiles are
 // bounded by nf + 1), plus launch tables and a rounding allowance per allocation.
 static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
-  const int64_t nc = (int64_t)d.nx * d.ny, nf = d.nf, ne = d.ne;
-  const int64_t gt = (int64_t)cdiv(d.nx, MC_TX) * cdiv(d.ny, MC_TY);
+  const int64_t nzp = d.nz > 1 ? d.nz : 1;
+  const int64_t nc = (int64_t)d.nx * d.ny * nzp, nf = d.nf, ne = d.ne;
+  const int64_t gt = (int64_t)cdiv(d.nx, MC_TX) * cdiv((int64_t)d.ny * nzp, MC_TY);
   const bool bic0 = ic_precond(o.precond), mixed = o.precision == MC_MIXED;
   int64_t b = 0, nalloc = 0;
   auto A = [&](int64_t bytes) {
@@ -2142,6 +2167,10 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
     if (grid) {
       A(8 * n);                   // tx
       A(8 * n);                   // ty
+      if (nzp > 1) {
+        A(8 * n);                 // tz
+        if (mixed) A(4 * n);      // tz32
+      }
     } else {
       A(8 * std::max<int64_t>(1, 2 * ne));
       A(8 * n);                   // mt
@@ -2463,6 +2492,8 @@ mc_status mc_set_options(mc_problem* P, const mc_options* o) {
   if (!m.empty()) throw mc::Error{MC_EINVAL, m};
   if (o->stream && o->stream != (void*)P->X.stream)
     throw mc::Error{MC_EINVAL, "the stream cannot change after creation"};
+  if (P->nz > 1 && o->precond == MC_MG)
+    throw mc::Error{MC_EINVAL, "the multigrid preconditioner needs a 2-D grid (nz <= 1)"};
   const mc_options& cur = P->X.opt;
   const bool rebuild = (o->scheme == MC_SCHEME_EX) != (cur.scheme == MC_SCHEME_EX) ||
                        (o->precision != cur.precision) || (o->precond != cur.precond);

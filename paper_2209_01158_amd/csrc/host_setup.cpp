@@ -19,11 +19,13 @@ std::string fmt(const char* f, long a = 0, long b = 0) {
 
 std::string validate_desc(const mc_problem_desc& d) {
   if (d.nx < 1 || d.ny < 1) return "nx and ny must be >= 1";
-  if ((long)d.nx * (long)d.ny > (1L << 31) - 2) return "grid too large for 32-bit cell indices";
+  if (d.nz < 0) return "nz must be >= 0 (0 or 1: a 2-D grid)";
+  const long nzp = d.nz > 1 ? d.nz : 1;
+  if ((long)d.nx * (long)d.ny * nzp > (1L << 31) - 2) return "grid too large for 32-bit cell indices";
   if (!(d.h > 0) || !fin(d.h)) return "h must be finite and > 0";
   if (!(d.tau > 0) || !fin(d.tau)) return "tau must be finite and > 0";
   if (d.n_omega != 1 && d.n_omega != 2) return "n_omega must be 1 or 2";
-  const long nc = (long)d.nx * d.ny;
+  const long nc = (long)d.nx * d.ny * nzp;
   for (int a = 0; a < d.n_omega; ++a) {
     const mc_omega_desc& o = d.omega[a];
     if (!(o.c > 0) || !fin(o.c)) return fmt("omega[%ld].c must be finite and > 0", a);
@@ -45,6 +47,11 @@ std::string validate_desc(const mc_problem_desc& d) {
     if (d.bc_type[s] != 0 && d.bc_type[s] != 1) return fmt("bc_type[%ld] must be 0 or 1", s);
     if (d.bc_type[s] == 1 && !fin(d.bc_value[s])) return fmt("bc_value[%ld] not finite", s);
   }
+  if (nzp > 1)
+    for (int s = 0; s < 2; ++s) {
+      if (d.bc_type_z[s] != 0 && d.bc_type_z[s] != 1) return fmt("bc_type_z[%ld] must be 0 or 1", s);
+      if (d.bc_type_z[s] == 1 && !fin(d.bc_value_z[s])) return fmt("bc_value_z[%ld] not finite", s);
+    }
   if (d.nf < 0) return "nf must be >= 0";
   if (d.nf > 0) {
     if (!d.host || !d.flen || !d.sigma_f) return "host, flen and sigma_f are required when nf > 0";

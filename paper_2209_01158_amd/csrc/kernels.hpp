@@ -114,7 +114,7 @@ __device__ __forceinline__ double harm(double a, double b) {
 }
 
 struct GridSetup {
-  int nx, ny;
+  int nx, ny, nz;   // ny rows per plane, nz planes (1: the 2-D model)
   const double* k;  // may be null
   double kc, c, h, tau, s12;
   int bc_type[4];
@@ -123,39 +123,60 @@ struct GridSetup {
   const int* hptr;
   const int* hidx;
   const double* hsig;
+  int bc_type_z[2];    // (3-D) bottom, top
+  double bc_value_z[2];
   int ex;
-  double *diag, *tx, *ty, *F;
+  double *diag, *tx, *ty, *tz, *F;   // tz: 3-D only
 };
 
-// Storage c h^2 / tau, harmonic-mean face conductances, half-cell Dirichlet faces (2 k),
-// transfer row sums S (sigma_omega h^2 plus the sigma of every fracture cell hosted here).
+// Storage c |cell| / tau, harmonic-mean face conductances, half-cell Dirichlet faces,
+// transfer row sums S (sigma_omega |cell| plus the sigma of every fracture cell hosted here).
+// 2-D: |cell| = h^2 and a face's |E| / d = 1.  3-D (nz > 1, planes stacked in z): |cell| = h^3,
+// |E| / d = h; ty is 0 on the last row of every plane (the plane above is not a north
+// neighbour) and tz couples a cell to the one above it.
 __global__ void k_setup_grid(GridSetup g) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long n = (long)g.nx * g.ny;
+  const long plane = (long)g.nx * g.ny;
+  const long n = plane * g.nz;
   if (i >= n) return;
-  const int x = (int)(i % g.nx), y = (int)(i / g.nx);
+  const int x = (int)(i % g.nx);
+  const int y = (int)((i / g.nx) % g.ny), z = (int)(i / plane);
+  const bool d3 = g.nz > 1;
+  const double fac = d3 ? g.h : 1.0;   // |E| / d of a face
   auto K = [&](long j) { return g.k ? g.k[j] : g.kc; };
   const double kc = K(i);
-  double tE = x + 1 < g.nx ? harm(kc, K(i + 1)) : 0.0;
-  double tN = y + 1 < g.ny ? harm(kc, K(i + g.nx)) : 0.0;
-  double tW = x > 0 ? harm(K(i - 1), kc) : 0.0;
-  double tS = y > 0 ? harm(K(i - g.nx), kc) : 0.0;
+  double tE = x + 1 < g.nx ? fac * harm(kc, K(i + 1)) : 0.0;
+  double tN = y + 1 < g.ny ? fac * harm(kc, K(i + g.nx)) : 0.0;
+  double tW = x > 0 ? fac * harm(K(i - 1), kc) : 0.0;
+  double tS = y > 0 ? fac * harm(K(i - g.nx), kc) : 0.0;
   double tb = 0.0, fb = 0.0;
-  const bool side[4] = {x == 0, x == g.nx - 1, y == 0, y == g.ny - 1};
-  for (int s = 0; s < 4; ++s)
-    if (side[s] && g.bc_type[s] == 1) {
-      tb += 2.0 * kc;
-      fb += 2.0 * kc * g.bc_value[s];
+  const bool side[6] = {x == 0, x == g.nx - 1, y == 0, y == g.ny - 1, d3 && z == 0,
+                        d3 && z == g.nz - 1};
+  for (int s = 0; s < 6; ++s) {
+    const int bt = s < 4 ? g.bc_type[s] : g.bc_type_z[s - 4];
+    if (side[s] && bt == 1) {
+      const double bv = s < 4 ? g.bc_value[s] : g.bc_value_z[s - 4];
+      tb += 2.0 * kc * fac;
+      fb += 2.0 * kc * fac * bv;
     }
+  }
   double S = g.s12;
   if (g.hptr)
     for (int j = g.hptr[i]; j < g.hptr[i + 1]; ++j) S += g.hsig[g.hidx[j]];
-  double d = g.c * g.h * g.h / g.tau + ((tE + tW) + (tN + tS)) + tb;
+  double faces = (tE + tW) + (tN + tS);
+  double tU = 0.0;
+  if (d3) {
+    tU = z + 1 < g.nz ? fac * harm(kc, K(i + plane)) : 0.0;
+    const double tD = z > 0 ? fac * harm(K(i - plane), kc) : 0.0;
+    faces += tU + tD;
+  }
+  double d = (d3 ? g.c * g.h * g.h * g.h : g.c * g.h * g.h) / g.tau + faces + tb;
   if (!g.ex) d += S;
   g.diag[i] = d;
   g.tx[i] = tE;
   g.ty[i] = tN;
-  g.F[i] = fb + (g.src ? g.src[i] * g.h * g.h : 0.0);
+  if (d3) g.tz[i] = tU;
+  g.F[i] = fb + (g.src ? (d3 ? g.src[i] * g.h * g.h * g.h : g.src[i] * g.h * g.h) : 0.0);
 }
 
 struct GraphSetup {
@@ -227,6 +248,11 @@ __device__ __forceinline__ T grid_Av(const PartD& P, int x, int y, long i, T vi,
     if (x + 1 < nx) acc -= tx[i] * v(i + 1);
     if (y > 0) acc -= ty[i - nx] * v(i - nx);
     if (y + 1 < P.ny) acc -= ty[i] * v(i + nx);
+    if (P.plane) {   // 3-D: the cells below and above (ty is 0 across a plane boundary)
+      const T* tz = pick<T>(P.tz, P.tz32);
+      if (i >= P.plane) acc -= tz[i - P.plane] * v(i - P.plane);
+      if (i + P.plane < (long)P.n) acc -= tz[i] * v(i + P.plane);
+    }
   } else {
     const T t = (T)P.tconst;
     T s = (T)0;
@@ -986,6 +1012,11 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
         }
         if (cx < nx && cy < ny) {
           const long i = (long)cy * nx + cx;
+          if (P.plane) {   // 3-D: the cells below and above, outside the plane's tile
+            const gconst<T> tz = gc(pick<T>(P.tz, P.tz32));
+            if (i >= P.plane) acc -= tz[i - P.plane] * pn_of(P, i - P.plane);
+            if (i + P.plane < (long)P.n) acc -= tz[i] * pn_of(P, i + P.plane);
+          }
           if (P.coupled) {
             auto vp = [&](int pj, long j) { return (double)pn_of(parts[pj], j); };
             acc = (T)((double)acc + grid_coupling(parts, P, i, vp));

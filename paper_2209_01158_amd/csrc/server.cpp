@@ -29,7 +29,7 @@ struct HostDesc {
 
   void take(const mc_problem_desc& in) {
     d = in;
-    const size_t nc = (size_t)in.nx * in.ny;
+    const size_t nc = (size_t)in.nx * in.ny * (in.nz > 1 ? in.nz : 1);
     auto cp = [](std::vector<double>& v, const double* a, size_t n) -> const double* {
       if (!a) return nullptr;
       v.assign(a, a + n);

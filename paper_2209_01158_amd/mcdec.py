@@ -51,7 +51,8 @@ class ProblemDesc(C.Structure):
                 ("edges", _ip), ("edge_d", _dp), ("k_f", C.c_double), ("c_f", C.c_double),
                 ("aperture", C.c_double), ("sigma_f", _dp), ("src_f", _dp), ("p0_f", _dp),
                 ("bc_type", C.c_int32 * 4), ("bc_value", C.c_double * 4), ("tau", C.c_double),
-                ("well_q", _dp), ("well_p", _dp)]
+                ("well_q", _dp), ("well_p", _dp), ("nz", C.c_int32),
+                ("bc_type_z", C.c_int32 * 2), ("bc_value_z", C.c_double * 2)]
 
 
 class Options(C.Structure):
@@ -288,6 +289,12 @@ def describe(prob):
         d.bc_type[s] = int(prob.bc_type[s])
         d.bc_value[s] = float(prob.bc_value[s])
     d.tau = prob.tau
+    nz = int(getattr(prob, "nz", 1))
+    d.nz = nz
+    if nz > 1:
+        for s in range(2):
+            d.bc_type_z[s] = int(prob.bc_type_z[s])
+            d.bc_value_z[s] = float(prob.bc_value_z[s])
     return d, keep
 
 

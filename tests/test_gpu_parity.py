@@ -461,3 +461,78 @@ def test_degenerate_inputs(name, precond):
         d = schemes.run(p, "D", 3, keep="last")
         c = schemes.run(p, "coupled", 3, keep="last")
         assert rel(d, c) < 1e-13
+
+
+# ------------------------------------------------------------------------------------
+# 3-D grids (stacked planes, 7-point stencil) with fracture planes
+# ------------------------------------------------------------------------------------
+def _box_zdirichlet():
+    # Dirichlet bottom and top as well; 70 = 64 + 6 columns and 70 * 5 = 350 = 21 * 16 + 14
+    # stacked rows: ragged tiles in both directions, planes meeting inside tiles
+    p = media.box_problem(n=70, nz=5, seed=3, nplane=6, plane_len=(5, 30))
+    p.bc_type_z = np.array([1, 1], np.int32)
+    p.bc_value_z = np.array([0.3, 0.8])
+    return p
+
+
+BOXES = {
+    "box24x12_3c": lambda: media.box_problem(n=24, nz=12, seed=7, three=True),
+    "box70x5_zdir": _box_zdirichlet,
+    "box2x3": lambda: media.box_problem(n=2, nz=3, seed=1, nplane=1, plane_len=(1, 2)),
+}
+
+
+@pytest.fixture(scope="module", params=list(BOXES))
+def box(request):
+    print(f"\n[3-D case {request.param}]", flush=True)
+    return request.param, BOXES[request.param]()
+
+
+def test_3d_operators(box):
+    name, p = box
+    asm = fv.assemble(p)
+    rng = np.random.default_rng(4)
+    with mcdec.Problem(p) as g:
+        for a in range(p.n_cont):
+            K = schemes.continuum_matrix(asm, p.tau, a)
+            x = rng.standard_normal(p.sizes()[a])
+            y = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
+            g.apply_continuum(a, T(x), y)
+            assert rel(y.cpu().numpy(), K @ x) < 1e-14, (name, a)
+        K = schemes.coupled_matrix(asm, p.tau)
+        x = rng.standard_normal(p.dof())
+        y = torch.zeros(p.dof(), dtype=torch.float64, device=DEV)
+        g.apply_coupled(T(x), y)
+        assert rel(y.cpu().numpy(), K @ x) < 1e-14, name
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "bic0"])
+@pytest.mark.parametrize("scheme", ["D", "coupled", "U"])
+def test_3d_trajectory(box, scheme, precond):
+    name, p = box
+    ref = schemes.run(p, scheme, 3, keep="all")
+    with mcdec.Problem(p, scheme=scheme, precond=precond, tol=1e-14) as g:
+        for n in range(1, 4):
+            rep = g.step(1)
+            err = rel(g.get_states(), ref[n])
+            assert err < 1e-10, (name, scheme, precond, n, err, rep)
+
+
+def test_3d_mixed_precision(box):
+    name, p = box
+    ref = schemes.run(p, "D", 3, keep="last")
+    with mcdec.Problem(p, precision="mixed", precond="bic0", outer_tol=1e-12) as g:
+        rep = g.step(3)
+        err = rel(g.get_states(), ref)
+        assert err < 1e-8, (name, err, rep)
+
+
+def test_3d_multigrid_refused():
+    p = media.box_problem(n=16, nz=4, seed=2)
+    with pytest.raises(mcdec.McError) as ei:
+        mcdec.Problem(p, precond="mg")
+    assert ei.value.status == mcdec.MC_EINVAL and "2-D" in str(ei.value)
+    with mcdec.Problem(p, precond="bic0") as g:
+        with pytest.raises(mcdec.McError) as ei:
+            g.set_options(precond="mg")
+        assert ei.value.status == mcdec.MC_EINVAL
