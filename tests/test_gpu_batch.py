@@ -231,3 +231,22 @@ def test_autotune_keeps_state_and_batch_equals_alone():
         for g in gs:
             g.close()
         mcdec.autotune_clear()
+
+
+@pytest.mark.parametrize("key", ["fp64_jacobi", "fp64_bic0", "mixed_bic0", "coupled"])
+def test_batch_with_3d_problems(key):
+    """3-D problems (stacked planes, fracture planes) share launches with 2-D ones: bitwise
+    equal to alone, and within the usual gate of the oracle."""
+    print(f"\n[batch 3-D {key}]", flush=True)
+    probs = [media.box_problem(n=24, nz=12, seed=7, three=True),
+             media.small_problem(n=70, seed=5, three=True, nseg=6, seg_len=(5, 40)),
+             media.box_problem(n=70, nz=5, seed=3, nplane=6, plane_len=(5, 30))]
+    opt = OPTS[key]
+    alone = alone_states(probs, 3, **opt)
+    mixed, reps = batch_states(probs, 3, **opt)
+    assert_bitwise(alone, mixed)
+    gate = 1e-8 if opt["precision"] == "mixed" else 1e-9
+    for p, s in zip(probs, mixed):
+        err = rel(s, schemes.run(p, opt["scheme"], 3, keep="last"))
+        print(p.nx, p.nz, err, flush=True)
+        assert err < gate

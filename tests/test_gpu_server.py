@@ -28,6 +28,7 @@ def requests():
         (media.small_problem(n=97, seed=9, three=True, nseg=0, lognormal=False), 5),
         (media.small_problem(n=160, seed=12, three=True, nseg=8, seg_len=(10, 60)), 2),
         (_wells(), 5),
+        (media.box_problem(n=24, nz=12, seed=7, three=True), 4),   # 3-D
     ]
 
 
