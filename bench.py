@@ -11,6 +11,9 @@ Workloads (``--workload``):
   C4            256 independent realizations of uneven size (128..1024 cells a side, two or
                 three continua), 50 layers, all advanced by shared launches in FP32 inner PCG
                 inside FP64 refinement.
+  3D            the 3-D extension: two continua on a 256 x 256 x 256 grid of cubes (lognormal
+                matrix permeability per plane, 40 fracture planes), 20 layers, D-scheme,
+                FP64 block IC(0) PCG to 1e-10.
   C5            serving: a seeded Poisson trace of simulation requests (mean 40/s, sides
                 64..2048, 10..500 layers each) replayed in real time against the server
                 (admission by device-memory footprint, continuous batching); a "step" there is
@@ -48,6 +51,8 @@ DEFAULTS = {
     "C3": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=1),
     "C4": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=2),
     "C5": dict(precond="mg", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
+    "3D": dict(precond="bic0", precision="fp64", tol=1e-10, steps=20, coupled_steps=2,
+               sample_every=2),
 }
 
 # HBM bytes per dispatch of the grid PCG kernels, from two rocprofv3 counter passes
@@ -83,10 +88,10 @@ def measured_traffic(workload, precond, kernel):
     return (m["fetch_kib"] * m["read_factor"] + m["write_kib"] * m["write_factor"]) * 1024.0
 
 
-def grid_bytes_per_cell(kernel, precision, precond, has_t):
+def grid_bytes_per_cell(kernel, precision, precond, has_t, dim=2):
     """Algorithmic bytes a grid PCG kernel must move per cell (w = 4 or 8 byte words).
 
-    A (operator): read z (Jacobi: r), p_old, diag [, tx, ty]; write p_new, q.
+    A (operator): read z (Jacobi: r), p_old, diag [, tx, ty] [3-D: tz]; write p_new, q.
     B (update):   read x, p, r, q; write x, r; Jacobi also reads diag (z = r / diag is
                   recomputed where needed, never stored); block IC(0) reads the FP32 copies
                   of the inverse pivots and of tx, ty (4 bytes each) and writes z (under mg
@@ -96,7 +101,7 @@ def grid_bytes_per_cell(kernel, precision, precond, has_t):
                   FP32 tx, ty, shared by the residual and the sweep]; write z."""
     w = 4 if precision == "mixed" else 8
     if kernel == "A":
-        return (3 + (2 if has_t else 0) + 2) * w
+        return (3 + (2 if has_t else 0) + (1 if dim == 3 else 0) + 2) * w
     if kernel == "P":
         return 3 * w + w / 4 + (2 + (2 if has_t else 0)) * 4
     if precond in ("bic0", "mg"):
@@ -206,6 +211,9 @@ def cpu_baseline(workload):
     elif workload == "C3":
         probs, steps = [media.configs._c3(n=1024, min_cells=150_000 // 16)], 3
         what = "C3 recipe at 1024x1024 (three continua)"
+    elif workload == "3D":
+        probs, steps = [media.configs._3d(n=32, nz=32)], 20
+        what = "3-D recipe at 32x32x32 (sparse LU of 3-D systems fills in fast)"
     else:
         probs, steps = media.configs.c4_problems(only=[55, 212]), 10
         what = "realizations 55 and 212 of the batched workload"
@@ -248,11 +256,12 @@ def kernels_of(precond):
 def step_bytes(p, rep, precision, precond):
     """Algorithmic bytes of the grid A, B (and mg: P) kernels for one layer of problem p."""
     out = {"A": 0.0, "B": 0.0} if precond != "mg" else {"A": 0.0, "B": 0.0, "P": 0.0}
+    dim = getattr(p, "dim", 2)
     for c in range(p.n_omega):
-        has_t = p.omega[c].k is not None
+        has_t = p.omega[c].k is not None or dim == 3
         for k in out:
             out[k] += rep["iters"][c] * p.ncell * grid_bytes_per_cell(k, precision, precond,
-                                                                      has_t)
+                                                                      has_t, dim)
     return out
 
 
@@ -355,7 +364,8 @@ def run_single(args, out):
     roof, roof2 = roofline(prof, tot, args.precision, args.precond, args.workload)
     out.update({
         "value": value, "ms_per_step": elapsed / args.steps * 1e3,
-        "config": {"workload": f"{args.workload}: {p.n_cont}-continuum {p.nx}x{p.ny} + "
+        "config": {"workload": f"{args.workload}: {p.n_cont}-continuum {p.nx}x{p.ny}"
+                   f"{'x%d' % p.nz if getattr(p, 'nz', 1) > 1 else ''} + "
                    f"{p.nf} fracture cells, tau={p.tau}, D-scheme {args.precision}, "
                    f"PCG {args.precond} tol {args.tol}", "dof": dof,
                    "precond": args.precond, "scheme": "D", "precision": args.precision,
@@ -604,8 +614,10 @@ def main():
                     help="C5: device memory the resident requests may hold")
     ap.add_argument("--max-resident", type=int, default=0, help="C5: resident requests (0=256)")
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--sample-every", type=int, default=32,
-                    help="time one grid PCG launch in this many (HIP events)")
+    ap.add_argument("--sample-every", type=int, default=None,
+                    help="time one grid PCG iteration in this many (HIP events; default 32, "
+                         "2 for the 3-D workload, whose layers take only a few grid "
+                         "iterations)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -619,6 +631,8 @@ def main():
     for k in ("precond", "precision", "tol", "steps", "coupled_steps"):
         if getattr(args, k) is None:
             setattr(args, k, d[k])
+    if args.sample_every is None:
+        args.sample_every = d.get("sample_every", 32)
     if args.inner_tol is None:
         args.inner_tol = 1e-4 if args.precond == "mg" else 1e-6
     if args.warm_start is None:

@@ -209,9 +209,18 @@ def _c3(seed: int = 3, n: int = 4096, min_cells: int = 150_000) -> Problem:
                          meta=dict(name="C3", precond="jacobi", tol=1e-10, precision="mixed"))
 
 
+def _3d(seed: int = 8, n: int = 256, nz: int = 256) -> Problem:
+    # plane sides scale with the grid (16..96 cells at n = 256)
+    lo, hi = max(2, 16 * n // 256), max(4, 96 * n // 256)
+    p = box_problem(n=n, nz=nz, seed=seed, nplane=40, plane_len=(lo, hi), nsteps=20)
+    p.meta.update(name="3D", precond="bic0", tol=1e-10, precision="fp64")
+    return p
+
+
 def config_problem(name: str, **kw) -> Problem:
-    """Problem of workload C1, C2 or C3 (C4 and C5 are families: see c4_problems, c5_trace)."""
-    return {"C1": _c1, "C2": _c2, "C3": _c3}[name](**kw)
+    """Problem of workload C1, C2, C3 or the 3-D extension (C4 and C5 are families: see
+    c4_problems, c5_trace)."""
+    return {"C1": _c1, "C2": _c2, "C3": _c3, "3D": _3d}[name](**kw)
 
 
 def _family_member(rng: np.random.Generator, n: int, three: bool, sigma_log: Optional[float],

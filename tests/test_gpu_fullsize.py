@@ -145,3 +145,33 @@ def test_c3_full_size_residual():
                       f"(outer passes {rep['outer'][a]})", flush=True)
                 assert rel < 1.2e-10, (n, a, rel)
             prev = new
+
+
+def test_3d_full_size_residual():
+    """The 3-D workload (256 x 256 x 256 cubes, two continua, 40 fracture planes; 16.9 million
+    unknowns) in the benchmark's configuration: D-scheme, FP64 block IC(0) PCG to 1e-10.  As
+    for C3, the oracle's own continuum matrices (no factorization) are applied to the GPU's
+    first two layers; each residual against the D-scheme right-hand side of the previous
+    layer must meet the PCG tolerance (2e-10 allows for the drift between PCG's recursive
+    residual and the true one, and for the rounding of the CPU product)."""
+    print("\n[3-D full size]", flush=True)
+    p = media.config_problem("3D")
+    asm = fv.assemble(p)
+    prev = p.initial_state()
+    with mcdec.Problem(p, scheme="D", precond="bic0", tol=1e-10) as g:
+        for n in (1, 2):
+            rep = g.step(1)
+            new = g.get_states()
+            for a in range(asm.L):
+                K = schemes.continuum_matrix(asm, p.tau, a)
+                b = schemes.decoupled_rhs(asm, p.tau, a, prev, "D")
+                nb = np.linalg.norm(b)
+                if nb == 0.0:
+                    print(f"layer {n} continuum {a}: zero right-hand side", flush=True)
+                    assert not np.any(new[a]), (n, a)
+                    continue
+                rel = np.linalg.norm(b - K @ new[a]) / nb
+                print(f"layer {n} continuum {a}: relative residual {rel:.2e} "
+                      f"(iterations {rep['iters'][a]})", flush=True)
+                assert rel < 2e-10, (n, a, rel)
+            prev = new
