@@ -61,11 +61,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "c1c131e3a6606e90", "fetch_kib": 83367.3,
-                        "write_kib": 65602.4, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "c1c131e3a6606e90", "fetch_kib": 90360.1,
-                        "write_kib": 98320.4, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "c1c131e3a6606e90", "fetch_kib": 82556.2,
+    ("C2", "mg", "A"): {"sources": "37d6041871f319e5", "fetch_kib": 83687.8,
+                        "write_kib": 65603.3, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "37d6041871f319e5", "fetch_kib": 90352.9,
+                        "write_kib": 98320.6, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "37d6041871f319e5", "fetch_kib": 82674.6,
                         "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
