@@ -79,7 +79,8 @@ typedef enum {
                     inverse of their Schur complement (formed once at setup, up to 6144
                     crossing cells; beyond that the crossing couplings are dropped)            */
   MC_MG = 2      /* grid: one symmetric multigrid V-cycle -- 2 x 2 cell aggregates, coarse
-                    operators P^T A P (again 5-point conductance stencils), block IC(0) as the
+                    operators P^T A P with their face conductances halved (again 5-point
+                    conductance stencils; row sums kept), block IC(0) as the
                     pre- and post-smoother on every level, the coarsest level (at most 256
                     cells) solved by its dense inverse; fracture graph: as MC_BIC0.  Grids of
                     at most 256 cells use plain block IC(0).  2-D grids only (nz <= 1)    */

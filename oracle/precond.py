@@ -124,9 +124,23 @@ def aggregate_prolongator(nx: int, ny: int):
     return P, cnx, cny
 
 
+def coarse_operator(K: sp.spmatrix, P: sp.spmatrix) -> sp.csr_matrix:
+    """The coarse operator of one aggregation level: the Galerkin product P^T K P with its
+    off-diagonal (face) conductances halved and the diagonal lowered by the same amount, so
+    that row sums are kept.  With piecewise-constant 2 x 2 aggregates the Galerkin product
+    carries twice the conductance a coarse cell of side 2h has (two fine faces of
+    conductance T in parallel, against T for the rediscretized face), while its storage and
+    transfer terms (the row sums) are exact; halving the faces restores the balance."""
+    Kc = sp.csr_matrix(P.T @ K @ P)
+    d = Kc.diagonal()
+    off = Kc - sp.diags(d)
+    rs = np.asarray(off.sum(axis=1)).ravel()          # minus the cell's face conductances
+    return sp.csr_matrix(0.5 * off + sp.diags(d + 0.5 * rs))
+
+
 def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256, coarse_rows: int = 4):
-    """Levels of the V-cycle of the grid operator K (nx x ny cells, row-major): Galerkin
-    coarse operators P^T K P until at most `coarse` cells remain; block IC(0) factors on
+    """Levels of the V-cycle of the grid operator K (nx x ny cells, row-major): coarse
+    operators from `coarse_operator` until at most `coarse` cells remain; block IC(0) factors on
     64 x 16 blocks on the finest level and 64 x `coarse_rows` blocks on the coarse levels
     above the coarsest; the coarsest level's dense inverse.  A grid of at most `coarse`
     cells has one level and the cycle is plain block IC(0)."""
@@ -135,7 +149,7 @@ def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256, coarse_row
     while nx * ny > coarse:
         P, nx, ny = aggregate_prolongator(nx, ny)
         levels[-1]["P"] = P
-        K = sp.csr_matrix(P.T @ K @ P)
+        K = coarse_operator(K, P)
         lev = dict(K=K, nx=nx, ny=ny)
         if nx * ny > coarse:
             lev["facs"] = block_precond(K, grid_tile_blocks(nx, ny, ty=coarse_rows))

@@ -1387,9 +1387,11 @@ struct CoarsenSetup {
   double* cty;
 };
 
-// Coarse operator P^T A P for 2 x 2 aggregates: the diagonal sums the aggregate's diagonal
-// entries and subtracts twice its internal face conductances; a coarse face conductance
-// sums the fine faces it covers.
+// Coarse operator for 2 x 2 aggregates: the Galerkin product P^T A P (the diagonal sums the
+// aggregate's diagonal entries and subtracts twice its internal face conductances; a coarse
+// face sums the fine faces it covers) with its face conductances halved and the diagonal
+// lowered by the same amount, which keeps the row sums (storage and transfer) exact.  The
+// Galerkin faces of piecewise-constant aggregates are twice those of a cell of side 2h.
 __global__ void k_mg_coarsen(CoarsenSetup g) {
   const long I = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= (long)g.cnx * g.cny) return;
@@ -1409,9 +1411,16 @@ __global__ void k_mg_coarsen(CoarsenSetup g) {
       if (b == 1 || y + 1 == g.ny) n += g.ty[i];        // north faces
     }
   }
-  g.cdiag[I] = d;
-  g.ctx[I] = X + 1 < g.cnx ? e : 0.0;
-  g.cty[I] = Y + 1 < g.cny ? n : 0.0;
+  double w = 0.0, s = 0.0;   // west and south faces (the neighbours' east / north faces)
+  for (int b = 0; b < 2 && X > 0; ++b)
+    if (2 * Y + b < g.ny) w += g.tx[(long)(2 * Y + b) * g.nx + 2 * X - 1];
+  for (int a = 0; a < 2 && Y > 0; ++a)
+    if (2 * X + a < g.nx) s += g.ty[(long)(2 * Y - 1) * g.nx + 2 * X + a];
+  e = X + 1 < g.cnx ? e : 0.0;
+  n = Y + 1 < g.cny ? n : 0.0;
+  g.cdiag[I] = d - 0.5 * ((e + w) + (n + s));
+  g.ctx[I] = 0.5 * e;
+  g.cty[I] = 0.5 * n;
 }
 
 // Dense symmetric matrix of a 5-point operator (n = nx * ny, leading dimension ld >= n; a
