@@ -61,11 +61,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "37d6041871f319e5", "fetch_kib": 83687.8,
-                        "write_kib": 65603.3, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "37d6041871f319e5", "fetch_kib": 90352.9,
+    ("C2", "mg", "A"): {"sources": "3222ce9f5e62dbba", "fetch_kib": 83813.9,
+                        "write_kib": 65603.0, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "3222ce9f5e62dbba", "fetch_kib": 90359.7,
                         "write_kib": 98320.6, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "37d6041871f319e5", "fetch_kib": 82674.6,
+    ("C2", "mg", "P"): {"sources": "3222ce9f5e62dbba", "fetch_kib": 82547.4,
                         "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
