@@ -48,8 +48,10 @@ HBM_PEAK_GBS = 8000.0
 DEFAULTS = {
     "C1": dict(precond="jacobi", precision="fp64", tol=1e-12, steps=20, coupled_steps=20),
     "C2": dict(precond="mg", precision="fp64", tol=1e-10, steps=100, coupled_steps=5),
-    "C3": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=1),
-    "C4": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=2),
+    "C3": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=1,
+               sample_every=4),
+    "C4": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=2,
+               sample_every=4),
     "C5": dict(precond="mg", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
     "3D": dict(precond="bic0", precision="fp64", tol=1e-10, steps=20, coupled_steps=2,
                sample_every=2),
@@ -615,9 +617,10 @@ def main():
     ap.add_argument("--max-resident", type=int, default=0, help="C5: resident requests (0=256)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--sample-every", type=int, default=None,
-                    help="time one grid PCG iteration in this many (HIP events; default 32, "
-                         "2 for the 3-D workload, whose layers take only a few grid "
-                         "iterations)")
+                    help="time one grid PCG iteration in this many (HIP events; default 32; "
+                         "4 for C3 and C4, whose launches serve systems of different "
+                         "iteration counts, and 2 for the 3-D workload, whose layers take "
+                         "only a few grid iterations)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-coupled", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
