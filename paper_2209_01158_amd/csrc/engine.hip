@@ -86,8 +86,11 @@ static int blocks_for(int ntiles, int kind, int fam, bool bic0, bool fp32) {
     auto it = g_tune.find(tune_key(ntiles, kind, fam, bic0, fp32));
     if (it != g_tune.end()) return std::max(1, (ntiles + it->second - 1) / it->second);
   }
+  // untuned defaults: a fracture graph gets one workgroup per tile (its chain solves are
+  // latency-bound), the grid operator up to 2048 workgroups, the update with block IC(0)
+  // four tiles per workgroup
   int cap;
-  if (kind == PART_GRAPH) cap = env_int("MCDEC_GRAPH_BLOCKS", 256);
+  if (kind == PART_GRAPH) cap = env_int("MCDEC_GRAPH_BLOCKS", std::max(256, ntiles));
   else if (fam == 0) cap = env_int("MCDEC_GRID_BLOCKS_A", 2048);
   else cap = bic0 ? std::max(1, env_int("MCDEC_GRID_BLOCKS_B", (ntiles + 3) / 4))
                   : env_int("MCDEC_GRID_BLOCKS_A", 2048);
