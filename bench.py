@@ -302,7 +302,6 @@ def run_single(args, out):
         g.set_states(p0)
         g.profile(True, every=args.sample_every)
         lat, iters = [], []
-        tot = {k: 0.0 for k in kernels_of(args.precond)}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -310,13 +309,17 @@ def run_single(args, out):
             rep = g.step(1)
             lat.append(time.perf_counter() - ts)
             iters.append(rep["iters"])
-            sb = step_bytes(p, rep, args.precision, args.precond)
-            for kk in tot:
-                tot[kk] += sb[kk]
             if (k + 1) % 20 == 0:
                 log(f"step {k + 1}/{args.steps}: iters {rep['iters']} outer {rep['outer']}")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        # algorithmic bytes of the timed layers, from their iteration counts (kept out of the
+        # timed loop)
+        tot = {k: 0.0 for k in kernels_of(args.precond)}
+        for it in iters:
+            sb = step_bytes(p, {"iters": it}, args.precision, args.precond)
+            for kk in tot:
+                tot[kk] += sb[kk]
         prof = read_profile(g, kernels_of(args.precond))
         g.profile(False)
         elapsed = t1 - t0
@@ -410,24 +413,28 @@ def run_batch(args, out):
             g.set_states(p.initial_state())
         b.profile(True, every=args.sample_every)
         lat = []
-        tot = {k: 0.0 for k in kernels_of(args.precond)}
-        iters_max = []
+        all_reps = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
             ts = time.perf_counter()
             reps = b.step(gs, 1)
             lat.append(time.perf_counter() - ts)
+            all_reps.append(reps)
+            if (k + 1) % 10 == 0:
+                log(f"step {k + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms, "
+                    f"max iters {max(max(r['iters']) for r in reps)}")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # algorithmic bytes and iteration maxima of the timed layers (kept out of the loop)
+        tot = {k: 0.0 for k in kernels_of(args.precond)}
+        iters_max = []
+        for reps in all_reps:
             for p, r in zip(probs, reps):
                 sb = step_bytes(p, r, args.precision, args.precond)
                 for kk in tot:
                     tot[kk] += sb[kk]
             iters_max.append(max(max(r["iters"]) for r in reps))
-            if (k + 1) % 10 == 0:
-                log(f"step {k + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms, "
-                    f"max iters {iters_max[-1]}")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
         prof = read_profile(b, kernels_of(args.precond))
         b.profile(False)
         elapsed = t1 - t0
