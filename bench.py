@@ -4,10 +4,11 @@
 Workloads (``--workload``):
   C2 (default)  two-continuum fractured medium on a 2048 x 2048 grid (lognormal matrix
                 permeability, 400 any-angle fracture segments, ~63k fracture cells),
-                tau = 1e-3, 100 backward-Euler layers, D-scheme, FP64, block IC(0) PCG to 1e-10.
+                tau = 1e-3, 100 backward-Euler layers, D-scheme, FP64 PCG to 1e-10 with the
+                multigrid V-cycle on the grid and the exact fracture solve.
   C1            64 x 64 two-continuum medium, 20 layers, Jacobi PCG to 1e-12 (latency-bound).
   C3            three continua on a 4096 x 4096 grid (~150k fracture cells), 50 layers,
-                FP32 inner PCG inside FP64 refinement to 1e-10.
+                FP32 inner PCG (V-cycle) inside FP64 refinement to 1e-10.
   C4            256 independent realizations of uneven size (128..1024 cells a side, two or
                 three continua), 50 layers, all advanced by shared launches in FP32 inner PCG
                 inside FP64 refinement.
