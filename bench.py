@@ -64,11 +64,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "3222ce9f5e62dbba", "fetch_kib": 83813.9,
-                        "write_kib": 65603.0, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "3222ce9f5e62dbba", "fetch_kib": 90359.7,
-                        "write_kib": 98320.6, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "3222ce9f5e62dbba", "fetch_kib": 82547.4,
+    ("C2", "mg", "A"): {"sources": "15ab832945e42fd7", "fetch_kib": 83985.4,
+                        "write_kib": 65603.6, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "15ab832945e42fd7", "fetch_kib": 90358.0,
+                        "write_kib": 98320.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "15ab832945e42fd7", "fetch_kib": 82706.4,
                         "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 

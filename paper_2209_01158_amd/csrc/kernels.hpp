@@ -786,6 +786,63 @@ struct Residual64 {
     if (P.coupled) ax += graph_coupling(P, l, xp);
     return P.b[l] - ax;
   }
+  // The residuals of a whole IC(0) block at this lane's column (uncoupled 2-D grid parts;
+  // false otherwise): x, the coefficients and b are loaded once per half block -- the rows
+  // above and below from the same column, the west and east neighbours from the adjacent
+  // lanes -- and the operator is applied in grid_Av's order, so the values are the same.
+  template <int R>
+  __device__ bool block_res(const IcBlkR<R>& B, double (&out)[R]) const {
+    if (P.coupled || P.plane) return false;
+    constexpr int H = R / 2;
+    static_assert(R % 2 == 0, "whole half blocks");
+    const int nx = P.nx, ny = P.ny, lane = (int)(threadIdx.x & 63);
+    const int x0 = B.cx - lane;
+    const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
+    auto row = [&](int j) { return (long)min(max(B.y0 + j, 0), ny - 1) * nx; };
+    const bool has_t = P.has_t;
+    const double tc = P.tconst;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j0 = h * H;
+      double xv[H + 2], xh[H], dv[H], te[H], th[H], tn[H + 1], bv[H];
+#pragma unroll
+      for (int j = 0; j < H + 2; ++j) xv[j] = x[row(j0 + j - 1) + B.cxs];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const long o = row(j0 + j);
+        xh[j] = x[o + hx];
+        dv[j] = P.diag[o + B.cxs];
+        bv[j] = P.b[o + B.cxs];
+        te[j] = has_t ? P.tx[o + B.cxs] : 0.0;
+        th[j] = has_t ? P.tx[o + hx] : 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < H + 1; ++j) tn[j] = has_t ? P.ty[row(j0 + j - 1) + B.cxs] : 0.0;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int y = B.y0 + j0 + j;
+        const double vw = dpp_d<0x138, 0xF>(xh[j], xv[j + 1]);   // lane 0 keeps its halo
+        const double ve = dpp_d<0x130, 0xF>(xh[j], xv[j + 1]);   // lane 63 keeps its halo
+        const double tw = dpp_d<0x138, 0xF>(th[j], te[j]);
+        double acc = dv[j] * xv[j + 1];
+        if (has_t) {
+          if (B.cx > 0) acc -= tw * vw;
+          if (B.cx + 1 < nx) acc -= te[j] * ve;
+          if (y > 0) acc -= tn[j] * xv[j];
+          if (y + 1 < ny) acc -= tn[j + 1] * xv[j + 2];
+        } else {
+          double s = 0.0;
+          if (B.cx > 0) s += vw;
+          if (B.cx + 1 < nx) s += ve;
+          if (y > 0) s += xv[j];
+          if (y + 1 < ny) s += xv[j + 2];
+          acc -= tc * s;
+        }
+        out[j0 + j] = B.act(j0 + j) ? bv[j] - acc : 0.0;
+      }
+    }
+    return true;
+  }
 };
 
 // Shared by the FP64 initial residual and the refinement residual: takes the FP64 residual
@@ -803,9 +860,11 @@ __device__ __forceinline__ void residual_and_precond(const PartD& P, const Tile&
     for_wave_tiles(t, [&](int unit) {
       const IcBlk B(P, unit);
       double r64[MC_ICY];
+      if (!Rs.block_res(B, r64)) {
 #pragma unroll
-      for (int y = 0; y < MC_ICY; ++y)   // loads only: all rows in flight together
-        r64[y] = B.act(y) ? res(B.cxs, min(B.y0 + y, B.ny - 1), B.cell(y)) : 0.0;
+        for (int y = 0; y < MC_ICY; ++y)   // loads only: all rows in flight together
+          r64[y] = B.act(y) ? res(B.cxs, min(B.y0 + y, B.ny - 1), B.cell(y)) : 0.0;
+      }
       T rs_[MC_ICY];
 #pragma unroll
       for (int y = 0; y < MC_ICY; ++y)
@@ -1210,6 +1269,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     double sc;
     __device__ double res(int, int, long i) const { return sc * r64[i]; }
     __device__ double resg(int l) const { return sc * r64[l]; }
+    __device__ bool block_res(const IcBlk&, double (&)[MC_ICY]) const { return false; }
   } R{r64, sc};
   auto emit = [&](long i, double ri, double) {
     const float rf = (float)ri;
