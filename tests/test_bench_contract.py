@@ -1,0 +1,51 @@
+"""Host-side checks of the benchmark's contract and of its byte accounting (no GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["n_gpus"] == 2 and "one GPU" in out["error"]
+
+
+@pytest.mark.parametrize("precision,w", [("fp64", 8), ("mixed", 4)])
+def test_algorithmic_bytes_per_cell(precision, w):
+    """The per-cell bytes stated for each grid kernel: operator A reads z, p_old, diag
+    (+ tx, ty with cellwise conductances, + tz in 3-D) and writes p_new, q; update B reads
+    x, p, r, q, writes x, r and z (block IC(0) and the V-cycle add the FP32 pivots and
+    conductances); P (V-cycle finest level) reads z_p, r, a quarter word of the coarse
+    correction and FP32 coefficients, writes z."""
+    g = bench.grid_bytes_per_cell
+    assert g("A", precision, "mg", True) == 7 * w
+    assert g("A", precision, "mg", False) == 5 * w
+    assert g("A", precision, "bic0", True, dim=3) == 8 * w
+    assert g("B", precision, "mg", True) == 7 * w + 12
+    assert g("B", precision, "jacobi", True) == 7 * w
+    assert g("P", precision, "mg", True) == 3 * w + w / 4 + 16
+    assert g("P", precision, "mg", False) == 3 * w + w / 4 + 8
+
+
+def test_roofline_from_samples():
+    """A dominant kernel is the one with the most estimated time; working launches are the
+    issued ones scaled by the working share of the samples; achieved = bytes / time."""
+    kind_time = {"A": (10, 5.0, 100, 8, 4.8), "B": (10, 2.0, 100, 10, 2.0)}
+    tot = {"A": 80 * 1e9, "B": 100 * 1e9}
+    dom, other = bench.roofline(kind_time, tot, "fp64", "mg", "C2")
+    assert dom["kernel"].startswith("k_pcg_A") and len(other) == 1
+    # A: 80 working launches of 0.6 ms carrying 1e9 bytes each
+    assert np.isclose(dom["avg_launch_us"], 600.0)
+    assert np.isclose(dom["algorithmic_bytes_per_launch"], 1e9)
+    assert np.isclose(dom["achieved"], 1e9 / 0.6e-3 / 1e9)
+    assert np.isclose(dom["frac"], dom["achieved"] / 8000.0)
