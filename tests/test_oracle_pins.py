@@ -3,8 +3,8 @@
 Each test is chosen so that a plausible slip in the oracle (a dropped term, a wrong sign,
 a wrong index, a transposed block) fails at least one of them:
 
-* hand-computed fixture (tests/golden/hand_2x1.json)       -> every assembled entry, F,
-                                                              coupled and D steps exactly
+* hand-computed fixtures (tests/golden/hand_2x1.json and   -> every assembled entry, F,
+  hand_frac.json: aperture, fracture edge, sigma_12 h^2)      coupled and D steps exactly
 * textbook eigenvalues of the 5-point operator            -> stencil assembly with BCs
 * layered-medium series-resistance solution              -> harmonic mean, Dirichlet faces
 * two-cell closed forms (coupled, D, EX)                  -> transfer and the recurrences
@@ -68,6 +68,64 @@ def test_hand_computed_fixture():
     h = schemes.run(p, "D", 2)
     np.testing.assert_allclose(np.concatenate(h[1]), frac(g["D_step1"]), rtol=0, atol=1e-15)
     assert abs(h[2][1][0] - float(Fraction(*g["D_step2_fracture"]))) < 1e-15
+
+
+def _exact_solve(A, b):
+    """Gaussian elimination in rationals (the fixture's own derivation, no oracle code)."""
+    n = len(A)
+    m = [list(r) + [bb] for r, bb in zip(A, b)]
+    for i in range(n):
+        piv = next(r for r in range(i, n) if m[r][i] != 0)
+        m[i], m[piv] = m[piv], m[i]
+        for r in range(n):
+            if r != i and m[r][i] != 0:
+                f = m[r][i] / m[i][i]
+                m[r] = [x - f * y for x, y in zip(m[r], m[i])]
+    return [m[i][n] / m[i][i] for i in range(n)]
+
+
+def test_hand_computed_fracture_fixture():
+    """Three continua, a fracture edge and aperture 1/4 (tests/golden/hand_frac.json): the
+    fracture storage c_f a l, the fracture conductance k_f a / d and the per-cell
+    sigma_12 h^2 each enter the hand matrix with a value that a dropped factor changes."""
+    g = json.load(open(os.path.join(GOLD, "hand_frac.json")))
+    q = g["problem"]
+    R = lambda v: Fraction(v)
+    p = Problem(nx=q["nx"], ny=q["ny"], h=q["h"],
+                omega=[OmegaContinuum(c=o["c"], k_const=o["k"]) for o in q["omega"]],
+                sigma_omega=q["sigma_omega"], host=np.array(q["host"], np.int32),
+                flen=np.array(q["flen"]), edges=np.array(q["edges"], np.int32),
+                edge_d=np.array(q["edge_d"]), k_f=q["k_f"], c_f=q["c_f"],
+                aperture=q["aperture"], sigma_f=np.array(q["sigma_f"]),
+                bc_type=np.array(q["bc_type"], np.int32), bc_value=np.array(q["bc_value"]),
+                tau=q["tau"])
+    p.check()
+    K_hand = [[R(v) for v in row] for row in g["coupled_matrix"]]
+    F_hand = [R(v) for v in g["F"]]
+    # the stored solutions are the exact solutions of the hand matrix
+    assert _exact_solve(K_hand, F_hand) == [R(v) for v in g["coupled_step1"]]
+    Dm = [[[R(v) for v in row] for row in blk] for blk in g["D_matrices"]]
+    d1 = [R(v) for v in g["D_step1"]]
+    assert _exact_solve(Dm[0], F_hand[0:2]) == d1[0:2]
+    assert _exact_solve(Dm[1], F_hand[2:4]) == d1[2:4]
+    # second D layer of the fracture: m_f/tau p_f^1 + Q_f0 p_0^1 + Q_f1 p_1^1 (p_f^1 = 0)
+    sf = q["sigma_f"]
+    rf = [R(sf[0][0]) * d1[0] + R(sf[1][0]) * d1[2], R(sf[0][1]) * d1[1] + R(sf[1][1]) * d1[3]]
+    assert _exact_solve(Dm[2], rf) == [R(v) for v in g["D_step2_fracture"]]
+    # the oracle against the hand values
+    asm = fv.assemble(p)
+    fl = lambda M: np.array([[float(v) for v in row] for row in M])
+    np.testing.assert_array_equal(schemes.coupled_matrix(asm, p.tau).toarray(), fl(K_hand))
+    np.testing.assert_array_equal(asm.Ffull(), np.array([float(v) for v in F_hand]))
+    for a in range(3):
+        np.testing.assert_array_equal(schemes.continuum_matrix(asm, p.tau, a, "D").toarray(),
+                                      fl(Dm[a]))
+    x = np.concatenate(schemes.run(p, "coupled", 1)[-1])
+    np.testing.assert_allclose(x, [float(R(v)) for v in g["coupled_step1"]], rtol=0, atol=1e-15)
+    h = schemes.run(p, "D", 2)
+    np.testing.assert_allclose(np.concatenate(h[1]), [float(v) for v in d1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(h[2][2], [float(R(v)) for v in g["D_step2_fracture"]], rtol=0,
+                               atol=1e-15)
 
 
 @pytest.mark.parametrize("bc", [(1, 1, 0, 0), (0, 0, 1, 1), (0, 0, 0, 0), (1, 1, 1, 1)])
