@@ -1,0 +1,285 @@
+"""Non-local multicontinuum (NLMC) coarse-grid schemes (oracle; test infrastructure only).
+
+Follows Section 4 of the paper:
+
+* coarse units K_j^a = Omega_a intersected with coarse cell K_j: for a grid continuum all fine
+  cells of K_j, for the fracture continuum the fracture cells hosted in K_j (a coarse cell
+  without fracture cells has no fracture unit);
+* the oversampled region K_i^+ = K_i enlarged by `layers` coarse cells (clipped to Omega);
+* a basis function psi^{i,b} per unit (i, b): the minimizer of the energy (A psi, psi) of the
+  fine coupled operator A = D + Q over vectors that vanish outside K_i^+ (zero Dirichlet
+  values on the part of its boundary inside Omega; the problem's own conditions stay on the
+  part on the boundary of Omega), subject to the mean of psi over every unit (j, a) with
+  K_j in K_i^+ being delta_ij delta_ab -- the saddle-point system of eq. eq:basis, solved
+  here as it stands (sparse LU of [[A_loc, C^T], [C, 0]]);
+* R = the matrix whose rows are the basis functions; the coarse operator A_bar = R A R^T,
+  the coarse storage M_bar (block diagonal, M_bar_a = R_aa M_a R_aa^T) and the coarse
+  right-hand side F_bar_a = R_aa F_a (eq. app-nlmc);
+* the coupled coarse scheme (eq. is-nlmc) and the D-, L- and U-schemes (eq. si-nlmc), whose
+  A_bar_0 is the block diagonal, block lower or block upper triangle of A_bar (its diagonal
+  block A_bar_aa = D_bar_aa + sum_b Q_bar_ab) and A_bar_1 = A_bar - A_bar_0.
+
+Readings where the paper is silent (each is also listed in the design notes):
+* A is the whole fine operator of the problem, the implicit wells of Section 5 included
+  (they sit on the fracture diagonal of D_f), so A_bar, M_bar and F_bar are Galerkin
+  products of exactly the fine quantities the fine-grid schemes use;
+* the mean of a unit weighs each fine cell by its measure (h^2; a l for a fracture cell);
+* the coarse unknowns are ordered continuum by continuum, the units of one continuum by
+  coarse cell (row-major), fracture units only where a coarse cell hosts fracture cells;
+* the coarse initial state is the unit means of the fine one, and the accuracy measure e_H
+  compares the coarse solution with the unit means of the fine coupled solution (Section 5).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fv import Assembled, assemble
+from .schemes import DirectSolver
+
+SCHEMES = ("coupled", "D", "L", "U")
+
+
+@dataclass
+class CoarseGrid:
+    """Coarse cells of bx x by fine cells over an nx x ny grid (nx % bx == ny % by == 0)."""
+    nx: int
+    ny: int
+    bx: int
+    by: int
+
+    @property
+    def ncx(self) -> int:
+        return self.nx // self.bx
+
+    @property
+    def ncy(self) -> int:
+        return self.ny // self.by
+
+    @property
+    def ncoarse(self) -> int:
+        return self.ncx * self.ncy
+
+    def coarse_of_cell(self) -> np.ndarray:
+        """Coarse cell index of every fine cell (row-major both)."""
+        y, x = np.divmod(np.arange(self.nx * self.ny), self.nx)
+        return (y // self.by) * self.ncx + (x // self.bx)
+
+    def oversampled(self, i: int, layers: int) -> np.ndarray:
+        """Coarse cells of K_i^+ (sorted)."""
+        cy, cx = divmod(i, self.ncx)
+        ys = np.arange(max(0, cy - layers), min(self.ncy, cy + layers + 1))
+        xs = np.arange(max(0, cx - layers), min(self.ncx, cx + layers + 1))
+        return (ys[:, None] * self.ncx + xs[None, :]).ravel()
+
+
+@dataclass
+class Units:
+    """The coarse units K_j^a: global fine indices (into the concatenated fine vector) and
+    measures of their cells, and the coarse unknown of each unit."""
+    cont: np.ndarray          # [N_H] continuum of each coarse unknown
+    coarse: np.ndarray        # [N_H] coarse cell of each coarse unknown
+    cells: List[np.ndarray]   # [N_H] global fine indices
+    meas: List[np.ndarray]    # [N_H] measures of those cells
+    index: Dict[Tuple[int, int], int]   # (continuum, coarse cell) -> coarse unknown
+    sizes: List[int]          # coarse unknowns per continuum
+
+    @property
+    def n(self) -> int:
+        return len(self.cont)
+
+
+def coarse_units(prob, cg: CoarseGrid) -> Units:
+    if getattr(prob, "nz", 1) > 1:
+        raise ValueError("NLMC is defined here for 2-D grids")
+    if prob.nx != cg.nx or prob.ny != cg.ny or prob.nx % cg.bx or prob.ny % cg.by:
+        raise ValueError("coarse cells must tile the grid")
+    nc = prob.nx * prob.ny
+    cof = cg.coarse_of_cell()
+    vol = prob.h ** 2
+    cont, coarse, cells, meas = [], [], [], []
+    index: Dict[Tuple[int, int], int] = {}
+    sizes = []
+    offset = 0
+    for a in range(prob.n_omega):
+        order = np.argsort(cof, kind="stable")
+        bounds = np.searchsorted(cof[order], np.arange(cg.ncoarse + 1))
+        for j in range(cg.ncoarse):
+            c = order[bounds[j]:bounds[j + 1]]
+            index[(a, j)] = len(cont)
+            cont.append(a)
+            coarse.append(j)
+            cells.append(offset + c)
+            meas.append(np.full(len(c), vol))
+        sizes.append(cg.ncoarse)
+        offset += nc
+    if prob.nf > 0:
+        a = prob.n_omega
+        fco = cof[np.asarray(prob.host, np.int64)]
+        fmeas = prob.aperture * np.asarray(prob.flen, np.float64)
+        k = 0
+        for j in range(cg.ncoarse):
+            c = np.nonzero(fco == j)[0]
+            if len(c) == 0:
+                continue
+            index[(a, j)] = len(cont)
+            cont.append(a)
+            coarse.append(j)
+            cells.append(offset + c)
+            meas.append(fmeas[c])
+            k += 1
+        sizes.append(k)
+    return Units(np.array(cont), np.array(coarse), cells, meas, index, sizes)
+
+
+def _local_cells(prob, cg: CoarseGrid, kplus: np.ndarray, units: Units) -> np.ndarray:
+    """Global fine indices of the unknowns of K_i^+: every cell of every unit whose coarse
+    cell lies in K_i^+ (these units tile the region)."""
+    inside = np.zeros(cg.ncoarse, bool)
+    inside[kplus] = True
+    sel = [u for u in range(units.n) if inside[units.coarse[u]]]
+    return np.sort(np.concatenate([units.cells[u] for u in sel])), sel
+
+
+class Basis:
+    """Multiscale basis functions of every coarse unit (eq. eq:basis), as the rows of R."""
+
+    def __init__(self, prob, cg: CoarseGrid, layers: int, asm: Optional[Assembled] = None):
+        self.prob, self.cg, self.layers = prob, cg, layers
+        self.asm = asm if asm is not None else assemble(prob)
+        self.A = self.asm.Afull().tocsr()
+        self.units = coarse_units(prob, cg)
+        self.N = self.A.shape[0]
+        U = self.units
+        rows, cols, vals = [], [], []
+        self.constraint_error = 0.0
+        cache: Dict[Tuple[int, ...], Tuple] = {}
+        for i in range(cg.ncoarse):
+            kplus = cg.oversampled(i, layers)
+            key = tuple(kplus)
+            if key not in cache:
+                loc, sel = _local_cells(prob, cg, kplus, U)
+                pos = {g: k for k, g in enumerate(loc)}
+                n = len(loc)
+                A_loc = self.A[loc][:, loc]
+                # constraint rows: mean over each unit of K_i^+ (measure-weighted)
+                cr, cc, cv = [], [], []
+                for r, u in enumerate(sel):
+                    w = U.meas[u] / U.meas[u].sum()
+                    cr += [r] * len(w)
+                    cc += [pos[g] for g in U.cells[u]]
+                    cv += list(w)
+                C = sp.csr_matrix((cv, (cr, cc)), shape=(len(sel), n))
+                K = sp.bmat([[A_loc, C.T], [C, None]], format="csc")
+                lu = spla.splu(K)
+                cache = {key: (loc, sel, C, K, lu)}   # neighbouring i share nothing else
+            loc, sel, C, K, lu = cache[key]
+            n = len(loc)
+            for r, u in enumerate(sel):
+                if U.coarse[u] != i:
+                    continue
+                rhs = np.zeros(K.shape[0])
+                rhs[n + r] = 1.0
+                sol = lu.solve(rhs)
+                for _ in range(3):            # FP64 iterative refinement of the LU solve
+                    sol = sol + lu.solve(rhs - K @ sol)
+                res = np.linalg.norm(K @ sol - rhs)
+                if res > 1e-12 * (1.0 + abs(K).max() * np.linalg.norm(sol)):
+                    raise RuntimeError(f"basis saddle-point residual {res:.2e} (unit {u})")
+                psi = sol[:n]
+                e = C @ psi
+                e[r] -= 1.0
+                self.constraint_error = max(self.constraint_error, float(np.abs(e).max()))
+                nz = np.nonzero(psi)[0]
+                rows.append(np.full(len(nz), u))
+                cols.append(loc[nz])
+                vals.append(psi[nz])
+        self.R = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows),
+                                                       np.concatenate(cols))),
+                               shape=(U.n, self.N))
+
+
+@dataclass
+class CoarseSystem:
+    """A_bar = R A R^T, M_bar (block diagonal), F_bar (eq. app-nlmc)."""
+    units: Units
+    A: np.ndarray        # dense N_H x N_H
+    M: np.ndarray        # dense N_H x N_H, block diagonal by continuum
+    F: np.ndarray        # N_H
+    blocks: List[slice]  # coarse unknowns of each continuum
+
+
+def coarse_system(basis: Basis) -> CoarseSystem:
+    """A_bar = R A R^T; M_bar_a = R_aa M_a R_aa^T and F_bar_a = R_aa F_a, where R_aa is the
+    continuum-a component of the basis functions of continuum-a units."""
+    U, asm, R = basis.units, basis.asm, basis.R
+    Abar = (R @ basis.A @ R.T).toarray()
+    Abar = 0.5 * (Abar + Abar.T)     # symmetric by construction; remove rounding asymmetry
+    offs = np.concatenate([[0], np.cumsum(asm.sizes)])
+    coffs = np.concatenate([[0], np.cumsum(U.sizes)])
+    blocks = [slice(int(coffs[a]), int(coffs[a + 1])) for a in range(asm.L)]
+    Mbar = np.zeros_like(Abar)
+    Fbar = np.zeros(U.n)
+    for a in range(asm.L):
+        Raa = R[blocks[a], :][:, int(offs[a]):int(offs[a + 1])]
+        Mbar[blocks[a], blocks[a]] = (Raa @ sp.diags(asm.M[a]) @ Raa.T).toarray()
+        Fbar[blocks[a]] = Raa @ asm.F[a]
+    return CoarseSystem(U, Abar, Mbar, Fbar, blocks)
+
+
+def unit_means(units: Units, p_fine: Sequence[np.ndarray]) -> np.ndarray:
+    """Mean of the fine state over every coarse unit (measure-weighted)."""
+    x = np.concatenate([np.ravel(v) for v in p_fine])
+    return np.array([float(x[c] @ m / m.sum()) for c, m in zip(units.cells, units.meas)])
+
+
+def split(cs: CoarseSystem, scheme: str) -> np.ndarray:
+    """A_bar_0 of a scheme (eq. si-nlmc): the whole A_bar (coupled), its block diagonal (D),
+    block lower triangle (L: lower-permeability continua first) or block upper triangle (U)."""
+    A0 = np.zeros_like(cs.A)
+    L = len(cs.blocks)
+    for a in range(L):
+        for b in range(L):
+            keep = (scheme == "coupled" or a == b or (scheme == "L" and b < a)
+                    or (scheme == "U" and b > a))
+            if keep:
+                A0[cs.blocks[a], cs.blocks[b]] = cs.A[cs.blocks[a], cs.blocks[b]]
+    return A0
+
+
+def step(cs: CoarseSystem, tau: float, scheme: str, p_prev: np.ndarray) -> np.ndarray:
+    """One layer of eq. is-nlmc (coupled) or eq. si-nlmc: (M_bar/tau + A_bar_0) p^n =
+    M_bar/tau p^{n-1} - A_bar_1 p^{n-1} + F_bar, solved densely (the coarse systems are
+    small)."""
+    if scheme not in SCHEMES:
+        raise ValueError(scheme)
+    A0 = split(cs, scheme)
+    A1 = cs.A - A0
+    K = cs.M / tau + A0
+    rhs = cs.M @ p_prev / tau - A1 @ p_prev + cs.F
+    x = np.linalg.solve(K, rhs)
+    if np.linalg.norm(K @ x - rhs) > 1e-12 * (np.linalg.norm(rhs) + np.abs(K).sum(1).max()
+                                              * np.linalg.norm(x)):
+        raise RuntimeError("coarse solve not certified")
+    return x
+
+
+def run(cs: CoarseSystem, tau: float, scheme: str, p0: np.ndarray, nsteps: int,
+        keep: str = "all"):
+    p = np.array(p0, np.float64)
+    hist = [p] if keep == "all" else None
+    for _ in range(nsteps):
+        p = step(cs, tau, scheme, p)
+        if hist is not None:
+            hist.append(p)
+    return hist if keep == "all" else p
+
+
+def e_H(p_coarse: np.ndarray, p_ref_means: np.ndarray) -> float:
+    """Relative L2 error of a coarse solution against the unit means of the fine reference
+    (Section 5, without the percent factor)."""
+    return float(np.linalg.norm(p_coarse - p_ref_means) / np.linalg.norm(p_ref_means))
