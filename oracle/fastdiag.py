@@ -78,3 +78,47 @@ def fd_pcg(K, b: np.ndarray, nx: int, ny: int, k: float, shift: float, bc_type,
         p = z + (rz_new / rz) * p
         rz = rz_new
     raise RuntimeError("fd_pcg did not converge")
+
+
+class FDStepper:
+    """D-scheme layers (Section 3.3, eq. si-mc with block-diagonal A0) for problems whose
+    Omega continua have constant permeability on a 2-D grid with matching side types per
+    direction, at sizes where a sparse LU of the grid systems is out of reach.
+
+    Each continuum's system matrix and right-hand side are the ones the sparse-direct
+    stepper uses (``schemes.continuum_matrix``, ``schemes.decoupled_rhs``).  A grid continuum
+    is solved by ``fd_pcg``, preconditioned by the exact solve of its constant part
+    (storage c h^2 / tau, the Omega-Omega transfer sigma_omega h^2 and the diffusion) and
+    started from the previous layer; the fracture continuum by the certified sparse LU.
+    Only the transfer to the fracture host cells is left to the CG iterations."""
+
+    def __init__(self, prob, rtol: float = 1e-14):
+        from . import fv, schemes
+        if getattr(prob, "nz", 1) > 1 or any(o.k is not None for o in prob.omega):
+            raise ValueError("FDStepper needs constant-permeability 2-D grid continua")
+        self.prob, self.rtol = prob, rtol
+        self.asm = fv.assemble(prob)
+        self.tau = float(prob.tau)
+        self.K = [schemes.continuum_matrix(self.asm, self.tau, a, "D")
+                  for a in range(self.asm.L)]
+        vol = prob.h ** 2
+        self.shift = [o.c * vol / self.tau + (prob.sigma_omega * vol if prob.n_omega == 2
+                                              else 0.0) for o in prob.omega]
+        self.frac = (schemes.DirectSolver(self.K[-1]) if prob.nf > 0 else None)
+        self.iterations: list = []
+
+    def step(self, p_prev):
+        from . import schemes
+        prob, asm = self.prob, self.asm
+        new, its = [], []
+        for a in range(asm.L):
+            rhs = schemes.decoupled_rhs(asm, self.tau, a, p_prev, "D")
+            if a < prob.n_omega:
+                x, it, _ = fd_pcg(self.K[a], rhs, prob.nx, prob.ny, prob.omega[a].k_const,
+                                  self.shift[a], prob.bc_type, x0=p_prev[a], rtol=self.rtol)
+                its.append(it)
+            else:
+                x = self.frac.solve(rhs)
+            new.append(x)
+        self.iterations.append(its)
+        return new

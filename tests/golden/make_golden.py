@@ -7,6 +7,8 @@ sample and by relative error on the norm.
 
     python tests/golden/make_golden.py C2        # about 5-10 minutes, ~20 GB RAM
     python tests/golden/make_golden.py C4        # six realizations of the batch, ~1 minute
+    python tests/golden/make_golden.py C3        # D layers by fast-diagonalization CG, ~1 hour
+    python tests/golden/make_golden.py C5        # final states of five served requests, ~1 min
 """
 import os
 import sys
@@ -19,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import media  # noqa: E402
-from oracle import schemes  # noqa: E402
+from oracle import fastdiag, schemes  # noqa: E402
 
 NSAMPLE = 20000
 
@@ -56,6 +58,31 @@ def run(name, d_steps, c_steps):
     print("wrote", out, os.path.getsize(out), "bytes")
 
 
+def run_c3(d_steps=(1, 2, 10, 50)):
+    """The 4096 x 4096 three-continuum workload: D-scheme layers from the fast-diagonalization
+    CG oracle (grid continua, residual 1e-14) and the sparse LU (fracture continuum)."""
+    p = media.config_problem("C3")
+    idx = sample_indices(p)
+    data = {f"idx{a}": idx[a] for a in range(p.n_cont)}
+    t = time.time()
+    st = fastdiag.FDStepper(p)
+    print(f"C3 setup {time.time() - t:.0f}s", flush=True)
+    x = p.initial_state()
+    for n in range(1, max(d_steps) + 1):
+        x = st.step(x)
+        print(f"  layer {n}: CG iterations {st.iterations[-1]} ({time.time() - t:.0f}s)",
+              flush=True)
+        if n in d_steps:
+            for a in range(p.n_cont):
+                data[f"D_s{n}_c{a}"] = x[a][idx[a]]
+                data[f"D_s{n}_norm{a}"] = np.array(np.linalg.norm(x[a]))
+    data["steps_D"] = np.array(d_steps)
+    data["steps_coupled"] = np.array([], np.int64)
+    out = os.path.join(HERE, "c3_oracle.npz")
+    np.savez_compressed(out, **data)
+    print("wrote", out, os.path.getsize(out), "bytes")
+
+
 # the three smallest two-continuum and three-continuum realizations of the batched workload
 C4_SUBSET = [168, 55, 253, 212, 105, 150]
 
@@ -85,13 +112,40 @@ def run_c4(d_steps=(1, 50), c_steps=(1, 2)):
     print("wrote", out, os.path.getsize(out), "bytes")
 
 
+# five small requests of the serving trace (two- and three-continuum, contrasts 1e2..1e6)
+C5_SUBSET = [288, 265, 152, 77, 389]
+
+
+def run_c5():
+    """Final D-scheme states of a subset of the served requests (each request is an
+    independent problem advanced by its own number of layers)."""
+    trace = media.configs.c5_trace()
+    data = {"requests": np.array(C5_SUBSET)}
+    for i in C5_SUBSET:
+        p = media.configs.c5_problem(trace[i])
+        t = time.time()
+        x = schemes.run(p, "D", trace[i][4], keep="last")
+        for a in range(p.n_cont):
+            data[f"r{i}_c{a}"] = x[a]
+        data[f"r{i}_steps"] = np.array(trace[i][4])
+        print(f"C5[{i}] n={p.nx} cont={p.n_cont} layers={trace[i][4]}: "
+              f"{time.time() - t:.1f}s", flush=True)
+    out = os.path.join(HERE, "c5_oracle.npz")
+    np.savez_compressed(out, **data)
+    print("wrote", out, os.path.getsize(out), "bytes")
+
+
 if __name__ == "__main__":
     name = sys.argv[1] if len(sys.argv) > 1 else "C2"
     if name == "C2":
         run("C2", d_steps=[1, 10, 100], c_steps=[1, 5, 100])
     elif name == "C4":
         run_c4()
+    elif name == "C3":
+        run_c3()
+    elif name == "C5":
+        run_c5()
     elif name == "C1":
-        run("C1", d_steps=list(range(1, 21)), c_steps=list(range(1, 21)))
+        run("C1", d_steps=[1, 2, 5, 10, 20], c_steps=[1, 2, 5, 10, 20])
     else:
         raise SystemExit("unknown workload " + name)

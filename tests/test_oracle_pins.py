@@ -521,6 +521,21 @@ def test_fast_diagonalization_matches_lu():
     np.testing.assert_allclose(xf, xs, rtol=1e-11, atol=0)
 
 
+def test_fd_stepper_matches_lu_on_c3_recipe():
+    """The stepper that writes the stored 4096 x 4096 three-continuum layers (fast-
+    diagonalization CG on the grid continua) against the sparse-LU D-scheme stepper on the
+    same recipe at 1024 x 1024 (three continua, about 38k fracture cells): two layers."""
+    p = media.config_problem("C3", n=1024, min_cells=37_500)
+    fd = fastdiag.FDStepper(p)
+    lu = schemes.Stepper(p, None, "D")
+    x = y = p.initial_state()
+    for _ in range(2):
+        x, y = fd.step(x), lu.step(y)
+        for a in range(p.n_cont):
+            assert np.linalg.norm(x[a] - y[a]) <= 1e-12 * np.linalg.norm(y[a]), a
+    assert schemes.rel_l2(x, y) < 1e-13
+
+
 def test_decoupled_close_to_coupled_c1():
     """The paper reports decoupled-vs-coupled errors well below 1% and the U-scheme as the
     most accurate (qualitative; its geometry cannot be reproduced)."""
