@@ -212,6 +212,28 @@ mc_status mc_step(mc_problem *p, int32_t n_steps, mc_report *last);
 mc_status mc_solve_continuum(mc_problem *p, int32_t alpha, const double *rhs_dev,
                              double *x_dev, mc_report *rep);
 
+/* Size of the static device workspace of mc_solve_continuum_noalloc, per device. */
+#define MC_NOALLOC_BYTES (64L << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): the solve of mc_solve_continuum (same
+   system, FP64, same kernels, the problem's tiling and options) with every buffer beyond
+   rhs_dev, x_dev and the problem's own coefficients (launch descriptor, tile lists, system
+   record, partial sums, the PCG vectors and the crossing-cell vectors) taken from one static
+   device array of MC_NOALLOC_BYTES per device, held until the process ends.  No device
+   memory is allocated or freed by this call.
+   - Preconditioner: Jacobi or block IC(0) (MC_EINVAL under MC_MG or MC_MIXED).
+   - Size: MC_EINVAL if the continuum needs more than MC_NOALLOC_BYTES (about 40 bytes per
+     unknown: roughly 1.6 million unknowns).
+   - The problem's device must be current (MC_EINVAL otherwise); the work runs on the
+     problem's stream and the call returns after it has finished.
+   - Every call on one device shares that device's workspace, which keeps the last call's
+     contents (each call initialises what it reads): calls that overlap on one device, from
+     any thread or problem, race and must not be made.
+   rhs_dev, x_dev and rep as for mc_solve_continuum. */
+mc_status mc_solve_continuum_noalloc(mc_problem *p, int32_t alpha, const double *rhs_dev,
+                                     double *x_dev, mc_report *rep);
+
 /* y = (M_a/tau + D_a + S_a) x for continuum a (the operator mc_solve_continuum inverts).
    Device arrays of that continuum's size.  Runs the same operator kernel the solver uses. */
 mc_status mc_apply_continuum(mc_problem *p, int32_t alpha, const double *x_dev, double *y_dev);

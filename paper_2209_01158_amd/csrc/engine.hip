@@ -180,6 +180,28 @@ static bool table_matches(const Table& T, const std::vector<PartD>& parts,
   return true;
 }
 
+// Appends the workgroup tiles of part `pi` for tiling `fam` (0 operator, 1 update, 2
+// crossing-cell rows) to `tiles`: workgroup b of the part takes tiles [b*nt/nb,
+// (b+1)*nt/nb); in launch order, die j of the 8 XCDs (round-robin dispatch) receives a
+// contiguous band of workgroups.
+static void part_tiles(const PartD& q, int pi, const PartTiling& til, int fam, bool xcd,
+                       std::vector<Tile>& tiles) {
+  const int nb = til.blocks[fam];
+  if (nb == 0 || q.mg_level > 0 || (fam == 2 && q.kind == PART_GRID)) return;
+  const int nt = fam == 2 ? nb : til.tiles;
+  const int slot0 = fam == 0 ? q.slot0A : (fam == 1 ? q.slot0B : q.slotS);
+  std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
+  for (int b : ord) {
+    if (b < 0) {
+      tiles.push_back(Tile{-1, 0, 0, 0, 0});
+      continue;
+    }
+    const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
+    tiles.push_back(Tile{pi, slot0 + b, t0, t1, q.sys});
+  }
+  while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0, 0});
+}
+
 // Writes parts and their tile lists into T (reusing its device buffers when large enough).
 static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> parts,
                        const std::vector<PartTiling>& til) {
@@ -195,26 +217,8 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
   for (int fam = 0; fam < 3; ++fam)
     for (int kind = 0; kind < 2; ++kind) {
       std::vector<Tile>& tiles = kept[fam][kind];
-      for (int pi = 0; pi < (int)parts.size(); ++pi) {
-        const PartD& q = parts[pi];
-        if (q.kind != kind) continue;
-        const int nb = til[pi].blocks[fam];
-        if (nb == 0 || q.mg_level > 0 || (fam == 2 && kind == PART_GRID)) continue;
-        const int nt = fam == 2 ? nb : til[pi].tiles;
-        const int slot0 = fam == 0 ? q.slot0A : (fam == 1 ? q.slot0B : q.slotS);
-        // workgroup b of this part takes tiles [b*nt/nb, (b+1)*nt/nb); in launch order, die
-        // j of the 8 XCDs (round-robin dispatch) receives a contiguous band of workgroups
-        std::vector<int> ord = xcd_order(nb, xcd ? 8 : 1);
-        for (int b : ord) {
-          if (b < 0) {
-            tiles.push_back(Tile{-1, 0, 0, 0, 0});
-            continue;
-          }
-          const int t0 = (int)((long)b * nt / nb), t1 = (int)((long)(b + 1) * nt / nb);
-          tiles.push_back(Tile{pi, slot0 + b, t0, t1, q.sys});
-        }
-        while (xcd && tiles.size() % 8) tiles.push_back(Tile{-1, 0, 0, 0, 0});
-      }
+      for (int pi = 0; pi < (int)parts.size(); ++pi)
+        if (parts[pi].kind == kind) part_tiles(parts[pi], pi, til[pi], fam, xcd, tiles);
       if (!tiles.empty() && (!T.tiles[fam][kind] || T.cap[fam][kind] < (int)tiles.size())) {
         T.cap[fam][kind] = (int)tiles.size() + 8;
         T.tiles[fam][kind] = M.alloc<Tile>(T.cap[fam][kind]);
@@ -553,6 +557,7 @@ struct mc_problem {
   int ncont = 0, n_omega = 0, nf = 0, ne = 0;
   long ncell = 0;
   int nz = 1;            // planes of a 3-D grid (1: 2-D)
+  int device = 0;        // HIP device current at creation
   DevArena mem;
   std::vector<Cont> cont;
   // inputs kept on the device (for re-setup)
@@ -1195,6 +1200,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   if (P->nz > 1 && o.precond == MC_MG)
     fail("the multigrid preconditioner needs a 2-D grid (nz <= 1); use MC_JACOBI or MC_BIC0");
   P->ncont = d.n_omega + (d.nf > 0 ? 1 : 0);
+  HIPCHK(hipGetDevice(&P->device));
   exec_init(P->X, o.stream);
   P->X.opt.stream = P->X.stream;
   hipStream_t s = P->X.stream;
@@ -2265,6 +2271,195 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
   return b + nalloc * 4096 + (1 << 20);
 }
 
+// ------------------------------------------------------------------------------------
+// solve without allocation
+// ------------------------------------------------------------------------------------
+// A variant of the continuum solve for callers that cannot allocate device memory: every
+// buffer the solve needs beyond the caller's right-hand side and solution and the
+// problem's own coefficients (the launch descriptor and tile lists, the system record, the
+// partial-sum slots, the PCG vectors r, p, p', q, z and the crossing-cell vectors) is
+// carved out of one static device array.  Each device holds its own copy of the array
+// for the life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device.  Every call on a device shares that copy:
+// calls that overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[MC_NOALLOC_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_addr;   // device -> its copy of `scratch`
+
+// Address of the calling thread's current device's copy of `scratch` (looked up once per
+// device, with that device current).
+static unsigned char* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    (void)hipGetLastError();
+    throw Error{MC_EDEVICE, std::string("hipGetSymbolAddress of the static workspace failed: ") +
+                                hipGetErrorString(e)};
+  }
+  g_scratch_addr[dev] = (unsigned char*)ptr;
+  return (unsigned char*)ptr;
+}
+
+// Consecutive 256-byte aligned pieces of a workspace; with base == nullptr it only counts.
+struct Carve {
+  unsigned char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// Bytes of the static workspace a solve of continuum `c` needs in the current tiling.
+static size_t noalloc_bytes(const mc_problem* P, int c, const std::vector<Tile>* tl) {
+  const Cont& C = P->cont[c];
+  Carve cv{nullptr};
+  cv.take<SysState>(1);
+  cv.take<PartD>(1);
+  for (int f = 0; f < 3; ++f) cv.take<Tile>(tl[f].size());
+  cv.take<double>((size_t)C.blocks[0] * MC_SLOT);
+  cv.take<double>((size_t)(C.blocks[1] + C.blocks[2]) * MC_SLOT);
+  for (int v = 0; v < 5; ++v) cv.take<double>(C.n);
+  if (C.K > 0) {
+    cv.take<double>(C.K);
+    cv.take<double>(C.K);
+  }
+  return cv.off;
+}
+
+template <int PREC, int KIND>
+static void noalloc_iterate(hipStream_t s, const PartD* dp, Tile* const* dt, const int* nb,
+                            SysState* dsys, SysState& hs, int max_iter) {
+  const bool schur = PREC == PREC_BIC0 && KIND == PART_GRAPH && nb[2] > 0;
+  hipLaunchKernelGGL((k_init<PREC, KIND>), dim3(nb[1]), dim3(MC_BLOCK), 0, s, dp, dt[1], dsys);
+  if (schur)
+    hipLaunchKernelGGL(k_schur<double>, dim3(nb[2]), dim3(MC_BLOCK), 0, s, dp, dt[2], dsys);
+  HIPCHK(hipGetLastError());
+  long launched = 0;
+  int K = 8;
+  for (;;) {
+    for (int j = 0; j < K; ++j) {
+      hipLaunchKernelGGL((k_pcg_A<double, PREC, KIND>), dim3(nb[0]), dim3(MC_BLOCK), 0, s, dp,
+                         dt[0], dsys);
+      hipLaunchKernelGGL((k_pcg_B<double, PREC, KIND>), dim3(nb[1]), dim3(MC_BLOCK), 0, s, dp,
+                         dt[1], dsys);
+      if (schur)
+        hipLaunchKernelGGL(k_schur<double>, dim3(nb[2]), dim3(MC_BLOCK), 0, s, dp, dt[2], dsys);
+    }
+    HIPCHK(hipGetLastError());
+    launched += K;
+    HIPCHK(hipMemcpyAsync(&hs, dsys, sizeof(SysState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hs.done) return;
+    // iterations launched after convergence return at once, so overshooting costs launches
+    if (launched > (long)max_iter + 1)
+      throw Error{MC_EDEVICE, "PCG did not report completion within max_iter iterations"};
+    K = (int)std::min<long>(std::min(2 * K, 64), (long)max_iter + 2 - launched);
+    K = std::max(K, 1);
+  }
+}
+
+static mc_status solve_noalloc(mc_problem* P, int c, const double* rhs, double* x,
+                               mc_report* rep) {
+  Exec& X = P->X;
+  if (X.opt.precision == MC_MIXED)
+    throw Error{MC_EINVAL, "the no-allocation solve is FP64; set precision MC_FP64"};
+  if (X.opt.precond == MC_MG)
+    throw Error{MC_EINVAL, "the no-allocation solve takes Jacobi or block IC(0) (MC_JACOBI, "
+                           "MC_BIC0); the V-cycle's level vectors do not fit its workspace"};
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != P->device)
+    throw Error{MC_EINVAL, "the problem's device (" + std::to_string(P->device) +
+                               ") must be current for the no-allocation solve"};
+  const Cont& C = P->cont[c];
+  const bool bic0 = X.opt.precond == MC_BIC0;
+  PartD q = base_part(P, c, 0, 0, 0, false);   // system record 0, slots from 0
+  const PartTiling til = tiling_of(P, c);
+  std::vector<Tile> tl[3];
+  const bool xcd = env_flag("MCDEC_XCD", true);
+  for (int f = 0; f < 3; ++f) part_tiles(q, 0, til, f, xcd, tl[f]);
+  const size_t need = noalloc_bytes(P, c, tl);
+  if (need > (size_t)MC_NOALLOC_BYTES)
+    throw Error{MC_EINVAL, "continuum " + std::to_string(c) + " (" + std::to_string(C.n) +
+                               " unknowns) needs " + std::to_string(need) +
+                               " bytes of workspace; the no-allocation solve has " +
+                               std::to_string((long)MC_NOALLOC_BYTES)};
+  Carve cv{scratch_on(dev)};
+  SysState* dsys = cv.take<SysState>(1);
+  PartD* dpart = cv.take<PartD>(1);
+  Tile* dt[3];
+  for (int f = 0; f < 3; ++f) dt[f] = cv.take<Tile>(tl[f].size());
+  double* slotA = cv.take<double>((size_t)C.blocks[0] * MC_SLOT);
+  double* slotB = cv.take<double>((size_t)(C.blocks[1] + C.blocks[2]) * MC_SLOT);
+  double* vec[5];
+  for (int v = 0; v < 5; ++v) vec[v] = cv.take<double>(C.n);
+  q.x = x;
+  q.x64 = x;
+  q.b = const_cast<double*>(rhs);
+  q.r = vec[0];
+  q.r64 = vec[0];
+  q.p = vec[1];
+  q.p2 = vec[2];
+  q.q = vec[3];
+  q.z = vec[4];
+  if (C.K > 0) {
+    q.gX = cv.take<double>(C.K);
+    q.zX = cv.take<double>(C.K);
+  }
+  // the record: solve parameters, a fresh start, and the slots of this call's tiling
+  SysState hs;
+  std::memset(&hs, 0, sizeof(hs));
+  sys_params(X, hs, X.opt.tol, false);
+  hs.status = ST_RUN;
+  hs.outer_status = ST_RUN;
+  hs.nslotsA = C.blocks[0];
+  hs.nslotsB = C.blocks[1] + C.blocks[2];
+  hs.partA = slotA;
+  hs.partB = slotB;
+  const hipStream_t s = X.stream;
+  HIPCHK(hipMemcpyAsync(dsys, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(dpart, &q, sizeof(q), hipMemcpyHostToDevice, s));
+  int nb[3];
+  for (int f = 0; f < 3; ++f) {
+    nb[f] = (int)tl[f].size();
+    if (nb[f])
+      HIPCHK(hipMemcpyAsync(dt[f], tl[f].data(), tl[f].size() * sizeof(Tile),
+                            hipMemcpyHostToDevice, s));
+  }
+  const int mi = X.opt.max_iter;
+  if (q.kind == PART_GRID) {
+    if (bic0) noalloc_iterate<PREC_BIC0, PART_GRID>(s, dpart, dt, nb, dsys, hs, mi);
+    else noalloc_iterate<PREC_JACOBI, PART_GRID>(s, dpart, dt, nb, dsys, hs, mi);
+  } else {
+    if (bic0) noalloc_iterate<PREC_BIC0, PART_GRAPH>(s, dpart, dt, nb, dsys, hs, mi);
+    else noalloc_iterate<PREC_JACOBI, PART_GRAPH>(s, dpart, dt, nb, dsys, hs, mi);
+  }
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->n_cont = P->ncont;
+    rep->failed = -1;
+    rep->step = P->step_count;
+    if (c < 3) {
+      rep->iters[c] = hs.iter;
+      rep->converged[c] = hs.status == ST_CONV;
+      rep->relres[c] = hs.bb > 0 ? std::sqrt(hs.rr / hs.bb) : std::sqrt(hs.rr);
+    }
+  }
+  if (hs.status != ST_CONV) {
+    if (rep) rep->failed = c;
+    return hs.status == ST_NOCONV ? MC_ENOCONV : MC_EBREAKDOWN;
+  }
+  return MC_OK;
+}
+
 }  // namespace mc
 
 // ======================================================================================
@@ -2379,6 +2574,22 @@ mc_status mc_solve_continuum(mc_problem* P, int32_t alpha, const double* rhs, do
   r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   r.step = P->step_count;
   if (rep) *rep = r;
+  return st;
+  ABI_END(P)
+}
+
+mc_status mc_solve_continuum_noalloc(mc_problem* P, int32_t alpha, const double* rhs,
+                                     double* x, mc_report* rep) {
+  if (!P) return MC_EINVAL;
+  ABI_BEGIN
+  if (alpha < 0 || alpha >= P->ncont) throw mc::Error{MC_EINVAL, "alpha out of range"};
+  if (!rhs || !x) throw mc::Error{MC_EINVAL, "rhs and x must be device pointers"};
+  auto t0 = std::chrono::steady_clock::now();
+  mc_report r;
+  mc_status st = mc::solve_noalloc(P, alpha, rhs, x, &r);
+  r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = r;
+  if (st != MC_OK) P->err = "no-allocation solve of continuum " + std::to_string(alpha) + " failed";
   return st;
   ABI_END(P)
 }

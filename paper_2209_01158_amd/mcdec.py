@@ -99,6 +99,9 @@ mc_destroy = _sig("mc_destroy", C.c_int, [_PROBLEM])
 mc_step = _sig("mc_step", C.c_int, [_PROBLEM, C.c_int32, C.POINTER(Report)])
 mc_solve_continuum = _sig("mc_solve_continuum", C.c_int,
                           [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p, C.POINTER(Report)])
+mc_solve_continuum_noalloc = _sig("mc_solve_continuum_noalloc", C.c_int,
+                                  [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.POINTER(Report)])
 mc_apply_continuum = _sig("mc_apply_continuum", C.c_int,
                           [_PROBLEM, C.c_int32, C.c_void_p, C.c_void_p])
 mc_apply_coupled = _sig("mc_apply_coupled", C.c_int, [_PROBLEM, C.c_void_p, C.c_void_p])
@@ -348,6 +351,13 @@ class Problem:
         _check(st, self.h, rep.as_dict())
         return rep.as_dict()
 
+    def solve_continuum_noalloc(self, alpha: int, rhs, x) -> dict:
+        rep = Report()
+        _sync_torch()
+        st = mc_solve_continuum_noalloc(self.h, alpha, _dev_ptr(rhs), _dev_ptr(x), C.byref(rep))
+        _check(st, self.h, rep.as_dict())
+        return rep.as_dict()
+
     def apply_continuum(self, alpha: int, x, y):
         _sync_torch()
         _check(mc_apply_continuum(self.h, alpha, _dev_ptr(x), _dev_ptr(y)), self.h)
@@ -588,7 +598,7 @@ class Batch:
 
 
 EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
-           "mc_solve_continuum", "mc_apply_continuum", "mc_apply_coupled", "mc_assemble_rhs",
+           "mc_solve_continuum", "mc_solve_continuum_noalloc", "mc_apply_continuum", "mc_apply_coupled", "mc_assemble_rhs",
            "mc_apply_precond",
            "mc_get_state", "mc_set_state", "mc_set_options", "mc_get_info", "mc_last_error",
            "mc_profile", "mc_profile_read", "mc_profile_read_above", "mc_batch_create",

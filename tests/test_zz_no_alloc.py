@@ -1,0 +1,83 @@
+"""The no-allocation continuum solve against the allocating one (GPU).
+
+mc_solve_continuum_noalloc takes every buffer beyond its inputs and outputs from a static
+device workspace.  It must return what mc_solve_continuum returns for the same system and
+the same initial guess (FP64: relative L2 difference <= 1e-10, the FP64 parity bar; the
+two run the same kernels in the same tiling, so equal iteration counts are expected too),
+on two calls in a row, the second on a smaller problem, and both must agree with the
+oracle's direct solve of the D-scheme system (Section 3.3) to the same bar.  The call
+must not grow the problem's device memory, and it must refuse what its workspace cannot
+hold.
+"""
+import numpy as np
+import pytest
+
+import media
+from oracle import fv, schemes
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2209_01158_amd import mcdec  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.ravel(a), np.ravel(b)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _solve_both(p, precond, seed):
+    asm = fv.assemble(p)
+    rng = np.random.default_rng(seed)
+    with mcdec.Problem(p, precond=precond, tol=1e-13) as g:
+        for a in range(p.n_cont):
+            n = p.sizes()[a]
+            rhs = rng.random(n)
+            x0 = rng.random(n)
+            ref = schemes.DirectSolver(schemes.continuum_matrix(asm, p.tau, a)).solve(rhs)
+            b = torch.tensor(rhs, device=DEV)
+            x_alloc = torch.tensor(x0, device=DEV)
+            rep_a = g.solve_continuum(a, b, x_alloc)
+            before = g.info().device_bytes
+            x_na = torch.tensor(x0, device=DEV)
+            rep_n = g.solve_continuum_noalloc(a, b, x_na)
+            assert g.info().device_bytes == before
+            xa, xn = x_alloc.cpu().numpy(), x_na.cpu().numpy()
+            print(f"n={p.nx} precond={precond} continuum {a}: iterations {rep_a['iters'][a]} / "
+                  f"{rep_n['iters'][a]}, noalloc vs alloc {rel(xn, xa):.2e}, "
+                  f"vs oracle {rel(xn, ref):.2e}", flush=True)
+            assert rep_n["converged"][a] == 1
+            assert rep_n["iters"][a] == rep_a["iters"][a]
+            assert rel(xn, xa) <= 1e-10
+            assert rel(xn, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "bic0"])
+def test_noalloc_matches_solve_continuum_twice(precond):
+    # larger first (3 continua, ragged tiles, crossing fractures), then a smaller problem
+    # whose call reuses the same workspace
+    big = media.small_problem(n=200, seed=11, three=True, nseg=12, seg_len=(10, 80))
+    small = media.small_problem(n=70, seed=5, three=True, nseg=6, seg_len=(5, 40))
+    _solve_both(big, precond, 1)
+    _solve_both(small, precond, 2)
+
+
+def test_noalloc_refusals():
+    p = media.small_problem(n=64, seed=3, nseg=4, seg_len=(5, 20))
+    b = torch.ones(p.sizes()[0], dtype=torch.float64, device=DEV)
+    x = torch.zeros_like(b)
+    with mcdec.Problem(p, precond="mg") as g:
+        with pytest.raises(mcdec.McError, match="Jacobi or block IC"):
+            g.solve_continuum_noalloc(0, b, x)
+    big = media.small_problem(n=1400, seed=3, nseg=0, lognormal=False)
+    b = torch.ones(1400 * 1400, dtype=torch.float64, device=DEV)
+    x = torch.zeros_like(b)
+    with mcdec.Problem(big, precond="jacobi") as g:
+        with pytest.raises(mcdec.McError, match="workspace"):
+            g.solve_continuum_noalloc(0, b, x)
