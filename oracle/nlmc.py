@@ -12,17 +12,31 @@ Follows Section 4 of the paper:
   part on the boundary of Omega), subject to the mean of psi over every unit (j, a) with
   K_j in K_i^+ being delta_ij delta_ab -- the saddle-point system of eq. eq:basis, solved
   here as it stands (sparse LU of [[A_loc, C^T], [C, 0]]);
-* R = the matrix whose rows are the basis functions; the coarse operator A_bar = R A R^T,
-  the coarse storage M_bar (block diagonal, M_bar_a = R_aa M_a R_aa^T) and the coarse
-  right-hand side F_bar_a = R_aa F_a (eq. app-nlmc);
+* R = the matrix whose rows are the basis functions; the nonlocal coarse operator A_bar
+  from the projection R A R^T (Section 4), and the coarse storage M_bar and right-hand side
+  F_bar computed directly on the coarse grid as the paper gives them for coefficients that
+  are constant in each coarse unit: m = c |K_j^a| on the diagonal and f |K_j^a| (eq.
+  app-nlmc and the formulas after it);
 * the coupled coarse scheme (eq. is-nlmc) and the D-, L- and U-schemes (eq. si-nlmc), whose
   A_bar_0 is the block diagonal, block lower or block upper triangle of A_bar (its diagonal
   block A_bar_aa = D_bar_aa + sum_b Q_bar_ab) and A_bar_1 = A_bar - A_bar_0.
 
 Readings where the paper is silent (each is also listed in the design notes):
 * A is the whole fine operator of the problem, the implicit wells of Section 5 included
-  (they sit on the fracture diagonal of D_f), so A_bar, M_bar and F_bar are Galerkin
-  products of exactly the fine quantities the fine-grid schemes use;
+  (they sit on the fracture diagonal of D_f);
+* A_bar is conservative, as the finite-volume operator it stands in for: its off-diagonal
+  entries (the nonlocal transmissibilities between coarse units) are those of R A R^T, and
+  its diagonal makes every row sum equal the summed fine row sums over the unit (zero away
+  from Dirichlet sides and wells).  Then a constant state is kept by every coarse scheme
+  exactly as by the fine ones, and with no-flow sides the coupled scheme conserves the
+  coarse mass.  The plain product R A R^T has these row sums only when the basis sums to
+  one (K_i^+ the whole domain without Dirichlet sides or wells); with local bases its
+  constants leak through the zero values on the boundaries of the K_i^+ (at k_f / k_m =
+  1e6 the coarse pressure of the paper's problems then decays to nearly zero, errors near
+  100 %, against 0.01-0.3 % with the conservative diagonal);
+* the storage, transfer-free sources and Dirichlet terms enter M_bar and F_bar as sums over
+  each unit's fine cells (the direct formulas, which the means constraints make equal to the
+  projected ones for coefficients constant in a unit);
 * the mean of a unit weighs each fine cell by its measure (h^2; a l for a fracture cell);
 * the coarse unknowns are ordered continuum by continuum, the units of one continuum by
   coarse cell (row-major), fracture units only where a coarse cell hosts fracture cells;
@@ -205,29 +219,33 @@ class Basis:
 
 @dataclass
 class CoarseSystem:
-    """A_bar = R A R^T, M_bar (block diagonal), F_bar (eq. app-nlmc)."""
+    """A_bar (conservative nonlocal operator), M_bar (diagonal), F_bar (eq. app-nlmc)."""
     units: Units
     A: np.ndarray        # dense N_H x N_H
-    M: np.ndarray        # dense N_H x N_H, block diagonal by continuum
+    M: np.ndarray        # dense N_H x N_H, diagonal
     F: np.ndarray        # N_H
     blocks: List[slice]  # coarse unknowns of each continuum
 
 
+def unit_sums(units: Units, v: np.ndarray) -> np.ndarray:
+    """Sum of a fine vector (concatenated continua) over the cells of every coarse unit."""
+    return np.array([float(v[c].sum()) for c in units.cells])
+
+
 def coarse_system(basis: Basis) -> CoarseSystem:
-    """A_bar = R A R^T; M_bar_a = R_aa M_a R_aa^T and F_bar_a = R_aa F_a, where R_aa is the
-    continuum-a component of the basis functions of continuum-a units."""
+    """Off-diagonal entries of A_bar from R A R^T; its diagonal from the row sums (each row of
+    A_bar sums to the unit's summed fine row sums of A); M_bar = diag(sum of the unit's fine
+    storage); F_bar = the unit's summed fine right-hand side."""
     U, asm, R = basis.units, basis.asm, basis.R
     Abar = (R @ basis.A @ R.T).toarray()
     Abar = 0.5 * (Abar + Abar.T)     # symmetric by construction; remove rounding asymmetry
-    offs = np.concatenate([[0], np.cumsum(asm.sizes)])
+    rowsum = unit_sums(U, np.asarray(basis.A @ np.ones(basis.N)).ravel())
+    np.fill_diagonal(Abar, 0.0)
+    np.fill_diagonal(Abar, rowsum - Abar.sum(axis=1))
     coffs = np.concatenate([[0], np.cumsum(U.sizes)])
     blocks = [slice(int(coffs[a]), int(coffs[a + 1])) for a in range(asm.L)]
-    Mbar = np.zeros_like(Abar)
-    Fbar = np.zeros(U.n)
-    for a in range(asm.L):
-        Raa = R[blocks[a], :][:, int(offs[a]):int(offs[a + 1])]
-        Mbar[blocks[a], blocks[a]] = (Raa @ sp.diags(asm.M[a]) @ Raa.T).toarray()
-        Fbar[blocks[a]] = Raa @ asm.F[a]
+    Mbar = np.diag(unit_sums(U, asm.Mfull()))
+    Fbar = unit_sums(U, asm.Ffull())
     return CoarseSystem(U, Abar, Mbar, Fbar, blocks)
 
 

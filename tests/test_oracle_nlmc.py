@@ -94,6 +94,10 @@ def test_single_cell_coarse_grid_is_the_fine_scheme(three, scheme):
 
 
 def test_whole_domain_basis_is_inverse_constraint_schur():
+    """Off the diagonal, A_bar = (C A^-1 C^T)^-1; every row of A_bar sums to the unit's share
+    of the fine row sums, which are only the Dirichlet half-cell conductances 2 k (west and
+    east sides of both grid continua) and the well term q_w a l, computed here from the
+    problem data."""
     p = _distinct_hosts_problem(True, n=6)
     cg = nlmc.CoarseGrid(6, 6, 3, 2)
     B = nlmc.Basis(p, cg, layers=10)
@@ -103,8 +107,20 @@ def test_whole_domain_basis_is_inverse_constraint_schur():
     C = np.zeros((U.n, A.shape[0]))
     for u in range(U.n):
         C[u, U.cells[u]] = U.meas[u] / U.meas[u].sum()
-    S = C @ np.linalg.inv(A) @ C.T
-    np.testing.assert_allclose(cs.A, np.linalg.inv(S), rtol=1e-9, atol=1e-9 * np.abs(cs.A).max())
+    Ainv = np.linalg.inv(C @ np.linalg.inv(A) @ C.T)
+    off = ~np.eye(U.n, dtype=bool)
+    np.testing.assert_allclose(cs.A[off], Ainv[off], rtol=1e-9, atol=1e-9 * np.abs(Ainv).max())
+    n = p.nx
+    fine_rowsum = []
+    for o in p.omega:
+        k = o.k_field(n, n).reshape(n, n)
+        r = np.zeros((n, n))
+        r[:, 0] += 2.0 * k[:, 0]
+        r[:, n - 1] += 2.0 * k[:, n - 1]
+        fine_rowsum.append(r.ravel())
+    fine_rowsum.append(p.well_q * p.aperture * p.flen)
+    want = nlmc.unit_sums(U, np.concatenate(fine_rowsum))
+    np.testing.assert_allclose(cs.A.sum(axis=1), want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
 
 
 def test_whole_domain_basis_partition_of_unity():
@@ -145,19 +161,60 @@ def test_coarse_operator_structure_and_energy(layers):
 
 
 def test_accuracy_improves_with_oversampling_and_scheme_order():
-    p = media.paper_problem("2C", n=40)
-    cg = nlmc.CoarseGrid(40, 40, 4, 4)
-    ref = schemes.run(p, "coupled", 50)[-1]
+    """The paper's two-continuum problem on its 200 x 200 grid and 20 x 20 coarse grid: the
+    error against the fine coupled solution falls as K_i^+ grows by 1, 2 and 3 layers and
+    reaches the size of Table tab-2c-ms (0.01 % coupled); the decoupled schemes rank as there
+    (U closest to coupled, D the least accurate).  The table values themselves are unpinned
+    (the fracture geometry is only in a figure)."""
+    p = media.paper_problem("2C")
+    cg = nlmc.CoarseGrid(200, 200, 10, 10)
+    ref = schemes.run(p, "coupled", 50, keep="last")
     err = {}
-    for layers in (1, 3, 4, 10):
+    for layers in (1, 2, 3):
         cs = nlmc.coarse_system(nlmc.Basis(p, cg, layers))
         x0 = nlmc.unit_means(cs.units, p.initial_state())
         ref_m = nlmc.unit_means(cs.units, ref)
         for scheme in ("coupled", "D", "L", "U"):
             x = nlmc.run(cs, p.tau, scheme, x0, 50, keep="last")
             err[(layers, scheme)] = nlmc.e_H(x, ref_m)
-    co = [err[(l, "coupled")] for l in (1, 3, 4, 10)]
-    assert all(a > b for a, b in zip(co, co[1:])), co
-    assert err[(10, "coupled")] < 1e-3
-    e = {s: err[(10, s)] for s in ("coupled", "D", "L", "U")}
-    assert e["U"] < e["L"] < e["D"] and e["U"] < 2 * e["coupled"], e
+    co = [err[(l, "coupled")] for l in (1, 2, 3)]
+    assert co[0] > co[1] > co[2], co
+    assert co[2] < 2e-4
+    e = {s: err[(3, s)] for s in ("coupled", "D", "L", "U")}
+    assert e["coupled"] < e["U"] < e["L"] < e["D"] < 5e-3, e
+
+
+@pytest.mark.parametrize("three", [False, True])
+def test_local_basis_keeps_constant_states(three):
+    """p^0 = C, Dirichlet values C, well pressure C and no sources: the fine schemes keep C
+    (pinned on their own), and so must every coarse scheme with local bases (one layer of
+    oversampling), exactly up to rounding."""
+    p = _distinct_hosts_problem(three, n=12)
+    cval = 0.7
+    p.bc_value = np.array([cval, cval, 0.0, 0.0])
+    p.well_p = np.full(p.nf, cval)
+    p.p0 = [np.full(s, cval) for s in p.sizes()]
+    cs = nlmc.coarse_system(nlmc.Basis(p, nlmc.CoarseGrid(12, 12, 3, 3), layers=1))
+    x0 = nlmc.unit_means(cs.units, p.initial_state())
+    np.testing.assert_allclose(x0, cval, rtol=1e-15)
+    for scheme in ("coupled", "D", "L", "U"):
+        x = nlmc.run(cs, p.tau, scheme, x0, 5, keep="last")
+        np.testing.assert_allclose(x, cval, rtol=1e-12, err_msg=scheme)
+
+
+def test_local_basis_coupled_mass_equals_fine_mass():
+    """No-flow sides, no wells, no sources: the fine coupled scheme conserves sum M p, and the
+    coarse coupled scheme with local bases conserves sum M_bar p_bar, which starts from the
+    same value (a unit's storage times its measure-weighted mean is its fine mass)."""
+    p = media.paper_problem("3C", n=40)
+    p.well_q = None
+    p.well_p = None
+    rng = np.random.default_rng(7)
+    p.p0 = [rng.random(s) for s in p.sizes()]
+    asm = fv.assemble(p)
+    fine_mass = float(asm.Mfull() @ np.concatenate(p.initial_state()))
+    cs = nlmc.coarse_system(nlmc.Basis(p, nlmc.CoarseGrid(40, 40, 8, 8), layers=1))
+    x = nlmc.unit_means(cs.units, p.initial_state())
+    for _ in range(10):
+        x = nlmc.step(cs, p.tau, "coupled", x)
+        assert abs(float(np.diag(cs.M) @ x) - fine_mass) < 1e-10 * abs(fine_mass)
