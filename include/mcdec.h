@@ -416,6 +416,68 @@ mc_status mc_server_step_seconds(mc_server *s, double *out, int64_t cap, int64_t
 
 const char *mc_server_last_error(const mc_server *s);
 
+/* ---- coarse-grid schemes: nonlocal multicontinuum (NLMC) upscaling (Section 4) ---------
+   A coarse grid of bx x by fine cells per coarse cell (nx % bx == ny % by == 0).  A coarse
+   unit is one continuum inside one coarse cell (K_j^a; a fracture unit only where the
+   coarse cell hosts fracture cells); units are ordered continuum by continuum, coarse cells
+   row-major.  For every unit a basis function minimizes the energy of the fine operator
+   A = D + Q (wells included) over vectors that vanish outside the oversampled region K_i^+
+   (K_i grown by `layers` coarse cells) and have mean one on their own unit and zero on
+   every other unit of K_i^+ (eq. eq:basis; the means weigh cells by their measure).  The
+   coarse operator A_bar takes its off-diagonal entries (nonlocal transmissibilities) from
+   R A R^T, R the matrix of basis functions, and its diagonal from conservation: each row
+   sums to the unit's summed fine row sums (zero away from Dirichlet sides and wells).
+   M_bar (diagonal) and F_bar sum the fine storage c|K| and right-hand side over each unit
+   (eq. app-nlmc and the direct coarse formulas after it).  Layers advance eq. is-nlmc
+   (coupled) or eq. si-nlmc (D, L, U: block-diagonal, block-lower or block-upper A_bar_0)
+   with direct solves (dense inverses of the coarse systems, formed at creation). */
+typedef struct mc_nlmc mc_nlmc;
+
+typedef struct {
+  int32_t n_units;               /* N_H, coarse unknowns                                       */
+  int32_t n_cont;                /* continua (grid continua, then the fracture if any)         */
+  int32_t sizes[3];              /* units per continuum                                        */
+  int32_t n_regions;             /* oversampled regions (one per coarse cell)                  */
+  int32_t max_region_unknowns;   /* largest local problem                                      */
+  int32_t max_band;              /* largest lower band width of a local operator               */
+  int32_t max_constraints;       /* most units inside one region                               */
+  int32_t pad;
+  int64_t n_pairs;               /* unit pairs whose basis functions interact                  */
+  int64_t device_bytes;          /* device memory held after creation                          */
+  double setup_ms[4];            /* GPU time of creation: [0] unit sums and local factors,     */
+                                 /* [1] basis functions, [2] coarse operator, [3] inverses     */
+  int64_t steps;                 /* layers advanced since the last mc_nlmc_set_state           */
+} mc_nlmc_info;
+
+/* Build the coarse system of fine problem `fine` (2-D grid; any scheme but MC_SCHEME_EX),
+   on its device (which must be current) and stream.  The coarse state starts as the unit
+   means of the fine problem's current state.  The fine problem is only read here.
+   MC_EINVAL: coarse cells that do not tile the grid, layers < 0, fracture connections
+   between hosts more than one cell apart, local bands too wide for the forward solve.
+   MC_EBREAKDOWN: a local operator or constraint system not positive definite (for example
+   a region covering a whole domain without Dirichlet sides or wells). */
+mc_status mc_nlmc_create(mc_problem *fine, int32_t bx, int32_t by, int32_t layers,
+                         mc_nlmc **out);
+mc_status mc_nlmc_destroy(mc_nlmc *nl);   /* NULL-safe */
+mc_status mc_nlmc_get_info(const mc_nlmc *nl, mc_nlmc_info *info);
+
+/* Copies of A_bar (row-major n_units x n_units), the diagonal of M_bar and F_bar to host
+   arrays (each may be NULL). */
+mc_status mc_nlmc_get_system(mc_nlmc *nl, double *A_host, double *M_host, double *F_host);
+
+/* Coarse state to / from host arrays of n_units values; host_in NULL restores the unit
+   means of the fine state at creation.  Synchronous. */
+mc_status mc_nlmc_set_state(mc_nlmc *nl, const double *host_in);
+mc_status mc_nlmc_get_state(mc_nlmc *nl, double *host_out);
+
+/* Advance n_steps layers of `scheme` (MC_SCHEME_COUPLED, _D, _L or _U) with the fine
+   problem's tau; synchronous. */
+mc_status mc_nlmc_step(mc_nlmc *nl, int32_t scheme, int32_t n_steps);
+
+/* Message of the last failure on this handle, or (NULL) of the calling thread's last failed
+   mc_nlmc_create.  Never NULL. */
+const char *mc_nlmc_last_error(const mc_nlmc *nl);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmcdec.so")
 SOURCES = [os.path.join(HERE, "csrc", f)
-           for f in ("engine.hip", "host_setup.cpp", "scheduler.cpp", "server.cpp")]
+           for f in ("engine.hip", "nlmc.hip", "host_setup.cpp", "nlmc_host.cpp", "scheduler.cpp",
+                     "server.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed FP32 instructions in any generated code

@@ -24,6 +24,7 @@
 
 #include "../../include/mcdec.h"
 #include "common.hpp"
+#include "fine_view.hpp"
 #include "host_setup.hpp"
 #include "kernels.hpp"
 
@@ -568,6 +569,7 @@ struct mc_problem {
   int *host = nullptr, *rowptr = nullptr, *col = nullptr, *eidx = nullptr, *hptr = nullptr,
       *hidx = nullptr, *chain_ptr = nullptr, *gtile = nullptr;
   GraphCSR gh;                       // host copies of the fracture graph structure
+  std::vector<int> host_h;           // host copy of the fracture cells' host cells
   std::vector<int> chains_h, gtile_h;
   int K_all = 0;                     // crossing cells of the fracture graph
   double *flen = nullptr, *edge_d = nullptr, *sigma_f = nullptr;
@@ -1233,6 +1235,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     P->ngtiles = (int)gt.size() - 1;
     P->K_all = count_crossing_cells(d.nf, d.ne, d.edges);
     P->gh = g;
+    P->host_h.assign(d.host, d.host + d.nf);
     P->chains_h = chains;
     P->gtile_h = gt;
     if (d.src_f) P->src[d.n_omega] = M.upload(d.src_f, d.nf, s);
@@ -2458,6 +2461,57 @@ static mc_status solve_noalloc(mc_problem* P, int c, const double* rhs, double* 
     return hs.status == ST_NOCONV ? MC_ENOCONV : MC_EBREAKDOWN;
   }
   return MC_OK;
+}
+
+void spd_inverse(double* S, int K, hipStream_t s, int lda) { invert_spd(S, K, s, lda); }
+
+void fine_view(const mc_problem* P, FineView& v) {
+  if (P->nz > 1) throw std::invalid_argument("the coarse-grid path is defined for 2-D grids");
+  if (P->X.opt.scheme == MC_SCHEME_EX)
+    throw std::invalid_argument("the coarse-grid path needs a problem whose diagonals include "
+                                "the transfer (any scheme but MC_SCHEME_EX)");
+  v.nx = P->d.nx;
+  v.ny = P->d.ny;
+  v.nz = P->nz;
+  v.n_omega = P->n_omega;
+  v.nf = P->nf;
+  v.ncont = P->ncont;
+  v.scheme = P->X.opt.scheme;
+  v.ncell = P->ncell;
+  v.h = P->d.h;
+  v.tau = P->d.tau;
+  v.s12 = P->n_omega == 2 ? omega_transfer(P) : 0.0;
+  for (int c = 0; c < P->ncont; ++c) {
+    const Cont& C = P->cont[c];
+    v.diag[c] = C.diag;
+    v.F[c] = C.F;
+    v.state[c] = C.ps[P->cur];
+    if (c < P->n_omega) {
+      v.mtau[c] = C.mtau;
+      v.c[c] = P->d.omega[c].c;
+      v.has_t[c] = C.has_t;
+      v.tconst[c] = C.tconst;
+      v.tx[c] = C.tx;
+      v.ty[c] = C.ty;
+    } else {
+      v.mt = C.mt;
+      v.val = C.val;
+    }
+  }
+  v.flen = P->flen;
+  v.aperture = P->d.aperture;
+  v.c_f = P->d.c_f;
+  v.rowptr = P->rowptr;
+  v.col = P->col;
+  v.host = P->host;
+  v.hptr = P->hptr;
+  v.hidx = P->hidx;
+  v.sigma_f = P->sigma_f;
+  v.stream = P->X.stream;
+  v.device = P->device;
+  v.h_host = P->host_h;
+  v.h_rowptr = P->gh.rowptr;
+  v.h_col = P->gh.col;
 }
 
 }  // namespace mc

@@ -82,6 +82,14 @@ class Info(C.Structure):
                 ("mg_levels", C.c_int32 * 3)]
 
 
+class NlmcInfo(C.Structure):
+    _fields_ = [("n_units", C.c_int32), ("n_cont", C.c_int32), ("sizes", C.c_int32 * 3),
+                ("n_regions", C.c_int32), ("max_region_unknowns", C.c_int32),
+                ("max_band", C.c_int32), ("max_constraints", C.c_int32), ("pad", C.c_int32),
+                ("n_pairs", C.c_int64), ("device_bytes", C.c_int64),
+                ("setup_ms", C.c_double * 4), ("steps", C.c_int64)]
+
+
 _PROBLEM = C.c_void_p
 
 
@@ -111,6 +119,15 @@ mc_get_state = _sig("mc_get_state", C.c_int, [_PROBLEM, C.c_int32, _dp])
 mc_set_state = _sig("mc_set_state", C.c_int, [_PROBLEM, C.c_int32, _dp])
 mc_set_options = _sig("mc_set_options", C.c_int, [_PROBLEM, C.POINTER(Options)])
 mc_get_info = _sig("mc_get_info", C.c_int, [_PROBLEM, C.POINTER(Info)])
+mc_nlmc_create = _sig("mc_nlmc_create", C.c_int,
+                      [_PROBLEM, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_void_p)])
+mc_nlmc_destroy = _sig("mc_nlmc_destroy", C.c_int, [C.c_void_p])
+mc_nlmc_get_info = _sig("mc_nlmc_get_info", C.c_int, [C.c_void_p, C.POINTER(NlmcInfo)])
+mc_nlmc_get_system = _sig("mc_nlmc_get_system", C.c_int, [C.c_void_p, _dp, _dp, _dp])
+mc_nlmc_set_state = _sig("mc_nlmc_set_state", C.c_int, [C.c_void_p, _dp])
+mc_nlmc_get_state = _sig("mc_nlmc_get_state", C.c_int, [C.c_void_p, _dp])
+mc_nlmc_step = _sig("mc_nlmc_step", C.c_int, [C.c_void_p, C.c_int32, C.c_int32])
+mc_nlmc_last_error = _sig("mc_nlmc_last_error", C.c_char_p, [C.c_void_p])
 mc_last_error = _sig("mc_last_error", C.c_char_p, [_PROBLEM])
 mc_profile = _sig("mc_profile", C.c_int, [_PROBLEM, C.c_int32])
 mc_profile_read = _sig("mc_profile_read", C.c_int,
@@ -432,6 +449,66 @@ class Problem:
         return n.value, ms.value
 
 
+class Nlmc:
+    """Coarse-grid NLMC system of a fine Problem (wraps mc_nlmc): bx x by fine cells per
+    coarse cell, basis functions on regions grown by `layers` coarse cells."""
+
+    def __init__(self, fine: "Problem", bx: int, by: int, layers: int):
+        h = C.c_void_p()
+        _check(mc_nlmc_create(fine.h, bx, by, layers, C.byref(h)), None,
+               last_error=mc_nlmc_last_error)
+        self.h = h
+        self.fine = fine
+        self.n = self.info().n_units
+
+    def info(self) -> NlmcInfo:
+        inf = NlmcInfo()
+        _check(mc_nlmc_get_info(self.h, C.byref(inf)), self.h, last_error=mc_nlmc_last_error)
+        return inf
+
+    def system(self):
+        """(A_bar, diagonal of M_bar, F_bar) as numpy arrays."""
+        A = np.empty((self.n, self.n))
+        M = np.empty(self.n)
+        F = np.empty(self.n)
+        _check(mc_nlmc_get_system(self.h, _ptr(A, C.c_double), _ptr(M, C.c_double),
+                                  _ptr(F, C.c_double)), self.h, last_error=mc_nlmc_last_error)
+        return A, M, F
+
+    def set_state(self, x=None):
+        xa = None if x is None else np.ascontiguousarray(x, np.float64)
+        if xa is not None and xa.size != self.n:
+            raise ValueError("state size mismatch")
+        _check(mc_nlmc_set_state(self.h, _ptr(xa, C.c_double)), self.h,
+               last_error=mc_nlmc_last_error)
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty(self.n)
+        _check(mc_nlmc_get_state(self.h, _ptr(out, C.c_double)), self.h,
+               last_error=mc_nlmc_last_error)
+        return out
+
+    def step(self, scheme: str, n: int = 1):
+        _check(mc_nlmc_step(self.h, SCHEMES[scheme], n), self.h, last_error=mc_nlmc_last_error)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mc_nlmc_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autotune(problems, iters: int = 20):
     """Pick the PCG launch shapes per size class by timing (mc_autotune); applies to these
     problems and to problems created later in the process."""
@@ -607,4 +684,6 @@ EXPORTS = ["mc_options_default", "mc_create_problem", "mc_destroy", "mc_step",
            "mc_autotune", "mc_autotune_clear", "mc_footprint", "mc_server_create",
            "mc_server_destroy", "mc_server_submit", "mc_server_poll", "mc_server_fetch",
            "mc_server_release", "mc_server_wait", "mc_server_get_stats",
-           "mc_server_step_seconds", "mc_server_last_error"]
+           "mc_server_step_seconds", "mc_server_last_error", "mc_nlmc_create",
+           "mc_nlmc_destroy", "mc_nlmc_get_info", "mc_nlmc_get_system", "mc_nlmc_set_state",
+           "mc_nlmc_get_state", "mc_nlmc_step", "mc_nlmc_last_error"]

@@ -42,7 +42,7 @@ def test_binding_covers_header():
 STRUCTS = {"OmegaDesc": "mc_omega_desc", "ProblemDesc": "mc_problem_desc",
            "Options": "mc_options", "Report": "mc_report", "Info": "mc_info",
            "ServerConfig": "mc_server_config", "RequestInfo": "mc_request_info",
-           "ServerStats": "mc_server_stats"}
+           "ServerStats": "mc_server_stats", "NlmcInfo": "mc_nlmc_info"}
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
