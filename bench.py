@@ -15,6 +15,9 @@ Workloads (``--workload``):
   3D            the 3-D extension: two continua on a 256 x 256 x 256 grid of cubes (lognormal
                 matrix permeability per plane, 40 fracture planes), 20 layers, D-scheme,
                 FP64 block IC(0) PCG to 1e-10.
+  NLMC          the coarse-grid NLMC schemes on the paper's 2C / 3C problems (200 x 200 with
+                wells) on 20 x 20 and 40 x 40 coarse grids: basis set-up, coarse layers of
+                every scheme, e_H against the fine coupled solution.
   C5            serving: a seeded Poisson trace of simulation requests (mean 40/s, sides
                 64..2048, 10..500 layers each) replayed in real time against the server
                 (admission by device-memory footprint, continuous batching); a "step" there is
@@ -56,6 +59,7 @@ DEFAULTS = {
     "C5": dict(precond="mg", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
     "3D": dict(precond="bic0", precision="fp64", tol=1e-10, steps=20, coupled_steps=2,
                sample_every=2),
+    "NLMC": dict(precond="mg", precision="fp64", tol=1e-12, steps=50, coupled_steps=0),
 }
 
 # HBM bytes per dispatch of the grid PCG kernels, from two rocprofv3 counter passes
@@ -112,35 +116,85 @@ def grid_bytes_per_cell(kernel, precision, precond, has_t, dim=2):
     return 7 * w
 
 
+MG_COARSE, MG_TAIL = 256, 1024   # coarsest level size; levels of at most MG_TAIL cells: tail
+
+
+def mg_levels(nx, ny):
+    """Grid shapes of the V-cycle levels: 2 x 2 aggregation until at most MG_COARSE cells."""
+    out = [(nx, ny)]
+    while nx * ny > MG_COARSE:
+        nx, ny = (nx + 1) // 2, (ny + 1) // 2
+        out.append((nx, ny))
+    return out
+
+
+def vcycle_bytes(nx, ny, precision, has_t, nlev=None):
+    """Algorithmic bytes of one V-cycle's coarse kernels (all levels), per timing slot.
+
+    RS (restriction into coarse level l with its pre-smoothing, every level above the tail):
+        per cell of level l-1 read r, z_p (2 words) and the FP32 diagonal [, tx, ty] (4 B
+        each; level 0 without a conductance field: the diagonal only); per cell of level l
+        write r_c, z_p (2 words) and read its FP32 inverse pivots, tx, ty (12 B).
+    PC (correction + post-smoothing at level l, levels above the tail except the finest):
+        read z_p, r, e (one word per 2 x 2 cells), FP32 diagonal, pivots, tx, ty; write z:
+        3 words + w / 4 + 16 B per cell.
+    R  (restriction into the tail's first level): the finer level's r, z_p, FP32 diagonal,
+        tx, ty read, r_c written.
+    TAIL (levels of at most MG_TAIL cells in one workgroup): counted as R's output only;
+        it is latency-bound."""
+    w = 4 if precision == "mixed" else 8
+    lv = mg_levels(nx, ny)
+    if nlev is not None:               # a hierarchy truncated above the tail
+        lv = lv[:nlev + 1]
+    n = [a * b for a, b in lv]
+    rs = pc = r = 0.0
+    for l in range(1, len(lv)):
+        fine_coef = (12 if (l > 1 or has_t) else 4)
+        if n[l] > MG_TAIL:
+            rs += n[l - 1] * (2 * w + fine_coef) + n[l] * (2 * w + 12)
+            pc += n[l] * (3 * w + w / 4 + 16)
+        elif n[l - 1] > MG_TAIL or l == 1:
+            r += n[l - 1] * (2 * w + fine_coef) + n[l] * w
+    return {"RS": rs, "PC": pc, "R": r, "TAIL": 0.0}
+
+
 KERNEL_NAMES = {
     "A": "k_pcg_A<{tp},{pn},GRID> (p = z + beta p; q = A p; partial p.q)",
     "B": "k_pcg_B<{tp},{pn},GRID> (x += alpha p; r -= alpha q; z = M^-1 r; partial r.z, r.r)",
     "P": "k_mg_post<{tp},FINAL> (z = z_p + P e + M^-1 (r - A (z_p + P e)); partial r.z)",
+    "RS": "k_mg_restrict_smooth<{tp}> (all coarse levels: r_c = P^T (r - A z_p); z_p = M^-1 r_c)",
+    "PC": "k_mg_post_c<{tp}> (all coarse levels: z = z_p + P e + M^-1 (r - A (z_p + P e)))",
+    "TAIL": "k_mg_tail<{tp}> (levels of <= 1024 cells and the dense coarsest solve, one "
+            "workgroup)",
+    "R": "k_mg_restrict<{tp}> (restriction into the tail's first level)",
 }
 
 
 def roofline(kind_time, bytes_total, precision, precond, workload):
-    """Roofline objects of the grid operator (A), update (B) and (mg) finest post-smoothing
-    (P) kernels; the one with the most total time is the dominant kernel.
+    """Roofline objects of every timed grid kernel: the operator (A), update (B) and, with
+    the V-cycle, the finest post-smoothing (P) and the coarse kernels summed over their
+    levels (RS, PC, TAIL, R); the one with the most total time is the dominant kernel.
 
     kind_time[k] = (sampled, summed ms, issued, working sampled, working summed ms), where the
     working samples are those of at least a quarter of the mean sample (the others are
     launches whose systems had all converged; they return at once and move no bytes).
-    Average duration = mean working sample; working launches = issued x working share of
-    the samples; algorithmic bytes per launch = total over the timed layers (iterations x
-    cells x bytes per cell of every grid system) / working launches."""
+    Total time = mean working sample x working launches (issued x working share of the
+    samples); achieved = algorithmic bytes of the timed layers / total time; the average
+    launch duration is the mean working sample."""
     out = {}
     for k, (sampled, ms, issued, wn, wms) in kind_time.items():
         if not sampled or not wn:
             continue
         avg_s = wms / wn * 1e-3
         working = issued * wn / sampled
+        total_s = avg_s * working
         per_launch = bytes_total[k] / max(working, 1)
-        achieved = per_launch / avg_s / 1e9
+        achieved = bytes_total[k] / total_s / 1e9 if total_s > 0 else 0.0
         tp = "float" if precision == "mixed" else "double"
         pn = {"bic0": "BIC0", "mg": "BIC0", "jacobi": "JACOBI"}[precond]
         name = KERNEL_NAMES[k].format(tp=tp, pn=pn)
-        out[k] = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        bound = "latency" if k == "TAIL" else "hbm"
+        out[k] = {"bound": bound, "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                   "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                   "traffic": measured_traffic(workload, precond, k),
                   "traffic_unit": "bytes per launch",
@@ -148,7 +202,7 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
                   "avg_launch_us": avg_s * 1e6, "sampled_launches": sampled,
                   "sampled_working_launches": wn, "issued_launches": issued,
                   "all_samples_avg_us": ms / sampled * 1e3,
-                  "total_ms_est": ms / sampled * issued}
+                  "total_ms_est": total_s * 1e3}
     if not out:
         return None, None
     order = sorted(out, key=lambda k: -out[k]["total_ms_est"])
@@ -252,20 +306,36 @@ def read_profile(h, kernels):
 
 
 def kernels_of(precond):
-    """Timed grid kernels, in the library's profile order (0 = A, 1 = B, 2 = P)."""
-    return ("A", "B", "P") if precond == "mg" else ("A", "B")
+    """Timed grid kernels, in the library's profile order (0 = A, 1 = B, 2 = P, then the
+    V-cycle's coarse kernels 3 = RS, 4 = PC, 5 = TAIL, 6 = R)."""
+    return ("A", "B", "P", "RS", "PC", "TAIL", "R") if precond == "mg" else ("A", "B")
 
 
-def step_bytes(p, rep, precision, precond):
-    """Algorithmic bytes of the grid A, B (and mg: P) kernels for one layer of problem p."""
-    out = {"A": 0.0, "B": 0.0} if precond != "mg" else {"A": 0.0, "B": 0.0, "P": 0.0}
+def step_bytes(p, rep, precision, precond, nlev=None):
+    """Algorithmic bytes of every timed grid kernel for one layer of problem p (iterations
+    x cells x bytes per cell; the V-cycle's coarse kernels per cycle from the level
+    shapes; nlev[c]: coarse levels of continuum c's hierarchy)."""
+    out = {k: 0.0 for k in kernels_of(precond)}
     dim = getattr(p, "dim", 2)
     for c in range(p.n_omega):
         has_t = p.omega[c].k is not None or dim == 3
-        for k in out:
-            out[k] += rep["iters"][c] * p.ncell * grid_bytes_per_cell(k, precision, precond,
-                                                                      has_t, dim)
+        it = rep["iters"][c]
+        for k in ("A", "B", "P"):
+            if k in out:
+                out[k] += it * p.ncell * grid_bytes_per_cell(k, precision, precond, has_t, dim)
+        if precond == "mg":
+            vb = vcycle_bytes(p.nx, p.ny, precision, has_t, None if nlev is None else nlev[c])
+            for k, b in vb.items():
+                out[k] += it * b
     return out
+
+
+def solve_bytes(p, precision):
+    """Algorithmic bytes of a layer outside the PCG iterations, per grid continuum: the
+    right-hand side (previous layer, F, the other continua's previous layers read; b and
+    the warm start written: 5 FP64 words) and the initial residual (b, x, diag, tx, ty read,
+    r and the first preconditioned residual written: 7 FP64 words)."""
+    return p.n_omega * p.ncell * (5 + 7) * 8
 
 
 def options(args):
@@ -276,6 +346,72 @@ def options(args):
     else:
         o.update(tol=args.tol)
     return o
+
+
+def accuracy_after(g, workload, step, scheme):
+    """Accuracy on the stored oracle sample at layer `step`, or, if that layer is not stored,
+    at the next stored layer after stepping there (untimed, after the timed region)."""
+    acc = golden_states(g.get_state, workload, step, scheme)
+    if acc is not None:
+        return acc
+    path = os.path.join(ROOT, "tests", "golden", f"{workload.lower()}_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    later = sorted(int(k) for k in z[f"steps_{scheme}"] if int(k) > step)
+    if not later:
+        return None
+    g.step(later[0] - step)
+    acc = golden_states(g.get_state, workload, later[0], scheme)
+    if acc is not None:
+        acc["note"] = f"stepped untimed from layer {step} to the stored layer {later[0]}"
+    return acc
+
+
+def form_run(g, p, p0, args, change, scheme, profile=False):
+    """Another form of the same decoupled scheme on the same problem and GPU (options
+    changed by `change`): ms per layer over the timed layers, PCG iterations, accuracy (the
+    next stored layer) and, with profile, its dominant grid kernel."""
+    import torch
+    opt = dict(options(args))
+    opt.update(change)
+    precond = opt["precond"]
+    g.set_options(**opt)
+    g.set_states(p0)
+    g.step(2)                           # graphs of the new tables captured
+    g.set_states(p0)
+    if profile:
+        g.profile(True, every=args.sample_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, lat = [], []
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        rep = g.step(1)
+        lat.append(time.perf_counter() - ts)
+        iters.append(rep["iters"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    res = {"options": change, "value": p.dof() * args.steps / el, "unit": "cell-updates/s",
+           "steps": args.steps, "ms_per_step": el / args.steps * 1e3,
+           "latency_ms": {"p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+                          "p99": float(np.percentile(np.array(lat) * 1e3, 99))},
+           "pcg_iters_per_step": np.array(iters).mean(axis=0).tolist()}
+    if profile:
+        tot = {k: 0.0 for k in kernels_of(precond)}
+        nlev = list(g.info().mg_levels)
+        for it in iters:
+            sb = step_bytes(p, {"iters": it}, opt["precision"], precond, nlev)
+            for kk in tot:
+                tot[kk] += sb[kk]
+        prof = read_profile(g, kernels_of(precond))
+        g.profile(False)
+        roof, roof2 = roofline(prof, tot, opt["precision"], precond, args.workload)
+        res["roofline"] = roof
+        res["roofline_other_kernels"] = roof2
+    res["accuracy_vs_oracle"] = accuracy_after(g, args.workload, args.steps, scheme)
+    log(f"form {change}: {res['value']:.4g} cell-updates/s, {res['ms_per_step']:.3f} ms/step")
+    return res
 
 
 def run_single(args, out):
@@ -317,16 +453,25 @@ def run_single(args, out):
         # algorithmic bytes of the timed layers, from their iteration counts (kept out of the
         # timed loop)
         tot = {k: 0.0 for k in kernels_of(args.precond)}
+        nlev = list(g.info().mg_levels)
         for it in iters:
-            sb = step_bytes(p, {"iters": it}, args.precision, args.precond)
+            sb = step_bytes(p, {"iters": it}, args.precision, args.precond, nlev)
             for kk in tot:
                 tot[kk] += sb[kk]
         prof = read_profile(g, kernels_of(args.precond))
         g.profile(False)
         elapsed = t1 - t0
         value = dof * args.steps / elapsed
-        acc = golden_states(g.get_state, args.workload, args.steps, "D")
-        log(f"decoupled: {value:.4g} cell-updates/s, {elapsed / args.steps * 1e3:.3f} ms/step")
+        all_bytes = sum(tot.values()) + args.steps * solve_bytes(p, args.precision)
+        pcg_frac = all_bytes / elapsed / 1e9 / HBM_PEAK_GBS
+        log(f"decoupled: {value:.4g} cell-updates/s, {elapsed / args.steps * 1e3:.3f} ms/step, "
+            f"grid-kernel bytes / elapsed = {pcg_frac:.3f} of {HBM_PEAK_GBS / 1e3:.0f} TB/s")
+        acc = accuracy_after(g, args.workload, args.steps, "D")
+        extra = {}
+        if args.workload == "C2" and not args.no_coupled:
+            extra["fp64_tol_1e-12"] = form_run(g, p, p0, args, dict(tol=1e-12), "D")
+            extra["bic0"] = form_run(g, p, p0, args, dict(precond="bic0"), "D", profile=True)
+            g.set_options(**options(args))
 
         coupled = None
         if not args.no_coupled and args.coupled_steps > 0:
@@ -342,7 +487,7 @@ def run_single(args, out):
             torch.cuda.synchronize()
             c1 = time.perf_counter()
             cval = dof * args.coupled_steps / (c1 - c0)
-            cacc = golden_states(g.get_state, args.workload, args.coupled_steps, "coupled")
+            cacc = accuracy_after(g, args.workload, args.coupled_steps, "coupled")
             coupled = {"value": cval, "unit": "cell-updates/s", "steps": args.coupled_steps,
                        "ms_per_step": (c1 - c0) / args.coupled_steps * 1e3,
                        "pcg_iters_per_step": float(np.mean(citers)),
@@ -382,6 +527,12 @@ def run_single(args, out):
         "pcg_iters_per_step": {"mean": it.mean(axis=0).tolist(), "max": it.max(axis=0).tolist()},
         "accuracy_vs_oracle": acc, "coupled_fp64": coupled, "plain_fp64": plain,
         "roofline": roof, "roofline_other_kernels": roof2,
+        "pcg_roofline": {"what": "algorithmic bytes of every timed grid kernel (PCG iterations "
+                         "and V-cycle levels, plus each layer's right-hand side and initial "
+                         "residual) / elapsed time of the timed layers", "bytes": all_bytes,
+                         "achieved": all_bytes / elapsed / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": pcg_frac},
+        **extra,
     })
     if args.precision == "mixed":
         out["dtype"] = "f32+f64"
@@ -406,6 +557,7 @@ def run_batch(args, out):
             ta = time.time()
             mcdec.autotune(gs, iters=10)
             log(f"autotune {time.time() - ta:.1f}s")
+        nlevs = [list(g.info().mg_levels) for g in gs]
         b = mcdec.Batch(stream=stream.cuda_stream, **opt)
         for k in range(args.warmup):
             reps = b.step(gs, 1)
@@ -431,8 +583,8 @@ def run_batch(args, out):
         tot = {k: 0.0 for k in kernels_of(args.precond)}
         iters_max = []
         for reps in all_reps:
-            for p, r in zip(probs, reps):
-                sb = step_bytes(p, r, args.precision, args.precond)
+            for p, r, nl in zip(probs, reps, nlevs):
+                sb = step_bytes(p, r, args.precision, args.precond, nl)
                 for kk in tot:
                     tot[kk] += sb[kk]
             iters_max.append(max(max(r["iters"]) for r in reps))
@@ -447,20 +599,42 @@ def run_batch(args, out):
         plain = None
         coupled = None
         if not args.no_coupled:
-            # plain FP64 form: one problem at a time, FP64 PCG to the same tolerance
+            # plain FP64 forms of the same decoupled scheme, problems created beforehand and
+            # only the layers timed: (1) batched like the mixed form, (2) each problem alone
             ns = 2
+            pg = [mcdec.Problem(p, stream=stream.cuda_stream, scheme="D", precision="fp64",
+                                precond=args.precond, tol=args.tol) for p in probs]
+            pb = mcdec.Batch(stream=stream.cuda_stream, scheme="D", precision="fp64",
+                             precond=args.precond, tol=args.tol)
+            pb.step(pg, 1)                                   # graphs captured
+            for g, p in zip(pg, probs):
+                g.set_states(p.initial_state())
+            torch.cuda.synchronize()
             c0 = time.perf_counter()
-            for p in probs:
-                with mcdec.Problem(p, stream=stream.cuda_stream, scheme="D", precision="fp64",
-                                   precond=args.precond, tol=args.tol) as g:
-                    g.step(ns)
+            for k in range(ns):
+                pb.step(pg, 1)
+            torch.cuda.synchronize()
+            pbv = dof * ns / (time.perf_counter() - c0)
+            pb.close()
+            for g, p in zip(pg, probs):
+                g.set_states(p.initial_state())
+                g.step(1)                                    # graphs of the lone problem
+                g.set_states(p.initial_state())
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            for g in pg:
+                g.step(ns)
             torch.cuda.synchronize()
             pv = dof * ns / (time.perf_counter() - c0)
-            plain = {"value": pv, "unit": "cell-updates/s", "steps": ns,
-                     "form": "each problem alone, D-scheme FP64",
-                     "note": "includes per-problem setup (coefficients, factors)",
-                     "batched_mixed_over_plain": value / pv}
-            log(f"plain fp64 alone: {pv:.4g} cell-updates/s")
+            for g in pg:
+                g.close()
+            plain = {"value": pbv, "unit": "cell-updates/s", "steps": ns,
+                     "form": "batched like the mixed form, D-scheme FP64 PCG",
+                     "batched_mixed_over_plain": value / pbv,
+                     "alone": {"value": pv, "unit": "cell-updates/s", "steps": ns,
+                               "form": "each problem stepped alone, D-scheme FP64 PCG",
+                               "batched_mixed_over_alone_fp64": value / pv}}
+            log(f"plain fp64: batched {pbv:.4g}, alone {pv:.4g} cell-updates/s")
             # coupled FP64, batched
             cg = [mcdec.Problem(p, stream=stream.cuda_stream, scheme="coupled", precision="fp64",
                                 precond=args.precond, tol=args.tol) for p in probs]
@@ -507,22 +681,19 @@ def run_batch(args, out):
     })
 
 
-def run_serve(args, out):
-    """Replays the seeded Poisson trace in real time against the server and reports the
-    served throughput with per-step and per-request latency percentiles."""
+def serve_trace(args, trace, probs, steps, precision):
+    """Replays the trace in real time against a server of the given precision; returns
+    (request infos, server stats, server step durations, accuracy of the stored requests)."""
     import threading
-    import media
     from paper_2209_01158_amd import mcdec
-    trace = media.configs.c5_trace(count=args.count, rate=args.rate)
-    t = time.time()
-    probs = [media.configs.c5_problem(e) for e in trace]
-    steps = [e[4] for e in trace]
-    work = sum(p.dof() * n for p, n in zip(probs, steps))
-    log(f"workload C5: {len(trace)} requests over {trace[-1][0]:.1f}s, {work:.3g} cell-updates "
-        f"(built in {time.time() - t:.1f}s)")
     budget = int(args.hbm_budget_gib * 2**30)
-    srv = mcdec.Server(budget, max_resident=args.max_resident,
-                       autotune=args.autotune, **options(args))
+    opt = dict(options(args))
+    opt["precision"] = precision
+    if precision == "fp64":
+        opt.pop("outer_tol", None)
+        opt.pop("inner_tol", None)
+        opt["tol"] = args.tol
+    srv = mcdec.Server(budget, max_resident=args.max_resident, autotune=args.autotune, **opt)
     ids = [None] * len(trace)
     t0 = time.perf_counter()
 
@@ -541,28 +712,75 @@ def run_serve(args, out):
         st = srv.stats()
         if st["finished"] != last:
             last = st["finished"]
-            log(f"{time.perf_counter() - t0:.0f}s: finished {st['finished']}, resident "
-                f"{st['resident']}, queued {st['queued']}")
+            log(f"{precision} {time.perf_counter() - t0:.0f}s: finished {st['finished']}, "
+                f"resident {st['resident']}, queued {st['queued']}")
     while True:
         try:
             srv.wait(timeout=10)
             break
         except mcdec.McError:
             st = srv.stats()
-            log(f"{time.perf_counter() - t0:.0f}s: finished {st['finished']}, resident "
-                f"{st['resident']}, queued {st['queued']}")
+            log(f"{precision} {time.perf_counter() - t0:.0f}s: finished {st['finished']}, "
+                f"resident {st['resident']}, queued {st['queued']}")
     infos = [srv.poll(i) for i in ids]
     st = srv.stats()
     step_s = srv.step_seconds()
+    # accuracy: final states of the requests the oracle stored, against the oracle
+    acc = None
+    path = os.path.join(ROOT, "tests", "golden", "c5_oracle.npz")
+    if os.path.exists(path) and len(trace) > 0:
+        z = np.load(path, allow_pickle=False)
+        per = {}
+        for i in (int(v) for v in z["requests"]):
+            if i >= len(ids) or infos[i]["state"] != "done":
+                continue
+            got = np.concatenate(srv.fetch(ids[i]))
+            ref = np.concatenate([z[f"r{i}_c{a}"] for a in range(probs[i].n_cont)])
+            per[str(i)] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        if per:
+            acc = {"rel_l2_max": max(per.values()), "per_request": per,
+                   "reference": os.path.relpath(path, ROOT),
+                   "what": "final state of each stored request, every cell"}
     srv.close()
-    fin = [i for i in infos if i["state"] == "done"]
-    span = max(i["t_finish"] for i in fin) - min(i["t_submit"] for i in infos)
+    return infos, st, step_s, acc
+
+
+def run_serve(args, out):
+    """Replays the seeded Poisson trace in real time against the server and reports the
+    served throughput with per-step and per-request latency percentiles, the accuracy of
+    the requests the oracle stored, and the same trace served in plain FP64."""
+    import media
+    trace = media.configs.c5_trace(count=args.count, rate=args.rate)
+    t = time.time()
+    probs = [media.configs.c5_problem(e) for e in trace]
+    steps = [e[4] for e in trace]
+    work = sum(p.dof() * n for p, n in zip(probs, steps))
+    log(f"workload C5: {len(trace)} requests over {trace[-1][0]:.1f}s, {work:.3g} cell-updates "
+        f"(built in {time.time() - t:.1f}s)")
+    infos, st, step_s, acc = serve_trace(args, trace, probs, steps, args.precision)
+
+    def served_rate(infos):
+        fin = [i for i in infos if i["state"] == "done"]
+        span = max(i["t_finish"] for i in fin) - min(i["t_submit"] for i in infos)
+        served = sum(p.dof() * n for p, n, i in zip(probs, steps, infos) if i["state"] == "done")
+        return fin, span, served / span
+
+    fin, span, value = served_rate(infos)
     req_lat = np.array([i["t_finish"] - i["t_submit"] for i in fin])
     queue = np.array([i["t_admit"] - i["t_submit"] for i in fin])
     per_layer = np.array([(i["t_finish"] - i["t_admit"]) / i["n_steps"] for i in fin])
-    served = sum(p.dof() * n for p, n, i in zip(probs, steps, infos) if i["state"] == "done")
-    value = served / span
     log(f"served {len(fin)}/{len(infos)}: {value:.4g} cell-updates/s over {span:.1f}s")
+    plain = None
+    if not args.no_coupled and args.precision != "fp64":
+        pinfos, pst, pstep_s, pacc = serve_trace(args, trace, probs, steps, "fp64")
+        pfin, pspan, pvalue = served_rate(pinfos)
+        plain = {"value": pvalue, "unit": "cell-updates/s", "form": "same trace served with "
+                 "FP64 PCG (same server, same preconditioner)", "finished": len(pfin),
+                 "makespan_s": pspan, "accuracy_vs_oracle": pacc,
+                 "server_step_ms": {"p50": float(np.percentile(pstep_s, 50)) * 1e3,
+                                    "p99": float(np.percentile(pstep_s, 99)) * 1e3},
+                 "mixed_over_fp64": value / pvalue}
+        log(f"plain fp64 served: {pvalue:.4g} cell-updates/s")
     pct = lambda a, q: float(np.percentile(a, q))  # noqa: E731
     out.update({
         "value": value, "ms_per_step": float(np.mean(step_s)) * 1e3, "dtype": "f32+f64",
@@ -585,6 +803,93 @@ def run_serve(args, out):
         "served": {"finished": len(fin), "failed": int(st["failed"]),
                    "makespan_s": span, "busy_s": st["busy_seconds"],
                    "cell_updates_per_busy_s": st["cell_updates"] / max(st["busy_seconds"], 1e-9)},
+        "accuracy_vs_oracle": acc, "plain_fp64": plain,
+    })
+
+
+def run_nlmc(args, out):
+    """The coarse-grid NLMC schemes (Section 4) on the paper's 2C and 3C problems (200 x 200
+    fine grid with wells) on 20 x 20 and 40 x 40 coarse grids: GPU setup time (basis
+    functions and coarse operator), time of 50 coarse layers per scheme, and e_H against
+    the unit means of the fine coupled solution (computed on the GPU in FP64)."""
+    import torch
+    import media
+    from paper_2209_01158_amd import mcdec
+    rows = []
+    layers = args.layers
+    for kind in ("2C", "3C"):
+        p = media.paper_problem(kind)
+        nsteps = 50
+        with mcdec.Problem(p, scheme="coupled", precond="mg", tol=1e-12) as g:
+            g.step(nsteps)
+            fine = np.concatenate(g.get_states())
+        nc = p.nx * p.ny
+        meas = np.concatenate([np.full(nc * p.n_omega, p.h ** 2), p.aperture * p.flen])
+        for nco in (20, 40):
+            b = p.nx // nco
+            with mcdec.Problem(p, scheme="D", precond="mg") as g:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                nl = mcdec.Nlmc(g, b, b, layers)
+                t_setup = time.perf_counter() - t0
+                inf = nl.info()
+                # unit means of the fine coupled solution (units: continuum by continuum,
+                # coarse cells row-major; fracture units where a coarse cell hosts cells)
+                y, x = np.divmod(np.arange(nc), p.nx)
+                cof = (y // b) * nco + x // b
+                ref = []
+                for a in range(p.n_omega):
+                    v = fine[a * nc:(a + 1) * nc]
+                    ref.append(np.bincount(cof, v, nco * nco) / np.bincount(cof, None, nco * nco))
+                fco = cof[np.asarray(p.host)]
+                fm = meas[p.n_omega * nc:]
+                fv = fine[p.n_omega * nc:]
+                num = np.bincount(fco, fm * fv, nco * nco)
+                den = np.bincount(fco, fm, nco * nco)
+                ref.append((num / np.where(den > 0, den, 1))[den > 0])
+                ref = np.concatenate(ref)
+                res = {}
+                for scheme in ("coupled", "L", "D", "U"):
+                    nl.set_state()
+                    nl.step(scheme, 1)                  # first launch of each kernel
+                    nl.set_state()
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    nl.step(scheme, nsteps)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t1
+                    xs = nl.get_state()
+                    res[scheme] = {"seconds_50_layers": dt, "ms_per_layer": dt / nsteps * 1e3,
+                                   "e_H_percent": 100 * float(np.linalg.norm(xs - ref) /
+                                                              np.linalg.norm(ref))}
+                rows.append({"problem": kind, "coarse_grid": f"{nco}x{nco}",
+                             "oversampling_layers": layers, "n_units": inf.n_units,
+                             "units_per_continuum": list(inf.sizes)[:inf.n_cont],
+                             "largest_local_problem": inf.max_region_unknowns,
+                             "largest_band": inf.max_band,
+                             "setup_s": t_setup, "setup_gpu_ms": list(inf.setup_ms),
+                             "schemes": res})
+                log(f"NLMC {kind} {nco}x{nco}: N_H {inf.n_units}, setup {t_setup:.3f}s, "
+                    + ", ".join(f"{k} {v['ms_per_layer']:.3f} ms/layer e_H "
+                                f"{v['e_H_percent']:.3f}%" for k, v in res.items()))
+                nl.close()
+    d = [r for r in rows if r["problem"] == "2C" and r["coarse_grid"] == "20x20"][0]
+    t = d["schemes"]["D"]["seconds_50_layers"]
+    out.update({
+        "value": d["n_units"] * 50 / t, "unit": "coarse cell-updates/s",
+        "ms_per_step": t / 50 * 1e3, "steps": 50, "warmup": 1,
+        "config": {"workload": "NLMC coarse-grid D-scheme (Section 4) on the paper's 2C "
+                   f"problem, 200x200 fine grid, 20x20 coarse grid, {layers} oversampling "
+                   "layers (value); every problem, grid and scheme under `nlmc`"},
+        "nlmc": rows,
+        "paper_context": {"hardware": "MacBook Pro, 2.3 GHz quad-core Core i7, Python + "
+                          "PETSc CG+ILU", "2C_20x20_seconds": {"coupled": 0.174, "L": 0.035,
+                          "D": 0.034, "U": 0.041}, "2C_40x40_seconds": {"coupled": 1.12,
+                          "L": 0.135, "D": 0.14, "U": 0.151}, "3C_20x20_seconds": {
+                          "coupled": 0.557, "L": 0.048, "D": 0.049, "U": 0.055},
+                          "3C_40x40_seconds": {"coupled": 4.14, "L": 0.234, "D": 0.204,
+                          "U": 0.234}, "e_H_percent_2C_20x20": {"coupled": 0.01, "L": 0.06,
+                          "D": 0.08, "U": 0.01}},
     })
 
 
@@ -624,6 +929,8 @@ def main():
                     help="C5: device memory the resident requests may hold")
     ap.add_argument("--max-resident", type=int, default=0, help="C5: resident requests (0=256)")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--layers", type=int, default=2,
+                    help="NLMC: oversampling layers of the regions K_i^+")
     ap.add_argument("--sample-every", type=int, default=None,
                     help="time one grid PCG iteration in this many (HIP events; default 32; "
                          "4 for C3 and C4, whose launches serve systems of different "
@@ -658,13 +965,15 @@ def main():
            "data": "synthetic (seeded generators of the workload recipe)"}
     if args.count is None:
         args.count = 400 if args.workload == "C5" else 256
-    if args.workload == "C4":
+    if args.workload == "NLMC":
+        run_nlmc(args, out)
+    elif args.workload == "C4":
         run_batch(args, out)
     elif args.workload == "C5":
         run_serve(args, out)
     else:
         run_single(args, out)
-    if not args.no_cpu and args.workload != "C5":
+    if not args.no_cpu and args.workload not in ("C5", "NLMC"):
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(out), flush=True)

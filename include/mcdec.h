@@ -271,12 +271,15 @@ const char *mc_last_error(const mc_problem *p);
    launches of the grid PCG kernels time the kernel execution itself.  which: 0 = grid
    operator kernel (p = z + beta p, q = A p), 1 = grid update kernel (x, r, z = M^-1 r;
    under MC_MG its sweep is the finest pre-smoothing), 2 = (MC_MG) the finest level's
-   correction and post-smoothing, which writes z.  enable >= 1 starts recording and clears
+   correction and post-smoothing, which writes z; the V-cycle's coarse kernels over all its
+   levels (MC_MG): 3 = restriction into a coarse level with its pre-smoothing, 4 = coarse
+   correction with post-smoothing, 5 = the small-level tail (one workgroup), 6 = restriction
+   into the tail's first level (a sampled V-cycle is timed whole).  enable >= 1 starts recording and clears
    the totals, sampling the kernels of one PCG iteration in `enable` (1 = every iteration;
    each sampled launch costs the stream a few microseconds); 0 stops.  Sampled iterations
    are launched one by one, the others still replayed from captured graphs.
    mc_profile_read returns the number of sampled launches and their summed duration, and
-   the number of launches issued while timing was on (sampled or not); which outside 0..2
+   the number of launches issued while timing was on (sampled or not); which outside 0..6
    gives MC_EINVAL. */
 mc_status mc_profile(mc_problem *p, int32_t enable);
 mc_status mc_profile_read(mc_problem *p, int32_t which, int64_t *sampled, double *sampled_ms,

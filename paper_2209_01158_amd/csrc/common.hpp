@@ -22,6 +22,8 @@
 #define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
 #define MC_MG_COARSE 256       // multigrid levels stop at this many cells (dense inverse there)
 #define MC_MG_TAIL 1024        // levels of at most this many cells run in one workgroup
+#define MC_MG_DOMINANCE 8.0    // a V-cycle stops at a level whose row sums reach this many
+                               // times its face conductances (summed over the level)
 #define MC_TAIL_THREADS 1024   // threads of that workgroup
 
 enum { PART_GRID = 0, PART_GRAPH = 1 };

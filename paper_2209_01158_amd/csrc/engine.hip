@@ -257,8 +257,10 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
         throw Error{MC_EDEVICE, "multigrid level without a finer level"};
       const PartD& f = parts[q.mg_prev];
       if (in_tail(q) && in_tail(f)) continue;          // run inside its tail's workgroup
-      if (!in_tail(q) && q.mg_next < 0)
-        throw Error{MC_EDEVICE, "coarsest multigrid level outside the small-level tail"};
+      // the last level is either the coarsest (dense inverse, solved in the tail) or a
+      // truncated level above the tail (smoothed twice, no coarser correction)
+      if (q.mg_next < 0 && in_tail(q) != (q.mg_inv != nullptr))
+        throw Error{MC_EDEVICE, "last multigrid level does not match the small-level tail"};
       tail_start = in_tail(q);
       if (tail_start) {                                // restriction into l: finer tiles
         const int ntf = (int)(cdiv(f.nx, MC_TX) * cdiv(f.ny, MC_TY));
@@ -372,11 +374,15 @@ struct Exec {
   bool prof = false;
   struct Ev { hipEvent_t a, b; int which; };
   std::vector<Ev> ev_free, ev_pending;
-  // [0] grid operator, [1] grid update, [2] finest V-cycle post-smoothing kernel
-  long prof_launch[3] = {0, 0, 0};
-  double prof_ms[3] = {0, 0, 0};
-  long prof_count[3] = {0, 0, 0};
-  std::vector<float> prof_samples[3];   // every sampled duration (ms)
+  // [0] grid operator, [1] grid update, [2] finest V-cycle post-smoothing kernel, and the
+  // V-cycle's coarse kernels over all levels: [3] restriction with pre-smoothing, [4]
+  // coarse correction with post-smoothing, [5] small-level tail, [6] restriction into the
+  // tail.  A V-cycle is timed whole when its finest post-smoothing is due for a sample.
+  static constexpr int NPROF = 7;
+  long prof_launch[NPROF] = {0, 0, 0, 0, 0, 0, 0};
+  double prof_ms[NPROF] = {0, 0, 0, 0, 0, 0, 0};
+  long prof_count[NPROF] = {0, 0, 0, 0, 0, 0, 0};
+  std::vector<float> prof_samples[NPROF];   // every sampled duration (ms)
   int prof_every = 8;
   // host threads that drive the extra groups of a solve (kept for the problem's lifetime)
   struct Worker {
@@ -787,8 +793,8 @@ static void add_mg_levels(mc_problem* P, std::vector<PartD>& parts, int i, bool 
     q.mg_level = (int)l + 1;
     q.mg_prev = base + prev;
     q.mg_next = -1;
-    q.mg_inv = L.inv;
-    q.mg_inv32 = L.inv32;
+    q.mg_inv = L.coarsest ? L.inv : nullptr;
+    q.mg_inv32 = L.coarsest ? L.inv32 : nullptr;
     q.mg_r = fp32 ? (void*)L.r32 : (void*)L.r;
     q.mg_zp = fp32 ? (void*)L.zp32 : (void*)L.zp;
     q.mg_z = fp32 ? (void*)L.z32 : (void*)L.z;
@@ -938,7 +944,21 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
   int nx = P->d.nx, ny = P->d.ny;
   const double *fd = C.diag, *ftx = C.tx, *fty = C.ty;
   size_t l = 0;
+  // The hierarchy stops early at a level above the small-level tail whose operator is
+  // strongly diagonally dominant: summed over its cells, the row sums (storage over tau,
+  // transfer) at least MC_MG_DOMINANCE times the face conductances.  Block IC(0) nearly
+  // solves such a level, so it is smoothed twice instead of corrected from coarser levels
+  // (MCDEC_MG_DOMINANCE overrides the ratio, 0 = never stop early; MCDEC_MG_LEVELS caps the
+  // number of coarse levels).
+  const long tail_n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
+  const int max_levels = std::max(1, env_int("MCDEC_MG_LEVELS", 1 << 20));
+  const char* dom_env = std::getenv("MCDEC_MG_DOMINANCE");
+  const double dominance = dom_env ? std::atof(dom_env) : MC_MG_DOMINANCE;
+  constexpr int dom_blocks = 128;
+  double* dom_part = nullptr;
+  bool stop = false;
   while ((long)nx * ny > MC_MG_COARSE) {
+    if (((int)l >= max_levels || stop) && (long)nx * ny > tail_n) break;
     const int cnx = (nx + 1) / 2, cny = (ny + 1) / 2;
     if (C.mg.size() <= l) C.mg.emplace_back();
     MgLevel& L = C.mg[l];
@@ -946,7 +966,8 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
     L.ny = cny;
     L.n = (long)cnx * cny;
     L.tiles = (int)(cdiv(cnx, MC_TX) * cdiv(cny, MC_TY));
-    L.coarsest = L.n <= MC_MG_COARSE;
+    L.coarsest = L.n <= MC_MG_COARSE;   // a level the hierarchy stops at above the tail is
+                                         // not: it gets IC(0) factors for its smoothing
     if (!L.diag) {
       L.diag = M.alloc<double>(L.n);
       L.tx = M.alloc<double>(L.n);
@@ -993,6 +1014,22 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
     cv(L.tx, L.tx32, L.n);
     cv(L.ty, L.ty32, L.n);
     HIPCHK(hipGetLastError());
+    if (dominance > 0 && L.n > tail_n) {
+      if (!dom_part) dom_part = M.alloc<double>(2 * dom_blocks);
+      hipLaunchKernelGGL(k_mg_dominance, dim3(dom_blocks), dim3(256), 0, s, cnx, cny, L.diag,
+                         L.tx, L.ty, dom_part);
+      HIPCHK(hipGetLastError());
+      std::vector<double> h(2 * dom_blocks);
+      HIPCHK(hipMemcpyAsync(h.data(), dom_part, h.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double rs = 0.0, fs = 0.0;
+      for (int b = 0; b < dom_blocks; ++b) {
+        rs += h[2 * b];
+        fs += h[2 * b + 1];
+      }
+      stop = rs >= dominance * fs;
+    }
     fd = L.diag;
     ftx = L.tx;
     fty = L.ty;
@@ -1375,27 +1412,55 @@ static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool fi
                           Exec* X = nullptr) {
   const int L = (int)Tb.mg.size();
   if (L == 0 || Tb.mg[0][3].n == 0) return;
-  auto go = [&](auto kern, const Table::List& li) {
-    if (li.n) hipLaunchKernelGGL(kern, dim3(li.n), dim3(MC_BLOCK), 0, s, Tb.parts, li.t, sys);
+  // X: count the launches for kernel timing, and time them all when the finest
+  // post-smoothing of this cycle is due for a sample
+  const bool timed = X && X->prof && final && (X->prof_count[2] % X->prof_every) == 0;
+  auto go = [&](auto kern, const Table::List& li, int slot, int threads) {
+    if (!li.n) return;
+    if (X && X->prof) X->prof_count[slot] += 1;
+    if (timed) {
+      Exec::Ev e = prof_take(*X, slot);
+      hipExtLaunchKernelGGL(kern, dim3(li.n), dim3(threads), 0, s, e.a, e.b, 0, Tb.parts, li.t,
+                            sys);
+      X->ev_pending.push_back(e);
+    } else {
+      hipLaunchKernelGGL(kern, dim3(li.n), dim3(threads), 0, s, Tb.parts, li.t, sys);
+    }
   };
   for (int l = 1; l < L; ++l) {
-    go(k_mg_restrict_smooth<T>, Tb.mg[l][1]);
-    go(k_mg_restrict<T>, Tb.mg[l][0]);
-    if (Tb.mg[l][2].n)
-      hipLaunchKernelGGL(k_mg_tail<T>, dim3(Tb.mg[l][2].n), dim3(MC_TAIL_THREADS), 0, s,
-                         Tb.parts, Tb.mg[l][2].t, sys);
+    go(k_mg_restrict_smooth<T>, Tb.mg[l][1], 3, MC_BLOCK);
+    go(k_mg_restrict<T>, Tb.mg[l][0], 6, MC_BLOCK);
+    go(k_mg_tail<T>, Tb.mg[l][2], 5, MC_TAIL_THREADS);
   }
-  for (int l = L - 2; l >= 1; --l) go(k_mg_post_c<T>, Tb.mg[l][3]);
+  for (int l = L - 1; l >= 1; --l) go(k_mg_post_c<T>, Tb.mg[l][3], 4, MC_BLOCK);
   if (!final) {
-    go(k_mg_post<T, false>, Tb.mg[0][3]);
-  } else if (X && X->prof && (X->prof_count[2]++ % X->prof_every) == 0) {
-    Exec::Ev e = prof_take(*X, 2);   // timed like the PCG kernels
-    hipExtLaunchKernelGGL(k_mg_post<T, true>, dim3(Tb.mg[0][3].n), dim3(MC_BLOCK), 0, s, e.a,
-                          e.b, 0, Tb.parts, Tb.mg[0][3].t, sys);
-    X->ev_pending.push_back(e);
+    hipLaunchKernelGGL((k_mg_post<T, false>), dim3(Tb.mg[0][3].n), dim3(MC_BLOCK), 0, s,
+                       Tb.parts, Tb.mg[0][3].t, sys);
   } else {
-    go(k_mg_post<T, true>, Tb.mg[0][3]);
+    if (X && X->prof) X->prof_count[2] += 1;
+    if (timed) {
+      Exec::Ev e = prof_take(*X, 2);   // timed like the PCG kernels
+      hipExtLaunchKernelGGL((k_mg_post<T, true>), dim3(Tb.mg[0][3].n), dim3(MC_BLOCK), 0, s,
+                            e.a, e.b, 0, Tb.parts, Tb.mg[0][3].t, sys);
+      X->ev_pending.push_back(e);
+    } else {
+      hipLaunchKernelGGL((k_mg_post<T, true>), dim3(Tb.mg[0][3].n), dim3(MC_BLOCK), 0, s,
+                         Tb.parts, Tb.mg[0][3].t, sys);
+    }
   }
+}
+
+// Launches of V-cycle kernel timing slot `slot` (3..6) in one cycle over table Tb.
+static int vcycle_launches(const Table& Tb, int slot) {
+  const int L = (int)Tb.mg.size();
+  int n = 0;
+  for (int l = 1; l < L; ++l) {
+    if (slot == 3 && Tb.mg[l][1].n) ++n;
+    if (slot == 6 && Tb.mg[l][0].n) ++n;
+    if (slot == 5 && Tb.mg[l][2].n) ++n;
+    if (slot == 4 && Tb.mg[l][3].n) ++n;
+  }
+  return n;
 }
 
 // One PCG iteration over the group's tiles: operator kernels, then update kernels.
@@ -1484,6 +1549,8 @@ static void launch_chunk(Exec& X, Group& G, int K) {
     replay(m);
     for (int w = 0; w < 3; ++w)
       if (w < 2 || post) X.prof_count[w] += m;
+    if (post)
+      for (int w = 3; w < Exec::NPROF; ++w) X.prof_count[w] += (long)m * vcycle_launches(*G.T, w);
     K -= m;
   }
 }
@@ -2196,8 +2263,9 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
       if (lx * ly > MC_MG_COARSE) {
         A(8 * n);                 // pre-smoothed z of the finest level
         if (mixed) A(4 * n);
+        A(8 * 2 * 128);           // partial sums of the levels' dominance test
       }
-      while (lx * ly > MC_MG_COARSE) {
+      while (lx * ly > MC_MG_COARSE) {   // (a hierarchy that stops early holds less)
         lx = (lx + 1) / 2;
         ly = (ly + 1) / 2;
         const int64_t m = lx * ly;
@@ -2806,7 +2874,7 @@ static mc_status exec_profile(mc::Exec& X, int32_t enable) {
   mc::prof_harvest(X);
   X.prof = enable != 0;
   if (enable) {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < mc::Exec::NPROF; ++k) {
       X.prof_launch[k] = 0;
       X.prof_ms[k] = 0;
       X.prof_count[k] = 0;
@@ -2819,7 +2887,7 @@ static mc_status exec_profile(mc::Exec& X, int32_t enable) {
 
 static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* sampled,
                                    double* sampled_ms, int64_t* issued) {
-  if (which < 0 || which > 2) return MC_EINVAL;
+  if (which < 0 || which >= mc::Exec::NPROF) return MC_EINVAL;
   HIPCHK(hipStreamSynchronize(X.stream));
   mc::prof_harvest(X);
   if (sampled) *sampled = X.prof_launch[which];
@@ -2830,7 +2898,7 @@ static mc_status exec_profile_read(mc::Exec& X, int32_t which, int64_t* sampled,
 
 static mc_status exec_profile_read_above(mc::Exec& X, int32_t which, double min_ms,
                                         int64_t* sampled, double* sampled_ms) {
-  if (which < 0 || which > 2) return MC_EINVAL;
+  if (which < 0 || which >= mc::Exec::NPROF) return MC_EINVAL;
   HIPCHK(hipStreamSynchronize(X.stream));
   mc::prof_harvest(X);
   int64_t n = 0;
@@ -2854,7 +2922,7 @@ mc_status mc_profile(mc_problem* P, int32_t enable) {
 
 mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* sampled, double* sampled_ms,
                           int64_t* issued) {
-  if (!P || which < 0 || which > 2) return MC_EINVAL;
+  if (!P || which < 0 || which >= mc::Exec::NPROF) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read(P->X, which, sampled, sampled_ms, issued);
   ABI_END(P)
@@ -2862,7 +2930,7 @@ mc_status mc_profile_read(mc_problem* P, int32_t which, int64_t* sampled, double
 
 mc_status mc_profile_read_above(mc_problem* P, int32_t which, double min_ms, int64_t* sampled,
                                 double* sampled_ms) {
-  if (!P || which < 0 || which > 2) return MC_EINVAL;
+  if (!P || which < 0 || which >= mc::Exec::NPROF) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read_above(P->X, which, min_ms, sampled, sampled_ms);
   ABI_END(P)
@@ -2967,7 +3035,7 @@ mc_status mc_batch_profile(mc_batch* B, int32_t enable) {
 
 mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* sampled,
                                 double* sampled_ms, int64_t* issued) {
-  if (!B || which < 0 || which > 2) return MC_EINVAL;
+  if (!B || which < 0 || which >= mc::Exec::NPROF) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read(B->X, which, sampled, sampled_ms, issued);
   ABI_END(B)
@@ -2975,7 +3043,7 @@ mc_status mc_batch_profile_read(mc_batch* B, int32_t which, int64_t* sampled,
 
 mc_status mc_batch_profile_read_above(mc_batch* B, int32_t which, double min_ms,
                                       int64_t* sampled, double* sampled_ms) {
-  if (!B || which < 0 || which > 2) return MC_EINVAL;
+  if (!B || which < 0 || which >= mc::Exec::NPROF) return MC_EINVAL;
   ABI_BEGIN
   return exec_profile_read_above(B->X, which, min_ms, sampled, sampled_ms);
   ABI_END(B)

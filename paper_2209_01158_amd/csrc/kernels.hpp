@@ -1503,6 +1503,42 @@ __global__ void k_mg_dense_fill(const double* __restrict__ diag, const double* _
   }
 }
 
+// Diagonal dominance of a level operator: per workgroup, the sums over its cells of the
+// row sum (diagonal minus the face conductances: storage, transfer and Dirichlet terms) and
+// of the face conductances -> part[2 b], part[2 b + 1] (grid-stride loop, fixed order).
+__global__ void __launch_bounds__(256) k_mg_dominance(int nx, int ny,
+                                                      const double* __restrict__ diag,
+                                                      const double* __restrict__ tx,
+                                                      const double* __restrict__ ty,
+                                                      double* __restrict__ part) {
+  __shared__ double sh[2][256];
+  const long n = (long)nx * ny;
+  double rs = 0.0, fs = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx), y = (int)(i / nx);
+    double f = tx[i] + ty[i];
+    if (x > 0) f += tx[i - 1];
+    if (y > 0) f += ty[i - nx];
+    rs += diag[i] - f;
+    fs += f;
+  }
+  sh[0][threadIdx.x] = rs;
+  sh[1][threadIdx.x] = fs;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + o];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0];
+    part[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+
 __global__ void k_fill0(double* __restrict__ a, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = 0.0;
@@ -1631,8 +1667,10 @@ __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const
   const int x0 = B.cx - lane;
   const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
   auto rowy = [&](int j) { return min(max(B.y0 + j, 0), ny - 1); };
+  // the last level of a truncated hierarchy has no coarser correction (e = 0)
   auto zfull = [&](int y, int x) {
-    return zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)];
+    return e ? zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)]
+             : zp[(long)y * nx + x];
   };
   T zo[R + 2];
 #pragma unroll

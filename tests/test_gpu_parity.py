@@ -5,6 +5,7 @@ difference is summation order and FMA contraction); FP64 solves and trajectories
 relative L2 error <= 1e-10; mixed-precision refinement to <= 1e-8.
 """
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 import media
@@ -268,6 +269,9 @@ MG_CASES = {
     # 300 x 270 -> 150 x 135 -> 75 x 68 -> 38 x 34 -> 19 x 17 -> 10 x 9 (dense): ragged
     # tiles and odd sizes on every level
     "rect300x270": lambda: media.rect_problem(300, 270, seed=5),
+    # diffusion-dominated (tau = 1e4): the full hierarchy down to the dense coarsest level
+    # (the storage-dominated cases above stop after their first coarse level)
+    "deep300x270": lambda: media.rect_problem(300, 270, seed=5, tau=1e4),
     "strip1x700": lambda: media.rect_problem(1, 700, seed=6),      # 700 -> 350 -> 175
     "ragged200": CASES["ragged200"],
     "three70": CASES["three70"],
@@ -291,8 +295,21 @@ def test_mg_apply(name):
             z = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
             g.apply_precond(a, T(r), z)
             if a < p.n_omega:
-                lev = precond.vcycle_setup(K, p.nx, p.ny)
-                assert inf.mg_levels[a] == len(lev) - 1
+                full = precond.vcycle_setup(K, p.nx, p.ny)
+                # the hierarchy stops at the first level above the 1024-cell tail whose row
+                # sums reach 8 times its face conductances (summed over the level)
+                want = len(full) - 1
+                for l in range(1, len(full)):
+                    Kl = full[l]["K"]
+                    if Kl.shape[0] <= 1024:
+                        break
+                    rs = float(np.asarray(Kl.sum(axis=1)).sum())
+                    fs = float(-(Kl - sp.diags(Kl.diagonal())).sum())
+                    if rs >= 8.0 * fs:
+                        want = l
+                        break
+                assert inf.mg_levels[a] == want, (inf.mg_levels[a], want)
+                lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=want)
                 ref = precond.vcycle_apply(lev, r)
                 tol = 2e-5
             else:
@@ -304,7 +321,7 @@ def test_mg_apply(name):
 
 
 @pytest.mark.parametrize("scheme", ["D", "coupled", "U"])
-@pytest.mark.parametrize("name", ["rect300x270", "ragged200", "three70"])
+@pytest.mark.parametrize("name", ["rect300x270", "deep300x270", "ragged200", "three70"])
 def test_trajectory_mg(name, scheme):
     print(f"\n[mg trajectory {name} {scheme}]", flush=True)
     p = MG_CASES[name]()
@@ -317,7 +334,7 @@ def test_trajectory_mg(name, scheme):
             assert err < 1e-10, (name, scheme, n, err, rep)
 
 
-@pytest.mark.parametrize("name", ["rect300x270", "three70", "strip1x700"])
+@pytest.mark.parametrize("name", ["rect300x270", "deep300x270", "three70", "strip1x700"])
 def test_mixed_precision_mg(name):
     print(f"\n[mg mixed {name}]", flush=True)
     p = MG_CASES[name]()
@@ -354,19 +371,29 @@ def test_kernel_timing_samples_and_keeps_results():
     with mcdec.Problem(p, precond="mg", tol=1e-12) as g:
         g.profile(True, every=4)
         rep = g.step(2)
-        reads = [g.profile_read(w) for w in range(3)]
+        reads = [g.profile_read(w) for w in range(7)]
+        levels = g.info().mg_levels[0]
         g.profile(False)
         got = g.get_states()
-    print(rep, reads)
+    print(rep, reads, levels)
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
-    for sampled, ms, issued in reads:
+    for sampled, ms, issued in reads[:3]:
         assert sampled >= 1 and ms > 0 and issued >= sum(rep["iters"][:1])
         assert sampled <= issued // 4 + 2
+    # the V-cycle's coarse kernels (this storage-dominated problem keeps one coarse level,
+    # restricted into with pre-smoothing and post-smoothed twice, no tail): one launch of
+    # each per cycle, a sampled cycle timed whole
+    assert levels == 1
+    cycles = reads[2][2]
+    for w in (3, 4):
+        sampled, ms, issued = reads[w]
+        assert issued == cycles and sampled == reads[2][0] and ms > 0
+    assert reads[5][2] == 0 and reads[6][2] == 0
     with pytest.raises(mcdec.McError):
         g2 = mcdec.Problem(p, precond="mg")
         try:
-            g2.profile_read(3)
+            g2.profile_read(7)
         finally:
             g2.close()
 

@@ -670,6 +670,33 @@ def test_two_grid_cycle_error_propagation():
     assert ev.min() > 0 and ev.max() < 2
 
 
+def test_truncated_cycle_error_propagation():
+    """A cycle truncated after its first coarse level (36 x 32 -> 18 x 16, whose own coarser
+    levels are dropped): the coarse solve Kc^-1 of the two-grid cycle becomes two sweeps of
+    the coarse smoother, (I - (I - Mc^-1 Kc)^2) Kc^-1, so V = (I - E) K^-1 with
+    E = S (I - P (I - Sc^2) Kc^-1 P^T K) S; V stays symmetric positive definite."""
+    p = media.rect_problem(36, 32, seed=4)
+    K = schemes.continuum_matrix(fv.assemble(p), p.tau, 0).toarray()
+    n = K.shape[0]
+    lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=1)
+    assert len(lev) == 2 and lev[1].get("smooth2") and "inv" not in lev[1]
+    Minv = _dense_inverse_of(lambda e: precond.block_precond_apply(lev[0]["facs"], e), n)
+    P = lev[0]["P"].toarray()
+    Kc = precond.coarse_operator(sp.csr_matrix(K), sp.csr_matrix(P)).toarray()
+    nc = Kc.shape[0]
+    Mc = _dense_inverse_of(lambda e: precond.block_precond_apply(lev[1]["facs"], e), nc)
+    Sc = np.eye(nc) - Mc @ Kc
+    coarse = (np.eye(nc) - Sc @ Sc) @ np.linalg.inv(Kc)
+    I = np.eye(n)
+    S = I - Minv @ K
+    E = S @ (I - P @ coarse @ P.T @ K) @ S
+    Vref = (I - E) @ np.linalg.inv(K)
+    V = _dense_inverse_of(lambda e: precond.vcycle_apply(lev, e), n)
+    assert np.abs(V - Vref).max() < 1e-10 * np.abs(Vref).max()
+    assert np.abs(V - V.T).max() < 1e-12 * np.abs(V).max()
+    assert np.linalg.eigvalsh(0.5 * (V + V.T)).min() > 0
+
+
 def test_three_level_cycle_symmetric_positive():
     """Three levels (36 x 32 -> 18 x 16 -> 9 x 8): (r1, V r2) = (r2, V r1), (r, V r) > 0."""
     p = media.rect_problem(36, 32, seed=4)
