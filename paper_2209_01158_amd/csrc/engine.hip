@@ -2197,7 +2197,12 @@ static void autotune(mc_problem* const* probs, int n, int iters) {
     }
     clear_tables(P);
   }
-  for (int i = 0; i < n; ++i) refresh_tilings(probs[i]);
+  // the timing runs wrote PCG iterates into the next-state buffers, which a following layer
+  // would otherwise take for the layer before the current one (its extrapolated warm start)
+  for (int i = 0; i < n; ++i) {
+    probs[i]->hist = 0;
+    refresh_tilings(probs[i]);
+  }
 }
 
 // Device bytes mc_create_problem allocates for a descriptor under options o (the sizes of

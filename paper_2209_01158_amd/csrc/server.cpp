@@ -1,9 +1,12 @@
-// Serving loop: simulation requests of different sizes arrive at any time; a worker thread
-// admits them by device-memory footprint (Scheduler), keeps their state resident on the
-// device, and advances every resident request by one time layer per batched step (all of
-// their continua in the same PCG launches through the batch executor).  Finished requests
-// hand their final state to host memory and free their device memory, which admits the
-// next ones.  Only the library's C ABI is used here.
+// Serving loop: simulation requests of different sizes arrive at any time; a stepping
+// thread admits them by device-memory footprint (Scheduler), keeps their state resident on
+// the device, and advances every ready resident request by one time layer per batched step
+// (all of their continua in the same PCG launches through the batch executor).  A setup
+// thread creates each admitted problem (device allocation, coefficients, factors, optional
+// autotuning) on the problem's own stream, so admission never stalls the resident requests'
+// steps; a request joins the batch once its problem is ready.  Finished requests hand their
+// final state to host memory and free their device memory, which admits the next ones.
+// Only the library's C ABI is used here.
 #include <stdint.h>
 
 #include <chrono>
@@ -81,9 +84,12 @@ struct mc_server {
   std::unique_ptr<mc::Scheduler> sched;
   std::map<uint64_t, Request> reqs;
   std::mutex mu;
-  std::condition_variable cv_work, cv_idle;
-  std::thread worker;
+  std::condition_variable cv_work, cv_idle, cv_setup;
+  std::thread worker, setup;
   bool stop = false;
+  std::vector<uint64_t> pending;   // admitted, problem not created yet (setup thread's queue)
+  int64_t setting_up = 0;          // problems being created right now
+  uint64_t events = 0;             // submissions and finished setups (wakes the stepper)
   uint64_t next_id = 1;
   std::chrono::steady_clock::time_point t0;
   // statistics (under mu)
@@ -97,56 +103,80 @@ static thread_local std::string g_server_error;
 
 namespace {
 
-void run_worker(mc_server* S) {
-  std::vector<uint64_t> ids;
-  std::vector<mc_problem*> probs;
-  std::vector<mc_report> reps;
+// Creates the admitted problems, oldest admission first; a failed creation fails the
+// request and frees its bytes.
+void run_setup(mc_server* S) {
   for (;;) {
-    std::vector<uint64_t> admitted;
+    uint64_t id;
+    Request* R;
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      admitted = S->sched->admit(now_since(S->t0));
-      if (admitted.empty() && S->sched->n_resident() == 0) {
-        S->cv_idle.notify_all();
-        S->cv_work.wait(lk, [&] { return S->stop || S->sched->queued() > 0; });
-        if (S->stop) return;
-        continue;
-      }
+      S->cv_setup.wait(lk, [&] { return S->stop || !S->pending.empty(); });
       if (S->stop) return;
+      id = S->pending.front();
+      S->pending.erase(S->pending.begin());
+      S->setting_up += 1;
+      R = &S->reqs[id];
     }
-    // create the admitted problems (device allocation and setup) outside the lock
-    for (uint64_t id : admitted) {
-      Request* R;
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        R = &S->reqs[id];
-      }
-      mc_problem* P = nullptr;
-      mc_status st = mc_create_problem(&R->desc->d, &S->opt, &P);
-      if (st == MC_OK && S->cfg.autotune) st = mc_autotune(&P, 1, 10);
+    mc_problem* P = nullptr;
+    mc_status st = mc_create_problem(&R->desc->d, &S->opt, &P);
+    if (st == MC_OK && S->cfg.autotune) st = mc_autotune(&P, 1, 10);
+    std::string why = st != MC_OK ? std::string(P ? mc_last_error(P) : mc_last_error(nullptr))
+                                  : std::string();
+    mc_info inf;
+    if (st == MC_OK) mc_get_info(P, &inf);
+    {
       std::lock_guard<std::mutex> lk(S->mu);
       if (st != MC_OK) {
         if (P) mc_destroy(P);
         S->sched->fail(id, st, now_since(S->t0));
         S->failed += 1;
-        S->worker_err = mc_last_error(nullptr);
+        S->worker_err = why;
       } else {
-        R->prob = P;
-        mc_info inf;
-        mc_get_info(P, &inf);
         R->ncont = inf.n_cont;
         for (int c = 0; c < inf.n_cont; ++c) R->dof += inf.sizes[c];
+        R->prob = P;
       }
       R->desc.reset();
+      S->setting_up -= 1;
+      S->events += 1;
     }
-    // one layer of every resident request
+    S->cv_work.notify_all();
+    S->cv_idle.notify_all();
+  }
+}
+
+void run_worker(mc_server* S) {
+  std::vector<uint64_t> ids;
+  std::vector<mc_problem*> probs;
+  std::vector<mc_report> reps;
+  for (;;) {
     {
-      std::lock_guard<std::mutex> lk(S->mu);
-      ids = S->sched->resident();
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->stop) return;
+      const std::vector<uint64_t> admitted = S->sched->admit(now_since(S->t0));
+      if (!admitted.empty()) {
+        S->pending.insert(S->pending.end(), admitted.begin(), admitted.end());
+        S->cv_setup.notify_all();
+      }
+      // step the resident requests whose problems are ready
+      ids.clear();
       probs.clear();
-      for (uint64_t id : ids) probs.push_back(S->reqs[id].prob);
+      for (uint64_t id : S->sched->resident()) {
+        mc_problem* P = S->reqs[id].prob;
+        if (P) {
+          ids.push_back(id);
+          probs.push_back(P);
+        }
+      }
+      if (ids.empty()) {
+        if (S->sched->n_resident() == 0 && S->sched->queued() == 0) S->cv_idle.notify_all();
+        // wait for a submission or a finished setup
+        const uint64_t seen = S->events;
+        S->cv_work.wait(lk, [&] { return S->stop || S->events != seen; });
+        continue;
+      }
     }
-    if (ids.empty()) continue;
     reps.assign(ids.size(), mc_report{});
     const double ta = now_since(S->t0);
     mc_status st = mc_batch_step(S->batch, probs.data(), (int32_t)probs.size(), 1, reps.data());
@@ -155,7 +185,7 @@ void run_worker(mc_server* S) {
     if (st == MC_OK || st == MC_ENOCONV || st == MC_EBREAKDOWN) {
       for (size_t i = 0; i < ids.size(); ++i) (reps[i].failed < 0 ? ok : bad).push_back(ids[i]);
     } else {
-      bad = ids;   // a device or argument error: every resident request fails
+      bad = ids;   // a device or argument error: every stepped request fails
     }
     std::vector<uint64_t> done;
     {
@@ -233,11 +263,13 @@ mc_status mc_server_create(const mc_server_config* cfg, const mc_options* opt,
     delete S;
     return st;
   }
-  // every problem of the server orders its work on the batch's stream
+  // each problem orders its setup on its own stream (the options' stream, or a stream of
+  // its own when none is given); the batched steps run on the batch's stream
   S->opt = o;
   S->sched.reset(new mc::Scheduler(S->cfg.hbm_budget, S->cfg.max_resident, S->cfg.max_bypass));
   S->t0 = std::chrono::steady_clock::now();
   S->worker = std::thread(run_worker, S);
+  S->setup = std::thread(run_setup, S);
   *out = S;
   return MC_OK;
 }
@@ -249,7 +281,9 @@ mc_status mc_server_destroy(mc_server* S) {
     S->stop = true;
   }
   S->cv_work.notify_all();
+  S->cv_setup.notify_all();
   if (S->worker.joinable()) S->worker.join();
+  if (S->setup.joinable()) S->setup.join();
   for (auto& kv : S->reqs)
     if (kv.second.prob) mc_destroy(kv.second.prob);
   mc_batch_destroy(S->batch);
@@ -280,6 +314,7 @@ mc_status mc_server_submit(mc_server* S, const mc_problem_desc* d, int32_t n_ste
   R.id = rid;
   R.desc = std::move(hd);
   S->submitted += 1;
+  S->events += 1;
   *id = rid;
   S->cv_work.notify_all();
   return MC_OK;
@@ -345,7 +380,8 @@ mc_status mc_server_wait(mc_server* S, double timeout_s) {
   if (!S) return MC_EINVAL;
   std::unique_lock<std::mutex> lk(S->mu);
   auto idle = [&] {
-    return S->sched->queued() == 0 && S->sched->n_resident() == 0 && S->finalizing == 0;
+    return S->sched->queued() == 0 && S->sched->n_resident() == 0 && S->finalizing == 0 &&
+           S->pending.empty() && S->setting_up == 0;
   };
   if (timeout_s < 0) {
     S->cv_idle.wait(lk, idle);
