@@ -68,12 +68,10 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "15ab832945e42fd7", "fetch_kib": 83985.4,
-                        "write_kib": 65603.6, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "15ab832945e42fd7", "fetch_kib": 90358.0,
-                        "write_kib": 98320.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "15ab832945e42fd7", "fetch_kib": 82706.4,
-                        "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "A"): {"sources": "f14337ee33a3cd8e", "fetch_kib": 83967.2,
+                        "write_kib": 65603.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "f14337ee33a3cd8e", "fetch_kib": 90359.9,
+                        "write_kib": 98320.4, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
 def log(*a):
@@ -170,7 +168,7 @@ KERNEL_NAMES = {
 }
 
 
-def roofline(kind_time, bytes_total, precision, precond, workload):
+def roofline(kind_time, bytes_total, precision, precond, workload, working=None):
     """Roofline objects of every timed grid kernel: the operator (A), update (B) and, with
     the V-cycle, the finest post-smoothing (P) and the coarse kernels summed over their
     levels (RS, PC, TAIL, R); the one with the most total time is the dominant kernel.
@@ -178,17 +176,20 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
     kind_time[k] = (sampled, summed ms, issued, working sampled, working summed ms), where the
     working samples are those of at least a quarter of the mean sample (the others are
     launches whose systems had all converged; they return at once and move no bytes).
-    Total time = mean working sample x working launches (issued x working share of the
-    samples); achieved = algorithmic bytes of the timed layers / total time; the average
+    working[k]: launches that did work, counted from the iterations the timed layers took
+    (a launch of the group's systems works while any of them still iterates); without it,
+    issued x working share of the samples.  Total time = mean working sample x working
+    launches; achieved = algorithmic bytes of the timed layers / total time; the average
     launch duration is the mean working sample."""
     out = {}
     for k, (sampled, ms, issued, wn, wms) in kind_time.items():
         if not sampled or not wn:
             continue
         avg_s = wms / wn * 1e-3
-        working = issued * wn / sampled
-        total_s = avg_s * working
-        per_launch = bytes_total[k] / max(working, 1)
+        work = working.get(k) if working else None
+        working_k = work if work else issued * wn / sampled
+        total_s = avg_s * working_k
+        per_launch = bytes_total[k] / max(working_k, 1)
         achieved = bytes_total[k] / total_s / 1e9 if total_s > 0 else 0.0
         tp = "float" if precision == "mixed" else "double"
         pn = {"bic0": "BIC0", "mg": "BIC0", "jacobi": "JACOBI"}[precond]
@@ -201,6 +202,7 @@ def roofline(kind_time, bytes_total, precision, precond, workload):
                   "algorithmic_bytes_per_launch": per_launch,
                   "avg_launch_us": avg_s * 1e6, "sampled_launches": sampled,
                   "sampled_working_launches": wn, "issued_launches": issued,
+                  "working_launches": working_k,
                   "all_samples_avg_us": ms / sampled * 1e3,
                   "total_ms_est": total_s * 1e3}
     if not out:
@@ -330,6 +332,27 @@ def step_bytes(p, rep, precision, precond, nlev=None):
     return out
 
 
+def working_launches(iter_rows, precond, nlevs, shapes):
+    """Launches of each timed grid kernel that did work over the timed layers: one operator,
+    update (and finest post-smoothing) launch per iteration while any grid system of the
+    launch still iterates (iter_rows: per layer, the iterations of every grid system served
+    by the launches), and per such iteration the V-cycle's coarse launches (levels above the
+    tail: restriction + pre-smoothing and post-smoothing; the tail and the restriction into
+    it once each when some hierarchy reaches the tail)."""
+    its = float(sum(max(r) if len(r) else 0 for r in iter_rows))
+    out = {"A": its, "B": its}
+    if precond == "mg":
+        out["P"] = its
+        above = tail = 0
+        for nl, (nx, ny) in zip(nlevs, shapes):
+            lv = mg_levels(nx, ny)[:nl + 1]
+            n = [a * b for a, b in lv]
+            above = max(above, sum(1 for v in n[1:] if v > MG_TAIL))
+            tail = max(tail, 1 if any(v <= MG_TAIL for v in n[1:]) else 0)
+        out.update({"RS": its * above, "PC": its * above, "TAIL": its * tail, "R": its * tail})
+    return out
+
+
 def solve_bytes(p, precision):
     """Algorithmic bytes of a layer outside the PCG iterations, per grid continuum: the
     right-hand side (previous layer, F, the other continua's previous layers read; b and
@@ -406,7 +429,9 @@ def form_run(g, p, p0, args, change, scheme, profile=False):
                 tot[kk] += sb[kk]
         prof = read_profile(g, kernels_of(precond))
         g.profile(False)
-        roof, roof2 = roofline(prof, tot, opt["precision"], precond, args.workload)
+        work = working_launches([r[:p.n_omega] for r in iters], precond, nlev[:p.n_omega],
+                                [(p.nx, p.ny)] * p.n_omega)
+        roof, roof2 = roofline(prof, tot, opt["precision"], precond, args.workload, work)
         res["roofline"] = roof
         res["roofline_other_kernels"] = roof2
     res["accuracy_vs_oracle"] = accuracy_after(g, args.workload, args.steps, scheme)
@@ -512,7 +537,9 @@ def run_single(args, out):
 
     lat_ms = np.array(lat) * 1e3
     it = np.array(iters)
-    roof, roof2 = roofline(prof, tot, args.precision, args.precond, args.workload)
+    work = working_launches([r[:p.n_omega] for r in iters], args.precond,
+                            nlev[:p.n_omega], [(p.nx, p.ny)] * p.n_omega)
+    roof, roof2 = roofline(prof, tot, args.precision, args.precond, args.workload, work)
     out.update({
         "value": value, "ms_per_step": elapsed / args.steps * 1e3,
         "config": {"workload": f"{args.workload}: {p.n_cont}-continuum {p.nx}x{p.ny}"
@@ -663,7 +690,11 @@ def run_batch(args, out):
             g.close()
         calibrate(args)
     lat_ms = np.array(lat) * 1e3
-    roof, roof2 = roofline(prof, tot, args.precision, args.precond, "C4")
+    rows = [[v for p, r in zip(probs, reps) for v in r["iters"][:p.n_omega]] for reps in all_reps]
+    nl_all = [v for p, nl in zip(probs, nlevs) for v in nl[:p.n_omega]]
+    shapes = [(p.nx, p.ny) for p in probs for _ in range(p.n_omega)]
+    work = working_launches(rows, args.precond, nl_all, shapes)
+    roof, roof2 = roofline(prof, tot, args.precision, args.precond, "C4", work)
     out.update({
         "value": value, "ms_per_step": elapsed / args.steps * 1e3, "dtype": "f32+f64",
         "config": {"workload": f"C4: {len(probs)} realizations (two/three continua, sides "

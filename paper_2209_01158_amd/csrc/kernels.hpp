@@ -1651,7 +1651,7 @@ __device__ __forceinline__ void smooth_unit(const PartD& P, int unit) {
 // 0 and 63), the residual of each half of the block from values loaded first, then the
 // sweep.  At the finest level of a PCG solve (FINAL) the result is the PCG vector z and
 // (r, z) is added to rz.
-template <class T, bool FINAL, bool HAS_T, int R>
+template <class T, bool FINAL, bool HAS_T, int R, bool HAS_E = true>
 __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const PartD& P,
                                           int unit, double& rz) {
   const T* zp = (const T*)P.mg_zp;
@@ -1667,10 +1667,10 @@ __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const
   const int x0 = B.cx - lane;
   const int hx = lane == 0 ? max(x0 - 1, 0) : (lane == 63 ? min(x0 + MC_TX, nx - 1) : B.cxs);
   auto rowy = [&](int j) { return min(max(B.y0 + j, 0), ny - 1); };
-  // the last level of a truncated hierarchy has no coarser correction (e = 0)
+  // the last level of a truncated hierarchy has no coarser correction (e = 0, !HAS_E)
   auto zfull = [&](int y, int x) {
-    return e ? zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)]
-             : zp[(long)y * nx + x];
+    if constexpr (HAS_E) return zp[(long)y * nx + x] + e[(long)(y >> 1) * cnx + (x >> 1)];
+    else return zp[(long)y * nx + x];
   };
   T zo[R + 2];
 #pragma unroll
@@ -1721,6 +1721,10 @@ __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const
 template <class T, bool FINAL, int R>
 __device__ __forceinline__ void post_unit_any(const PartD* __restrict__ parts, const PartD& P,
                                               int unit, double& rz) {
+  if (!P.mg_e) {   // truncated hierarchy: its last level (always with face arrays)
+    post_unit<T, FINAL, true, R, false>(parts, P, unit, rz);
+    return;
+  }
   if (P.has_t) post_unit<T, FINAL, true, R>(parts, P, unit, rz);
   else post_unit<T, FINAL, false, R>(parts, P, unit, rz);
 }

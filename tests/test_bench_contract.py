@@ -49,3 +49,28 @@ def test_roofline_from_samples():
     assert np.isclose(dom["algorithmic_bytes_per_launch"], 1e9)
     assert np.isclose(dom["achieved"], 1e9 / 0.6e-3 / 1e9)
     assert np.isclose(dom["frac"], dom["achieved"] / 8000.0)
+
+
+def test_vcycle_levels_and_bytes():
+    """A 2048 x 2048 grid coarsens 2048^2 -> 1024^2 -> ... -> 16^2 (<= 256 cells); levels of at
+    most 1024 cells form the tail.  Restriction + pre-smoothing and post-smoothing run on
+    every level above the tail: RS moves (2 words + 12 B) per cell of the finer level
+    (4 B at a finest level without conductance arrays) and (2 words + 12 B) per coarse
+    cell; PC moves 3 words + w / 4 + 16 B per cell; R (into the tail) the finer level's
+    2 words + 12 B and one coarse word per cell.  A hierarchy cut after 3 levels has no
+    tail."""
+    lv = bench.mg_levels(2048, 2048)
+    assert [a for a, _ in lv] == [2048, 1024, 512, 256, 128, 64, 32, 16]
+    n = [a * a for a, _ in lv]
+    b = bench.vcycle_bytes(2048, 2048, "fp64", True)
+    rs = sum(n[l - 1] * 28 + n[l] * 28 for l in range(1, 6))
+    pc = sum(n[l] * 42 for l in range(1, 6))
+    assert np.isclose(b["RS"], rs) and np.isclose(b["PC"], pc)
+    assert np.isclose(b["R"], n[5] * 28 + n[6] * 8) and b["TAIL"] == 0
+    b3 = bench.vcycle_bytes(2048, 2048, "fp64", False, nlev=3)
+    assert np.isclose(b3["RS"], n[0] * 20 + n[1] * 28 + sum(n[l - 1] * 28 + n[l] * 28
+                                                          for l in (2, 3)))
+    assert b3["R"] == 0
+    w = bench.working_launches([[7, 3], [5, 9]], "mg", [3, 6], [(2048, 2048), (2048, 2048)])
+    # 7 + 9 iterations; 5 levels above the tail in the deeper hierarchy, which has a tail
+    assert w["A"] == 16 and w["RS"] == 16 * 5 and w["TAIL"] == 16 and w["R"] == 16
