@@ -50,7 +50,8 @@ METRIC = ("cell-updates/s per decoupled time step vs coupled+FP64 at 1e-8 rel er
 HBM_PEAK_GBS = 8000.0
 
 DEFAULTS = {
-    "C1": dict(precond="jacobi", precision="fp64", tol=1e-12, steps=20, coupled_steps=20),
+    "C1": dict(precond="jacobi", precision="fp64", tol=1e-12, steps=20, coupled_steps=20,
+               small_max=8192),
     "C2": dict(precond="mg", precision="fp64", tol=1e-10, steps=100, coupled_steps=5),
     "C3": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=1,
                sample_every=4),
@@ -363,7 +364,7 @@ def solve_bytes(p, precision):
 
 def options(args):
     o = dict(scheme="D", precision=args.precision, precond=args.precond,
-             warm_start=args.warm_start)
+             warm_start=args.warm_start, small_max=args.small_max)
     if args.precision == "mixed":
         o.update(outer_tol=args.tol, inner_tol=args.inner_tol)
     else:
@@ -959,6 +960,9 @@ def main():
     ap.add_argument("--hbm-budget-gib", type=float, default=128.0,
                     help="C5: device memory the resident requests may hold")
     ap.add_argument("--max-resident", type=int, default=0, help="C5: resident requests (0=256)")
+    ap.add_argument("--small-max", type=int, default=None,
+                    help="systems of at most this many unknowns run their whole PCG in one "
+                         "workgroup (default 8192 for C1, else 0: off)")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--layers", type=int, default=2,
                     help="NLMC: oversampling layers of the regions K_i^+")
@@ -982,6 +986,8 @@ def main():
             setattr(args, k, d[k])
     if args.sample_every is None:
         args.sample_every = d.get("sample_every", 32)
+    if args.small_max is None:
+        args.small_max = d.get("small_max", 0)
     if args.inner_tol is None:
         args.inner_tol = 1e-4 if args.precond == "mg" else 1e-6
     if args.warm_start is None:

@@ -152,6 +152,12 @@ typedef struct {
                             2 p^{n-1} - p^{n-2} once the previous two layers were computed by
                             this problem (else p^{n-1}); 1 always p^{n-1}.  Changes iteration
                             counts only, never the tolerance the solution meets             */
+  int32_t small_max;     /* 0 (default) or N >= 1: when every continuum has at most N unknowns,
+                            the decoupled schemes (D, L, U, EX) in FP64 with MC_JACOBI solve
+                            each continuum by one workgroup running its whole PCG in a single
+                            launch (mc_step only; batches and the server keep the general
+                            path).  Same stopping test; the solution meets the same tolerance
+                            but differs from the general path's in rounding                 */
   void *stream;          /* hipStream_t to order all work on, or NULL (library-owned stream)   */
 } mc_options;
 

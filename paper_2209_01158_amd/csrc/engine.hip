@@ -1893,6 +1893,53 @@ static void fill_coupled_report(int ncont, mc_report* rep) {
   }
 }
 
+// The small-system path applies: FP64 Jacobi decoupled schemes with every continuum at
+// most opt.small_max unknowns.
+static bool small_path(const mc_problem* P) {
+  const mc_options& o = P->X.opt;
+  if (o.small_max <= 0 || o.precision != MC_FP64 || o.precond != MC_JACOBI ||
+      o.scheme == MC_SCHEME_COUPLED)
+    return false;
+  for (const Cont& C : P->cont)
+    if (C.n > o.small_max) return false;
+  return true;
+}
+
+// Right-hand sides and warm starts of table T (k_rhs), then one workgroup per system of
+// parts [0, nsys) runs its whole PCG, all systems in one launch; the records of systems
+// [s0, s0 + nsys) are read back.
+static void small_solve(mc_problem* P, Table& T, int s0, int nsys) {
+  Exec& X = P->X;
+  launch_all(X.stream, T, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+  set_sys_params(X, s0, s0 + nsys, X.opt.tol, false);
+  // LDS-resident form when every system fits: 2-D grids of at most 4096 cells, fracture
+  // systems whose p and CSR take at most 64 KiB
+  size_t lds = 0;
+  bool fits = true;
+  for (int k = 0; k < nsys; ++k) {
+    const PartD& q = T.hparts[k];
+    size_t b = (size_t)q.n * sizeof(double);
+    if (q.kind == PART_GRID) {
+      fits = fits && q.n <= 1024 * 4 && q.plane == 0;
+    } else {
+      const size_t nnz = P->gh.col.size();
+      b += nnz * (sizeof(double) + sizeof(int)) + (size_t)(q.n + 1) * sizeof(int);
+      fits = fits && q.n <= 1024 * 4;
+    }
+    lds = std::max(lds, b);
+  }
+  if (fits && lds <= 64 * 1024)
+    hipLaunchKernelGGL((k_small_pcg_lds<1024, 4>), dim3(nsys), dim3(1024), lds, X.stream,
+                       T.parts, X.sys);
+  else
+    hipLaunchKernelGGL(k_small_pcg<1024>, dim3(nsys), dim3(1024), 0, X.stream, T.parts, 0,
+                       X.sys);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(X.h_sys + s0, X.sys + s0, nsys * sizeof(SysState),
+                        hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+}
+
 static mc_status step_once(mc_problem* P, mc_report* rep) {
   Exec& X = P->X;
   const bool mixed = X.opt.precision == MC_MIXED;
@@ -1900,7 +1947,28 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
   std::vector<int> all;
   for (int c = 0; c < P->ncont; ++c) all.push_back(c);
   mc_status st;
-  if (sch == MC_SCHEME_COUPLED) {
+  const bool small = small_path(P);
+  if (small && (sch == MC_SCHEME_D || sch == MC_SCHEME_EX)) {
+    Table& T = upload_table(P, "d" + std::to_string(P->cur), decoupled_parts(P, all, false));
+    small_solve(P, T, 0, P->ncont);
+    st = fill_report(X, all, all, rep, false);
+  } else if (small) {
+    st = MC_OK;
+    std::vector<int> order = all;
+    if (sch == MC_SCHEME_U) std::reverse(order.begin(), order.end());
+    for (size_t k = 0; k < order.size(); ++k) {
+      const int c = order[k];
+      std::vector<PartD> parts = decoupled_parts(P, {c}, false);
+      for (size_t j = 0; j < k; ++j) parts[0].tsrc[order[j]] = P->cont[order[j]].ps[1 - P->cur];
+      Table& T = upload_table(P, "s" + std::to_string(c) + "_" + std::to_string(P->cur), parts);
+      small_solve(P, T, c, 1);
+      mc_status s1 = fill_report(X, {c}, {c}, rep, false);
+      if (s1 != MC_OK) {
+        st = s1;
+        break;
+      }
+    }
+  } else if (sch == MC_SCHEME_COUPLED) {
     Table& T = upload_table(P, "coupled" + std::to_string(P->cur), coupled_parts(P, P->ncont, 0));
     set_sys_params(X, P->ncont, P->ncont + 1, X.opt.tol, false);
     solve_table(X, T, P->ncont, P->ncont + 1, true, false, false);

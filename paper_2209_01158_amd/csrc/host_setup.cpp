@@ -108,6 +108,7 @@ std::string validate_options(const mc_options& o) {
     return "tile_rows must be 0 (default) or 32 in this build";
   if (o.warm_start != 0 && o.warm_start != 1)
     return "warm_start must be 0 (extrapolate) or 1 (previous layer)";
+  if (o.small_max < 0) return "small_max must be >= 0";
   return "";
 }
 

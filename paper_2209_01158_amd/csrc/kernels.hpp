@@ -1983,6 +1983,287 @@ k_mg_tail(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   }
 }
 
+// ------------------------------------------------------------------------------------
+// small systems: one workgroup runs a whole Jacobi-PCG solve (FP64)
+// ------------------------------------------------------------------------------------
+// Workgroup b solves the decoupled system of part part0 + b (its record sys[P.sys] holds the
+// tolerance and iteration limit; b and the warm start x come from k_rhs).  The vectors stay
+// in global memory (L2-resident at these sizes); every dot product is a fixed-order
+// workgroup reduction, so every thread sees the same scalars.  Same stopping test as the
+// general path: ||r||^2 <= tol^2 ||b||^2 on the recursive residual, or max_iter.
+// Wave total by a DPP inclusive scan (row_shr 1, 2, 4, 8 within rows of 16 lanes, then
+// row_bcast:15 and row_bcast:31 across rows; lanes without a source add the identity 0):
+// lane 63 ends with the sum of all 64 lanes, read back into every lane.
+__device__ __forceinline__ double wave_total_dpp(double v) {
+  v += dpp_d<0x111, 0xF>(0.0, v);
+  v += dpp_d<0x112, 0xF>(0.0, v);
+  v += dpp_d<0x114, 0xF>(0.0, v);
+  v += dpp_d<0x118, 0xF>(0.0, v);
+  v += dpp_d<0x142, 0xA>(0.0, v);
+  v += dpp_d<0x143, 0xC>(0.0, v);
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int NT>
+__device__ __forceinline__ void small_sum(double (&v)[3], double (*buf)[3]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = wave_total_dpp(v[k]);
+  if (lane == 0)
+    for (int k = 0; k < 3; ++k) buf[wv][k] = v[k];
+  __syncthreads();
+  for (int k = 0; k < 3; ++k) {
+    double t = 0.0;
+    for (int w = 0; w < NT / 64; ++w) t += buf[w][k];
+    v[k] = t;
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_small_pcg(const PartD* __restrict__ parts, int part0,
+                                                  SysState* __restrict__ sys) {
+  __shared__ double red[2][NT / 64][3];   // two buffers: a reduction never reuses the last
+  const PartD& P = parts[part0 + blockIdx.x];
+  SysState& S = sys[P.sys];
+  const long n = P.n;
+  const int tid = threadIdx.x;
+  double* x = (double*)P.x;
+  double* r = (double*)P.r;
+  double* p = (double*)P.p;
+  double* q = (double*)P.q;
+  const double* b = P.b;
+  const double* d = P.diag;
+  const bool grid = P.kind == PART_GRID;
+  auto Av = [&](long i, const double* v) {
+    auto vs = [&](long j) { return v[j]; };
+    if (grid) return grid_Av<double>(P, (int)(i % P.nx), (int)(i / P.nx), i, v[i], vs);
+    return graph_Av<double>(P, (int)i, v[i], vs);
+  };
+  int rb = 0;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (long i = tid; i < n; i += NT) {      // r = b - A x, p = z = r / diag
+    const double ri = b[i] - Av(i, x);
+    const double zi = ri / d[i];
+    r[i] = ri;
+    p[i] = zi;
+    v[0] += ri * zi;
+    v[1] += ri * ri;
+    v[2] += b[i] * b[i];
+  }
+  small_sum<NT>(v, red[rb]);
+  rb ^= 1;
+  double rz = v[0], rr = v[1];
+  const double bb = v[2], tol2 = S.tol2;
+  const int max_iter = S.max_iter;
+  int k = 0, st = ST_RUN;
+  for (;;) {
+    if (rr <= tol2 * bb) st = ST_CONV;
+    else if (!finite(rz) || !finite(rr) || !(rz > 0.0)) st = ST_BREAK;
+    else if (k >= max_iter) st = ST_NOCONV;
+    if (st != ST_RUN) break;
+    __syncthreads();                        // p complete before A p
+    double w[3] = {0.0, 0.0, 0.0};
+    for (long i = tid; i < n; i += NT) {
+      const double qi = Av(i, p);
+      q[i] = qi;
+      w[0] += p[i] * qi;
+    }
+    small_sum<NT>(w, red[rb]);
+    rb ^= 1;
+    const double pq = w[0];
+    if (!(pq > 0.0) || !finite(pq)) {
+      st = ST_BREAK;
+      break;
+    }
+    const double alpha = rz / pq;
+    double u[3] = {0.0, 0.0, 0.0};
+    for (long i = tid; i < n; i += NT) {
+      x[i] += alpha * p[i];
+      const double ri = r[i] - alpha * q[i];
+      r[i] = ri;
+      const double zi = ri / d[i];
+      u[0] += ri * zi;
+      u[1] += ri * ri;
+    }
+    small_sum<NT>(u, red[rb]);
+    rb ^= 1;
+    const double beta = u[0] / rz;
+    rz = u[0];
+    rr = u[1];
+    for (long i = tid; i < n; i += NT) p[i] = r[i] / d[i] + beta * p[i];
+    ++k;
+  }
+  if (tid == 0) {
+    S.bb = bb;
+    S.rr = rr;
+    S.iter = k;
+    S.total_iter = k;
+    S.status = st;
+    S.done = 1;
+  }
+}
+
+// The same solve with the search direction p in LDS and every cell's coefficients and x,
+// r, q in registers (thread t owns cells t, t + NT, ...; at most CPT each): one workgroup per
+// 2-D grid system of at most NT * CPT cells, or per fracture system whose CSR also fits the
+// LDS.  LDS layout: p [n]; for a fracture system then val [nnz], col [nnz], rowptr [n + 1].
+template <int NT, int CPT>
+__global__ void __launch_bounds__(NT) k_small_pcg_lds(const PartD* __restrict__ parts,
+                                                      SysState* __restrict__ sys) {
+  extern __shared__ double lds[];
+  __shared__ double red[2][NT / 64][3];
+  const PartD& P = parts[blockIdx.x];
+  SysState& S = sys[P.sys];
+  const int n = P.n, tid = threadIdx.x, nx = P.nx;
+  const bool grid = P.kind == PART_GRID;
+  double* pl = lds;
+  double* vall = lds + n;
+  int nnz = 0;
+  if (!grid) nnz = P.rowptr[n];
+  int* coll = (int*)(vall + nnz);
+  int* rpl = coll + nnz;
+  if (!grid) {
+    for (int j = tid; j < nnz; j += NT) {
+      vall[j] = P.val[j];
+      coll[j] = P.col[j];
+    }
+    for (int j = tid; j <= n; j += NT) rpl[j] = P.rowptr[j];
+  }
+  double dg[CPT], tw[CPT], te[CPT], ts[CPT], tn[CPT], x[CPT], r[CPT], q[CPT];
+  const double* xg = (const double*)P.x;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * NT;
+    dg[k] = 1.0;
+    tw[k] = te[k] = ts[k] = tn[k] = x[k] = 0.0;
+    if (i < n) {
+      dg[k] = P.diag[i];
+      x[k] = xg[i];
+      if (grid) {
+        const int cx = i % nx, cy = i / nx;
+        const double tc = P.tconst;
+        if (cx > 0) tw[k] = P.has_t ? P.tx[i - 1] : tc;
+        if (cx + 1 < nx) te[k] = P.has_t ? P.tx[i] : tc;
+        if (cy > 0) ts[k] = P.has_t ? P.ty[i - nx] : tc;
+        if (cy + 1 < P.ny) tn[k] = P.has_t ? P.ty[i] : tc;
+      }
+    }
+  }
+  // (A v)_i from v in LDS: the grid's 5-point operator (faces of missing neighbours are 0)
+  // or the fracture CSR
+  auto Av = [&](int k, const double* v) {
+    const int i = tid + k * NT;
+    double acc = dg[k] * v[i];
+    if (grid) {
+      if (tw[k] != 0.0) acc -= tw[k] * v[i - 1];
+      if (te[k] != 0.0) acc -= te[k] * v[i + 1];
+      if (ts[k] != 0.0) acc -= ts[k] * v[i - nx];
+      if (tn[k] != 0.0) acc -= tn[k] * v[i + nx];
+    } else {
+      for (int j = rpl[i]; j < rpl[i + 1]; ++j) acc -= vall[j] * v[coll[j]];
+    }
+    return acc;
+  };
+  // r = b - A x and p = z = r / diag: x goes through the LDS once
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * NT;
+    if (i < n) pl[i] = x[k];
+  }
+  __syncthreads();
+  int rb = 0;
+  double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * NT;
+    r[k] = 0.0;
+    if (i < n) {
+      const double bi = P.b[i];
+      r[k] = bi - Av(k, pl);
+      const double zi = r[k] / dg[k];
+      v[0] += r[k] * zi;
+      v[1] += r[k] * r[k];
+      v[2] += bi * bi;
+    }
+  }
+  small_sum<NT>(v, red[rb]);   // its barrier also ends every read of x from the LDS
+  rb ^= 1;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * NT;
+    if (i < n) pl[i] = r[k] / dg[k];
+  }
+  double rz = v[0], rr = v[1];
+  const double bb = v[2], tol2 = S.tol2;
+  const int max_iter = S.max_iter;
+  int it = 0, st = ST_RUN;
+  for (;;) {
+    if (rr <= tol2 * bb) st = ST_CONV;
+    else if (!finite(rz) || !finite(rr) || !(rz > 0.0)) st = ST_BREAK;
+    else if (it >= max_iter) st = ST_NOCONV;
+    if (st != ST_RUN) break;
+    __syncthreads();                        // p complete before A p
+    double w[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int i = tid + k * NT;
+      q[k] = 0.0;
+      if (i < n) {
+        q[k] = Av(k, pl);
+        w[0] += pl[i] * q[k];
+      }
+    }
+    small_sum<NT>(w, red[rb]);
+    rb ^= 1;
+    const double pq = w[0];
+    if (!(pq > 0.0) || !finite(pq)) {
+      st = ST_BREAK;
+      break;
+    }
+    const double alpha = rz / pq;
+    double u[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int i = tid + k * NT;
+      if (i < n) {
+        x[k] += alpha * pl[i];
+        r[k] -= alpha * q[k];
+        const double zi = r[k] / dg[k];
+        u[0] += r[k] * zi;
+        u[1] += r[k] * r[k];
+      }
+    }
+    small_sum<NT>(u, red[rb]);   // its barrier also ends every read of p in this iteration
+    rb ^= 1;
+    const double beta = u[0] / rz;
+    rz = u[0];
+    rr = u[1];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int i = tid + k * NT;
+      if (i < n) pl[i] = r[k] / dg[k] + beta * pl[i];
+    }
+    ++it;
+  }
+  double* xo = (double*)P.x;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int i = tid + k * NT;
+    if (i < n) xo[i] = x[k];
+  }
+  if (tid == 0) {
+    S.bb = bb;
+    S.rr = rr;
+    S.iter = it;
+    S.total_iter = it;
+    S.status = st;
+    S.done = 1;
+  }
+}
+
 // Solve parameters of the system records [s0, s1)
 __global__ void k_set_params(SysState* sys, int s0, int s1, double tol2, double otol2,
                              int max_iter, int max_outer, int mixed) {

@@ -60,7 +60,7 @@ class Options(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("outer_tol", C.c_double),
                 ("max_outer", C.c_int32), ("inner_tol", C.c_double),
                 ("check_every", C.c_int32), ("tile_rows", C.c_int32), ("warm_start", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("small_max", C.c_int32), ("stream", C.c_void_p)]
 
 
 class Report(C.Structure):
@@ -212,7 +212,7 @@ def _ptr(a, ctype):
 
 def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_iter=20000,
                  outer_tol=1e-10, max_outer=30, inner_tol=1e-6, check_every=0, tile_rows=0,
-                 warm_start="extrapolate", stream=None) -> Options:
+                 warm_start="extrapolate", small_max=0, stream=None) -> Options:
     o = Options()
     _check(mc_options_default(C.byref(o)))
     o.scheme = SCHEMES[scheme]
@@ -222,6 +222,7 @@ def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_
     o.outer_tol, o.max_outer, o.inner_tol = outer_tol, max_outer, inner_tol
     o.check_every, o.tile_rows = check_every, tile_rows
     o.warm_start = WARM_STARTS[warm_start]
+    o.small_max = small_max
     o.stream = stream
     return o
 
@@ -417,7 +418,7 @@ class Problem:
                    max_outer=self.opt.max_outer, inner_tol=self.opt.inner_tol,
                    check_every=self.opt.check_every, tile_rows=self.opt.tile_rows,
                    warm_start={v: k for k, v in WARM_STARTS.items()}[self.opt.warm_start],
-                   stream=self.opt.stream)
+                   small_max=self.opt.small_max, stream=self.opt.stream)
         cur.update(kw)
         o = make_options(**cur)
         _check(mc_set_options(self.h, C.byref(o)), self.h)

@@ -147,6 +147,31 @@ def test_c3_full_size_residual():
             prev = new
 
 
+C3GOLD = os.path.join(os.path.dirname(__file__), "golden", "c3_oracle.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(C3GOLD), reason="stored C3 oracle layers not written")
+def test_c3_against_stored_oracle():
+    """The 4096 x 4096 three-continuum workload in the benchmark's configuration (FP32 inner
+    PCG to 1e-4 with the V-cycle inside FP64 refinement to 1e-10) over its 50 layers, against
+    the oracle's D-scheme layers 1, 2, 10 and 50 (fast-diagonalization CG on the grid
+    continua to a residual of 1e-14, sparse LU on the fracture; tests/golden/c3_oracle.npz,
+    20 000 seeded cells per continuum): the mixed-precision gate, 1e-8 relative L2."""
+    print("\n[c3 against the stored oracle]", flush=True)
+    p = media.config_problem("C3")
+    z = np.load(C3GOLD, allow_pickle=False)
+    keep = [int(v) for v in z["steps_D"]]
+    with mcdec.Problem(p, scheme="D", precision="mixed", precond="mg", outer_tol=1e-10,
+                       inner_tol=1e-4) as g:
+        for n in range(1, max(keep) + 1):
+            rep = g.step(1)
+            if n in keep:
+                err = sampled_error(g, z, "D", n)
+                print(f"layer {n}: sampled rel L2 {err:.2e} (outer passes {rep['outer']})",
+                      flush=True)
+                assert err < 1e-8, (n, err)
+
+
 def test_3d_full_size_residual():
     """The 3-D workload (256 x 256 x 256 cubes, two continua, 40 fracture planes; 16.9 million
     unknowns) in the benchmark's configuration: D-scheme, FP64 block IC(0) PCG to 1e-10.  As

@@ -117,6 +117,23 @@ def test_trajectory(case, scheme):
             assert err < 1e-10, (name, scheme, n, err, rep)
 
 
+@pytest.mark.parametrize("scheme", ["D", "L", "U", "EX"])
+@pytest.mark.parametrize("name", ["c1", "three70"])
+def test_small_system_path(name, scheme):
+    """Small systems (small_max): one workgroup per continuum runs its whole Jacobi PCG in
+    one launch; the layers match the oracle's as the general path's do."""
+    p = CASES[name]() if scheme != "EX" else media.small_problem(n=40, seed=2, nseg=4,
+                                                                   tau=1e-5, nsteps=3)
+    nsteps = 4 if scheme != "EX" else 3
+    ref = schemes.run(p, scheme, nsteps, keep="all")
+    with mcdec.Problem(p, scheme=scheme, precond="jacobi", tol=1e-14, small_max=1 << 20) as g:
+        for n in range(1, nsteps + 1):
+            rep = g.step(1)
+            err = rel(g.get_states(), ref[n])
+            assert err < 1e-10, (name, scheme, n, err, rep)
+            assert all(rep["converged"]), rep
+
+
 def test_ex_scheme_small_tau():
     p = media.small_problem(n=40, seed=2, nseg=4, tau=1e-5, nsteps=3)
     ref = schemes.run(p, "EX", 3, keep="last")
