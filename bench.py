@@ -69,10 +69,12 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "f14337ee33a3cd8e", "fetch_kib": 83967.2,
-                        "write_kib": 65603.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "f14337ee33a3cd8e", "fetch_kib": 90359.9,
-                        "write_kib": 98320.4, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "A"): {"sources": "975b53ffc6ff4087", "fetch_kib": 83487.6,
+                        "write_kib": 65602.8, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "975b53ffc6ff4087", "fetch_kib": 90357.0,
+                        "write_kib": 98320.6, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "975b53ffc6ff4087", "fetch_kib": 87233.9,
+                        "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
 def log(*a):
