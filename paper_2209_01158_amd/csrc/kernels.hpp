@@ -26,6 +26,13 @@ __device__ __forceinline__ gconst<T> gc(const T* p) {
   return (gconst<T>)p;
 }
 
+// Cache policy.  One PCG iteration streams several times the capacity of the L2 and the
+// memory-side cache, and most vectors are written by one kernel and read by the next (p and
+// q from the operator to the update, r and z_p from the update to the V-cycle, z from the
+// V-cycle to the operator).  Streams whose next reader is a whole iteration away -- the
+// operator and factor coefficients, and x and q in the update -- are read (x also written)
+// with non-temporal accesses, so that they do not displace those vectors.
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -57,12 +64,17 @@ __device__ __forceinline__ double ld_agent(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Partial sums are stored component-major: component k of slot s at part[k * nslots + s],
+// so that a wavefront reads 64 consecutive slots of one component and a reader loads only
+// the components it uses.  Every slot s < nslots of a record is written before it is read.
+
 // Sum of all partial slots of a system, in slot order.  Every workgroup of the system runs
 // the same loads and the same reduction tree, so all obtain the identical value.  Must be
-// reached by all threads of the workgroup.
+// reached by all threads of the workgroup.  Only the first `nv` components are loaded (the
+// others come back 0).
 template <int NV>
 __device__ __forceinline__ void reduce_slots(const double* __restrict__ part, int nslots,
-                                             double (&tot)[NV]) {
+                                             double (&tot)[NV], int nv = NV) {
   __shared__ double red[4][NV];
   __shared__ double bc[NV];
   double a[NV];
@@ -70,7 +82,8 @@ __device__ __forceinline__ void reduce_slots(const double* __restrict__ part, in
   for (int k = 0; k < NV; ++k) a[k] = 0.0;
   for (int s = threadIdx.x; s < nslots; s += MC_BLOCK) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) a[k] += part[s * MC_SLOT + k];
+    for (int k = 0; k < NV; ++k)
+      if (k < nv) a[k] += part[(long)k * nslots + s];
   }
   block_sum<NV>(a, red);
   if (threadIdx.x == 0) {
@@ -84,12 +97,13 @@ __device__ __forceinline__ void reduce_slots(const double* __restrict__ part, in
 
 // Reduce this workgroup's NV values and store them in its slot.
 template <int NV>
-__device__ __forceinline__ void write_slot(double* __restrict__ part, int slot, double (&v)[NV]) {
+__device__ __forceinline__ void write_slot(double* __restrict__ part, int nslots, int slot,
+                                           double (&v)[NV]) {
   __shared__ double red[4][NV];
   block_sum<NV>(v, red);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && slot < nslots) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) part[slot * MC_SLOT + k] = v[k];
+    for (int k = 0; k < NV; ++k) part[(long)k * nslots + slot] = v[k];
   }
 }
 
@@ -551,11 +565,11 @@ __device__ __forceinline__ void ic0_coefs(const PartD& P, const IcBlkR<R>& B, fl
   for (int y = 0; y < R; ++y) {
     const bool act = B.act(y);
     const long i = B.cell(y);
-    const float d = dinv[i];
+    const float d = __builtin_nontemporal_load(&dinv[i]);   // (cache policy above)
     float e, n;
     if constexpr (HAS_T) {
-      e = LOADED ? ex[y] : tx[i];
-      n = LOADED ? nx_[y] : ty[i];
+      e = LOADED ? ex[y] : __builtin_nontemporal_load(&tx[i]);
+      n = LOADED ? nx_[y] : __builtin_nontemporal_load(&ty[i]);
     } else {
       e = B.cx + 1 < B.nx ? tc : 0.0f;
       n = B.y0 + y + 1 < B.ny ? tc : 0.0f;
@@ -924,7 +938,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   };
   const Residual64 R{parts, P, (const double*)P.x, false};
   residual_and_precond<double, PREC, KIND>(P, t, R, r, (double*)P.z, emit, v);
-  write_slot<5>(S.partB, t.slot, v);
+  write_slot<5>(S.partB, S.nslotsB, t.slot, v);
 }
 
 template <class T, int PREC, int KIND>
@@ -943,8 +957,8 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
   // one thread writes the record (total_iter is a read-modify-write)
   const bool w0 = t.slot == 0 && threadIdx.x == 0;
   if (w0) S.kb = k;
-  double v[5];
-  reduce_slots<5>(S.partB, S.nslotsB, v);
+  double v[5];   // (r,z), (r,r); (b,b) at k = 0; the FP64 norms after a refinement residual
+  reduce_slots<5>(S.partB, S.nslotsB, v, outer_check ? 5 : (k == 0 ? 3 : 2));
   if (outer_check) {   // first inner iteration after an FP64 residual: refinement test
     const double orr = v[3];
     const double obb = S.outer == 0 ? v[4] : S.obb;
@@ -1022,10 +1036,10 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
 #pragma unroll
       for (int r = 0; r < WR; ++r) {
         const long i = (long)min(r0 + r, ny - 1) * nx + cxs;
-        dv[r] = d[i];
+        dv[r] = __builtin_nontemporal_load(&d[i]);   // coefficients: non-temporal
         if (P.has_t) {
-          te[r] = tx[i];
-          tn[r] = ty[i];
+          te[r] = __builtin_nontemporal_load(&tx[i]);
+          tn[r] = __builtin_nontemporal_load(&ty[i]);
           tw[r] = cx > 0 && cx < nx ? tx[i - 1] : (T)0;
         }
       }
@@ -1105,7 +1119,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
     }
   }
   double o[1] = {pq};
-  write_slot<1>(S.partA, t.slot, o);
+  write_slot<1>(S.partA, S.nslotsA, t.slot, o);
 }
 
 template <class T, int PREC, int KIND>
@@ -1126,7 +1140,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   if (!(pq > 0.0) || !finite(pq)) {
     // breakdown: every workgroup sees it; the NaN stops the system in the next A
     o[0] = __builtin_nan("");
-    write_slot<2>(S.partB, t.slot, o);
+    write_slot<2>(S.partB, S.nslotsB, t.slot, o);
     return;
   }
   const T alpha = (T)(S.rzh[k & 1] / pq);
@@ -1150,17 +1164,17 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 #pragma unroll
       for (int y = 0; y < MC_ICY; ++y) {
         const long i = B.cell(y);
-        xv[y] = xg[i];
+        xv[y] = __builtin_nontemporal_load(&xg[i]);   // x and q: non-temporal
         pv[y] = pg[i];
         rv[y] = rg[i];
-        qv[y] = qg[i];
+        qv[y] = __builtin_nontemporal_load(&qg[i]);
       }
 #pragma unroll
       for (int y = 0; y < MC_ICY; ++y) {
         const T xn = xv[y] + alpha * pv[y];
         const T rn = rv[y] - alpha * qv[y];
         if (B.act(y)) {
-          x[B.cell(y)] = xn;
+          __builtin_nontemporal_store(xn, &x[B.cell(y)]);
           r[B.cell(y)] = rn;
         }
         rv[y] = B.act(y) ? rn : (T)0;
@@ -1199,7 +1213,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     };
     for_cells<KIND>(P, t, [&](int, int, long i) { body(i); }, [&](int l) { body(l); });
   }
-  write_slot<2>(S.partB, t.slot, o);
+  write_slot<2>(S.partB, S.nslotsB, t.slot, o);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1239,7 +1253,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_residual64(const PartD* __restrict
         v[0] += ri * ri;
         v[1] += P.b[l] * P.b[l];
       });
-  write_slot<2>(S.partA, t.slot, v);
+  write_slot<2>(S.partA, S.nslotsA, t.slot, v);
 }
 
 template <int PREC, int KIND>
@@ -1282,7 +1296,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   const bool w0 = t.slot == 0 && threadIdx.x == 0;
   v[3] = w0 ? orr : 0.0;   // the FP64 norms, once per system
   v[4] = w0 ? obb : 0.0;
-  write_slot<5>(S.partB, t.slot, v);
+  write_slot<5>(S.partB, S.nslotsB, t.slot, v);
   if (w0) {   // a new inner solve starts
     S.rscale = sc;
     S.ka = 0;
@@ -1405,7 +1419,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_schur(const PartD* __restrict__ pa
   const PartD& P = parts[t.part];
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   schur_rows<T, true>(P, t, v[0]);
-  write_slot<5>(S.partB, t.slot, v);
+  write_slot<5>(S.partB, S.nslotsB, t.slot, v);
 }
 
 // boundary call z = M^-1 r: the crossing solution, then z = y + block responses in place
@@ -1688,13 +1702,14 @@ __device__ __forceinline__ void post_unit(const PartD* __restrict__ parts, const
       const long o = (long)y * nx;
       zh[j] = zfull(y, hx);
       rr[j] = r[o + B.cxs];
-      dv[j] = d[o + B.cxs];
-      te[j] = HAS_T ? txp[o + B.cxs] : 0.0f;
+      dv[j] = __builtin_nontemporal_load(&d[o + B.cxs]);
+      te[j] = HAS_T ? __builtin_nontemporal_load(&txp[o + B.cxs]) : 0.0f;
       th[j] = HAS_T ? txp[o + hx] : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < H + 1; ++j)
-      ty[j] = HAS_T ? typ[(long)rowy(h * H + j - 1) * nx + B.cxs] : 0.0f;
+      ty[j] = HAS_T ? __builtin_nontemporal_load(&typ[(long)rowy(h * H + j - 1) * nx + B.cxs])
+                    : 0.0f;
 #pragma unroll
     for (int j = 0; j < H; ++j) {
       const int jj = h * H + j, y = B.y0 + jj;
@@ -1775,17 +1790,17 @@ __device__ __forceinline__ void restrict_smooth_unit(const PartD& C, int unit) {
       zh[j] = zf[o + hx];
       r0[j] = rf[o + fx0];
       r1[j] = rf[o + fx1];
-      d0[j] = d[o + fx0];
-      d1[j] = d[o + fx1];
-      e0[j] = HAS_T ? txp[o + fx0] : 0.0f;
-      e1[j] = HAS_T ? txp[o + fx1] : 0.0f;
+      d0[j] = __builtin_nontemporal_load(&d[o + fx0]);
+      d1[j] = __builtin_nontemporal_load(&d[o + fx1]);
+      e0[j] = HAS_T ? __builtin_nontemporal_load(&txp[o + fx0]) : 0.0f;
+      e1[j] = HAS_T ? __builtin_nontemporal_load(&txp[o + fx1]) : 0.0f;
       eh[j] = HAS_T ? txp[o + hx] : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < H + 1; ++j) {
       const long o = row(j0 + j - 1);
-      n0[j] = HAS_T ? typ[o + fx0] : 0.0f;
-      n1[j] = HAS_T ? typ[o + fx1] : 0.0f;
+      n0[j] = HAS_T ? __builtin_nontemporal_load(&typ[o + fx0]) : 0.0f;
+      n1[j] = HAS_T ? __builtin_nontemporal_load(&typ[o + fx1]) : 0.0f;
     }
 #pragma unroll
     for (int j = 0; j < H; ++j) {
@@ -1909,7 +1924,7 @@ k_mg_post(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
   const PartD& P = parts[t.part];
   double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for_wave_tiles(t, [&](int unit) { post_unit_any<T, FINAL, MC_ICY>(parts, P, unit, v[0]); });
-  if (FINAL) write_slot<5>(sys[P.sys].partB, t.slot, v);
+  if (FINAL) write_slot<5>(sys[P.sys].partB, sys[P.sys].nslotsB, t.slot, v);
 }
 
 // The small levels of a V-cycle in one workgroup: starting at level part t.part (whose
