@@ -96,14 +96,17 @@ def measured_traffic(workload, precond, kernel):
     return (m["fetch_kib"] * m["read_factor"] + m["write_kib"] * m["write_factor"]) * 1024.0
 
 
-def grid_bytes_per_cell(kernel, precision, precond, has_t, dim=2):
+def grid_bytes_per_cell(kernel, precision, precond, has_t, dim=2, fused=False):
     """Algorithmic bytes a grid PCG kernel must move per cell (w = 4 or 8 byte words).
 
     A (operator): read z (Jacobi: r), p_old, diag [, tx, ty] [3-D: tz]; write p_new, q.
     B (update):   read x, p, r, q; write x, r; Jacobi also reads diag (z = r / diag is
                   recomputed where needed, never stored); block IC(0) reads the FP32 copies
                   of the inverse pivots and of tx, ty (4 bytes each) and writes z (under mg
-                  the same sweep is the finest pre-smoothing and writes z_p).
+                  the same sweep is the finest pre-smoothing and writes z_p).  Fused with the
+                  restriction into level 1 (mg, level 1 above the tail) it also reads the
+                  FP32 diagonal and writes the in-block part of r_c (one word per 2 x 2
+                  cells) and the block edges (two words and 4 B per 64 cells).
     P (mg: finest correction + post-smoothing): read z_p, r, the coarse correction e (one
                   word per 2 x 2 cells), the FP32 diagonal, the FP32 inverse pivots [and
                   FP32 tx, ty, shared by the residual and the sweep]; write z."""
@@ -113,8 +116,19 @@ def grid_bytes_per_cell(kernel, precision, precond, has_t, dim=2):
     if kernel == "P":
         return 3 * w + w / 4 + (2 + (2 if has_t else 0)) * 4
     if precond in ("bic0", "mg"):
-        return 7 * w + 3 * 4
+        return 7 * w + 3 * 4 + ((4 + w / 4 + (2 * w + 4) / 64) if fused else 0.0)
     return 7 * w
+
+
+def mg_fused(nx, ny, nlev=None, dim=2):
+    """The update kernel forms the finest level's in-block share of the restriction into
+    level 1 (2-D V-cycles whose level 1 is above the tail; MCDEC_MG_FUSE=0 turns it off)."""
+    if dim != 2 or os.environ.get("MCDEC_MG_FUSE", "1") == "0":
+        return False
+    lv = mg_levels(nx, ny)
+    if len(lv) < 2 or (nlev is not None and nlev < 1):
+        return False
+    return lv[1][0] * lv[1][1] > MG_TAIL
 
 
 MG_COARSE, MG_TAIL = 256, 1024   # coarsest level size; levels of at most MG_TAIL cells: tail
@@ -129,13 +143,17 @@ def mg_levels(nx, ny):
     return out
 
 
-def vcycle_bytes(nx, ny, precision, has_t, nlev=None):
+def vcycle_bytes(nx, ny, precision, has_t, nlev=None, fused=False):
     """Algorithmic bytes of one V-cycle's coarse kernels (all levels), per timing slot.
 
     RS (restriction into coarse level l with its pre-smoothing, every level above the tail):
         per cell of level l-1 read r, z_p (2 words) and the FP32 diagonal [, tx, ty] (4 B
         each; level 0 without a conductance field: the diagonal only); per cell of level l
-        write r_c, z_p (2 words) and read its FP32 inverse pivots, tx, ty (12 B).
+        write r_c, z_p (2 words) and read its FP32 inverse pivots, tx, ty (12 B).  Into a
+        fused level 1 (the update kernel summed the in-block part of r_c): per cell of
+        level 1 read and write r_c, write z_p (3 words), read its factor (12 B), plus the
+        finest row next to a block edge (a word and 4 B per fine column, one fine row in 8)
+        and the block edges (3 per 128 fine columns, a word and 4 B per fine row).
     PC (correction + post-smoothing at level l, levels above the tail except the finest):
         read z_p, r, e (one word per 2 x 2 cells), FP32 diagonal, pivots, tx, ty; write z:
         3 words + w / 4 + 16 B per cell.
@@ -151,7 +169,10 @@ def vcycle_bytes(nx, ny, precision, has_t, nlev=None):
     rs = pc = r = 0.0
     for l in range(1, len(lv)):
         fine_coef = (12 if (l > 1 or has_t) else 4)
-        if n[l] > MG_TAIL:
+        if n[l] > MG_TAIL and l == 1 and fused:
+            rs += n[l] * (3 * w + 12 + (w + 4) / 2 + 24 * (w + 4) / 256)
+            pc += n[l] * (3 * w + w / 4 + 16)
+        elif n[l] > MG_TAIL:
             rs += n[l - 1] * (2 * w + fine_coef) + n[l] * (2 * w + 12)
             pc += n[l] * (3 * w + w / 4 + 16)
         elif n[l - 1] > MG_TAIL or l == 1:
@@ -325,11 +346,14 @@ def step_bytes(p, rep, precision, precond, nlev=None):
     for c in range(p.n_omega):
         has_t = p.omega[c].k is not None or dim == 3
         it = rep["iters"][c]
+        nl = None if nlev is None else nlev[c]
+        fused = precond == "mg" and mg_fused(p.nx, p.ny, nl, dim)
         for k in ("A", "B", "P"):
             if k in out:
-                out[k] += it * p.ncell * grid_bytes_per_cell(k, precision, precond, has_t, dim)
+                out[k] += it * p.ncell * grid_bytes_per_cell(k, precision, precond, has_t, dim,
+                                                             fused)
         if precond == "mg":
-            vb = vcycle_bytes(p.nx, p.ny, precision, has_t, None if nlev is None else nlev[c])
+            vb = vcycle_bytes(p.nx, p.ny, precision, has_t, nl, fused)
             for k, b in vb.items():
                 out[k] += it * b
     return out

@@ -143,14 +143,23 @@ struct PartD {
   // (restriction)
   const void* mg_e;        // coarser level's z
   int mg_cnx;              // coarser level's nx
-  int mg_fnx, mg_fny, mg_ftiles_x, mg_fhas_t, mg_pad;
+  int mg_fnx, mg_fny, mg_ftiles_x, mg_fhas_t;
+  int mg_fuse;             // (level 0) the update kernel forms this level's share of the
+                           // restriction into level 1 (level 1 is not in the small-level tail)
   double mg_ftc;           // finer level's constant conductance (no conductance field)
   const void* mg_fr;       // finer level's right-hand side (level 0: the PCG residual)
   const void* mg_fzp;      // finer level's z_p
   const float* mg_fd32;    // finer level's FP32 diagonal and face conductances
   const float* mg_ftx32;
   const float* mg_fty32;
-                           // (level 0: the PCG vector z)
+  // block edges of a fused restriction (level 0 writes them, level 1 reads the copies): per
+  // IC(0) block column k (64 grid columns) and grid row y, z_p of the block's first and last
+  // column at [(k * ny + y) * 2 + 0 / 1] (launch precision) and the east face conductance of
+  // its last column at [k * ny + y] (FP32)
+  void* mg_edz;
+  float* mg_edt;
+  const void* mg_fedz;
+  const float* mg_fedt;
   // transfer structure
   const int* hptr;         // (grid) [n+1] fracture cells hosted per cell (CSR)
   const int* hidx;         // (grid) [nf]   their fracture indices

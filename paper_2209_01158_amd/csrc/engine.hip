@@ -61,6 +61,13 @@ static int env_int(const char* name, int dflt) {
   return std::atoi(v);
 }
 
+// Coarse levels of at most this many cells form the small-level tail of a V-cycle
+// (MCDEC_MG_TAIL overrides the size; the coarsest level is always in the tail).
+static long mg_tail_cells() {
+  static const long n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
+  return n;
+}
+
 // Workgroups per launch over a continuum, for the operator tiling (fam 0) and for the
 // update / init / residual tiling (fam 1).  A tuned choice (tiles per workgroup, recorded
 // per size class by mc_autotune) wins; otherwise one workgroup per tile up to a cap, beyond
@@ -155,6 +162,7 @@ struct Table {
     int n = 0, cap = 0;
   };
   std::vector<std::array<List, 4>> mg;
+  bool mg_fused = false;   // the finest parts' update kernels restrict into level 1
   std::map<long, hipGraphExec_t> graphs;
 };
 
@@ -230,6 +238,8 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
       T.nblk[fam][kind] = (int)tiles.size();
     }
   // multigrid lists
+  T.mg_fused = false;
+  for (auto& q : parts) T.mg_fused = T.mg_fused || (q.kind == PART_GRID && q.mg_fuse);
   int L = 0;
   for (auto& q : parts)
     if (q.kind == PART_GRID && (q.mg_next >= 0 || q.mg_level > 0)) L = std::max(L, q.mg_level + 1);
@@ -238,7 +248,7 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
   // a coarse level of at most MC_MG_TAIL cells belongs to its chain's tail (a suffix of the
   // levels), which one workgroup runs from the tail's first level down and back up
   // (MCDEC_MG_TAIL overrides the size; the coarsest level is always in the tail)
-  static const long tail_n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
+  const long tail_n = mg_tail_cells();
   auto in_tail = [&](const PartD& q) { return q.mg_level > 0 && (long)q.n <= tail_n; };
   for (int pi = 0; pi < (int)parts.size(); ++pi) {
     const PartD& q = parts[pi];
@@ -344,6 +354,8 @@ struct Cont {  // one continuum
   bool mg_on = false;
   double* zpre = nullptr;
   float* zpre32 = nullptr;
+  double* mg_edz = nullptr;   // block edges of the fused restriction into level 1
+  float* mg_edt = nullptr;
   // state and PCG vectors
   double* ps[2] = {nullptr, nullptr};
   double *b = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *z = nullptr;
@@ -682,6 +694,8 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.mg_prev = -1;
   q.mg_slot = slot0B + C.blocks[1];
   q.mg_zp = fp32 ? (void*)C.zpre32 : (void*)C.zpre;
+  q.mg_edz = C.mg_edz;
+  q.mg_edt = C.mg_edt;
   if (C.kind == PART_GRID) {
     q.hptr = P->nf ? P->hptr : nullptr;
     q.hidx = P->hidx;
@@ -718,15 +732,21 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
 // Fills the copies of neighbouring V-cycle levels' fields in every level part (after the
 // parts' own pointers are final: a caller may have redirected r or z of a finest part).
 static void link_mg(std::vector<PartD>& parts) {
+  // the update kernel forms the finest level's share of the restriction into level 1 when
+  // that level is smoothed by its own kernel (MCDEC_MG_FUSE=0: the restriction kernel does it all)
+  const bool fuse = env_flag("MCDEC_MG_FUSE", true);
   for (auto& q : parts) {
     if (q.kind != PART_GRID) continue;
     const int n = (int)parts.size();
     if ((q.mg_next >= n) || (q.mg_level > 0 && (q.mg_prev < 0 || q.mg_prev >= n)))
       throw Error{MC_EDEVICE, "multigrid level link outside the launch table"};
+    q.mg_fuse = 0;
     if (q.mg_next >= 0) {
       const PartD& c = parts[q.mg_next];
       q.mg_e = c.mg_z;
       q.mg_cnx = c.nx;
+      q.mg_fuse = fuse && q.mg_level == 0 && q.plane == 0 && q.mg_edz &&
+                  (long)c.n > mg_tail_cells();
     }
     if (q.mg_level > 0) {
       const PartD& f = parts[q.mg_prev];
@@ -740,6 +760,8 @@ static void link_mg(std::vector<PartD>& parts) {
       q.mg_fd32 = f.diag32;
       q.mg_ftx32 = f.tx32;
       q.mg_fty32 = f.ty32;
+      q.mg_fedz = f.mg_edz;
+      q.mg_fedt = f.mg_edt;
     }
   }
 }
@@ -950,7 +972,7 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
   // solves such a level, so it is smoothed twice instead of corrected from coarser levels
   // (MCDEC_MG_DOMINANCE overrides the ratio, 0 = never stop early; MCDEC_MG_LEVELS caps the
   // number of coarse levels).
-  const long tail_n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
+  const long tail_n = mg_tail_cells();
   const int max_levels = std::max(1, env_int("MCDEC_MG_LEVELS", 1 << 20));
   const char* dom_env = std::getenv("MCDEC_MG_DOMINANCE");
   const double dominance = dom_env ? std::atof(dom_env) : MC_MG_DOMINANCE;
@@ -1041,6 +1063,11 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
   C.mg_on = l > 0;
   if (C.mg_on && !C.zpre) C.zpre = M.alloc<double>(C.n);
   if (C.mg_on && mixed && !C.zpre32) C.zpre32 = M.alloc<float>(C.n);
+  if (C.mg_on && !C.mg_edz) {   // (sized for FP64; an FP32 solve uses the same indices)
+    const long ne = cdiv(P->d.nx, MC_TX) * (long)P->d.ny;
+    C.mg_edz = M.alloc<double>(2 * ne);
+    C.mg_edt = M.alloc<float>(ne);
+  }
 }
 
 static void build_coefficients(mc_problem* P) {
@@ -1407,9 +1434,11 @@ static void launch_schur(Exec& X, const Table& Tb, hipStream_t s) {
 // coarsest solve among them, in one workgroup per chain), the corrections with
 // post-smoothing going up.  The finest post-smoothing writes z and, when
 // `final`, (r, z) to the update slots.  `sys` null: no test of the solve's end.
+// after_update: the cycle follows the PCG update kernel, which has summed the finest
+// level's in-block share of the restriction into level 1 (fused tables)
 template <class T>
 static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool final,
-                          Exec* X = nullptr) {
+                          Exec* X = nullptr, bool after_update = false) {
   const int L = (int)Tb.mg.size();
   if (L == 0 || Tb.mg[0][3].n == 0) return;
   // X: count the launches for kernel timing, and time them all when the finest
@@ -1428,7 +1457,8 @@ static void launch_vcycle(const Table& Tb, hipStream_t s, SysState* sys, bool fi
     }
   };
   for (int l = 1; l < L; ++l) {
-    go(k_mg_restrict_smooth<T>, Tb.mg[l][1], 3, MC_BLOCK);
+    if (l == 1 && after_update && Tb.mg_fused) go(k_mg_fix_smooth<T>, Tb.mg[l][1], 3, MC_BLOCK);
+    else go(k_mg_restrict_smooth<T>, Tb.mg[l][1], 3, MC_BLOCK);
     go(k_mg_restrict<T>, Tb.mg[l][0], 6, MC_BLOCK);
     go(k_mg_tail<T>, Tb.mg[l][2], 5, MC_TAIL_THREADS);
   }
@@ -1486,7 +1516,7 @@ static void launch_iter(Exec& X, Group& G, bool timed) {
   L(k_pcg_A<T, PREC, PART_GRID>, PART_GRID, 0);
   L(k_pcg_A<T, PREC, PART_GRAPH>, PART_GRAPH, 0);
   L(k_pcg_B<T, PREC, PART_GRID>, PART_GRID, 1);
-  if (G.kinds & 1) launch_vcycle<T>(Tb, G.s, X.sys, true, timed ? &X : nullptr);
+  if (G.kinds & 1) launch_vcycle<T>(Tb, G.s, X.sys, true, timed ? &X : nullptr, true);
   L(k_pcg_B<T, PREC, PART_GRAPH>, PART_GRAPH, 1);
   if (G.kinds & 2) launch_schur<T>(X, Tb, G.s);
 }
@@ -2337,6 +2367,9 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
         A(8 * n);                 // pre-smoothed z of the finest level
         if (mixed) A(4 * n);
         A(8 * 2 * 128);           // partial sums of the levels' dominance test
+        const int64_t ne = (lx + MC_TX - 1) / MC_TX * ly;
+        A(8 * 2 * ne);            // block edges of the fused restriction
+        A(4 * ne);
       }
       while (lx * ly > MC_MG_COARSE) {   // (a hierarchy that stops early holds less)
         lx = (lx + 1) / 2;

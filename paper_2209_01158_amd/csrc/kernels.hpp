@@ -25,6 +25,12 @@ template <class T>
 __device__ __forceinline__ gconst<T> gc(const T* p) {
   return (gconst<T>)p;
 }
+template <class T>
+using gmut = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gmut<T> gm(T* p) {
+  return (gmut<T>)p;
+}
 
 // Cache policy.  One PCG iteration streams several times the capacity of the L2 and the
 // memory-side cache, and most vectors are written by one kernel and read by the next (p and
@@ -645,6 +651,97 @@ __device__ __forceinline__ void ic0_block(const PartD& P, const IcBlkR<R>& B, co
   }, rz, rr);
 }
 
+// The finest pre-smoothing of a V-cycle, z_p = M^-1 r on one block (as ic0_block), fused with
+// the block's share of the restriction into level 1: r_c += P^T (r - A_B z_p), where A_B
+// keeps the operator's couplings inside the block.  The couplings to the neighbouring blocks
+// are added by the level-1 kernel (k_mg_fix_smooth): from the block edges recorded here (z_p
+// of the first and last column, the east face of the last column, per row) and from the rows
+// next to the block's first and last row.  The fine residual is formed in the launch
+// precision and summed in FP64, as in the unfused restriction.  Without `fuse` this is
+// ic0_block storing z to zout (one copy of the sweep serves both).  For the residual pass
+// after the sweep, z_p waits in the wavefront's LDS slice `zs` (MC_ICY rows of 64), the
+// operator's FP32 diagonal is loaded straight into `ds` (global_load_lds: no registers; it
+// lands with the factor loads) and r is read back from rg, where this thread stored it
+// before the sweep.  Every lane reads only its own LDS entries (the west and east values come
+// by DPP).
+template <class T, bool HAS_T>
+__device__ __forceinline__ void ic0_block_restrict(const PartD* __restrict__ parts,
+                                                   const PartD& P, const IcBlk& B,
+                                                   const T (&rv)[MC_ICY], const T* rg,
+                                                   T* __restrict__ zout, bool fuse, T* zs,
+                                                   float* ds, double& rz, double& rr) {
+  constexpr int R = MC_ICY;
+  const int lane = threadIdx.x & 63;
+  float dv[R], te[R], tn[R];
+  ic0_coefs<HAS_T, R>(P, B, dv, te, tn);
+  if (fuse) {
+#pragma unroll
+    for (int y = 0; y < R; ++y)   // (a lane outside the grid loads a clamped in-grid cell)
+      __builtin_amdgcn_global_load_lds((const void*)(P.diag32 + B.cell(y)),
+                                       (__attribute__((address_space(3))) void*)(ds + y * 64),
+                                       4, 0, 0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+  }
+  const gmut<T> zo = gm(zout);   // (global, not flat, accesses: no LDS counter in their waits)
+  ic0_sweep_core<T, R>(B, rv, dv, te, tn, [&](int y, T a) {
+    if (B.act(y)) zo[B.cell(y)] = a;
+    if (fuse) zs[y * 64 + lane] = a;
+  }, rz, rr);
+  if (!fuse) return;
+  T rb[R];
+#pragma unroll
+  for (int y = 0; y < R; ++y) rb[y] = B.act(y) ? gc(rg)[B.cell(y)] : (T)0;
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  // block edges: z_p of the first and last column, the last column's east face
+  const gmut<T> edz = gm((T*)P.mg_edz);
+  const gmut<float> edt = gm(P.mg_edt);
+  const long e0 = (long)((B.cx - lane) / MC_TX) * P.ny + B.y0;
+  if (lane == 0 || lane == 63) {
+#pragma unroll
+    for (int y = 0; y < R; ++y)
+      if (B.y0 + y < P.ny) {
+        edz[(e0 + y) * 2 + (lane == 63)] = zs[y * 64 + lane];
+        if (lane == 63) edt[e0 + y] = te[y];
+      }
+  }
+  // residual pass: r - A_B z_p row by row, 2 x 2 sums into r_c
+  const PartD& C = parts[P.mg_next];
+  const gmut<T> rc = gm((T*)C.mg_r);
+  double sprev = 0.0;
+#pragma unroll
+  for (int y = 0; y < R; ++y) {
+    const float tw = dpp_d<0x138, 0xF>(0.0f, te[y]);   // lane 0: no west coupling
+    const T zc = zs[y * 64 + lane];
+    const T zw = lane > 0 ? zs[y * 64 + lane - 1] : (T)0;
+    const T ze = lane < 63 ? zs[y * 64 + lane + 1] : (T)0;
+    T a = (T)ds[y * 64 + lane] * zc;
+    a -= (T)tw * zw;
+    if (lane < 63) a -= (T)te[y] * ze;
+    if (y > 0) a -= (T)tn[y - 1] * zs[(y - 1) * 64 + lane];
+    if (y + 1 < R) a -= (T)tn[y] * zs[(y + 1) * 64 + lane];   // tn = 0 on the last row
+    const double sv = B.act(y) ? (double)rb[y] - (double)a : 0.0;
+    if (!(y & 1)) {
+      sprev = sv;
+      continue;
+    }
+    double v = sprev + sv;
+    v += dpp_d<0xB1, 0xF>(0.0, v);
+    if (!(lane & 1) && B.act(y - 1))
+      rc[(long)((B.y0 + y) >> 1) * C.nx + (B.cx >> 1)] = (T)v;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void ic0_block_restrict_any(const PartD* __restrict__ parts,
+                                                       const PartD& P, const IcBlk& B,
+                                                       const T (&rv)[MC_ICY], const T* rg,
+                                                       T* __restrict__ zout, bool fuse, T* zs,
+                                                       float* ds, double& rz, double& rr) {
+  if (P.has_t) ic0_block_restrict<T, true>(parts, P, B, rv, rg, zout, fuse, zs, ds, rz, rr);
+  else ic0_block_restrict<T, false>(parts, P, B, rv, rg, zout, fuse, zs, ds, rz, rr);
+}
+
 // Runs f(unit) for the IC(0) blocks of the workgroup's tile run, one wavefront per block.
 template <class F>
 __device__ __forceinline__ void for_wave_tiles(const Tile& t, const F& f) {
@@ -1158,6 +1255,9 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
     const gconst<T> pg = gc(p);
     const gconst<T> rg = gc((const T*)r);
     const gconst<T> qg = gc(q);
+    // each wavefront's z_p rows and FP32 diagonal rows (fused restriction)
+    __shared__ T zstash[4 * MC_ICY * 64];
+    __shared__ float dstash[4 * MC_ICY * 64];
     for_wave_tiles(t, [&](int unit) {
       const IcBlk B(P, unit);
       T xv[MC_ICY], pv[MC_ICY], rv[MC_ICY], qv[MC_ICY];
@@ -1174,13 +1274,19 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
         const T xn = xv[y] + alpha * pv[y];
         const T rn = rv[y] - alpha * qv[y];
         if (B.act(y)) {
-          __builtin_nontemporal_store(xn, &x[B.cell(y)]);
-          r[B.cell(y)] = rn;
+          __builtin_nontemporal_store(xn, &gm(x)[B.cell(y)]);
+          gm(r)[B.cell(y)] = rn;
         }
         rv[y] = B.act(y) ? rn : (T)0;
       }
-      // under a V-cycle this is the pre-smoothing of the finest level
-      ic0_block<T>(P, B, rv, P.mg_next >= 0 ? (T*)P.mg_zp : z, o[0], o[1]);
+      __builtin_amdgcn_sched_barrier(0);
+      // under a V-cycle this is the pre-smoothing of the finest level (with the block's
+      // share of the restriction into level 1, when that level is not in the small tail)
+      ic0_block_restrict_any<T>(parts, P, B, rv, (const T*)r,
+                                P.mg_next >= 0 ? (T*)P.mg_zp : z,
+                                P.mg_fuse != 0, zstash + (threadIdx.x >> 6) * MC_ICY * 64,
+                                dstash + (threadIdx.x >> 6) * MC_ICY * 64,
+                                o[0], o[1]);
     });
     if (P.mg_next >= 0) o[0] = 0.0;   // (r, z) comes from the final smoothing
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
@@ -1864,6 +1970,74 @@ __device__ __forceinline__ void restrict_smooth_unit(const PartD& C, int unit) {
   ic0_block<T, R>(C, B, rv, (T*)C.mg_zp, dz, dr);
 }
 
+// Level 1 after a fused finest pre-smoothing (ic0_block_restrict): completes r_c = P^T (r -
+// A z_p) with the couplings across the edges of the finest IC(0) blocks (64 x MC_ICY), whose
+// in-block part the update kernel has summed into r_c already, then pre-smooths z_p = M^-1
+// r_c, on IC(0) block `unit` of level 1 (one wavefront, lane = coarse column X over fine
+// columns 2X, 2X+1; fine rows 2 y0 .. 2 y0 + 2 MC_ICYC - 1).  The band's fine columns start
+// at a multiple of 128, so block edges fall at lanes 0 / 31 / 32 / 63, and its fine rows
+// start at a multiple of 8, so it holds either the first or the last row of a block row.
+// A fine cell next to an edge gets t z_p of the cell across it (r - A z_p has +t z_p there).
+template <class T, bool HAS_T>
+__device__ __forceinline__ void fix_smooth_unit(const PartD& C, int unit) {
+  static_assert(2 * MC_ICYC <= MC_ICY && MC_ICY % (2 * MC_ICYC) == 0 && 2 * MC_TX == 128,
+                "a level-1 block covers whole halves of finest IC(0) blocks");
+  constexpr int R = MC_ICYC, FR = 2 * R;
+  const IcBlkR<R> B(C, unit);
+  const int lane = threadIdx.x & 63;
+  const int nx = C.mg_fnx, ny = C.mg_fny;
+  const T* zf = (const T*)C.mg_fzp;
+  const T* edz = (const T*)C.mg_fedz;
+  const float* edt = C.mg_fedt;
+  T* rcp = (T*)C.mg_r;
+  const int fxb = 2 * (B.cx - lane);   // the band's first fine column
+  const int fy0 = 2 * B.y0;            // its first fine row
+  const int kb = fxb / MC_TX;          // IC(0) block column of fxb
+  double rc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) rc[k] = B.act(k) ? (double)rcp[B.cell(k)] : 0.0;
+  // vertical edges: (block across, its column 0 / 1 = first / last, face's block)
+  int kz = -1, cz = 0, kt = 0;
+  if (lane == 0 && kb >= 1 && fxb < nx) kz = kb - 1, cz = 1, kt = kb - 1;
+  if (lane == 31 && fxb + MC_TX < nx) kz = kb + 1, cz = 0, kt = kb;
+  if (lane == 32 && fxb + MC_TX < nx) kz = kb, cz = 1, kt = kb;
+  if (lane == 63 && fxb + 2 * MC_TX < nx) kz = kb + 2, cz = 0, kt = kb + 1;
+  if (kz >= 0) {
+#pragma unroll
+    for (int j = 0; j < FR; ++j) {
+      const int fy = fy0 + j;
+      if (fy < ny)
+        rc[j >> 1] += (double)edt[(long)kt * ny + fy] * (double)edz[((long)kz * ny + fy) * 2 + cz];
+    }
+  }
+  // horizontal edge: the band's first fine row is a block's first row (south neighbour
+  // across), or its last fine row is a block's last row (north neighbour across)
+  const bool south = (fy0 % MC_ICY) == 0;
+  const int fyc = south ? fy0 : fy0 + FR - 1;    // the fine row next to the edge
+  const int fya = south ? fy0 - 1 : fy0 + FR;    // the row across it
+  const int fyt = south ? fy0 - 1 : fy0 + FR - 1;  // the row whose north face it is
+  const int k = south ? 0 : R - 1;
+  if (fya >= 0 && fya < ny && fyc < ny) {
+    const T tc = (T)C.mg_ftc;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int fx = 2 * B.cx + c;
+      if (fx < nx) {
+        const double t = HAS_T ? (double)C.mg_fty32[(long)fyt * nx + fx] : (double)tc;
+        rc[k] += t * (double)zf[(long)fya * nx + fx];
+      }
+    }
+  }
+  T rv[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    rv[q] = B.act(q) ? (T)rc[q] : (T)0;
+    if (B.act(q)) rcp[B.cell(q)] = rv[q];
+  }
+  double dz = 0.0, dr = 0.0;
+  ic0_block<T, R>(C, B, rv, (T*)C.mg_zp, dz, dr);
+}
+
 // (Every V-cycle kernel skips systems whose solve has ended: the iterations launched past
 // convergence in a replayed chunk then cost only their launches.  The done flag is found
 // from the tile alone.  `sys` is null for a plain application of the preconditioner.)
@@ -1894,6 +2068,22 @@ k_mg_restrict_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ t
   for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) {
     if (C.mg_fhas_t) restrict_smooth_unit<T, true>(C, u);
     else restrict_smooth_unit<T, false>(C, u);
+  }
+}
+
+// completion of the restriction into level 1 and its pre-smoothing, after a fused finest
+// pre-smoothing (the same level-1 IC(0) blocks as k_mg_restrict_smooth)
+template <class T>
+__global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_mg_fix_smooth(const PartD* __restrict__ parts, const Tile* __restrict__ tiles,
+                SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  if (sys && ld_flag(&sys[t.sys].done)) return;
+  const PartD& C = parts[t.part];
+  for (int u = t.t0 + (int)(threadIdx.x >> 6); u < t.t1; u += 4) {
+    if (C.mg_fhas_t) fix_smooth_unit<T, true>(C, u);
+    else fix_smooth_unit<T, false>(C, u);
   }
 }
 

@@ -35,6 +35,9 @@ def test_algorithmic_bytes_per_cell(precision, w):
     assert g("B", precision, "jacobi", True) == 7 * w
     assert g("P", precision, "mg", True) == 3 * w + w / 4 + 16
     assert g("P", precision, "mg", False) == 3 * w + w / 4 + 8
+    # fused with the restriction into level 1: + FP32 diagonal, a quarter word of r_c and
+    # the block edges (two words and 4 B per 64 cells)
+    assert g("B", precision, "mg", True, fused=True) == 7 * w + 16 + w / 4 + (2 * w + 4) / 64
 
 
 def test_roofline_from_samples():
@@ -71,6 +74,13 @@ def test_vcycle_levels_and_bytes():
     assert np.isclose(b3["RS"], n[0] * 20 + n[1] * 28 + sum(n[l - 1] * 28 + n[l] * 28
                                                           for l in (2, 3)))
     assert b3["R"] == 0
+    # fused: level 1 reads and writes r_c, writes z_p, reads its factor, plus one fine edge
+    # row in 8 (a word and 4 B per fine column) and 3 edge columns per 128 fine columns
+    bf = bench.vcycle_bytes(2048, 2048, "fp64", True, nlev=3, fused=True)
+    assert np.isclose(bf["RS"], n[1] * (36 + 6 + 24 * 12 / 256)
+                      + sum(n[l - 1] * 28 + n[l] * 28 for l in (2, 3)))
+    assert bench.mg_fused(2048, 2048) and not bench.mg_fused(64, 64)
+    assert not bench.mg_fused(2048, 2048, dim=3) and not bench.mg_fused(2048, 2048, nlev=0)
     w = bench.working_launches([[7, 3], [5, 9]], "mg", [3, 6], [(2048, 2048), (2048, 2048)])
     # 7 + 9 iterations; 5 levels above the tail in the deeper hierarchy, which has a tail
     assert w["A"] == 16 and w["RS"] == 16 * 5 and w["TAIL"] == 16 and w["R"] == 16

@@ -364,6 +364,29 @@ def test_mixed_precision_mg(name):
         assert err < 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["rect300x270", "deep300x270", "ragged200", "three70"])
+def test_fused_restriction_matches_unfused(name, prec, monkeypatch):
+    """Inside PCG the update kernel forms the finest level's in-block share of the
+    restriction into level 1 and the level-1 kernel adds the couplings across the block
+    edges; the same cycle with the restriction kernel doing it all (MCDEC_MG_FUSE=0) gives the
+    same iterations and states up to rounding."""
+    print(f"\n[mg fused restriction {name} {prec}]", flush=True)
+    p = MG_CASES[name]()
+    kw = dict(precond="mg", precision=prec)
+    kw.update(dict(tol=1e-12) if prec == "fp64" else dict(outer_tol=1e-12, inner_tol=1e-5))
+    out = {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("MCDEC_MG_FUSE", fuse)
+        with mcdec.Problem(p, **kw) as g:
+            rep = g.step(3)
+            out[fuse] = (rep["iters"], np.concatenate(g.get_states()))
+    print(out["0"][0], out["1"][0], rel(out["1"][1], out["0"][1]))
+    for a, b in zip(out["0"][0], out["1"][0]):
+        assert abs(a - b) <= 1, (out["0"][0], out["1"][0])
+    assert rel(out["1"][1], out["0"][1]) < 1e-10
+
+
 def test_mg_fewer_iterations_than_block_ic0():
     """On a 300 x 270 lognormal grid with a long time step (diffusion dominates storage,
     k tau / h^2 of order 100) the V-cycle needs well under half the PCG iterations of
