@@ -69,12 +69,12 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "975b53ffc6ff4087", "fetch_kib": 83487.6,
-                        "write_kib": 65602.8, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "975b53ffc6ff4087", "fetch_kib": 90357.0,
-                        "write_kib": 98320.6, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "975b53ffc6ff4087", "fetch_kib": 87233.9,
-                        "write_kib": 32800.0, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "A"): {"sources": "bed4384f78478dc0", "fetch_kib": 83299.2,
+                        "write_kib": 65552.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "bed4384f78478dc0", "fetch_kib": 110905.2,
+                        "write_kib": 107788.1, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "bed4384f78478dc0", "fetch_kib": 82495.2,
+                        "write_kib": 32848.1, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
 def log(*a):
@@ -120,10 +120,11 @@ def grid_bytes_per_cell(kernel, precision, precond, has_t, dim=2, fused=False):
     return 7 * w
 
 
-def mg_fused(nx, ny, nlev=None, dim=2):
+def mg_fused(nx, ny, nlev=None, dim=2, precision="fp64"):
     """The update kernel forms the finest level's in-block share of the restriction into
-    level 1 (2-D V-cycles whose level 1 is above the tail; MCDEC_MG_FUSE=0 turns it off)."""
-    if dim != 2 or os.environ.get("MCDEC_MG_FUSE", "1") == "0":
+    level 1 (FP64 solves of 2-D V-cycles whose level 1 is above the tail; MCDEC_MG_FUSE=0
+    turns it off)."""
+    if dim != 2 or precision != "fp64" or os.environ.get("MCDEC_MG_FUSE", "1") == "0":
         return False
     lv = mg_levels(nx, ny)
     if len(lv) < 2 or (nlev is not None and nlev < 1):
@@ -347,7 +348,7 @@ def step_bytes(p, rep, precision, precond, nlev=None):
         has_t = p.omega[c].k is not None or dim == 3
         it = rep["iters"][c]
         nl = None if nlev is None else nlev[c]
-        fused = precond == "mg" and mg_fused(p.nx, p.ny, nl, dim)
+        fused = precond == "mg" and mg_fused(p.nx, p.ny, nl, dim, precision)
         for k in ("A", "B", "P"):
             if k in out:
                 out[k] += it * p.ncell * grid_bytes_per_cell(k, precision, precond, has_t, dim,

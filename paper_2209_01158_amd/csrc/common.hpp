@@ -76,6 +76,7 @@ struct PartD {
   int ex;            // EX split: diagonal excludes S, RHS subtracts S p^{n-1}
   int extrap;        // initial guess 2 p^{n-1} - p^{n-2} (x holds p^{n-2} on entry), else p^{n-1}
   int has_t;         // grid: per-face conductance arrays (0 = constant tconst)
+  int fp32;          // the PCG vectors are FP32 (inner solve of FP64 refinement)
   int n_omega;
   int other;         // (grid, 3C) part index of the other Omega continuum in this table or -1
   int frac;          // (grid) part index of the fracture part in this table or -1

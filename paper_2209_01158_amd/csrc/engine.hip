@@ -694,6 +694,7 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.mg_prev = -1;
   q.mg_slot = slot0B + C.blocks[1];
   q.mg_zp = fp32 ? (void*)C.zpre32 : (void*)C.zpre;
+  q.fp32 = fp32 ? 1 : 0;
   q.mg_edz = C.mg_edz;
   q.mg_edt = C.mg_edt;
   if (C.kind == PART_GRID) {
@@ -733,7 +734,9 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
 // parts' own pointers are final: a caller may have redirected r or z of a finest part).
 static void link_mg(std::vector<PartD>& parts) {
   // the update kernel forms the finest level's share of the restriction into level 1 when
-  // that level is smoothed by its own kernel (MCDEC_MG_FUSE=0: the restriction kernel does it all)
+  // that level is smoothed by its own kernel, in FP64 solves (an FP32 update kernel moves half
+  // the bytes, and its added latency outweighs the bytes it saves); MCDEC_MG_FUSE=0: the
+  // restriction kernel does it all
   const bool fuse = env_flag("MCDEC_MG_FUSE", true);
   for (auto& q : parts) {
     if (q.kind != PART_GRID) continue;
@@ -745,7 +748,7 @@ static void link_mg(std::vector<PartD>& parts) {
       const PartD& c = parts[q.mg_next];
       q.mg_e = c.mg_z;
       q.mg_cnx = c.nx;
-      q.mg_fuse = fuse && q.mg_level == 0 && q.plane == 0 && q.mg_edz &&
+      q.mg_fuse = fuse && !q.fp32 && q.mg_level == 0 && q.plane == 0 && q.mg_edz &&
                   (long)c.n > mg_tail_cells();
     }
     if (q.mg_level > 0) {

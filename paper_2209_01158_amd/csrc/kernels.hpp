@@ -1284,7 +1284,8 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
       // share of the restriction into level 1, when that level is not in the small tail)
       ic0_block_restrict_any<T>(parts, P, B, rv, (const T*)r,
                                 P.mg_next >= 0 ? (T*)P.mg_zp : z,
-                                P.mg_fuse != 0, zstash + (threadIdx.x >> 6) * MC_ICY * 64,
+                                P.mg_fuse != 0 && P.mg_next >= 0,
+                                zstash + (threadIdx.x >> 6) * MC_ICY * 64,
                                 dstash + (threadIdx.x >> 6) * MC_ICY * 64,
                                 o[0], o[1]);
     });

@@ -81,6 +81,7 @@ def test_vcycle_levels_and_bytes():
                       + sum(n[l - 1] * 28 + n[l] * 28 for l in (2, 3)))
     assert bench.mg_fused(2048, 2048) and not bench.mg_fused(64, 64)
     assert not bench.mg_fused(2048, 2048, dim=3) and not bench.mg_fused(2048, 2048, nlev=0)
+    assert not bench.mg_fused(2048, 2048, precision="mixed")
     w = bench.working_launches([[7, 3], [5, 9]], "mg", [3, 6], [(2048, 2048), (2048, 2048)])
     # 7 + 9 iterations; 5 levels above the tail in the deeper hierarchy, which has a tail
     assert w["A"] == 16 and w["RS"] == 16 * 5 and w["TAIL"] == 16 and w["R"] == 16

@@ -367,10 +367,11 @@ def test_mixed_precision_mg(name):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("name", ["rect300x270", "deep300x270", "ragged200", "three70"])
 def test_fused_restriction_matches_unfused(name, prec, monkeypatch):
-    """Inside PCG the update kernel forms the finest level's in-block share of the
+    """Inside FP64 PCG the update kernel forms the finest level's in-block share of the
     restriction into level 1 and the level-1 kernel adds the couplings across the block
     edges; the same cycle with the restriction kernel doing it all (MCDEC_MG_FUSE=0) gives the
-    same iterations and states up to rounding."""
+    same iterations and states up to rounding (mixed precision: the FP32 inner solves keep
+    the separate restriction, so both runs agree as well)."""
     print(f"\n[mg fused restriction {name} {prec}]", flush=True)
     p = MG_CASES[name]()
     kw = dict(precond="mg", precision=prec)
