@@ -69,11 +69,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "bed4384f78478dc0", "fetch_kib": 83299.2,
-                        "write_kib": 65552.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "bed4384f78478dc0", "fetch_kib": 110905.2,
-                        "write_kib": 107788.1, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "bed4384f78478dc0", "fetch_kib": 82495.2,
+    ("C2", "mg", "A"): {"sources": "0d49f5bcd4d66928", "fetch_kib": 83313.6,
+                        "write_kib": 65552.4, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "0d49f5bcd4d66928", "fetch_kib": 110768.7,
+                        "write_kib": 107787.9, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "0d49f5bcd4d66928", "fetch_kib": 82506.7,
                         "write_kib": 32848.1, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
@@ -185,7 +185,9 @@ KERNEL_NAMES = {
     "A": "k_pcg_A<{tp},{pn},GRID> (p = z + beta p; q = A p; partial p.q)",
     "B": "k_pcg_B<{tp},{pn},GRID> (x += alpha p; r -= alpha q; z = M^-1 r; partial r.z, r.r)",
     "P": "k_mg_post<{tp},FINAL> (z = z_p + P e + M^-1 (r - A (z_p + P e)); partial r.z)",
-    "RS": "k_mg_restrict_smooth<{tp}> (all coarse levels: r_c = P^T (r - A z_p); z_p = M^-1 r_c)",
+    "RS": "k_mg_restrict_smooth<{tp}> / k_mg_fix_smooth<{tp}> (all coarse levels: r_c = P^T "
+          "(r - A z_p); z_p = M^-1 r_c; level 1 of an FP64 solve completes the update kernel's "
+          "in-block restriction)",
     "PC": "k_mg_post_c<{tp}> (all coarse levels: z = z_p + P e + M^-1 (r - A (z_p + P e)))",
     "TAIL": "k_mg_tail<{tp}> (levels of <= 1024 cells and the dense coarsest solve, one "
             "workgroup)",
