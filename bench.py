@@ -975,9 +975,11 @@ def main():
     ap.add_argument("--precond", default=None, choices=["jacobi", "bic0", "mg"])
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed"])
     ap.add_argument("--tol", type=float, default=None)
-    ap.add_argument("--warm-start", default=None, choices=["extrapolate", "previous"],
+    ap.add_argument("--warm-start", default=None,
+                    choices=["extrapolate", "previous", "adaptive"],
                     help="PCG initial guess: linear extrapolation of the last two layers "
-                         "(default) or the previous layer")
+                         "(default), the previous layer, or the extrapolation order (0-3) "
+                         "that best predicted the previous layer")
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="mixed: inner FP32 PCG tolerance relative to the outer residual "
                          "(default 1e-4 with the V-cycle, whose passes are bounded by FP32 "

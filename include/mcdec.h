@@ -148,10 +148,14 @@ typedef struct {
                             estimated from the observed residual decrease); the device stops
                             each system at its own tolerance either way                        */
   int32_t tile_rows;     /* grid tile height in rows: 0 (default) or 32                         */
-  int32_t warm_start;    /* PCG initial guess of a layer: 0 (default) linear extrapolation
-                            2 p^{n-1} - p^{n-2} once the previous two layers were computed by
-                            this problem (else p^{n-1}); 1 always p^{n-1}.  Changes iteration
-                            counts only, never the tolerance the solution meets             */
+  int32_t warm_start;    /* PCG initial guess of a layer: 0 (default) the linear extrapolation
+                            2 p^{n-1} - p^{n-2}; 1 always p^{n-1}; 2 adaptive: the order (0-3)
+                            of the polynomial extrapolation of the last layers that best
+                            predicted the previous layer (the problem keeps three more states
+                            per continuum).  Extrapolation uses only layers this problem
+                            computed in a row (after creation, mc_set_state or a failed layer
+                            it starts from p^{n-1}).  Changes iteration counts only, never the
+                            tolerance the solution meets                                    */
   int32_t small_max;     /* 0 (default) or N >= 1: when every continuum has at most N unknowns,
                             the decoupled schemes (D, L, U, EX) in FP64 with MC_JACOBI solve
                             each continuum by one workgroup running its whole PCG in a single
@@ -171,6 +175,8 @@ typedef struct {
   double seconds;        /* host wall time of the call                                         */
   int64_t step;          /* time layers completed since creation or the last mc_set_time       */
   int32_t failed;        /* -1, or the continuum whose solve failed                            */
+  int32_t warm_order[3]; /* order of the warm start's extrapolation in the last step per
+                            continuum (0 = the previous layer; see mc_options.warm_start)    */
 } mc_report;
 
 typedef struct {

@@ -29,6 +29,9 @@
 enum { PART_GRID = 0, PART_GRAPH = 1 };
 enum { PREC_JACOBI = 0, PREC_BIC0 = 1 };
 enum { ST_RUN = 0, ST_CONV = 1, ST_NOCONV = 2, ST_BREAK = 3 };
+// warm start of a layer's PCG: 2 p^{n-1} - p^{n-2}; p^{n-1}; the order (0-3) of the polynomial
+// extrapolation of the layer history that best predicted the previous layer
+enum { WS_LINEAR = 0, WS_PREVIOUS = 1, WS_ADAPTIVE = 2 };
 
 // Per-system state.  Reductions never cross workgroups inside a kernel: every kernel writes
 // one partial-sum slot per workgroup, and the next kernel in stream order has each of its
@@ -54,10 +57,12 @@ struct SysState {
   // and sets ka = kb + 1 for the next operator kernel
   int ka, kb;
   int mixed;            // inner solve of FP64 refinement: iteration 0 first tests the outer residual
-  int pad0;
+  int hist;             // layers computed in a row before the current one (warm start)
   double rscale;        // refinement: power-of-two scale of the FP32 residual of the inner solve
   int nslotsA;          // workgroups (partial slots) of this system in an operator launch
   int nslotsB;          // ... in an update / init / residual launch (its own tiling)
+  int wsorder;          // extrapolation order of the current layer's warm start
+  int pad1;
   double* partA;        // [nslotsA * MC_SLOT] written by operator kernels
   double* partB;        // [nslotsB * MC_SLOT] written by update / init / residual kernels
 };
@@ -74,7 +79,7 @@ struct PartD {
   int slot0A, slot0B; // first partial slot of this part inside its system (per tiling)
   int coupled;       // operator includes the off-diagonal transfer blocks (coupled scheme)
   int ex;            // EX split: diagonal excludes S, RHS subtracts S p^{n-1}
-  int extrap;        // initial guess 2 p^{n-1} - p^{n-2} (x holds p^{n-2} on entry), else p^{n-1}
+  int extrap;        // warm start (WS_*): the PCG initial guess of a layer (k_rhs)
   int has_t;         // grid: per-face conductance arrays (0 = constant tconst)
   int fp32;          // the PCG vectors are FP32 (inner solve of FP64 refinement)
   int n_omega;
@@ -178,6 +183,7 @@ struct PartD {
   void* p2;          // and writes the other buffer (neighbouring tiles still read the old one)
   void* q;
   void* z;
+  double* hx[3];           // (WS_ADAPTIVE) states p^{n-3}, p^{n-4}, p^{n-5} of the layer history
   double* b;               // FP64 right-hand side
   double* r64;             // FP64 residual scratch (refinement)
   double* x64;             // FP64 iterate (refinement)

@@ -358,6 +358,7 @@ struct Cont {  // one continuum
   float* mg_edt = nullptr;
   // state and PCG vectors
   double* ps[2] = {nullptr, nullptr};
+  double* hx[3] = {nullptr, nullptr, nullptr};   // (adaptive warm start) p^{n-3}, p^{n-4}, p^{n-5}
   double *b = nullptr, *r = nullptr, *p = nullptr, *p2 = nullptr, *q = nullptr, *z = nullptr;
   float *x32 = nullptr, *r32 = nullptr, *p32 = nullptr, *p232 = nullptr, *q32 = nullptr,
         *z32 = nullptr;
@@ -644,7 +645,8 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.slot0A = slot0A;
   q.slot0B = slot0B;
   q.ex = P->X.opt.scheme == MC_SCHEME_EX;
-  q.extrap = P->X.opt.warm_start == 0 && P->hist >= 1;
+  q.extrap = P->X.opt.warm_start;   // WS_* (the history depth comes from the system record)
+  for (int k = 0; k < 3; ++k) q.hx[k] = C.hx[k];
   q.has_t = C.has_t;
   q.n_omega = P->n_omega;
   q.other = -1;
@@ -1254,6 +1256,14 @@ static void set_slot_counts(mc_problem* P, SysState* hs) {
   hs[P->ncont].nslotsB = cb;
 }
 
+// The layer history the adaptive warm start keeps (three more states per continuum).
+static void ensure_history(mc_problem* P) {
+  if (P->X.opt.warm_start != WS_ADAPTIVE) return;
+  for (auto& C : P->cont)
+    for (int k = 0; k < 3; ++k)
+      if (!C.hx[k]) C.hx[k] = P->mem.alloc<double>(C.n);
+}
+
 static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o) {
   std::string m = validate_desc(d);
   if (!m.empty()) fail(m);
@@ -1340,6 +1350,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     if (p0) HIPCHK(hipMemcpyAsync(C.ps[0], p0, C.n * sizeof(double), hipMemcpyHostToDevice, s));
     else HIPCHK(hipMemsetAsync(C.ps[0], 0, C.n * sizeof(double), s));
   }
+  ensure_history(P);
   // systems: one per continuum + the coupled one
   const int nsys = P->ncont + 1;
   exec_sys_capacity(P->X, nsys);
@@ -1717,7 +1728,10 @@ static void advance_t(Exec& X, Group& G) {
       launch_seq(X, G, (long)PREC << 3 | (long)G.assemble << 2 | 0, [&] {
         hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys,
                            G.s0, G.s1);
-        if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+        if (G.assemble) {
+          launch2(G, 0, k_extrap_err<PART_GRID>, k_extrap_err<PART_GRAPH>, X.sys);
+          launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>, X.sys);
+        }
         launch2(G, 1, k_init<PREC, PART_GRID>, k_init<PREC, PART_GRAPH>, X.sys);
         if (G.kinds & 1) launch_vcycle<double>(*G.T, G.s, X.sys, true);
         if (G.kinds & 2) launch_schur<double>(X, *G.T, G.s);
@@ -1742,7 +1756,10 @@ static void advance_t(Exec& X, Group& G) {
     launch_seq(X, G, (long)PREC << 3 | (long)G.assemble << 2 | 1, [&] {
       hipLaunchKernelGGL(k_reset, dim3(cdiv(G.s1 - G.s0, 64)), dim3(64), 0, G.s, X.sys, G.s0,
                          G.s1);
-      if (G.assemble) launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+      if (G.assemble) {
+        launch2(G, 0, k_extrap_err<PART_GRID>, k_extrap_err<PART_GRAPH>, X.sys);
+        launch2(G, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>, X.sys);
+      }
       launch2(G, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
       launch2(G, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
       if (G.kinds & 1) launch_vcycle<float>(*G.T, G.s, X.sys, true);
@@ -1849,12 +1866,13 @@ static void sys_params(const Exec& X, SysState& S, double tol, bool mixed) {
 }
 
 // Solve parameters of the records [s0, s1), set by a kernel in stream order (no host wait).
-static void set_sys_params(Exec& X, int s0, int s1, double tol, bool mixed) {
+// hist: layers the problem computed in a row before this one (the warm start's history)
+static void set_sys_params(Exec& X, int s0, int s1, double tol, bool mixed, int hist = 0) {
   SysState S;
   std::memset(&S, 0, sizeof(S));
   sys_params(X, S, tol, mixed);
   hipLaunchKernelGGL(k_set_params, dim3(cdiv(s1 - s0, 64)), dim3(64), 0, X.stream, X.sys, s0,
-                     s1, S.tol2, S.otol2, S.max_iter, S.max_outer, S.mixed);
+                     s1, S.tol2, S.otol2, S.max_iter, S.max_outer, S.mixed, hist);
   HIPCHK(hipGetLastError());
 }
 
@@ -1906,6 +1924,7 @@ static mc_status fill_report(const Exec& X, const std::vector<int>& systems,
       rep->converged[c] = status == ST_CONV;
       rep->relres[c] = mixed ? (S.obb > 0 ? std::sqrt(S.orr / S.obb) : std::sqrt(S.orr))
                              : (S.bb > 0 ? std::sqrt(S.rr / S.bb) : std::sqrt(S.rr));
+      rep->warm_order[c] = S.wsorder;
     }
     if (status != ST_CONV && st == MC_OK) {
       st = status == ST_NOCONV ? MC_ENOCONV : MC_EBREAKDOWN;
@@ -1923,6 +1942,7 @@ static void fill_coupled_report(int ncont, mc_report* rep) {
     rep->outer[c] = rep->outer[0];
     rep->converged[c] = rep->converged[0];
     rep->relres[c] = rep->relres[0];
+    rep->warm_order[c] = rep->warm_order[0];
   }
 }
 
@@ -1943,8 +1963,9 @@ static bool small_path(const mc_problem* P) {
 // [s0, s0 + nsys) are read back.
 static void small_solve(mc_problem* P, Table& T, int s0, int nsys) {
   Exec& X = P->X;
-  launch_all(X.stream, T, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
-  set_sys_params(X, s0, s0 + nsys, X.opt.tol, false);
+  set_sys_params(X, s0, s0 + nsys, X.opt.tol, false, P->hist);
+  launch_all(X.stream, T, 0, k_extrap_err<PART_GRID>, k_extrap_err<PART_GRAPH>, X.sys);
+  launch_all(X.stream, T, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>, X.sys);
   // LDS-resident form when every system fits: 2-D grids of at most 4096 cells, fracture
   // systems whose p and CSR take at most 64 KiB
   size_t lds = 0;
@@ -2003,14 +2024,14 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
     }
   } else if (sch == MC_SCHEME_COUPLED) {
     Table& T = upload_table(P, "coupled" + std::to_string(P->cur), coupled_parts(P, P->ncont, 0));
-    set_sys_params(X, P->ncont, P->ncont + 1, X.opt.tol, false);
+    set_sys_params(X, P->ncont, P->ncont + 1, X.opt.tol, false, P->hist);
     solve_table(X, T, P->ncont, P->ncont + 1, true, false, false);
     st = fill_report(X, {P->ncont}, {0}, rep, false);
     fill_coupled_report(P->ncont, rep);
   } else if (sch == MC_SCHEME_D || sch == MC_SCHEME_EX) {
     Table& T = upload_table(P, std::string(mixed ? "dm" : "d") + std::to_string(P->cur),
                             decoupled_parts(P, all, mixed));
-    set_sys_params(X, 0, P->ncont, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
+    set_sys_params(X, 0, P->ncont, mixed ? X.opt.inner_tol : X.opt.tol, mixed, P->hist);
     solve_table(X, T, 0, P->ncont, true, mixed, true);
     st = fill_report(X, all, all, rep, mixed);
   } else {
@@ -2025,7 +2046,7 @@ static mc_status step_once(mc_problem* P, mc_report* rep) {
       for (size_t j = 0; j < k; ++j) parts[0].tsrc[order[j]] = P->cont[order[j]].ps[1 - P->cur];
       Table& T = upload_table(P, std::string(mixed ? "sm" : "s") + std::to_string(c) + "_" +
                                      std::to_string(P->cur), parts);
-      set_sys_params(X, c, c + 1, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
+      set_sys_params(X, c, c + 1, mixed ? X.opt.inner_tol : X.opt.tol, mixed, P->hist);
       solve_table(X, T, c, c + 1, true, mixed, false);
       mc_status s1 = fill_report(X, {c}, {c}, rep, mixed);
       if (s1 != MC_OK) {
@@ -2087,6 +2108,7 @@ static mc_status batch_step_once(mc_batch* B, mc_problem* const* probs, int n, m
     S.partB = P->partB[sI];
     S.nslotsA = nA;
     S.nslotsB = nB;
+    S.hist = P->hist;
     S.done = 1;
     sys_params(X, S, mixed ? X.opt.inner_tol : X.opt.tol, mixed);
     hs.push_back(S);
@@ -2200,7 +2222,7 @@ static double time_tiling(mc_problem* P, int c, int fam, int iters) {
   S.done = 1;
   HIPCHK(hipMemcpyAsync(X.sys + c, &S, sizeof(S), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, X.sys, c, c + 1);
-  launch_all(s, Tb, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>);
+  launch_all(s, Tb, 0, k_rhs<PART_GRID>, k_rhs<PART_GRAPH>, X.sys);
   if (fp32) {
     launch_all(s, Tb, 0, k_residual64<PART_GRID>, k_residual64<PART_GRAPH>, X.sys);
     launch_all(s, Tb, 1, k_residual<PREC, PART_GRID>, k_residual<PREC, PART_GRAPH>, X.sys);
@@ -2361,6 +2383,8 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
       A(8 * n);                   // mt
     }
     for (int k = 0; k < 7; ++k) A(8 * n);   // two states, b, r, p, p2, q
+    if (o.warm_start == WS_ADAPTIVE)
+      for (int k = 0; k < 3; ++k) A(8 * n);   // the adaptive warm start's layer history
     A(8 * MC_SLOT * slots);       // partials of its decoupled system
     A(8 * MC_SLOT * slots);
     if (grid && o.precond == MC_MG) {   // V-cycle levels
@@ -2897,10 +2921,10 @@ mc_status mc_assemble_rhs(mc_problem* P, int32_t alpha, double* b) {
   std::vector<PartD> parts = mc::decoupled_parts(P, {alpha}, false);
   parts[0].b = b;
   parts[0].x64 = P->cont[alpha].r;    // warm-start copy goes to scratch
-  parts[0].extrap = 0;
+  parts[0].extrap = WS_PREVIOUS;      // (no history kept or read)
   parts[0].coupled = 0;
   mc::Table& T = mc::upload_table(P, "rhs" + std::to_string(alpha), parts);
-  mc::launch_all(P->X.stream, T, 0, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>);
+  mc::launch_all(P->X.stream, T, 0, mc::k_rhs<PART_GRID>, mc::k_rhs<PART_GRAPH>, P->X.sys);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(P->X.stream));
   return MC_OK;
@@ -2942,8 +2966,10 @@ mc_status mc_set_options(mc_problem* P, const mc_options* o) {
   const mc_options& cur = P->X.opt;
   const bool rebuild = (o->scheme == MC_SCHEME_EX) != (cur.scheme == MC_SCHEME_EX) ||
                        (o->precision != cur.precision) || (o->precond != cur.precond);
+  if (o->warm_start != cur.warm_start) P->hist = 0;   // the history is kept per mode
   P->X.opt = *o;
   P->X.opt.stream = P->X.stream;
+  mc::ensure_history(P);
   if (rebuild) mc::build_coefficients(P);
   mc::clear_tables(P);
   // the update tiling depends on the preconditioner: refresh the slot counts

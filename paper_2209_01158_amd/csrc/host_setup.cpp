@@ -106,8 +106,9 @@ std::string validate_options(const mc_options& o) {
   if (o.check_every < 0) return "check_every must be >= 0";
   if (o.tile_rows != 0 && o.tile_rows != 32)
     return "tile_rows must be 0 (default) or 32 in this build";
-  if (o.warm_start != 0 && o.warm_start != 1)
-    return "warm_start must be 0 (extrapolate) or 1 (previous layer)";
+  if (o.warm_start < 0 || o.warm_start > 2)
+    return "warm_start must be 0 (linear extrapolation), 1 (previous layer) or 2 (adaptive "
+           "extrapolation)";
   if (o.small_max < 0) return "small_max must be >= 0";
   return "";
 }

@@ -813,16 +813,87 @@ __device__ __forceinline__ void schur_gather(const PartD& P, int tile, const T* 
 // right-hand side assembly, always FP64 (Section 3.3, D-scheme; Section 3.2, coupled):
 // decoupled  b = M/tau p_old + F + sum_b Q_ab p_b   [EX: - S p_old]
 // coupled    b = M/tau p_old + F
-// and the warm start x = p_old, or 2 p_old - p_(n-2) when extrapolating (x holds p_(n-2) on
-// entry)
+// and the warm start of the layer's PCG (x holds p^{n-2} on entry).  The warm start changes
+// iteration counts only, never the tolerance the solution meets.
 // ------------------------------------------------------------------------------------
+// Polynomial extrapolation of order k from the history g[0] = p^{n-1}, g[1] = p^{n-2}, ...
+__device__ __forceinline__ double extrapolate(int k, double g0, double g1, double g2,
+                                              double g3) {
+  switch (k) {
+    case 1: return 2.0 * g0 - g1;
+    case 2: return 3.0 * g0 - 3.0 * g1 + g2;
+    case 3: return 4.0 * g0 - 6.0 * g1 + 4.0 * g2 - g3;
+    default: return g0;
+  }
+}
+
+// Adaptive warm start (WS_ADAPTIVE), first pass: how well each extrapolation order k = 0 ..
+// min(hist - 1, 3) predicts the previous layer p^{n-1} from the layers before it,
+// sum (p^{n-1} - E_k(p^{n-2}, ...))^2 per system -> partA slots (4 components).  k_rhs picks
+// the order with the least error (the lower order on ties): high orders win once the
+// solution varies smoothly in time and lose in the first layers after a jump.
 template <int KIND>
-__global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ parts,
-                                                  const Tile* __restrict__ tiles) {
+__global__ void __launch_bounds__(MC_BLOCK) k_extrap_err(const PartD* __restrict__ parts,
+                                                         const Tile* __restrict__ tiles,
+                                                         SysState* __restrict__ sys) {
   const Tile t = tiles[blockIdx.x];
   if (t.part < 0) return;
   const PartD& P = parts[t.part];
+  SysState& S = sys[P.sys];
+  if (P.extrap != WS_ADAPTIVE || S.hist < 2) return;   // uniform over the system
+  const int kmax = min(S.hist - 1, 3);
+  const double* x = P.x64;   // p^{n-2}
+  double e[4] = {0.0, 0.0, 0.0, 0.0};
+  auto cell = [&](long i) {
+    const double g0 = P.pold[i], g1 = x[i];
+    const double g2 = kmax >= 1 ? P.hx[0][i] : 0.0;
+    const double g3 = kmax >= 2 ? P.hx[1][i] : 0.0;
+    const double g4 = kmax >= 3 ? P.hx[2][i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k <= kmax) {
+        const double d = g0 - extrapolate(k, g1, g2, g3, g4);
+        e[k] += d * d;
+      }
+  };
+  for_cells<KIND>(P, t, [&](int, int, long i) { cell(i); }, [&](int l) { cell(l); });
+  write_slot<4>(S.partA, S.nslotsA, t.slot, e);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ parts,
+                                                  const Tile* __restrict__ tiles,
+                                                  SysState* __restrict__ sys) {
+  const Tile t = tiles[blockIdx.x];
+  if (t.part < 0) return;
+  const PartD& P = parts[t.part];
+  SysState& Sy = sys[P.sys];
+  // the warm start's order: every workgroup of the system reaches the same one
+  const int hist = Sy.hist;
+  int order = 0;
+  if (P.extrap == WS_LINEAR || (P.extrap == WS_ADAPTIVE && hist == 1)) order = hist >= 1;
+  if (P.extrap == WS_ADAPTIVE && hist >= 2) {
+    const int kmax = min(hist - 1, 3);
+    double e[4];
+    reduce_slots<4>(Sy.partA, Sy.nslotsA, e, kmax + 1);
+    for (int k = 1; k <= kmax; ++k)
+      if (e[k] < e[order]) order = k;
+  }
+  if (t.slot == 0 && threadIdx.x == 0) Sy.wsorder = order;
+  // the adaptive warm start keeps the history: p^{n-3..n-5} <- p^{n-2..n-4}
+  const bool shift = P.extrap == WS_ADAPTIVE;
   double* x = P.x64;
+  auto guess = [&](long i, double po) {
+    const double g1 = x[i];
+    const double g2 = shift || order >= 2 ? P.hx[0][i] : 0.0;
+    const double g3 = shift || order >= 3 ? P.hx[1][i] : 0.0;
+    x[i] = extrapolate(order, po, g1, g2, g3);
+    if (shift) {
+      P.hx[2][i] = g3;
+      P.hx[1][i] = g2;
+      P.hx[0][i] = g1;
+    }
+  };
   for_cells<KIND>(
       P, t,
       [&](int, int, long i) {
@@ -846,7 +917,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ part
           if (P.ex) b -= S * po;
         }
         P.b[i] = b;
-        x[i] = P.extrap ? 2.0 * po - x[i] : po;
+        guess(i, po);
       },
       [&](int l) {
         const double po = P.pold[l];
@@ -863,7 +934,7 @@ __global__ void __launch_bounds__(MC_BLOCK) k_rhs(const PartD* __restrict__ part
           if (P.ex) b -= S * po;
         }
         P.b[l] = b;
-        x[l] = P.extrap ? 2.0 * po - x[l] : po;
+        guess(l, po);
       });
 }
 
@@ -2472,7 +2543,7 @@ __global__ void __launch_bounds__(NT) k_small_pcg_lds(const PartD* __restrict__ 
 
 // Solve parameters of the system records [s0, s1)
 __global__ void k_set_params(SysState* sys, int s0, int s1, double tol2, double otol2,
-                             int max_iter, int max_outer, int mixed) {
+                             int max_iter, int max_outer, int mixed, int hist) {
   const int s = s0 + blockIdx.x * blockDim.x + threadIdx.x;
   if (s < s1) {
     SysState& S = sys[s];
@@ -2481,6 +2552,7 @@ __global__ void k_set_params(SysState* sys, int s0, int s1, double tol2, double 
     S.max_iter = max_iter;
     S.max_outer = max_outer;
     S.mixed = mixed;
+    S.hist = hist;
   }
 }
 

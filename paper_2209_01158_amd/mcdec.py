@@ -33,7 +33,7 @@ REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 SCHEMES = {"D": 0, "coupled": 1, "L": 2, "U": 3, "EX": 4}
 PRECISIONS = {"fp64": 0, "mixed": 1}
 PRECONDS = {"jacobi": 0, "bic0": 1, "mg": 2}
-WARM_STARTS = {"extrapolate": 0, "previous": 1}
+WARM_STARTS = {"extrapolate": 0, "previous": 1, "adaptive": 2}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -66,13 +66,15 @@ class Options(C.Structure):
 class Report(C.Structure):
     _fields_ = [("n_cont", C.c_int32), ("iters", C.c_int32 * 3), ("outer", C.c_int32 * 3),
                 ("converged", C.c_int32 * 3), ("relres", C.c_double * 3),
-                ("seconds", C.c_double), ("step", C.c_int64), ("failed", C.c_int32)]
+                ("seconds", C.c_double), ("step", C.c_int64), ("failed", C.c_int32),
+                ("warm_order", C.c_int32 * 3)]
 
     def as_dict(self):
         n = self.n_cont
         return dict(iters=list(self.iters)[:n], outer=list(self.outer)[:n],
                     converged=list(self.converged)[:n], relres=list(self.relres)[:n],
-                    seconds=self.seconds, step=self.step, failed=self.failed)
+                    seconds=self.seconds, step=self.step, failed=self.failed,
+                    warm_order=list(self.warm_order)[:n])
 
 
 class Info(C.Structure):

@@ -458,16 +458,25 @@ def test_reports_are_deterministic():
 
 
 def test_warm_start_modes_and_history_reset():
-    """The extrapolated initial guess (default) and the previous-layer guess both meet the
-    oracle trajectory; a state change resets the layer history, so stepping after
-    set_states(p0) gives bitwise the layers of a fresh problem."""
+    """Every warm start (linear extrapolation, the default; the previous layer; adaptive
+    extrapolation) meets the oracle trajectory over 8 layers.  The adaptive mode's order stays
+    within the history it has: p^{n-1} at the first layer, linear at the second, then at most
+    min(n - 2, 3).  A state change resets the layer history, so stepping after set_states(p0)
+    gives bitwise the layers of a fresh problem."""
     p = CASES["ragged200"]()
-    ref = schemes.run(p, "D", 3, keep="all")
-    for ws in ("extrapolate", "previous"):
+    ref = schemes.run(p, "D", 8, keep="all")
+    for ws in ("extrapolate", "previous", "adaptive"):
         with mcdec.Problem(p, precond="mg", tol=1e-14, warm_start=ws) as g:
-            for n in range(1, 4):
-                g.step(1)
+            for n in range(1, 9):
+                rep = g.step(1)
                 assert rel(g.get_states(), ref[n]) < 1e-10, (ws, n)
+                for o in rep["warm_order"]:
+                    if ws == "previous":
+                        assert o == 0
+                    elif ws == "extrapolate":
+                        assert o == (1 if n >= 2 else 0)
+                    else:
+                        assert o == (0 if n == 1 else 1) if n <= 2 else 0 <= o <= min(n - 2, 3)
     with mcdec.Problem(p, precond="mg", tol=1e-12) as a, \
             mcdec.Problem(p, precond="mg", tol=1e-12) as b:
         a.step(3)
@@ -476,6 +485,26 @@ def test_warm_start_modes_and_history_reset():
         b.step(2)
         for x, y in zip(a.get_states(), b.get_states()):
             assert np.array_equal(x, y)
+
+
+def test_adaptive_warm_start_saves_iterations():
+    """On a smooth trajectory (300 x 270 lognormal grid, 16 layers) the adaptive warm start
+    settles on high extrapolation orders and needs fewer PCG iterations than the linear one
+    (the default); both meet the oracle."""
+    p = MG_CASES["rect300x270"]()
+    ref = schemes.run(p, "D", 16, keep="last")
+    its, orders = {}, {}
+    for ws in ("extrapolate", "adaptive"):
+        with mcdec.Problem(p, precond="mg", tol=1e-12, warm_start=ws) as g:
+            its[ws], orders[ws] = 0, []
+            for _ in range(16):
+                rep = g.step(1)
+                its[ws] += rep["iters"][0]
+                orders[ws].append(rep["warm_order"][0])
+            assert rel(g.get_states(), ref) < 1e-9, ws
+    print(its, orders)
+    assert its["adaptive"] < its["extrapolate"], its
+    assert max(orders["adaptive"][8:]) >= 2, orders
 
 
 # ------------------------------------------------------------------------------------
