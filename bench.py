@@ -58,7 +58,7 @@ DEFAULTS = {
     "C3": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=1,
                sample_every=4, inner_tol=1e-3),
     "C4": dict(precond="mg", precision="mixed", tol=1e-10, steps=50, coupled_steps=2,
-               sample_every=4),
+               sample_every=4, autotune=True),
     "C5": dict(precond="mg", precision="mixed", tol=1e-10, steps=0, coupled_steps=0),
     "3D": dict(precond="bic0", precision="fp64", tol=1e-10, steps=20, coupled_steps=2,
                sample_every=2),
@@ -579,7 +579,7 @@ def run_single(args, out):
                    f"{p.nf} fracture cells, tau={p.tau}, D-scheme {args.precision}, "
                    f"PCG {args.precond} tol {args.tol}", "dof": dof,
                    "precond": args.precond, "scheme": "D", "precision": args.precision,
-                   "warm_start": args.warm_start,
+                   "warm_start": args.warm_start, "autotuned": bool(args.autotune),
                    **({"inner_tol": args.inner_tol} if args.precision == "mixed" else {})},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)),
                        "p99": float(np.percentile(lat_ms, 99)), "max": float(lat_ms.max())},
@@ -996,7 +996,8 @@ def main():
     ap.add_argument("--small-max", type=int, default=None,
                     help="systems of at most this many unknowns run their whole PCG in one "
                          "workgroup (default 8192 for C1, else 0: off)")
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true", default=None,
+                    help="time the launch shapes per size class first (default for C4)")
     ap.add_argument("--layers", type=int, default=2,
                     help="NLMC: oversampling layers of the regions K_i^+")
     ap.add_argument("--sample-every", type=int, default=None,
@@ -1019,6 +1020,8 @@ def main():
             setattr(args, k, d[k])
     if args.sample_every is None:
         args.sample_every = d.get("sample_every", 32)
+    if args.autotune is None:
+        args.autotune = d.get("autotune", False)
     if args.small_max is None:
         args.small_max = d.get("small_max", 0)
     if args.inner_tol is None:
