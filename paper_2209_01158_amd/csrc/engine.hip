@@ -976,11 +976,16 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
   // transfer) at least MC_MG_DOMINANCE times the face conductances.  Block IC(0) nearly
   // solves such a level, so it is smoothed twice instead of corrected from coarser levels
   // (MCDEC_MG_DOMINANCE overrides the ratio, 0 = never stop early; MCDEC_MG_LEVELS caps the
-  // number of coarse levels).
+  // number of coarse levels).  The inner FP32 solves of mixed precision stop at a ratio of
+  // 2: they reduce the residual by 1e-3 at a time, which the deeper levels do not speed
+  // up, while a FP64 solve to 1e-10 over many layers needs them for the smooth part of the
+  // increments.
+  constexpr double dominance_mixed = 2.0;
   const long tail_n = mg_tail_cells();
   const int max_levels = std::max(1, env_int("MCDEC_MG_LEVELS", 1 << 20));
   const char* dom_env = std::getenv("MCDEC_MG_DOMINANCE");
-  const double dominance = dom_env ? std::atof(dom_env) : MC_MG_DOMINANCE;
+  const double dominance = dom_env ? std::atof(dom_env)
+                                  : mixed ? dominance_mixed : MC_MG_DOMINANCE;
   constexpr int dom_blocks = 128;
   double* dom_part = nullptr;
   bool stop = false;

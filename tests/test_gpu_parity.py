@@ -290,9 +290,46 @@ MG_CASES = {
     # (the storage-dominated cases above stop after their first coarse level)
     "deep300x270": lambda: media.rect_problem(300, 270, seed=5, tau=1e4),
     "strip1x700": lambda: media.rect_problem(1, 700, seed=6),      # 700 -> 350 -> 175
+    # level ratios (row sums over face conductances) 1.0, 4.0, 16 on levels 1-3: FP64
+    # solves stop at level 3 (1292 cells, above the tail), mixed precision at level 2
+    "mid300x270": lambda: media.rect_problem(300, 270, seed=5, tau=0.046),
     "ragged200": CASES["ragged200"],
     "three70": CASES["three70"],
 }
+
+
+def mg_depth(K, nx, ny, ratio):
+    """Coarse levels of the V-cycle for operator K: the hierarchy stops at the first level
+    above the 1024-cell tail whose row sums reach `ratio` times its face conductances
+    (both summed over the level), else it runs down to the dense coarsest level."""
+    full = precond.vcycle_setup(K, nx, ny)
+    for l in range(1, len(full)):
+        Kl = full[l]["K"]
+        if Kl.shape[0] <= 1024:
+            break
+        rs = float(np.asarray(Kl.sum(axis=1)).sum())
+        fs = float(-(Kl - sp.diags(Kl.diagonal())).sum())
+        if rs >= ratio * fs:
+            return l
+    return len(full) - 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["mid300x270", "deep300x270", "three70"])
+def test_mg_depth(name, precision):
+    """Where the hierarchy stops: a row-sum ratio of 8 for FP64 solves, 2 for the inner FP32
+    solves of mixed precision."""
+    print(f"\n[mg depth {name} {precision}]", flush=True)
+    p = MG_CASES[name]()
+    asm = fv.assemble(p)
+    with mcdec.Problem(p, precond="mg", precision=precision) as g:
+        got = list(g.info().mg_levels)
+    want = [mg_depth(schemes.continuum_matrix(asm, p.tau, a), p.nx, p.ny,
+                     8.0 if precision == "fp64" else 2.0) for a in range(p.n_omega)]
+    print(name, precision, got[:p.n_omega], want, flush=True)
+    assert got[:p.n_omega] == want
+    if name == "mid300x270":
+        assert want == [3 if precision == "fp64" else 2]
 
 
 @pytest.mark.parametrize("name", list(MG_CASES))
@@ -312,19 +349,7 @@ def test_mg_apply(name):
             z = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
             g.apply_precond(a, T(r), z)
             if a < p.n_omega:
-                full = precond.vcycle_setup(K, p.nx, p.ny)
-                # the hierarchy stops at the first level above the 1024-cell tail whose row
-                # sums reach 8 times its face conductances (summed over the level)
-                want = len(full) - 1
-                for l in range(1, len(full)):
-                    Kl = full[l]["K"]
-                    if Kl.shape[0] <= 1024:
-                        break
-                    rs = float(np.asarray(Kl.sum(axis=1)).sum())
-                    fs = float(-(Kl - sp.diags(Kl.diagonal())).sum())
-                    if rs >= 8.0 * fs:
-                        want = l
-                        break
+                want = mg_depth(K, p.nx, p.ny, 8.0)
                 assert inf.mg_levels[a] == want, (inf.mg_levels[a], want)
                 lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=want)
                 ref = precond.vcycle_apply(lev, r)
