@@ -71,11 +71,11 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "5d5b52b529a6dd4f", "fetch_kib": 83327.8,
-                        "write_kib": 65552.6, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "5d5b52b529a6dd4f", "fetch_kib": 110823.8,
-                        "write_kib": 107788.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "5d5b52b529a6dd4f", "fetch_kib": 82016.4,
+    ("C2", "mg", "A"): {"sources": "742dae88e17fcd56", "fetch_kib": 83430.3,
+                        "write_kib": 65552.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "742dae88e17fcd56", "fetch_kib": 110834.6,
+                        "write_kib": 107789.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "742dae88e17fcd56", "fetch_kib": 82023.0,
                         "write_kib": 32848.1, "read_factor": 1.9999, "write_factor": 1.0},
 }
 

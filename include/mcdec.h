@@ -193,6 +193,11 @@ typedef struct {
                             (MC_BIC0 / MC_MG; 0 with Jacobi, without crossings, or beyond 6144) */
   int32_t mg_levels[3];  /* (MC_MG) coarse levels of each grid continuum's V-cycle, else 0;
                             the last one holds at most 256 cells                               */
+  int32_t n_frac_blocks; /* (MC_BIC0 / MC_MG) blocks of the two-level fracture preconditioner
+                            that replaces the exact solve beyond 6144 crossing cells (connected
+                            blocks of at most 64 cells, dense block inverses, and the Galerkin
+                            coarse system over the blocks); 0 when the solve is exact or with
+                            more than 6144 blocks (the chains alone then)                       */
 } mc_info;
 
 typedef struct mc_problem mc_problem;

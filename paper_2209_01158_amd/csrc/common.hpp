@@ -18,7 +18,7 @@
 #define MC_ICY 16              // rows of a grid block of the block IC(0) preconditioner
 #define MC_ICB (MC_TY / MC_ICY)  // IC(0) blocks per grid tile
 #define MC_ICYC 4              // rows of an IC(0) block on the coarse levels of a V-cycle
-#define MC_SCHUR_ROWS 16       // rows of the crossing-cell inverse per workgroup
+#define MC_SCHUR_ROWS 4        // rows of the crossing-cell inverse per workgroup (one per wave)
 #define MC_SCHUR_KMAX 6144     // most crossing cells solved exactly (FP64 right-hand side in LDS)
 #define MC_MG_COARSE 256       // multigrid levels stop at this many cells (dense inverse there)
 #define MC_MG_TAIL 1024        // levels of at most this many cells run in one workgroup
@@ -118,7 +118,7 @@ struct PartD {
   // crossing cells, the crossing cells are solved by the inverse of their Schur complement
   int K;                   // crossing cells (0: none, or too many: crossings left out)
   int slotS;               // first partial slot of the Schur product (after the update slots)
-  int pad3;
+  int blocks;              // 1: two-level block preconditioner instead (K = blocks, below)
   const int* xcells;       // [K] crossing cells, ascending
   const int* xtile;        // [ntiles + 1] crossing cells of each work tile
   const int* xlr;          // [2n] crossing neighbours (left, right) of each cell's block or -1
@@ -130,6 +130,11 @@ struct PartD {
   const double* cxr;
   const double* sinv;      // [K*K] inverse of the Schur complement (symmetric)
   const float* sinv32;
+  // two-level block preconditioner: connected blocks of at most 64 cells solved by their
+  // dense inverses, the coarse system over the blocks by sinv (the inverse of P^T A P); xtile
+  // then holds the first block of each work tile, xlr / cl the block of each cell and 1
+  const int* bnode;        // [K*64] cells of each block, -1 padding
+  const float* binv;       // [K*64*64] block inverses, entry (i, j) at j*64 + i
   void* gX;                // [K] crossing right-hand side g = r_X - A_XI y (launch precision)
   void* zX;                // [K] crossing solution S^-1 g (launch precision)
   // (grid) multigrid V-cycle: this part is level mg_level of a continuum; coarser and finer

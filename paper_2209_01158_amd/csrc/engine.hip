@@ -63,6 +63,17 @@ static int env_int(const char* name, int dflt) {
 
 // Coarse levels of at most this many cells form the small-level tail of a V-cycle
 // (MCDEC_MG_TAIL overrides the size; the coarsest level is always in the tail).
+// Most crossing cells a fracture graph's exact solve takes (MC_SCHUR_KMAX; the environment
+// variable MCDEC_FRACTURE_EXACT_MAX lowers it, 0 = the two-level block preconditioner for
+// every graph with crossings).  Beyond it the two-level block preconditioner takes over
+// (MCDEC_FRACTURE_BLOCKS = 0 leaves the chains alone instead).
+static bool fracture_blocks_on() { return env_int("MCDEC_FRACTURE_BLOCKS", 1) != 0; }
+
+static int exact_crossing_max() {
+  const int v = env_int("MCDEC_FRACTURE_EXACT_MAX", MC_SCHUR_KMAX);
+  return std::min(MC_SCHUR_KMAX, std::max(0, v));
+}
+
 static long mg_tail_cells() {
   static const long n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
   return n;
@@ -349,6 +360,10 @@ struct Cont {  // one continuum
   float *cl32 = nullptr, *cr32 = nullptr, *sinv32 = nullptr;
   double *gX = nullptr, *zX = nullptr;
   float *gX32 = nullptr, *zX32 = nullptr;
+  // (graph) two-level block preconditioner in place of the exact solve (K = blocks)
+  bool fblocks = false;
+  int* bnode = nullptr;
+  float* binv = nullptr;
   // (grid) multigrid levels 1.. and the finest level's pre-smoothed solution
   std::vector<MgLevel> mg;
   bool mg_on = false;
@@ -591,6 +606,7 @@ struct mc_problem {
   std::vector<int> host_h;           // host copy of the fracture cells' host cells
   std::vector<int> chains_h, gtile_h;
   int K_all = 0;                     // crossing cells of the fracture graph
+  int nb_frac = 0;                   // blocks of its two-level preconditioner (if K_all > 0)
   double *flen = nullptr, *edge_d = nullptr, *sigma_f = nullptr;
   int nchains = 0, ngtiles = 0;
   // systems: 0..ncont-1 decoupled per continuum, ncont = coupled; their partial-sum slots
@@ -689,6 +705,9 @@ static PartD base_part(mc_problem* P, int c, int sys, int slot0A, int slot0B, bo
   q.cxr = C.cxr;
   q.sinv = C.sinv;
   q.sinv32 = C.sinv32;
+  q.blocks = C.fblocks ? 1 : 0;
+  q.bnode = C.bnode;
+  q.binv = C.binv;
   q.gX = fp32 ? (void*)C.gX32 : (void*)C.gX;
   q.zX = fp32 ? (void*)C.zX32 : (void*)C.zX;
   q.mg_level = 0;
@@ -854,6 +873,10 @@ static std::vector<PartD> coupled_parts(mc_problem* P, int sysI, int base) {
     slotA += P->cont[c].blocks[0];
     slotB += P->cont[c].blocks[1] + P->cont[c].blocks[2];
     q.coupled = 1;
+    if (q.blocks) {   // the coupled system keeps the chain solves of the fracture block (the
+      q.blocks = 0;   // two-level one did not lower its iterations); its crossing-cell
+      q.K = 0;        // workgroups then add nothing
+    }
     parts.push_back(q);
   }
   for (int c = 0; c < P->ncont; ++c) {
@@ -904,6 +927,57 @@ static void invert_spd(double* S, int K, hipStream_t s, int lda = 0) {
   HIPCHK(hipGetLastError());
 }
 
+// Two-level block preconditioner of a fracture graph whose crossing cells are too many for the
+// exact solve: dense inverses of connected blocks of at most 64 cells and the inverse of the
+// Galerkin coarse operator over the blocks, which the crossing-cell kernels apply (K = blocks,
+// every cell's response is the coarse value of its own block).  False (nothing changed) if
+// the graph needs more blocks than the coarse inverse takes.
+static bool setup_block_solve(mc_problem* P, Cont& C, const std::vector<double>& diag,
+                              const std::vector<double>& val) {
+  hipStream_t s = P->X.stream;
+  const long nf = C.n;
+  BlockHost H = build_block_solve((int)nf, P->gh, (int)P->gtile_h.size() - 1, diag.data(),
+                                  val.data(), MC_SCHUR_KMAX);
+  if (!H.ok) throw Error{MC_EDEVICE, "a fracture block matrix is not positive definite"};
+  if (H.nb == 0) return false;
+  const int K = H.nb;
+  DevArena& M = P->mem;
+  // device arrays keep the size of the first setup (the graph does not change afterwards)
+  if (!C.bnode) {
+    C.bnode = M.alloc<int>((size_t)K * kBlockCells);
+    C.binv = M.alloc<float>((size_t)K * kBlockCells * kBlockCells);
+    C.xtile = M.alloc<int>(H.xtile.size());
+    C.xlr = M.alloc<int>(2 * nf);
+    C.cl = M.alloc<double>(nf);
+    C.cr = M.alloc<double>(nf);
+    C.sinv = M.alloc<double>((size_t)K * K);
+    C.gX = M.alloc<double>(K);
+    C.zX = M.alloc<double>(K);
+  }
+  std::vector<int> xlr(2 * nf);
+  std::vector<double> one(nf, 1.0), zero(nf, 0.0);
+  for (long l = 0; l < nf; ++l) {
+    xlr[2 * l] = H.blk[l];
+    xlr[2 * l + 1] = -1;
+  }
+  HIPCHK(hipMemcpyAsync(C.bnode, H.node.data(), H.node.size() * sizeof(int),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.binv, H.binv.data(), H.binv.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.xtile, H.xtile.data(), H.xtile.size() * sizeof(int),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.xlr, xlr.data(), 2 * nf * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.cl, one.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.cr, zero.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(C.sinv, H.Ac.data(), (size_t)K * K * sizeof(double),
+                        hipMemcpyHostToDevice, s));
+  invert_spd(C.sinv, K, s);
+  C.K = K;
+  C.fblocks = true;
+  HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
+  return true;
+}
+
 // Fracture block preconditioner of the block IC(0) option: factors of the chain blocks cut at
 // the crossing cells and the inverse Schur complement of the crossing cells (an exact solve
 // of the fracture system), built on the host in FP64 from the device coefficients.
@@ -914,12 +988,18 @@ static void setup_fracture_solve(mc_problem* P, Cont& C) {
   HIPCHK(hipMemcpyAsync(diag.data(), C.diag, nf * sizeof(double), hipMemcpyDeviceToHost, s));
   if (ne2) HIPCHK(hipMemcpyAsync(val.data(), C.val, ne2 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  const int kmax = exact_crossing_max();
   SchurHost H = build_schur((int)nf, P->gh, P->chains_h, P->gtile_h, diag.data(), val.data(),
-                            MC_SCHUR_KMAX);
+                            kmax);
   DevArena& M = P->mem;
+  C.fblocks = false;
   if (!C.cT) C.cT = M.alloc<double>(nf);
   HIPCHK(hipMemcpyAsync(C.fdinv, H.dinv.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(C.cT, H.cT.data(), nf * sizeof(double), hipMemcpyHostToDevice, s));
+  // beyond the exact solve's limit the decoupled fracture solve takes the two-level block
+  // preconditioner; the chain factors stay for the coupled system
+  if (H.K == 0 && H.K_all > kmax && fracture_blocks_on() && setup_block_solve(P, C, diag, val))
+    return;
   C.K = H.K;
   std::vector<int> xlr;
   if (H.K > 0) {
@@ -1148,7 +1228,10 @@ static void build_coefficients(mc_problem* P) {
     hipLaunchKernelGGL(k_setup_graph, dim3(cdiv(P->nf, 256)), dim3(256), 0, s, g);
   }
   HIPCHK(hipGetLastError());
-  for (auto& C : P->cont) C.K = 0;   // set again below for block IC(0)
+  for (auto& C : P->cont) {   // set again below for block IC(0)
+    C.K = 0;
+    C.fblocks = false;
+  }
   if (ic_precond(P->X.opt.precond)) {
     for (auto& C : P->cont) {
       if (!C.fdinv) C.fdinv = P->mem.alloc<double>(C.n);
@@ -1316,6 +1399,10 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
     P->gtile = M.upload(gt.data(), gt.size(), s);
     P->ngtiles = (int)gt.size() - 1;
     P->K_all = count_crossing_cells(d.nf, d.ne, d.edges);
+    if (P->K_all > 0) {
+      std::vector<int> bn, bb;
+      P->nb_frac = build_blocks(d.nf, g, bn, bb);
+    }
     P->gh = g;
     P->host_h.assign(d.host, d.host + d.nf);
     P->chains_h = chains;
@@ -1364,7 +1451,10 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   // partial-slot arrays sized for one workgroup per tile (the most any tiling uses), so the
   // tilings can follow option changes
   // (a fracture continuum adds the workgroups of its crossing-cell product)
-  const int kslots = P->K_all <= MC_SCHUR_KMAX ? (int)cdiv(P->K_all, MC_SCHUR_ROWS) : 0;
+  // (its rows are the crossing cells of the exact solve or the blocks of the two-level one)
+  const int krows = std::max(P->K_all <= MC_SCHUR_KMAX ? P->K_all : 0,
+                             P->nb_frac <= MC_SCHUR_KMAX ? P->nb_frac : 0);
+  const int kslots = (int)cdiv(krows, MC_SCHUR_ROWS);
   // (a grid continuum with a V-cycle adds the workgroups of its final smoothing)
   auto slots_of = [&](int c) {
     return P->cont[c].tiles + (P->cont[c].kind == PART_GRAPH ? kslots : P->cont[c].tiles);
@@ -2448,7 +2538,17 @@ static int64_t footprint(const mc_problem_desc& d, const mc_options& o) {
   // responses and indices
   if (nf && bic0) {
     const int64_t Kall = count_crossing_cells(d.nf, d.ne, d.edges);
-    const int64_t K = Kall <= MC_SCHUR_KMAX ? Kall : 0;
+    const int64_t kmax = exact_crossing_max();
+    int64_t K = Kall <= kmax ? Kall : 0;
+    if (Kall > kmax && fracture_blocks_on()) {   // the two-level block preconditioner
+      std::vector<int> node, blk;
+      const int64_t nb = build_blocks(d.nf, build_graph(d.nf, d.ne, d.edges), node, blk);
+      if (nb <= MC_SCHUR_KMAX) {
+        K = nb;
+        A(4 * K * kBlockCells);                 // block cells
+        A(4 * K * kBlockCells * kBlockCells);   // block inverses
+      }
+    }
     if (K > 0) {
       A(4 * K);                   // xcells
       A(4 * (nf + 2));            // xtile
@@ -2994,7 +3094,11 @@ mc_status mc_get_info(const mc_problem* P, mc_info* info) {
   info->device_bytes = (int64_t)P->mem.bytes;
   info->grid_tiles = P->ncont ? P->cont[0].tiles : 0;
   info->n_chains = P->nchains;
-  info->n_crossing = P->ncont > P->n_omega ? P->cont[P->n_omega].K : 0;
+  if (P->ncont > P->n_omega) {
+    const Cont& F = P->cont[P->n_omega];
+    info->n_crossing = F.fblocks ? 0 : F.K;
+    info->n_frac_blocks = F.fblocks ? F.K : 0;
+  }
   for (int c = 0; c < P->ncont && c < 3; ++c) {
     info->tiles[c] = P->cont[c].tiles;
     info->blocks[c][0] = P->cont[c].blocks[0];

@@ -305,6 +305,106 @@ SchurHost build_schur(int nf, const GraphCSR& g, const std::vector<int>& chain_p
   return H;
 }
 
+int build_blocks(int nf, const GraphCSR& g, std::vector<int>& node, std::vector<int>& blk) {
+  blk.assign(nf, -1);
+  node.clear();
+  std::vector<int> queue;
+  queue.reserve(kBlockCells);
+  int nb = 0;
+  for (int s = 0; s < nf; ++s) {
+    if (blk[s] >= 0) continue;
+    // breadth-first from s over unassigned cells until the block is full or closed
+    queue.clear();
+    queue.push_back(s);
+    blk[s] = nb;
+    for (size_t h = 0; h < queue.size() && (int)queue.size() < kBlockCells; ++h) {
+      const int u = queue[h];
+      for (int j = g.rowptr[u]; j < g.rowptr[u + 1] && (int)queue.size() < kBlockCells; ++j) {
+        const int v = g.col[j];
+        if (blk[v] < 0) {
+          blk[v] = nb;
+          queue.push_back(v);
+        }
+      }
+    }
+    node.insert(node.end(), queue.begin(), queue.end());
+    node.insert(node.end(), kBlockCells - queue.size(), -1);
+    ++nb;
+  }
+  return nb;
+}
+
+BlockHost build_block_solve(int nf, const GraphCSR& g, int ntiles, const double* diag,
+                            const double* val, int nbmax) {
+  BlockHost H;
+  const int nb = build_blocks(nf, g, H.node, H.blk);
+  if (nb > nbmax || nb == 0) {
+    H = BlockHost{};
+    return H;
+  }
+  H.nb = nb;
+  constexpr int W = kBlockCells;
+  H.binv.assign((size_t)nb * W * W, 0.0f);
+  H.Ac.assign((size_t)nb * nb, 0.0);
+  std::vector<int> pos(nf, -1);   // position of a cell inside its block
+  std::vector<double> a(W * W), L(W * W), inv(W * W);
+  for (int b = 0; b < nb; ++b) {
+    const int* nd = &H.node[(size_t)b * W];
+    int m = 0;
+    while (m < W && nd[m] >= 0) pos[nd[m]] = m, ++m;
+    // block matrix: the diagonal and minus the conductances inside the block
+    std::fill(a.begin(), a.end(), 0.0);
+    for (int i = 0; i < m; ++i) {
+      const int l = nd[i];
+      a[i * W + i] = diag[l];
+      for (int j = g.rowptr[l]; j < g.rowptr[l + 1]; ++j)
+        if (H.blk[g.col[j]] == b) a[i * W + pos[g.col[j]]] -= val[j];
+    }
+    // Cholesky a = L L^T (lower), then the inverse column by column from L
+    std::fill(L.begin(), L.end(), 0.0);
+    for (int j = 0; j < m; ++j) {
+      double d = a[j * W + j];
+      for (int k = 0; k < j; ++k) d -= L[j * W + k] * L[j * W + k];
+      if (!(d > 0.0)) {
+        H.ok = false;
+        return H;
+      }
+      L[j * W + j] = std::sqrt(d);
+      for (int i = j + 1; i < m; ++i) {
+        double v = a[i * W + j];
+        for (int k = 0; k < j; ++k) v -= L[i * W + k] * L[j * W + k];
+        L[i * W + j] = v / L[j * W + j];
+      }
+    }
+    for (int c = 0; c < m; ++c) {   // solve L L^T x = e_c
+      std::vector<double> w(m, 0.0);
+      for (int i = 0; i < m; ++i) {
+        double v = i == c ? 1.0 : 0.0;
+        for (int k = 0; k < i; ++k) v -= L[i * W + k] * w[k];
+        w[i] = v / L[i * W + i];
+      }
+      for (int i = m - 1; i >= 0; --i) {
+        double v = w[i];
+        for (int k = i + 1; k < m; ++k) v -= L[k * W + i] * inv[c * W + k];
+        inv[c * W + i] = v / L[i * W + i];
+      }
+    }
+    float* bo = &H.binv[(size_t)b * W * W];
+    for (int i = 0; i < m; ++i)      // symmetric by construction: store the mean of (i,j), (j,i)
+      for (int j = 0; j < m; ++j) bo[j * W + i] = (float)(0.5 * (inv[j * W + i] + inv[i * W + j]));
+  }
+  // coarse operator: sum of the fracture matrix over pairs of blocks
+  for (int l = 0; l < nf; ++l) {
+    const int bl = H.blk[l];
+    H.Ac[(size_t)bl * nb + bl] += diag[l];
+    for (int j = g.rowptr[l]; j < g.rowptr[l + 1]; ++j)
+      H.Ac[(size_t)H.blk[g.col[j]] * nb + bl] -= val[j];
+  }
+  H.xtile.resize(ntiles + 1);
+  for (int t = 0; t <= ntiles; ++t) H.xtile[t] = (int)((long)t * nb / ntiles);
+  return H;
+}
+
 std::vector<int> xcd_order(int n, int nxcd) {
   if (nxcd <= 1 || n < 2 * nxcd) {
     std::vector<int> o(n);

@@ -69,6 +69,35 @@ SchurHost build_schur(int nf, const GraphCSR& g, const std::vector<int>& chain_p
 // Number of crossing cells of a connection list (cells joined to a cell other than l-1, l+1).
 int count_crossing_cells(int nf, int ne, const int32_t* edges);
 
+// Two-level block preconditioner of a fracture graph with more crossing cells than the exact
+// solve takes (fracture planes, dense networks).  The cells are grouped into connected blocks
+// of at most kBlockCells = 64 cells, grown breadth-first from the lowest unassigned cell;
+// with B the block diagonal of the fracture matrix A and P the block indicator (P_lb = 1 if
+// cell l is in block b),
+//   z = B^-1 r + P A_c^-1 P^T r,   A_c = P^T A P,
+// symmetric positive definite as PCG needs.  The coarse solve A_c^-1 runs in the crossing-cell
+// kernels (K = nb rows, e = A_c^-1 g with g = P^T r), and the response of cell l is e of its
+// own block (xl = block, cl = 1).
+constexpr int kBlockCells = 64;
+struct BlockHost {
+  int nb = 0;                  // blocks
+  std::vector<int> node;       // [nb * 64] cells of each block, ascending BFS order; -1 padding
+  std::vector<int> blk;        // [nf] block of each cell
+  std::vector<float> binv;     // [nb * 64 * 64] inverse of each block's matrix (symmetric,
+                               // entry (i, j) at j * 64 + i; 0 on padding rows and columns)
+  std::vector<double> Ac;      // [nb * nb] coarse operator P^T A P, column-major
+  std::vector<int> xtile;      // [ntiles + 1] first block of each fracture work tile
+  bool ok = true;              // false if a block matrix was not positive definite
+};
+
+// Blocks only (cell lists and the block of each cell); returns the number of blocks.
+int build_blocks(int nf, const GraphCSR& g, std::vector<int>& node, std::vector<int>& blk);
+
+// diag, val as for build_schur; the blocks are spread evenly over `ntiles` work tiles.
+// Returns nb = 0 (and nothing else) when more than nbmax blocks would be needed.
+BlockHost build_block_solve(int nf, const GraphCSR& g, int ntiles, const double* diag,
+                            const double* val, int nbmax);
+
 // Launch order of `n` work items such that hardware round-robin dispatch over `nxcd`
 // compute dies gives die j a contiguous range of items.  Entries of -1 are padding.
 std::vector<int> xcd_order(int n, int nxcd);

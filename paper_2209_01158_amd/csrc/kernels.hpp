@@ -774,6 +774,41 @@ __device__ __forceinline__ void for_cells(const PartD& P, const Tile& t, const F
   }
 }
 
+// Two-level block preconditioner of a fracture graph (PartD::blocks): one wavefront per block
+// of at most 64 cells.  Each lane takes one cell's residual from `rval(l)` (which also does
+// that cell's own pointwise work), the block's dense inverse gives y_b = B_b^-1 r_b (the
+// residuals broadcast through LDS, the inverse read one coalesced column per step), and the
+// block sum g_b = sum of r_b is the coarse right-hand side that the crossing-cell kernel
+// solves; (r, y) and (r, r) accumulate into rz, rr.
+template <class T, class RV>
+__device__ __forceinline__ void block_precond(const PartD& P, const Tile& t, T* __restrict__ z,
+                                              const RV& rval, double& rz, double& rr) {
+  __shared__ T rsh[MC_BLOCK];
+  const int lane = threadIdx.x & 63;
+  T* rw = rsh + (threadIdx.x & ~63);
+  T* g = (T*)P.gX;
+  for (int tile = t.t0; tile < t.t1; ++tile) {
+    const int b1 = P.xtile[tile + 1];
+    for (int b = P.xtile[tile] + (int)(threadIdx.x >> 6); b < b1; b += MC_BLOCK / 64) {
+      const int l = P.bnode[(long)b * 64 + lane];
+      const T rl = l >= 0 ? rval(l) : (T)0;
+      rw[lane] = rl;
+      __threadfence_block();   // the block's residuals are read by every lane
+      __builtin_amdgcn_wave_barrier();
+      const gconst<float> Bi = gc(P.binv + (long)b * 4096);
+      T y = (T)0;
+#pragma unroll
+      for (int j = 0; j < 64; ++j) y += (T)Bi[j * 64 + lane] * rw[j];
+      if (l >= 0) z[l] = y;
+      rz += (double)rl * (double)y;
+      rr += (double)rl * (double)rl;
+      const double gs = wave_sum((double)rl);
+      if (lane == 0) g[b] = (T)gs;
+      __builtin_amdgcn_wave_barrier();   // rw is written again for the next block
+    }
+  }
+}
+
 // z = M^-1 r at cell i.  Jacobi: r / diag.  Block IC(0): the stored z; on a fracture graph
 // with crossing cells the stored vector is y = A_II^-1 r (0 on crossing cells) and the
 // crossing solution z_X enters through the responses of each block to its end cells.
@@ -787,6 +822,7 @@ __device__ __forceinline__ T zval(const PartD& P, long i) {
     T z = ((const T*)P.z)[i];
     if (P.K > 0) {
       const T* zX = (const T*)P.zX;
+      if (P.blocks) return z + zX[P.xlr[2 * i]];   // the coarse value of the cell's block
       const int xl = P.xlr[2 * i], xr = P.xlr[2 * i + 1];
       if (xl >= 0) z += pick<T>(P.cl, P.cl32)[i] * zX[xl];
       if (xr >= 0) z += pick<T>(P.cr, P.cr32)[i] * zX[xr];
@@ -1058,7 +1094,9 @@ __device__ __forceinline__ void residual_and_precond(const PartD& P, const Tile&
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     const T* dinv = pick<T>(P.fdinv, P.fdinv32);
     const T* cT = pick<T>(P.cT, P.cT32);
-    for (int tile = t.t0; tile < t.t1; ++tile) {
+    if (P.blocks)
+      block_precond<T>(P, t, z, [&](int l) { return emit(l, resg(l), P.b[l]); }, v[0], v[1]);
+    for (int tile = t.t0; tile < t.t1 && !P.blocks; ++tile) {
       const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
       const int l0 = P.chain_ptr[c0], l1 = P.chain_ptr[c1];
       for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) emit(l, resg(l), P.b[l]);
@@ -1364,7 +1402,15 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
     const T* dinv = pick<T>(P.fdinv, P.fdinv32);
     const T* cT = pick<T>(P.cT, P.cT32);
-    for (int tile = t.t0; tile < t.t1; ++tile) {
+    if (P.blocks) {   // the update of each cell is done by the lane that holds it in a block
+      block_precond<T>(P, t, z, [&](int l) {
+        x[l] = x[l] + alpha * p[l];
+        const T rn = r[l] - alpha * q[l];
+        r[l] = rn;
+        return rn;
+      }, o[0], o[1]);
+    }
+    for (int tile = t.t0; tile < t.t1 && !P.blocks; ++tile) {
       const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
       const int l0 = P.chain_ptr[c0], l1 = P.chain_ptr[c1];
       for (int l = l0 + (int)threadIdx.x; l < l1; l += MC_BLOCK) {
@@ -1544,7 +1590,9 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
       ic0_block<double>(P, B, rv, P.mg_next >= 0 ? (double*)P.mg_zp : z, dz, dr);
     });
   } else if constexpr (PREC == PREC_BIC0 && KIND == PART_GRAPH) {
-    for (int tile = t.t0; tile < t.t1; ++tile) {
+    double rz = 0.0, rr = 0.0;
+    if (P.blocks) block_precond<double>(P, t, z, [&](int l) { return r[l]; }, rz, rr);
+    for (int tile = t.t0; tile < t.t1 && !P.blocks; ++tile) {
       const int c0 = P.gtile[tile], c1 = P.gtile[tile + 1];
       for (int c = c0 + (int)(threadIdx.x >> 6); c < c1; c += 4)
         chain_solve<double>(r, z, P.fdinv, P.cT, P.chain_ptr[c], P.chain_ptr[c + 1]);
@@ -1575,9 +1623,18 @@ __device__ __forceinline__ void schur_rows(const PartD& P, const Tile& t, double
   const int k1 = min(t.t1 * MC_SCHUR_ROWS, K);
   for (int k = t.t0 * MC_SCHUR_ROWS + (int)(threadIdx.x >> 6); k < k1; k += 4) {
     const long row = (long)k * K;
-    double acc = 0.0;
-    for (int j = lane; j < K; j += 64) acc += (double)Sv[row + j] * (double)gs[j];
-    acc = wave_sum(acc);
+    // four partial sums over interleaved columns: independent loads stay in flight
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int j = lane;
+#pragma unroll 2
+    for (; j + 192 < K; j += 256) {
+      a0 += (double)Sv[row + j] * (double)gs[j];
+      a1 += (double)Sv[row + j + 64] * (double)gs[j + 64];
+      a2 += (double)Sv[row + j + 128] * (double)gs[j + 128];
+      a3 += (double)Sv[row + j + 192] * (double)gs[j + 192];
+    }
+    for (; j < K; j += 64) a0 += (double)Sv[row + j] * (double)gs[j];
+    const double acc = wave_sum((a0 + a1) + (a2 + a3));
     if (lane == 0) {
       const T zk = (T)acc;
       zX[k] = zk;

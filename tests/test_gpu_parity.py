@@ -649,6 +649,128 @@ def test_3d_mixed_precision(box):
         assert err < 1e-8, (name, err, rep)
 
 
+# ------------------------------------------------------------------------------------
+# two-level block preconditioner of fracture graphs with more crossing cells than the exact
+# solve takes (fracture planes, dense networks); MCDEC_FRACTURE_EXACT_MAX = 0 selects it for
+# every graph with crossings
+# ------------------------------------------------------------------------------------
+FRAC_BLOCK_CASES = {
+    "dense48": DENSE,
+    "box24x12_3c": BOXES["box24x12_3c"],
+    "box70x5_zdir": BOXES["box70x5_zdir"],
+    "box96x8": lambda: media.box_problem(n=96, nz=8, seed=4, nplane=8, plane_len=(10, 40)),
+}
+
+
+def bfs_blocks(nf, edges, size=64):
+    """Blocks of at most `size` connected fracture cells, grown breadth-first from the
+    lowest unassigned cell over neighbours in ascending order."""
+    nbr = [[] for _ in range(nf)]
+    for a, b in np.asarray(edges, np.int64).reshape(-1, 2):
+        nbr[a].append(b)
+        nbr[b].append(a)
+    for v in nbr:
+        v.sort()
+    blk = -np.ones(nf, np.int64)
+    nb = 0
+    for s in range(nf):
+        if blk[s] >= 0:
+            continue
+        queue, blk[s] = [s], nb
+        h = 0
+        while h < len(queue) and len(queue) < size:
+            for v in nbr[queue[h]]:
+                if blk[v] < 0 and len(queue) < size:
+                    blk[v] = nb
+                    queue.append(v)
+            h += 1
+        nb += 1
+    return blk, nb
+
+
+def two_level_apply(K, blk, nb, r):
+    """z = B^-1 r + P (P^T K P)^-1 P^T r with B the block diagonal of K."""
+    n = K.shape[0]
+    Pm = sp.csr_matrix((np.ones(n), (np.arange(n), blk)), shape=(n, nb))
+    Kc = sp.coo_matrix(K)
+    m = blk[Kc.row] == blk[Kc.col]
+    B = sp.csc_matrix((Kc.data[m], (Kc.row[m], Kc.col[m])), shape=(n, n))
+    y = sp.linalg.splu(B).solve(r)
+    Ac = (Pm.T @ K @ Pm).toarray()
+    return y + Pm @ np.linalg.solve(Ac, Pm.T @ r)
+
+
+@pytest.mark.parametrize("name", list(FRAC_BLOCK_CASES))
+def test_fracture_blocks_apply(name, monkeypatch):
+    """z = M^-1 r of the two-level block preconditioner against the same formula formed with
+    sparse and dense direct solves (FP32 block inverses: relative error within 1e-5)."""
+    print(f"\n[fracture blocks apply {name}]", flush=True)
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    p = FRAC_BLOCK_CASES[name]()
+    asm = fv.assemble(p)
+    a = p.n_omega
+    K = schemes.continuum_matrix(asm, p.tau, a)
+    blk, nb = bfs_blocks(p.sizes()[a], p.edges)
+    rng = np.random.default_rng(8)
+    with mcdec.Problem(p, precond="bic0") as g:
+        inf = g.info()
+        assert inf.n_frac_blocks == nb and inf.n_crossing == 0, (inf.n_frac_blocks, nb)
+        r = rng.standard_normal(p.sizes()[a])
+        z = torch.zeros(p.sizes()[a], dtype=torch.float64, device=DEV)
+        g.apply_precond(a, T(r), z)
+    ref = two_level_apply(K, blk, nb, r)
+    err = rel(z.cpu().numpy(), ref)
+    print(name, nb, err, flush=True)
+    assert err < 1e-5, (name, err)
+
+
+@pytest.mark.parametrize("scheme", ["D", "coupled", "U"])
+@pytest.mark.parametrize("name", ["dense48", "box24x12_3c", "box70x5_zdir"])
+def test_fracture_blocks_trajectory(name, scheme, monkeypatch):
+    print(f"\n[fracture blocks trajectory {name} {scheme}]", flush=True)
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    p = FRAC_BLOCK_CASES[name]()
+    ref = schemes.run(p, scheme, 3, keep="all")
+    with mcdec.Problem(p, scheme=scheme, precond="bic0", tol=1e-14) as g:
+        assert g.info().n_frac_blocks > 0
+        for n in range(1, 4):
+            rep = g.step(1)
+            err = rel(g.get_states(), ref[n])
+            assert err < 1e-10, (name, scheme, n, err, rep)
+
+
+@pytest.mark.parametrize("name", ["dense48", "box96x8"])
+def test_fracture_blocks_mixed(name, monkeypatch):
+    """Inside FP32 refinement (the FP32 inner solve reads the same block inverses), and in
+    fewer fracture iterations than with the chains alone."""
+    print(f"\n[fracture blocks mixed {name}]", flush=True)
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    p = FRAC_BLOCK_CASES[name]()
+    ref = schemes.run(p, "D", 3, keep="last")
+    with mcdec.Problem(p, precision="mixed", precond="bic0", outer_tol=1e-12) as g:
+        assert g.info().n_frac_blocks > 0
+        rep = g.step(3)
+        err = rel(g.get_states(), ref)
+        print(name, rep, err, flush=True)
+        assert err < 1e-8, (name, err, rep)
+
+
+def test_fracture_blocks_fewer_iterations(monkeypatch):
+    """On fracture planes the two-level preconditioner needs far fewer PCG iterations than
+    the chains alone (MCDEC_FRACTURE_BLOCKS = 0 leaves the chains)."""
+    p = FRAC_BLOCK_CASES["box96x8"]()
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    its = {}
+    for on in ("0", "1"):
+        monkeypatch.setenv("MCDEC_FRACTURE_BLOCKS", on)
+        with mcdec.Problem(p, precond="bic0", tol=1e-10) as g:
+            inf = g.info()
+            assert (inf.n_frac_blocks > 0) == (on == "1") and inf.n_crossing == 0
+            its[on] = sum(g.step(1)["iters"][-1] for _ in range(3))   # fracture continuum
+    print(its, flush=True)
+    assert its["1"] * 2 < its["0"], its
+
+
 def test_3d_multigrid_refused():
     p = media.box_problem(n=16, nz=4, seed=2)
     with pytest.raises(mcdec.McError) as ei:

@@ -23,3 +23,22 @@ def test_schur_host_selftest(tmp_path):
     assert res.returncode == 0, res.stderr
     run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert run.returncode == 0 and run.stdout.strip().endswith("OK"), run.stdout + run.stderr
+
+
+BLOCK_SRC = [os.path.join(ROOT, "tests", "blocks_selftest.cpp"),
+             os.path.join(ROOT, "paper_2209_01158_amd", "csrc", "host_setup.cpp")]
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_block_preconditioner_host_selftest(tmp_path):
+    """Blocks of the two-level fracture preconditioner (connected, at most 64 cells, grown
+    breadth-first until full), their inverses and the Galerkin coarse operator."""
+    exe = str(tmp_path / "blocks")
+    base = ["g++", "-std=c++17", "-O1", "-g", "-I", os.path.join(ROOT, "include")]
+    res = subprocess.run(base + ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"] +
+                         BLOCK_SRC + ["-o", exe], capture_output=True, text=True)
+    if res.returncode != 0:
+        res = subprocess.run(base + BLOCK_SRC + ["-o", exe], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert run.returncode == 0 and run.stdout.strip().endswith("OK"), run.stdout[-3000:] + run.stderr
