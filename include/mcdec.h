@@ -163,6 +163,19 @@ typedef struct {
                             path).  Same stopping test; the solution meets the same tolerance
                             but differs from the general path's in rounding                 */
   void *stream;          /* hipStream_t to order all work on, or NULL (library-owned stream)   */
+  /* Device allocator hooks (both or neither; NULL: hipMalloc / hipFree).  A problem, batch or
+     server takes its device arrays (coefficients, states, PCG and level vectors, launch
+     tables) from dev_alloc(bytes, alloc_ctx), which must return memory of the current device
+     aligned to at least 256 bytes, or NULL (the call then fails with MC_ENOMEM), and gives
+     each back once through dev_free(ptr, alloc_ctx) when it is destroyed, after its streams
+     are idle.  The hooks in force at creation stay with the object (mc_set_options does not
+     move memory).  They are called on the creating thread, except that a server creates its
+     admitted problems on its own setup thread.  The per-system records (a few hundred bytes),
+     pinned host mirrors and one-off setup scratch stay with hipMalloc.  This is how a caller
+     hands the library torch's caching allocator (the Python binding does with alloc="torch"). */
+  void *(*dev_alloc)(size_t bytes, void *ctx);
+  void (*dev_free)(void *ptr, void *ctx);
+  void *alloc_ctx;
 } mc_options;
 
 typedef struct {

@@ -122,14 +122,33 @@ static int blocks_for(int ntiles, int kind, int fam, bool bic0, bool fp32) {
 struct DevArena {
   std::vector<void*> ptrs;
   size_t bytes = 0;
+  // the caller's allocator (mc_options.dev_alloc / dev_free), fixed when the owner is created
+  void* (*hook_alloc)(size_t, void*) = nullptr;
+  void (*hook_free)(void*, void*) = nullptr;
+  void* hook_ctx = nullptr;
+  void use_hooks(const mc_options& o) {
+    hook_alloc = o.dev_alloc;
+    hook_free = o.dev_free;
+    hook_ctx = o.alloc_ctx;
+  }
   template <class T>
   T* alloc(size_t n) {
     if (n == 0) n = 1;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error{MC_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+    if (hook_alloc) {
+      p = hook_alloc(n * sizeof(T), hook_ctx);
+      if (!p)
+        throw Error{MC_ENOMEM, "dev_alloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+      if ((uintptr_t)p % 256 != 0) {
+        hook_free(p, hook_ctx);
+        throw Error{MC_EINVAL, "dev_alloc returned memory not aligned to 256 bytes"};
+      }
+    } else {
+      hipError_t e = hipMalloc(&p, n * sizeof(T));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{MC_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+      }
     }
     ptrs.push_back(p);
     bytes += n * sizeof(T);
@@ -142,7 +161,10 @@ struct DevArena {
     return d;
   }
   void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) {
+      if (hook_free) hook_free(p, hook_ctx);
+      else (void)hipFree(p);
+    }
     ptrs.clear();
     bytes = 0;
   }
@@ -1359,6 +1381,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   if (!m.empty()) fail(m);
   P->d = d;
   P->X.opt = o;
+  P->mem.use_hooks(o);
   P->n_omega = d.n_omega;
   P->nf = d.nf;
   P->ne = d.ne;
@@ -2886,8 +2909,8 @@ mc_status mc_destroy(mc_problem* P) {
   if (!P) return MC_OK;
   if (P->X.stream) (void)hipStreamSynchronize(P->X.stream);
   mc::clear_tables(P);
+  mc::exec_release(P->X);   // every stream idle before the memory goes back
   P->mem.release();
-  mc::exec_release(P->X);
   delete P;
   return MC_OK;
 }
@@ -3228,6 +3251,7 @@ mc_status mc_batch_create(const mc_options* o, mc_batch** out) {
   mc_batch* B = new mc_batch();
   try {
     B->X.opt = od;
+    B->mem.use_hooks(od);
     mc::exec_init(B->X, od.stream);
     B->X.opt.stream = B->X.stream;
   } catch (const mc::Error& e) {
@@ -3243,8 +3267,8 @@ mc_status mc_batch_destroy(mc_batch* B) {
   if (!B) return MC_OK;
   if (B->X.stream) (void)hipStreamSynchronize(B->X.stream);
   for (auto& t : B->tab) mc::drop_graphs(t);
-  B->mem.release();
   mc::exec_release(B->X);
+  B->mem.release();
   delete B;
   return MC_OK;
 }

@@ -110,6 +110,8 @@ std::string validate_options(const mc_options& o) {
     return "warm_start must be 0 (linear extrapolation), 1 (previous layer) or 2 (adaptive "
            "extrapolation)";
   if (o.small_max < 0) return "small_max must be >= 0";
+  if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr))
+    return "dev_alloc and dev_free must be given together (or neither)";
   return "";
 }
 

@@ -60,7 +60,8 @@ class Options(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int32), ("outer_tol", C.c_double),
                 ("max_outer", C.c_int32), ("inner_tol", C.c_double),
                 ("check_every", C.c_int32), ("tile_rows", C.c_int32), ("warm_start", C.c_int32),
-                ("small_max", C.c_int32), ("stream", C.c_void_p)]
+                ("small_max", C.c_int32), ("stream", C.c_void_p),
+                ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p)]
 
 
 class Report(C.Structure):
@@ -212,9 +213,28 @@ def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
 
 
+# Device allocator hooks handing the library torch's caching allocator (mc_options.dev_alloc /
+# dev_free): allocations on the current device and torch's current stream of the calling
+# thread.  A failed allocation (an exception in the callback) reaches the library as NULL.
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+def _torch_dev_alloc(nbytes, ctx):
+    return torch.cuda.caching_allocator_alloc(nbytes)
+
+
+def _torch_dev_free(ptr, ctx):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+_TORCH_HOOKS = (_ALLOC_FN(_torch_dev_alloc), _FREE_FN(_torch_dev_free))   # alive for the process
+
+
 def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_iter=20000,
                  outer_tol=1e-10, max_outer=30, inner_tol=1e-6, check_every=0, tile_rows=0,
-                 warm_start="extrapolate", small_max=0, stream=None) -> Options:
+                 warm_start="extrapolate", small_max=0, stream=None, alloc=None) -> Options:
+    """alloc: None (the library's hipMalloc) or "torch" (torch's caching allocator)."""
     o = Options()
     _check(mc_options_default(C.byref(o)))
     o.scheme = SCHEMES[scheme]
@@ -226,6 +246,13 @@ def make_options(scheme="D", precision="fp64", precond="jacobi", tol=1e-10, max_
     o.warm_start = WARM_STARTS[warm_start]
     o.small_max = small_max
     o.stream = stream
+    if alloc == "torch":
+        if torch is None:
+            raise RuntimeError("alloc='torch' needs torch")
+        o.dev_alloc = C.cast(_TORCH_HOOKS[0], C.c_void_p)
+        o.dev_free = C.cast(_TORCH_HOOKS[1], C.c_void_p)
+    elif alloc is not None:
+        raise ValueError(f"unknown allocator {alloc!r}")
     return o
 
 

@@ -4,8 +4,11 @@ Tolerances: FP64 operator applications agree to rounding (<= 1e-14 relative, the
 difference is summation order and FMA contraction); FP64 solves and trajectories to a
 relative L2 error <= 1e-10; mixed-precision refinement to <= 1e-8.
 """
+import ctypes as C
+
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg  # noqa: F401  (sp.linalg)
 import pytest
 
 import media
@@ -780,3 +783,45 @@ def test_3d_multigrid_refused():
         with pytest.raises(mcdec.McError) as ei:
             g.set_options(precond="mg")
         assert ei.value.status == mcdec.MC_EINVAL
+
+
+# ------------------------------------------------------------------------------------
+# device allocator hooks (mc_options.dev_alloc / dev_free)
+# ------------------------------------------------------------------------------------
+@pytest.mark.parametrize("precond", ["mg", "bic0"])
+def test_torch_allocator_hooks(precond):
+    """With torch's caching allocator as the hooks, the problem's device arrays come from
+    torch (its allocated bytes grow by at least the problem's device bytes and fall back
+    when the problem is destroyed) and the layers are bitwise those of the library's own
+    allocation, also when torch hands back blocks that held NaN (no array is read before
+    the library writes it)."""
+    print(f"\n[allocator hooks {precond}]", flush=True)
+    p = CASES["three70"]()
+    poison = torch.full((8 << 20,), float("nan"), dtype=torch.float64, device=DEV)
+    del poison   # the block stays in torch's cache with this content
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    with mcdec.Problem(p, precond=precond, alloc="torch") as g:
+        g.step(3)
+        held = torch.cuda.memory_allocated() - base
+        dev_bytes = g.info().device_bytes
+        a = g.get_states()
+    torch.cuda.synchronize()
+    left = torch.cuda.memory_allocated() - base
+    with mcdec.Problem(p, precond=precond) as g:
+        g.step(3)
+        b = g.get_states()
+    print(precond, held, dev_bytes, left, flush=True)
+    assert held >= dev_bytes > 0 and left == 0, (held, dev_bytes, left)
+    assert len(a) == len(b) and all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_allocator_hooks_both_or_neither():
+    p = CASES["three70"]()
+    d, keep = mcdec.describe(p)
+    o = mcdec.make_options(alloc="torch")
+    o.dev_free = None
+    h = mcdec._PROBLEM()
+    st = mcdec.mc_create_problem(C.byref(d), C.byref(o), C.byref(h))
+    assert st == mcdec.MC_EINVAL and not h.value
+    assert b"dev_free" in mcdec.mc_last_error(None)

@@ -101,3 +101,30 @@ def test_server_refuses_request_larger_than_budget():
         with pytest.raises(mcdec.McError) as ei:
             srv.poll(12345)
         assert ei.value.status == mcdec.MC_ENOTFOUND
+
+
+def test_server_with_torch_allocator():
+    """A server whose problems take their device memory from torch's caching allocator
+    (the hooks then run on the server's setup thread): the results equal those of each
+    request stepped alone with the library's own allocation, and the memory goes back to
+    torch when the server is destroyed."""
+    reqs = requests()[:3]
+    alone = []
+    for p, n in reqs:
+        with mcdec.Problem(p, **OPT) as g:
+            g.step(n)
+            alone.append(g.get_states())
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    with mcdec.Server(sum(mcdec.footprint(p, **OPT) for p, _ in reqs), alloc="torch",
+                      **OPT) as srv:
+        ids = [srv.submit(p, n) for p, n in reqs]
+        srv.wait(timeout=120)
+        assert torch.cuda.memory_allocated() > base
+        for k, i in enumerate(ids):
+            assert srv.poll(i)["state"] == "done"
+            for x, y in zip(srv.fetch(i), alone[k]):
+                assert np.array_equal(x, y), k
+            srv.release(i)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == base
