@@ -71,12 +71,12 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "742dae88e17fcd56", "fetch_kib": 83430.3,
-                        "write_kib": 65552.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "742dae88e17fcd56", "fetch_kib": 110834.6,
-                        "write_kib": 107789.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "742dae88e17fcd56", "fetch_kib": 82023.0,
-                        "write_kib": 32848.1, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "A"): {"sources": "f37260229afa7736", "fetch_kib": 83492.1,
+                        "write_kib": 65552.7, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "f37260229afa7736", "fetch_kib": 110844.9,
+                        "write_kib": 107787.5, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "f37260229afa7736", "fetch_kib": 82020.1,
+                        "write_kib": 32848.0, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
 def log(*a):

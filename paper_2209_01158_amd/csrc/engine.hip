@@ -184,6 +184,7 @@ struct Table {
   int nblk[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   int cap[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   int nparts = 0;
+  bool has_blocks = false;   // a fracture part with the two-level block preconditioner
   std::vector<PartD> hparts;
   std::vector<int> htil;                      // tiles and the three workgroup counts per part
   // multigrid tile lists per level: [0] restriction into the level when it starts the tail,
@@ -336,6 +337,7 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     for (auto& li : T.mg[l]) li.n = 0;
   HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
   T.nparts = (int)parts.size();
+  T.has_blocks = std::any_of(parts.begin(), parts.end(), [](const PartD& q) { return q.blocks; });
   T.hparts = std::move(parts);
   T.htil.clear();
   for (auto& t : til) {
@@ -410,10 +412,11 @@ struct Exec {
   mc_options opt{};
   hipStream_t stream = nullptr;    // main stream (grid group, coupled systems, setup)
   hipStream_t stream2 = nullptr;   // fracture group of a decoupled solve (created on first use)
-  // optional CU-partitioned streams of a decoupled solve (MCDEC_FRAC_CUS > 0): the fracture
-  // group gets its own compute units
+  // CU-partitioned streams of a decoupled solve (see create_cu_streams): the fracture group
+  // gets its own compute units
   hipStream_t stream_grid = nullptr, stream_frac = nullptr;
   bool own_stream = false, side = false;
+  bool auto_cus = false;           // a single problem's executor (batches share all units)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_poll[2] = {nullptr, nullptr};
   SysState* sys = nullptr;         // device system records
   SysState* h_sys = nullptr;       // pinned mirror
@@ -503,25 +506,34 @@ static void exec_init(Exec& X, void* user_stream) {
   X.graphs = env_flag("MCDEC_GRAPHS", true);
 }
 
-// CU partition (opt-in): the fracture group gets every k-th compute unit, spread over all
-// dies, the grid group the rest.  Left out if the masked streams cannot be created.
-static void create_cu_streams(Exec& X) {
+// CU partition of a split solve (grid and fracture groups on their own streams): the
+// fracture group gets groups of 8 consecutive compute units spread evenly over the chip, the
+// grid group the rest (the runtime refused masks of single scattered units here).  By
+// default a problem whose fracture takes the two-level block preconditioner (a
+// latency-bound solve of many more iterations than the grid's, slowed severalfold by the
+// grid kernels' traffic when they share every unit) gets a quarter of the units, one group
+// per 32, i.e. one per die of the chip; other solves and batches share all units.
+// MCDEC_FRAC_CUS sets the fracture's units (rounded up to a multiple of 8; 0 = no
+// partition).  Left out if the masked streams cannot be created.
+static void create_cu_streams(Exec& X, bool frac_blocks) {
   int dev = 0, ncu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  const int fcu = env_int("MCDEC_FRAC_CUS", 0);
-  if (fcu <= 0 || fcu >= ncu) return;
-  const int words = (ncu + 31) / 32, stride = ncu / fcu;
+  constexpr int G = 8;
+  const int ngroups = ncu / G;
+  const int dflt = X.auto_cus && frac_blocks ? ncu / 4 : 0;
+  const int fg = (env_int("MCDEC_FRAC_CUS", dflt) + G - 1) / G;   // groups for the fracture
+  if (fg <= 0 || fg >= ngroups) return;
+  const int words = (ncu + 31) / 32;
   std::vector<uint32_t> fm(words, 0u), gm(words, 0u);
   int taken = 0;
-  for (int c = 0; c < ncu; ++c) {
-    if (c % stride == 0 && taken < fcu) {
-      fm[c / 32] |= 1u << (c % 32);
-      ++taken;
-    } else {
-      gm[c / 32] |= 1u << (c % 32);
-    }
+  for (int gi = 0; gi < ngroups; ++gi) {
+    // group gi goes to the fracture when it starts a new 1/fg share of the groups
+    const bool frac = taken < fg && (long)gi * fg >= (long)taken * ngroups;
+    if (frac) ++taken;
+    for (int c = gi * G; c < gi * G + G; ++c) (frac ? fm : gm)[c / 32] |= 1u << (c % 32);
   }
+  for (int c = ngroups * G; c < ncu; ++c) gm[c / 32] |= 1u << (c % 32);
   hipStream_t a = nullptr, b = nullptr;
   if (hipExtStreamCreateWithCUMask(&a, words, gm.data()) != hipSuccess ||
       hipExtStreamCreateWithCUMask(&b, words, fm.data()) != hipSuccess) {
@@ -534,10 +546,10 @@ static void create_cu_streams(Exec& X) {
   X.stream_frac = b;
 }
 
-static void exec_side_streams(Exec& X) {
+static void exec_side_streams(Exec& X, bool frac_blocks) {
   if (X.side) return;
   HIPCHK(hipStreamCreateWithFlags(&X.stream2, hipStreamNonBlocking));
-  create_cu_streams(X);
+  create_cu_streams(X, frac_blocks);
   X.side = true;
 }
 
@@ -994,6 +1006,10 @@ static bool setup_block_solve(mc_problem* P, Cont& C, const std::vector<double>&
   HIPCHK(hipMemcpyAsync(C.sinv, H.Ac.data(), (size_t)K * K * sizeof(double),
                         hipMemcpyHostToDevice, s));
   invert_spd(C.sinv, K, s);
+  if (!C.sinv32) C.sinv32 = M.alloc<float>((size_t)K * K);   // the coarse solve reads FP32
+  hipLaunchKernelGGL(k_to_f32, dim3(cdiv((long)K * K, 256)), dim3(256), 0, s, C.sinv, C.sinv32,
+                     (long)K * K);
+  HIPCHK(hipGetLastError());
   C.K = K;
   C.fblocks = true;
   HIPCHK(hipStreamSynchronize(s));   // host vectors die at return
@@ -1381,6 +1397,7 @@ static void create(mc_problem* P, const mc_problem_desc& d, const mc_options& o)
   if (!m.empty()) fail(m);
   P->d = d;
   P->X.opt = o;
+  P->X.auto_cus = true;
   P->mem.use_hooks(o);
   P->n_omega = d.n_omega;
   P->nf = d.nf;
@@ -2016,7 +2033,7 @@ static void solve_table(Exec& X, Table& Tb, int s0, int s1, bool assemble, bool 
     int ngrid = 0;
     for (auto& q : Tb.hparts) ngrid += q.kind == PART_GRID && q.mg_level == 0;
     const bool one = env_flag("MCDEC_ONE_STREAM", false);
-    if (!one) exec_side_streams(X);
+    if (!one) exec_side_streams(X, Tb.has_blocks);
     const bool part = X.stream_grid && !one;
     mk(1, s0, s0 + ngrid, part ? X.stream_grid : X.stream);
     mk(2, s0 + ngrid, s1, one ? X.stream : (part ? X.stream_frac : X.stream2));

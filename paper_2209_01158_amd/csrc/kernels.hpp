@@ -1610,14 +1610,10 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 // MC_SCHUR_ROWS rows; in a PCG launch the partial g . z_X completes (r, z) in the update
 // slots that follow the graph update kernel's own.
 // ------------------------------------------------------------------------------------
-template <class T, bool PCG>
-__device__ __forceinline__ void schur_rows(const PartD& P, const Tile& t, double& gz) {
-  __shared__ T gs[MC_SCHUR_KMAX];
+template <class T, class M, bool PCG>
+__device__ __forceinline__ void schur_rows_m(const PartD& P, const Tile& t, const T* gs,
+                                             const gconst<M> Sv, double& gz) {
   const int K = P.K;
-  const T* g = (const T*)P.gX;
-  for (int j = threadIdx.x; j < K; j += MC_BLOCK) gs[j] = g[j];
-  __syncthreads();
-  const gconst<T> Sv = gc(pick<T>(P.sinv, P.sinv32));
   T* zX = (T*)P.zX;
   const int lane = threadIdx.x & 63;
   const int k1 = min(t.t1 * MC_SCHUR_ROWS, K);
@@ -1641,6 +1637,20 @@ __device__ __forceinline__ void schur_rows(const PartD& P, const Tile& t, double
       if (PCG) gz += (double)gs[k] * (double)zk;
     }
   }
+}
+
+template <class T, bool PCG>
+__device__ __forceinline__ void schur_rows(const PartD& P, const Tile& t, double& gz) {
+  __shared__ T gs[MC_SCHUR_KMAX];
+  const int K = P.K;
+  const T* g = (const T*)P.gX;
+  for (int j = threadIdx.x; j < K; j += MC_BLOCK) gs[j] = g[j];
+  __syncthreads();
+  // the coarse inverse of the two-level block preconditioner is read in FP32 (symmetric as
+  // stored, so the preconditioner stays symmetric); the exact solve's Schur inverse in the
+  // solve's precision
+  if (P.blocks && sizeof(T) == 8) schur_rows_m<T, float, PCG>(P, t, gs, gc(P.sinv32), gz);
+  else schur_rows_m<T, T, PCG>(P, t, gs, gc(pick<T>(P.sinv, P.sinv32)), gz);
 }
 
 template <class T>

@@ -706,7 +706,8 @@ def two_level_apply(K, blk, nb, r):
 @pytest.mark.parametrize("name", list(FRAC_BLOCK_CASES))
 def test_fracture_blocks_apply(name, monkeypatch):
     """z = M^-1 r of the two-level block preconditioner against the same formula formed with
-    sparse and dense direct solves (FP32 block inverses: relative error within 1e-5)."""
+    sparse and dense direct solves (FP32 block and coarse inverses: relative error within
+    1e-5)."""
     print(f"\n[fracture blocks apply {name}]", flush=True)
     monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
     p = FRAC_BLOCK_CASES[name]()
