@@ -1231,8 +1231,21 @@ __global__ void __launch_bounds__(MC_BLOCK) k_pcg_A(const PartD* __restrict__ pa
     const gconst<T> zsrc = gc((const T*)(PREC == PREC_JACOBI ? P.r : P.z));
     const gconst<T> pold = gc((const T*)(par ? P.p2 : P.p));
     const T tc = (T)P.tconst;
+    // 3-D grid whose planes hold whole tile rows: consecutive tile rows in launch order go
+    // through the planes (z fastest), so the tiles above and below, whose z and p_old the
+    // z-couplings read again, are read by workgroups in flight at the same time
+    int rp = 0, nzp = 0;
+    if (P.plane) {
+      const int rows = (int)(P.plane / nx);
+      if (rows % MC_TY == 0) {
+        rp = rows / MC_TY;
+        nzp = ny / rows;
+      }
+    }
     for (int tile = t.t0; tile < t.t1; ++tile) {
-      const int x0 = (tile % P.tiles_x) * MC_TX, y0 = (tile / P.tiles_x) * MC_TY;
+      int trow = tile / P.tiles_x;
+      if (rp) trow = (trow % nzp) * rp + trow / nzp;
+      const int x0 = (tile % P.tiles_x) * MC_TX, y0 = trow * MC_TY;
       const int cx = x0 + lane, cxs = min(cx, nx - 1);
       const int r0 = y0 + wv * WR;   // first row of this wave
       // every load of the tile is issued before the first dependent step: the wave's

@@ -604,6 +604,8 @@ BOXES = {
     "box24x12_3c": lambda: media.box_problem(n=24, nz=12, seed=7, three=True),
     "box70x5_zdir": _box_zdirichlet,
     "box2x3": lambda: media.box_problem(n=2, nz=3, seed=1, nplane=1, plane_len=(1, 2)),
+    # planes of two whole tile rows: the operator kernel takes its tile rows z-fastest
+    "box64x5": lambda: media.box_problem(n=64, nz=5, seed=9, nplane=4, plane_len=(4, 24)),
 }
 
 
