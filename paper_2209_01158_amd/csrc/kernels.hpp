@@ -1624,7 +1624,7 @@ __global__ void __launch_bounds__(MC_BLOCK) __attribute__((amdgpu_waves_per_eu(2
 // slots that follow the graph update kernel's own.
 // ------------------------------------------------------------------------------------
 template <class T, class M, bool PCG>
-__device__ __forceinline__ void schur_rows_m(const PartD& P, const Tile& t, const T* gs,
+__device__ __forceinline__ void schur_rows_m(const PartD& P, const Tile& t, const gconst<T> gs,
                                              const gconst<M> Sv, double& gz) {
   const int K = P.K;
   T* zX = (T*)P.zX;
@@ -1654,11 +1654,9 @@ __device__ __forceinline__ void schur_rows_m(const PartD& P, const Tile& t, cons
 
 template <class T, bool PCG>
 __device__ __forceinline__ void schur_rows(const PartD& P, const Tile& t, double& gz) {
-  __shared__ T gs[MC_SCHUR_KMAX];
-  const int K = P.K;
-  const T* g = (const T*)P.gX;
-  for (int j = threadIdx.x; j < K; j += MC_BLOCK) gs[j] = g[j];
-  __syncthreads();
+  // g (at most 6144 values) is read by every row of every workgroup: it stays in L1 / L2,
+  // so it is read in place rather than first copied to LDS behind a barrier
+  const gconst<T> gs = gc((const T*)P.gX);
   // the coarse inverse of the two-level block preconditioner is read in FP32 (symmetric as
   // stored, so the preconditioner stays symmetric); the exact solve's Schur inverse in the
   // solve's precision
