@@ -71,12 +71,12 @@ DEFAULTS = {
 # factor 1.9999) and a 2 GiB fill (write factor 1.0).  Valid only for the kernel sources
 # they were taken on (hash of kernels.hpp + common.hpp); otherwise traffic is reported null.
 MEASURED_TRAFFIC = {
-    ("C2", "mg", "A"): {"sources": "f37260229afa7736", "fetch_kib": 83492.1,
+    ("C2", "mg", "A"): {"sources": "92bffb5b6cc8c44b", "fetch_kib": 83653.5,
                         "write_kib": 65552.7, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "B"): {"sources": "f37260229afa7736", "fetch_kib": 110844.9,
-                        "write_kib": 107787.5, "read_factor": 1.9999, "write_factor": 1.0},
-    ("C2", "mg", "P"): {"sources": "f37260229afa7736", "fetch_kib": 82020.1,
-                        "write_kib": 32848.0, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "B"): {"sources": "92bffb5b6cc8c44b", "fetch_kib": 110852.7,
+                        "write_kib": 107788.8, "read_factor": 1.9999, "write_factor": 1.0},
+    ("C2", "mg", "P"): {"sources": "92bffb5b6cc8c44b", "fetch_kib": 81977.1,
+                        "write_kib": 32848.1, "read_factor": 1.9999, "write_factor": 1.0},
 }
 
 def log(*a):
@@ -146,7 +146,7 @@ def mg_levels(nx, ny):
     return out
 
 
-def vcycle_bytes(nx, ny, precision, has_t, nlev=None, fused=False):
+def vcycle_bytes(nx, ny, precision, has_t, nlev=None, fused=False, once=False):
     """Algorithmic bytes of one V-cycle's coarse kernels (all levels), per timing slot.
 
     RS (restriction into coarse level l with its pre-smoothing, every level above the tail):
@@ -163,7 +163,8 @@ def vcycle_bytes(nx, ny, precision, has_t, nlev=None, fused=False):
     R  (restriction into the tail's first level): the finer level's r, z_p, FP32 diagonal,
         tx, ty read, r_c written.
     TAIL (levels of at most MG_TAIL cells in one workgroup): counted as R's output only;
-        it is latency-bound."""
+        it is latency-bound.
+    once: the last level of a truncated hierarchy is smoothed once (no PC launch there)."""
     w = 4 if precision == "mixed" else 8
     lv = mg_levels(nx, ny)
     if nlev is not None:               # a hierarchy truncated above the tail
@@ -177,7 +178,8 @@ def vcycle_bytes(nx, ny, precision, has_t, nlev=None, fused=False):
             pc += n[l] * (3 * w + w / 4 + 16)
         elif n[l] > MG_TAIL:
             rs += n[l - 1] * (2 * w + fine_coef) + n[l] * (2 * w + 12)
-            pc += n[l] * (3 * w + w / 4 + 16)
+            if not (once and l == len(lv) - 1):
+                pc += n[l] * (3 * w + w / 4 + 16)
         elif n[l - 1] > MG_TAIL or l == 1:
             r += n[l - 1] * (2 * w + fine_coef) + n[l] * w
     return {"RS": rs, "PC": pc, "R": r, "TAIL": 0.0}
@@ -342,10 +344,11 @@ def kernels_of(precond):
     return ("A", "B", "P", "RS", "PC", "TAIL", "R") if precond == "mg" else ("A", "B")
 
 
-def step_bytes(p, rep, precision, precond, nlev=None):
+def step_bytes(p, rep, precision, precond, nlev=None, once=None):
     """Algorithmic bytes of every timed grid kernel for one layer of problem p (iterations
     x cells x bytes per cell; the V-cycle's coarse kernels per cycle from the level
-    shapes; nlev[c]: coarse levels of continuum c's hierarchy)."""
+    shapes; nlev[c]: coarse levels of continuum c's hierarchy, once[c]: its truncated last
+    level smoothed once)."""
     out = {k: 0.0 for k in kernels_of(precond)}
     dim = getattr(p, "dim", 2)
     for c in range(p.n_omega):
@@ -358,30 +361,34 @@ def step_bytes(p, rep, precision, precond, nlev=None):
                 out[k] += it * p.ncell * grid_bytes_per_cell(k, precision, precond, has_t, dim,
                                                              fused)
         if precond == "mg":
-            vb = vcycle_bytes(p.nx, p.ny, precision, has_t, nl, fused)
+            vb = vcycle_bytes(p.nx, p.ny, precision, has_t, nl, fused,
+                              bool(once and once[c]))
             for k, b in vb.items():
                 out[k] += it * b
     return out
 
 
-def working_launches(iter_rows, precond, nlevs, shapes):
+def working_launches(iter_rows, precond, nlevs, shapes, onces=None):
     """Launches of each timed grid kernel that did work over the timed layers: one operator,
     update (and finest post-smoothing) launch per iteration while any grid system of the
     launch still iterates (iter_rows: per layer, the iterations of every grid system served
     by the launches), and per such iteration the V-cycle's coarse launches (levels above the
     tail: restriction + pre-smoothing and post-smoothing; the tail and the restriction into
-    it once each when some hierarchy reaches the tail)."""
+    it once each when some hierarchy reaches the tail; a truncated last level smoothed once
+    has no post-smoothing launch)."""
     its = float(sum(max(r) if len(r) else 0 for r in iter_rows))
     out = {"A": its, "B": its}
     if precond == "mg":
         out["P"] = its
-        above = tail = 0
-        for nl, (nx, ny) in zip(nlevs, shapes):
+        above = post = tail = 0
+        for k, (nl, (nx, ny)) in enumerate(zip(nlevs, shapes)):
             lv = mg_levels(nx, ny)[:nl + 1]
             n = [a * b for a, b in lv]
-            above = max(above, sum(1 for v in n[1:] if v > MG_TAIL))
+            na = sum(1 for v in n[1:] if v > MG_TAIL)
+            above = max(above, na)
+            post = max(post, na - (1 if onces and onces[k] and na and n[-1] > MG_TAIL else 0))
             tail = max(tail, 1 if any(v <= MG_TAIL for v in n[1:]) else 0)
-        out.update({"RS": its * above, "PC": its * above, "TAIL": its * tail, "R": its * tail})
+        out.update({"RS": its * above, "PC": its * post, "TAIL": its * tail, "R": its * tail})
     return out
 
 
@@ -455,14 +462,15 @@ def form_run(g, p, p0, args, change, scheme, profile=False):
     if profile:
         tot = {k: 0.0 for k in kernels_of(precond)}
         nlev = list(g.info().mg_levels)
+        once = [v == 1 for v in g.info().mg_stop_sweeps]
         for it in iters:
-            sb = step_bytes(p, {"iters": it}, opt["precision"], precond, nlev)
+            sb = step_bytes(p, {"iters": it}, opt["precision"], precond, nlev, once)
             for kk in tot:
                 tot[kk] += sb[kk]
         prof = read_profile(g, kernels_of(precond))
         g.profile(False)
         work = working_launches([r[:p.n_omega] for r in iters], precond, nlev[:p.n_omega],
-                                [(p.nx, p.ny)] * p.n_omega)
+                                [(p.nx, p.ny)] * p.n_omega, once[:p.n_omega])
         roof, roof2 = roofline(prof, tot, opt["precision"], precond, args.workload, work)
         res["roofline"] = roof
         res["roofline_other_kernels"] = roof2
@@ -511,8 +519,9 @@ def run_single(args, out):
         # timed loop)
         tot = {k: 0.0 for k in kernels_of(args.precond)}
         nlev = list(g.info().mg_levels)
+        once = [v == 1 for v in g.info().mg_stop_sweeps]
         for it in iters:
-            sb = step_bytes(p, {"iters": it}, args.precision, args.precond, nlev)
+            sb = step_bytes(p, {"iters": it}, args.precision, args.precond, nlev, once)
             for kk in tot:
                 tot[kk] += sb[kk]
         prof = read_profile(g, kernels_of(args.precond))
@@ -570,7 +579,7 @@ def run_single(args, out):
     lat_ms = np.array(lat) * 1e3
     it = np.array(iters)
     work = working_launches([r[:p.n_omega] for r in iters], args.precond,
-                            nlev[:p.n_omega], [(p.nx, p.ny)] * p.n_omega)
+                            nlev[:p.n_omega], [(p.nx, p.ny)] * p.n_omega, once[:p.n_omega])
     roof, roof2 = roofline(prof, tot, args.precision, args.precond, args.workload, work)
     out.update({
         "value": value, "ms_per_step": elapsed / args.steps * 1e3,
@@ -617,6 +626,7 @@ def run_batch(args, out):
             mcdec.autotune(gs, iters=10)
             log(f"autotune {time.time() - ta:.1f}s")
         nlevs = [list(g.info().mg_levels) for g in gs]
+        onces = [[v == 1 for v in g.info().mg_stop_sweeps] for g in gs]
         b = mcdec.Batch(stream=stream.cuda_stream, **opt)
         for k in range(args.warmup):
             reps = b.step(gs, 1)
@@ -642,8 +652,8 @@ def run_batch(args, out):
         tot = {k: 0.0 for k in kernels_of(args.precond)}
         iters_max = []
         for reps in all_reps:
-            for p, r, nl in zip(probs, reps, nlevs):
-                sb = step_bytes(p, r, args.precision, args.precond, nl)
+            for p, r, nl, on in zip(probs, reps, nlevs, onces):
+                sb = step_bytes(p, r, args.precision, args.precond, nl, on)
                 for kk in tot:
                     tot[kk] += sb[kk]
             iters_max.append(max(max(r["iters"]) for r in reps))
@@ -724,8 +734,9 @@ def run_batch(args, out):
     lat_ms = np.array(lat) * 1e3
     rows = [[v for p, r in zip(probs, reps) for v in r["iters"][:p.n_omega]] for reps in all_reps]
     nl_all = [v for p, nl in zip(probs, nlevs) for v in nl[:p.n_omega]]
+    on_all = [v for p, on in zip(probs, onces) for v in on[:p.n_omega]]
     shapes = [(p.nx, p.ny) for p in probs for _ in range(p.n_omega)]
-    work = working_launches(rows, args.precond, nl_all, shapes)
+    work = working_launches(rows, args.precond, nl_all, shapes, on_all)
     roof, roof2 = roofline(prof, tot, args.precision, args.precond, "C4", work)
     out.update({
         "value": value, "ms_per_step": elapsed / args.steps * 1e3, "dtype": "f32+f64",

@@ -211,6 +211,10 @@ typedef struct {
                             blocks of at most 64 cells, dense block inverses, and the Galerkin
                             coarse system over the blocks); 0 when the solve is exact or with
                             more than 6144 blocks (the chains alone then)                       */
+  int32_t mg_stop_sweeps[3]; /* (MC_MG) 0 if the continuum's V-cycle runs down to its dense
+                            coarsest level; else its last level, above the one-workgroup tail,
+                            is smoothed by 1 block IC(0) sweep (its row sums reach 8 times its
+                            face conductances) or 2 (z_p, then z = z_p + M^-1 (r - A z_p))      */
 } mc_info;
 
 typedef struct mc_problem mc_problem;

@@ -139,19 +139,20 @@ def coarse_operator(K: sp.spmatrix, P: sp.spmatrix) -> sp.csr_matrix:
 
 
 def vcycle_setup(K: sp.spmatrix, nx: int, ny: int, coarse: int = 256, coarse_rows: int = 4,
-                 max_levels=None):
+                 max_levels=None, last_sweeps: int = 2):
     """Levels of the V-cycle of the grid operator K (nx x ny cells, row-major): coarse
     operators from `coarse_operator` until at most `coarse` cells remain; block IC(0) factors on
     64 x 16 blocks on the finest level and 64 x `coarse_rows` blocks on the coarse levels
     above the coarsest; the coarsest level's dense inverse.  A grid of at most `coarse`
     cells has one level and the cycle is plain block IC(0).  With `max_levels`, the cycle
     is truncated after that many coarse levels: its last level (if above `coarse` cells) has
-    no coarser correction and is smoothed twice (a truncated V-cycle)."""
+    no coarser correction and is smoothed `last_sweeps` times (1: z = M^-1 r; 2: then
+    z += M^-1 (r - K z)), a truncated V-cycle, symmetric either way."""
     K = sp.csr_matrix(K)
     levels = [dict(K=K, nx=nx, ny=ny, facs=block_precond(K, grid_tile_blocks(nx, ny)))]
     while nx * ny > coarse:
         if max_levels is not None and len(levels) - 1 >= max_levels:
-            levels[-1]["smooth2"] = True
+            levels[-1]["sweeps"] = last_sweeps
             break
         P, nx, ny = aggregate_prolongator(nx, ny)
         levels[-1]["P"] = P
@@ -172,8 +173,10 @@ def vcycle_apply(levels, r: np.ndarray, l: int = 0) -> np.ndarray:
     r = np.asarray(r, np.float64)
     if "inv" in L:
         return L["inv"] @ r
-    if "smooth2" in L:           # last level of a truncated cycle: smoothed twice
+    if "sweeps" in L:            # last level of a truncated cycle: one or two sweeps
         zp = block_precond_apply(L["facs"], r)
+        if L["sweeps"] == 1:
+            return zp
         return zp + block_precond_apply(L["facs"], r - L["K"] @ zp)
     if "P" not in L:
         return block_precond_apply(L["facs"], r)

@@ -157,6 +157,9 @@ struct PartD {
   int mg_fnx, mg_fny, mg_ftiles_x, mg_fhas_t;
   int mg_fuse;             // (level 0) the update kernel forms this level's share of the
                            // restriction into level 1 (level 1 is not in the small-level tail)
+  int mg_once;             // (last level above the tail) smoothed once: the finer level takes
+                           // its pre-smoothed z_p as the correction, no post-smoothing here
+  int mg_pad0;
   double mg_ftc;           // finer level's constant conductance (no conductance field)
   const void* mg_fr;       // finer level's right-hand side (level 0: the PCG residual)
   const void* mg_fzp;      // finer level's z_p

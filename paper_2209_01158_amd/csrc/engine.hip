@@ -74,6 +74,17 @@ static int exact_crossing_max() {
   return std::min(MC_SCHUR_KMAX, std::max(0, v));
 }
 
+static long mg_tail_cells();
+
+// The last level of a truncated V-cycle, above the small-level tail, smoothed once (its
+// dominance reached MC_MG_DOMINANCE; MCDEC_MG_STOP_ONCE = 0 / 1 forces twice / once).
+static bool stop_smoothed_once(const PartD& c) {
+  if (c.mg_level == 0 || c.mg_next >= 0 || c.mg_inv != nullptr || (long)c.n <= mg_tail_cells())
+    return false;
+  const int f = env_int("MCDEC_MG_STOP_ONCE", -1);
+  return f < 0 ? c.mg_once != 0 : f != 0;
+}
+
 static long mg_tail_cells() {
   static const long n = std::max(env_int("MCDEC_MG_TAIL", MC_MG_TAIL), MC_MG_COARSE);
   return n;
@@ -319,7 +330,8 @@ static void fill_table(Table& T, DevArena& M, hipStream_t s, std::vector<PartD> 
     const int units = nt * (MC_TY / MC_ICYC);
     if (l > 0) add(1, (int)cdiv(units, 4), units, 0);  // restriction + pre-smoothing
     if (l == 0) add(3, til[pi].blocks[1], nt, q.mg_slot);
-    else add(3, (int)cdiv(units, 4), units, 0);        // post-smoothing
+    else if (!stop_smoothed_once(q))
+      add(3, (int)cdiv(units, 4), units, 0);           // post-smoothing
   }
   for (int l = 0; l < L; ++l)
     for (int op = 0; op < 4; ++op) {
@@ -353,6 +365,8 @@ struct MgLevel {
   int nx = 0, ny = 0, tiles = 0;
   long n = 0;
   bool coarsest = false;
+  bool smooth_once = false;   // last level, truncated where its row sums reach MC_MG_DOMINANCE
+                              // times its face conductances: one block IC(0) sweep
   double *diag = nullptr, *tx = nullptr, *ty = nullptr, *fdinv = nullptr;
   float *diag32 = nullptr, *tx32 = nullptr, *ty32 = nullptr, *fdinv32 = nullptr;
   double *r = nullptr, *zp = nullptr, *z = nullptr;
@@ -801,7 +815,7 @@ static void link_mg(std::vector<PartD>& parts) {
     q.mg_fuse = 0;
     if (q.mg_next >= 0) {
       const PartD& c = parts[q.mg_next];
-      q.mg_e = c.mg_z;
+      q.mg_e = stop_smoothed_once(c) ? c.mg_zp : c.mg_z;   // once: its pre-smoothed z_p
       q.mg_cnx = c.nx;
       q.mg_fuse = fuse && !q.fp32 && q.mg_level == 0 && q.plane == 0 && q.mg_edz &&
                   (long)c.n > mg_tail_cells();
@@ -871,6 +885,7 @@ static void add_mg_levels(mc_problem* P, std::vector<PartD>& parts, int i, bool 
     q.fdinv = L.fdinv;
     q.fdinv32 = L.fdinv32;
     q.mg_level = (int)l + 1;
+    q.mg_once = L.smooth_once && l + 1 == C.mg.size() ? 1 : 0;
     q.mg_prev = base + prev;
     q.mg_next = -1;
     q.mg_inv = L.coarsest ? L.inv : nullptr;
@@ -1116,6 +1131,7 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
     L.ny = cny;
     L.n = (long)cnx * cny;
     L.tiles = (int)(cdiv(cnx, MC_TX) * cdiv(cny, MC_TY));
+    L.smooth_once = false;
     L.coarsest = L.n <= MC_MG_COARSE;   // a level the hierarchy stops at above the tail is
                                          // not: it gets IC(0) factors for its smoothing
     if (!L.diag) {
@@ -1179,6 +1195,8 @@ static void setup_multigrid(mc_problem* P, Cont& C) {
         fs += h[2 * b + 1];
       }
       stop = rs >= dominance * fs;
+      // a level that strongly dominant is nearly solved by one sweep of its block IC(0)
+      L.smooth_once = stop && rs >= MC_MG_DOMINANCE * fs;
     }
     fd = L.diag;
     ftx = L.tx;
@@ -3144,6 +3162,13 @@ mc_status mc_get_info(const mc_problem* P, mc_info* info) {
     info->blocks[c][0] = P->cont[c].blocks[0];
     info->blocks[c][1] = P->cont[c].blocks[1];
     info->mg_levels[c] = P->cont[c].mg_on ? (int32_t)P->cont[c].mg.size() : 0;
+    if (P->cont[c].mg_on) {   // a last level above the tail: smoothed once or twice
+      const mc::MgLevel& last = P->cont[c].mg.back();
+      if (!last.coarsest && last.n > mc::mg_tail_cells()) {
+        const int f = mc::env_int("MCDEC_MG_STOP_ONCE", -1);
+        info->mg_stop_sweeps[c] = (f < 0 ? last.smooth_once : f != 0) ? 1 : 2;
+      }
+    }
   }
   return MC_OK;
 }

@@ -82,7 +82,8 @@ class Info(C.Structure):
     _fields_ = [("n_cont", C.c_int32), ("sizes", C.c_int32 * 3), ("device_bytes", C.c_int64),
                 ("grid_tiles", C.c_int32), ("n_chains", C.c_int32), ("tiles", C.c_int32 * 3),
                 ("blocks", (C.c_int32 * 2) * 3), ("n_crossing", C.c_int32),
-                ("mg_levels", C.c_int32 * 3), ("n_frac_blocks", C.c_int32)]
+                ("mg_levels", C.c_int32 * 3), ("n_frac_blocks", C.c_int32),
+                ("mg_stop_sweeps", C.c_int32 * 3)]
 
 
 class NlmcInfo(C.Structure):

@@ -85,3 +85,9 @@ def test_vcycle_levels_and_bytes():
     w = bench.working_launches([[7, 3], [5, 9]], "mg", [3, 6], [(2048, 2048), (2048, 2048)])
     # 7 + 9 iterations; 5 levels above the tail in the deeper hierarchy, which has a tail
     assert w["A"] == 16 and w["RS"] == 16 * 5 and w["TAIL"] == 16 and w["R"] == 16
+    # a truncated last level smoothed once has no post-smoothing launch or bytes
+    b1 = bench.vcycle_bytes(2048, 2048, "fp64", True, nlev=3, once=True)
+    b2 = bench.vcycle_bytes(2048, 2048, "fp64", True, nlev=3)
+    assert np.isclose(b2["PC"] - b1["PC"], n[3] * 42) and b1["RS"] == b2["RS"]
+    w1 = bench.working_launches([[6]], "mg", [3], [(2048, 2048)], [True])
+    assert w1["RS"] == 18 and w1["PC"] == 12 and w1["TAIL"] == 0

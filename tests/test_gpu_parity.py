@@ -327,12 +327,15 @@ def test_mg_depth(name, precision):
     asm = fv.assemble(p)
     with mcdec.Problem(p, precond="mg", precision=precision) as g:
         got = list(g.info().mg_levels)
+        sw = list(g.info().mg_stop_sweeps)
     want = [mg_depth(schemes.continuum_matrix(asm, p.tau, a), p.nx, p.ny,
                      8.0 if precision == "fp64" else 2.0) for a in range(p.n_omega)]
     print(name, precision, got[:p.n_omega], want, flush=True)
     assert got[:p.n_omega] == want
     if name == "mid300x270":
         assert want == [3 if precision == "fp64" else 2]
+        # the FP64 stop level (ratio 16) is smoothed once, the mixed one (ratio 4) twice
+        assert sw[0] == (1 if precision == "fp64" else 2), sw
 
 
 @pytest.mark.parametrize("name", list(MG_CASES))
@@ -354,7 +357,12 @@ def test_mg_apply(name):
             if a < p.n_omega:
                 want = mg_depth(K, p.nx, p.ny, 8.0)
                 assert inf.mg_levels[a] == want, (inf.mg_levels[a], want)
-                lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=want)
+                # an FP64 hierarchy stops only where a level's row sums reach 8 times its
+                # face conductances: that level is smoothed once
+                full = len(precond.vcycle_setup(K, p.nx, p.ny)) - 1
+                sweeps = 1 if want < full else 0
+                assert inf.mg_stop_sweeps[a] == sweeps, (inf.mg_stop_sweeps[a], sweeps)
+                lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=want, last_sweeps=1)
                 ref = precond.vcycle_apply(lev, r)
                 tol = 2e-5
             else:
@@ -442,6 +450,7 @@ def test_kernel_timing_samples_and_keeps_results():
         rep = g.step(2)
         reads = [g.profile_read(w) for w in range(7)]
         levels = g.info().mg_levels[0]
+        sweeps = g.info().mg_stop_sweeps[0]
         g.profile(False)
         got = g.get_states()
     print(rep, reads, levels)
@@ -451,14 +460,14 @@ def test_kernel_timing_samples_and_keeps_results():
         assert sampled >= 1 and ms > 0 and issued >= sum(rep["iters"][:1])
         assert sampled <= issued // 4 + 2
     # the V-cycle's coarse kernels (this storage-dominated problem keeps one coarse level,
-    # restricted into with pre-smoothing and post-smoothed twice, no tail): one launch of
-    # each per cycle, a sampled cycle timed whole
-    assert levels == 1
+    # row sums 45 times its conductances, restricted into with pre-smoothing and smoothed
+    # once, no tail): one restriction launch per cycle, a sampled cycle timed whole, and no
+    # coarse post-smoothing
+    assert levels == 1 and sweeps == 1
     cycles = reads[2][2]
-    for w in (3, 4):
-        sampled, ms, issued = reads[w]
-        assert issued == cycles and sampled == reads[2][0] and ms > 0
-    assert reads[5][2] == 0 and reads[6][2] == 0
+    sampled, ms, issued = reads[3]
+    assert issued == cycles and sampled == reads[2][0] and ms > 0
+    assert reads[4][2] == 0 and reads[5][2] == 0 and reads[6][2] == 0
     with pytest.raises(mcdec.McError):
         g2 = mcdec.Problem(p, precond="mg")
         try:

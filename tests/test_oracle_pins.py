@@ -670,23 +670,25 @@ def test_two_grid_cycle_error_propagation():
     assert ev.min() > 0 and ev.max() < 2
 
 
-def test_truncated_cycle_error_propagation():
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_truncated_cycle_error_propagation(sweeps):
     """A cycle truncated after its first coarse level (36 x 32 -> 18 x 16, whose own coarser
-    levels are dropped): the coarse solve Kc^-1 of the two-grid cycle becomes two sweeps of
-    the coarse smoother, (I - (I - Mc^-1 Kc)^2) Kc^-1, so V = (I - E) K^-1 with
-    E = S (I - P (I - Sc^2) Kc^-1 P^T K) S; V stays symmetric positive definite."""
+    levels are dropped): the coarse solve Kc^-1 of the two-grid cycle becomes s sweeps of
+    the coarse smoother, (I - (I - Mc^-1 Kc)^s) Kc^-1 (for s = 1 just Mc^-1), so
+    V = (I - E) K^-1 with E = S (I - P (I - Sc^s) Kc^-1 P^T K) S; V stays symmetric positive
+    definite."""
     p = media.rect_problem(36, 32, seed=4)
     K = schemes.continuum_matrix(fv.assemble(p), p.tau, 0).toarray()
     n = K.shape[0]
-    lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=1)
-    assert len(lev) == 2 and lev[1].get("smooth2") and "inv" not in lev[1]
+    lev = precond.vcycle_setup(K, p.nx, p.ny, max_levels=1, last_sweeps=sweeps)
+    assert len(lev) == 2 and lev[1].get("sweeps") == sweeps and "inv" not in lev[1]
     Minv = _dense_inverse_of(lambda e: precond.block_precond_apply(lev[0]["facs"], e), n)
     P = lev[0]["P"].toarray()
     Kc = precond.coarse_operator(sp.csr_matrix(K), sp.csr_matrix(P)).toarray()
     nc = Kc.shape[0]
     Mc = _dense_inverse_of(lambda e: precond.block_precond_apply(lev[1]["facs"], e), nc)
     Sc = np.eye(nc) - Mc @ Kc
-    coarse = (np.eye(nc) - Sc @ Sc) @ np.linalg.inv(Kc)
+    coarse = (np.eye(nc) - np.linalg.matrix_power(Sc, sweeps)) @ np.linalg.inv(Kc)
     I = np.eye(n)
     S = I - Minv @ K
     E = S @ (I - P @ coarse @ P.T @ K) @ S
