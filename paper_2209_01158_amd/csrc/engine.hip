@@ -400,6 +400,7 @@ struct Cont {  // one continuum
   float *gX32 = nullptr, *zX32 = nullptr;
   // (graph) two-level block preconditioner in place of the exact solve (K = blocks)
   bool fblocks = false;
+  int fmode = 0;   // preconditioner the K-sized arrays above were made for: 1 exact, 2 blocks
   int* bnode = nullptr;
   float* binv = nullptr;
   // (grid) multigrid levels 1.. and the finest level's pre-smoothed solution
@@ -991,8 +992,12 @@ static bool setup_block_solve(mc_problem* P, Cont& C, const std::vector<double>&
   if (H.nb == 0) return false;
   const int K = H.nb;
   DevArena& M = P->mem;
-  // device arrays keep the size of the first setup (the graph does not change afterwards)
-  if (!C.bnode) {
+  // device arrays are made on the first setup of this preconditioner (the graph does not
+  // change afterwards, so neither does K); the FP32 copies sized by K are made again
+  if (C.fmode != 2) {
+    C.fmode = 2;
+    C.sinv32 = nullptr;
+    C.gX32 = C.zX32 = nullptr;
     C.bnode = M.alloc<int>((size_t)K * kBlockCells);
     C.binv = M.alloc<float>((size_t)K * kBlockCells * kBlockCells);
     C.xtile = M.alloc<int>(H.xtile.size());
@@ -1057,7 +1062,10 @@ static void setup_fracture_solve(mc_problem* P, Cont& C) {
   std::vector<int> xlr;
   if (H.K > 0) {
     const int K = H.K;
-    if (!C.xcells) {
+    if (C.fmode != 1) {   // first setup of the exact solve (K fixed by the graph)
+      C.fmode = 1;
+      C.sinv32 = nullptr;   // FP32 copies sized by K are made again for this solve's K
+      C.gX32 = C.zX32 = nullptr;
       C.xcells = M.alloc<int>(K);
       C.xtile = M.alloc<int>(H.xtile.size());
       C.xlr = M.alloc<int>(2 * nf);

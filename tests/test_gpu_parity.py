@@ -770,6 +770,35 @@ def test_fracture_blocks_mixed(name, monkeypatch):
         assert err < 1e-8, (name, err, rep)
 
 
+def test_fracture_preconditioner_switch_on_rebuild(monkeypatch):
+    """One problem whose fracture solve changes between the two-level blocks (43 blocks) and
+    the exact solve (hundreds of crossing cells) when option changes rebuild its
+    coefficients: each layer still matches the oracle (the K-sized arrays, and their FP32
+    copies in mixed precision, are made for the preconditioner in use)."""
+    p = DENSE()
+    ref = schemes.run(p, "D", 4, keep="all")
+    mixed = dict(precision="mixed", outer_tol=1e-12, inner_tol=1e-6)
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    with mcdec.Problem(p, precond="bic0", **mixed) as g:
+        assert g.info().n_frac_blocks > 0 and g.info().n_crossing == 0
+        g.step(1)
+        assert rel(g.get_states(), ref[1]) < 1e-8
+        monkeypatch.delenv("MCDEC_FRACTURE_EXACT_MAX")
+        g.set_options(precision="fp64", tol=1e-13)          # rebuild: the exact solve
+        inf = g.info()
+        assert inf.n_frac_blocks == 0 and inf.n_crossing > 43, inf.n_crossing
+        g.step(1)
+        assert rel(g.get_states(), ref[2]) < 1e-10
+        g.set_options(**mixed)                               # rebuild: exact, in FP32 copies
+        g.step(1)
+        assert rel(g.get_states(), ref[3]) < 1e-8
+        monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+        g.set_options(precision="fp64", tol=1e-13)          # rebuild: the blocks again
+        assert g.info().n_frac_blocks > 0
+        g.step(1)
+        assert rel(g.get_states(), ref[4]) < 1e-10
+
+
 def test_fracture_blocks_fewer_iterations(monkeypatch):
     """On fracture planes the two-level preconditioner needs far fewer PCG iterations than
     the chains alone (MCDEC_FRACTURE_BLOCKS = 0 leaves the chains)."""
