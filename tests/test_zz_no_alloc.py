@@ -68,6 +68,19 @@ def test_noalloc_matches_solve_continuum_twice(precond):
     _solve_both(small, precond, 2)
 
 
+def test_noalloc_fracture_blocks(monkeypatch):
+    """The fracture continuum with the two-level block preconditioner (forced on by setting
+    the exact solve's crossing-cell limit to 0): blocks and coarse stage run in the same
+    kernels with the workspace's coarse vectors; a fracture network, then 3-D planes."""
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    dense = media.small_problem(n=48, seed=13, nseg=40, seg_len=(10, 40))
+    box = media.box_problem(n=24, nz=12, seed=7, three=True)
+    for p, seed in ((dense, 3), (box, 4)):
+        with mcdec.Problem(p, precond="bic0") as g:
+            assert g.info().n_frac_blocks > 0
+        _solve_both(p, "bic0", seed)
+
+
 def test_noalloc_refusals():
     p = media.small_problem(n=64, seed=3, nseg=4, seg_len=(5, 20))
     b = torch.ones(p.sizes()[0], dtype=torch.float64, device=DEV)
