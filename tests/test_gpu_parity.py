@@ -799,6 +799,27 @@ def test_fracture_preconditioner_switch_on_rebuild(monkeypatch):
         assert rel(g.get_states(), ref[4]) < 1e-10
 
 
+def test_cu_partition_keeps_results(monkeypatch):
+    """A problem whose fracture takes the two-level block preconditioner runs its fracture
+    group on its own compute units by default; with every unit shared (MCDEC_FRAC_CUS=0)
+    the layers are bitwise the same (the partial sums are reduced in a fixed order)."""
+    monkeypatch.setenv("MCDEC_FRACTURE_EXACT_MAX", "0")
+    p = BOXES["box64x5"]()
+    out = {}
+    for cus in (None, "0"):
+        if cus is None:
+            monkeypatch.delenv("MCDEC_FRAC_CUS", raising=False)
+        else:
+            monkeypatch.setenv("MCDEC_FRAC_CUS", cus)
+        with mcdec.Problem(p, precond="bic0", tol=1e-12) as g:
+            assert g.info().n_frac_blocks > 0
+            reps = [g.step(1) for _ in range(3)]
+            out[cus] = (g.get_states(), [r["iters"] for r in reps])
+    (a, ia), (b, ib) = out[None], out["0"]
+    assert ia == ib
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
 def test_fracture_blocks_fewer_iterations(monkeypatch):
     """On fracture planes the two-level preconditioner needs far fewer PCG iterations than
     the chains alone (MCDEC_FRACTURE_BLOCKS = 0 leaves the chains)."""
